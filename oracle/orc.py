@@ -1,0 +1,251 @@
+"""ctypes wrapper of the FP64 CPU oracle (liborc.so).
+
+TEST INFRASTRUCTURE ONLY: imported by tests, the smoke check and the
+CPU-baseline leg of the benchmark; never by the GPU library or its binding.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liborc.so")
+
+CROSS, SCATTER, ESCAPE, FLOOR, RUNAWAY = 0, 1, 2, 3, 4
+CLASS_BG, CLASS_DUST, CLASS_PS0 = 0, 1, 2
+
+
+class _Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("nlevels", C.c_int32),
+                ("ncells", C.c_int64), ("level_offset", C.POINTER(C.c_int64)),
+                ("root_cell_cm", C.c_double), ("words", C.POINTER(C.c_uint32))]
+
+
+class _Freq(C.Structure):
+    _fields_ = [("nu", C.c_double), ("w_nu", C.c_double), ("sigma_abs", C.c_double),
+                ("sigma_sca", C.c_double), ("g", C.c_double)]
+
+
+class _Sources(C.Structure):
+    _fields_ = [("I_bg_nu", C.c_double), ("n_ps", C.c_int32), ("ps_pos", C.POINTER(C.c_double)),
+                ("ps_L_nu", C.POINTER(C.c_double)), ("T", C.POINTER(C.c_float)),
+                ("n_bg", C.c_uint64), ("n_ps_pk", C.c_uint64), ("n_dust", C.c_uint64),
+                ("dust_mode", C.c_int32)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("packages", C.c_uint64), ("cell_steps", C.c_uint64), ("scatterings", C.c_uint64),
+                ("runaways", C.c_uint64), ("e_emitted", C.c_double), ("e_absorbed", C.c_double),
+                ("e_escaped", C.c_double)]
+
+
+class _Segment(C.Structure):
+    _fields_ = [("cell", C.c_int64), ("ds", C.c_double), ("event", C.c_int32)]
+
+
+class _TStats(C.Structure):
+    _fields_ = [("mean_T", C.c_double), ("hot5_mean_T", C.c_double),
+                ("mean_rel_change", C.c_double), ("clamped", C.c_uint64)]
+
+
+SEGMENT_DTYPE = np.dtype([("cell", np.int64), ("ds", np.float64), ("event", np.int32)], align=True)
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"oracle library not built: {_LIB_PATH} (run __graft_entry__.build())")
+        L = C.CDLL(_LIB_PATH)
+        L.orc_u01.restype = C.c_double
+        L.orc_planck.restype = C.c_double
+        L.orc_planck.argtypes = [C.c_double, C.c_double]
+        L.orc_gamma.restype = C.c_double
+        L.orc_gamma.argtypes = [C.POINTER(_Freq), C.c_int32, C.c_double]
+        L.orc_leaf.restype = C.c_int64
+        L.orc_validate_grid.restype = C.c_int32
+        for name in ("orc_simulate_frequency", "orc_trace_package", "orc_trace_from",
+                     "orc_update_temperature", "orc_map"):
+            getattr(L, name).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct)) if a is not None else None
+
+
+class GridView:
+    """Keeps the numpy arrays of a workloads.Grid alive for a call."""
+
+    def __init__(self, g):
+        self.lo = np.ascontiguousarray(g.level_offset, dtype=np.int64)
+        self.words = np.ascontiguousarray(g.words, dtype=np.uint32)
+        self.s = _Grid(g.nx, g.ny, g.nz, g.nlevels, self.words.shape[0], _p(self.lo, C.c_int64),
+                       float(g.root_cell_cm), _p(self.words, C.c_uint32))
+
+
+def _freq(f):
+    nu, w, sabs, ssca, g = f
+    return _Freq(float(nu), float(w), float(sabs), float(ssca), float(g))
+
+
+def philox(ctr, key):
+    c = (C.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (C.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return [int(x) for x in o]
+
+
+def u01(x):
+    return lib().orc_u01(C.c_uint32(x))
+
+
+def uniforms(seed, iteration, cls, freq_index, package_id, n):
+    out = np.zeros(n, dtype=np.float64)
+    lib().orc_uniforms(C.c_uint64(seed), C.c_uint32(iteration), C.c_uint32(cls), C.c_uint32(freq_index),
+                       C.c_uint32(package_id), C.c_int32(n), _p(out, C.c_double))
+    return out
+
+
+def planck(nu, T):
+    return lib().orc_planck(float(nu), float(T))
+
+
+def gamma(emit_nu, emit_w, emit_sabs, T):
+    arr = (_Freq * len(emit_nu))(*[_Freq(float(a), float(b), float(c), 0.0, 0.0)
+                                   for a, b, c in zip(emit_nu, emit_w, emit_sabs)])
+    return lib().orc_gamma(arr, len(emit_nu), float(T))
+
+
+def leaf(grid, p):
+    gv = GridView(grid)
+    pp = (C.c_double * 3)(*p)
+    lo = (C.c_double * 3)()
+    sz = C.c_double()
+    c = lib().orc_leaf(C.byref(gv.s), pp, lo, C.byref(sz))
+    return int(c), (lo[0], lo[1], lo[2]), sz.value
+
+
+def validate(grid):
+    gv = GridView(grid)
+    return int(lib().orc_validate_grid(C.byref(gv.s)))
+
+
+def hg_scatter(g, u0, xi):
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    n = xi.shape[0] // 2
+    out = np.zeros((n, 3), dtype=np.float64)
+    u = (C.c_double * 3)(*u0)
+    lib().orc_hg_scatter(C.c_double(g), u, C.c_int32(n), _p(xi, C.c_double), _p(out, C.c_double))
+    return out
+
+
+class _SourcesView:
+    def __init__(self, I_bg=0.0, ps_pos=None, ps_Lnu=None, T=None, n_bg=0, n_ps_pk=0, n_dust=0, dust_mode=1):
+        self.pos = np.ascontiguousarray(ps_pos if ps_pos is not None else np.zeros((0, 3)), dtype=np.float64)
+        self.L = np.ascontiguousarray(ps_Lnu if ps_Lnu is not None else np.zeros(0), dtype=np.float64)
+        self.T = None if T is None else np.ascontiguousarray(T, dtype=np.float32)
+        n_ps = self.pos.shape[0]
+        self.s = _Sources(float(I_bg), n_ps, _p(self.pos, C.c_double) if n_ps else None,
+                          _p(self.L, C.c_double) if n_ps else None,
+                          _p(self.T, C.c_float) if self.T is not None else None,
+                          int(n_bg), int(n_ps_pk), int(n_dust), int(dust_mode))
+
+
+def _stats_dict(st):
+    return {k: getattr(st, k) for k, _ in _Stats._fields_}
+
+
+def simulate_frequency(grid, freq, *, I_bg=0.0, ps_pos=None, ps_Lnu=None, T=None, n_bg=0, n_ps_pk=0,
+                       n_dust=0, dust_mode=1, seed=1, iteration=0, freq_index=0, step_cap=0,
+                       nthreads=1, absorbed=None, want_path=False):
+    """One Monte Carlo pass at one frequency.  freq = (nu, w, sigma_abs,
+    sigma_sca, g).  Returns (absorbed float64[ncells], stats dict,
+    path lengths or None)."""
+    gv = GridView(grid)
+    sv = _SourcesView(I_bg, ps_pos, ps_Lnu, T, n_bg, n_ps_pk, n_dust, dust_mode)
+    f = _freq(freq)
+    if absorbed is None:
+        absorbed = np.zeros(grid.ncells, dtype=np.float64)
+    n_tot = int(n_bg) + sv.pos.shape[0] * int(n_ps_pk) + (int(n_dust) if T is not None else 0)
+    path = np.zeros(n_tot, dtype=np.float64) if want_path else None
+    st = _Stats()
+    rc = lib().orc_simulate_frequency(C.byref(gv.s), C.byref(f), C.byref(sv.s), C.c_uint64(seed),
+                                      C.c_uint32(iteration), C.c_uint32(freq_index), C.c_int64(step_cap),
+                                      C.c_int32(nthreads), _p(absorbed, C.c_double), C.byref(st),
+                                      _p(path, C.c_double) if path is not None else None)
+    if rc != 0:
+        raise ValueError(f"orc_simulate_frequency failed: {rc}")
+    return absorbed, _stats_dict(st), path
+
+
+def trace_package(grid, freq, cls, package_id, *, I_bg=0.0, ps_pos=None, ps_Lnu=None, T=None, n_bg=0,
+                  n_ps_pk=0, n_dust=0, dust_mode=1, seed=1, iteration=0, freq_index=0, step_cap=0,
+                  max_seg=100000):
+    gv = GridView(grid)
+    sv = _SourcesView(I_bg, ps_pos, ps_Lnu, T, n_bg, n_ps_pk, n_dust, dust_mode)
+    f = _freq(freq)
+    out = np.zeros(max_seg, dtype=SEGMENT_DTYPE)
+    ns = C.c_int32()
+    rc = lib().orc_trace_package(C.byref(gv.s), C.byref(f), C.byref(sv.s), C.c_uint64(seed),
+                                 C.c_uint32(iteration), C.c_uint32(freq_index), C.c_uint32(cls),
+                                 C.c_uint32(package_id), C.c_int64(step_cap),
+                                 out.ctypes.data_as(C.POINTER(_Segment)), C.c_int32(max_seg), C.byref(ns))
+    if rc != 0:
+        raise ValueError(f"orc_trace_package failed: {rc}")
+    return out[: min(ns.value, max_seg)].copy()
+
+
+def trace_from(grid, freq, p0, u0, W0, tau0, *, seed=1, package_id=0, step_cap=0, absorbed=None,
+               max_seg=100000):
+    gv = GridView(grid)
+    f = _freq(freq)
+    out = np.zeros(max_seg, dtype=SEGMENT_DTYPE)
+    ns = C.c_int32()
+    wesc = C.c_double()
+    rc = lib().orc_trace_from(C.byref(gv.s), C.byref(f), (C.c_double * 3)(*p0), (C.c_double * 3)(*u0),
+                              C.c_double(W0), C.c_double(tau0), C.c_uint64(seed), C.c_uint32(package_id),
+                              C.c_int64(step_cap), _p(absorbed, C.c_double),
+                              out.ctypes.data_as(C.POINTER(_Segment)), C.c_int32(max_seg), C.byref(ns),
+                              C.byref(wesc))
+    if rc != 0:
+        raise ValueError(f"orc_trace_from failed: {rc}")
+    return out[: min(ns.value, max_seg)].copy(), wesc.value
+
+
+def update_temperature(grid, emit_nu, emit_w, emit_sabs, absorbed, T_old=None, T_floor=2.0, T_max=3000.0):
+    gv = GridView(grid)
+    K = len(emit_nu)
+    arr = (_Freq * K)(*[_Freq(float(a), float(b), float(c), 0.0, 0.0)
+                        for a, b, c in zip(emit_nu, emit_w, emit_sabs)])
+    A = np.ascontiguousarray(absorbed, dtype=np.float64)
+    To = None if T_old is None else np.ascontiguousarray(T_old, dtype=np.float32)
+    Tn = np.zeros(grid.ncells, dtype=np.float32)
+    st = _TStats()
+    rc = lib().orc_update_temperature(C.byref(gv.s), arr, C.c_int32(K), C.c_double(T_floor), C.c_double(T_max),
+                                      _p(A, C.c_double), _p(To, C.c_float) if To is not None else None,
+                                      _p(Tn, C.c_float), C.byref(st))
+    if rc != 0:
+        raise ValueError(f"orc_update_temperature failed: {rc}")
+    return Tn, {k: getattr(st, k) for k, _ in _TStats._fields_}
+
+
+def map_image(grid, freq, T, axis):
+    gv = GridView(grid)
+    f = _freq(freq)
+    Tc = np.ascontiguousarray(T, dtype=np.float32)
+    npx, npy = C.c_int32(), C.c_int32()
+    lib().orc_map(C.byref(gv.s), C.byref(f), _p(Tc, C.c_float), C.c_int32(axis), None,
+                  C.byref(npx), C.byref(npy))
+    img = np.zeros(npx.value * npy.value, dtype=np.float64)
+    rc = lib().orc_map(C.byref(gv.s), C.byref(f), _p(Tc, C.c_float), C.c_int32(axis), _p(img, C.c_double),
+                       C.byref(npx), C.byref(npy))
+    if rc != 0:
+        raise ValueError(f"orc_map failed: {rc}")
+    return img.reshape(npy.value, npx.value)

@@ -1,0 +1,501 @@
+"""Pins of the FP64 CPU oracle against facts fixed by mathematics and by
+published definitions (no GPU).  Each test states what it pins; together
+they are chosen so that a dropped term, a wrong sign or index, or a
+transposed operand anywhere in the oracle fails at least one of them.
+"""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+from scipy import integrate, special, stats
+
+from oracle import orc
+from paper_1812_06632_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+H, KB, CL, SIGMA_SB = 6.62607015e-27, 1.380649e-16, 2.99792458e10, 5.670374419e-5
+
+
+# ---------------------------------------------------------------- Philox
+def _kat():
+    rows = []
+    with open(os.path.join(GOLDEN, "philox_kat.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            v = [int(x, 16) for x in line.split()]
+            rows.append((v[0:4], v[4:6], v[6:10]))
+    return rows
+
+
+@pytest.mark.parametrize("ctr,key,out", _kat())
+def test_philox_known_answers(ctr, key, out):
+    """Random123 known-answer vectors of Philox4x32-10."""
+    assert orc.philox(ctr, key) == out
+
+
+def test_philox_matches_rocrand_black_box(tmp_path):
+    """rocRAND's host-callable Philox engine, compiled here and run as a
+    black box, produces the same blocks for counters (block, 0, sub_lo,
+    sub_hi) and key = seed."""
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path / "rrdump")
+    src = os.path.join(os.path.dirname(__file__), "helpers", "rocrand_philox_dump.cpp")
+    subprocess.run([hipcc, "-O1", src, "-o", exe], check=True, capture_output=True, cwd=str(tmp_path))
+    rng = np.random.default_rng(7)
+    for _ in range(6):
+        seed = int(rng.integers(0, 2 ** 63))
+        sub = int(rng.integers(0, 2 ** 63))
+        block = int(rng.integers(0, 2 ** 31))
+        out = subprocess.run([exe, str(seed), str(sub), str(block)], check=True, capture_output=True,
+                             text=True).stdout.split()
+        ref = [int(x, 16) for x in out]
+        ctr = [block & 0xFFFFFFFF, block >> 32, sub & 0xFFFFFFFF, sub >> 32]
+        key = [seed & 0xFFFFFFFF, seed >> 32]
+        assert orc.philox(ctr, key) == ref
+
+
+def test_uniform_mapping_and_stream():
+    """u = ((x >> 8) + 1/2) 2^-24 lies strictly inside (0,1) at both ends;
+    a package stream takes the four words of consecutive counter blocks in
+    order; uniforms pass a KS test."""
+    assert orc.u01(0) == 0.5 * 2.0 ** -24
+    assert orc.u01(0xFFFFFFFF) == 1.0 - 0.5 * 2.0 ** -24
+    u = orc.uniforms(seed=0x1234_5678_9ABC, iteration=3, cls=2, freq_index=5, package_id=77, n=9)
+    for b in range(2):
+        words = orc.philox([b, 77, 5, (3 << 8) | 2], [0x5678_9ABC, 0x1234])
+        assert np.array_equal(u[4 * b: 4 * b + 4], [orc.u01(w) for w in words])
+    big = orc.uniforms(seed=99, iteration=0, cls=0, freq_index=0, package_id=1, n=200000)
+    assert stats.kstest(big, "uniform").pvalue > 1e-3
+
+
+# ---------------------------------------------------------------- HG
+def _hg_cdf(mu, g):
+    # integral of the HG phase function (1-g^2)/(2 (1+g^2-2 g mu)^1.5) from -1 to mu
+    return (1 - g * g) / (2 * g) * (1.0 / np.sqrt(1 + g * g - 2 * g * mu) - 1.0 / (1 + g))
+
+
+@pytest.mark.parametrize("g", [0.5, -0.3, 0.85])
+def test_hg_scattering_distribution(g):
+    """Henyey-Greenstein: <cos> = g, KS against the analytic CDF, unit
+    directions, for an incoming direction near the pole and a generic one."""
+    rng = np.random.default_rng(11)
+    xi = rng.random(2 * 100000)
+    for u0 in ([0.0, 0.0, 1.0], [0.48, -0.6, 0.64]):
+        out = orc.hg_scatter(g, u0, xi)
+        mu = out @ np.array(u0)
+        assert np.allclose(np.linalg.norm(out, axis=1), 1.0, atol=1e-12)
+        assert abs(mu.mean() - g) < 5 * mu.std() / math.sqrt(mu.size)
+        assert stats.kstest(mu, lambda m: _hg_cdf(m, g)).pvalue > 1e-3
+        # azimuth uniform around u0: the mean of the new direction is g*u0
+        assert np.allclose(out.mean(axis=0), g * np.array(u0), atol=0.01)
+
+
+def test_isotropic_limit():
+    """|g| < 1e-4 draws mu = 2 xi - 1: <mu> = 0 and <mu^2> = 1/3."""
+    xi = np.random.default_rng(3).random(200000)
+    out = orc.hg_scatter(0.0, [0.0, 0.6, 0.8], xi)
+    mu = out @ np.array([0.0, 0.6, 0.8])
+    assert abs(mu.mean()) < 0.01 and abs((mu * mu).mean() - 1 / 3) < 0.01
+
+
+# ---------------------------------------------------------------- Planck / Gamma
+def test_planck_limits_and_stefan_boltzmann():
+    """Rayleigh-Jeans and Wien limits; pi * integral of B_nu = sigma_SB T^4."""
+    T = 30.0
+    nu_rj = 1e8
+    assert orc.planck(nu_rj, T) == pytest.approx(2 * nu_rj ** 2 * KB * T / CL ** 2, rel=1e-4)
+    nu_w = 2e14
+    x = H * nu_w / (KB * T)
+    assert orc.planck(nu_w, T) == pytest.approx(2 * H * nu_w ** 3 / CL ** 2 * math.exp(-x), rel=1e-12)
+    val, _ = integrate.quad(lambda lnu: math.exp(lnu) * orc.planck(math.exp(lnu), T),
+                            math.log(1e8), math.log(1e15), limit=400)
+    assert math.pi * val == pytest.approx(SIGMA_SB * T ** 4, rel=1e-6)
+    assert orc.planck(1e12, 0.0) == 0.0
+
+
+def test_temperature_single_frequency_inverse_planck():
+    """One frequency: the solved T equals the closed-form inverse Planck
+    T = (h nu / k) / ln(1 + 2 h nu^3 / (c^2 B)) with B = A / (4 pi w sigma n V)."""
+    g = W.regular_grid(np.array([[[1.0, 2.0, 0.5, 3.0]]], np.float32), 2.0)
+    nu, w, sabs = 3e12, 1e11, 2e-23
+    dens = g.density().astype(np.float64)
+    V = 8.0
+    B = np.array([1e-16, 3e-15, 2e-14, 7e-14])
+    A = 4 * math.pi * w * sabs * dens * V * B
+    T, st = orc.update_temperature(g, [nu], [w], [sabs], A)
+    expect = (H * nu / KB) / np.log1p(2 * H * nu ** 3 / (CL ** 2 * B))
+    assert np.allclose(T, expect, rtol=2e-7)
+    assert st["clamped"] == 0
+
+
+def test_temperature_grey_closed_form():
+    """Grey sigma_abs on a dense frequency grid: Gamma(T) -> 4 sigma sigma_SB
+    T^4, so T = (A / (4 sigma sigma_SB n V))^(1/4) to the quadrature error."""
+    nu, w = W.frequency_grid(4000, 0.5, 1e5)
+    sabs = np.full_like(nu, 1e-22)
+    g = W.regular_grid(np.array([[[1.0, 1.0, 1.0]]], np.float32), 1.0)
+    Ttrue = np.array([8.0, 20.0, 60.0])
+    A = 4 * 1e-22 * SIGMA_SB * Ttrue ** 4
+    T, _ = orc.update_temperature(g, nu, w, sabs, A)
+    assert np.allclose(T, Ttrue, rtol=1e-4)
+
+
+def test_temperature_boundary_cases_and_stats():
+    """Empty cells -> 0 and excluded from statistics, unhit cells -> T_floor
+    (counted), too-hot -> T_max (counted); hot-5% mean and mean relative
+    change follow their definitions."""
+    dens = np.ones(40, np.float32)
+    dens[0] = 0.0
+    g = W.regular_grid(dens.reshape(1, 1, 40), 1.0)
+    nu, w = W.frequency_grid(16)
+    sabs, _, _ = W.dust_model(nu)
+    Tt = np.linspace(5, 80, 40)
+    A = np.array([orc.gamma(nu, w, sabs, t) for t in Tt])
+    A[1] = 0.0
+    A[2] = 1e30
+    Told = np.full(40, 10.0, np.float32)
+    T, st = orc.update_temperature(g, nu, w, sabs, A, T_old=Told, T_floor=2.0, T_max=3000.0)
+    assert T[0] == 0.0 and T[1] == 2.0 and T[2] == 3000.0
+    assert np.allclose(T[3:], Tt[3:], rtol=1e-6)
+    assert st["clamped"] == 2
+    vals = np.sort(T[1:].astype(np.float64))[::-1]
+    k = math.ceil(0.05 * 39)
+    assert st["hot5_mean_T"] == pytest.approx(vals[:k].mean(), rel=1e-7)
+    assert st["mean_T"] == pytest.approx(vals.mean(), rel=1e-7)
+    assert st["mean_rel_change"] == pytest.approx(np.mean(np.abs(T[1:] - 10.0) / 10.0), rel=1e-6)
+
+
+# ---------------------------------------------------------------- geometry
+def test_grid_validation_rejects_malformed():
+    g = W.refine_all_once(W.regular_grid(np.ones((2, 2, 2), np.float32), 1.0))
+    assert orc.validate(g) == 0
+    bad = [g.words.copy() for _ in range(4)]
+    w32 = [b.view(np.int32) for b in bad]
+    w32[0][0] = -(g.ncells + 8)          # link out of range
+    w32[1][0] = -(g.nroot + 3)           # misaligned octet
+    w32[2][1] = w32[2][0]                # octet linked twice
+    bad[3][5] = np.float32(np.nan).view(np.uint32)
+    for b in bad:
+        gg = W.Grid(g.nx, g.ny, g.nz, g.nlevels, g.level_offset, g.root_cell_cm, b)
+        assert orc.validate(gg) < 0
+
+
+def test_octree_lookup_matches_doubled_regular_grid():
+    """In a grid whose root cells are all refined once, the leaf containing p
+    is the child of the root cell floor(p) at octant floor(2p) mod 2."""
+    rng = np.random.default_rng(5)
+    reg = W.regular_grid(rng.random((3, 4, 5)).astype(np.float32), 1.0)
+    oc = W.refine_all_once(reg)
+    for _ in range(300):
+        p = rng.random(3) * [5, 4, 3]
+        c, lo, sz = orc.leaf(oc, p)
+        ix, iy, iz = (int(v) for v in np.floor(p))
+        ox, oy, oz = (int(v) for v in np.floor(2 * p) % 2)
+        root = ix + 5 * (iy + 4 * iz)
+        assert c == oc.nroot + 8 * root + ox + 2 * oy + 4 * oz
+        assert sz == 0.5 and np.allclose(lo, np.floor(2 * p) / 2)
+    assert orc.leaf(oc, [5.0, 0.1, 0.1])[0] == -1
+
+
+def test_normal_incidence_pure_absorber_transmission_exact():
+    """A package crossing a row of cells along +x escapes with exactly
+    W0 exp(-sum_i sigma n_i s): every segment has length 1."""
+    dens = np.array([0.3, 0.0, 1.7, 0.9, 2.2], np.float32)
+    g = W.regular_grid(dens.reshape(1, 1, 5), 2.0)
+    sabs = 0.4
+    A = np.zeros(5)
+    seg, wesc = orc.trace_from(g, (1e12, 1.0, sabs, 0.0, 0.0), [0.0, 0.5, 0.5], [1.0, 0.0, 0.0], 3.0, 1.0,
+                               absorbed=A)
+    tau = sabs * 2.0 * dens.astype(np.float64).sum()
+    assert wesc == pytest.approx(3.0 * math.exp(-tau), rel=1e-14)
+    assert list(seg["cell"]) == [0, 1, 2, 3, 4]
+    assert np.allclose(seg["ds"], 1.0, rtol=1e-14)
+    assert list(seg["event"]) == [0, 0, 0, 0, orc.ESCAPE]
+    exp_dep = 3.0 * np.exp(-sabs * 2.0 * np.concatenate([[0], np.cumsum(dens.astype(np.float64))[:-1]])) * \
+        (1 - np.exp(-sabs * 2.0 * dens.astype(np.float64)))
+    assert np.allclose(A, exp_dep, rtol=1e-13, atol=0)
+
+
+def test_random_rays_uniform_absorber_match_box_chord():
+    """Uniform pure absorber: the escaped weight is W0 exp(-k L) with L the
+    analytic ray-box exit distance, and the summed segment lengths equal L,
+    for regular and octree grids alike."""
+    rng = np.random.default_rng(9)
+    reg = W.regular_grid(np.full((3, 4, 5), 0.8, np.float32), 1.5)
+    oc = W.refine_all_once(reg)
+    N = np.array([5.0, 4.0, 3.0])
+    sabs = 0.3
+    k = sabs * float(np.float32(0.8)) * 1.5
+    for g in (reg, oc):
+        for _ in range(50):
+            p = rng.random(3) * N
+            u = rng.standard_normal(3)
+            u /= np.linalg.norm(u)
+            L = min(((N[i] if u[i] > 0 else 0.0) - p[i]) / u[i] for i in range(3))
+            seg, wesc = orc.trace_from(g, (1e12, 1.0, sabs, 0.0, 0.0), p, u, 1.0, 5.0)
+            assert seg["ds"].sum() == pytest.approx(L, rel=1e-12)
+            assert wesc == pytest.approx(math.exp(-k * L), rel=1e-12)
+            assert seg["event"][-1] == orc.ESCAPE
+
+
+def test_tiny_grid_hand_traces():
+    """2x2x2 grid: an axis-aligned ray crosses two unit cells; a ray through
+    an edge (x and y faces hit together) continues in the diagonal cell; the
+    octree of one refined root cell sees half-unit children."""
+    g = W.regular_grid(np.ones((2, 2, 2), np.float32), 1.0)
+    f = (1e12, 1.0, 0.0, 0.0, 0.0)
+    seg, _ = orc.trace_from(g, f, [0.5, 0.5, 0.0], [0.0, 0.0, 1.0], 1.0, 1.0)
+    assert list(seg["cell"]) == [0, 4] and np.allclose(seg["ds"], [1.0, 1.0])
+    r2 = math.sqrt(0.5)
+    seg, _ = orc.trace_from(g, f, [0.5, 0.5, 0.5], [r2, r2, 0.0], 1.0, 1.0)
+    assert list(seg["cell"]) == [0, 3]
+    assert np.allclose(seg["ds"], [math.sqrt(0.5), math.sqrt(2.0)], rtol=1e-12)
+    oc = W.refine_all_once(W.regular_grid(np.ones((1, 1, 1), np.float32), 1.0))
+    seg, _ = orc.trace_from(oc, f, [0.25, 0.25, 0.0], [0.0, 0.0, 1.0], 1.0, 1.0)
+    assert list(seg["cell"]) == [1, 5] and np.allclose(seg["ds"], [0.5, 0.5])
+
+
+def test_scattering_position_is_tau_over_k():
+    """In a pure scatterer the first segment ends after tau0 / k_sca."""
+    g = W.regular_grid(np.full((1, 1, 20), 2.0, np.float32), 0.5)
+    ssca = 0.7
+    seg, _ = orc.trace_from(g, (1e12, 1.0, 0.0, ssca, 0.3), [0.0, 0.5, 0.5], [1.0, 0.0, 0.0], 1.0, 1.9)
+    k = ssca * 2.0 * 0.5
+    first = np.nonzero(seg["event"] == orc.SCATTER)[0][0]
+    assert seg["ds"][: first + 1].sum() == pytest.approx(1.9 / k, rel=1e-13)
+
+
+# ---------------------------------------------------------------- sources + transport
+def test_energy_conservation_mixed_sources():
+    """Sum of absorbed plus escaped equals emitted for background, point
+    sources and weighted dust emission with scattering (to 1e-12)."""
+    rng = np.random.default_rng(2)
+    g = W.regular_grid((rng.random((6, 7, 8)) * 2).astype(np.float32), 0.3)
+    T = rng.uniform(5, 50, g.ncells).astype(np.float32)
+    A, st, _ = orc.simulate_frequency(
+        g, (3e13, 2e12, 0.9, 1.4, 0.4), I_bg=1e-15, ps_pos=[[2.5, 3.5, 3.2], [6.1, 0.2, 5.9]],
+        ps_Lnu=[1e-3, 4e-4], T=T, n_bg=3000, n_ps_pk=2000, n_dust=5000, dust_mode=1, seed=5, nthreads=4)
+    assert st["packages"] == 3000 + 4000 + 5000
+    assert (A.sum() + st["e_escaped"]) / st["e_emitted"] == pytest.approx(1.0, abs=1e-12)
+    assert st["e_absorbed"] == pytest.approx(A.sum(), rel=1e-12)
+
+
+def test_pure_scatterer_absorbs_nothing():
+    rng = np.random.default_rng(4)
+    g = W.regular_grid((rng.random((5, 5, 5)) * 3).astype(np.float32), 1.0)
+    A, st, _ = orc.simulate_frequency(g, (3e13, 1.0, 0.0, 1.0, 0.7), I_bg=1.0, n_bg=3000, nthreads=4)
+    assert np.all(A == 0.0) and st["e_escaped"] == pytest.approx(st["e_emitted"], rel=1e-12)
+    assert st["scatterings"] > 0
+
+
+def test_cauchy_mean_chord_empty_box():
+    """Isotropic external field through an empty box: the mean chord of the
+    cosine-weighted face emission is 4V/S (Cauchy), for a non-cubic box."""
+    g = W.regular_grid(np.zeros((3, 5, 8), np.float32), 1.0)
+    _, st, path = orc.simulate_frequency(g, (1e12, 1.0, 0.1, 0.0, 0.0), I_bg=1.0, n_bg=200000,
+                                         want_path=True, nthreads=8)
+    V, S = 3 * 5 * 8, 2 * (15 + 24 + 40)
+    assert abs(path.mean() - 4 * V / S) < 4 * path.std() / math.sqrt(path.size)
+    assert st["e_emitted"] == pytest.approx(math.pi * 1.0 * S, rel=1e-12)
+
+
+def test_isotropic_field_on_absorbing_sphere():
+    """Pure-absorber sphere of radius R and centre-to-edge optical depth t in
+    an isotropic field absorbs the fraction 1 - [1-(1+2t)e^{-2t}]/(2t^2) of
+    the power pi I 4 pi R^2 that enters it (continuous sphere; 0.5% for the
+    voxel sphere of radius 24 cells)."""
+    N, R, t = 64, 24.0, 1.0
+    g = W.regular_grid(W.sphere_density(N, R, 1.0), 1.0)
+    A, st, _ = orc.simulate_frequency(g, (1e12, 1.0, t / R, 0.0, 0.0), I_bg=1.0, n_bg=300000, nthreads=8)
+    Tr = (1 - (1 + 2 * t) * math.exp(-2 * t)) / (2 * t * t)
+    pred = 4 * math.pi * R * R / (6 * N * N) * (1 - Tr)
+    assert A.sum() / st["e_emitted"] == pytest.approx(pred, rel=0.01)
+
+
+def test_point_source_in_uniform_cube_direction_average():
+    """Isotropic point source at the centre of a uniform pure-absorber cube:
+    the absorbed fraction is 1 - <exp(-k d(u))> over directions, d the
+    distance to the cube surface (numerical quadrature over the sphere)."""
+    N, k = 8, 0.15
+    g = W.regular_grid(np.full((N, N, N), 1.0, np.float32), 1.0)
+    A, st, _ = orc.simulate_frequency(g, (1e12, 1.0, k, 0.0, 0.0), ps_pos=[[4.0, 4.0, 4.0]], ps_Lnu=[1.0],
+                                      n_ps_pk=200000, nthreads=8)
+
+    def trans(theta, phi):
+        u = np.array([math.sin(theta) * math.cos(phi), math.sin(theta) * math.sin(phi), math.cos(theta)])
+        d = min(4.0 / abs(x) if x != 0 else 1e30 for x in u)
+        return math.exp(-k * d) * math.sin(theta) / (4 * math.pi)
+
+    val, _ = integrate.dblquad(lambda th, ph: trans(th, ph), 0, 2 * math.pi, 0, math.pi, epsabs=1e-10)
+    frac = A.sum() / st["e_emitted"]
+    assert frac == pytest.approx(1 - val, abs=0.004)
+
+
+def _batched(fn, nb):
+    vals = np.array([fn(b) for b in range(nb)])
+    return vals.mean(axis=0), vals.std(axis=0, ddof=1) / math.sqrt(nb)
+
+
+def test_kirchhoff_isothermal_enclosure():
+    """Isotropic field B_nu(T0) and dust at T0 with emission on: the expected
+    absorbed power in every cell equals its emission 4 pi sigma_abs n V
+    B_nu(T0) w, whatever the albedo, g and densities (thermodynamic
+    equilibrium); and the temperature solve returns T0."""
+    T0, nu = 25.0, 4e12
+    B = orc.planck(nu, T0)
+    rng = np.random.default_rng(8)
+    d = rng.uniform(0.2, 3.0, (4, 5, 6)).astype(np.float32)
+    g = W.regular_grid(d, 0.4)
+    sabs, ssca, gg = 0.8, 1.1, 0.6
+    T = np.full(g.ncells, T0, np.float32)
+    L = 4 * math.pi * sabs * d.ravel().astype(np.float64) * 0.4 ** 3 * B
+
+    def run(b):
+        A, _, _ = orc.simulate_frequency(g, (nu, 1.0, sabs, ssca, gg), I_bg=B, n_bg=40000, T=T, n_dust=40000,
+                                         dust_mode=1, seed=100 + b, nthreads=8)
+        return A
+
+    m, se = _batched(run, 16)
+    z = (m - L) / se
+    assert abs(z.mean()) < 4 / math.sqrt(z.size) + 0.05
+    assert 0.6 < z.std() < 1.5
+    assert abs(np.mean(m / L) - 1) < 0.003
+    Tn, _ = orc.update_temperature(g, [nu], [1.0], [sabs], L)
+    assert np.allclose(Tn, T0, rtol=1e-7)
+
+
+def test_dust_emission_counts():
+    """Uniform mode: every leaf emits exactly n_dust / n_leaves packages.
+    Weighted mode (systematic sampling): each cell emits floor or ceil of
+    N L_c / sum L packages."""
+    rng = np.random.default_rng(12)
+    d = rng.uniform(0.0, 2.0, (2, 3, 4)).astype(np.float32)
+    d[0, 0, 0] = 0.0
+    g = W.regular_grid(d, 1.0)
+    T = rng.uniform(10, 60, g.ncells).astype(np.float32)
+    f = (5e12, 1.0, 0.5, 0.0, 0.0)
+    first = []
+    for j in range(48):
+        seg = orc.trace_package(g, f, orc.CLASS_DUST, j, T=T, n_dust=48, dust_mode=0)
+        # the empty cell 0 has zero luminosity: its packages carry no weight
+        # and are not traced
+        first.append(seg["cell"][0] if len(seg) else -1)
+    assert first[:2] == [-1, -1]
+    assert np.array_equal(np.bincount(first[2:], minlength=24), np.r_[0, np.full(23, 2)])
+    N = 3000
+    counts = np.zeros(24, int)
+    for j in range(N):
+        seg = orc.trace_package(g, f, orc.CLASS_DUST, j, T=T, n_dust=N, dust_mode=1, max_seg=1)
+        counts[seg["cell"][0]] += 1
+    L = np.array([0.5 * d.ravel()[c] * orc.planck(5e12, T[c]) for c in range(24)])
+    expect = N * L / L.sum()
+    assert np.all(np.abs(counts - expect) < 1.0 + 1e-9)
+    assert counts[0] == 0
+
+
+def test_octree_refined_once_equals_doubled_regular_grid():
+    """A grid with every root cell refined once into equal-density children
+    describes the same medium as the regular grid of twice the resolution:
+    background and point-source packages follow the same paths (segment by
+    segment, up to rounding) through corresponding cells."""
+    rng = np.random.default_rng(21)
+    base = rng.uniform(0.1, 2.0, (3, 3, 3)).astype(np.float32)
+    oc = W.refine_all_once(W.regular_grid(base, 2.0))
+    fine = np.repeat(np.repeat(np.repeat(base, 2, 0), 2, 1), 2, 2)
+    reg = W.regular_grid(fine, 1.0)
+    f = (1e13, 1.0, 0.3, 0.5, 0.5)
+    kw_o = dict(I_bg=1.0, ps_pos=[[1.3, 1.7, 1.1]], ps_Lnu=[1.0], n_bg=64, n_ps_pk=64)
+    kw_r = dict(I_bg=1.0, ps_pos=[[2.6, 3.4, 2.2]], ps_Lnu=[1.0], n_bg=64, n_ps_pk=64)
+
+    def to_fine(c):
+        o = c - oc.nroot
+        root, oct_ = divmod(o, 8)
+        rx, ry, rz = root % 3, (root // 3) % 3, root // 9
+        return (2 * rx + (oct_ & 1)) + 6 * ((2 * ry + ((oct_ >> 1) & 1)) + 6 * (2 * rz + ((oct_ >> 2) & 1)))
+
+    for cls in (orc.CLASS_BG, orc.CLASS_PS0):
+        for j in range(64):
+            so = orc.trace_package(oc, f, cls, j, **kw_o)
+            sr = orc.trace_package(reg, f, cls, j, **kw_r)
+            so = so[so["ds"] > 0]
+            sr = sr[sr["ds"] > 0]
+            assert len(so) == len(sr)
+            assert [to_fine(c) for c in so["cell"]] == list(sr["cell"])
+            assert np.allclose(2 * so["ds"], sr["ds"], rtol=1e-9, atol=1e-12)
+            assert list(so["event"]) == list(sr["event"])
+
+
+def test_step_cap_and_weight_floor_keep_energy():
+    """Step cap 1: every package that neither escapes nor scatters out in its
+    first segment is a runaway and deposits its remainder; energy still
+    balances.  A very opaque absorber ends packages at the weight floor."""
+    g = W.regular_grid(np.full((4, 4, 4), 1.0, np.float32), 1.0)
+    A, st, _ = orc.simulate_frequency(g, (1e12, 1.0, 0.2, 0.5, 0.0), I_bg=1.0, n_bg=2000, step_cap=1)
+    assert st["runaways"] > 0 and st["cell_steps"] == 2000
+    assert (A.sum() + st["e_escaped"]) / st["e_emitted"] == pytest.approx(1.0, abs=1e-12)
+    g2 = W.regular_grid(np.full((1, 1, 8), 1.0, np.float32), 1.0)
+    seg, wesc = orc.trace_from(g2, (1e12, 1.0, 20.0, 0.0, 0.0), [0.0, 0.5, 0.5], [1.0, 0.0, 0.0], 1.0, 1.0)
+    assert seg["event"][-1] == orc.FLOOR and wesc == 0.0 and len(seg) == 2
+
+
+def test_noise_scales_as_inverse_sqrt_packages():
+    """Per-cell noise (difference of two identical runs, Sect. 3.1) falls as
+    n_P^-1/2: quadrupling the packages halves the rms difference."""
+    rng = np.random.default_rng(31)
+    g = W.regular_grid(rng.uniform(0.5, 1.5, (10, 10, 10)).astype(np.float32), 1.0)
+    f = (1e13, 1.0, 0.2, 0.2, 0.3)
+
+    def rms(n):
+        a, _, _ = orc.simulate_frequency(g, f, I_bg=1.0, n_bg=n, seed=1, nthreads=8)
+        b, _, _ = orc.simulate_frequency(g, f, I_bg=1.0, n_bg=n, seed=2, nthreads=8)
+        return np.sqrt(np.mean((a - b) ** 2))
+
+    # 1000 cells: each rms is known to ~2%, the ratio to ~3%
+    ratio = rms(40000) / rms(160000)
+    assert 1.8 < ratio < 2.2
+
+
+# ---------------------------------------------------------------- map
+def test_map_uniform_temperature_column():
+    """Emission-only map of an isothermal column: I = (sigma_abs/sigma_ext)
+    B(T) (1 - e^{-tau}) whatever the density profile along the ray; empty
+    columns are dark; an octree refined once gives the same image at twice
+    the pixel count."""
+    rng = np.random.default_rng(3)
+    d = rng.uniform(0.0, 2.0, (4, 3, 5)).astype(np.float32)
+    d[:, 0, 0] = 0.0
+    g = W.regular_grid(d, 0.7)
+    T = np.full(g.ncells, 30.0, np.float32)
+    f = (2e12, 1.0, 0.6, 0.4, 0.0)
+    S = 0.6 / 1.0 * orc.planck(2e12, 30.0)
+    for axis, ax_np in ((2, 0), (1, 1), (0, 2), (2 | 4, 0)):
+        img = orc.map_image(g, f, T, axis)
+        tau = 1.0 * d.astype(np.float64).sum(axis=ax_np) * 0.7
+        assert np.allclose(img, S * (1 - np.exp(-tau)), rtol=1e-12, atol=0)
+    oc = W.refine_all_once(g)
+    To = np.full(oc.ncells, 30.0, np.float32)
+    img_o = orc.map_image(oc, f, To, 2)
+    img_r = orc.map_image(g, f, T, 2)
+    assert img_o.shape == (2 * img_r.shape[0], 2 * img_r.shape[1])
+    assert np.allclose(img_o[::2, ::2], img_r, rtol=1e-12)
+
+
+def test_map_front_attenuation_order():
+    """Two-cell column with different temperatures: the cell nearer the
+    observer attenuates the far one, I = S_near (1-e^{-t1}) + S_far (1-e^{-t2}) e^{-t1}."""
+    d = np.array([1.0, 2.0], np.float32).reshape(2, 1, 1)   # z = 0, 1
+    g = W.regular_grid(d, 1.0)
+    T = np.array([10.0, 40.0], np.float32)
+    f = (3e12, 1.0, 0.5, 0.0, 0.0)
+    B0, B1 = orc.planck(3e12, 10.0), orc.planck(3e12, 40.0)
+    t0, t1 = 0.5, 1.0
+    up = orc.map_image(g, f, T, 2)[0, 0]              # observer at +z: cell z=1 is near
+    assert up == pytest.approx(B1 * (1 - math.exp(-t1)) + B0 * (1 - math.exp(-t0)) * math.exp(-t1), rel=1e-12)
+    down = orc.map_image(g, f, T, 2 | 4)[0, 0]
+    assert down == pytest.approx(B0 * (1 - math.exp(-t0)) + B1 * (1 - math.exp(-t1)) * math.exp(-t0), rel=1e-12)
