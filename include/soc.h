@@ -1,0 +1,219 @@
+/*
+ * soc.h -- C ABI of the SOC Monte Carlo dust radiative-transfer hot path on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow Juvela, "SOC program for dust continuum radiative
+ * transfer" (A&A 2019, arXiv:1812.06632), Sect. 2.1.1 "Basic program": the
+ * cloud is one vector of cells on a hierarchical (octree) grid, photon
+ * packages are simulated one frequency at a time by a kernel that counts
+ * the energy absorbed in each cell, a second kernel solves the equilibrium
+ * dust temperature from the frequency-integrated absorbed energy, and a
+ * third makes surface-brightness maps from that solution.
+ *
+ * Conventions shared by every call
+ *  - Every call returns soc_status (0 = SOC_OK, < 0 = error).  No call
+ *    aborts, exits or throws; on error the text of the failure is available
+ *    from soc_last_error(ctx) until the next call on that context.
+ *  - Pointers named d_* are device pointers (HIP device memory of the
+ *    context's device, e.g. torch tensors' data_ptr()).  Other pointers are
+ *    host pointers, read or written only during the call.
+ *  - Large arrays are owned by the caller; a soc_grid borrows the caller's
+ *    cell array for its lifetime.  The library allocates only private
+ *    scratch, owned by the context (or grid) and freed by its destroy call.
+ *  - Work is enqueued on the context's HIP stream and the call returns
+ *    without waiting, unless it returns host results (statistics, traces),
+ *    in which case it synchronises that stream before returning.
+ *  - Units are cgs: cell size in cm, density in H cm^-3, cross sections in
+ *    cm^2 per H, intensity in erg s^-1 cm^-2 Hz^-1 sr^-1, luminosity in
+ *    erg s^-1 Hz^-1, absorbed energy in erg s^-1 per cell (already
+ *    multiplied by the frequency quadrature weight), temperature in K.
+ *    Positions are in root-cell units inside [0,nx) x [0,ny) x [0,nz).
+ *  - Validation happens before any launch: NULL pointers, negative counts,
+ *    negative or non-finite cross sections, |g| >= 1 -> SOC_EINVAL; a
+ *    malformed grid -> SOC_EGRID; HIP failures -> SOC_EHIP.
+ */
+#ifndef SOC_H
+#define SOC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SOC_OK = 0,
+    SOC_EINVAL = -1,   /* bad argument */
+    SOC_ENOMEM = -2,   /* device or host allocation failed */
+    SOC_EHIP = -3,     /* HIP runtime error */
+    SOC_EGRID = -4,    /* malformed grid */
+    SOC_ESTATE = -5    /* call not valid in the current state */
+} soc_status;
+
+typedef struct soc_ctx_s *soc_ctx;
+typedef struct soc_grid_s *soc_grid;
+
+/* ---------------------------------------------------------------- context */
+/* Create a context bound to HIP device `hip_device` and the HIP stream
+ * `hip_stream` (a hipStream_t; NULL = the device's null stream).  The
+ * stream is borrowed, never destroyed by the library. */
+soc_status soc_ctx_create(int32_t hip_device, void *hip_stream, soc_ctx *out);
+void soc_ctx_destroy(soc_ctx ctx);
+soc_status soc_ctx_set_stream(soc_ctx ctx, void *hip_stream);
+/* Text of the last failure on this context ("" if none).  Valid until the
+ * next call on the context. */
+const char *soc_last_error(soc_ctx ctx);
+
+/* Tunables of the Monte Carlo kernels (defaults in brackets). */
+typedef enum {
+    SOC_OPT_STEP_CAP = 0,        /* steps per package before it is stopped [10000000] */
+    SOC_OPT_BLOCK = 1,           /* threads per workgroup of the MC kernel, 64..1024 [256] */
+    SOC_OPT_BLOCKS_PER_CU = 2,   /* persistent workgroups launched per compute unit [8] */
+    SOC_OPT_REFILL_MIN = 3,      /* refill a wave once this many lanes are idle, 1..64 [1] */
+    SOC_OPT_INNER_STEPS = 4,     /* cell steps between refill checks, 1..64 [1] */
+    SOC_OPT_TIMING = 5           /* 1 = time each MC launch with HIP events [0] */
+} soc_option;
+soc_status soc_ctx_set_option(soc_ctx ctx, soc_option opt, int64_t value);
+soc_status soc_ctx_get_option(soc_ctx ctx, soc_option opt, int64_t *value);
+/* With SOC_OPT_TIMING on: total milliseconds and number of timed MC kernel
+ * launches since the last reset (synchronises the stream). */
+soc_status soc_ctx_mc_timing(soc_ctx ctx, double *total_ms, int64_t *launches, int32_t reset);
+
+/* ---------------------------------------------------------------- grid */
+/* Hierarchical grid of Sect. 2.1.1.  The cells form one vector: the root
+ * grid first (x fastest, then y, then z), then every cell of level 2, then
+ * level 3 and so on.  Each cell holds one 32-bit word: an FP32 density >= 0,
+ * or, for a refined cell, the int32 value -(index of the first cell of its
+ * child octet).  Octets are 8 consecutive cells with child octant
+ * o = ix + 2 iy + 4 iz (i* = 1 for the upper half of the parent on that
+ * axis).  nlevels == 1 is a regular grid. */
+typedef struct {
+    int32_t nx, ny, nz, nlevels;
+    int64_t ncells;
+    const int64_t *level_offset;   /* host, nlevels+1: first cell of each level, last = ncells */
+    double root_cell_cm;           /* edge of a root cell in cm */
+    const uint32_t *d_words;       /* device, ncells words, borrowed */
+} soc_grid_desc;
+
+/* Validate the grid on the device (links in range, octet-aligned, every
+ * octet linked exactly once, densities finite and >= 0) and build the
+ * reverse links of Sect. 2.1.1 (one parent index per non-root octet) and
+ * the leaf list.  Synchronises the stream.  SOC_EGRID on a malformed grid. */
+soc_status soc_build_grid(soc_ctx ctx, const soc_grid_desc *desc, soc_grid *out);
+void soc_grid_destroy(soc_grid grid);
+/* Number of leaf cells and (optional) device pointer to the reverse links
+ * (int32 per non-root octet; NULL for a regular grid). */
+soc_status soc_grid_info(soc_grid grid, int64_t *n_leaves, const int32_t **d_parent);
+
+/* ---------------------------------------------------------------- simulation */
+/* Dust properties at the simulated frequency (Sect. 2.1.1: the kernel only
+ * needs the data of one frequency).  w_nu is the quadrature weight (Hz) by
+ * which this frequency's energy enters the frequency integral. */
+typedef struct {
+    double nu, w_nu;               /* Hz, Hz */
+    double sigma_abs, sigma_sca;   /* cm^2 per H */
+    double g;                      /* Henyey-Greenstein asymmetry, |g| < 1 */
+} soc_freq;
+
+typedef struct { double x, y, z, L_nu; } soc_point_source;   /* root units; erg s^-1 Hz^-1 */
+
+/* Radiation sources of one call (Sect. 2.2, 3.1, 3.2).
+ *  - background: isotropic intensity I_bg_nu entering through the box
+ *    faces, total energy pi I_bg w A_box, n_bg packages;
+ *  - point sources: n_ps <= 32 isotropic sources, each with n_ps_pk
+ *    packages and energy L_nu w;
+ *  - dust emission at temperatures d_T (NULL = off): cell c emits
+ *    4 pi sigma_abs n_c V_c B_nu(T_c) w; dust_mode 0 sends the same number
+ *    of packages from every leaf (n_dust must be a multiple of the leaf
+ *    count), dust_mode 1 draws n_dust packages in proportion to the cell
+ *    luminosity by systematic sampling. */
+typedef struct {
+    double I_bg_nu;
+    int32_t n_ps;
+    const soc_point_source *ps;    /* host, n_ps entries */
+    const float *d_T;              /* device, ncells temperatures, or NULL */
+    uint64_t n_bg, n_ps_pk, n_dust;
+    int32_t dust_mode;
+} soc_sources;
+
+typedef struct {
+    uint64_t packages, cell_steps, scatterings, runaways;
+    double e_emitted, e_absorbed, e_escaped;   /* erg s^-1 */
+} soc_sim_stats;
+
+/* Monte Carlo pass at one frequency: emit every package, draw its free
+ * path in scattering optical depth, step it cell by cell depositing
+ * W (1 - exp(-k_abs d)) in each cell crossed, scatter it with the
+ * Henyey-Greenstein function, until it leaves the box, falls below 1e-12
+ * of its initial weight or reaches the step cap (the rest of its weight is
+ * then deposited in its cell).  Deposits are added (+=) to d_absorbed
+ * (FP64, ncells).  Random numbers come from Philox4x32-10 with counter
+ * (block, package id, freq_index, iteration << 8 | class) and key = seed,
+ * class 0 = background, 1 = dust, 2 + s = point source s, so each
+ * package's numbers depend only on its identity.  If stats is non-NULL the
+ * call synchronises and fills it with this call's totals. */
+soc_status soc_simulate_frequency(soc_ctx ctx, soc_grid grid, const soc_freq *freq,
+                                  const soc_sources *src, uint64_t seed, uint32_t iteration,
+                                  uint32_t freq_index, double *d_absorbed, soc_sim_stats *stats);
+
+/* Statistics summed over every soc_simulate_frequency call on the context
+ * since the last reset (synchronises). */
+soc_status soc_read_stats(soc_ctx ctx, soc_sim_stats *out, int32_t reset);
+
+/* Deterministic single-package mode: trace n packages of one class
+ * (ids[i] within that class) with the same random numbers and the same
+ * transport code as soc_simulate_frequency, recording up to max_seg
+ * segments each.  precision 0 = the FP32 production arithmetic, 1 = the
+ * same code in FP64.  out (host) holds n * max_seg segments; n_seg (host)
+ * receives each package's full segment count (may exceed max_seg). */
+typedef struct { int64_t cell; double ds; int32_t event; int32_t pad; } soc_segment;
+enum { SOC_EV_CROSS = 0, SOC_EV_SCATTER = 1, SOC_EV_ESCAPE = 2, SOC_EV_FLOOR = 3, SOC_EV_RUNAWAY = 4 };
+soc_status soc_trace_packages(soc_ctx ctx, soc_grid grid, const soc_freq *freq, const soc_sources *src,
+                              uint64_t seed, uint32_t iteration, uint32_t freq_index, uint32_t cls,
+                              const uint32_t *ids, int32_t n, int32_t precision,
+                              soc_segment *out, int32_t max_seg, int32_t *n_seg);
+
+/* ---------------------------------------------------------------- temperature */
+/* Equilibrium temperature table (Sect. 2.1.1 temperature kernel): built on
+ * the device from the K frequencies of the dust emission model (host
+ * arrays nu, w_nu, sigma_abs) as Gamma(T) = 4 pi sum_k w_k sigma_abs,k
+ * B_nu_k(T) on nT log-spaced temperatures in [T_floor, T_max], 16 <= nT <= 4096
+ * (the table is staged in LDS by the temperature kernel). */
+typedef struct soc_temp_table_s *soc_temp_table;
+soc_status soc_temp_table_build(soc_ctx ctx, int32_t K, const double *nu, const double *w_nu,
+                                const double *sigma_abs, double T_floor, double T_max, int32_t nT,
+                                soc_temp_table *out);
+void soc_temp_table_destroy(soc_temp_table t);
+
+typedef struct {
+    double mean_T;            /* over leaves with n > 0 */
+    double hot5_mean_T;       /* mean over the hottest 5% (ceil) of those leaves */
+    double mean_rel_change;   /* mean |T_new - T_old| / T_old over cells with T_old > 0 (NaN if none) */
+    uint64_t clamped;         /* leaves clamped to T_floor (incl. unhit) or T_max */
+} soc_temp_stats;
+
+/* Solve Gamma(T_c) = A_c / (n_c V_c) for every leaf (inverse of the
+ * tabulated log-log relation).  Empty and refined cells get T = 0; unhit
+ * cells and values outside the table are clamped to [T_floor, T_max] and
+ * counted.  d_T_old may equal d_T_new or be NULL (then no relative
+ * change).  If stats is non-NULL the call synchronises and fills it (the
+ * hottest-5% mean is resolved on a 16384-bin log-T histogram). */
+soc_status soc_update_temperature(soc_ctx ctx, soc_grid grid, soc_temp_table table,
+                                  const double *d_absorbed, const float *d_T_old, float *d_T_new,
+                                  soc_temp_stats *stats);
+
+/* ---------------------------------------------------------------- map */
+/* Emission map (Sect. 2.1.1 map kernel, pixel = smallest cell, Sect. 3.2)
+ * seen along root-grid axis `axis & 3` (0..2) from the positive side, or
+ * from the negative side when bit 2 is set:
+ * I = sum over cells on the ray of S_c (1 - exp(-dtau)) exp(-tau_front),
+ * S_c = (sigma_abs / sigma_ext) B_nu(T_c), dtau = sigma_ext n_c ds.
+ * d_image (device, FP32) has npy rows of npx pixels: npx spans the lower of
+ * the two other axes, npy the higher, each N * 2^(nlevels-1) pixels. */
+soc_status soc_map(soc_ctx ctx, soc_grid grid, const soc_freq *freq, const float *d_T, int32_t axis,
+                   float *d_image, int32_t npx, int32_t npy);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SOC_H */

@@ -164,10 +164,11 @@ def _stats_dict(st):
 
 def simulate_frequency(grid, freq, *, I_bg=0.0, ps_pos=None, ps_Lnu=None, T=None, n_bg=0, n_ps_pk=0,
                        n_dust=0, dust_mode=1, seed=1, iteration=0, freq_index=0, step_cap=0,
-                       nthreads=1, absorbed=None, want_path=False):
+                       nthreads=1, absorbed=None, want_path=False, hits=None):
     """One Monte Carlo pass at one frequency.  freq = (nu, w, sigma_abs,
     sigma_sca, g).  Returns (absorbed float64[ncells], stats dict,
-    path lengths or None)."""
+    path lengths or None).  hits: optional int64[ncells] accumulated with
+    the number of depositing segments per cell."""
     gv = GridView(grid)
     sv = _SourcesView(I_bg, ps_pos, ps_Lnu, T, n_bg, n_ps_pk, n_dust, dust_mode)
     f = _freq(freq)
@@ -179,7 +180,8 @@ def simulate_frequency(grid, freq, *, I_bg=0.0, ps_pos=None, ps_Lnu=None, T=None
     rc = lib().orc_simulate_frequency(C.byref(gv.s), C.byref(f), C.byref(sv.s), C.c_uint64(seed),
                                       C.c_uint32(iteration), C.c_uint32(freq_index), C.c_int64(step_cap),
                                       C.c_int32(nthreads), _p(absorbed, C.c_double), C.byref(st),
-                                      _p(path, C.c_double) if path is not None else None)
+                                      _p(path, C.c_double) if path is not None else None,
+                                      _p(hits, C.c_int64) if hits is not None else None)
     if rc != 0:
         raise ValueError(f"orc_simulate_frequency failed: {rc}")
     return absorbed, _stats_dict(st), path

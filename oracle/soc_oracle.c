@@ -52,7 +52,7 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
     out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
-double orc_u01(uint32_t x) { return ((double)(x >> 8) + 0.5) * (1.0 / 16777216.0); }
+double orc_u01(uint32_t x) { return ((double)(x >> 9) + 0.5) * (1.0 / 8388608.0); }
 
 /* One stream per package: counter = (block, package id, frequency index,
  * iteration<<8 | source class), key = (seed low word, seed high word). */
@@ -246,7 +246,7 @@ typedef struct {
  * in the leaf; the package crosses, scatters (HG), escapes the box, falls
  * under the weight floor or hits the step cap. */
 static void transport(const orc_grid *g, const orc_freq *f, double p[3], double u[3], double W0,
-                      double tau, stream_t *rs, int64_t cap, double *absorbed, pk_tally *t,
+                      double tau, stream_t *rs, int64_t cap, double *absorbed, int64_t *hits, pk_tally *t,
                       orc_segment *seg, int32_t max_seg, int32_t *nseg)
 {
     double W = W0;
@@ -279,6 +279,7 @@ static void transport(const orc_grid *g, const orc_freq *f, double p[3], double 
         }
         double dep = W * (-expm1(-ka * d));
         if (absorbed && dep != 0.0) absorbed[c] += dep;
+        if (hits && dep != 0.0) hits[c] += 1;
         W -= dep;
         p[0] += d * u[0]; p[1] += d * u[1]; p[2] += d * u[2];
         t->steps++;
@@ -437,7 +438,7 @@ static int64_t weighted_cell(const sim_ctx *X, uint64_t j)
 
 /* Emission of global package gid (class order bg | ps0..psN-1 | dust) and
  * its transport.  Returns the initial weight W0. */
-static double run_package(const sim_ctx *X, uint64_t gid, double *absorbed, pk_tally *t,
+static double run_package(const sim_ctx *X, uint64_t gid, double *absorbed, int64_t *hits, pk_tally *t,
                           orc_segment *seg, int32_t max_seg, int32_t *nseg)
 {
     const orc_grid *g = X->g;
@@ -500,7 +501,7 @@ static double run_package(const sim_ctx *X, uint64_t gid, double *absorbed, pk_t
         iso_dir(x3, x4, u);
     }
     double tau = -log(stream_next(&rs));
-    transport(g, X->f, p, u, W0, tau, &rs, X->cap, absorbed, t, seg, max_seg, nseg);
+    transport(g, X->f, p, u, W0, tau, &rs, X->cap, absorbed, hits, t, seg, max_seg, nseg);
     return W0;
 }
 
@@ -520,7 +521,7 @@ static int32_t check_inputs(const orc_grid *g, const orc_freq *f, const orc_sour
 int32_t orc_simulate_frequency(const orc_grid *g, const orc_freq *f, const orc_sources *s,
                                uint64_t seed, uint32_t iteration, uint32_t freq_index,
                                int64_t step_cap, int32_t nthreads,
-                               double *absorbed, orc_stats *stats, double *path_len)
+                               double *absorbed, orc_stats *stats, double *path_len, int64_t *hits)
 {
     int32_t rc = check_inputs(g, f, s);
     if (rc) return rc;
@@ -541,17 +542,18 @@ int32_t orc_simulate_frequency(const orc_grid *g, const orc_freq *f, const orc_s
 #endif
     {
         double *priv = (double *)calloc((size_t)ncells, sizeof(double));
+        int64_t *phits = hits ? (int64_t *)calloc((size_t)ncells, sizeof(int64_t)) : NULL;
         orc_stats loc;
         memset(&loc, 0, sizeof loc);
-        if (!priv) failed = 1;
+        if (!priv || (hits && !phits)) failed = 1;
 #ifdef _OPENMP
 #pragma omp for schedule(dynamic, 64)
 #endif
         for (int64_t gid = 0; gid < (int64_t)NT; ++gid) {
-            if (!priv) continue;
+            if (!priv || (hits && !phits)) continue;
             pk_tally t;
             memset(&t, 0, sizeof t);
-            double W0 = run_package(&X, (uint64_t)gid, priv, &t, NULL, 0, NULL);
+            double W0 = run_package(&X, (uint64_t)gid, priv, phits, &t, NULL, 0, NULL);
             loc.packages++;
             loc.cell_steps += t.steps;
             loc.scatterings += t.scatterings;
@@ -570,11 +572,14 @@ int32_t orc_simulate_frequency(const orc_grid *g, const orc_freq *f, const orc_s
                 for (int64_t c = 0; c < ncells; ++c) a += priv[c];
                 loc.e_absorbed = a;
             }
+            if (phits)
+                for (int64_t c = 0; c < ncells; ++c) hits[c] += phits[c];
             tot.packages += loc.packages; tot.cell_steps += loc.cell_steps;
             tot.scatterings += loc.scatterings; tot.runaways += loc.runaways;
             tot.e_emitted += loc.e_emitted; tot.e_escaped += loc.e_escaped; tot.e_absorbed += loc.e_absorbed;
         }
         free(priv);
+        free(phits);
     }
     sim_free(&X);
     if (failed) return -3;
@@ -610,7 +615,7 @@ int32_t orc_trace_package(const orc_grid *g, const orc_freq *f, const orc_source
     pk_tally t;
     memset(&t, 0, sizeof t);
     *n_seg = 0;
-    run_package(&X, gid, NULL, &t, out, max_seg, n_seg);
+    run_package(&X, gid, NULL, NULL, &t, out, max_seg, n_seg);
     sim_free(&X);
     return 0;
 }
@@ -627,7 +632,7 @@ int32_t orc_trace_from(const orc_grid *g, const orc_freq *f, const double p0[3],
     pk_tally t;
     memset(&t, 0, sizeof t);
     int32_t ns = 0;
-    transport(g, f, p, u, W0, tau0, &rs, step_cap > 0 ? step_cap : 10000000, absorbed, &t, out, max_seg, &ns);
+    transport(g, f, p, u, W0, tau0, &rs, step_cap > 0 ? step_cap : 10000000, absorbed, NULL, &t, out, max_seg, &ns);
     if (n_seg) *n_seg = ns;
     if (w_escaped) *w_escaped = t.escaped;
     return 0;

@@ -82,7 +82,8 @@ typedef struct { int64_t cell; double ds; int32_t event; } orc_segment;
 
 /* ---- random numbers: Philox4x32-10 (Salmon et al. 2011, SC'11) ---- */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
-/* Uniform in (0,1): ((x >> 8) + 0.5) * 2^-24, exact in FP32 and FP64. */
+/* Uniform in (0,1): ((x >> 9) + 0.5) * 2^-23 -- an odd multiple of 2^-24,
+ * exactly representable in FP32 and FP64. */
 double orc_u01(uint32_t x);
 /* n consecutive uniforms of one package stream (for statistical pins). */
 void orc_uniforms(uint64_t seed, uint32_t iteration, uint32_t cls, uint32_t freq_index,
@@ -101,11 +102,12 @@ void orc_hg_scatter(double g, const double u0[3], int32_t n, const double *xi, d
 /* ---- the Monte Carlo pass at one frequency ---- */
 /* absorbed (+=) must hold ncells doubles.  path_len (optional) receives the
  * total path length in root units of each package, in class order
- * [bg | ps0 | ps1 ... | dust].  Returns 0 or a negative error. */
+ * [bg | ps0 | ps1 ... | dust].  hits (optional, +=) counts the segments that
+ * deposited energy in each cell.  Returns 0 or a negative error. */
 int32_t orc_simulate_frequency(const orc_grid *g, const orc_freq *f, const orc_sources *s,
                                uint64_t seed, uint32_t iteration, uint32_t freq_index,
                                int64_t step_cap, int32_t nthreads,
-                               double *absorbed, orc_stats *stats, double *path_len);
+                               double *absorbed, orc_stats *stats, double *path_len, int64_t *hits);
 
 /* Segments of one package (class, package id within that class). */
 int32_t orc_trace_package(const orc_grid *g, const orc_freq *f, const orc_sources *s,

@@ -1,0 +1,702 @@
+// api.hip -- host implementation of the C ABI declared in include/soc.h.
+//
+// Each call validates its arguments before any launch, converts the
+// physical inputs of one frequency into the per-launch argument block
+// (McArgs) and enqueues the kernels on the context's stream.  The library
+// owns only private scratch (statistics, the refill counter, dust-emission
+// tables, trace buffers), grown on demand and freed with the context.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "soc.h"
+#include "soc_device.h"
+#include "soc_kernels.h"
+
+using namespace soc;
+
+struct soc_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int num_cus = 256;
+    int64_t step_cap = 10000000;
+    int64_t block = 256;
+    int64_t blocks_per_cu = 8;
+    int64_t refill_min = 1;
+    int64_t inner_steps = 1;
+    int64_t timing = 0;
+    int64_t chunk = 256;
+    // scratch
+    DevStats *d_stats = nullptr;              // [0] per call, [1] running total
+    unsigned long long *d_counter = nullptr;
+    double *d_tmp_out = nullptr;              // small result buffer (temperature stats)
+    double *d_L = nullptr, *d_incl = nullptr, *d_scan = nullptr;
+    int64_t cap_L = 0, cap_incl = 0, cap_scan = 0;
+    int32_t *d_pkcell = nullptr;
+    uint64_t cap_pk = 0;
+    double *d_tacc = nullptr;
+    unsigned int *d_hist_n = nullptr;
+    double *d_hist_T = nullptr;
+    std::vector<hipEvent_t> ev_start, ev_stop;
+};
+
+struct soc_grid_s {
+    soc_ctx ctx = nullptr;
+    int32_t nx = 0, ny = 0, nz = 0, nlevels = 0;
+    int64_t ncells = 0, nroot = 0, nleaves = 0;
+    std::vector<int64_t> level_offset;
+    double root_cell_cm = 0.0;
+    const uint32_t *d_words = nullptr;
+    int32_t *d_parent = nullptr;
+    int64_t *d_leaves = nullptr;
+};
+
+struct soc_temp_table_s {
+    soc_ctx ctx = nullptr;
+    int32_t nT = 0;
+    double T_floor = 0.0, T_max = 0.0, lnTf = 0.0, dlnT = 0.0;
+    double *d_lnG = nullptr;
+};
+
+namespace {
+
+soc_status fail(soc_ctx c, soc_status s, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                         \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail((ctx), SOC_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+soc_status grow(soc_ctx c, T **p, int64_t &cap, int64_t need)
+{
+    if (need <= cap && *p) return SOC_OK;
+    if (*p) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return fail(c, SOC_EHIP, "sync before regrow: %s", hipGetErrorString(e));
+        (void)hipFree(*p);
+        *p = nullptr;
+        cap = 0;
+    }
+    if (hipMalloc((void **)p, sizeof(T) * (size_t)(need > 0 ? need : 1)) != hipSuccess) {
+        *p = nullptr;
+        return fail(c, SOC_ENOMEM, "device allocation of %lld elements failed", (long long)need);
+    }
+    cap = need;
+    return SOC_OK;
+}
+
+bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+
+soc_status check_freq(soc_ctx c, const soc_freq *f)
+{
+    if (!f) return fail(c, SOC_EINVAL, "freq is NULL");
+    if (!(std::isfinite(f->nu) && f->nu > 0.0)) return fail(c, SOC_EINVAL, "nu must be finite and > 0");
+    if (!finite_nonneg(f->w_nu)) return fail(c, SOC_EINVAL, "w_nu must be finite and >= 0");
+    if (!finite_nonneg(f->sigma_abs) || !finite_nonneg(f->sigma_sca))
+        return fail(c, SOC_EINVAL, "cross sections must be finite and >= 0");
+    if (!(std::fabs(f->g) < 1.0)) return fail(c, SOC_EINVAL, "|g| must be < 1");
+    return SOC_OK;
+}
+
+// Per-frequency argument block shared by the production and trace kernels.
+soc_status prepare(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *s, uint64_t seed,
+                   uint32_t iteration, uint32_t freq_index, double *d_absorbed, McArgs &A)
+{
+    soc_status st = check_freq(c, f);
+    if (st) return st;
+    if (!g) return fail(c, SOC_EINVAL, "grid is NULL");
+    if (g->ctx != c) return fail(c, SOC_EINVAL, "grid belongs to another context");
+    if (g->nlevels != 1) return fail(c, SOC_EINVAL, "octree grids are not supported by this build of the MC kernel");
+    if (!s) return fail(c, SOC_EINVAL, "sources is NULL");
+    if (!finite_nonneg(s->I_bg_nu)) return fail(c, SOC_EINVAL, "I_bg_nu must be finite and >= 0");
+    if (s->n_ps < 0 || s->n_ps > kMaxPs) return fail(c, SOC_EINVAL, "n_ps must be in [0, %d]", kMaxPs);
+    if (s->n_ps > 0 && !s->ps) return fail(c, SOC_EINVAL, "ps is NULL");
+    if (s->d_T && s->dust_mode != 0 && s->dust_mode != 1) return fail(c, SOC_EINVAL, "dust_mode must be 0 or 1");
+    if (s->n_bg > 0xFFFFFFFFull || s->n_ps_pk > 0xFFFFFFFFull || s->n_dust > 0x7FFFFFFFull)
+        return fail(c, SOC_EINVAL, "package counts exceed the 32-bit package id range");
+
+    std::memset(&A, 0, sizeof A);
+    A.words = g->d_words;
+    A.parent = g->d_parent;
+    A.nx = g->nx; A.ny = g->ny; A.nz = g->nz; A.nlevels = g->nlevels;
+    A.ncells = g->ncells;
+    for (int i = 0; i <= kMaxLevels; ++i)
+        A.level_offset[i] = i <= g->nlevels ? g->level_offset[i] : g->ncells;
+    const double s_cm = g->root_cell_cm;
+    A.ks_d = f->sigma_sca * s_cm;
+    A.ka_d = f->sigma_abs * s_cm;
+    A.g_d = f->g;
+    A.ks_f = (float)A.ks_d;
+    A.ka_f = (float)A.ka_d;
+    A.g_f = (float)f->g;
+
+    // background: pi I w A_box through the faces, face chosen by area
+    const double N0 = g->nx, N1 = g->ny, N2 = g->nz;
+    const double area[6] = {N1 * N2, N1 * N2, N0 * N2, N0 * N2, N0 * N1, N0 * N1};
+    double tot = 0.0;
+    for (int k = 0; k < 6; ++k) tot += area[k];
+    double cum = 0.0;
+    for (int k = 0; k < 6; ++k) {
+        cum += area[k];
+        A.face_cum[k] = cum;
+    }
+    A.face_tot = tot;
+    const double E_bg = M_PI * s->I_bg_nu * f->w_nu * tot * (s_cm * s_cm);
+    A.n_bg = s->n_bg;
+    A.W_bg = s->n_bg ? E_bg / (double)s->n_bg : 0.0;
+
+    A.n_ps = s->n_ps;
+    A.n_ps_pk = s->n_ps > 0 ? s->n_ps_pk : 0;
+    for (int i = 0; i < s->n_ps; ++i) {
+        const soc_point_source &q = s->ps[i];
+        if (!(q.x >= 0.0 && q.x < N0 && q.y >= 0.0 && q.y < N1 && q.z >= 0.0 && q.z < N2))
+            return fail(c, SOC_EINVAL, "point source %d lies outside the box", i);
+        if (!finite_nonneg(q.L_nu)) return fail(c, SOC_EINVAL, "point source %d: L_nu must be finite and >= 0", i);
+        A.ps[i].x = q.x; A.ps[i].y = q.y; A.ps[i].z = q.z;
+        A.ps[i].W = A.n_ps_pk ? q.L_nu * f->w_nu / (double)A.n_ps_pk : 0.0;
+    }
+
+    // dust emission: per-cell luminosity, inclusive cumulative sum and, for
+    // the weighted mode, the cell of every package
+    A.n_dust = 0;
+    A.dust_mode = s->dust_mode;
+    if (s->d_T && s->n_dust > 0) {
+        A.n_dust = s->n_dust;
+        if ((st = grow(c, &c->d_L, c->cap_L, g->ncells))) return st;
+        HIPCHK(c, launch_dust_luminosity(g->d_words, g->ncells, g->level_offset.data(), g->nlevels, s_cm, f->nu,
+                                         f->sigma_abs, f->w_nu, s->d_T, c->d_L, c->stream));
+        A.dust_L = c->d_L;
+        if (s->dust_mode == 0) {
+            if (s->n_dust % (uint64_t)g->nleaves != 0)
+                return fail(c, SOC_EINVAL, "uniform dust mode needs n_dust to be a multiple of the %lld leaves",
+                            (long long)g->nleaves);
+            A.per_leaf = s->n_dust / (uint64_t)g->nleaves;
+            A.leaves = g->d_leaves;
+        } else {
+            if ((st = grow(c, &c->d_incl, c->cap_incl, g->ncells))) return st;
+            if ((st = grow(c, &c->d_scan, c->cap_scan, (int64_t)scan_f64_scratch_elems(g->ncells)))) return st;
+            HIPCHK(c, launch_scan_f64(c->d_L, c->d_incl, g->ncells, c->d_scan, c->stream));
+            int64_t cap_pk = (int64_t)c->cap_pk;
+            if ((st = grow(c, &c->d_pkcell, cap_pk, (int64_t)s->n_dust))) return st;
+            c->cap_pk = (uint64_t)cap_pk;
+            // systematic offset: first uniform of the stream of package id 2^32-1 of the dust class
+            uint32_t x0 = 0, x1 = 0xFFFFFFFFu, x2 = freq_index, x3 = (iteration << 8) | kClassDust;
+            philox4x32_10(x0, x1, x2, x3, (uint32_t)seed, (uint32_t)(seed >> 32));
+            const double u_sys = u01<double>(x0);
+            HIPCHK(c, launch_dust_select(c->d_incl, g->ncells, s->n_dust, u_sys, c->d_pkcell, c->stream));
+            A.dust_incl = c->d_incl;
+            A.dust_cell = c->d_pkcell;
+        }
+    }
+    A.n_total = A.n_bg + (uint64_t)A.n_ps * A.n_ps_pk + A.n_dust;
+    A.key0 = (uint32_t)seed;
+    A.key1 = (uint32_t)(seed >> 32);
+    A.freq_index = freq_index;
+    A.iteration = iteration;
+    A.step_cap = c->step_cap;
+    A.absorbed = d_absorbed;
+    A.next_id = c->d_counter;
+    A.st_call = c->d_stats;
+    A.st_total = c->d_stats + 1;
+    A.refill_min = (int32_t)c->refill_min;
+    A.inner_steps = (int32_t)c->inner_steps;
+    A.chunk = (int32_t)c->chunk;
+    return SOC_OK;
+}
+
+void to_public(const DevStats &d, soc_sim_stats *o)
+{
+    o->packages = d.packages;
+    o->cell_steps = d.steps;
+    o->scatterings = d.scatterings;
+    o->runaways = d.runaways;
+    o->e_emitted = d.emitted;
+    o->e_absorbed = d.absorbed;
+    o->e_escaped = d.escaped;
+}
+
+}  // namespace
+
+extern "C" {
+
+soc_status soc_ctx_create(int32_t hip_device, void *hip_stream, soc_ctx *out)
+{
+    if (!out) return SOC_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return SOC_EHIP;
+    if (hip_device < 0 || hip_device >= ndev) return SOC_EINVAL;
+    soc_ctx c = new (std::nothrow) soc_ctx_s;
+    if (!c) return SOC_ENOMEM;
+    c->device = hip_device;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipSetDevice(hip_device) != hipSuccess) { delete c; return SOC_EHIP; }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->num_cus = prop.multiProcessorCount;
+    if (hipMalloc((void **)&c->d_stats, 2 * sizeof(DevStats)) != hipSuccess ||
+        hipMalloc((void **)&c->d_counter, sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc((void **)&c->d_tmp_out, 8 * sizeof(double)) != hipSuccess) {
+        soc_ctx_destroy(c);
+        return SOC_ENOMEM;
+    }
+    if (launch_fill_u64((unsigned long long *)c->d_stats, 0ull, 2 * (int64_t)(sizeof(DevStats) / 8), c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        soc_ctx_destroy(c);
+        return SOC_EHIP;
+    }
+    *out = c;
+    return SOC_OK;
+}
+
+void soc_ctx_destroy(soc_ctx c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto e : c->ev_start) (void)hipEventDestroy(e);
+    for (auto e : c->ev_stop) (void)hipEventDestroy(e);
+    (void)hipFree(c->d_stats);
+    (void)hipFree(c->d_counter);
+    (void)hipFree(c->d_tmp_out);
+    (void)hipFree(c->d_L);
+    (void)hipFree(c->d_incl);
+    (void)hipFree(c->d_scan);
+    (void)hipFree(c->d_pkcell);
+    (void)hipFree(c->d_tacc);
+    (void)hipFree(c->d_hist_n);
+    (void)hipFree(c->d_hist_T);
+    delete c;
+}
+
+soc_status soc_ctx_set_stream(soc_ctx c, void *hip_stream)
+{
+    if (!c) return SOC_EINVAL;
+    c->stream = (hipStream_t)hip_stream;
+    return SOC_OK;
+}
+
+const char *soc_last_error(soc_ctx c) { return c ? c->err.c_str() : "NULL context"; }
+
+soc_status soc_ctx_set_option(soc_ctx c, soc_option opt, int64_t v)
+{
+    if (!c) return SOC_EINVAL;
+    switch (opt) {
+    case SOC_OPT_STEP_CAP:
+        if (v < 1) return fail(c, SOC_EINVAL, "step cap must be >= 1");
+        c->step_cap = v;
+        return SOC_OK;
+    case SOC_OPT_BLOCK:
+        if (v < 64 || v > 1024 || v % 64) return fail(c, SOC_EINVAL, "block must be a multiple of 64 in [64,1024]");
+        c->block = v;
+        return SOC_OK;
+    case SOC_OPT_BLOCKS_PER_CU:
+        if (v < 1 || v > 64) return fail(c, SOC_EINVAL, "blocks per CU must be in [1,64]");
+        c->blocks_per_cu = v;
+        return SOC_OK;
+    case SOC_OPT_REFILL_MIN:
+        if (v < 1 || v > 64) return fail(c, SOC_EINVAL, "refill threshold must be in [1,64]");
+        c->refill_min = v;
+        return SOC_OK;
+    case SOC_OPT_INNER_STEPS:
+        if (v < 1 || v > 64) return fail(c, SOC_EINVAL, "inner steps must be in [1,64]");
+        c->inner_steps = v;
+        return SOC_OK;
+    case SOC_OPT_TIMING:
+        c->timing = v ? 1 : 0;
+        return SOC_OK;
+    }
+    return fail(c, SOC_EINVAL, "unknown option %d", (int)opt);
+}
+
+soc_status soc_ctx_get_option(soc_ctx c, soc_option opt, int64_t *v)
+{
+    if (!c || !v) return SOC_EINVAL;
+    switch (opt) {
+    case SOC_OPT_STEP_CAP: *v = c->step_cap; return SOC_OK;
+    case SOC_OPT_BLOCK: *v = c->block; return SOC_OK;
+    case SOC_OPT_BLOCKS_PER_CU: *v = c->blocks_per_cu; return SOC_OK;
+    case SOC_OPT_REFILL_MIN: *v = c->refill_min; return SOC_OK;
+    case SOC_OPT_INNER_STEPS: *v = c->inner_steps; return SOC_OK;
+    case SOC_OPT_TIMING: *v = c->timing; return SOC_OK;
+    }
+    return fail(c, SOC_EINVAL, "unknown option %d", (int)opt);
+}
+
+soc_status soc_ctx_mc_timing(soc_ctx c, double *total_ms, int64_t *launches, int32_t reset)
+{
+    if (!c) return SOC_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    for (size_t i = 0; i < c->ev_start.size(); ++i) {
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev_start[i], c->ev_stop[i]));
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = (int64_t)c->ev_start.size();
+    if (reset) {
+        for (auto e : c->ev_start) (void)hipEventDestroy(e);
+        for (auto e : c->ev_stop) (void)hipEventDestroy(e);
+        c->ev_start.clear();
+        c->ev_stop.clear();
+    }
+    return SOC_OK;
+}
+
+soc_status soc_build_grid(soc_ctx c, const soc_grid_desc *d, soc_grid *out)
+{
+    if (!c) return SOC_EINVAL;
+    if (!d || !out) return fail(c, SOC_EINVAL, "desc/out is NULL");
+    *out = nullptr;
+    if (d->nx <= 0 || d->ny <= 0 || d->nz <= 0) return fail(c, SOC_EINVAL, "grid dimensions must be > 0");
+    if (d->nlevels < 1 || d->nlevels > kMaxLevels) return fail(c, SOC_EINVAL, "nlevels must be in [1,%d]", kMaxLevels);
+    if (!d->level_offset || !d->d_words) return fail(c, SOC_EINVAL, "level_offset/d_words is NULL");
+    if (!(std::isfinite(d->root_cell_cm) && d->root_cell_cm > 0.0)) return fail(c, SOC_EINVAL, "root_cell_cm must be > 0");
+    const int64_t nroot = (int64_t)d->nx * d->ny * d->nz;
+    if (d->ncells > 0x7FFFFFFFll) return fail(c, SOC_EINVAL, "more than 2^31-1 cells");
+    if (d->level_offset[0] != 0 || d->level_offset[1] != nroot || d->level_offset[d->nlevels] != d->ncells)
+        return fail(c, SOC_EGRID, "level offsets inconsistent with the root grid and ncells");
+    for (int L = 1; L <= d->nlevels; ++L) {
+        if (d->level_offset[L] < d->level_offset[L - 1]) return fail(c, SOC_EGRID, "level offsets decrease");
+        if (L >= 2 && (d->level_offset[L] - d->level_offset[L - 1]) % 8)
+            return fail(c, SOC_EGRID, "level %d is not a whole number of octets", L);
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    soc_grid g = new (std::nothrow) soc_grid_s;
+    if (!g) return fail(c, SOC_ENOMEM, "host allocation failed");
+    g->ctx = c;
+    g->nx = d->nx; g->ny = d->ny; g->nz = d->nz; g->nlevels = d->nlevels;
+    g->ncells = d->ncells;
+    g->nroot = nroot;
+    g->level_offset.assign(d->level_offset, d->level_offset + d->nlevels + 1);
+    g->root_cell_cm = d->root_cell_cm;
+    g->d_words = d->d_words;
+    const int64_t noct = (d->ncells - nroot) / 8;
+    int32_t *d_count = nullptr, *d_flags = nullptr;
+    int64_t *d_tmp = nullptr, *d_scr = nullptr;
+    auto cleanup = [&](soc_status s) {
+        (void)hipFree(d_count); (void)hipFree(d_flags); (void)hipFree(d_tmp); (void)hipFree(d_scr);
+        if (s != SOC_OK) soc_grid_destroy(g);
+        return s;
+    };
+    if (hipMalloc((void **)&d_flags, sizeof(int32_t)) != hipSuccess) return cleanup(fail(c, SOC_ENOMEM, "alloc"));
+    if (noct > 0) {
+        if (hipMalloc((void **)&g->d_parent, sizeof(int32_t) * noct) != hipSuccess ||
+            hipMalloc((void **)&d_count, sizeof(int32_t) * noct) != hipSuccess)
+            return cleanup(fail(c, SOC_ENOMEM, "alloc of reverse links failed"));
+        if (launch_fill_i32(d_count, 0, noct, c->stream) != hipSuccess ||
+            launch_fill_i32(g->d_parent, -1, noct, c->stream) != hipSuccess)
+            return cleanup(fail(c, SOC_EHIP, "fill failed"));
+    }
+    if (launch_fill_i32(d_flags, 0, 1, c->stream) != hipSuccess) return cleanup(fail(c, SOC_EHIP, "fill failed"));
+    if (launch_validate_grid(d->d_words, d->ncells, d->level_offset, d->nlevels, nroot, g->d_parent, d_count, d_flags,
+                             c->stream) != hipSuccess ||
+        launch_check_octets(d_count, noct, d_flags, c->stream) != hipSuccess)
+        return cleanup(fail(c, SOC_EHIP, "grid validation launch failed: %s", hipGetErrorString(hipGetLastError())));
+    int32_t flags = 0;
+    if (hipMemcpyAsync(&flags, d_flags, sizeof flags, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return cleanup(fail(c, SOC_EHIP, "grid validation failed: %s", hipGetErrorString(hipGetLastError())));
+    if (flags) {
+        return cleanup(fail(c, SOC_EGRID, "malformed grid:%s%s%s", (flags & 1) ? " bad link" : "",
+                            (flags & 2) ? " bad density" : "", (flags & 4) ? " octet not linked exactly once" : ""));
+    }
+    if (d->nlevels == 1) {
+        g->nleaves = d->ncells;
+    } else {
+        const size_t ns = scan_i64_scratch_elems(d->ncells);
+        if (hipMalloc((void **)&g->d_leaves, sizeof(int64_t) * d->ncells) != hipSuccess ||
+            hipMalloc((void **)&d_tmp, sizeof(int64_t) * d->ncells) != hipSuccess ||
+            hipMalloc((void **)&d_scr, sizeof(int64_t) * ns) != hipSuccess)
+            return cleanup(fail(c, SOC_ENOMEM, "alloc of leaf list failed"));
+        if (launch_leaf_list(d->d_words, d->ncells, d_tmp, d_scr, g->d_leaves, c->stream) != hipSuccess)
+            return cleanup(fail(c, SOC_EHIP, "leaf list launch failed"));
+        int64_t last_pos = 0;
+        uint32_t last_word = 0;
+        if (hipMemcpyAsync(&last_pos, d_tmp + d->ncells - 1, sizeof last_pos, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipMemcpyAsync(&last_word, d->d_words + d->ncells - 1, sizeof last_word, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            return cleanup(fail(c, SOC_EHIP, "leaf count readback failed"));
+        g->nleaves = last_pos + (((int32_t)last_word >= 0) ? 1 : 0);
+    }
+    *out = g;
+    return cleanup(SOC_OK);
+}
+
+void soc_grid_destroy(soc_grid g)
+{
+    if (!g) return;
+    if (g->ctx) {
+        (void)hipSetDevice(g->ctx->device);
+        (void)hipStreamSynchronize(g->ctx->stream);
+    }
+    (void)hipFree(g->d_parent);
+    (void)hipFree(g->d_leaves);
+    delete g;
+}
+
+soc_status soc_grid_info(soc_grid g, int64_t *n_leaves, const int32_t **d_parent)
+{
+    if (!g) return SOC_EINVAL;
+    if (n_leaves) *n_leaves = g->nleaves;
+    if (d_parent) *d_parent = g->d_parent;
+    return SOC_OK;
+}
+
+soc_status soc_simulate_frequency(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *s, uint64_t seed,
+                                  uint32_t iteration, uint32_t freq_index, double *d_absorbed, soc_sim_stats *stats)
+{
+    if (!c) return SOC_EINVAL;
+    if (!d_absorbed) return fail(c, SOC_EINVAL, "d_absorbed is NULL");
+    HIPCHK(c, hipSetDevice(c->device));
+    McArgs A;
+    soc_status st = prepare(c, g, f, s, seed, iteration, freq_index, d_absorbed, A);
+    if (st) return st;
+    HIPCHK(c, launch_fill_u64((unsigned long long *)c->d_stats, 0ull, (int64_t)(sizeof(DevStats) / 8), c->stream));
+    HIPCHK(c, launch_fill_u64(c->d_counter, 0ull, 1, c->stream));
+    const int blocks = (int)(c->num_cus * c->blocks_per_cu);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        HIPCHK(c, hipEventCreate(&e0));
+        HIPCHK(c, hipEventCreate(&e1));
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+    }
+    HIPCHK(c, launch_mc_regular(A, blocks, (int)c->block, c->stream));
+    if (c->timing) {
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        c->ev_start.push_back(e0);
+        c->ev_stop.push_back(e1);
+    }
+    if (stats) {
+        DevStats h;
+        HIPCHK(c, hipMemcpyAsync(&h, c->d_stats, sizeof h, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        to_public(h, stats);
+    }
+    return SOC_OK;
+}
+
+soc_status soc_read_stats(soc_ctx c, soc_sim_stats *out, int32_t reset)
+{
+    if (!c || !out) return SOC_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    DevStats h;
+    HIPCHK(c, hipMemcpyAsync(&h, c->d_stats + 1, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    to_public(h, out);
+    if (reset) HIPCHK(c, launch_fill_u64((unsigned long long *)(c->d_stats + 1), 0ull, (int64_t)(sizeof(DevStats) / 8), c->stream));
+    return SOC_OK;
+}
+
+soc_status soc_trace_packages(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *s, uint64_t seed,
+                              uint32_t iteration, uint32_t freq_index, uint32_t cls, const uint32_t *ids, int32_t n,
+                              int32_t precision, soc_segment *out, int32_t max_seg, int32_t *n_seg)
+{
+    if (!c) return SOC_EINVAL;
+    if (!ids || !out || !n_seg || n <= 0 || max_seg <= 0) return fail(c, SOC_EINVAL, "bad trace buffers");
+    if (precision != 0 && precision != 1) return fail(c, SOC_EINVAL, "precision must be 0 or 1");
+    HIPCHK(c, hipSetDevice(c->device));
+    McArgs A;
+    soc_status st = prepare(c, g, f, s, seed, iteration, freq_index, nullptr, A);
+    if (st) return st;
+    uint64_t limit;
+    if (cls == kClassBg) limit = A.n_bg;
+    else if (cls == kClassDust) limit = A.n_dust;
+    else if (cls >= kClassPs0 && (int32_t)(cls - kClassPs0) < A.n_ps) limit = A.n_ps_pk;
+    else return fail(c, SOC_EINVAL, "class %u has no packages", cls);
+    for (int32_t i = 0; i < n; ++i)
+        if (ids[i] >= limit) return fail(c, SOC_EINVAL, "package id %u out of range for class %u", ids[i], cls);
+    static_assert(sizeof(SegmentDev) == sizeof(soc_segment), "segment layout");
+    uint32_t *d_ids = nullptr;
+    SegmentDev *d_out = nullptr;
+    int32_t *d_n = nullptr;
+    auto cleanup = [&](soc_status r) {
+        (void)hipFree(d_ids); (void)hipFree(d_out); (void)hipFree(d_n);
+        return r;
+    };
+    if (hipMalloc((void **)&d_ids, sizeof(uint32_t) * n) != hipSuccess ||
+        hipMalloc((void **)&d_out, sizeof(SegmentDev) * (size_t)n * max_seg) != hipSuccess ||
+        hipMalloc((void **)&d_n, sizeof(int32_t) * n) != hipSuccess)
+        return cleanup(fail(c, SOC_ENOMEM, "trace buffers"));
+    TraceArgs T;
+    T.cls = cls;
+    T.ids = d_ids;
+    T.n = n;
+    T.max_seg = max_seg;
+    T.out = d_out;
+    T.nseg = d_n;
+    if (hipMemcpyAsync(d_ids, ids, sizeof(uint32_t) * n, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        return cleanup(fail(c, SOC_EHIP, "copy ids"));
+    hipError_t e = launch_trace_regular(A, T, precision, c->stream);
+    if (e != hipSuccess) return cleanup(fail(c, SOC_EHIP, "trace launch: %s", hipGetErrorString(e)));
+    if (hipMemcpyAsync(out, d_out, sizeof(SegmentDev) * (size_t)n * max_seg, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipMemcpyAsync(n_seg, d_n, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return cleanup(fail(c, SOC_EHIP, "trace readback: %s", hipGetErrorString(hipGetLastError())));
+    return cleanup(SOC_OK);
+}
+
+soc_status soc_temp_table_build(soc_ctx c, int32_t K, const double *nu, const double *w_nu, const double *sigma_abs,
+                                double T_floor, double T_max, int32_t nT, soc_temp_table *out)
+{
+    if (!c) return SOC_EINVAL;
+    if (!out || !nu || !w_nu || !sigma_abs || K < 1) return fail(c, SOC_EINVAL, "bad temperature table inputs");
+    if (!(T_floor > 0.0 && T_max > T_floor && std::isfinite(T_max))) return fail(c, SOC_EINVAL, "need 0 < T_floor < T_max");
+    if (nT < 16 || nT > 4096) return fail(c, SOC_EINVAL, "nT must be in [16,4096]");
+    for (int k = 0; k < K; ++k)
+        if (!(nu[k] > 0.0 && std::isfinite(nu[k])) || !finite_nonneg(w_nu[k]) || !finite_nonneg(sigma_abs[k]))
+            return fail(c, SOC_EINVAL, "frequency %d: bad nu, w or sigma_abs", k);
+    *out = nullptr;
+    HIPCHK(c, hipSetDevice(c->device));
+    soc_temp_table t = new (std::nothrow) soc_temp_table_s;
+    if (!t) return fail(c, SOC_ENOMEM, "host allocation");
+    t->ctx = c;
+    t->nT = nT;
+    t->T_floor = T_floor;
+    t->T_max = T_max;
+    t->lnTf = std::log(T_floor);
+    t->dlnT = (std::log(T_max) - t->lnTf) / (nT - 1);
+    double *d_f = nullptr;
+    auto cleanup = [&](soc_status r) {
+        (void)hipFree(d_f);
+        if (r != SOC_OK) soc_temp_table_destroy(t);
+        return r;
+    };
+    if (hipMalloc((void **)&t->d_lnG, sizeof(double) * nT) != hipSuccess ||
+        hipMalloc((void **)&d_f, sizeof(double) * 3 * K) != hipSuccess)
+        return cleanup(fail(c, SOC_ENOMEM, "temperature table"));
+    if (hipMemcpyAsync(d_f, nu, sizeof(double) * K, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(d_f + K, w_nu, sizeof(double) * K, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(d_f + 2 * K, sigma_abs, sizeof(double) * K, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        return cleanup(fail(c, SOC_EHIP, "table upload"));
+    if (launch_temp_table(d_f, d_f + K, d_f + 2 * K, K, t->lnTf, t->dlnT, nT, t->d_lnG, c->stream) != hipSuccess)
+        return cleanup(fail(c, SOC_EHIP, "table launch"));
+    std::vector<double> h(nT);
+    if (hipMemcpyAsync(h.data(), t->d_lnG, sizeof(double) * nT, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return cleanup(fail(c, SOC_EHIP, "table readback"));
+    for (int j = 0; j < nT; ++j) {
+        if (!std::isfinite(h[j]) || (j > 0 && !(h[j] > h[j - 1])))
+            return cleanup(fail(c, SOC_EINVAL, "Gamma(T) is not finite and increasing on [T_floor, T_max] (bin %d)", j));
+    }
+    *out = t;
+    return cleanup(SOC_OK);
+}
+
+void soc_temp_table_destroy(soc_temp_table t)
+{
+    if (!t) return;
+    if (t->ctx) {
+        (void)hipSetDevice(t->ctx->device);
+        (void)hipStreamSynchronize(t->ctx->stream);
+    }
+    (void)hipFree(t->d_lnG);
+    delete t;
+}
+
+soc_status soc_update_temperature(soc_ctx c, soc_grid g, soc_temp_table t, const double *d_absorbed,
+                                  const float *d_T_old, float *d_T_new, soc_temp_stats *stats)
+{
+    if (!c) return SOC_EINVAL;
+    if (!g || !t || !d_absorbed || !d_T_new) return fail(c, SOC_EINVAL, "NULL argument");
+    if (g->ctx != c || t->ctx != c) return fail(c, SOC_EINVAL, "grid/table belong to another context");
+    HIPCHK(c, hipSetDevice(c->device));
+    TempArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.words = g->d_words;
+    a.ncells = g->ncells;
+    for (int i = 0; i <= kMaxLevels; ++i) a.level_offset[i] = i <= g->nlevels ? g->level_offset[i] : g->ncells;
+    a.nlevels = g->nlevels;
+    a.root_cell_cm = g->root_cell_cm;
+    a.lnG = t->d_lnG;
+    a.nT = t->nT;
+    a.lnTf = t->lnTf;
+    a.dlnT = t->dlnT;
+    a.T_floor = t->T_floor;
+    a.T_max = t->T_max;
+    a.absorbed = d_absorbed;
+    a.T_old = d_T_old;
+    a.T_new = d_T_new;
+    if (stats) {
+        if (!c->d_tacc) {
+            if (hipMalloc((void **)&c->d_tacc, 8 * sizeof(double)) != hipSuccess ||
+                hipMalloc((void **)&c->d_hist_n, kHistBins * sizeof(unsigned int)) != hipSuccess ||
+                hipMalloc((void **)&c->d_hist_T, kHistBins * sizeof(double)) != hipSuccess)
+                return fail(c, SOC_ENOMEM, "temperature statistics buffers");
+        }
+        HIPCHK(c, launch_fill_f64(c->d_tacc, 0.0, 8, c->stream));
+        HIPCHK(c, launch_fill_i32((int32_t *)c->d_hist_n, 0, kHistBins, c->stream));
+        HIPCHK(c, launch_fill_f64(c->d_hist_T, 0.0, kHistBins, c->stream));
+        a.acc = c->d_tacc;
+        a.hist_n = c->d_hist_n;
+        a.hist_T = c->d_hist_T;
+    }
+    HIPCHK(c, launch_temp_update(a, c->stream));
+    if (stats) {
+        HIPCHK(c, launch_temp_finish(a, c->d_tmp_out, c->stream));
+        double h[4];
+        HIPCHK(c, hipMemcpyAsync(h, c->d_tmp_out, sizeof h, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        stats->mean_T = h[0];
+        stats->hot5_mean_T = h[1];
+        stats->mean_rel_change = h[2];
+        stats->clamped = (uint64_t)h[3];
+    }
+    return SOC_OK;
+}
+
+soc_status soc_map(soc_ctx c, soc_grid g, const soc_freq *f, const float *d_T, int32_t axis, float *d_image,
+                   int32_t npx, int32_t npy)
+{
+    if (!c) return SOC_EINVAL;
+    soc_status st = check_freq(c, f);
+    if (st) return st;
+    if (!g || !d_T || !d_image) return fail(c, SOC_EINVAL, "NULL argument");
+    if (g->ctx != c) return fail(c, SOC_EINVAL, "grid belongs to another context");
+    const int a = axis & 3;
+    if (a > 2 || (axis & ~7)) return fail(c, SOC_EINVAL, "axis must be 0..2, optionally | 4");
+    const int64_t scale = (int64_t)1 << (g->nlevels - 1);
+    const int32_t N[3] = {g->nx, g->ny, g->nz};
+    const int b = a == 0 ? 1 : 0, cc = a == 2 ? 1 : 2;
+    if ((int64_t)npx != N[b] * scale || (int64_t)npy != N[cc] * scale)
+        return fail(c, SOC_EINVAL, "image must be %lld x %lld pixels", (long long)(N[b] * scale), (long long)(N[cc] * scale));
+    HIPCHK(c, hipSetDevice(c->device));
+    MapArgs m;
+    m.words = g->d_words;
+    m.nx = g->nx; m.ny = g->ny; m.nz = g->nz; m.nlevels = g->nlevels;
+    m.root_cell_cm = g->root_cell_cm;
+    m.axis = a;
+    m.neg = (axis >> 2) & 1;
+    m.npx = npx;
+    m.npy = npy;
+    m.nu = f->nu;
+    m.sigma_abs = f->sigma_abs;
+    m.sigma_ext = f->sigma_abs + f->sigma_sca;
+    m.T = d_T;
+    m.image = d_image;
+    HIPCHK(c, launch_map(m, c->stream));
+    return SOC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,184 @@
+// mc.hip -- Monte Carlo photon-package kernels for a regular grid
+// (Juvela 2019, Sect. 2.1.1: one package per thread, one frequency per
+// launch, absorbed energy counted per cell).
+//
+// Production kernel: persistent waves.  Every lane owns one package; when
+// lanes finish (escape, weight floor, step cap) the wave refills them
+// together: a ballot of the idle lanes, their rank from the lane mask,
+// ids taken from a wave-private pool that is topped up with one atomic per
+// `chunk` ids.  Creation and tracking of packages are thereby interleaved
+// (the scheme the paper suggests in Sect. 4.2), so lanes do not idle until
+// the slowest package of the wave ends.  Deposits go straight to the FP64
+// absorbed array with hardware FP64 atomics (global_atomic_add_f64).
+#include "soc_device.h"
+
+namespace soc {
+
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += (unsigned long long)__shfl_xor((long long)v, o, 64);
+    return v;
+}
+__device__ inline double wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline void add_stats(DevStats *t, unsigned long long pk, unsigned long long st, unsigned long long sc,
+                                 unsigned long long ru, double em, double ab, double es)
+{
+    atomicAdd(&t->packages, pk);
+    atomicAdd(&t->steps, st);
+    atomicAdd(&t->scatterings, sc);
+    atomicAdd(&t->runaways, ru);
+    unsafeAtomicAdd(&t->emitted, em);
+    unsafeAtomicAdd(&t->absorbed, ab);
+    unsafeAtomicAdd(&t->escaped, es);
+}
+
+__device__ inline void flush_stats(const McArgs &A, unsigned long long pk, unsigned long long st,
+                                   unsigned long long sc, unsigned long long ru, double em, double ab, double es)
+{
+    pk = wave_sum_u64(pk);
+    st = wave_sum_u64(st);
+    sc = wave_sum_u64(sc);
+    ru = wave_sum_u64(ru);
+    em = wave_sum_f64(em);
+    ab = wave_sum_f64(ab);
+    es = wave_sum_f64(es);
+    if ((threadIdx.x & 63) == 0) {
+        add_stats(A.st_call, pk, st, sc, ru, em, ab, es);
+        add_stats(A.st_total, pk, st, sc, ru, em, ab, es);
+    }
+}
+
+__global__ __launch_bounds__(1024) void mc_regular_kernel(McArgs A)
+{
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    Pkg<float> p;
+    Rng rng;
+    bool active = false;
+    unsigned long long pool_next = 0, pool_end = 0;   // wave-uniform
+    bool exhausted = false;                           // wave-uniform
+    unsigned long long n_pk = 0, n_st = 0, n_sc = 0, n_ru = 0;
+    double e_em = 0.0, e_ab = 0.0, e_es = 0.0;
+    const float ks = A.ks_f, ka = A.ka_f, g = A.g_f;
+
+    for (;;) {
+        const unsigned long long idle = __ballot(!active);
+        const int nidle = __popcll(idle);
+        if (!exhausted && nidle > 0 && (nidle >= A.refill_min || nidle == 64)) {
+            const unsigned long long avail = pool_end - pool_next;
+            unsigned long long fresh = 0;
+            if (avail < (unsigned long long)nidle) {
+                const int leader = __ffsll((long long)idle) - 1;
+                unsigned long long b = 0;
+                if (lane == leader) b = atomicAdd(A.next_id, (unsigned long long)A.chunk);
+                fresh = (unsigned long long)__shfl((long long)b, leader, 64);
+            }
+            if (!active) {
+                const unsigned long long r = (unsigned long long)__popcll(idle & below);
+                const unsigned long long id = r < avail ? pool_next + r : fresh + (r - avail);
+                if (id < A.n_total) {
+                    uint32_t cls, pid;
+                    double W0;
+                    const bool ok = emit_regular<float>(A, id, p, rng, cls, pid, W0);
+                    n_pk += 1;
+                    if (ok) e_em += W0;
+                    active = ok;
+                }
+            }
+            if (avail < (unsigned long long)nidle) {
+                pool_next = fresh + ((unsigned long long)nidle - avail);
+                pool_end = fresh + (unsigned long long)A.chunk;
+            } else {
+                pool_next += (unsigned long long)nidle;
+            }
+            if (pool_next >= A.n_total) exhausted = true;
+        }
+        if (!__any(active)) {
+            if (exhausted) break;
+            continue;
+        }
+        for (int s = 0; s < A.inner_steps; ++s) {
+            if (active) {
+                float d;
+                const StepOut o = step_regular<float>(p, A, ks, ka, d);
+                n_st += 1;
+                if (o.dep > 0.0) {
+                    unsafeAtomicAdd(&A.absorbed[o.cell], o.dep);
+                    e_ab += o.dep;
+                }
+                if (o.event == kEvScatter) {
+                    scatter_new_direction<float>(p, rng, A, g);
+                    n_sc += 1;
+                } else if (o.event != kEvCross) {
+                    active = false;
+                    if (o.event == kEvEscape) e_es += p.W;
+                    if (o.event == kEvRunaway) n_ru += 1;
+                }
+            }
+        }
+    }
+    flush_stats(A, n_pk, n_st, n_sc, n_ru, e_em, e_ab, e_es);
+}
+
+hipError_t launch_mc_regular(const McArgs &a, int blocks, int threads, hipStream_t s)
+{
+    hipLaunchKernelGGL(mc_regular_kernel, dim3(blocks), dim3(threads), 0, s, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ traces
+template <typename R>
+__global__ __launch_bounds__(256) void trace_regular_kernel(McArgs A, TraceArgs T)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= T.n) return;
+    const uint32_t id = T.ids[i];
+    const uint64_t nps_tot = (uint64_t)A.n_ps * A.n_ps_pk;
+    uint64_t gid;
+    if (T.cls == kClassBg) gid = id;
+    else if (T.cls == kClassDust) gid = A.n_bg + nps_tot + id;
+    else gid = A.n_bg + (uint64_t)(T.cls - kClassPs0) * A.n_ps_pk + id;
+    Pkg<R> p;
+    Rng rng;
+    uint32_t cls, pid;
+    double W0;
+    int32_t ns = 0;
+    const R ks = sizeof(R) == 8 ? (R)A.ks_d : (R)A.ks_f;
+    const R ka = sizeof(R) == 8 ? (R)A.ka_d : (R)A.ka_f;
+    const R g = sizeof(R) == 8 ? (R)A.g_d : (R)A.g_f;
+    SegmentDev *out = T.out + (int64_t)i * T.max_seg;
+    if (emit_regular<R>(A, gid, p, rng, cls, pid, W0)) {
+        for (;;) {
+            R d;
+            const StepOut o = step_regular<R>(p, A, ks, ka, d);
+            if (ns < T.max_seg) {
+                out[ns].cell = o.cell;
+                out[ns].ds = (double)d;
+                out[ns].event = o.event;
+                out[ns].pad = 0;
+            }
+            ++ns;
+            if (o.event == kEvScatter) scatter_new_direction<R>(p, rng, A, g);
+            else if (o.event != kEvCross) break;
+        }
+    }
+    T.nseg[i] = ns;
+}
+
+hipError_t launch_trace_regular(const McArgs &a, const TraceArgs &t, int precision, hipStream_t s)
+{
+    const int threads = 64;
+    const int blocks = (t.n + threads - 1) / threads;
+    if (precision == 1) hipLaunchKernelGGL(trace_regular_kernel<double>, dim3(blocks), dim3(threads), 0, s, a, t);
+    else hipLaunchKernelGGL(trace_regular_kernel<float>, dim3(blocks), dim3(threads), 0, s, a, t);
+    return hipGetLastError();
+}
+
+}  // namespace soc

@@ -1,0 +1,311 @@
+// setup.hip -- per-frequency setup and grid preparation kernels.
+//
+//  * dust luminosity per cell, 4 pi sigma_abs n V B_nu(T) w (Sect. 3.2 dust
+//    re-emission), its inclusive prefix sum and the systematic selection
+//    of the cell of every weighted dust package;
+//  * device-side validation of the hierarchical grid and construction of
+//    the reverse (parent) links and the leaf list (Sect. 2.1.1);
+//  * small fills used instead of hipMemsetAsync so that captured graphs
+//    contain only kernels.
+#include <hip/hip_runtime.h>
+
+#include "soc_kernels.h"
+
+namespace soc {
+
+// ------------------------------------------------------------------ fills
+template <typename T>
+__global__ void fill_kernel(T *p, T v, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <typename T>
+static hipError_t fill(T *p, T v, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
+hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
+
+// ------------------------------------------------------------------ levels
+__device__ inline int level_of(int64_t c, const int64_t *lo, int32_t nlevels)
+{
+    int L = 0;
+    while (L + 1 < nlevels && c >= lo[L + 1]) ++L;
+    return L;
+}
+
+struct Levels {
+    int64_t off[kMaxLevels + 1];
+};
+
+// ------------------------------------------------------------------ Planck
+// B_nu(T) = 2 h nu^3 / c^2 / (exp(h nu / k T) - 1), CODATA 2018 cgs.
+__device__ inline double planck_nu(double nu, double T)
+{
+    const double h = 6.62607015e-27, k = 1.380649e-16, c = 2.99792458e10;
+    if (!(T > 0.0)) return 0.0;
+    const double x = h * nu / (k * T);
+    const double pre = 2.0 * h * nu * nu * nu / (c * c);
+    if (x > 700.0) return pre * exp(-x);
+    return pre / expm1(x);
+}
+
+__global__ void dust_luminosity_kernel(const uint32_t *words, int64_t ncells, Levels lv, int32_t nlevels,
+                                       double root_cell_cm, double nu, double sigma_abs, double w_nu,
+                                       const float *T, double *L)
+{
+    const double four_pi = 12.566370614359172;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncells; c += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t w = words[c];
+        double out = 0.0;
+        if ((int32_t)w >= 0) {
+            const double n = (double)__uint_as_float(w);
+            const int Lv = level_of(c, lv.off, nlevels);
+            const double s = ldexp(root_cell_cm, -Lv);
+            out = four_pi * sigma_abs * n * (s * s * s) * planck_nu(nu, (double)T[c]) * w_nu;
+        }
+        L[c] = out;
+    }
+}
+
+hipError_t launch_dust_luminosity(const uint32_t *words, int64_t ncells, const int64_t *level_offset,
+                                  int32_t nlevels, double root_cell_cm, double nu, double sigma_abs,
+                                  double w_nu, const float *T, double *L, hipStream_t s)
+{
+    Levels lv;
+    for (int i = 0; i <= kMaxLevels; ++i) lv.off[i] = i <= nlevels ? level_offset[i] : ncells;
+    int64_t blocks = (ncells + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(dust_luminosity_kernel, dim3((unsigned)blocks), dim3(256), 0, s, words, ncells, lv,
+                       nlevels, root_cell_cm, nu, sigma_abs, w_nu, T, L);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ scans
+// Three-pass inclusive scan: tile sums, a single-workgroup scan of the tile
+// sums (looping over chunks with a carry), then the per-tile scan with its
+// offset.  Tiles of 256 threads x 8 items.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+template <typename T>
+__device__ inline T block_inclusive_scan(T v, T *sh)
+{
+    // Hillis-Steele over the workgroup through LDS
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int o = 1; o < kScanThreads; o <<= 1) {
+        T add = t >= o ? sh[t - o] : (T)0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    T r = sh[t];
+    __syncthreads();
+    return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void scan_tile_sums(const T *in, int64_t n, T *sums)
+{
+    __shared__ T sh[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    T acc = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + k;
+        if (i < n) acc += in[i];
+    }
+    T tot = block_inclusive_scan<T>(acc, sh);
+    if (threadIdx.x == kScanThreads - 1) sums[blockIdx.x] = tot;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void scan_sums_exclusive(T *sums, int64_t m)
+{
+    __shared__ T sh[kScanThreads];
+    __shared__ T tail;
+    T carry = 0;
+    for (int64_t base = 0; base < m; base += kScanThreads) {
+        const int64_t i = base + threadIdx.x;
+        const T v = i < m ? sums[i] : (T)0;
+        const T inc = block_inclusive_scan<T>(v, sh);
+        if (i < m) sums[i] = carry + inc - v;
+        if (threadIdx.x == kScanThreads - 1) tail = inc;
+        __syncthreads();
+        carry += tail;
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void scan_tiles_apply(const T *in, int64_t n, const T *offsets, T *out,
+                                                                 int inclusive)
+{
+    __shared__ T sh[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    T v[kScanItems];
+    T acc = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + k;
+        v[k] = i < n ? in[i] : (T)0;
+        acc += v[k];
+    }
+    const T inc = block_inclusive_scan<T>(acc, sh);
+    T run = offsets[blockIdx.x] + inc - acc;
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + k;
+        const T before = run;
+        run += v[k];
+        if (i < n) out[i] = inclusive ? run : before;
+    }
+}
+
+template <typename T>
+static hipError_t scan_generic(const T *in, T *out, int64_t n, T *scratch, int inclusive, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(scan_tile_sums<T>, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, in, n, scratch);
+    hipLaunchKernelGGL(scan_sums_exclusive<T>, dim3(1), dim3(kScanThreads), 0, s, scratch, tiles);
+    hipLaunchKernelGGL(scan_tiles_apply<T>, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, in, n,
+                       (const T *)scratch, out, inclusive);
+    return hipGetLastError();
+}
+
+size_t scan_f64_scratch_elems(int64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile) + 1; }
+size_t scan_i64_scratch_elems(int64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile) + 1; }
+
+hipError_t launch_scan_f64(const double *in, double *out, int64_t n, double *scratch, hipStream_t s)
+{
+    return scan_generic<double>(in, out, n, scratch, 1, s);
+}
+
+// Weighted dust emission: package j takes the first cell whose inclusive
+// cumulative luminosity exceeds x_j = (j + u) S / N (systematic sampling:
+// every cell receives floor or ceil of N L_c / S packages).
+__global__ void dust_select_kernel(const double *incl, int64_t ncells, uint64_t n_dust, double u_sys, int32_t *cell)
+{
+    const double S = incl[ncells - 1];
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_dust; j += (uint64_t)gridDim.x * blockDim.x) {
+        const double x = (((double)j + u_sys) * S) / (double)n_dust;
+        int64_t lo = 0, hi = ncells;
+        while (lo < hi) {
+            const int64_t mid = lo + ((hi - lo) >> 1);
+            if (incl[mid] > x) hi = mid; else lo = mid + 1;
+        }
+        if (lo >= ncells) {
+            // rounding pushed x to S: take the last cell with L > 0
+            lo = ncells - 1;
+            while (lo > 0 && incl[lo - 1] == incl[ncells - 1]) --lo;
+        }
+        cell[j] = (int32_t)lo;
+    }
+}
+
+hipError_t launch_dust_select(const double *incl, int64_t ncells, uint64_t n_dust, double u_sys,
+                              int32_t *cell_out, hipStream_t s)
+{
+    if (n_dust == 0) return hipSuccess;
+    uint64_t blocks = (n_dust + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(dust_select_kernel, dim3((unsigned)blocks), dim3(256), 0, s, incl, ncells, n_dust, u_sys,
+                       cell_out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ grid checks
+// flags[0] |= 1: bad link (range, alignment, level); 2: bad density;
+// 4: octet linked more or less than once.
+__global__ void validate_grid_kernel(const uint32_t *words, int64_t ncells, Levels lv, int32_t nlevels,
+                                     int64_t nroot, int32_t *parent, int32_t *octet_count, int32_t *flags)
+{
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncells; c += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t w = (int32_t)words[c];
+        if (w < 0) {
+            const int L = level_of(c, lv.off, nlevels);
+            const int64_t first = -(int64_t)w;
+            bool ok = L + 1 < nlevels;
+            if (ok) {
+                const int64_t a = lv.off[L + 1], b = lv.off[L + 2];
+                ok = first >= a && first + 8 <= b && ((first - a) & 7) == 0;
+            }
+            if (!ok) {
+                atomicOr(flags, 1);
+            } else {
+                const int64_t oct = (first - nroot) >> 3;
+                atomicAdd(&octet_count[oct], 1);
+                parent[oct] = (int32_t)c;
+            }
+        } else {
+            const float v = __uint_as_float((uint32_t)w);
+            if (!(v >= 0.0f) || !(v <= 3.4e38f)) atomicOr(flags, 2);
+        }
+    }
+}
+
+hipError_t launch_validate_grid(const uint32_t *words, int64_t ncells, const int64_t *level_offset,
+                                int32_t nlevels, int64_t nroot, int32_t *parent, int32_t *octet_count,
+                                int32_t *flags, hipStream_t s)
+{
+    Levels lv;
+    for (int i = 0; i <= kMaxLevels; ++i) lv.off[i] = i <= nlevels ? level_offset[i] : ncells;
+    int64_t blocks = (ncells + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(validate_grid_kernel, dim3((unsigned)blocks), dim3(256), 0, s, words, ncells, lv, nlevels,
+                       nroot, parent, octet_count, flags);
+    return hipGetLastError();
+}
+
+__global__ void check_octets_kernel(const int32_t *cnt, int64_t noct, int32_t *flags)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < noct; i += (int64_t)gridDim.x * blockDim.x)
+        if (cnt[i] != 1) atomicOr(flags, 4);
+}
+
+hipError_t launch_check_octets(const int32_t *octet_count, int64_t noct, int32_t *flags, hipStream_t s)
+{
+    if (noct <= 0) return hipSuccess;
+    int64_t blocks = (noct + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(check_octets_kernel, dim3((unsigned)blocks), dim3(256), 0, s, octet_count, noct, flags);
+    return hipGetLastError();
+}
+
+// Leaf list: exclusive scan of the leaf flags, then scatter.
+__global__ void leaf_flags_kernel(const uint32_t *words, int64_t n, int64_t *flag)
+{
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
+        flag[c] = (int32_t)words[c] >= 0 ? 1 : 0;
+}
+
+__global__ void leaf_scatter_kernel(const uint32_t *words, int64_t n, const int64_t *pos, int64_t *leaves)
+{
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
+        if ((int32_t)words[c] >= 0) leaves[pos[c]] = c;
+}
+
+hipError_t launch_leaf_list(const uint32_t *words, int64_t ncells, int64_t *scan_tmp, int64_t *scratch,
+                            int64_t *leaves, hipStream_t s)
+{
+    int64_t blocks = (ncells + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(leaf_flags_kernel, dim3((unsigned)blocks), dim3(256), 0, s, words, ncells, leaves);
+    hipError_t e = scan_generic<int64_t>(leaves, scan_tmp, ncells, scratch, 0, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(leaf_scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, s, words, ncells,
+                       (const int64_t *)scan_tmp, leaves);
+    return hipGetLastError();
+}
+
+}  // namespace soc

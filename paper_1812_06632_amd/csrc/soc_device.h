@@ -1,0 +1,389 @@
+// soc_device.h -- device-side building blocks of the SOC Monte Carlo path
+// (Juvela 2019, arXiv:1812.06632, Sect. 2.1.1): counter-based random
+// numbers, source emission, Henyey-Greenstein scattering and the per-cell
+// transport step.  Everything is templated on the tracing precision R so
+// that the FP32 production kernel and the FP64 deterministic trace mode
+// execute the same code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "soc_kernels.h"
+
+namespace soc {
+
+// ------------------------------------------------------------------ Philox
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
+// 32x32 -> 64-bit products with the published multipliers; the key is
+// bumped by the published Weyl constants between rounds.
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+__host__ __device__ inline void philox4x32_10(uint32_t &x0, uint32_t &x1, uint32_t &x2, uint32_t &x3,
+                                              uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)kPhiloxM0 * x0;
+        const uint64_t p1 = (uint64_t)kPhiloxM1 * x2;
+        const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        const uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        x1 = (uint32_t)p1;
+        x3 = (uint32_t)p0;
+        x0 = y0;
+        x2 = y2;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+}
+
+// Uniform in (0,1) on the odd multiples of 2^-24: exact in FP32 and FP64,
+// so both precisions consume bit-identical numbers.
+template <typename R>
+__host__ __device__ inline R u01(uint32_t x)
+{
+    return ((R)(x >> 9) + (R)0.5) * (R)(1.0 / 8388608.0);
+}
+
+// Per-package stream: counter (block, package id, frequency index,
+// iteration << 8 | class); the key (seed) is kernel-uniform and passed in.
+struct Rng {
+    uint32_t blk, pid, tag;
+    uint32_t b0, b1, b2, b3;
+    int avail;
+
+    __device__ void init(uint32_t package_id, uint32_t iteration, uint32_t cls)
+    {
+        blk = 0;
+        pid = package_id;
+        tag = (iteration << 8) | (cls & 0xffu);
+        avail = 0;
+    }
+    __device__ uint32_t word(uint32_t k0, uint32_t k1, uint32_t freq_index)
+    {
+        if (avail == 0) {
+            uint32_t x0 = blk, x1 = pid, x2 = freq_index, x3 = tag;
+            philox4x32_10(x0, x1, x2, x3, k0, k1);
+            b0 = x0; b1 = x1; b2 = x2; b3 = x3;
+            avail = 4;
+            ++blk;
+        }
+        const uint32_t r = b0;
+        b0 = b1; b1 = b2; b2 = b3;
+        --avail;
+        return r;
+    }
+};
+
+// ------------------------------------------------------------------ math
+__device__ inline float m_sqrt(float x) { return sqrtf(x); }
+__device__ inline double m_sqrt(double x) { return sqrt(x); }
+__device__ inline float m_log(float x) { return logf(x); }
+__device__ inline double m_log(double x) { return log(x); }
+__device__ inline void m_sincos2pi(float t, float *s, float *c) { sincospif(2.0f * t, s, c); }
+__device__ inline void m_sincos2pi(double t, double *s, double *c) { sincospi(2.0 * t, s, c); }
+__device__ inline float m_abs(float x) { return fabsf(x); }
+__device__ inline double m_abs(double x) { return fabs(x); }
+__device__ inline float m_min(float a, float b) { return fminf(a, b); }
+__device__ inline double m_min(double a, double b) { return fmin(a, b); }
+__device__ inline float m_max(float a, float b) { return fmaxf(a, b); }
+__device__ inline double m_max(double a, double b) { return fmax(a, b); }
+template <typename R> __device__ inline R m_inf();
+template <> __device__ inline float m_inf<float>() { return __builtin_huge_valf(); }
+template <> __device__ inline double m_inf<double>() { return __builtin_huge_val(); }
+
+// 1 - exp(-x) for x >= 0 without cancellation: a degree-6 Taylor polynomial
+// below 1/16 (truncation < 2e-9 relative), the exponential above.
+__device__ inline float one_minus_exp_neg(float x)
+{
+    if (x < 0.0625f) {
+        return x * (1.0f - x * (0.5f - x * (1.0f / 6.0f - x * (1.0f / 24.0f - x * (1.0f / 120.0f - x * (1.0f / 720.0f))))));
+    }
+    return 1.0f - expf(-x);
+}
+__device__ inline double one_minus_exp_neg(double x) { return -expm1(-x); }
+
+// ------------------------------------------------------------------ state
+// One photon package on a regular grid: integer cell, position inside the
+// cell in [0,1]^3 (kept cell-relative so that FP32 rounding does not grow
+// with the distance travelled), direction and its reciprocals, remaining
+// free path in scattering optical depth, weight and floor.
+template <typename R>
+struct Pkg {
+    int32_t cx, cy, cz;
+    R fx, fy, fz;
+    R ux, uy, uz;
+    R ix, iy, iz;   // 1/u (inf where u == 0)
+    R tau;
+    double W, Wfloor;
+    uint32_t steps;
+};
+
+template <typename R>
+__device__ inline void set_inverse(Pkg<R> &p)
+{
+    p.ix = p.ux != (R)0 ? (R)1 / p.ux : m_inf<R>();
+    p.iy = p.uy != (R)0 ? (R)1 / p.uy : m_inf<R>();
+    p.iz = p.uz != (R)0 ? (R)1 / p.uz : m_inf<R>();
+}
+
+// Henyey-Greenstein draw (analytic inversion of the cumulative
+// distribution; isotropic for |g| < 1e-4) and rotation of the direction
+// by polar cosine mu and azimuth 2 pi xi_phi about the old direction.
+template <typename R>
+__device__ inline void hg_scatter(R g, R xi_mu, R xi_phi, R &ux, R &uy, R &uz)
+{
+    R mu;
+    if (m_abs(g) < (R)1e-4) {
+        mu = (R)2 * xi_mu - (R)1;
+    } else {
+        const R s = ((R)1 - g * g) / ((R)1 - g + (R)2 * g * xi_mu);
+        mu = ((R)1 + g * g - s * s) / ((R)2 * g);
+    }
+    mu = m_min((R)1, m_max((R)-1, mu));
+    const R st = m_sqrt(m_max((R)0, (R)1 - mu * mu));
+    R sp, cp;
+    m_sincos2pi(xi_phi, &sp, &cp);
+    R n0, n1, n2;
+    if (m_abs(uz) > (R)0.99999) {
+        n0 = st * cp;
+        n1 = st * sp;
+        n2 = (uz >= (R)0 ? mu : -mu);
+    } else {
+        const R t = m_sqrt((R)1 - uz * uz);
+        n0 = st * (ux * uz * cp - uy * sp) / t + ux * mu;
+        n1 = st * (uy * uz * cp + ux * sp) / t + uy * mu;
+        n2 = -st * cp * t + uz * mu;
+    }
+    const R nn = m_sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+    ux = n0 / nn;
+    uy = n1 / nn;
+    uz = n2 / nn;
+}
+
+template <typename R>
+__device__ inline void iso_dir(R xi_mu, R xi_phi, R &ux, R &uy, R &uz)
+{
+    const R mu = (R)2 * xi_mu - (R)1;
+    const R st = m_sqrt(m_max((R)0, (R)1 - mu * mu));
+    R sp, cp;
+    m_sincos2pi(xi_phi, &sp, &cp);
+    ux = st * cp;
+    uy = st * sp;
+    uz = mu;
+}
+
+template <typename R>
+__device__ inline R next_u(Rng &rng, const McArgs &A)
+{
+    return u01<R>(rng.word(A.key0, A.key1, A.freq_index));
+}
+
+// Split a coordinate (root units, FP64) into a cell index and an offset
+// inside the cell.
+template <typename R>
+__device__ inline void split_coord(double p, int32_t n, int32_t &c, R &f)
+{
+    double fl = floor(p);
+    if (fl > (double)(n - 1)) fl = (double)(n - 1);
+    if (fl < 0.0) fl = 0.0;
+    c = (int32_t)fl;
+    f = (R)(p - fl);
+}
+
+// ------------------------------------------------------------------ emission
+// Emit package `gid` (global order: background | point sources | dust) and
+// draw its first free path.  Returns false for a package that carries no
+// energy (it is counted but not traced).  `cls`/`pid` receive the class
+// and the id within the class; W0 the package energy.
+template <typename R>
+__device__ inline bool emit_regular(const McArgs &A, uint64_t gid, Pkg<R> &p, Rng &rng, uint32_t &cls,
+                                    uint32_t &pid, double &W0)
+{
+    const uint64_t nps_tot = (uint64_t)A.n_ps * A.n_ps_pk;
+    if (gid < A.n_bg) {
+        cls = kClassBg;
+        pid = (uint32_t)gid;
+        rng.init(pid, A.iteration, cls);
+        W0 = A.W_bg;
+        if (!(W0 > 0.0)) return false;
+        const double x0 = next_u<double>(rng, A);
+        const R x1 = next_u<R>(rng, A), x2 = next_u<R>(rng, A), x3 = next_u<R>(rng, A), x4 = next_u<R>(rng, A);
+        const double tt = x0 * A.face_tot;
+        int face = 5;
+        for (int k = 0; k < 6; ++k) {
+            if (tt < A.face_cum[k]) { face = k; break; }
+        }
+        const int a = face >> 1;
+        const bool neg = (face & 1) == 0;
+        const R mu = m_sqrt(x3);
+        const R st = m_sqrt(m_max((R)0, (R)1 - mu * mu));
+        R sp, cp;
+        m_sincos2pi(x4, &sp, &cp);
+        const R ua = neg ? mu : -mu, ub = st * cp, uc = st * sp;
+        // tangential axes b < c of face axis a
+        int32_t cb, cc;
+        R fb, fc;
+        const int32_t Nb = a == 0 ? A.ny : A.nx;
+        const int32_t Nc = a == 2 ? A.ny : A.nz;
+        split_coord<R>((double)x1 * Nb, Nb, cb, fb);
+        split_coord<R>((double)x2 * Nc, Nc, cc, fc);
+        const int32_t Na = a == 0 ? A.nx : (a == 1 ? A.ny : A.nz);
+        const int32_t ca = neg ? 0 : Na - 1;
+        const R fa = neg ? (R)0 : (R)1;
+        if (a == 0) {
+            p.cx = ca; p.fx = fa; p.ux = ua;
+            p.cy = cb; p.fy = fb; p.uy = ub;
+            p.cz = cc; p.fz = fc; p.uz = uc;
+        } else if (a == 1) {
+            p.cx = cb; p.fx = fb; p.ux = ub;
+            p.cy = ca; p.fy = fa; p.uy = ua;
+            p.cz = cc; p.fz = fc; p.uz = uc;
+        } else {
+            p.cx = cb; p.fx = fb; p.ux = ub;
+            p.cy = cc; p.fy = fc; p.uy = uc;
+            p.cz = ca; p.fz = fa; p.uz = ua;
+        }
+    } else if (gid < A.n_bg + nps_tot) {
+        const uint64_t k = gid - A.n_bg;
+        const int32_t s = (int32_t)(k / A.n_ps_pk);
+        cls = kClassPs0 + (uint32_t)s;
+        pid = (uint32_t)(k - (uint64_t)s * A.n_ps_pk);
+        rng.init(pid, A.iteration, cls);
+        W0 = A.ps[s].W;
+        if (!(W0 > 0.0)) return false;
+        split_coord<R>(A.ps[s].x, A.nx, p.cx, p.fx);
+        split_coord<R>(A.ps[s].y, A.ny, p.cy, p.fy);
+        split_coord<R>(A.ps[s].z, A.nz, p.cz, p.fz);
+        const R x0 = next_u<R>(rng, A), x1 = next_u<R>(rng, A);
+        iso_dir<R>(x0, x1, p.ux, p.uy, p.uz);
+    } else {
+        const uint64_t j = gid - A.n_bg - nps_tot;
+        cls = kClassDust;
+        pid = (uint32_t)j;
+        rng.init(pid, A.iteration, cls);
+        int64_t c;
+        if (A.dust_mode == 0) {
+            c = A.leaves ? A.leaves[j / A.per_leaf] : (int64_t)(j / A.per_leaf);
+            W0 = A.dust_L[c] / (double)A.per_leaf;
+        } else {
+            c = A.dust_cell[j];
+            W0 = A.dust_incl[A.ncells - 1] / (double)A.n_dust;
+        }
+        if (!(W0 > 0.0)) return false;
+        p.cx = (int32_t)(c % A.nx);
+        p.cy = (int32_t)((c / A.nx) % A.ny);
+        p.cz = (int32_t)(c / ((int64_t)A.nx * A.ny));
+        p.fx = next_u<R>(rng, A);
+        p.fy = next_u<R>(rng, A);
+        p.fz = next_u<R>(rng, A);
+        const R x3 = next_u<R>(rng, A), x4 = next_u<R>(rng, A);
+        iso_dir<R>(x3, x4, p.ux, p.uy, p.uz);
+    }
+    set_inverse(p);
+    p.tau = -m_log(next_u<R>(rng, A));
+    p.W = W0;
+    p.Wfloor = 1e-12 * W0;
+    p.steps = 0;
+    return true;
+}
+
+// ------------------------------------------------------------------ transport
+struct StepOut {
+    int64_t cell;
+    double dep;     // energy deposited in `cell` by this segment (incl. floor/runaway remainder)
+    int event;
+};
+
+// One segment of the per-cell loop on a regular grid: distance to the exit
+// face against the distance to the next scattering, continuous absorption
+// W (1 - e^{-k_abs d}), then crossing (DDA, ties broken x < y < z),
+// scattering position, escape, weight floor or step cap.  The caller adds
+// `dep` to the absorbed array and draws the new direction after a
+// scattering.
+template <typename R>
+__device__ inline StepOut step_regular(Pkg<R> &p, const McArgs &A, R ks_scale, R ka_scale, R &d_out)
+{
+    StepOut o;
+    const int64_t c = (int64_t)p.cx + (int64_t)A.nx * ((int64_t)p.cy + (int64_t)A.ny * (int64_t)p.cz);
+    o.cell = c;
+    const R n = (R)__uint_as_float(A.words[c]);
+    const R ks = n * ks_scale, ka = n * ka_scale;
+    const R dx = p.ux != (R)0 ? ((p.ux > (R)0 ? (R)1 : (R)0) - p.fx) * p.ix : m_inf<R>();
+    const R dy = p.uy != (R)0 ? ((p.uy > (R)0 ? (R)1 : (R)0) - p.fy) * p.iy : m_inf<R>();
+    const R dz = p.uz != (R)0 ? ((p.uz > (R)0 ? (R)1 : (R)0) - p.fz) * p.iz : m_inf<R>();
+    const int ax = (dx <= dy && dx <= dz) ? 0 : (dy <= dz ? 1 : 2);
+    const R dexit = m_max((R)0, ax == 0 ? dx : (ax == 1 ? dy : dz));
+    R d;
+    int ev;
+    const R tcell = ks * dexit;
+    if (ks > (R)0 && tcell >= p.tau) {
+        d = m_min(p.tau / ks, dexit);
+        ev = kEvScatter;
+    } else {
+        d = dexit;
+        p.tau -= tcell;
+        ev = kEvCross;
+    }
+    const R fr = one_minus_exp_neg(ka * d);
+    double dep = p.W * (double)fr;
+    p.W -= dep;
+    p.steps += 1;
+    if (ev == kEvCross) {
+        if (ax == 0) {
+            p.fy = m_min((R)1, m_max((R)0, p.fy + d * p.uy));
+            p.fz = m_min((R)1, m_max((R)0, p.fz + d * p.uz));
+            const bool fw = p.ux > (R)0;
+            p.fx = fw ? (R)0 : (R)1;
+            p.cx += fw ? 1 : -1;
+            if (p.cx < 0 || p.cx >= A.nx) ev = kEvEscape;
+        } else if (ax == 1) {
+            p.fx = m_min((R)1, m_max((R)0, p.fx + d * p.ux));
+            p.fz = m_min((R)1, m_max((R)0, p.fz + d * p.uz));
+            const bool fw = p.uy > (R)0;
+            p.fy = fw ? (R)0 : (R)1;
+            p.cy += fw ? 1 : -1;
+            if (p.cy < 0 || p.cy >= A.ny) ev = kEvEscape;
+        } else {
+            p.fx = m_min((R)1, m_max((R)0, p.fx + d * p.ux));
+            p.fy = m_min((R)1, m_max((R)0, p.fy + d * p.uy));
+            const bool fw = p.uz > (R)0;
+            p.fz = fw ? (R)0 : (R)1;
+            p.cz += fw ? 1 : -1;
+            if (p.cz < 0 || p.cz >= A.nz) ev = kEvEscape;
+        }
+    } else {
+        p.fx = m_min((R)1, m_max((R)0, p.fx + d * p.ux));
+        p.fy = m_min((R)1, m_max((R)0, p.fy + d * p.uy));
+        p.fz = m_min((R)1, m_max((R)0, p.fz + d * p.uz));
+    }
+    if (ev != kEvEscape) {
+        if (p.W < p.Wfloor) {
+            dep += p.W;
+            p.W = 0.0;
+            ev = kEvFloor;
+        } else if ((int64_t)p.steps >= A.step_cap) {
+            dep += p.W;
+            p.W = 0.0;
+            ev = kEvRunaway;
+        }
+    }
+    o.dep = dep;
+    o.event = ev;
+    d_out = d;
+    return o;
+}
+
+template <typename R>
+__device__ inline void scatter_new_direction(Pkg<R> &p, Rng &rng, const McArgs &A, R g)
+{
+    const R xm = next_u<R>(rng, A), xp = next_u<R>(rng, A);
+    hg_scatter<R>(g, xm, xp, p.ux, p.uy, p.uz);
+    set_inverse(p);
+    p.tau = -m_log(next_u<R>(rng, A));
+}
+
+}  // namespace soc

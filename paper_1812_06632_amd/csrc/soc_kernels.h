@@ -1,0 +1,146 @@
+// soc_kernels.h -- argument blocks and launchers shared by the C-ABI host
+// code (api.hip) and the kernel translation units.  Host-visible only; no
+// device code here.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace soc {
+
+// Source classes: the low byte of Philox counter word 3.
+constexpr uint32_t kClassBg = 0;
+constexpr uint32_t kClassDust = 1;
+constexpr uint32_t kClassPs0 = 2;
+
+// Segment end events (same values as SOC_EV_* in soc.h).
+constexpr int kEvCross = 0;
+constexpr int kEvScatter = 1;
+constexpr int kEvEscape = 2;
+constexpr int kEvFloor = 3;
+constexpr int kEvRunaway = 4;
+
+constexpr int kMaxPs = 32;
+constexpr int kMaxLevels = 16;
+
+struct PsArg {
+    double x, y, z;   // root units
+    double W;         // energy per package
+};
+
+struct DevStats {
+    unsigned long long packages, steps, scatterings, runaways;
+    double emitted, absorbed, escaped;
+};
+
+// Everything one Monte Carlo launch needs, passed by value.
+struct McArgs {
+    // grid
+    const uint32_t *words;
+    const int32_t *parent;      // reverse links (octree only)
+    int32_t nx, ny, nz, nlevels;
+    int64_t ncells;
+    int64_t level_offset[kMaxLevels + 1];
+    // frequency: k = sigma * root_cell_cm per unit density per root unit
+    float ks_f, ka_f, g_f;
+    double ks_d, ka_d, g_d;
+    // sources
+    uint64_t n_bg, n_ps_pk, n_dust, n_total;
+    int32_t n_ps, dust_mode;
+    double W_bg;
+    double face_cum[6];
+    double face_tot;
+    PsArg ps[kMaxPs];
+    const double *dust_L;        // per-cell luminosity (uniform mode)
+    const double *dust_incl;     // inclusive cumulative luminosity (weighted mode)
+    const int32_t *dust_cell;    // cell of every dust package (weighted mode)
+    const int64_t *leaves;       // leaf list (octree, uniform mode); NULL = identity
+    uint64_t per_leaf;
+    // random numbers
+    uint32_t key0, key1, freq_index, iteration;
+    // transport
+    int64_t step_cap;
+    double *absorbed;
+    // persistent scheduling
+    unsigned long long *next_id;
+    DevStats *st_call, *st_total;
+    int32_t refill_min, inner_steps, chunk;
+};
+
+struct SegmentDev {
+    int64_t cell;
+    double ds;
+    int32_t event, pad;
+};
+
+struct TraceArgs {
+    uint32_t cls;
+    const uint32_t *ids;
+    int32_t n, max_seg;
+    SegmentDev *out;
+    int32_t *nseg;
+};
+
+// ---- launchers (each returns the launch status) ----
+hipError_t launch_mc_regular(const McArgs &a, int blocks, int threads, hipStream_t s);
+hipError_t launch_trace_regular(const McArgs &a, const TraceArgs &t, int precision, hipStream_t s);
+
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+
+// dust emission setup
+hipError_t launch_dust_luminosity(const uint32_t *words, int64_t ncells, const int64_t *level_offset,
+                                  int32_t nlevels, double root_cell_cm, double nu, double sigma_abs,
+                                  double w_nu, const float *T, double *L, hipStream_t s);
+size_t scan_f64_scratch_elems(int64_t n);
+hipError_t launch_scan_f64(const double *in, double *out, int64_t n, double *scratch, hipStream_t s);
+hipError_t launch_dust_select(const double *incl, int64_t ncells, uint64_t n_dust, double u_sys,
+                              int32_t *cell_out, hipStream_t s);
+
+// grid validation / reverse links / leaf list
+hipError_t launch_validate_grid(const uint32_t *words, int64_t ncells, const int64_t *level_offset,
+                                int32_t nlevels, int64_t nroot, int32_t *parent, int32_t *octet_count,
+                                int32_t *flags, hipStream_t s);
+hipError_t launch_check_octets(const int32_t *octet_count, int64_t noct, int32_t *flags, hipStream_t s);
+size_t scan_i64_scratch_elems(int64_t n);
+hipError_t launch_leaf_list(const uint32_t *words, int64_t ncells, int64_t *scan_tmp, int64_t *scratch,
+                            int64_t *leaves, hipStream_t s);
+
+// temperature
+hipError_t launch_temp_table(const double *nu, const double *w, const double *sabs, int32_t K, double lnTf,
+                             double dlnT, int32_t nT, double *lnG, hipStream_t s);
+struct TempArgs {
+    const uint32_t *words;
+    int64_t ncells;
+    int64_t level_offset[kMaxLevels + 1];
+    int32_t nlevels;
+    double root_cell_cm;
+    const double *lnG;
+    int32_t nT;
+    double lnTf, dlnT, T_floor, T_max;
+    const double *absorbed;
+    const float *T_old;
+    float *T_new;
+    // statistics (NULL = not requested)
+    double *acc;                 // [0] count, [1] sum T, [2] sum rel, [3] n rel, [4] clamped
+    unsigned int *hist_n;        // kHistBins
+    double *hist_T;              // kHistBins
+};
+constexpr int kHistBins = 16384;
+hipError_t launch_temp_update(const TempArgs &a, hipStream_t s);
+hipError_t launch_temp_finish(const TempArgs &a, double *out4, hipStream_t s);
+
+// map
+struct MapArgs {
+    const uint32_t *words;
+    int32_t nx, ny, nz, nlevels;
+    double root_cell_cm;
+    int32_t axis, neg, npx, npy;
+    double nu, sigma_abs, sigma_ext;
+    const float *T;
+    float *image;
+};
+hipError_t launch_map(const MapArgs &a, hipStream_t s);
+
+}  // namespace soc

@@ -1,0 +1,309 @@
+"""Python binding of the SOC C-ABI library (libsoc.so, gfx950).
+
+Argument marshalling only: every step of the Monte Carlo path, the
+temperature solve and the map runs in the HIP kernels behind include/soc.h.
+Device arrays are torch CUDA tensors (passed by data_ptr()); the library
+enqueues its work on the torch stream given to the Context.  There is no
+CPU fallback: importing this module fails if the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsoc.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build the HIP library first (python __graft_entry__.py)")
+_lib = C.CDLL(LIB_PATH)
+
+OK, EINVAL, ENOMEM, EHIP, EGRID, ESTATE = 0, -1, -2, -3, -4, -5
+CROSS, SCATTER, ESCAPE, FLOOR, RUNAWAY = 0, 1, 2, 3, 4
+CLASS_BG, CLASS_DUST, CLASS_PS0 = 0, 1, 2
+OPTIONS = {"step_cap": 0, "block": 1, "blocks_per_cu": 2, "refill_min": 3, "inner_steps": 4, "timing": 5}
+
+
+class SocError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"soc status {status}: {msg}")
+        self.status = status
+
+
+class _GridDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("nlevels", C.c_int32),
+                ("ncells", C.c_int64), ("level_offset", C.POINTER(C.c_int64)),
+                ("root_cell_cm", C.c_double), ("d_words", C.c_void_p)]
+
+
+class _Freq(C.Structure):
+    _fields_ = [("nu", C.c_double), ("w_nu", C.c_double), ("sigma_abs", C.c_double),
+                ("sigma_sca", C.c_double), ("g", C.c_double)]
+
+
+class _PointSource(C.Structure):
+    _fields_ = [("x", C.c_double), ("y", C.c_double), ("z", C.c_double), ("L_nu", C.c_double)]
+
+
+class _Sources(C.Structure):
+    _fields_ = [("I_bg_nu", C.c_double), ("n_ps", C.c_int32), ("ps", C.POINTER(_PointSource)),
+                ("d_T", C.c_void_p), ("n_bg", C.c_uint64), ("n_ps_pk", C.c_uint64), ("n_dust", C.c_uint64),
+                ("dust_mode", C.c_int32)]
+
+
+class _SimStats(C.Structure):
+    _fields_ = [("packages", C.c_uint64), ("cell_steps", C.c_uint64), ("scatterings", C.c_uint64),
+                ("runaways", C.c_uint64), ("e_emitted", C.c_double), ("e_absorbed", C.c_double),
+                ("e_escaped", C.c_double)]
+
+
+class _TempStats(C.Structure):
+    _fields_ = [("mean_T", C.c_double), ("hot5_mean_T", C.c_double), ("mean_rel_change", C.c_double),
+                ("clamped", C.c_uint64)]
+
+
+SEGMENT_DTYPE = np.dtype([("cell", np.int64), ("ds", np.float64), ("event", np.int32), ("pad", np.int32)])
+
+_lib.soc_last_error.restype = C.c_char_p
+_lib.soc_last_error.argtypes = [C.c_void_p]
+_lib.soc_ctx_create.argtypes = [C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
+_lib.soc_ctx_destroy.argtypes = [C.c_void_p]
+_lib.soc_ctx_set_stream.argtypes = [C.c_void_p, C.c_void_p]
+_lib.soc_ctx_set_option.argtypes = [C.c_void_p, C.c_int, C.c_int64]
+_lib.soc_ctx_get_option.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int64)]
+_lib.soc_ctx_mc_timing.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
+_lib.soc_build_grid.argtypes = [C.c_void_p, C.POINTER(_GridDesc), C.POINTER(C.c_void_p)]
+_lib.soc_grid_destroy.argtypes = [C.c_void_p]
+_lib.soc_grid_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_void_p)]
+_lib.soc_simulate_frequency.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Freq), C.POINTER(_Sources), C.c_uint64,
+                                        C.c_uint32, C.c_uint32, C.c_void_p, C.POINTER(_SimStats)]
+_lib.soc_read_stats.argtypes = [C.c_void_p, C.POINTER(_SimStats), C.c_int32]
+_lib.soc_trace_packages.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Freq), C.POINTER(_Sources), C.c_uint64,
+                                    C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint32), C.c_int32, C.c_int32,
+                                    C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]
+_lib.soc_temp_table_build.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double), C.c_double, C.c_double, C.c_int32,
+                                      C.POINTER(C.c_void_p)]
+_lib.soc_temp_table_destroy.argtypes = [C.c_void_p]
+_lib.soc_update_temperature.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.POINTER(_TempStats)]
+_lib.soc_map.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Freq), C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
+                         C.c_int32]
+
+
+def exported_symbols():
+    """Names of the C-ABI entry points this binding uses."""
+    return [n for n in dir(_lib) if n.startswith("soc_")]
+
+
+def _dev_ptr(t, dtype, name):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A library context bound to one device and one torch stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        rc = _lib.soc_ctx_create(device, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != OK:
+            raise SocError(rc, "soc_ctx_create failed")
+        self.h = h
+
+    def check(self, rc):
+        if rc != OK:
+            raise SocError(rc, _lib.soc_last_error(self.h).decode())
+
+    def set_option(self, name: str, value: int):
+        self.check(_lib.soc_ctx_set_option(self.h, OPTIONS[name], int(value)))
+
+    def get_option(self, name: str) -> int:
+        v = C.c_int64()
+        self.check(_lib.soc_ctx_get_option(self.h, OPTIONS[name], C.byref(v)))
+        return v.value
+
+    def mc_timing(self, reset: bool = False):
+        ms, n = C.c_double(), C.c_int64()
+        self.check(_lib.soc_ctx_mc_timing(self.h, C.byref(ms), C.byref(n), int(reset)))
+        return ms.value, n.value
+
+    def read_stats(self, reset: bool = False) -> dict:
+        st = _SimStats()
+        self.check(_lib.soc_read_stats(self.h, C.byref(st), int(reset)))
+        return {k: getattr(st, k) for k, _ in _SimStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.soc_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Grid:
+    """A validated grid; keeps the caller's device word array alive."""
+
+    def __init__(self, ctx: Context, h, words: torch.Tensor, desc):
+        self.ctx, self.h, self.words, self.desc = ctx, h, words, desc
+        self.nx, self.ny, self.nz, self.nlevels = desc.nx, desc.ny, desc.nz, desc.nlevels
+        self.ncells = desc.ncells
+
+    @property
+    def n_leaves(self) -> int:
+        n = C.c_int64()
+        self.ctx.check(_lib.soc_grid_info(self.h, C.byref(n), None))
+        return n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.soc_grid_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_grid(ctx: Context, nx, ny, nz, nlevels, level_offset, root_cell_cm, words: torch.Tensor) -> Grid:
+    """soc_build_grid: words is a device int32/uint32-bit tensor of ncells words."""
+    if words.dtype not in (torch.int32,):
+        raise TypeError("words must be an int32 tensor holding the raw 32-bit cell words")
+    lo = np.ascontiguousarray(level_offset, dtype=np.int64)
+    desc = _GridDesc(int(nx), int(ny), int(nz), int(nlevels), int(words.numel()),
+                     lo.ctypes.data_as(C.POINTER(C.c_int64)), float(root_cell_cm), _dev_ptr(words, torch.int32, "words"))
+    desc._lo = lo
+    h = C.c_void_p()
+    ctx.check(_lib.soc_build_grid(ctx.h, C.byref(desc), C.byref(h)))
+    return Grid(ctx, h, words, desc)
+
+
+def grid_from_workload(ctx: Context, g, device="cuda") -> Grid:
+    """Upload a workloads.Grid and build it."""
+    words = torch.from_numpy(g.words.view(np.int32).copy()).to(device)
+    return build_grid(ctx, g.nx, g.ny, g.nz, g.nlevels, g.level_offset, g.root_cell_cm, words)
+
+
+def _freq(f):
+    nu, w, sabs, ssca, g = (float(x) for x in f)
+    return _Freq(nu, w, sabs, ssca, g)
+
+
+class _SourceView:
+    def __init__(self, I_bg=0.0, ps_pos=None, ps_Lnu=None, T=None, n_bg=0, n_ps_pk=0, n_dust=0, dust_mode=1):
+        pos = np.zeros((0, 3)) if ps_pos is None else np.asarray(ps_pos, dtype=np.float64).reshape(-1, 3)
+        L = np.zeros(0) if ps_Lnu is None else np.asarray(ps_Lnu, dtype=np.float64).reshape(-1)
+        n_ps = pos.shape[0]
+        self.arr = (_PointSource * max(n_ps, 1))(*[_PointSource(*pos[i], L[i]) for i in range(n_ps)])
+        self.T = T
+        self.s = _Sources(float(I_bg), n_ps, C.cast(self.arr, C.POINTER(_PointSource)) if n_ps else None,
+                          _dev_ptr(T, torch.float32, "T") if T is not None else None,
+                          int(n_bg), int(n_ps_pk), int(n_dust), int(dust_mode))
+
+
+def simulate_frequency(ctx: Context, grid: Grid, freq, absorbed: torch.Tensor, *, I_bg=0.0, ps_pos=None,
+                       ps_Lnu=None, T=None, n_bg=0, n_ps_pk=0, n_dust=0, dust_mode=1, seed=1, iteration=0,
+                       freq_index=0, stats=False):
+    """soc_simulate_frequency.  freq = (nu, w_nu, sigma_abs, sigma_sca, g);
+    absorbed: float64 CUDA tensor of ncells (accumulated).  Returns the
+    call's statistics dict if stats, else None (asynchronous)."""
+    sv = _SourceView(I_bg, ps_pos, ps_Lnu, T, n_bg, n_ps_pk, n_dust, dust_mode)
+    f = _freq(freq)
+    st = _SimStats() if stats else None
+    ctx.check(_lib.soc_simulate_frequency(ctx.h, grid.h, C.byref(f), C.byref(sv.s), C.c_uint64(seed),
+                                          C.c_uint32(iteration), C.c_uint32(freq_index),
+                                          _dev_ptr(absorbed, torch.float64, "absorbed"),
+                                          C.byref(st) if st is not None else None))
+    if st is None:
+        return None
+    return {k: getattr(st, k) for k, _ in _SimStats._fields_}
+
+
+def trace_packages(ctx: Context, grid: Grid, freq, cls, ids, *, precision=0, max_seg=4096, I_bg=0.0, ps_pos=None,
+                   ps_Lnu=None, T=None, n_bg=0, n_ps_pk=0, n_dust=0, dust_mode=1, seed=1, iteration=0,
+                   freq_index=0):
+    """soc_trace_packages: returns (segments[n, max_seg], n_seg[n])."""
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    n = ids.shape[0]
+    out = np.zeros((n, max_seg), dtype=SEGMENT_DTYPE)
+    nseg = np.zeros(n, dtype=np.int32)
+    sv = _SourceView(I_bg, ps_pos, ps_Lnu, T, n_bg, n_ps_pk, n_dust, dust_mode)
+    f = _freq(freq)
+    ctx.check(_lib.soc_trace_packages(ctx.h, grid.h, C.byref(f), C.byref(sv.s), C.c_uint64(seed),
+                                      C.c_uint32(iteration), C.c_uint32(freq_index), C.c_uint32(cls),
+                                      ids.ctypes.data_as(C.POINTER(C.c_uint32)), n, int(precision),
+                                      C.c_void_p(out.ctypes.data), int(max_seg),
+                                      nseg.ctypes.data_as(C.POINTER(C.c_int32))))
+    return out, nseg
+
+
+class TempTable:
+    def __init__(self, ctx, h):
+        self.ctx, self.h = ctx, h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.soc_temp_table_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def temp_table_build(ctx: Context, nu, w_nu, sigma_abs, T_floor=2.0, T_max=3000.0, nT=4096) -> TempTable:
+    nu = np.ascontiguousarray(nu, dtype=np.float64)
+    w = np.ascontiguousarray(w_nu, dtype=np.float64)
+    s = np.ascontiguousarray(sigma_abs, dtype=np.float64)
+    h = C.c_void_p()
+    P = C.POINTER(C.c_double)
+    ctx.check(_lib.soc_temp_table_build(ctx.h, nu.shape[0], nu.ctypes.data_as(P), w.ctypes.data_as(P),
+                                        s.ctypes.data_as(P), float(T_floor), float(T_max), int(nT), C.byref(h)))
+    return TempTable(ctx, h)
+
+
+def update_temperature(ctx: Context, grid: Grid, table: TempTable, absorbed: torch.Tensor, T_new: torch.Tensor,
+                       T_old: torch.Tensor | None = None, stats=False):
+    st = _TempStats() if stats else None
+    ctx.check(_lib.soc_update_temperature(ctx.h, grid.h, table.h, _dev_ptr(absorbed, torch.float64, "absorbed"),
+                                          _dev_ptr(T_old, torch.float32, "T_old") if T_old is not None else None,
+                                          _dev_ptr(T_new, torch.float32, "T_new"),
+                                          C.byref(st) if st is not None else None))
+    if st is None:
+        return None
+    return {k: getattr(st, k) for k, _ in _TempStats._fields_}
+
+
+def map_shape(grid: Grid, axis: int):
+    a = axis & 3
+    N = [grid.nx, grid.ny, grid.nz]
+    b, c = (1, 2) if a == 0 else ((0, 2) if a == 1 else (0, 1))
+    scale = 1 << (grid.nlevels - 1)
+    return N[c] * scale, N[b] * scale
+
+
+def map_image(ctx: Context, grid: Grid, freq, T: torch.Tensor, axis: int, image: torch.Tensor | None = None):
+    npy, npx = map_shape(grid, axis)
+    if image is None:
+        image = torch.empty((npy, npx), dtype=torch.float32, device=T.device)
+    f = _freq(freq)
+    ctx.check(_lib.soc_map(ctx.h, grid.h, C.byref(f), _dev_ptr(T, torch.float32, "T"), int(axis),
+                           _dev_ptr(image, torch.float32, "image"), npx, npy))
+    return image

@@ -61,11 +61,15 @@ def test_philox_matches_rocrand_black_box(tmp_path):
 
 
 def test_uniform_mapping_and_stream():
-    """u = ((x >> 8) + 1/2) 2^-24 lies strictly inside (0,1) at both ends;
+    """u = ((x >> 9) + 1/2) 2^-23 lies strictly inside (0,1) at both ends and
+    is exactly representable in FP32;
     a package stream takes the four words of consecutive counter blocks in
     order; uniforms pass a KS test."""
-    assert orc.u01(0) == 0.5 * 2.0 ** -24
-    assert orc.u01(0xFFFFFFFF) == 1.0 - 0.5 * 2.0 ** -24
+    assert orc.u01(0) == 2.0 ** -24
+    assert orc.u01(0xFFFFFFFF) == 1.0 - 2.0 ** -24
+    xs = np.random.default_rng(1).integers(0, 2 ** 32, 1000, dtype=np.uint64)
+    vals = np.array([orc.u01(int(x)) for x in xs])
+    assert np.array_equal(vals.astype(np.float32).astype(np.float64), vals)
     u = orc.uniforms(seed=0x1234_5678_9ABC, iteration=3, cls=2, freq_index=5, package_id=77, n=9)
     for b in range(2):
         words = orc.philox([b, 77, 5, (3 << 8) | 2], [0x5678_9ABC, 0x1234])
