@@ -100,6 +100,8 @@ typedef struct {
  * reverse links of Sect. 2.1.1 (one parent index per non-root octet) and
  * the leaf list.  Synchronises the stream.  SOC_EGRID on a malformed grid. */
 soc_status soc_build_grid(soc_ctx ctx, const soc_grid_desc *desc, soc_grid *out);
+/* Frees the grid's private arrays; valid before or after its context is
+ * destroyed. */
 void soc_grid_destroy(soc_grid grid);
 /* Number of leaf cells and (optional) device pointer to the reverse links
  * (int32 per non-root octet; NULL for a regular grid). */
@@ -183,7 +185,7 @@ typedef struct soc_temp_table_s *soc_temp_table;
 soc_status soc_temp_table_build(soc_ctx ctx, int32_t K, const double *nu, const double *w_nu,
                                 const double *sigma_abs, double T_floor, double T_max, int32_t nT,
                                 soc_temp_table *out);
-void soc_temp_table_destroy(soc_temp_table t);
+void soc_temp_table_destroy(soc_temp_table t);   /* valid before or after its context is destroyed */
 
 typedef struct {
     double mean_T;            /* over leaves with n > 0 */

@@ -185,8 +185,9 @@ int32_t orc_validate_grid(const orc_grid *g)
 
 /* ------------------------------------------------------------------ */
 /* Henyey-Greenstein scattering (analytic inversion of the HG cumulative
- * distribution) followed by the rotation of the direction about the old
- * one by polar angle acos(mu) and azimuth phi. */
+ * distribution) followed by the exact rotation of the direction about the
+ * old one by polar angle acos(mu) and azimuth phi (the z-axis formula is
+ * used only when the old direction is the z axis itself). */
 static void scatter_dir(double g, double xi_mu, double xi_phi, double u[3])
 {
     double mu;
@@ -202,12 +203,13 @@ static void scatter_dir(double g, double xi_mu, double xi_phi, double u[3])
     double phi = 2.0 * ORC_PI * xi_phi;
     double cp = cos(phi), sp = sin(phi);
     double ux = u[0], uy = u[1], uz = u[2], n0, n1, n2;
-    if (fabs(uz) > 0.99999) {
+    double t2 = ux * ux + uy * uy;   /* squared transverse length of the old direction */
+    if (t2 < 1e-30) {
         n0 = st * cp;
         n1 = st * sp;
         n2 = (uz >= 0.0 ? 1.0 : -1.0) * mu;
     } else {
-        double t = sqrt(1.0 - uz * uz);
+        double t = sqrt(t2);
         n0 = st * (ux * uz * cp - uy * sp) / t + ux * mu;
         n1 = st * (uy * uz * cp + ux * sp) / t + uy * mu;
         n2 = -st * cp * t + uz * mu;

@@ -47,7 +47,8 @@ struct soc_ctx_s {
 };
 
 struct soc_grid_s {
-    soc_ctx ctx = nullptr;
+    soc_ctx ctx = nullptr;   // identity check only; never dereferenced after creation
+    int device = 0;
     int32_t nx = 0, ny = 0, nz = 0, nlevels = 0;
     int64_t ncells = 0, nroot = 0, nleaves = 0;
     std::vector<int64_t> level_offset;
@@ -58,7 +59,8 @@ struct soc_grid_s {
 };
 
 struct soc_temp_table_s {
-    soc_ctx ctx = nullptr;
+    soc_ctx ctx = nullptr;   // identity check only; never dereferenced after creation
+    int device = 0;
     int32_t nT = 0;
     double T_floor = 0.0, T_max = 0.0, lnTf = 0.0, dlnT = 0.0;
     double *d_lnG = nullptr;
@@ -386,6 +388,7 @@ soc_status soc_build_grid(soc_ctx c, const soc_grid_desc *d, soc_grid *out)
     soc_grid g = new (std::nothrow) soc_grid_s;
     if (!g) return fail(c, SOC_ENOMEM, "host allocation failed");
     g->ctx = c;
+    g->device = c->device;
     g->nx = d->nx; g->ny = d->ny; g->nz = d->nz; g->nlevels = d->nlevels;
     g->ncells = d->ncells;
     g->nroot = nroot;
@@ -447,10 +450,9 @@ soc_status soc_build_grid(soc_ctx c, const soc_grid_desc *d, soc_grid *out)
 void soc_grid_destroy(soc_grid g)
 {
     if (!g) return;
-    if (g->ctx) {
-        (void)hipSetDevice(g->ctx->device);
-        (void)hipStreamSynchronize(g->ctx->stream);
-    }
+    // hipFree waits for work that uses the memory; the context may already
+    // be gone, so only the device id recorded at creation is used
+    (void)hipSetDevice(g->device);
     (void)hipFree(g->d_parent);
     (void)hipFree(g->d_leaves);
     delete g;
@@ -572,6 +574,7 @@ soc_status soc_temp_table_build(soc_ctx c, int32_t K, const double *nu, const do
     soc_temp_table t = new (std::nothrow) soc_temp_table_s;
     if (!t) return fail(c, SOC_ENOMEM, "host allocation");
     t->ctx = c;
+    t->device = c->device;
     t->nT = nT;
     t->T_floor = T_floor;
     t->T_max = T_max;
@@ -607,10 +610,7 @@ soc_status soc_temp_table_build(soc_ctx c, int32_t K, const double *nu, const do
 void soc_temp_table_destroy(soc_temp_table t)
 {
     if (!t) return;
-    if (t->ctx) {
-        (void)hipSetDevice(t->ctx->device);
-        (void)hipStreamSynchronize(t->ctx->stream);
-    }
+    (void)hipSetDevice(t->device);
     (void)hipFree(t->d_lnG);
     delete t;
 }

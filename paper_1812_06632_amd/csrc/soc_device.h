@@ -133,27 +133,38 @@ __device__ inline void set_inverse(Pkg<R> &p)
 // Henyey-Greenstein draw (analytic inversion of the cumulative
 // distribution; isotropic for |g| < 1e-4) and rotation of the direction
 // by polar cosine mu and azimuth 2 pi xi_phi about the old direction.
+// sin(theta) is formed from the factors 1 - mu and 1 + mu written without
+// cancellation, and the transverse length of the old direction from its
+// x and y components, so that FP32 keeps full relative accuracy near
+// forward/backward scattering and near the poles.
 template <typename R>
 __device__ inline void hg_scatter(R g, R xi_mu, R xi_phi, R &ux, R &uy, R &uz)
 {
-    R mu;
+    R mu, one_m, one_p;
     if (m_abs(g) < (R)1e-4) {
         mu = (R)2 * xi_mu - (R)1;
+        one_m = (R)2 * ((R)1 - xi_mu);
+        one_p = (R)2 * xi_mu;
     } else {
-        const R s = ((R)1 - g * g) / ((R)1 - g + (R)2 * g * xi_mu);
+        const R den = (R)1 - g + (R)2 * g * xi_mu;
+        const R s = ((R)1 - g * g) / den;
         mu = ((R)1 + g * g - s * s) / ((R)2 * g);
+        // 1 - mu = (1-g)(1-xi)(s+1-g)/den,  1 + mu = (1+g) xi (1+g+s)/den
+        one_m = ((R)1 - g) * ((R)1 - xi_mu) * (s + (R)1 - g) / den;
+        one_p = ((R)1 + g) * xi_mu * ((R)1 + g + s) / den;
     }
     mu = m_min((R)1, m_max((R)-1, mu));
-    const R st = m_sqrt(m_max((R)0, (R)1 - mu * mu));
+    const R st = m_sqrt(m_max((R)0, one_m * one_p));
     R sp, cp;
     m_sincos2pi(xi_phi, &sp, &cp);
     R n0, n1, n2;
-    if (m_abs(uz) > (R)0.99999) {
+    const R t2 = ux * ux + uy * uy;
+    if (t2 < (R)1e-30) {
         n0 = st * cp;
         n1 = st * sp;
         n2 = (uz >= (R)0 ? mu : -mu);
     } else {
-        const R t = m_sqrt((R)1 - uz * uz);
+        const R t = m_sqrt(t2);
         n0 = st * (ux * uz * cp - uy * sp) / t + ux * mu;
         n1 = st * (uy * uz * cp + ux * sp) / t + uy * mu;
         n2 = -st * cp * t + uz * mu;
@@ -168,7 +179,7 @@ template <typename R>
 __device__ inline void iso_dir(R xi_mu, R xi_phi, R &ux, R &uy, R &uz)
 {
     const R mu = (R)2 * xi_mu - (R)1;
-    const R st = m_sqrt(m_max((R)0, (R)1 - mu * mu));
+    const R st = (R)2 * m_sqrt(xi_mu * ((R)1 - xi_mu));   // sqrt(1 - mu^2) without cancellation
     R sp, cp;
     m_sincos2pi(xi_phi, &sp, &cp);
     ux = st * cp;
@@ -220,7 +231,7 @@ __device__ inline bool emit_regular(const McArgs &A, uint64_t gid, Pkg<R> &p, Rn
         const int a = face >> 1;
         const bool neg = (face & 1) == 0;
         const R mu = m_sqrt(x3);
-        const R st = m_sqrt(m_max((R)0, (R)1 - mu * mu));
+        const R st = m_sqrt((R)1 - x3);   // exact 1 - x3 on the uniform grid
         R sp, cp;
         m_sincos2pi(x4, &sp, &cp);
         const R ua = neg ? mu : -mu, ub = st * cp, uc = st * sp;

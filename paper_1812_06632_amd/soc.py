@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 import torch
@@ -119,6 +120,7 @@ class Context:
         if rc != OK:
             raise SocError(rc, "soc_ctx_create failed")
         self.h = h
+        self._children = weakref.WeakSet()
 
     def check(self, rc):
         if rc != OK:
@@ -143,7 +145,10 @@ class Context:
         return {k: getattr(st, k) for k, _ in _SimStats._fields_}
 
     def close(self):
+        """Destroy the context after the grids and tables created on it."""
         if getattr(self, "h", None):
+            for ch in list(getattr(self, "_children", ())):
+                ch.close()
             _lib.soc_ctx_destroy(self.h)
             self.h = None
 
@@ -159,6 +164,7 @@ class Grid:
 
     def __init__(self, ctx: Context, h, words: torch.Tensor, desc):
         self.ctx, self.h, self.words, self.desc = ctx, h, words, desc
+        ctx._children.add(self)
         self.nx, self.ny, self.nz, self.nlevels = desc.nx, desc.ny, desc.nz, desc.nlevels
         self.ncells = desc.ncells
 
@@ -255,6 +261,7 @@ def trace_packages(ctx: Context, grid: Grid, freq, cls, ids, *, precision=0, max
 class TempTable:
     def __init__(self, ctx, h):
         self.ctx, self.h = ctx, h
+        ctx._children.add(self)
 
     def close(self):
         if getattr(self, "h", None):

@@ -33,13 +33,30 @@ def compare_trace(gpu_seg, orc_seg, rtol, atol=1e-12):
 
 
 def batch_z(gpu_batches, orc_batches):
-    """Per-cell z-scores between two sets of independent batches."""
+    """Per-cell z-scores between two sets of B independent batches with the
+    pooled batch variance: under the null hypothesis z follows Student's t
+    with 2B - 2 degrees of freedom.  Returns (z, mean_gpu, mean_orc, dof)."""
     g = np.asarray(gpu_batches)
     o = np.asarray(orc_batches)
+    B = g.shape[0]
     mg, mo = g.mean(0), o.mean(0)
-    sg = g.std(0, ddof=1) / math.sqrt(g.shape[0])
-    so = o.std(0, ddof=1) / math.sqrt(o.shape[0])
-    den = np.sqrt(sg * sg + so * so)
+    sp2 = 0.5 * (g.var(0, ddof=1) + o.var(0, ddof=1))
     with np.errstate(divide="ignore", invalid="ignore"):
-        z = (mg - mo) / den
-    return z, mg, mo
+        z = (mg - mo) / np.sqrt(sp2 * 2.0 / B)
+    return z, mg, mo, 2 * B - 2
+
+
+def check_z(z, mg, mo, dof, label):
+    """Parity criteria on selected cells: |mean z| < 0.1, std z within 0.1
+    of the Student-t value, KS p > 1e-3 against t(dof), aggregate relative
+    bias sum(mg - mo) / sum(mo) below 0.3%."""
+    from scipy import stats
+    t_std = math.sqrt(dof / (dof - 2.0))
+    p = stats.kstest(z, stats.t(dof).cdf).pvalue
+    bias = float(np.sum(mg - mo) / np.sum(mo))
+    print(f"\n{label}: {z.size} cells, z mean {z.mean():.3f} std {z.std():.3f} (t std {t_std:.3f}) "
+          f"KS p {p:.3g} bias {bias:.2e}")
+    assert abs(z.mean()) < 0.1
+    assert abs(z.std() - t_std) < 0.1
+    assert p > 1e-3
+    assert abs(bias) < 3e-3
