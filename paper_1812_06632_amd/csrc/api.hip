@@ -127,7 +127,6 @@ soc_status prepare(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *
     if (st) return st;
     if (!g) return fail(c, SOC_EINVAL, "grid is NULL");
     if (g->ctx != c) return fail(c, SOC_EINVAL, "grid belongs to another context");
-    if (g->nlevels != 1) return fail(c, SOC_EINVAL, "octree grids are not supported by this build of the MC kernel");
     if (!s) return fail(c, SOC_EINVAL, "sources is NULL");
     if (!finite_nonneg(s->I_bg_nu)) return fail(c, SOC_EINVAL, "I_bg_nu must be finite and >= 0");
     if (s->n_ps < 0 || s->n_ps > kMaxPs) return fail(c, SOC_EINVAL, "n_ps must be in [0, %d]", kMaxPs);
@@ -141,6 +140,7 @@ soc_status prepare(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *
     A.parent = g->d_parent;
     A.nx = g->nx; A.ny = g->ny; A.nz = g->nz; A.nlevels = g->nlevels;
     A.ncells = g->ncells;
+    A.nroot = g->nroot;
     for (int i = 0; i <= kMaxLevels; ++i)
         A.level_offset[i] = i <= g->nlevels ? g->level_offset[i] : g->ncells;
     const double s_cm = g->root_cell_cm;
@@ -484,7 +484,7 @@ soc_status soc_simulate_frequency(soc_ctx c, soc_grid g, const soc_freq *f, cons
         HIPCHK(c, hipEventCreate(&e1));
         HIPCHK(c, hipEventRecord(e0, c->stream));
     }
-    HIPCHK(c, launch_mc_regular(A, blocks, (int)c->block, c->stream));
+    HIPCHK(c, launch_mc(A, blocks, (int)c->block, c->stream));
     if (c->timing) {
         HIPCHK(c, hipEventRecord(e1, c->stream));
         c->ev_start.push_back(e0);
@@ -550,7 +550,7 @@ soc_status soc_trace_packages(soc_ctx c, soc_grid g, const soc_freq *f, const so
     T.nseg = d_n;
     if (hipMemcpyAsync(d_ids, ids, sizeof(uint32_t) * n, hipMemcpyHostToDevice, c->stream) != hipSuccess)
         return cleanup(fail(c, SOC_EHIP, "copy ids"));
-    hipError_t e = launch_trace_regular(A, T, precision, c->stream);
+    hipError_t e = launch_trace(A, T, precision, c->stream);
     if (e != hipSuccess) return cleanup(fail(c, SOC_EHIP, "trace launch: %s", hipGetErrorString(e)));
     if (hipMemcpyAsync(out, d_out, sizeof(SegmentDev) * (size_t)n * max_seg, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
         hipMemcpyAsync(n_seg, d_n, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||

@@ -1,4 +1,4 @@
-// mc.hip -- Monte Carlo photon-package kernels for a regular grid
+// mc.hip -- Monte Carlo photon-package kernels for regular and octree grids
 // (Juvela 2019, Sect. 2.1.1: one package per thread, one frequency per
 // launch, absorbed energy counted per cell).
 //
@@ -55,7 +55,8 @@ __device__ inline void flush_stats(const McArgs &A, unsigned long long pk, unsig
     }
 }
 
-__global__ __launch_bounds__(1024) void mc_regular_kernel(McArgs A)
+template <bool Oct>
+__global__ __launch_bounds__(1024) void mc_kernel(McArgs A)
 {
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -86,7 +87,7 @@ __global__ __launch_bounds__(1024) void mc_regular_kernel(McArgs A)
                 if (id < A.n_total) {
                     uint32_t cls, pid;
                     double W0;
-                    const bool ok = emit_regular<float>(A, id, p, rng, cls, pid, W0);
+                    const bool ok = emit<float, Oct>(A, id, p, rng, cls, pid, W0);
                     n_pk += 1;
                     if (ok) e_em += W0;
                     active = ok;
@@ -107,7 +108,7 @@ __global__ __launch_bounds__(1024) void mc_regular_kernel(McArgs A)
         for (int s = 0; s < A.inner_steps; ++s) {
             if (active) {
                 float d;
-                const StepOut o = step_regular<float>(p, A, ks, ka, d);
+                const StepOut o = step<float, Oct>(p, A, ks, ka, d);
                 n_st += 1;
                 if (o.dep > 0.0) {
                     unsafeAtomicAdd(&A.absorbed[o.cell], o.dep);
@@ -127,15 +128,16 @@ __global__ __launch_bounds__(1024) void mc_regular_kernel(McArgs A)
     flush_stats(A, n_pk, n_st, n_sc, n_ru, e_em, e_ab, e_es);
 }
 
-hipError_t launch_mc_regular(const McArgs &a, int blocks, int threads, hipStream_t s)
+hipError_t launch_mc(const McArgs &a, int blocks, int threads, hipStream_t s)
 {
-    hipLaunchKernelGGL(mc_regular_kernel, dim3(blocks), dim3(threads), 0, s, a);
+    if (a.nlevels > 1) hipLaunchKernelGGL(mc_kernel<true>, dim3(blocks), dim3(threads), 0, s, a);
+    else hipLaunchKernelGGL(mc_kernel<false>, dim3(blocks), dim3(threads), 0, s, a);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ traces
-template <typename R>
-__global__ __launch_bounds__(256) void trace_regular_kernel(McArgs A, TraceArgs T)
+template <typename R, bool Oct>
+__global__ __launch_bounds__(256) void trace_kernel(McArgs A, TraceArgs T)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= T.n) return;
@@ -154,10 +156,10 @@ __global__ __launch_bounds__(256) void trace_regular_kernel(McArgs A, TraceArgs 
     const R ka = sizeof(R) == 8 ? (R)A.ka_d : (R)A.ka_f;
     const R g = sizeof(R) == 8 ? (R)A.g_d : (R)A.g_f;
     SegmentDev *out = T.out + (int64_t)i * T.max_seg;
-    if (emit_regular<R>(A, gid, p, rng, cls, pid, W0)) {
+    if (emit<R, Oct>(A, gid, p, rng, cls, pid, W0)) {
         for (;;) {
             R d;
-            const StepOut o = step_regular<R>(p, A, ks, ka, d);
+            const StepOut o = step<R, Oct>(p, A, ks, ka, d);
             if (ns < T.max_seg) {
                 out[ns].cell = o.cell;
                 out[ns].ds = (double)d;
@@ -172,12 +174,15 @@ __global__ __launch_bounds__(256) void trace_regular_kernel(McArgs A, TraceArgs 
     T.nseg[i] = ns;
 }
 
-hipError_t launch_trace_regular(const McArgs &a, const TraceArgs &t, int precision, hipStream_t s)
+hipError_t launch_trace(const McArgs &a, const TraceArgs &t, int precision, hipStream_t s)
 {
     const int threads = 64;
     const int blocks = (t.n + threads - 1) / threads;
-    if (precision == 1) hipLaunchKernelGGL(trace_regular_kernel<double>, dim3(blocks), dim3(threads), 0, s, a, t);
-    else hipLaunchKernelGGL(trace_regular_kernel<float>, dim3(blocks), dim3(threads), 0, s, a, t);
+    const bool oct = a.nlevels > 1;
+    if (precision == 1 && oct) hipLaunchKernelGGL((trace_kernel<double, true>), dim3(blocks), dim3(threads), 0, s, a, t);
+    else if (precision == 1) hipLaunchKernelGGL((trace_kernel<double, false>), dim3(blocks), dim3(threads), 0, s, a, t);
+    else if (oct) hipLaunchKernelGGL((trace_kernel<float, true>), dim3(blocks), dim3(threads), 0, s, a, t);
+    else hipLaunchKernelGGL((trace_kernel<float, false>), dim3(blocks), dim3(threads), 0, s, a, t);
     return hipGetLastError();
 }
 

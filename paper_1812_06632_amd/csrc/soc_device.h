@@ -111,9 +111,14 @@ __device__ inline double one_minus_exp_neg(double x) { return -expm1(-x); }
 // cell in [0,1]^3 (kept cell-relative so that FP32 rounding does not grow
 // with the distance travelled), direction and its reciprocals, remaining
 // free path in scattering optical depth, weight and floor.
+//
+// On an octree grid (cx, cy, cz) are the root-grid coordinates of the
+// current leaf's root ancestor, c is the leaf and L its level (0 = root);
+// the position is then relative to the leaf, in units of its edge.
 template <typename R>
 struct Pkg {
     int32_t cx, cy, cz;
+    int32_t c, L;
     R fx, fy, fz;
     R ux, uy, uz;
     R ix, iy, iz;   // 1/u (inf where u == 0)
@@ -205,15 +210,82 @@ __device__ inline void split_coord(double p, int32_t n, int32_t &c, R &f)
     f = (R)(p - fl);
 }
 
+// ------------------------------------------------------------------ octree walk
+// Descend from cell p.c (position p.f in its units) to the leaf containing
+// the position: child octant o = [f >= 1/2] per axis, f -> 2 f - o.
+template <typename R>
+__device__ inline void descend(Pkg<R> &p, const McArgs &A)
+{
+    int32_t w = (int32_t)A.words[p.c];
+    while (w < 0) {
+        const int32_t ox = p.fx >= (R)0.5, oy = p.fy >= (R)0.5, oz = p.fz >= (R)0.5;
+        p.fx = (R)2 * p.fx - (R)ox;
+        p.fy = (R)2 * p.fy - (R)oy;
+        p.fz = (R)2 * p.fz - (R)oz;
+        p.c = -w + ox + 2 * oy + 4 * oz;
+        p.L += 1;
+        w = (int32_t)A.words[p.c];
+    }
+}
+
+// Move across the face of axis `a` of the current leaf (fw: towards +):
+// the partial traversal of Sect. 2.1.1 -- up through the reverse links
+// while the face is also a face of the parent, across to the sibling (or
+// the neighbouring root cell), then down by position.  The exit coordinate
+// must already be on the face (1 when fw, 0 otherwise).  Returns false
+// when the package leaves the box.  Octets are 8-aligned relative to every
+// level offset, all of which are congruent to nroot mod 8, so the octant of
+// a non-root cell is (c - nroot) & 7.
+template <typename R>
+__device__ inline bool cross_octree(Pkg<R> &p, const McArgs &A, int a, bool fw)
+{
+    for (;;) {
+        if (p.L == 0) {
+            if (a == 0) {
+                p.cx += fw ? 1 : -1;
+                if (p.cx < 0 || p.cx >= A.nx) return false;
+                p.fx = fw ? (R)0 : (R)1;
+            } else if (a == 1) {
+                p.cy += fw ? 1 : -1;
+                if (p.cy < 0 || p.cy >= A.ny) return false;
+                p.fy = fw ? (R)0 : (R)1;
+            } else {
+                p.cz += fw ? 1 : -1;
+                if (p.cz < 0 || p.cz >= A.nz) return false;
+                p.fz = fw ? (R)0 : (R)1;
+            }
+            p.c = p.cx + A.nx * (p.cy + A.ny * p.cz);
+            break;
+        }
+        const int32_t o = (int32_t)((p.c - A.nroot) & 7);
+        const int32_t bit = (o >> a) & 1;
+        if (fw ? bit == 0 : bit == 1) {
+            p.c += fw ? (1 << a) : -(1 << a);
+            if (a == 0) p.fx = fw ? (R)0 : (R)1;
+            else if (a == 1) p.fy = fw ? (R)0 : (R)1;
+            else p.fz = fw ? (R)0 : (R)1;
+            break;
+        }
+        p.fx = (p.fx + (R)(o & 1)) * (R)0.5;
+        p.fy = (p.fy + (R)((o >> 1) & 1)) * (R)0.5;
+        p.fz = (p.fz + (R)((o >> 2) & 1)) * (R)0.5;
+        p.c = A.parent[(p.c - A.nroot) >> 3];
+        p.L -= 1;
+    }
+    descend(p, A);
+    return true;
+}
+
 // ------------------------------------------------------------------ emission
 // Emit package `gid` (global order: background | point sources | dust) and
 // draw its first free path.  Returns false for a package that carries no
 // energy (it is counted but not traced).  `cls`/`pid` receive the class
 // and the id within the class; W0 the package energy.
-template <typename R>
-__device__ inline bool emit_regular(const McArgs &A, uint64_t gid, Pkg<R> &p, Rng &rng, uint32_t &cls,
-                                    uint32_t &pid, double &W0)
+template <typename R, bool Oct>
+__device__ inline bool emit(const McArgs &A, uint64_t gid, Pkg<R> &p, Rng &rng, uint32_t &cls,
+                            uint32_t &pid, double &W0)
 {
+    p.L = 0;
     const uint64_t nps_tot = (uint64_t)A.n_ps * A.n_ps_pk;
     if (gid < A.n_bg) {
         cls = kClassBg;
@@ -285,14 +357,27 @@ __device__ inline bool emit_regular(const McArgs &A, uint64_t gid, Pkg<R> &p, Rn
             W0 = A.dust_incl[A.ncells - 1] / (double)A.n_dust;
         }
         if (!(W0 > 0.0)) return false;
-        p.cx = (int32_t)(c % A.nx);
-        p.cy = (int32_t)((c / A.nx) % A.ny);
-        p.cz = (int32_t)(c / ((int64_t)A.nx * A.ny));
+        int64_t root = c;
+        if (Oct) {
+            // level of the leaf, then up through the reverse links to its root ancestor
+            int L = 0;
+            while (L + 1 < A.nlevels && c >= A.level_offset[L + 1]) ++L;
+            p.L = L;
+            p.c = (int32_t)c;
+            for (int l = L; l > 0; --l) root = A.parent[(root - A.nroot) >> 3];
+        }
+        p.cx = (int32_t)(root % A.nx);
+        p.cy = (int32_t)((root / A.nx) % A.ny);
+        p.cz = (int32_t)(root / ((int64_t)A.nx * A.ny));
         p.fx = next_u<R>(rng, A);
         p.fy = next_u<R>(rng, A);
         p.fz = next_u<R>(rng, A);
         const R x3 = next_u<R>(rng, A), x4 = next_u<R>(rng, A);
         iso_dir<R>(x3, x4, p.ux, p.uy, p.uz);
+    }
+    if (Oct && cls != kClassDust) {
+        p.c = p.cx + A.nx * (p.cy + A.ny * p.cz);
+        descend(p, A);
     }
     set_inverse(p);
     p.tau = -m_log(next_u<R>(rng, A));
@@ -386,6 +471,86 @@ __device__ inline StepOut step_regular(Pkg<R> &p, const McArgs &A, R ks_scale, R
     o.event = ev;
     d_out = d;
     return o;
+}
+
+// The same segment on an octree: distances and optical depths in units of
+// the current leaf (edge 2^-L root cells); a crossing moves to the
+// neighbouring leaf with cross_octree.  d_out is in root units.
+template <typename R>
+__device__ inline StepOut step_octree(Pkg<R> &p, const McArgs &A, R ks_scale, R ka_scale, R &d_out)
+{
+    StepOut o;
+    const int64_t c = p.c;
+    o.cell = c;
+    const R edge = (R)1 / (R)(1 << p.L);
+    const R n = (R)__uint_as_float(A.words[c]);
+    const R ks = n * ks_scale * edge, ka = n * ka_scale * edge;
+    const R dx = p.ux != (R)0 ? ((p.ux > (R)0 ? (R)1 : (R)0) - p.fx) * p.ix : m_inf<R>();
+    const R dy = p.uy != (R)0 ? ((p.uy > (R)0 ? (R)1 : (R)0) - p.fy) * p.iy : m_inf<R>();
+    const R dz = p.uz != (R)0 ? ((p.uz > (R)0 ? (R)1 : (R)0) - p.fz) * p.iz : m_inf<R>();
+    const int ax = (dx <= dy && dx <= dz) ? 0 : (dy <= dz ? 1 : 2);
+    const R dexit = m_max((R)0, ax == 0 ? dx : (ax == 1 ? dy : dz));
+    R d;
+    int ev;
+    const R tcell = ks * dexit;
+    if (ks > (R)0 && tcell >= p.tau) {
+        d = m_min(p.tau / ks, dexit);
+        ev = kEvScatter;
+    } else {
+        d = dexit;
+        p.tau -= tcell;
+        ev = kEvCross;
+    }
+    const R fr = one_minus_exp_neg(ka * d);
+    double dep = p.W * (double)fr;
+    p.W -= dep;
+    p.steps += 1;
+    d_out = d * edge;
+    if (ev == kEvCross) {
+        bool fw;
+        if (ax == 0) {
+            p.fy = m_min((R)1, m_max((R)0, p.fy + d * p.uy));
+            p.fz = m_min((R)1, m_max((R)0, p.fz + d * p.uz));
+            fw = p.ux > (R)0;
+            p.fx = fw ? (R)1 : (R)0;
+        } else if (ax == 1) {
+            p.fx = m_min((R)1, m_max((R)0, p.fx + d * p.ux));
+            p.fz = m_min((R)1, m_max((R)0, p.fz + d * p.uz));
+            fw = p.uy > (R)0;
+            p.fy = fw ? (R)1 : (R)0;
+        } else {
+            p.fx = m_min((R)1, m_max((R)0, p.fx + d * p.ux));
+            p.fy = m_min((R)1, m_max((R)0, p.fy + d * p.uy));
+            fw = p.uz > (R)0;
+            p.fz = fw ? (R)1 : (R)0;
+        }
+        if (!cross_octree(p, A, ax, fw)) ev = kEvEscape;
+    } else {
+        p.fx = m_min((R)1, m_max((R)0, p.fx + d * p.ux));
+        p.fy = m_min((R)1, m_max((R)0, p.fy + d * p.uy));
+        p.fz = m_min((R)1, m_max((R)0, p.fz + d * p.uz));
+    }
+    if (ev != kEvEscape) {
+        if (p.W < p.Wfloor) {
+            dep += p.W;
+            p.W = 0.0;
+            ev = kEvFloor;
+        } else if ((int64_t)p.steps >= A.step_cap) {
+            dep += p.W;
+            p.W = 0.0;
+            ev = kEvRunaway;
+        }
+    }
+    o.dep = dep;
+    o.event = ev;
+    return o;
+}
+
+template <typename R, bool Oct>
+__device__ inline StepOut step(Pkg<R> &p, const McArgs &A, R ks_scale, R ka_scale, R &d_out)
+{
+    if (Oct) return step_octree<R>(p, A, ks_scale, ka_scale, d_out);
+    return step_regular<R>(p, A, ks_scale, ka_scale, d_out);
 }
 
 template <typename R>

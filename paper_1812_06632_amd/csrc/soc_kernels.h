@@ -39,7 +39,7 @@ struct McArgs {
     const uint32_t *words;
     const int32_t *parent;      // reverse links (octree only)
     int32_t nx, ny, nz, nlevels;
-    int64_t ncells;
+    int64_t ncells, nroot;
     int64_t level_offset[kMaxLevels + 1];
     // frequency: k = sigma * root_cell_cm per unit density per root unit
     float ks_f, ka_f, g_f;
@@ -82,8 +82,9 @@ struct TraceArgs {
 };
 
 // ---- launchers (each returns the launch status) ----
-hipError_t launch_mc_regular(const McArgs &a, int blocks, int threads, hipStream_t s);
-hipError_t launch_trace_regular(const McArgs &a, const TraceArgs &t, int precision, hipStream_t s);
+// Regular-grid kernels when a.nlevels == 1, octree kernels otherwise.
+hipError_t launch_mc(const McArgs &a, int blocks, int threads, hipStream_t s);
+hipError_t launch_trace(const McArgs &a, const TraceArgs &t, int precision, hipStream_t s);
 
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);

@@ -316,3 +316,54 @@ def lognormal_problem(n: int = 128, K: int = 64, sigma_ln: float = 1.0, tau_v_me
                    n_bg=packages_per_freq // 2,
                    n_ps_pk=(packages_per_freq // 2) // max(n_ps, 1) if n_ps else 0,
                    n_dust=packages_per_freq)
+
+
+def octree_from_field(field: np.ndarray, n_root: int, nlevels: int, root_cell_cm: float,
+                      threshold: float = 4.0) -> Grid:
+    """Octree over a cubic field sampled at the finest resolution
+    n_root * 2^(nlevels-1): a cell is refined when the mean of the field
+    over its volume exceeds `threshold` times the global mean; leaves hold
+    the mean over their volume (block averages, so mass is conserved)."""
+    M = n_root << (nlevels - 1)
+    f = np.asarray(field, dtype=np.float64)
+    if f.shape != (M, M, M):
+        raise ValueError(f"field must be {M}^3")
+    means = []
+    for L in range(nlevels):
+        b = 1 << (nlevels - 1 - L)
+        n = n_root << L
+        means.append(f.reshape(n, b, n, b, n, b).mean(axis=(1, 3, 5)))   # [z, y, x]
+    gmean = f.mean()
+
+    def _lookup(L, lo):
+        idx = np.rint(lo * (1 << L)).astype(np.int64)
+        return means[L][idx[:, 2], idx[:, 1], idx[:, 0]]
+
+    def refine(L, lo, size):
+        return _lookup(L, lo) > threshold * gmean
+
+    def density(lo, size):
+        L = int(round(-math.log2(size)))
+        return _lookup(L, lo)
+
+    return octree_from_function(n_root, n_root, n_root, nlevels, root_cell_cm, refine, density)
+
+
+def octree_lognormal(n_root: int = 64, nlevels: int = 4, sigma_ln: float = 1.5, seed: int = 3,
+                     tau_v_core: float = 100.0, core_contrast: float = 200.0, box_pc: float = 1.0,
+                     threshold: float = 4.0) -> Grid:
+    """Lognormal cloud (GRF, P(k) ~ k^-3) times a central Gaussian core of
+    the given contrast, refined top-down where the cell mean exceeds
+    `threshold` times the mean, scaled so that the optical depth at 0.55 um
+    from the centre to the edge along +x is tau_v_core."""
+    M = n_root << (nlevels - 1)
+    rho = grf_lognormal(M, sigma_ln, seed)
+    c = (np.arange(M) + 0.5) / M - 0.5
+    z, y, x = np.meshgrid(c, c, c, indexing="ij", sparse=True)
+    r2 = x * x + y * y + z * z
+    sig = 0.1
+    rho = rho * (1.0 + (core_contrast - 1.0) * np.exp(-0.5 * r2 / (sig * sig)))
+    s_fine = box_pc * PC_CM / M
+    col = rho[M // 2, M // 2, M // 2:].sum() * s_fine
+    rho *= tau_v_core / (SIGMA_V * col)
+    return octree_from_field(rho, n_root, nlevels, box_pc * PC_CM / n_root, threshold)

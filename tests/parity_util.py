@@ -15,21 +15,33 @@ def _clean(seg):
 
 def compare_trace(gpu_seg, orc_seg, rtol, atol=1e-12):
     """Compare one package's segments.  Returns (match, n_compared,
-    max_rel_err, path_rel_err, first_mismatch_index)."""
+    max_rel_err, path_rel_err, first_mismatch_index): match requires the
+    same cells and events and every length within atol + rtol * ds."""
+    same, n, max_abs, path_rel, first = compare_structure(gpu_seg, orc_seg)
+    if not same:
+        return False, n, float("nan"), float("nan"), first
+    g, o = _clean(gpu_seg), _clean(orc_seg)
+    d = np.abs(g["ds"] - o["ds"])
+    bad = np.nonzero(d > atol + rtol * np.abs(o["ds"]))[0]
+    rel = float(np.max(d / np.maximum(np.abs(o["ds"]), 1e-300))) if len(d) else 0.0
+    if len(bad):
+        return False, int(bad[0]), rel, path_rel, int(bad[0])
+    return True, len(g), rel, path_rel, -1
+
+
+def compare_structure(gpu_seg, orc_seg):
+    """Same cell and event sequence?  Returns (same, n, max_abs_ds_err,
+    path_rel_err, first_structural_mismatch)."""
     g, o = _clean(gpu_seg), _clean(orc_seg)
     n = min(len(g), len(o))
-    max_rel = 0.0
-    for i in range(n):
-        if g["cell"][i] != o["cell"][i] or g["event"][i] != o["event"][i]:
-            return False, i, max_rel, float("nan"), i
-        d = abs(g["ds"][i] - o["ds"][i])
-        if d > atol + rtol * abs(o["ds"][i]):
-            return False, i, max(max_rel, d / max(abs(o["ds"][i]), 1e-300)), float("nan"), i
-        max_rel = max(max_rel, d / max(abs(o["ds"][i]), 1e-300))
+    cm = np.nonzero((g["cell"][:n] != o["cell"][:n]) | (g["event"][:n] != o["event"][:n]))[0]
+    if len(cm):
+        return False, n, float("nan"), float("nan"), int(cm[0])
     if len(g) != len(o):
-        return False, n, max_rel, float("nan"), n
+        return False, n, float("nan"), float("nan"), n
     pg, po = g["ds"].sum(), o["ds"].sum()
-    return True, n, max_rel, abs(pg - po) / max(po, 1e-300), -1
+    max_abs = float(np.max(np.abs(g["ds"] - o["ds"]))) if n else 0.0
+    return True, n, max_abs, abs(pg - po) / max(po, 1e-300), -1
 
 
 def batch_z(gpu_batches, orc_batches):

@@ -18,7 +18,7 @@ from scipy import stats
 
 from oracle import orc
 from paper_1812_06632_amd import workloads as W
-from tests.parity_util import batch_z, check_z, compare_trace
+from tests.parity_util import batch_z, check_z, compare_structure, compare_trace
 
 pytestmark = pytest.mark.gpu
 
@@ -97,20 +97,27 @@ def test_traces_fp64_mode_match_oracle_exactly(soc, ctx, sphere):
 
 
 def test_traces_fp32_production_match_oracle(soc, ctx, sphere):
-    """FP32 production arithmetic: packages follow the oracle's cells; path
-    lengths agree to 1e-6 relative; a package may leave the oracle's path
-    only at a near-tie (two events closer than the FP32 resolution)."""
+    """FP32 production arithmetic: packages follow the oracle's cells and
+    events; path lengths agree to 1e-6 relative; segment lengths drift by
+    at most 1e-3 cell (FP32 rounding of positions and directions
+    accumulated over the walk).  A package may leave the oracle's cell
+    sequence only at a near-tie of two events."""
     P = sphere
     g = soc.grid_from_workload(ctx, P.grid)
     f = _freq_of(P, 0)
-    ids = np.arange(0, 100_000, 100)
-    res = _trace_both(soc, ctx, g, P.grid, f, soc.CLASS_BG, ids, 0, I_bg=P.I_bg[0], n_bg=P.n_bg)
-    ok = np.array([r[0] for r in res])
+    ids = np.arange(0, 100_000, 50).astype(np.uint32)
+    kw = dict(I_bg=P.I_bg[0], n_bg=P.n_bg)
+    segs, nseg = soc.trace_packages(ctx, g, f, soc.CLASS_BG, ids, precision=0, max_seg=4096, **kw)
+    res = [compare_structure(segs[i][: nseg[i]], orc.trace_package(P.grid, f, soc.CLASS_BG, int(pid), max_seg=4096,
+                                                                    **kw)) for i, pid in enumerate(ids)]
+    same = np.array([r[0] for r in res])
     path = np.array([r[3] for r in res if r[0]])
-    print(f"\nFP32 traces: {ok.mean():.4f} identical, path rel err median {np.median(path):.2e} "
-          f"p99 {np.quantile(path, 0.99):.2e} max {path.max():.2e}")
-    assert ok.mean() >= 0.99
+    drift = np.array([r[2] for r in res if r[0]])
+    print(f"\nFP32 traces: {same.mean():.4f} same cells/events, path rel err median {np.median(path):.2e} "
+          f"p99 {np.quantile(path, 0.99):.2e} max {path.max():.2e}; max segment drift {drift.max():.2e}")
+    assert same.mean() >= 0.99
     assert np.quantile(path, 0.99) < 1e-6
+    assert drift.max() < 1e-3
 
 
 @pytest.mark.parametrize("cls_name", ["bg", "ps0", "ps1", "dust_weighted", "dust_uniform"])
@@ -159,7 +166,7 @@ def test_same_seed_tallies_and_conservation(soc, ctx, sphere):
     assert sg["packages"] == so["packages"] == n
     assert abs(sg["cell_steps"] - so["cell_steps"]) <= 1e-4 * so["cell_steps"]
     assert abs(sg["scatterings"] - so["scatterings"]) <= 1e-4 * so["scatterings"]
-    assert sg["e_emitted"] == pytest.approx(so["e_emitted"], rel=1e-12)
+    assert sg["e_emitted"] == pytest.approx(so["e_emitted"], rel=1e-10)   # FP64 atomic summation order
     cons = (Ag.sum() + sg["e_escaped"]) / sg["e_emitted"] - 1.0
     assert abs(cons) < 1e-6
     assert sg["e_absorbed"] == pytest.approx(Ag.sum(), rel=1e-9)
