@@ -67,11 +67,12 @@ const char *soc_last_error(soc_ctx ctx);
 /* Tunables of the Monte Carlo kernels (defaults in brackets). */
 typedef enum {
     SOC_OPT_STEP_CAP = 0,        /* steps per package before it is stopped [10000000] */
-    SOC_OPT_BLOCK = 1,           /* threads per workgroup of the MC kernel, 64..1024 [256] */
+    SOC_OPT_BLOCK = 1,           /* threads per workgroup of the MC kernel, multiple of 64 in 64..512 [256] */
     SOC_OPT_BLOCKS_PER_CU = 2,   /* persistent workgroups launched per compute unit [8] */
     SOC_OPT_REFILL_MIN = 3,      /* refill a wave once this many lanes are idle, 1..64 [1] */
-    SOC_OPT_INNER_STEPS = 4,     /* cell steps between refill checks, 1..64 [1] */
-    SOC_OPT_TIMING = 5           /* 1 = time each MC launch with HIP events [0] */
+    SOC_OPT_INNER_STEPS = 4,     /* cell steps between refill checks, 1..8 [1] */
+    SOC_OPT_TIMING = 5,          /* 1 = time each MC launch with HIP events [0] */
+    SOC_OPT_SCATTER_MIN = 6      /* draw new directions once this many lanes of a wave wait for one, 1..64 [1] */
 } soc_option;
 soc_status soc_ctx_set_option(soc_ctx ctx, soc_option opt, int64_t value);
 soc_status soc_ctx_get_option(soc_ctx ctx, soc_option opt, int64_t *value);
@@ -199,7 +200,8 @@ typedef struct {
  * cells and values outside the table are clamped to [T_floor, T_max] and
  * counted.  d_T_old may equal d_T_new or be NULL (then no relative
  * change).  If stats is non-NULL the call synchronises and fills it (the
- * hottest-5% mean is resolved on a 16384-bin log-T histogram). */
+ * hottest-5% mean is found exactly from a coarse log-T histogram and a
+ * fine histogram of the bin holding the threshold). */
 soc_status soc_update_temperature(soc_ctx ctx, soc_grid grid, soc_temp_table table,
                                   const double *d_absorbed, const float *d_T_old, float *d_T_new,
                                   soc_temp_stats *stats);

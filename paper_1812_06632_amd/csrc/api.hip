@@ -32,6 +32,7 @@ struct soc_ctx_s {
     int64_t inner_steps = 1;
     int64_t timing = 0;
     int64_t chunk = 256;
+    int64_t scatter_min = 1;
     // scratch
     DevStats *d_stats = nullptr;              // [0] per call, [1] running total
     unsigned long long *d_counter = nullptr;
@@ -40,9 +41,11 @@ struct soc_ctx_s {
     int64_t cap_L = 0, cap_incl = 0, cap_scan = 0;
     int32_t *d_pkcell = nullptr;
     uint64_t cap_pk = 0;
-    double *d_tacc = nullptr;
-    unsigned int *d_hist_n = nullptr;
-    double *d_hist_T = nullptr;
+    double *d_tpart = nullptr;           // temperature statistics scratch
+    unsigned int *d_thist = nullptr;
+    double *d_tmeta = nullptr;
+    unsigned int *d_tfine_n = nullptr;
+    double *d_tfine_T = nullptr;
     std::vector<hipEvent_t> ev_start, ev_stop;
 };
 
@@ -222,6 +225,7 @@ soc_status prepare(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *
     A.refill_min = (int32_t)c->refill_min;
     A.inner_steps = (int32_t)c->inner_steps;
     A.chunk = (int32_t)c->chunk;
+    A.scatter_min = (int32_t)c->scatter_min;
     return SOC_OK;
 }
 
@@ -284,9 +288,11 @@ void soc_ctx_destroy(soc_ctx c)
     (void)hipFree(c->d_incl);
     (void)hipFree(c->d_scan);
     (void)hipFree(c->d_pkcell);
-    (void)hipFree(c->d_tacc);
-    (void)hipFree(c->d_hist_n);
-    (void)hipFree(c->d_hist_T);
+    (void)hipFree(c->d_tpart);
+    (void)hipFree(c->d_thist);
+    (void)hipFree(c->d_tmeta);
+    (void)hipFree(c->d_tfine_n);
+    (void)hipFree(c->d_tfine_T);
     delete c;
 }
 
@@ -308,7 +314,8 @@ soc_status soc_ctx_set_option(soc_ctx c, soc_option opt, int64_t v)
         c->step_cap = v;
         return SOC_OK;
     case SOC_OPT_BLOCK:
-        if (v < 64 || v > 1024 || v % 64) return fail(c, SOC_EINVAL, "block must be a multiple of 64 in [64,1024]");
+        if (v < 64 || v > kMcMaxBlock || v % 64)
+            return fail(c, SOC_EINVAL, "block must be a multiple of 64 in [64,%d]", kMcMaxBlock);
         c->block = v;
         return SOC_OK;
     case SOC_OPT_BLOCKS_PER_CU:
@@ -320,11 +327,15 @@ soc_status soc_ctx_set_option(soc_ctx c, soc_option opt, int64_t v)
         c->refill_min = v;
         return SOC_OK;
     case SOC_OPT_INNER_STEPS:
-        if (v < 1 || v > 64) return fail(c, SOC_EINVAL, "inner steps must be in [1,64]");
+        if (v < 1 || v > kDepSlots) return fail(c, SOC_EINVAL, "inner steps must be in [1,%d]", kDepSlots);
         c->inner_steps = v;
         return SOC_OK;
     case SOC_OPT_TIMING:
         c->timing = v ? 1 : 0;
+        return SOC_OK;
+    case SOC_OPT_SCATTER_MIN:
+        if (v < 1 || v > 64) return fail(c, SOC_EINVAL, "scatter threshold must be in [1,64]");
+        c->scatter_min = v;
         return SOC_OK;
     }
     return fail(c, SOC_EINVAL, "unknown option %d", (int)opt);
@@ -340,6 +351,7 @@ soc_status soc_ctx_get_option(soc_ctx c, soc_option opt, int64_t *v)
     case SOC_OPT_REFILL_MIN: *v = c->refill_min; return SOC_OK;
     case SOC_OPT_INNER_STEPS: *v = c->inner_steps; return SOC_OK;
     case SOC_OPT_TIMING: *v = c->timing; return SOC_OK;
+    case SOC_OPT_SCATTER_MIN: *v = c->scatter_min; return SOC_OK;
     }
     return fail(c, SOC_EINVAL, "unknown option %d", (int)opt);
 }
@@ -638,23 +650,29 @@ soc_status soc_update_temperature(soc_ctx c, soc_grid g, soc_temp_table t, const
     a.absorbed = d_absorbed;
     a.T_old = d_T_old;
     a.T_new = d_T_new;
+    int64_t blocks = (g->ncells + 255) / 256;
+    a.blocks = (int32_t)(blocks < kTempBlocks ? (blocks < 1 ? 1 : blocks) : kTempBlocks);
     if (stats) {
-        if (!c->d_tacc) {
-            if (hipMalloc((void **)&c->d_tacc, 8 * sizeof(double)) != hipSuccess ||
-                hipMalloc((void **)&c->d_hist_n, kHistBins * sizeof(unsigned int)) != hipSuccess ||
-                hipMalloc((void **)&c->d_hist_T, kHistBins * sizeof(double)) != hipSuccess)
+        if (!c->d_tpart) {
+            if (hipMalloc((void **)&c->d_tpart, (size_t)kTempBlocks * 8 * sizeof(double)) != hipSuccess ||
+                hipMalloc((void **)&c->d_thist, (size_t)(kTempBlocks + 1) * kHistBins * sizeof(unsigned int)) != hipSuccess ||
+                hipMalloc((void **)&c->d_tmeta, 8 * sizeof(double)) != hipSuccess ||
+                hipMalloc((void **)&c->d_tfine_n, kHistBins * sizeof(unsigned int)) != hipSuccess ||
+                hipMalloc((void **)&c->d_tfine_T, kHistBins * sizeof(double)) != hipSuccess)
                 return fail(c, SOC_ENOMEM, "temperature statistics buffers");
         }
-        HIPCHK(c, launch_fill_f64(c->d_tacc, 0.0, 8, c->stream));
-        HIPCHK(c, launch_fill_i32((int32_t *)c->d_hist_n, 0, kHistBins, c->stream));
-        HIPCHK(c, launch_fill_f64(c->d_hist_T, 0.0, kHistBins, c->stream));
-        a.acc = c->d_tacc;
-        a.hist_n = c->d_hist_n;
-        a.hist_T = c->d_hist_T;
+        HIPCHK(c, launch_fill_i32((int32_t *)c->d_tfine_n, 0, kHistBins, c->stream));
+        HIPCHK(c, launch_fill_f64(c->d_tfine_T, 0.0, kHistBins, c->stream));
+        a.part = c->d_tpart;
+        a.hist_part = c->d_thist;
+        a.hist_total = c->d_thist + (size_t)kTempBlocks * kHistBins;
+        a.meta = c->d_tmeta;
+        a.fine_n = c->d_tfine_n;
+        a.fine_T = c->d_tfine_T;
     }
     HIPCHK(c, launch_temp_update(a, c->stream));
     if (stats) {
-        HIPCHK(c, launch_temp_finish(a, c->d_tmp_out, c->stream));
+        HIPCHK(c, launch_temp_stats(a, c->d_tmp_out, c->stream));
         double h[4];
         HIPCHK(c, hipMemcpyAsync(h, c->d_tmp_out, sizeof h, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));

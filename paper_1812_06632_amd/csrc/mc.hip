@@ -9,7 +9,13 @@
 // `chunk` ids.  Creation and tracking of packages are thereby interleaved
 // (the scheme the paper suggests in Sect. 4.2), so lanes do not idle until
 // the slowest package of the wave ends.  Deposits go straight to the FP64
-// absorbed array with hardware FP64 atomics (global_atomic_add_f64).
+// absorbed array with hardware FP64 atomics (global_atomic_add_f64), but
+// not one by one: on CDNA the vector-memory counter retires loads and
+// atomics in issue order, so a wait for the next cell's density would also
+// wait for the previous step's atomic round trip.  Each lane therefore
+// stages its deposits in an LDS ring of kDepSlots entries and the wave
+// flushes the rings as one burst of atomics every kDepSlots iterations:
+// one atomic latency per kDepSlots steps instead of per step.
 #include "soc_device.h"
 
 namespace soc {
@@ -56,20 +62,29 @@ __device__ inline void flush_stats(const McArgs &A, unsigned long long pk, unsig
 }
 
 template <bool Oct>
-__global__ __launch_bounds__(1024) void mc_kernel(McArgs A)
+__global__ __launch_bounds__(kMcMaxBlock) void mc_kernel(McArgs A)
 {
+    extern __shared__ double lds_dep[];   // [kDepSlots][blockDim.x] deposits, then cells
+    int32_t *lds_cell = (int32_t *)(lds_dep + kDepSlots * blockDim.x);
+    const int tid = threadIdx.x;
+    const int bd = blockDim.x;
+    int nbuf = 0;          // deposits staged by this lane
+    int since_flush = 0;   // wave-uniform
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     Pkg<float> p;
     Rng rng;
-    bool active = false;
+    bool active = false;   // lane holds a package
+    bool pend = false;     // its last segment ended in a scattering whose new direction is not drawn yet
     unsigned long long pool_next = 0, pool_end = 0;   // wave-uniform
     bool exhausted = false;                           // wave-uniform
     unsigned long long n_pk = 0, n_st = 0, n_sc = 0, n_ru = 0;
     double e_em = 0.0, e_ab = 0.0, e_es = 0.0;
-    const float ks = A.ks_f, ka = A.ka_f, g = A.g_f;
+    const float ks = A.ks_f, ka = A.ka_f;
+    const HG<float> hg(A.g_f);
 
     for (;;) {
+        // refill idle lanes from the wave's id pool
         const unsigned long long idle = __ballot(!active);
         const int nidle = __popcll(idle);
         if (!exhausted && nidle > 0 && (nidle >= A.refill_min || nidle == 64)) {
@@ -105,17 +120,37 @@ __global__ __launch_bounds__(1024) void mc_kernel(McArgs A)
             if (exhausted) break;
             continue;
         }
+        // scatterings are drawn together once enough lanes wait for one
+        // (or no lane could step otherwise)
+        const unsigned long long pm = __ballot(pend);
+        if (pm) {
+            if (__popcll(pm) >= A.scatter_min || __ballot(active && !pend) == 0) {
+                if (pend) {
+                    scatter_new_direction<float>(p, rng, A, hg);
+                    pend = false;
+                }
+            }
+        }
+        if ((since_flush + 1) * A.inner_steps > kDepSlots) {
+            for (int j = 0; j < kDepSlots; ++j)
+                if (j < nbuf) unsafeAtomicAdd(&A.absorbed[lds_cell[j * bd + tid]], lds_dep[j * bd + tid]);
+            nbuf = 0;
+            since_flush = 0;
+        }
+        ++since_flush;
         for (int s = 0; s < A.inner_steps; ++s) {
-            if (active) {
+            if (active && !pend) {
                 float d;
                 const StepOut o = step<float, Oct>(p, A, ks, ka, d);
                 n_st += 1;
                 if (o.dep > 0.0) {
-                    unsafeAtomicAdd(&A.absorbed[o.cell], o.dep);
+                    lds_dep[nbuf * bd + tid] = o.dep;
+                    lds_cell[nbuf * bd + tid] = o.cell;
+                    ++nbuf;
                     e_ab += o.dep;
                 }
                 if (o.event == kEvScatter) {
-                    scatter_new_direction<float>(p, rng, A, g);
+                    pend = true;
                     n_sc += 1;
                 } else if (o.event != kEvCross) {
                     active = false;
@@ -125,13 +160,16 @@ __global__ __launch_bounds__(1024) void mc_kernel(McArgs A)
             }
         }
     }
+    for (int j = 0; j < kDepSlots; ++j)
+        if (j < nbuf) unsafeAtomicAdd(&A.absorbed[lds_cell[j * bd + tid]], lds_dep[j * bd + tid]);
     flush_stats(A, n_pk, n_st, n_sc, n_ru, e_em, e_ab, e_es);
 }
 
 hipError_t launch_mc(const McArgs &a, int blocks, int threads, hipStream_t s)
 {
-    if (a.nlevels > 1) hipLaunchKernelGGL(mc_kernel<true>, dim3(blocks), dim3(threads), 0, s, a);
-    else hipLaunchKernelGGL(mc_kernel<false>, dim3(blocks), dim3(threads), 0, s, a);
+    const size_t lds = (size_t)kDepSlots * threads * (sizeof(double) + sizeof(int32_t));
+    if (a.nlevels > 1) hipLaunchKernelGGL(mc_kernel<true>, dim3(blocks), dim3(threads), lds, s, a);
+    else hipLaunchKernelGGL(mc_kernel<false>, dim3(blocks), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
@@ -154,7 +192,7 @@ __global__ __launch_bounds__(256) void trace_kernel(McArgs A, TraceArgs T)
     int32_t ns = 0;
     const R ks = sizeof(R) == 8 ? (R)A.ks_d : (R)A.ks_f;
     const R ka = sizeof(R) == 8 ? (R)A.ka_d : (R)A.ka_f;
-    const R g = sizeof(R) == 8 ? (R)A.g_d : (R)A.g_f;
+    const HG<R> hg(sizeof(R) == 8 ? (R)A.g_d : (R)A.g_f);
     SegmentDev *out = T.out + (int64_t)i * T.max_seg;
     if (emit<R, Oct>(A, gid, p, rng, cls, pid, W0)) {
         for (;;) {
@@ -167,7 +205,7 @@ __global__ __launch_bounds__(256) void trace_kernel(McArgs A, TraceArgs T)
                 out[ns].pad = 0;
             }
             ++ns;
-            if (o.event == kEvScatter) scatter_new_direction<R>(p, rng, A, g);
+            if (o.event == kEvScatter) scatter_new_direction<R>(p, rng, A, hg);
             else if (o.event != kEvCross) break;
         }
     }

@@ -1,9 +1,11 @@
 // soc_device.h -- device-side building blocks of the SOC Monte Carlo path
 // (Juvela 2019, arXiv:1812.06632, Sect. 2.1.1): counter-based random
 // numbers, source emission, Henyey-Greenstein scattering and the per-cell
-// transport step.  Everything is templated on the tracing precision R so
-// that the FP32 production kernel and the FP64 deterministic trace mode
-// execute the same code.
+// transport step on regular and octree grids.  Everything is templated on
+// the tracing precision R so that the FP32 production kernel and the FP64
+// deterministic trace mode execute the same code; the FP32 instantiation
+// uses the hardware reciprocal / reciprocal square root (1 ulp), the FP64
+// one exact division.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -81,6 +83,10 @@ struct Rng {
 // ------------------------------------------------------------------ math
 __device__ inline float m_sqrt(float x) { return sqrtf(x); }
 __device__ inline double m_sqrt(double x) { return sqrt(x); }
+__device__ inline float m_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double m_rcp(double x) { return 1.0 / x; }
+__device__ inline float m_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double m_rsqrt(double x) { return 1.0 / sqrt(x); }
 __device__ inline float m_log(float x) { return logf(x); }
 __device__ inline double m_log(double x) { return log(x); }
 __device__ inline void m_sincos2pi(float t, float *s, float *c) { sincospif(2.0f * t, s, c); }
@@ -91,38 +97,44 @@ __device__ inline float m_min(float a, float b) { return fminf(a, b); }
 __device__ inline double m_min(double a, double b) { return fmin(a, b); }
 __device__ inline float m_max(float a, float b) { return fmaxf(a, b); }
 __device__ inline double m_max(double a, double b) { return fmax(a, b); }
+__device__ inline float m_clamp01(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
+__device__ inline double m_clamp01(double x) { return fmin(1.0, fmax(0.0, x)); }
 template <typename R> __device__ inline R m_inf();
 template <> __device__ inline float m_inf<float>() { return __builtin_huge_valf(); }
 template <> __device__ inline double m_inf<double>() { return __builtin_huge_val(); }
 
 // 1 - exp(-x) for x >= 0 without cancellation: a degree-6 Taylor polynomial
-// below 1/16 (truncation < 2e-9 relative), the exponential above.
+// below 1/16 (truncation < 2e-9 relative), the exponential above; both are
+// evaluated and selected so that lanes do not diverge.
 __device__ inline float one_minus_exp_neg(float x)
 {
-    if (x < 0.0625f) {
-        return x * (1.0f - x * (0.5f - x * (1.0f / 6.0f - x * (1.0f / 24.0f - x * (1.0f / 120.0f - x * (1.0f / 720.0f))))));
-    }
-    return 1.0f - expf(-x);
+    const float poly =
+        x * (1.0f - x * (0.5f - x * (1.0f / 6.0f - x * (1.0f / 24.0f - x * (1.0f / 120.0f - x * (1.0f / 720.0f))))));
+    const float big = 1.0f - __expf(-x);
+    return x < 0.0625f ? poly : big;
 }
 __device__ inline double one_minus_exp_neg(double x) { return -expm1(-x); }
 
 // ------------------------------------------------------------------ state
-// One photon package on a regular grid: integer cell, position inside the
-// cell in [0,1]^3 (kept cell-relative so that FP32 rounding does not grow
-// with the distance travelled), direction and its reciprocals, remaining
-// free path in scattering optical depth, weight and floor.
-//
-// On an octree grid (cx, cy, cz) are the root-grid coordinates of the
-// current leaf's root ancestor, c is the leaf and L its level (0 = root);
-// the position is then relative to the leaf, in units of its edge.
+// One photon package.  Regular grid: (cx, cy, cz) the cell, c its linear
+// index, position inside the cell in [0,1]^3 (kept cell-relative so that
+// FP32 rounding does not grow with the distance travelled).  Octree:
+// (cx, cy, cz) the root ancestor of the current leaf c at level L, the
+// position relative to the leaf in units of its edge.  t* is the exit
+// coordinate towards which each component of the direction points (1, 0,
+// or 2 with an infinite reciprocal when the component is zero), so the
+// distance to the exit face on each axis is (t - f) / u without branches.
+// n is the density of the current cell, loaded as soon as the cell is
+// known (before the deposit of the previous segment is issued).
 template <typename R>
 struct Pkg {
     int32_t cx, cy, cz;
     int32_t c, L;
     R fx, fy, fz;
     R ux, uy, uz;
-    R ix, iy, iz;   // 1/u (inf where u == 0)
-    R tau;
+    R ix, iy, iz;
+    R tx, ty, tz;
+    R tau, n;
     double W, Wfloor;
     uint32_t steps;
 };
@@ -130,10 +142,24 @@ struct Pkg {
 template <typename R>
 __device__ inline void set_inverse(Pkg<R> &p)
 {
-    p.ix = p.ux != (R)0 ? (R)1 / p.ux : m_inf<R>();
-    p.iy = p.uy != (R)0 ? (R)1 / p.uy : m_inf<R>();
-    p.iz = p.uz != (R)0 ? (R)1 / p.uz : m_inf<R>();
+    p.ix = p.ux != (R)0 ? m_rcp(p.ux) : m_inf<R>();
+    p.iy = p.uy != (R)0 ? m_rcp(p.uy) : m_inf<R>();
+    p.iz = p.uz != (R)0 ? m_rcp(p.uz) : m_inf<R>();
+    p.tx = p.ux > (R)0 ? (R)1 : (p.ux < (R)0 ? (R)0 : (R)2);
+    p.ty = p.uy > (R)0 ? (R)1 : (p.uy < (R)0 ? (R)0 : (R)2);
+    p.tz = p.uz > (R)0 ? (R)1 : (p.uz < (R)0 ? (R)0 : (R)2);
 }
+
+// Henyey-Greenstein constants of one frequency.
+template <typename R>
+struct HG {
+    R g, one_m_g, one_p_g, one_m_g2, one_p_g2, inv_2g;
+    __device__ explicit HG(R gg)
+        : g(gg), one_m_g((R)1 - gg), one_p_g((R)1 + gg), one_m_g2((R)1 - gg * gg), one_p_g2((R)1 + gg * gg),
+          inv_2g(m_abs(gg) < (R)1e-4 ? (R)0 : (R)1 / ((R)2 * gg))
+    {
+    }
+};
 
 // Henyey-Greenstein draw (analytic inversion of the cumulative
 // distribution; isotropic for |g| < 1e-4) and rotation of the direction
@@ -143,20 +169,20 @@ __device__ inline void set_inverse(Pkg<R> &p)
 // x and y components, so that FP32 keeps full relative accuracy near
 // forward/backward scattering and near the poles.
 template <typename R>
-__device__ inline void hg_scatter(R g, R xi_mu, R xi_phi, R &ux, R &uy, R &uz)
+__device__ inline void hg_scatter(const HG<R> &h, R xi_mu, R xi_phi, R &ux, R &uy, R &uz)
 {
     R mu, one_m, one_p;
-    if (m_abs(g) < (R)1e-4) {
+    if (m_abs(h.g) < (R)1e-4) {
         mu = (R)2 * xi_mu - (R)1;
         one_m = (R)2 * ((R)1 - xi_mu);
         one_p = (R)2 * xi_mu;
     } else {
-        const R den = (R)1 - g + (R)2 * g * xi_mu;
-        const R s = ((R)1 - g * g) / den;
-        mu = ((R)1 + g * g - s * s) / ((R)2 * g);
+        const R rden = m_rcp(h.one_m_g + (R)2 * h.g * xi_mu);
+        const R s = h.one_m_g2 * rden;
+        mu = (h.one_p_g2 - s * s) * h.inv_2g;
         // 1 - mu = (1-g)(1-xi)(s+1-g)/den,  1 + mu = (1+g) xi (1+g+s)/den
-        one_m = ((R)1 - g) * ((R)1 - xi_mu) * (s + (R)1 - g) / den;
-        one_p = ((R)1 + g) * xi_mu * ((R)1 + g + s) / den;
+        one_m = h.one_m_g * ((R)1 - xi_mu) * (s + h.one_m_g) * rden;
+        one_p = h.one_p_g * xi_mu * (h.one_p_g + s) * rden;
     }
     mu = m_min((R)1, m_max((R)-1, mu));
     const R st = m_sqrt(m_max((R)0, one_m * one_p));
@@ -169,15 +195,16 @@ __device__ inline void hg_scatter(R g, R xi_mu, R xi_phi, R &ux, R &uy, R &uz)
         n1 = st * sp;
         n2 = (uz >= (R)0 ? mu : -mu);
     } else {
-        const R t = m_sqrt(t2);
-        n0 = st * (ux * uz * cp - uy * sp) / t + ux * mu;
-        n1 = st * (uy * uz * cp + ux * sp) / t + uy * mu;
+        const R rt = m_rsqrt(t2);
+        const R t = t2 * rt;
+        n0 = st * (ux * uz * cp - uy * sp) * rt + ux * mu;
+        n1 = st * (uy * uz * cp + ux * sp) * rt + uy * mu;
         n2 = -st * cp * t + uz * mu;
     }
-    const R nn = m_sqrt(n0 * n0 + n1 * n1 + n2 * n2);
-    ux = n0 / nn;
-    uy = n1 / nn;
-    uz = n2 / nn;
+    const R rn = m_rsqrt(n0 * n0 + n1 * n1 + n2 * n2);
+    ux = n0 * rn;
+    uy = n1 * rn;
+    uz = n2 * rn;
 }
 
 template <typename R>
@@ -212,7 +239,8 @@ __device__ inline void split_coord(double p, int32_t n, int32_t &c, R &f)
 
 // ------------------------------------------------------------------ octree walk
 // Descend from cell p.c (position p.f in its units) to the leaf containing
-// the position: child octant o = [f >= 1/2] per axis, f -> 2 f - o.
+// the position: child octant o = [f >= 1/2] per axis, f -> 2 f - o.  The
+// leaf's word is its density.
 template <typename R>
 __device__ inline void descend(Pkg<R> &p, const McArgs &A)
 {
@@ -226,6 +254,7 @@ __device__ inline void descend(Pkg<R> &p, const McArgs &A)
         p.L += 1;
         w = (int32_t)A.words[p.c];
     }
+    p.n = (R)__int_as_float(w);
 }
 
 // Move across the face of axis `a` of the current leaf (fw: towards +):
@@ -330,6 +359,7 @@ __device__ inline bool emit(const McArgs &A, uint64_t gid, Pkg<R> &p, Rng &rng, 
             p.cy = cc; p.fy = fc; p.uy = uc;
             p.cz = ca; p.fz = fa; p.uz = ua;
         }
+        p.c = p.cx + A.nx * (p.cy + A.ny * p.cz);
     } else if (gid < A.n_bg + nps_tot) {
         const uint64_t k = gid - A.n_bg;
         const int32_t s = (int32_t)(k / A.n_ps_pk);
@@ -341,6 +371,7 @@ __device__ inline bool emit(const McArgs &A, uint64_t gid, Pkg<R> &p, Rng &rng, 
         split_coord<R>(A.ps[s].x, A.nx, p.cx, p.fx);
         split_coord<R>(A.ps[s].y, A.ny, p.cy, p.fy);
         split_coord<R>(A.ps[s].z, A.nz, p.cz, p.fz);
+        p.c = p.cx + A.nx * (p.cy + A.ny * p.cz);
         const R x0 = next_u<R>(rng, A), x1 = next_u<R>(rng, A);
         iso_dir<R>(x0, x1, p.ux, p.uy, p.uz);
     } else {
@@ -363,9 +394,9 @@ __device__ inline bool emit(const McArgs &A, uint64_t gid, Pkg<R> &p, Rng &rng, 
             int L = 0;
             while (L + 1 < A.nlevels && c >= A.level_offset[L + 1]) ++L;
             p.L = L;
-            p.c = (int32_t)c;
             for (int l = L; l > 0; --l) root = A.parent[(root - A.nroot) >> 3];
         }
+        p.c = (int32_t)c;
         p.cx = (int32_t)(root % A.nx);
         p.cy = (int32_t)((root / A.nx) % A.ny);
         p.cz = (int32_t)(root / ((int64_t)A.nx * A.ny));
@@ -375,10 +406,8 @@ __device__ inline bool emit(const McArgs &A, uint64_t gid, Pkg<R> &p, Rng &rng, 
         const R x3 = next_u<R>(rng, A), x4 = next_u<R>(rng, A);
         iso_dir<R>(x3, x4, p.ux, p.uy, p.uz);
     }
-    if (Oct && cls != kClassDust) {
-        p.c = p.cx + A.nx * (p.cy + A.ny * p.cz);
-        descend(p, A);
-    }
+    if (Oct && cls != kClassDust) descend(p, A);
+    else p.n = (R)__uint_as_float(A.words[p.c]);
     set_inverse(p);
     p.tau = -m_log(next_u<R>(rng, A));
     p.W = W0;
@@ -389,147 +418,96 @@ __device__ inline bool emit(const McArgs &A, uint64_t gid, Pkg<R> &p, Rng &rng, 
 
 // ------------------------------------------------------------------ transport
 struct StepOut {
-    int64_t cell;
+    int32_t cell;
+    int32_t event;
     double dep;     // energy deposited in `cell` by this segment (incl. floor/runaway remainder)
-    int event;
 };
 
-// One segment of the per-cell loop on a regular grid: distance to the exit
-// face against the distance to the next scattering, continuous absorption
-// W (1 - e^{-k_abs d}), then crossing (DDA, ties broken x < y < z),
-// scattering position, escape, weight floor or step cap.  The caller adds
-// `dep` to the absorbed array and draws the new direction after a
-// scattering.
-template <typename R>
-__device__ inline StepOut step_regular(Pkg<R> &p, const McArgs &A, R ks_scale, R ka_scale, R &d_out)
+// One segment of the per-cell loop (Sect. 2.1.1): distance to the exit
+// face (ties broken x < y < z) against the distance to the next
+// scattering, continuous absorption W (1 - e^{-k_abs d}) deposited in the
+// cell, then the crossing -- a DDA step on a regular grid, the partial
+// up/down traversal on an octree -- or the scattering position; escape,
+// weight floor and step cap end the package with the remainder deposited.
+// On an octree distances and optical depths are in units of the current
+// leaf (edge 2^-L root cells).  d_out is in root units.  The density of
+// the next cell is loaded here, before the caller issues the deposit, so
+// that waiting for it never waits for the atomic.  The caller adds `dep`
+// to the absorbed array and draws the new direction after a scattering.
+template <typename R, bool Oct>
+__device__ inline StepOut step(Pkg<R> &p, const McArgs &A, R ks_scale, R ka_scale, R &d_out)
 {
     StepOut o;
-    const int64_t c = (int64_t)p.cx + (int64_t)A.nx * ((int64_t)p.cy + (int64_t)A.ny * (int64_t)p.cz);
-    o.cell = c;
-    const R n = (R)__uint_as_float(A.words[c]);
-    const R ks = n * ks_scale, ka = n * ka_scale;
-    const R dx = p.ux != (R)0 ? ((p.ux > (R)0 ? (R)1 : (R)0) - p.fx) * p.ix : m_inf<R>();
-    const R dy = p.uy != (R)0 ? ((p.uy > (R)0 ? (R)1 : (R)0) - p.fy) * p.iy : m_inf<R>();
-    const R dz = p.uz != (R)0 ? ((p.uz > (R)0 ? (R)1 : (R)0) - p.fz) * p.iz : m_inf<R>();
+    o.cell = p.c;
+    R edge = (R)1;
+    if (Oct) edge = m_rcp((R)(1 << p.L));
+    const R ks = p.n * ks_scale * edge, ka = p.n * ka_scale * edge;
+    const R dx = (p.tx - p.fx) * p.ix;
+    const R dy = (p.ty - p.fy) * p.iy;
+    const R dz = (p.tz - p.fz) * p.iz;
     const int ax = (dx <= dy && dx <= dz) ? 0 : (dy <= dz ? 1 : 2);
     const R dexit = m_max((R)0, ax == 0 ? dx : (ax == 1 ? dy : dz));
     R d;
     int ev;
     const R tcell = ks * dexit;
     if (ks > (R)0 && tcell >= p.tau) {
-        d = m_min(p.tau / ks, dexit);
+        d = m_min(p.tau * m_rcp(ks), dexit);
         ev = kEvScatter;
     } else {
         d = dexit;
         p.tau -= tcell;
         ev = kEvCross;
     }
-    const R fr = one_minus_exp_neg(ka * d);
-    double dep = p.W * (double)fr;
-    p.W -= dep;
-    p.steps += 1;
     if (ev == kEvCross) {
+        bool fw;
         if (ax == 0) {
-            p.fy = m_min((R)1, m_max((R)0, p.fy + d * p.uy));
-            p.fz = m_min((R)1, m_max((R)0, p.fz + d * p.uz));
-            const bool fw = p.ux > (R)0;
-            p.fx = fw ? (R)0 : (R)1;
-            p.cx += fw ? 1 : -1;
-            if (p.cx < 0 || p.cx >= A.nx) ev = kEvEscape;
+            p.fy = m_clamp01(p.fy + d * p.uy);
+            p.fz = m_clamp01(p.fz + d * p.uz);
+            fw = p.ux > (R)0;
         } else if (ax == 1) {
-            p.fx = m_min((R)1, m_max((R)0, p.fx + d * p.ux));
-            p.fz = m_min((R)1, m_max((R)0, p.fz + d * p.uz));
-            const bool fw = p.uy > (R)0;
-            p.fy = fw ? (R)0 : (R)1;
-            p.cy += fw ? 1 : -1;
-            if (p.cy < 0 || p.cy >= A.ny) ev = kEvEscape;
+            p.fx = m_clamp01(p.fx + d * p.ux);
+            p.fz = m_clamp01(p.fz + d * p.uz);
+            fw = p.uy > (R)0;
         } else {
-            p.fx = m_min((R)1, m_max((R)0, p.fx + d * p.ux));
-            p.fy = m_min((R)1, m_max((R)0, p.fy + d * p.uy));
-            const bool fw = p.uz > (R)0;
-            p.fz = fw ? (R)0 : (R)1;
-            p.cz += fw ? 1 : -1;
-            if (p.cz < 0 || p.cz >= A.nz) ev = kEvEscape;
+            p.fx = m_clamp01(p.fx + d * p.ux);
+            p.fy = m_clamp01(p.fy + d * p.uy);
+            fw = p.uz > (R)0;
+        }
+        if (Oct) {
+            if (ax == 0) p.fx = fw ? (R)1 : (R)0;
+            else if (ax == 1) p.fy = fw ? (R)1 : (R)0;
+            else p.fz = fw ? (R)1 : (R)0;
+            if (!cross_octree(p, A, ax, fw)) ev = kEvEscape;
+        } else {
+            const int32_t step_i = fw ? 1 : -1;
+            if (ax == 0) {
+                p.fx = fw ? (R)0 : (R)1;
+                p.cx += step_i;
+                p.c += step_i;
+                if ((uint32_t)p.cx >= (uint32_t)A.nx) ev = kEvEscape;
+            } else if (ax == 1) {
+                p.fy = fw ? (R)0 : (R)1;
+                p.cy += step_i;
+                p.c += step_i * A.nx;
+                if ((uint32_t)p.cy >= (uint32_t)A.ny) ev = kEvEscape;
+            } else {
+                p.fz = fw ? (R)0 : (R)1;
+                p.cz += step_i;
+                p.c += step_i * A.nx * A.ny;
+                if ((uint32_t)p.cz >= (uint32_t)A.nz) ev = kEvEscape;
+            }
+            if (ev != kEvEscape) p.n = (R)__uint_as_float(A.words[p.c]);
         }
     } else {
-        p.fx = m_min((R)1, m_max((R)0, p.fx + d * p.ux));
-        p.fy = m_min((R)1, m_max((R)0, p.fy + d * p.uy));
-        p.fz = m_min((R)1, m_max((R)0, p.fz + d * p.uz));
-    }
-    if (ev != kEvEscape) {
-        if (p.W < p.Wfloor) {
-            dep += p.W;
-            p.W = 0.0;
-            ev = kEvFloor;
-        } else if ((int64_t)p.steps >= A.step_cap) {
-            dep += p.W;
-            p.W = 0.0;
-            ev = kEvRunaway;
-        }
-    }
-    o.dep = dep;
-    o.event = ev;
-    d_out = d;
-    return o;
-}
-
-// The same segment on an octree: distances and optical depths in units of
-// the current leaf (edge 2^-L root cells); a crossing moves to the
-// neighbouring leaf with cross_octree.  d_out is in root units.
-template <typename R>
-__device__ inline StepOut step_octree(Pkg<R> &p, const McArgs &A, R ks_scale, R ka_scale, R &d_out)
-{
-    StepOut o;
-    const int64_t c = p.c;
-    o.cell = c;
-    const R edge = (R)1 / (R)(1 << p.L);
-    const R n = (R)__uint_as_float(A.words[c]);
-    const R ks = n * ks_scale * edge, ka = n * ka_scale * edge;
-    const R dx = p.ux != (R)0 ? ((p.ux > (R)0 ? (R)1 : (R)0) - p.fx) * p.ix : m_inf<R>();
-    const R dy = p.uy != (R)0 ? ((p.uy > (R)0 ? (R)1 : (R)0) - p.fy) * p.iy : m_inf<R>();
-    const R dz = p.uz != (R)0 ? ((p.uz > (R)0 ? (R)1 : (R)0) - p.fz) * p.iz : m_inf<R>();
-    const int ax = (dx <= dy && dx <= dz) ? 0 : (dy <= dz ? 1 : 2);
-    const R dexit = m_max((R)0, ax == 0 ? dx : (ax == 1 ? dy : dz));
-    R d;
-    int ev;
-    const R tcell = ks * dexit;
-    if (ks > (R)0 && tcell >= p.tau) {
-        d = m_min(p.tau / ks, dexit);
-        ev = kEvScatter;
-    } else {
-        d = dexit;
-        p.tau -= tcell;
-        ev = kEvCross;
+        p.fx = m_clamp01(p.fx + d * p.ux);
+        p.fy = m_clamp01(p.fy + d * p.uy);
+        p.fz = m_clamp01(p.fz + d * p.uz);
     }
     const R fr = one_minus_exp_neg(ka * d);
     double dep = p.W * (double)fr;
     p.W -= dep;
     p.steps += 1;
     d_out = d * edge;
-    if (ev == kEvCross) {
-        bool fw;
-        if (ax == 0) {
-            p.fy = m_min((R)1, m_max((R)0, p.fy + d * p.uy));
-            p.fz = m_min((R)1, m_max((R)0, p.fz + d * p.uz));
-            fw = p.ux > (R)0;
-            p.fx = fw ? (R)1 : (R)0;
-        } else if (ax == 1) {
-            p.fx = m_min((R)1, m_max((R)0, p.fx + d * p.ux));
-            p.fz = m_min((R)1, m_max((R)0, p.fz + d * p.uz));
-            fw = p.uy > (R)0;
-            p.fy = fw ? (R)1 : (R)0;
-        } else {
-            p.fx = m_min((R)1, m_max((R)0, p.fx + d * p.ux));
-            p.fy = m_min((R)1, m_max((R)0, p.fy + d * p.uy));
-            fw = p.uz > (R)0;
-            p.fz = fw ? (R)1 : (R)0;
-        }
-        if (!cross_octree(p, A, ax, fw)) ev = kEvEscape;
-    } else {
-        p.fx = m_min((R)1, m_max((R)0, p.fx + d * p.ux));
-        p.fy = m_min((R)1, m_max((R)0, p.fy + d * p.uy));
-        p.fz = m_min((R)1, m_max((R)0, p.fz + d * p.uz));
-    }
     if (ev != kEvEscape) {
         if (p.W < p.Wfloor) {
             dep += p.W;
@@ -546,18 +524,11 @@ __device__ inline StepOut step_octree(Pkg<R> &p, const McArgs &A, R ks_scale, R 
     return o;
 }
 
-template <typename R, bool Oct>
-__device__ inline StepOut step(Pkg<R> &p, const McArgs &A, R ks_scale, R ka_scale, R &d_out)
-{
-    if (Oct) return step_octree<R>(p, A, ks_scale, ka_scale, d_out);
-    return step_regular<R>(p, A, ks_scale, ka_scale, d_out);
-}
-
 template <typename R>
-__device__ inline void scatter_new_direction(Pkg<R> &p, Rng &rng, const McArgs &A, R g)
+__device__ inline void scatter_new_direction(Pkg<R> &p, Rng &rng, const McArgs &A, const HG<R> &h)
 {
     const R xm = next_u<R>(rng, A), xp = next_u<R>(rng, A);
-    hg_scatter<R>(g, xm, xp, p.ux, p.uy, p.uz);
+    hg_scatter<R>(h, xm, xp, p.ux, p.uy, p.uz);
     set_inverse(p);
     p.tau = -m_log(next_u<R>(rng, A));
 }

@@ -21,6 +21,8 @@ constexpr int kEvFloor = 3;
 constexpr int kEvRunaway = 4;
 
 constexpr int kMaxPs = 32;
+constexpr int kDepSlots = 8;      // LDS deposit ring per lane of the MC kernel
+constexpr int kMcMaxBlock = 512;  // MC workgroup size limit (LDS ring: 48 KB at 512)
 constexpr int kMaxLevels = 16;
 
 struct PsArg {
@@ -64,7 +66,7 @@ struct McArgs {
     // persistent scheduling
     unsigned long long *next_id;
     DevStats *st_call, *st_total;
-    int32_t refill_min, inner_steps, chunk;
+    int32_t refill_min, inner_steps, chunk, scatter_min;
 };
 
 struct SegmentDev {
@@ -123,14 +125,20 @@ struct TempArgs {
     const double *absorbed;
     const float *T_old;
     float *T_new;
-    // statistics (NULL = not requested)
-    double *acc;                 // [0] count, [1] sum T, [2] sum rel, [3] n rel, [4] clamped
-    unsigned int *hist_n;        // kHistBins
-    double *hist_T;              // kHistBins
+    int32_t blocks;              // workgroups of the update and refine passes
+    // statistics (part == NULL: not requested)
+    double *part;                // blocks x 8 partial sums
+    unsigned int *hist_part;     // blocks x kHistBins coarse ln T histograms
+    unsigned int *hist_total;    // kHistBins
+    double *meta;                // 8 values, see temp_stats_reduce_kernel
+    unsigned int *fine_n;        // kHistBins fine bins inside the threshold bin
+    double *fine_T;
 };
-constexpr int kHistBins = 16384;
+constexpr int kHistBins = 4096;
+constexpr int kTempBlocks = 512;
 hipError_t launch_temp_update(const TempArgs &a, hipStream_t s);
-hipError_t launch_temp_finish(const TempArgs &a, double *out4, hipStream_t s);
+// Hottest-5% statistics after launch_temp_update (fine_n / fine_T zeroed).
+hipError_t launch_temp_stats(const TempArgs &a, double *out4, hipStream_t s);
 
 // map
 struct MapArgs {

@@ -51,13 +51,28 @@ __device__ inline int level_index(int64_t c, const int64_t *lo, int32_t nlevels)
 
 constexpr int kTempThreads = 256;
 
+__device__ inline int coarse_bin(double lnT, double lnTf, double scale)
+{
+    int b = (int)((lnT - lnTf) * scale);
+    return b < 0 ? 0 : (b >= kHistBins ? kHistBins - 1 : b);
+}
+
+// Temperature of every leaf.  With statistics requested, each workgroup
+// also writes its partial sums (count, sum T, sum |dT|/T_old, count with
+// T_old > 0, clamped) and its histogram of ln T over kHistBins coarse bins
+// (privatised in LDS) to its own row -- no global atomics, so the result
+// is deterministic.
 __global__ __launch_bounds__(kTempThreads) void temp_update_kernel(TempArgs a)
 {
     extern __shared__ double lds_lnG[];
+    __shared__ unsigned int sh_hist[kHistBins];
+    __shared__ double sh_red[kTempThreads / 64][5];
+    const bool want = a.part != nullptr;
     for (int j = threadIdx.x; j < a.nT; j += blockDim.x) lds_lnG[j] = a.lnG[j];
+    if (want)
+        for (int j = threadIdx.x; j < kHistBins; j += blockDim.x) sh_hist[j] = 0u;
     __syncthreads();
     const double G0 = lds_lnG[0], Gn = lds_lnG[a.nT - 1];
-    const bool want = a.acc != nullptr;
     double cnt = 0.0, sumT = 0.0, sumrel = 0.0, nrel = 0.0, ncl = 0.0;
     const double hist_scale = (double)kHistBins / ((a.nT - 1) * a.dlnT);
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.ncells; c += (int64_t)gridDim.x * blockDim.x) {
@@ -104,64 +119,158 @@ __global__ __launch_bounds__(kTempThreads) void temp_update_kernel(TempArgs a)
                         nrel += 1.0;
                     }
                 }
-                int b = (int)((log(Tf) - a.lnTf) * hist_scale);
-                b = b < 0 ? 0 : (b >= kHistBins ? kHistBins - 1 : b);
-                atomicAdd(&a.hist_n[b], 1u);
-                unsafeAtomicAdd(&a.hist_T[b], Tf);
+                atomicAdd(&sh_hist[coarse_bin(log(Tf), a.lnTf, hist_scale)], 1u);
             }
         }
         a.T_new[c] = Tout;
     }
-    if (want) {
-        // wave reduction, then one atomic per wave
-        for (int o = 32; o >= 1; o >>= 1) {
-            cnt += __shfl_xor(cnt, o, 64);
-            sumT += __shfl_xor(sumT, o, 64);
-            sumrel += __shfl_xor(sumrel, o, 64);
-            nrel += __shfl_xor(nrel, o, 64);
-            ncl += __shfl_xor(ncl, o, 64);
-        }
-        if ((threadIdx.x & 63) == 0 && cnt > 0.0) {
-            unsafeAtomicAdd(&a.acc[0], cnt);
-            unsafeAtomicAdd(&a.acc[1], sumT);
-            unsafeAtomicAdd(&a.acc[2], sumrel);
-            unsafeAtomicAdd(&a.acc[3], nrel);
-            unsafeAtomicAdd(&a.acc[4], ncl);
-        }
+    if (!want) return;
+    for (int o = 32; o >= 1; o >>= 1) {
+        cnt += __shfl_xor(cnt, o, 64);
+        sumT += __shfl_xor(sumT, o, 64);
+        sumrel += __shfl_xor(sumrel, o, 64);
+        nrel += __shfl_xor(nrel, o, 64);
+        ncl += __shfl_xor(ncl, o, 64);
     }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh_red[wv][0] = cnt;
+        sh_red[wv][1] = sumT;
+        sh_red[wv][2] = sumrel;
+        sh_red[wv][3] = nrel;
+        sh_red[wv][4] = ncl;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        double v = 0.0;
+        for (int k = 0; k < kTempThreads / 64; ++k) v += sh_red[k][threadIdx.x];
+        a.part[(int64_t)blockIdx.x * 8 + threadIdx.x] = v;
+    }
+    for (int j = threadIdx.x; j < kHistBins; j += blockDim.x) a.hist_part[(int64_t)blockIdx.x * kHistBins + j] = sh_hist[j];
 }
 
 hipError_t launch_temp_update(const TempArgs &a, hipStream_t s)
 {
-    int64_t blocks = (a.ncells + kTempThreads - 1) / kTempThreads;
-    if (blocks > 2048) blocks = 2048;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(temp_update_kernel, dim3((unsigned)blocks), dim3(kTempThreads), sizeof(double) * a.nT, s, a);
+    hipLaunchKernelGGL(temp_update_kernel, dim3((unsigned)a.blocks), dim3(kTempThreads), sizeof(double) * a.nT, s, a);
     return hipGetLastError();
 }
 
-// Hottest-5% mean from the histogram: chunks of bins from the top, a
-// workgroup scan of chunk counts, then the chunk holding the k-th hottest
-// cell resolves it bin by bin (the partial bin contributes its mean T).
+// Reduce the per-workgroup partial sums and histograms, then locate the
+// coarse bin holding the k-th hottest leaf (k = ceil(0.05 n)).
+// meta: [0] count [1] sum T [2] sum rel [3] n rel [4] clamped
+//       [5] threshold bin [6] cells still needed from that bin [7] k
 constexpr int kFinThreads = 1024;
 constexpr int kFinPer = kHistBins / kFinThreads;
 
-__global__ __launch_bounds__(kFinThreads) void temp_finish_kernel(TempArgs a, double *out)
+__global__ __launch_bounds__(kFinThreads) void temp_stats_reduce_kernel(TempArgs a)
+{
+    __shared__ double sh_n[kFinThreads];
+    __shared__ double sh_p[8];
+    const int t = threadIdx.x;
+    if (t < 5) {
+        double v = 0.0;
+        for (int b = 0; b < a.blocks; ++b) v += a.part[(int64_t)b * 8 + t];
+        sh_p[t] = v;
+    }
+    // chunk t covers bins [hi - per, hi), counted from the top
+    const int hi = kHistBins - t * kFinPer;
+    double loc[kFinPer];
+    double n = 0.0;
+    for (int q = 0; q < kFinPer; ++q) {
+        loc[q] = (double)a.hist_total[hi - 1 - q];
+        n += loc[q];
+    }
+    sh_n[t] = n;
+    __syncthreads();
+    for (int o = 1; o < kFinThreads; o <<= 1) {
+        const double add = t >= o ? sh_n[t - o] : 0.0;
+        __syncthreads();
+        sh_n[t] += add;
+        __syncthreads();
+    }
+    const double count = sh_p[0];
+    const double k = ceil(0.05 * count);
+    const double before = t > 0 ? sh_n[t - 1] : 0.0;
+    if (count > 0.0 && before < k && sh_n[t] >= k) {
+        double cn = before;
+        for (int q = 0; q < kFinPer; ++q) {
+            if (cn + loc[q] >= k) {
+                a.meta[5] = (double)(hi - 1 - q);
+                a.meta[6] = k - cn;
+                break;
+            }
+            cn += loc[q];
+        }
+    }
+    if (t < 5) a.meta[t] = sh_p[t];
+    if (t == 0) {
+        a.meta[7] = k;
+        if (!(count > 0.0)) {
+            a.meta[5] = (double)kHistBins;
+            a.meta[6] = 0.0;
+        }
+    }
+}
+
+// Second pass over the temperatures: exact sum of T above the threshold
+// bin (per-workgroup partials) and a fine histogram (counts and sums) of
+// the cells inside it, which are few.
+__global__ __launch_bounds__(kTempThreads) void temp_stats_refine_kernel(TempArgs a)
+{
+    __shared__ double sh[kTempThreads / 64];
+    const int tb = (int)a.meta[5];
+    const double hist_scale = (double)kHistBins / ((a.nT - 1) * a.dlnT);
+    const double lo_b = a.lnTf + (double)tb / hist_scale;
+    const double fine_scale = hist_scale * (double)kHistBins;
+    double above = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.ncells; c += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t w = a.words[c];
+        if ((int32_t)w < 0 || !(__uint_as_float(w) > 0.0f)) continue;
+        const double Tf = (double)a.T_new[c];
+        const double lt = log(Tf);
+        const int b = coarse_bin(lt, a.lnTf, hist_scale);
+        if (b > tb) {
+            above += Tf;
+        } else if (b == tb) {
+            int f = (int)((lt - lo_b) * fine_scale);
+            f = f < 0 ? 0 : (f >= kHistBins ? kHistBins - 1 : f);
+            atomicAdd(&a.fine_n[f], 1u);
+            unsafeAtomicAdd(&a.fine_T[f], Tf);
+        }
+    }
+    for (int o = 32; o >= 1; o >>= 1) above += __shfl_xor(above, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = above;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = 0.0;
+        for (int k = 0; k < kTempThreads / 64; ++k) v += sh[k];
+        a.part[(int64_t)blockIdx.x * 8 + 5] = v;
+    }
+}
+
+// Final statistics: mean T, hottest-5% mean (cells above the threshold bin
+// plus the hottest cells inside it, resolved on the fine histogram whose
+// bins are 2^-24 of the ln T range wide), mean relative change, clamps.
+__global__ __launch_bounds__(kFinThreads) void temp_stats_finish_kernel(TempArgs a, double *out)
 {
     __shared__ double sh_n[kFinThreads];
     __shared__ double sh_T[kFinThreads];
+    __shared__ double sh_above;
     const int t = threadIdx.x;
-    // chunk t covers bins [top - (t+1)*per, top - t*per)
+    if (t == 0) {
+        double v = 0.0;
+        for (int b = 0; b < a.blocks; ++b) v += a.part[(int64_t)b * 8 + 5];
+        sh_above = v;
+    }
     const int hi = kHistBins - t * kFinPer;
     double n = 0.0, sT = 0.0;
     for (int b = hi - 1; b >= hi - kFinPer; --b) {
-        n += (double)a.hist_n[b];
-        sT += a.hist_T[b];
+        n += (double)a.fine_n[b];
+        sT += a.fine_T[b];
     }
     sh_n[t] = n;
     sh_T[t] = sT;
     __syncthreads();
-    // inclusive scans from the top (Hillis-Steele)
     for (int o = 1; o < kFinThreads; o <<= 1) {
         const double an = t >= o ? sh_n[t - o] : 0.0;
         const double aT = t >= o ? sh_T[t - o] : 0.0;
@@ -170,34 +279,49 @@ __global__ __launch_bounds__(kFinThreads) void temp_finish_kernel(TempArgs a, do
         sh_T[t] += aT;
         __syncthreads();
     }
-    const double count = a.acc[0];
-    const double k = ceil(0.05 * count);
+    const double count = a.meta[0];
+    const double need = a.meta[6];
+    const double k = a.meta[7];
     const double before_n = t > 0 ? sh_n[t - 1] : 0.0;
     const double before_T = t > 0 ? sh_T[t - 1] : 0.0;
-    if (count > 0.0 && before_n < k && sh_n[t] >= k) {
+    if (count > 0.0 && need > 0.0 && before_n < need && sh_n[t] >= need) {
         double cn = before_n, cT = before_T;
         for (int b = hi - 1; b >= hi - kFinPer; --b) {
-            const double bn = (double)a.hist_n[b];
-            if (cn + bn >= k) {
-                cT += (k - cn) * (a.hist_T[b] / bn);
+            const double bn = (double)a.fine_n[b];
+            if (cn + bn >= need) {
+                cT += (need - cn) * (a.fine_T[b] / bn);
                 break;
             }
             cn += bn;
-            cT += a.hist_T[b];
+            cT += a.fine_T[b];
         }
-        out[1] = cT / k;
+        out[1] = (sh_above + cT) / k;
     }
     if (t == 0) {
-        out[0] = count > 0.0 ? a.acc[1] / count : 0.0;
-        out[2] = a.acc[3] > 0.0 ? a.acc[2] / a.acc[3] : __builtin_nan("");
-        out[3] = a.acc[4];
+        out[0] = count > 0.0 ? a.meta[1] / count : 0.0;
+        out[2] = a.meta[3] > 0.0 ? a.meta[2] / a.meta[3] : __builtin_nan("");
+        out[3] = a.meta[4];
         if (!(count > 0.0)) out[1] = 0.0;
+        else if (!(need > 0.0)) out[1] = sh_above / k;
     }
 }
 
-hipError_t launch_temp_finish(const TempArgs &a, double *out4, hipStream_t s)
+// Sum of the per-workgroup histograms, one bin per thread (coalesced).
+__global__ __launch_bounds__(256) void temp_hist_reduce_kernel(TempArgs a)
 {
-    hipLaunchKernelGGL(temp_finish_kernel, dim3(1), dim3(kFinThreads), 0, s, a, out4);
+    const int bin = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bin >= kHistBins) return;
+    unsigned int sum = 0;
+    for (int b = 0; b < a.blocks; ++b) sum += a.hist_part[(int64_t)b * kHistBins + bin];
+    a.hist_total[bin] = sum;
+}
+
+hipError_t launch_temp_stats(const TempArgs &a, double *out4, hipStream_t s)
+{
+    hipLaunchKernelGGL(temp_hist_reduce_kernel, dim3(kHistBins / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(temp_stats_reduce_kernel, dim3(1), dim3(kFinThreads), 0, s, a);
+    hipLaunchKernelGGL(temp_stats_refine_kernel, dim3((unsigned)a.blocks), dim3(kTempThreads), 0, s, a);
+    hipLaunchKernelGGL(temp_stats_finish_kernel, dim3(1), dim3(kFinThreads), 0, s, a, out4);
     return hipGetLastError();
 }
 

@@ -84,7 +84,9 @@ def test_octree_traces_fp64(soc, ctx, octo, cls_name):
 
 def test_octree_traces_fp32_structure(soc, ctx, octo):
     """FP32 production arithmetic on the octree: same cells and events for
-    >= 99% of packages, path lengths to 1e-6 (p99)."""
+    >= 99% of packages, path lengths to 5e-6 (p99; the ascent to a parent,
+    (f + o)/2 in FP32, rounds the leaf-relative position once per level
+    climbed, which the regular grid never does)."""
     G, f, T, src = octo
     g = soc.grid_from_workload(ctx, G)
     kw = dict(src, n_bg=4000, n_ps_pk=1000, seed=4)
@@ -95,7 +97,7 @@ def test_octree_traces_fp32_structure(soc, ctx, octo):
     same = np.array([r[0] for r in res])
     path = np.array([r[3] for r in res if r[0]])
     print(f"\noctree FP32 traces: {same.mean():.4f} same, path rel err p99 {np.quantile(path, 0.99):.2e}")
-    assert same.mean() >= 0.99 and np.quantile(path, 0.99) < 1e-6
+    assert same.mean() >= 0.99 and np.quantile(path, 0.99) < 5e-6
 
 
 def test_octree_refined_once_equals_doubled_regular_on_gpu(soc, ctx):

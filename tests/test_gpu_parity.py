@@ -237,10 +237,11 @@ def test_launch_configuration_independence(soc, ctx, cloud):
     kw = dict(I_bg=P.I_bg[k], ps_pos=P.ps_pos, ps_Lnu=P.ps_Lnu[:, k], n_bg=5000, n_ps_pk=3000, n_dust=7001,
               dust_mode=1, T=Td, iteration=1, freq_index=k)
     ref, sref = _gpu_run(soc, ctx, g, P.grid.ncells, f, 77, **kw)
-    saved = {n: ctx.get_option(n) for n in ("block", "blocks_per_cu", "refill_min", "inner_steps")}
+    saved = {n: ctx.get_option(n) for n in ("block", "blocks_per_cu", "refill_min", "inner_steps", "scatter_min")}
     try:
-        for cfg in ({"block": 64, "blocks_per_cu": 1}, {"block": 1024, "blocks_per_cu": 2},
-                    {"refill_min": 32, "inner_steps": 7}, {"refill_min": 64, "inner_steps": 64}):
+        for cfg in ({"block": 64, "blocks_per_cu": 1}, {"block": 512, "blocks_per_cu": 2},
+                    {"refill_min": 32, "inner_steps": 7}, {"refill_min": 64, "inner_steps": 8},
+                    {"scatter_min": 24}, {"scatter_min": 64, "inner_steps": 3}):
             for n_, v in cfg.items():
                 ctx.set_option(n_, v)
             A, st = _gpu_run(soc, ctx, g, P.grid.ncells, f, 77, **kw)
