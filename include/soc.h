@@ -217,6 +217,54 @@ soc_status soc_update_temperature(soc_ctx ctx, soc_grid grid, soc_temp_table tab
 soc_status soc_map(soc_ctx ctx, soc_grid grid, const soc_freq *freq, const float *d_T, int32_t axis,
                    float *d_image, int32_t npx, int32_t npy);
 
+/* ---------------------------------------------------------------- batches */
+/* Many independent Monte Carlo problems -- (cloud model, frequency) pairs
+ * over regular grids of any size -- simulated by one persistent launch that
+ * pulls tiles of package ids from a queue (the work of soc_simulate_frequency
+ * for each pair, background and point sources).  Pair i uses the Philox key
+ * (seed low word, seed high word XOR grids[pairs[i].grid] index), so its
+ * random numbers equal those of a single soc_simulate_frequency call with
+ * seed ^ ((uint64_t)grid << 32). */
+typedef struct {
+    int32_t grid;                  /* index into the grids given to soc_batch_create */
+    uint32_t freq_index;           /* Philox counter word of this frequency */
+    soc_freq freq;
+    double I_bg_nu;
+    uint64_t n_bg;
+    int32_t n_ps;                  /* <= 32 */
+    const soc_point_source *ps;    /* host, copied at creation */
+    uint64_t n_ps_pk;
+    double *d_absorbed;            /* device FP64 of the grid's ncells, accumulated (+=) */
+} soc_batch_pair;
+
+typedef struct soc_batch_s *soc_batch;
+/* Copies the pair table and the tile queue (tiles of at most tile_packages
+ * ids, ordered by decreasing estimated cost) to the device.  Synchronises. */
+soc_status soc_batch_create(soc_ctx ctx, int32_t n_grids, const soc_grid *grids, int32_t n_pairs,
+                            const soc_batch_pair *pairs, uint64_t seed, uint64_t tile_packages, soc_batch *out);
+void soc_batch_destroy(soc_batch b);
+soc_status soc_batch_info(soc_batch b, int32_t *n_tiles, uint64_t *n_packages);
+/* One persistent launch over every tile.  iteration: the Philox iteration
+ * word (bits 8..31 of counter word 3); SOC_ITER_ADVANCE instead adds one to
+ * the value the previous run used (so that a captured graph advances on
+ * every replay).  With stats non-NULL the call synchronises and returns
+ * the totals of this run; pass NULL inside a graph capture. */
+#define SOC_ITER_ADVANCE 0xFFFFFFFFu
+soc_status soc_batch_run(soc_batch b, uint32_t iteration, soc_sim_stats *stats);
+
+/* ---------------------------------------------------------------- graphs */
+/* Capture the library calls issued on the context's stream between
+ * soc_graph_begin and soc_graph_end into a HIP graph (stream capture,
+ * relaxed mode) and replay it with soc_graph_launch.  The stream must not
+ * be the null stream.  Calls that allocate or synchronise (statistics,
+ * traces, grid or table construction) return SOC_ESTATE while capturing;
+ * library scratch is reset with kernels, never memset nodes. */
+typedef struct soc_graph_s *soc_graph;
+soc_status soc_graph_begin(soc_ctx ctx);
+soc_status soc_graph_end(soc_ctx ctx, soc_graph *out);
+soc_status soc_graph_launch(soc_graph g);
+void soc_graph_destroy(soc_graph g);
+
 #ifdef __cplusplus
 }
 #endif

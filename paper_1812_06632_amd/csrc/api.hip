@@ -7,6 +7,7 @@
 // tables, trace buffers), grown on demand and freed with the context.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -47,6 +48,26 @@ struct soc_ctx_s {
     unsigned int *d_tfine_n = nullptr;
     double *d_tfine_T = nullptr;
     std::vector<hipEvent_t> ev_start, ev_stop;
+    bool capturing = false;
+};
+
+struct soc_batch_s {
+    soc_ctx ctx = nullptr;
+    int device = 0;
+    int32_t n_tiles = 0;
+    uint64_t n_packages = 0;
+    PairDev *d_pairs = nullptr;
+    TileDev *d_tiles = nullptr;
+    PsArg *d_ps = nullptr;
+    unsigned int *d_counter = nullptr;
+    uint32_t *d_iteration = nullptr;
+};
+
+struct soc_graph_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 struct soc_grid_s {
@@ -94,6 +115,7 @@ template <typename T>
 soc_status grow(soc_ctx c, T **p, int64_t &cap, int64_t need)
 {
     if (need <= cap && *p) return SOC_OK;
+    if (c->capturing) return fail(c, SOC_ESTATE, "scratch would grow during graph capture; run the call once before capturing");
     if (*p) {
         hipError_t e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return fail(c, SOC_EHIP, "sync before regrow: %s", hipGetErrorString(e));
@@ -110,6 +132,11 @@ soc_status grow(soc_ctx c, T **p, int64_t &cap, int64_t need)
 }
 
 bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+
+#define NOT_WHILE_CAPTURING(c)                                                                    \
+    do {                                                                                          \
+        if ((c)->capturing) return fail((c), SOC_ESTATE, "call not allowed during graph capture"); \
+    } while (0)
 
 soc_status check_freq(soc_ctx c, const soc_freq *f)
 {
@@ -359,6 +386,7 @@ soc_status soc_ctx_get_option(soc_ctx c, soc_option opt, int64_t *v)
 soc_status soc_ctx_mc_timing(soc_ctx c, double *total_ms, int64_t *launches, int32_t reset)
 {
     if (!c) return SOC_EINVAL;
+    NOT_WHILE_CAPTURING(c);
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     double tot = 0.0;
@@ -381,6 +409,7 @@ soc_status soc_ctx_mc_timing(soc_ctx c, double *total_ms, int64_t *launches, int
 soc_status soc_build_grid(soc_ctx c, const soc_grid_desc *d, soc_grid *out)
 {
     if (!c) return SOC_EINVAL;
+    NOT_WHILE_CAPTURING(c);
     if (!d || !out) return fail(c, SOC_EINVAL, "desc/out is NULL");
     *out = nullptr;
     if (d->nx <= 0 || d->ny <= 0 || d->nz <= 0) return fail(c, SOC_EINVAL, "grid dimensions must be > 0");
@@ -484,6 +513,7 @@ soc_status soc_simulate_frequency(soc_ctx c, soc_grid g, const soc_freq *f, cons
     if (!c) return SOC_EINVAL;
     if (!d_absorbed) return fail(c, SOC_EINVAL, "d_absorbed is NULL");
     HIPCHK(c, hipSetDevice(c->device));
+    if (c->capturing && (stats || c->timing)) return fail(c, SOC_ESTATE, "statistics/timing not allowed during graph capture");
     McArgs A;
     soc_status st = prepare(c, g, f, s, seed, iteration, freq_index, d_absorbed, A);
     if (st) return st;
@@ -514,6 +544,7 @@ soc_status soc_simulate_frequency(soc_ctx c, soc_grid g, const soc_freq *f, cons
 soc_status soc_read_stats(soc_ctx c, soc_sim_stats *out, int32_t reset)
 {
     if (!c || !out) return SOC_EINVAL;
+    NOT_WHILE_CAPTURING(c);
     HIPCHK(c, hipSetDevice(c->device));
     DevStats h;
     HIPCHK(c, hipMemcpyAsync(&h, c->d_stats + 1, sizeof h, hipMemcpyDeviceToHost, c->stream));
@@ -528,6 +559,7 @@ soc_status soc_trace_packages(soc_ctx c, soc_grid g, const soc_freq *f, const so
                               int32_t precision, soc_segment *out, int32_t max_seg, int32_t *n_seg)
 {
     if (!c) return SOC_EINVAL;
+    NOT_WHILE_CAPTURING(c);
     if (!ids || !out || !n_seg || n <= 0 || max_seg <= 0) return fail(c, SOC_EINVAL, "bad trace buffers");
     if (precision != 0 && precision != 1) return fail(c, SOC_EINVAL, "precision must be 0 or 1");
     HIPCHK(c, hipSetDevice(c->device));
@@ -575,6 +607,7 @@ soc_status soc_temp_table_build(soc_ctx c, int32_t K, const double *nu, const do
                                 double T_floor, double T_max, int32_t nT, soc_temp_table *out)
 {
     if (!c) return SOC_EINVAL;
+    NOT_WHILE_CAPTURING(c);
     if (!out || !nu || !w_nu || !sigma_abs || K < 1) return fail(c, SOC_EINVAL, "bad temperature table inputs");
     if (!(T_floor > 0.0 && T_max > T_floor && std::isfinite(T_max))) return fail(c, SOC_EINVAL, "need 0 < T_floor < T_max");
     if (nT < 16 || nT > 4096) return fail(c, SOC_EINVAL, "nT must be in [16,4096]");
@@ -633,6 +666,7 @@ soc_status soc_update_temperature(soc_ctx c, soc_grid g, soc_temp_table t, const
     if (!c) return SOC_EINVAL;
     if (!g || !t || !d_absorbed || !d_T_new) return fail(c, SOC_EINVAL, "NULL argument");
     if (g->ctx != c || t->ctx != c) return fail(c, SOC_EINVAL, "grid/table belong to another context");
+    if (c->capturing && stats) return fail(c, SOC_ESTATE, "statistics not allowed during graph capture");
     HIPCHK(c, hipSetDevice(c->device));
     TempArgs a;
     std::memset(&a, 0, sizeof a);
@@ -715,6 +749,231 @@ soc_status soc_map(soc_ctx c, soc_grid g, const soc_freq *f, const float *d_T, i
     m.image = d_image;
     HIPCHK(c, launch_map(m, c->stream));
     return SOC_OK;
+}
+
+soc_status soc_batch_create(soc_ctx c, int32_t n_grids, const soc_grid *grids, int32_t n_pairs,
+                            const soc_batch_pair *pairs, uint64_t seed, uint64_t tile_packages, soc_batch *out)
+{
+    if (!c) return SOC_EINVAL;
+    NOT_WHILE_CAPTURING(c);
+    if (!out || !grids || !pairs || n_grids <= 0 || n_pairs <= 0) return fail(c, SOC_EINVAL, "bad batch arguments");
+    if (tile_packages < 64 || tile_packages > 0x7FFFFFFFull) return fail(c, SOC_EINVAL, "tile_packages must be in [64, 2^31)");
+    *out = nullptr;
+    for (int32_t i = 0; i < n_grids; ++i) {
+        if (!grids[i] || grids[i]->ctx != c) return fail(c, SOC_EINVAL, "grid %d is NULL or belongs to another context", i);
+        if (grids[i]->nlevels != 1) return fail(c, SOC_EINVAL, "grid %d: batches take regular grids", i);
+    }
+    std::vector<PairDev> hp(n_pairs);
+    std::vector<PsArg> hps;
+    std::vector<int64_t> ps_off(n_pairs, 0);
+    struct TileCost { double cost; TileDev t; };
+    std::vector<TileCost> tiles;
+    uint64_t total = 0;
+    for (int32_t i = 0; i < n_pairs; ++i) {
+        const soc_batch_pair &q = pairs[i];
+        if (q.grid < 0 || q.grid >= n_grids) return fail(c, SOC_EINVAL, "pair %d: grid index out of range", i);
+        const soc_grid g = grids[q.grid];
+        soc_status st = check_freq(c, &q.freq);
+        if (st) return st;
+        if (!q.d_absorbed) return fail(c, SOC_EINVAL, "pair %d: d_absorbed is NULL", i);
+        if (!finite_nonneg(q.I_bg_nu)) return fail(c, SOC_EINVAL, "pair %d: bad I_bg_nu", i);
+        if (q.n_ps < 0 || q.n_ps > kMaxPs || (q.n_ps > 0 && !q.ps)) return fail(c, SOC_EINVAL, "pair %d: bad point sources", i);
+        if (q.n_bg > 0xFFFFFFFFull || q.n_ps_pk > 0xFFFFFFFFull) return fail(c, SOC_EINVAL, "pair %d: package count too large", i);
+        PairDev &P = hp[i];
+        std::memset(&P, 0, sizeof P);
+        P.words = g->d_words;
+        P.absorbed = q.d_absorbed;
+        P.nx = g->nx; P.ny = g->ny; P.nz = g->nz;
+        P.ncells = g->ncells;
+        const double s_cm = g->root_cell_cm;
+        P.ks_f = (float)(q.freq.sigma_sca * s_cm);
+        P.ka_f = (float)(q.freq.sigma_abs * s_cm);
+        P.g_f = (float)q.freq.g;
+        const double N0 = g->nx, N1 = g->ny, N2 = g->nz;
+        const double area[6] = {N1 * N2, N1 * N2, N0 * N2, N0 * N2, N0 * N1, N0 * N1};
+        double tot = 0.0, cum = 0.0;
+        for (int k = 0; k < 6; ++k) tot += area[k];
+        for (int k = 0; k < 6; ++k) { cum += area[k]; P.face_cum[k] = cum; }
+        P.face_tot = tot;
+        const double E_bg = M_PI * q.I_bg_nu * q.freq.w_nu * tot * (s_cm * s_cm);
+        P.n_bg = q.n_bg;
+        P.W_bg = q.n_bg ? E_bg / (double)q.n_bg : 0.0;
+        P.n_ps = q.n_ps;
+        P.n_ps_pk = q.n_ps > 0 ? q.n_ps_pk : 0;
+        ps_off[i] = (int64_t)hps.size();
+        for (int k = 0; k < q.n_ps; ++k) {
+            const soc_point_source &ps = q.ps[k];
+            if (!(ps.x >= 0.0 && ps.x < N0 && ps.y >= 0.0 && ps.y < N1 && ps.z >= 0.0 && ps.z < N2) || !finite_nonneg(ps.L_nu))
+                return fail(c, SOC_EINVAL, "pair %d: point source %d outside the box or bad L_nu", i, k);
+            PsArg a;
+            a.x = ps.x; a.y = ps.y; a.z = ps.z;
+            a.W = P.n_ps_pk ? ps.L_nu * q.freq.w_nu / (double)P.n_ps_pk : 0.0;
+            hps.push_back(a);
+        }
+        P.n_total = P.n_bg + (uint64_t)P.n_ps * P.n_ps_pk;
+        if (P.n_total > 0xFFFFFFFFull) return fail(c, SOC_EINVAL, "pair %d: more than 2^32 packages", i);
+        P.key0 = (uint32_t)seed;
+        P.key1 = (uint32_t)(seed >> 32) ^ (uint32_t)q.grid;
+        P.freq_index = q.freq_index;
+        // tiles, costed by packages x (optical size + grid extent)
+        const double extent = (double)(g->nx + g->ny + g->nz);
+        for (uint64_t b = 0; b < P.n_total; b += tile_packages) {
+            TileCost tc;
+            tc.t.pair = i;
+            tc.t.begin = (uint32_t)b;
+            tc.t.end = (uint32_t)std::min<uint64_t>(P.n_total, b + tile_packages);
+            tc.t.pad = 0;
+            tc.cost = (double)(tc.t.end - tc.t.begin) * extent;
+            tiles.push_back(tc);
+        }
+        total += P.n_total;
+    }
+    std::stable_sort(tiles.begin(), tiles.end(), [](const TileCost &a, const TileCost &b) { return a.cost > b.cost; });
+    HIPCHK(c, hipSetDevice(c->device));
+    soc_batch b = new (std::nothrow) soc_batch_s;
+    if (!b) return fail(c, SOC_ENOMEM, "host allocation");
+    b->ctx = c;
+    b->device = c->device;
+    b->n_tiles = (int32_t)tiles.size();
+    b->n_packages = total;
+    auto cleanup = [&](soc_status r) {
+        if (r != SOC_OK) soc_batch_destroy(b);
+        return r;
+    };
+    if (hipMalloc((void **)&b->d_pairs, sizeof(PairDev) * n_pairs) != hipSuccess ||
+        hipMalloc((void **)&b->d_tiles, sizeof(TileDev) * std::max<size_t>(1, tiles.size())) != hipSuccess ||
+        hipMalloc((void **)&b->d_ps, sizeof(PsArg) * std::max<size_t>(1, hps.size())) != hipSuccess ||
+        hipMalloc((void **)&b->d_counter, sizeof(unsigned int)) != hipSuccess ||
+        hipMalloc((void **)&b->d_iteration, sizeof(uint32_t)) != hipSuccess)
+        return cleanup(fail(c, SOC_ENOMEM, "batch tables"));
+    for (int32_t i = 0; i < n_pairs; ++i) hp[i].ps = hp[i].n_ps ? b->d_ps + ps_off[i] : nullptr;
+    std::vector<TileDev> ht(tiles.size());
+    for (size_t i = 0; i < tiles.size(); ++i) ht[i] = tiles[i].t;
+    if (hipMemcpy(b->d_pairs, hp.data(), sizeof(PairDev) * n_pairs, hipMemcpyHostToDevice) != hipSuccess ||
+        (ht.size() && hipMemcpy(b->d_tiles, ht.data(), sizeof(TileDev) * ht.size(), hipMemcpyHostToDevice) != hipSuccess) ||
+        (hps.size() && hipMemcpy(b->d_ps, hps.data(), sizeof(PsArg) * hps.size(), hipMemcpyHostToDevice) != hipSuccess))
+        return cleanup(fail(c, SOC_EHIP, "batch upload"));
+    if (launch_advance_iteration(b->d_iteration, 0, 0u, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return cleanup(fail(c, SOC_EHIP, "batch init"));
+    *out = b;
+    return SOC_OK;
+}
+
+void soc_batch_destroy(soc_batch b)
+{
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    (void)hipFree(b->d_pairs);
+    (void)hipFree(b->d_tiles);
+    (void)hipFree(b->d_ps);
+    (void)hipFree(b->d_counter);
+    (void)hipFree(b->d_iteration);
+    delete b;
+}
+
+soc_status soc_batch_info(soc_batch b, int32_t *n_tiles, uint64_t *n_packages)
+{
+    if (!b) return SOC_EINVAL;
+    if (n_tiles) *n_tiles = b->n_tiles;
+    if (n_packages) *n_packages = b->n_packages;
+    return SOC_OK;
+}
+
+soc_status soc_batch_run(soc_batch b, uint32_t iteration, soc_sim_stats *stats)
+{
+    if (!b) return SOC_EINVAL;
+    soc_ctx c = b->ctx;
+    if (c->capturing && (stats || c->timing)) return fail(c, SOC_ESTATE, "statistics/timing not allowed during graph capture");
+    if (iteration != SOC_ITER_ADVANCE && iteration > 0xFFFFFFu) return fail(c, SOC_EINVAL, "iteration must be < 2^24");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_fill_u64((unsigned long long *)c->d_stats, 0ull, (int64_t)(sizeof(DevStats) / 8), c->stream));
+    HIPCHK(c, launch_fill_i32((int32_t *)b->d_counter, 0, 1, c->stream));
+    HIPCHK(c, launch_advance_iteration(b->d_iteration, iteration == SOC_ITER_ADVANCE ? 1 : 0,
+                                       iteration == SOC_ITER_ADVANCE ? 0u : iteration, c->stream));
+    BatchArgs a;
+    a.pairs = b->d_pairs;
+    a.tiles = b->d_tiles;
+    a.n_tiles = b->n_tiles;
+    a.next_tile = b->d_counter;
+    a.iteration = b->d_iteration;
+    a.step_cap = c->step_cap;
+    a.st_call = c->d_stats;
+    a.st_total = c->d_stats + 1;
+    a.refill_min = (int32_t)c->refill_min;
+    a.inner_steps = (int32_t)c->inner_steps;
+    a.scatter_min = (int32_t)c->scatter_min;
+    const int blocks = (int)(c->num_cus * c->blocks_per_cu);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        HIPCHK(c, hipEventCreate(&e0));
+        HIPCHK(c, hipEventCreate(&e1));
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+    }
+    HIPCHK(c, launch_mc_batch(a, blocks, (int)c->block, c->stream));
+    if (c->timing) {
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        c->ev_start.push_back(e0);
+        c->ev_stop.push_back(e1);
+    }
+    if (stats) {
+        DevStats h;
+        HIPCHK(c, hipMemcpyAsync(&h, c->d_stats, sizeof h, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        to_public(h, stats);
+    }
+    return SOC_OK;
+}
+
+soc_status soc_graph_begin(soc_ctx c)
+{
+    if (!c) return SOC_EINVAL;
+    NOT_WHILE_CAPTURING(c);
+    if (!c->stream) return fail(c, SOC_ESTATE, "graph capture needs a stream other than the null stream");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+    c->capturing = true;
+    return SOC_OK;
+}
+
+soc_status soc_graph_end(soc_ctx c, soc_graph *out)
+{
+    if (!c || !out) return SOC_EINVAL;
+    if (!c->capturing) return fail(c, SOC_ESTATE, "no capture in progress");
+    c->capturing = false;
+    hipGraph_t graph = nullptr;
+    HIPCHK(c, hipStreamEndCapture(c->stream, &graph));
+    soc_graph g = new (std::nothrow) soc_graph_s;
+    if (!g) {
+        (void)hipGraphDestroy(graph);
+        return fail(c, SOC_ENOMEM, "host allocation");
+    }
+    g->device = c->device;
+    g->stream = c->stream;
+    g->graph = graph;
+    hipError_t e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        soc_graph_destroy(g);
+        return fail(c, SOC_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    *out = g;
+    return SOC_OK;
+}
+
+soc_status soc_graph_launch(soc_graph g)
+{
+    if (!g) return SOC_EINVAL;
+    if (hipSetDevice(g->device) != hipSuccess) return SOC_EHIP;
+    return hipGraphLaunch(g->exec, g->stream) == hipSuccess ? SOC_OK : SOC_EHIP;
+}
+
+void soc_graph_destroy(soc_graph g)
+{
+    if (!g) return;
+    (void)hipSetDevice(g->device);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
 }
 
 }  // extern "C"

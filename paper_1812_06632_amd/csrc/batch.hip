@@ -1,0 +1,191 @@
+// batch.hip -- many independent Monte Carlo problems in one persistent
+// launch: every (cloud model, frequency) pair is cut into tiles of package
+// ids, and waves pull tiles from one queue.  A wave works on one tile at a
+// time: its lanes are refilled from the tile's id range (wave ballot and
+// lane rank, as in the single-problem kernel), and once the range is used
+// up and every lane has finished, the wave flushes its LDS deposit ring
+// into that model's absorbed array and takes the next tile.  Pair
+// parameters are read as wave-uniform (scalar) data at each tile switch.
+#include "soc_device.h"
+
+namespace soc {
+
+__device__ inline unsigned long long wsum_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += (unsigned long long)__shfl_xor((long long)v, o, 64);
+    return v;
+}
+__device__ inline double wsum_f64(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline void batch_add_stats(DevStats *t, unsigned long long pk, unsigned long long st,
+                                       unsigned long long sc, unsigned long long ru, double em, double ab, double es)
+{
+    atomicAdd(&t->packages, pk);
+    atomicAdd(&t->steps, st);
+    atomicAdd(&t->scatterings, sc);
+    atomicAdd(&t->runaways, ru);
+    unsafeAtomicAdd(&t->emitted, em);
+    unsafeAtomicAdd(&t->absorbed, ab);
+    unsafeAtomicAdd(&t->escaped, es);
+}
+
+__global__ __launch_bounds__(kMcMaxBlock) void mc_batch_kernel(BatchArgs B)
+{
+    extern __shared__ double lds_dep[];
+    int32_t *lds_cell = (int32_t *)(lds_dep + kDepSlots * blockDim.x);
+    const int tid = threadIdx.x;
+    const int bd = blockDim.x;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t iteration = __builtin_amdgcn_readfirstlane(*B.iteration);
+
+    BatchView A;
+    A.parent = nullptr;
+    A.nlevels = 1;
+    A.nroot = 0;
+    A.level_offset = nullptr;
+    A.n_dust = 0;
+    A.dust_mode = 1;
+    A.dust_L = nullptr;
+    A.dust_incl = nullptr;
+    A.dust_cell = nullptr;
+    A.leaves = nullptr;
+    A.per_leaf = 1;
+    A.iteration = iteration;
+    A.step_cap = B.step_cap;
+    double *absorbed = nullptr;
+    float ks = 0.0f, ka = 0.0f, gg = 0.0f;
+
+    Pkg<float> p;
+    Rng rng;
+    bool active = false, pend = false;
+    unsigned long long pool_next = 0, pool_end = 0;   // wave-uniform: the current tile's remaining ids
+    int nbuf = 0, since_flush = 0;
+    unsigned long long n_pk = 0, n_st = 0, n_sc = 0, n_ru = 0;
+    double e_em = 0.0, e_ab = 0.0, e_es = 0.0;
+
+    for (;;) {
+        if (pool_next >= pool_end && !__any(active)) {
+            // tile finished: flush its deposits, take the next tile
+            for (int j = 0; j < kDepSlots; ++j)
+                if (j < nbuf) unsafeAtomicAdd(&absorbed[lds_cell[j * bd + tid]], lds_dep[j * bd + tid]);
+            nbuf = 0;
+            since_flush = 0;
+            unsigned int t = 0;
+            if (lane == 0) t = atomicAdd(B.next_tile, 1u);
+            t = __builtin_amdgcn_readfirstlane(__shfl((int)t, 0, 64));
+            if ((int32_t)t >= B.n_tiles) break;
+            const TileDev tile = B.tiles[t];
+            const int32_t pi = __builtin_amdgcn_readfirstlane(tile.pair);
+            const PairDev &P = B.pairs[pi];
+            A.words = P.words;
+            A.nx = P.nx; A.ny = P.ny; A.nz = P.nz;
+            A.ncells = P.ncells;
+            A.n_bg = P.n_bg; A.n_ps_pk = P.n_ps_pk; A.n_total = P.n_total; A.n_ps = P.n_ps;
+            A.W_bg = P.W_bg;
+            for (int k = 0; k < 6; ++k) A.face_cum[k] = P.face_cum[k];
+            A.face_tot = P.face_tot;
+            A.ps = P.ps;
+            A.key0 = P.key0; A.key1 = P.key1; A.freq_index = P.freq_index;
+            absorbed = P.absorbed;
+            ks = P.ks_f; ka = P.ka_f; gg = P.g_f;
+            pool_next = __builtin_amdgcn_readfirstlane(tile.begin);
+            pool_end = __builtin_amdgcn_readfirstlane(tile.end);
+            continue;
+        }
+        const unsigned long long idle = __ballot(!active);
+        const int nidle = __popcll(idle);
+        if (pool_next < pool_end && nidle > 0 && (nidle >= B.refill_min || nidle == 64)) {
+            if (!active) {
+                const unsigned long long id = pool_next + (unsigned long long)__popcll(idle & below);
+                if (id < pool_end) {
+                    uint32_t cls, pid;
+                    double W0;
+                    const bool ok = emit<float, false>(A, id, p, rng, cls, pid, W0);
+                    n_pk += 1;
+                    if (ok) e_em += W0;
+                    active = ok;
+                }
+            }
+            pool_next += (unsigned long long)nidle;
+            if (pool_next > pool_end) pool_next = pool_end;
+        }
+        if (!__any(active)) continue;
+        const HG<float> hg(gg);
+        const unsigned long long pm = __ballot(pend);
+        if (pm) {
+            if (__popcll(pm) >= B.scatter_min || __ballot(active && !pend) == 0) {
+                if (pend) {
+                    scatter_new_direction<float>(p, rng, A, hg);
+                    pend = false;
+                }
+            }
+        }
+        if ((since_flush + 1) * B.inner_steps > kDepSlots) {
+            for (int j = 0; j < kDepSlots; ++j)
+                if (j < nbuf) unsafeAtomicAdd(&absorbed[lds_cell[j * bd + tid]], lds_dep[j * bd + tid]);
+            nbuf = 0;
+            since_flush = 0;
+        }
+        ++since_flush;
+        for (int s = 0; s < B.inner_steps; ++s) {
+            if (active && !pend) {
+                float d;
+                const StepOut o = step<float, false>(p, A, ks, ka, d);
+                n_st += 1;
+                if (o.dep > 0.0) {
+                    lds_dep[nbuf * bd + tid] = o.dep;
+                    lds_cell[nbuf * bd + tid] = o.cell;
+                    ++nbuf;
+                    e_ab += o.dep;
+                }
+                if (o.event == kEvScatter) {
+                    pend = true;
+                    n_sc += 1;
+                } else if (o.event != kEvCross) {
+                    active = false;
+                    if (o.event == kEvEscape) e_es += p.W;
+                    if (o.event == kEvRunaway) n_ru += 1;
+                }
+            }
+        }
+    }
+    n_pk = wsum_u64(n_pk);
+    n_st = wsum_u64(n_st);
+    n_sc = wsum_u64(n_sc);
+    n_ru = wsum_u64(n_ru);
+    e_em = wsum_f64(e_em);
+    e_ab = wsum_f64(e_ab);
+    e_es = wsum_f64(e_es);
+    if (lane == 0) {
+        batch_add_stats(B.st_call, n_pk, n_st, n_sc, n_ru, e_em, e_ab, e_es);
+        batch_add_stats(B.st_total, n_pk, n_st, n_sc, n_ru, e_em, e_ab, e_es);
+    }
+}
+
+hipError_t launch_mc_batch(const BatchArgs &a, int blocks, int threads, hipStream_t s)
+{
+    const size_t lds = (size_t)kDepSlots * threads * (sizeof(double) + sizeof(int32_t));
+    hipLaunchKernelGGL(mc_batch_kernel, dim3(blocks), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+// mode 0: set the iteration word to value; mode 1: advance it by one
+__global__ void advance_iteration_kernel(uint32_t *it, int32_t mode, uint32_t value)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *it = mode ? *it + 1u : value;
+}
+
+hipError_t launch_advance_iteration(uint32_t *it, int32_t mode, uint32_t value, hipStream_t s)
+{
+    hipLaunchKernelGGL(advance_iteration_kernel, dim3(1), dim3(64), 0, s, it, mode, value);
+    return hipGetLastError();
+}
+
+}  // namespace soc

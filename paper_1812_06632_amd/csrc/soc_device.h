@@ -219,8 +219,8 @@ __device__ inline void iso_dir(R xi_mu, R xi_phi, R &ux, R &uy, R &uz)
     uz = mu;
 }
 
-template <typename R>
-__device__ inline R next_u(Rng &rng, const McArgs &A)
+template <typename R, typename AT>
+__device__ inline R next_u(Rng &rng, const AT &A)
 {
     return u01<R>(rng.word(A.key0, A.key1, A.freq_index));
 }
@@ -241,8 +241,8 @@ __device__ inline void split_coord(double p, int32_t n, int32_t &c, R &f)
 // Descend from cell p.c (position p.f in its units) to the leaf containing
 // the position: child octant o = [f >= 1/2] per axis, f -> 2 f - o.  The
 // leaf's word is its density.
-template <typename R>
-__device__ inline void descend(Pkg<R> &p, const McArgs &A)
+template <typename R, typename AT>
+__device__ inline void descend(Pkg<R> &p, const AT &A)
 {
     int32_t w = (int32_t)A.words[p.c];
     while (w < 0) {
@@ -265,8 +265,8 @@ __device__ inline void descend(Pkg<R> &p, const McArgs &A)
 // when the package leaves the box.  Octets are 8-aligned relative to every
 // level offset, all of which are congruent to nroot mod 8, so the octant of
 // a non-root cell is (c - nroot) & 7.
-template <typename R>
-__device__ inline bool cross_octree(Pkg<R> &p, const McArgs &A, int a, bool fw)
+template <typename R, typename AT>
+__device__ inline bool cross_octree(Pkg<R> &p, const AT &A, int a, bool fw)
 {
     for (;;) {
         if (p.L == 0) {
@@ -310,8 +310,8 @@ __device__ inline bool cross_octree(Pkg<R> &p, const McArgs &A, int a, bool fw)
 // draw its first free path.  Returns false for a package that carries no
 // energy (it is counted but not traced).  `cls`/`pid` receive the class
 // and the id within the class; W0 the package energy.
-template <typename R, bool Oct>
-__device__ inline bool emit(const McArgs &A, uint64_t gid, Pkg<R> &p, Rng &rng, uint32_t &cls,
+template <typename R, bool Oct, typename AT>
+__device__ inline bool emit(const AT &A, uint64_t gid, Pkg<R> &p, Rng &rng, uint32_t &cls,
                             uint32_t &pid, double &W0)
 {
     p.L = 0;
@@ -434,8 +434,8 @@ struct StepOut {
 // the next cell is loaded here, before the caller issues the deposit, so
 // that waiting for it never waits for the atomic.  The caller adds `dep`
 // to the absorbed array and draws the new direction after a scattering.
-template <typename R, bool Oct>
-__device__ inline StepOut step(Pkg<R> &p, const McArgs &A, R ks_scale, R ka_scale, R &d_out)
+template <typename R, bool Oct, typename AT>
+__device__ inline StepOut step(Pkg<R> &p, const AT &A, R ks_scale, R ka_scale, R &d_out)
 {
     StepOut o;
     o.cell = p.c;
@@ -524,8 +524,8 @@ __device__ inline StepOut step(Pkg<R> &p, const McArgs &A, R ks_scale, R ka_scal
     return o;
 }
 
-template <typename R>
-__device__ inline void scatter_new_direction(Pkg<R> &p, Rng &rng, const McArgs &A, const HG<R> &h)
+template <typename R, typename AT>
+__device__ inline void scatter_new_direction(Pkg<R> &p, Rng &rng, const AT &A, const HG<R> &h)
 {
     const R xm = next_u<R>(rng, A), xp = next_u<R>(rng, A);
     hg_scatter<R>(h, xm, xp, p.ux, p.uy, p.uz);

@@ -140,6 +140,64 @@ hipError_t launch_temp_update(const TempArgs &a, hipStream_t s);
 // Hottest-5% statistics after launch_temp_update (fine_n / fine_T zeroed).
 hipError_t launch_temp_stats(const TempArgs &a, double *out4, hipStream_t s);
 
+// ---- batched launch: many (model, frequency) pairs in one persistent launch
+// One (model, frequency) pair: the grid, its absorbed array and the
+// background / point sources of that frequency, as McArgs would hold them.
+struct PairDev {
+    const uint32_t *words;
+    double *absorbed;
+    const PsArg *ps;          // n_ps entries, device
+    int32_t nx, ny, nz, n_ps;
+    int64_t ncells;
+    float ks_f, ka_f, g_f, pad;
+    double W_bg, face_tot;
+    double face_cum[6];
+    uint64_t n_bg, n_ps_pk, n_total;
+    uint32_t key0, key1, freq_index, pad2;
+};
+
+struct TileDev {
+    int32_t pair;
+    uint32_t begin, end;      // package ids [begin, end) of the pair
+    int32_t pad;
+};
+
+struct BatchArgs {
+    const PairDev *pairs;
+    const TileDev *tiles;
+    int32_t n_tiles;
+    unsigned int *next_tile;
+    const uint32_t *iteration;   // device word, read at launch
+    int64_t step_cap;
+    DevStats *st_call, *st_total;
+    int32_t refill_min, inner_steps, scatter_min;
+};
+
+// The lean per-pair view the emission and step code read in the batched
+// kernel (regular grids, background and point sources).
+struct BatchView {
+    const uint32_t *words;
+    const int32_t *parent;
+    int32_t nx, ny, nz, nlevels;
+    int64_t ncells, nroot;
+    const int64_t *level_offset;
+    uint64_t n_bg, n_ps_pk, n_dust, n_total;
+    int32_t n_ps, dust_mode;
+    double W_bg;
+    double face_cum[6];
+    double face_tot;
+    const PsArg *ps;
+    const double *dust_L, *dust_incl;
+    const int32_t *dust_cell;
+    const int64_t *leaves;
+    uint64_t per_leaf;
+    uint32_t key0, key1, freq_index, iteration;
+    int64_t step_cap;
+};
+
+hipError_t launch_mc_batch(const BatchArgs &a, int blocks, int threads, hipStream_t s);
+hipError_t launch_advance_iteration(uint32_t *it, int32_t mode, uint32_t value, hipStream_t s);
+
 // map
 struct MapArgs {
     const uint32_t *words;

@@ -315,3 +315,104 @@ def map_image(ctx: Context, grid: Grid, freq, T: torch.Tensor, axis: int, image:
     ctx.check(_lib.soc_map(ctx.h, grid.h, C.byref(f), _dev_ptr(T, torch.float32, "T"), int(axis),
                            _dev_ptr(image, torch.float32, "image"), npx, npy))
     return image
+
+
+# ---------------------------------------------------------------- batches
+class _BatchPair(C.Structure):
+    _fields_ = [("grid", C.c_int32), ("freq_index", C.c_uint32), ("freq", _Freq), ("I_bg_nu", C.c_double),
+                ("n_bg", C.c_uint64), ("n_ps", C.c_int32), ("ps", C.POINTER(_PointSource)), ("n_ps_pk", C.c_uint64),
+                ("d_absorbed", C.c_void_p)]
+
+
+ITER_ADVANCE = 0xFFFFFFFF
+
+_lib.soc_batch_create.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.c_int32, C.POINTER(_BatchPair),
+                                  C.c_uint64, C.c_uint64, C.POINTER(C.c_void_p)]
+_lib.soc_batch_destroy.argtypes = [C.c_void_p]
+_lib.soc_batch_info.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_uint64)]
+_lib.soc_batch_run.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(_SimStats)]
+_lib.soc_graph_begin.argtypes = [C.c_void_p]
+_lib.soc_graph_end.argtypes = [C.c_void_p, C.POINTER(C.c_void_p)]
+_lib.soc_graph_launch.argtypes = [C.c_void_p]
+_lib.soc_graph_destroy.argtypes = [C.c_void_p]
+
+
+class Batch:
+    """soc_batch: (grid, frequency) pairs simulated by one persistent launch."""
+
+    def __init__(self, ctx: Context, grids, pairs, seed=1, tile_packages=16384):
+        """pairs: list of dicts with keys grid (index), freq (5-tuple),
+        freq_index, absorbed (float64 CUDA tensor of that grid's ncells),
+        I_bg, n_bg, and optionally ps_pos, ps_Lnu, n_ps_pk."""
+        self.ctx, self.grids = ctx, list(grids)
+        self._keep = []
+        arr = (_BatchPair * len(pairs))()
+        for i, q in enumerate(pairs):
+            pos = np.asarray(q.get("ps_pos", np.zeros((0, 3))), dtype=np.float64).reshape(-1, 3)
+            L = np.asarray(q.get("ps_Lnu", np.zeros(0)), dtype=np.float64).reshape(-1)
+            ps = (_PointSource * max(len(pos), 1))(*[_PointSource(*pos[k], L[k]) for k in range(len(pos))])
+            self._keep.append((ps, q["absorbed"]))
+            arr[i] = _BatchPair(int(q["grid"]), int(q.get("freq_index", 0)), _freq(q["freq"]), float(q.get("I_bg", 0.0)),
+                                int(q.get("n_bg", 0)), len(pos), C.cast(ps, C.POINTER(_PointSource)) if len(pos) else None,
+                                int(q.get("n_ps_pk", 0)), _dev_ptr(q["absorbed"], torch.float64, "absorbed"))
+        gh = (C.c_void_p * len(self.grids))(*[g.h.value if isinstance(g.h, C.c_void_p) else g.h for g in self.grids])
+        h = C.c_void_p()
+        ctx.check(_lib.soc_batch_create(ctx.h, len(self.grids), gh, len(pairs), arr, C.c_uint64(seed),
+                                        C.c_uint64(tile_packages), C.byref(h)))
+        self.h = h
+        ctx._children.add(self)
+
+    def info(self):
+        nt, npk = C.c_int32(), C.c_uint64()
+        self.ctx.check(_lib.soc_batch_info(self.h, C.byref(nt), C.byref(npk)))
+        return nt.value, npk.value
+
+    def run(self, iteration=0, stats=False):
+        st = _SimStats() if stats else None
+        self.ctx.check(_lib.soc_batch_run(self.h, C.c_uint32(iteration), C.byref(st) if st is not None else None))
+        return None if st is None else {k: getattr(st, k) for k, _ in _SimStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.soc_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A captured sequence of library calls (soc_graph_begin/end)."""
+
+    def __init__(self, ctx: Context, h):
+        self.ctx, self.h = ctx, h
+        ctx._children.add(self)
+
+    def launch(self):
+        rc = _lib.soc_graph_launch(self.h)
+        if rc != OK:
+            raise SocError(rc, "soc_graph_launch failed")
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.soc_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def graph_begin(ctx: Context):
+    ctx.check(_lib.soc_graph_begin(ctx.h))
+
+
+def graph_end(ctx: Context) -> Graph:
+    h = C.c_void_p()
+    ctx.check(_lib.soc_graph_end(ctx.h, C.byref(h)))
+    return Graph(ctx, h)
