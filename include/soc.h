@@ -252,6 +252,18 @@ soc_status soc_batch_info(soc_batch b, int32_t *n_tiles, uint64_t *n_packages);
 #define SOC_ITER_ADVANCE 0xFFFFFFFFu
 soc_status soc_batch_run(soc_batch b, uint32_t iteration, soc_sim_stats *stats);
 
+/* ---------------------------------------------------------------- ceilings */
+/* Device micro-benchmarks for the roofline of the Monte Carlo kernel
+ * (times one launch with HIP events, synchronises):
+ *  which 0: random FP64 atomic adds, per_thread per thread, into d_buf
+ *           (n doubles; mode 1: one slice of n doubles per XCD, selected by
+ *           the hardware XCC id, so d_buf must hold 8 n doubles);
+ *  which 1: dependent random 4-byte gathers over n words of d_buf;
+ *  which 2: streaming copy of n bytes from d_buf to d_buf2.
+ * ms receives the kernel time. */
+soc_status soc_ubench(soc_ctx ctx, int32_t which, void *d_buf, void *d_buf2, uint64_t n, int32_t per_thread,
+                      int32_t mode, int32_t blocks, int32_t threads, double *ms);
+
 /* ---------------------------------------------------------------- graphs */
 /* Capture the library calls issued on the context's stream between
  * soc_graph_begin and soc_graph_end into a HIP graph (stream capture,

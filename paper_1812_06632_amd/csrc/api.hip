@@ -925,6 +925,30 @@ soc_status soc_batch_run(soc_batch b, uint32_t iteration, soc_sim_stats *stats)
     return SOC_OK;
 }
 
+soc_status soc_ubench(soc_ctx c, int32_t which, void *d_buf, void *d_buf2, uint64_t n, int32_t per_thread,
+                      int32_t mode, int32_t blocks, int32_t threads, double *ms)
+{
+    if (!c) return SOC_EINVAL;
+    NOT_WHILE_CAPTURING(c);
+    if (!d_buf || !ms || n == 0 || n > 0xFFFFFFFFull || per_thread < 1 || blocks < 1 || threads < 64 ||
+        threads > 1024 || which < 0 || which > 2 || (which != 0 && !d_buf2))
+        return fail(c, SOC_EINVAL, "bad micro-benchmark arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    HIPCHK(c, launch_ubench(which, d_buf, d_buf2, n, per_thread, mode, blocks, threads, c->stream));
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float t = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = t;
+    return SOC_OK;
+}
+
 soc_status soc_graph_begin(soc_ctx c)
 {
     if (!c) return SOC_EINVAL;

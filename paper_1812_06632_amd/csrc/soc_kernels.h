@@ -198,6 +198,13 @@ struct BatchView {
 hipError_t launch_mc_batch(const BatchArgs &a, int blocks, int threads, hipStream_t s);
 hipError_t launch_advance_iteration(uint32_t *it, int32_t mode, uint32_t value, hipStream_t s);
 
+// micro-benchmarks: which 0 = random FP64 atomics (mode 0 shared, 1 per
+// XCD slice; buf holds n doubles, or 8 n in mode 1), 1 = dependent random
+// 4-byte gathers over n words (buf2: 1-word sink), 2 = copy of n bytes
+// from buf to buf2.
+hipError_t launch_ubench(int32_t which, void *buf, void *buf2, uint64_t n, int32_t per_thread, int32_t mode,
+                         int blocks, int threads, hipStream_t s);
+
 // map
 struct MapArgs {
     const uint32_t *words;

@@ -1,0 +1,74 @@
+// ubench.hip -- micro-benchmarks that measure the ceilings the Monte Carlo
+// kernel is bounded by on this device: random FP64 atomic adds into an
+// array of a given size (shared by all XCDs, or one private slice per XCD
+// chosen by the hardware XCC id), dependent random 4-byte gathers, and a
+// plain streaming copy (the reference for HBM traffic counters).
+#include <hip/hip_runtime.h>
+
+#include "soc_kernels.h"
+
+namespace soc {
+
+__device__ inline uint32_t mix32(uint32_t x)
+{
+    // integer hash (xorshift-multiply), a cheap address scrambler
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+__device__ inline uint32_t xcc_id()
+{
+    return __builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & 7u;   // HW_REG_XCC_ID[3:0]
+}
+
+// mode 0: one array shared by every XCD; mode 1: slice xcc_id() of 8.
+__global__ void ubench_atomic_kernel(double *a, uint32_t n, int32_t per_thread, int32_t mode)
+{
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    double *base = mode ? a + (size_t)xcc_id() * n : a;
+    uint32_t h = tid * 0x9E3779B9u + 1u;
+    for (int i = 0; i < per_thread; ++i) {
+        h = mix32(h + (uint32_t)i);
+        unsafeAtomicAdd(&base[h % n], 1.0);
+    }
+}
+
+__global__ void ubench_gather_kernel(const uint32_t *w, uint32_t n, int32_t per_thread, uint32_t *out)
+{
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t h = mix32(tid + 12345u) % n;
+    uint32_t acc = 0;
+    for (int i = 0; i < per_thread; ++i) {
+        const uint32_t v = w[h];
+        acc += v;
+        h = mix32(h ^ v) % n;   // dependent chain: the next address needs this load
+    }
+    if (acc == 0xFFFFFFFFu) out[0] = acc;
+}
+
+__global__ void ubench_copy_kernel(const float4 *src, float4 *dst, size_t n4)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+hipError_t launch_ubench(int32_t which, void *buf, void *buf2, uint64_t n, int32_t per_thread, int32_t mode,
+                         int blocks, int threads, hipStream_t s)
+{
+    if (which == 0)
+        hipLaunchKernelGGL(ubench_atomic_kernel, dim3(blocks), dim3(threads), 0, s, (double *)buf, (uint32_t)n,
+                           per_thread, mode);
+    else if (which == 1)
+        hipLaunchKernelGGL(ubench_gather_kernel, dim3(blocks), dim3(threads), 0, s, (const uint32_t *)buf,
+                           (uint32_t)n, per_thread, (uint32_t *)buf2);
+    else
+        hipLaunchKernelGGL(ubench_copy_kernel, dim3(blocks), dim3(threads), 0, s, (const float4 *)buf,
+                           (float4 *)buf2, (size_t)(n / 16));
+    return hipGetLastError();
+}
+
+}  // namespace soc

@@ -416,3 +416,17 @@ def graph_end(ctx: Context) -> Graph:
     h = C.c_void_p()
     ctx.check(_lib.soc_graph_end(ctx.h, C.byref(h)))
     return Graph(ctx, h)
+
+
+_lib.soc_ubench.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_uint64, C.c_int32, C.c_int32,
+                            C.c_int32, C.c_int32, C.POINTER(C.c_double)]
+
+
+def ubench(ctx: Context, which: int, buf: torch.Tensor, buf2: torch.Tensor | None, n: int, per_thread: int,
+           mode: int = 0, blocks: int = 4096, threads: int = 256) -> float:
+    """soc_ubench: milliseconds of one micro-benchmark launch."""
+    ms = C.c_double()
+    ctx.check(_lib.soc_ubench(ctx.h, int(which), C.c_void_p(buf.data_ptr()),
+                              C.c_void_p(buf2.data_ptr()) if buf2 is not None else None, C.c_uint64(n),
+                              int(per_thread), int(mode), int(blocks), int(threads), C.byref(ms)))
+    return ms.value

@@ -367,3 +367,29 @@ def octree_lognormal(n_root: int = 64, nlevels: int = 4, sigma_ln: float = 1.5, 
     col = rho[M // 2, M // 2, M // 2:].sum() * s_fine
     rho *= tau_v_core / (SIGMA_V * col)
     return octree_from_field(rho, n_root, nlevels, box_pc * PC_CM / n_root, threshold)
+
+
+def batch_clouds(n_models: int = 256, K: int = 32, n_min: int = 16, n_max: int = 96, seed: int = 4000,
+                 pk_min: float = 1e5, pk_max: float = 1e6, box_pc: float = 1.0):
+    """Independent lognormal clouds of uneven size for the batched launch:
+    model m has an N_m^3 grid with N_m log-uniform in [n_min, n_max] (a
+    multiple of 8), sigma_ln ~ U(0.5, 1.5), mean face-to-face tau_V
+    log-uniform in [1, 50], GRF seed seed + m; K frequencies; the package
+    count of every (model, frequency) pair log-uniform in [pk_min, pk_max].
+    Returns (grids, frequency table (nu, w, sigma_abs, sigma_sca, g, I_bg),
+    packages[m, k])."""
+    rng = np.random.default_rng(seed)
+    grids = []
+    for m in range(n_models):
+        n = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max))) / 8.0)) * 8
+        n = max(n_min, min(n_max, n))
+        sig = rng.uniform(0.5, 1.5)
+        tau = math.exp(rng.uniform(math.log(1.0), math.log(50.0)))
+        rho = grf_lognormal(n, sig, seed + m)
+        s_cm = box_pc * PC_CM / n
+        rho *= tau / (SIGMA_V * s_cm * n * rho.mean())
+        grids.append(regular_grid(rho.astype(np.float32), s_cm))
+    nu, w = frequency_grid(K)
+    sabs, ssca, g = dust_model(nu)
+    pk = np.exp(rng.uniform(math.log(pk_min), math.log(pk_max), size=(n_models, K))).astype(np.int64)
+    return grids, (nu, w, sabs, ssca, g, isrf(nu)), pk
