@@ -169,56 +169,43 @@ def forward(P, x, levels):
 
 
 def backward(P, cache, dy, levels):
-    """Gradients of sum(dy * output) with respect to every parameter."""
-    G = {}
-    dx, dw, db = conv3_bwd(cache["out_in"], P["out"][0], dy)
-    G["out"] = (dw, db)
-    g = dx
-    dskips = {}
-    ch = [P[f"e{l}a"][0].shape[4] for l in range(levels)]
-    for l in range(levels - 1):
-        for s in "ba":
-            gz = lrelu_bwd(cache[f"q{l}{s}_z"], g)
-            gx, dw, db = conv3_bwd(cache[f"q{l}{s}_in"], P[f"q{l}{s}"][0], gz)
-            G[f"q{l}{s}"] = (dw, db)
-            g = gx
-        dskips[l] = g[..., :ch[l]]
-        gz = lrelu_bwd(cache[f"u{l}_z"], g[..., ch[l]:])
-        gx, dw, db = up2_bwd(cache[f"u{l}_in"], P[f"u{l}"][0], gz)
-        G[f"u{l}"] = (dw, db)
-        g = gx
-        if l + 1 < levels - 1:
-            pass
-    # the loop above walks the decoder from the top level (levels-2) down;
-    # redo it in that order
-    return _backward_ordered(P, cache, dy, levels)
-
-
-def _backward_ordered(P, cache, dy, levels):
+    """Gradients of sum(dy * output) with respect to every parameter, as a
+    dict name -> (dw, db).  Decoder stages are undone from the top (level
+    0) down, then the encoder from the bottom up, adding the skip gradient
+    of each level to the gradient coming back through its down
+    convolution."""
     G = {}
     ch = [P[f"e{l}a"][0].shape[4] for l in range(levels)]
     gx, dw, db = conv3_bwd(cache["out_in"], P["out"][0], dy)
     G["out"] = (dw, db)
     g = gx
-    dskips = {}
+    dskip = {}
     for l in range(0, levels - 1):
         for s in "ba":
             gz = lrelu_bwd(cache[f"q{l}{s}_z"], g)
             gx, dw, db = conv3_bwd(cache[f"q{l}{s}_in"], P[f"q{l}{s}"][0], gz)
             G[f"q{l}{s}"] = (dw, db)
             g = gx
-        dskips[l] = g[..., :ch[l]]
+        dskip[l] = g[..., :ch[l]]
         gz = lrelu_bwd(cache[f"u{l}_z"], g[..., ch[l]:])
         gx, dw, db = up2_bwd(cache[f"u{l}_in"], P[f"u{l}"][0], gz)
         G[f"u{l}"] = (dw, db)
         g = gx
-        if l < levels - 2:
-            break_level = l + 1
-            # the upsampled input of level l is the output of decoder level l+1
-            for s in "ba":
-                gz = lrelu_bwd(cache[f"q{break_level}{s}_z"], g)
-                gx, dw, db = conv3_bwd(cache[f"q{break_level}{s}_in"], P[f"q{break_level}{s}"][0], gz)
-                G[f"q{break_level}{s}"] = (dw, db)
-                g = gx
-            raise NotImplementedError
+    for l in range(levels - 1, -1, -1):
+        for s in "ba":
+            gz = lrelu_bwd(cache[f"e{l}{s}_z"], g)
+            gx, dw, db = conv3_bwd(cache[f"e{l}{s}_in"], P[f"e{l}{s}"][0], gz)
+            G[f"e{l}{s}"] = (dw, db)
+            g = gx
+        if l > 0:
+            gz = lrelu_bwd(cache[f"d{l - 1}_z"], g)
+            gx, dw, db = down2_bwd(cache[f"d{l - 1}_in"], P[f"d{l - 1}"][0], gz)
+            G[f"d{l - 1}"] = (dw, db)
+            g = gx + dskip[l - 1]
     return G
+
+
+def mse(y, t):
+    """Mean squared error and its gradient."""
+    d = y - t
+    return float(np.mean(d * d)), 2.0 * d / d.size
