@@ -32,10 +32,87 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_STEP = 12.0   # 4 B density gather + 8 B FP64 absorbed update per cell step
+MC_KERNEL = "soc::mc_kernel<false>"   # regular-grid instantiation of the persistent MC kernel
+# HBM traffic of the MC kernel measured with rocprofv3 counters (FETCH_SIZE,
+# WRITE_SIZE, scaled by a 1 GiB copy); used only while the kernel sources
+# still hash to the value recorded with it.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mc_kernel_lognormal128_traffic.md")
+MC_SOURCES = ("mc.hip", "soc_device.h", "soc_kernels.h")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def mc_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in MC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1812_06632_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """Bytes per MC launch from the committed counter summary, or None when
+    it is absent or was taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("mc_source_sha256") != mc_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def device_ceilings(soc, ctx, torch, ncells):
+    """Measured ceilings of the MC kernel's memory operations at the grid's
+    size: random FP64 atomic adds and a 1 GiB streaming copy (the copy is
+    also the scale reference of the HBM byte counters)."""
+    a = torch.zeros(ncells, dtype=torch.float64, device="cuda")
+    blocks, threads, per = 4096, 256, 64
+    soc.ubench(ctx, 0, a, None, ncells, per, 0, blocks, threads)
+    ms = min(soc.ubench(ctx, 0, a, None, ncells, per, 0, blocks, threads) for _ in range(3))
+    atomics = blocks * threads * per / (ms * 1e-3)
+    nbytes = 1 << 30
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    soc.ubench(ctx, 2, src, dst, nbytes, 1, 0, 8192, 256)
+    ms = min(soc.ubench(ctx, 2, src, dst, nbytes, 1, 0, 8192, 256) for _ in range(3))
+    copy_gbs = 2 * nbytes / (ms * 1e-3) / 1e9
+    del a, src, dst
+    return atomics, copy_gbs
+
+
+def ceilings(soc, torch, ncells):
+    """Every micro-benchmark mode at the benchmark grid's size."""
+    ctx = soc.Context(0)
+    blocks, threads, per = 4096, 256, 64
+    a = torch.zeros(8 * ncells, dtype=torch.float64, device="cuda")
+    names = {0: "random, one shared array", 1: "random, one private copy per XCD (hardware XCC id)",
+             2: "wave-coalesced 64-double blocks", 3: "random in a 4096-double LDS array"}
+    for mode, label in names.items():
+        soc.ubench(ctx, 0, a, None, ncells, per, mode, blocks, threads)
+        ms = min(soc.ubench(ctx, 0, a, None, ncells, per, mode, blocks, threads) for _ in range(3))
+        print(json.dumps({"kind": "fp64_atomic_add", "mode": mode, "pattern": label, "array_doubles": ncells,
+                          "ms": ms, "per_s": blocks * threads * per / (ms * 1e-3)}), flush=True)
+    w = torch.randint(0, 2**31 - 1, (ncells,), dtype=torch.int32, device="cuda")
+    out = torch.zeros(4, dtype=torch.int32, device="cuda")
+    for nb in (4096, 16384):
+        soc.ubench(ctx, 1, w, out, ncells, per, 0, nb, threads)
+        ms = min(soc.ubench(ctx, 1, w, out, ncells, per, 0, nb, threads) for _ in range(3))
+        print(json.dumps({"kind": "dependent_gather_4B", "array_words": ncells, "blocks": nb, "ms": ms,
+                          "per_s": nb * threads * per / (ms * 1e-3)}), flush=True)
+    _, copy_gbs = device_ceilings(soc, ctx, torch, ncells)
+    print(json.dumps({"kind": "copy", "bytes": 1 << 30, "GBs_read_plus_write": copy_gbs}), flush=True)
+    ctx.close()
 
 
 def main():
@@ -49,6 +126,8 @@ def main():
     ap.add_argument("--max-iter", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-converge", action="store_true")
+    ap.add_argument("--ceilings", action="store_true",
+                    help="only run the device micro-benchmarks (one JSON line each) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the design notes describe how the "
@@ -59,6 +138,10 @@ def main():
     import torch
 
     from paper_1812_06632_amd import soc, workloads as W
+
+    if args.ceilings:
+        ceilings(soc, torch, args.n ** 3)
+        return
 
     t_setup = time.time()
     P = W.lognormal_problem(n=args.n, K=args.freqs, packages_per_freq=args.packages)
@@ -126,6 +209,8 @@ def main():
     achieved = BYTES_PER_STEP * steps_per_launch / avg_launch_s / 1e9
     log(f"timed: {elapsed:.3f}s for {args.steps} iterations, {pk_per_s:.3e} packages/s, {steps_per_s:.3e} "
         f"cell-steps/s, MC kernel avg {avg_launch_s * 1e3:.3f} ms/launch")
+    atomic_ceiling, copy_gbs = device_ceilings(soc, ctx, torch, nc)
+    log(f"ceilings: random FP64 atomics {atomic_ceiling:.3e}/s over {nc} doubles, copy {copy_gbs:.0f} GB/s")
 
     # ---- continue to the 1% stopping rule (plain method)
     time_to_conv = None
@@ -156,7 +241,7 @@ def main():
         ncpu = min(os.cpu_count() or 1, 16)
         Th = T.cpu().numpy()
         sample_f = [K // 4, K // 2, 3 * K // 4]
-        npk = 100_000
+        npk = 10_000_000
         t0 = time.time()
         tot_pk = tot_st = 0
         for k in sample_f:
@@ -171,6 +256,7 @@ def main():
                "sample": f"dust emission, {npk} weighted packages at each of frequencies {sample_f} of the "
                          f"same {args.n}^3 workload and temperatures (FP64 C oracle, OpenMP)"}
 
+    traffic = recorded_traffic()
     out = {
         "metric": "photon packages/s",
         "value": pk_per_s,
@@ -193,9 +279,12 @@ def main():
         "time_to_1pct_T_s": time_to_conv,
         "iterations_to_1pct": conv_iter,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "mc_regular_kernel", "avg_launch_ms": avg_launch_s * 1e3,
-                     "bytes_per_cell_step": BYTES_PER_STEP},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": MC_KERNEL, "avg_launch_ms": avg_launch_s * 1e3,
+                     "cell_steps_per_launch": steps_per_launch, "bytes_per_cell_step": BYTES_PER_STEP,
+                     "atomic_ceiling_per_s": atomic_ceiling,
+                     "atomic_frac": steps_per_launch / avg_launch_s / atomic_ceiling,
+                     "copy_GBs": copy_gbs},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -1,8 +1,9 @@
 // ubench.hip -- micro-benchmarks that measure the ceilings the Monte Carlo
-// kernel is bounded by on this device: random FP64 atomic adds into an
-// array of a given size (shared by all XCDs, or one private slice per XCD
-// chosen by the hardware XCC id), dependent random 4-byte gathers, and a
-// plain streaming copy (the reference for HBM traffic counters).
+// kernel is bounded by on this device: FP64 atomic adds (random addresses
+// in an array shared by all XCDs or in one private slice per XCD chosen by
+// the hardware XCC id, wave-coalesced blocks, or an LDS array), dependent
+// random 4-byte gathers, and a plain streaming copy (the reference for HBM
+// traffic counters).
 #include <hip/hip_runtime.h>
 
 #include "soc_kernels.h"
@@ -25,15 +26,39 @@ __device__ inline uint32_t xcc_id()
     return __builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & 7u;   // HW_REG_XCC_ID[3:0]
 }
 
-// mode 0: one array shared by every XCD; mode 1: slice xcc_id() of 8.
+// mode 0: random addresses in one array shared by every XCD;
+// mode 1: random addresses in slice xcc_id() of 8 (per-XCD private copies);
+// mode 2: wave-coalesced, every wave updating the 64 consecutive doubles of
+//         one random 64-double block (n >= 64);
+// mode 3: random addresses in a 4096-double LDS array of the workgroup
+//         (the LDS sum is folded into a[0..4095] at the end; n >= 4096).
+constexpr int kUbLds = 4096;
+
 __global__ void ubench_atomic_kernel(double *a, uint32_t n, int32_t per_thread, int32_t mode)
 {
+    __shared__ double lds[kUbLds];
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
-    double *base = mode ? a + (size_t)xcc_id() * n : a;
+    const uint32_t lane = threadIdx.x & 63u;
+    double *base = mode == 1 ? a + (size_t)xcc_id() * n : a;
+    if (mode == 3) {
+        for (int i = threadIdx.x; i < kUbLds; i += blockDim.x) lds[i] = 0.0;
+        __syncthreads();
+    }
     uint32_t h = tid * 0x9E3779B9u + 1u;
     for (int i = 0; i < per_thread; ++i) {
         h = mix32(h + (uint32_t)i);
-        unsafeAtomicAdd(&base[h % n], 1.0);
+        if (mode == 2) {
+            const uint32_t blk = __builtin_amdgcn_readfirstlane(h) % (n >> 6);
+            unsafeAtomicAdd(&base[blk * 64u + lane], 1.0);
+        } else if (mode == 3) {
+            unsafeAtomicAdd(&lds[h & (kUbLds - 1)], 1.0);
+        } else {
+            unsafeAtomicAdd(&base[h % n], 1.0);
+        }
+    }
+    if (mode == 3) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < kUbLds; i += blockDim.x) unsafeAtomicAdd(&a[i], lds[i]);
     }
 }
 
