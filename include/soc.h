@@ -255,9 +255,13 @@ soc_status soc_batch_run(soc_batch b, uint32_t iteration, soc_sim_stats *stats);
 /* ---------------------------------------------------------------- ceilings */
 /* Device micro-benchmarks for the roofline of the Monte Carlo kernel
  * (times one launch with HIP events, synchronises):
- *  which 0: random FP64 atomic adds, per_thread per thread, into d_buf
- *           (n doubles; mode 1: one slice of n doubles per XCD, selected by
- *           the hardware XCC id, so d_buf must hold 8 n doubles);
+ *  which 0: FP64 atomic adds of 1.0, per_thread per thread, into d_buf
+ *           (n doubles): mode 0 random addresses; mode 1 random addresses
+ *           in one slice of n doubles per XCD, selected by the hardware XCC
+ *           id, so d_buf must hold 8 n doubles; mode 2 each wave adds to
+ *           the 64 consecutive doubles of one random 64-double block
+ *           (n >= 64); mode 3 random addresses in a 4096-double LDS array
+ *           per workgroup, folded into d_buf[0..4095] (n >= 4096);
  *  which 1: dependent random 4-byte gathers over n words of d_buf;
  *  which 2: streaming copy of n bytes from d_buf to d_buf2.
  * ms receives the kernel time. */
@@ -276,6 +280,64 @@ soc_status soc_graph_begin(soc_ctx ctx);
 soc_status soc_graph_end(soc_ctx ctx, soc_graph *out);
 soc_status soc_graph_launch(soc_graph g);
 void soc_graph_destroy(soc_graph g);
+
+/* ---------------------------------------------------------------- surrogate */
+/* Learned starting temperatures.  The paper speeds up the iteration by
+ * starting it from a reference field (Sec. 2.1.2); here a 3-D
+ * convolutional U-Net, trained on fields the plain method produced,
+ * predicts the field the iteration starts from, and the plain iterations
+ * that follow keep the result unbiased.
+ *
+ * Network: `levels` resolution levels with base * 2^l channels; each level
+ * has two 3^3 convolutions (zero padding) with a leaky ReLU of slope 0.1; a
+ * stride-2 2^3 convolution (+ leaky ReLU) goes down, a stride-2 transposed
+ * 2^3 convolution (+ leaky ReLU) comes up and is concatenated after the
+ * skip tensor of the level; a last 3^3 convolution without activation
+ * gives `cout` channels.  BF16 activations and weights in the matrix-core
+ * products, FP32 accumulation, FP32 master weights and Adam state.
+ *
+ * Parameters: one FP32 array, layer by layer in the order
+ *   e0a e0b d0 e1a e1b d1 ... e{L-1}a e{L-1}b u{L-2} q{L-2}a q{L-2}b ... u0 q0a q0b out
+ * (e encoder convolutions, d down, u up, q decoder convolutions), each as
+ * weights w[kz][ky][kx][cin][cout] followed by biases b[cout].
+ *
+ * Tensors passed to the calls are device FP32, channels-last:
+ * x[n][nz][ny][nx][cin], y[n][nz][ny][nx][cout].  The network owns its
+ * parameters, optimiser state, activations and gradients (allocated at
+ * creation for up to nmax samples); calls enqueue on the context's stream.
+ * forward, backward and adam allocate nothing and may be captured in a
+ * graph; calls with host buffers synchronise and return SOC_ESTATE while
+ * capturing. */
+typedef struct soc_unet_s *soc_unet;
+typedef struct {
+    int32_t cin, cout;     /* input and output channels (>= 1) */
+    int32_t base, levels;  /* level-0 channels (a positive multiple of 16), 1 <= levels <= 6 */
+    int32_t nmax;          /* largest batch */
+    int32_t nz, ny, nx;    /* cells of one sample, each divisible by 2^(levels-1) */
+} soc_unet_desc;
+/* He-normal weights from seed, zero biases.  SOC_EINVAL on a bad shape. */
+soc_status soc_unet_create(soc_ctx ctx, const soc_unet_desc *desc, uint64_t seed, soc_unet *out);
+void soc_unet_destroy(soc_unet u);
+soc_status soc_unet_param_count(soc_unet u, int64_t *count);
+/* 2 x multiply-adds of one forward pass over n samples (unpadded shapes). */
+soc_status soc_unet_flops(soc_unet u, int32_t n, int64_t *flops);
+/* Host FP32 arrays of soc_unet_param_count elements. */
+soc_status soc_unet_set_params(soc_ctx ctx, soc_unet u, const float *h_params);
+soc_status soc_unet_get_params(soc_ctx ctx, soc_unet u, float *h_params);
+soc_status soc_unet_get_grads(soc_ctx ctx, soc_unet u, float *h_grads);
+/* y = net(x) for n <= nmax samples. */
+soc_status soc_unet_forward(soc_ctx ctx, soc_unet u, int32_t n, const float *d_x, float *d_y);
+/* Gradients of sum(dy * y) with respect to every parameter, for the
+ * inputs of the last forward call; they replace the previous gradients. */
+soc_status soc_unet_backward(soc_ctx ctx, soc_unet u, const float *d_dy);
+/* Mean of (y - t)^2 over n samples x cells x cout into *loss (host; NULL:
+ * no result and no synchronisation) and its gradient 2 (y - t) / count into
+ * d_dy (NULL: not written). */
+soc_status soc_unet_mse(soc_ctx ctx, soc_unet u, int32_t n, const float *d_y, const float *d_t, float *d_dy,
+                        double *loss);
+/* One Adam step (bias-corrected moments, step counts from 1) with the
+ * current gradients; refreshes the BF16 weight copies. */
+soc_status soc_unet_adam(soc_ctx ctx, soc_unet u, float lr, float beta1, float beta2, float eps, int32_t step);
 
 #ifdef __cplusplus
 }

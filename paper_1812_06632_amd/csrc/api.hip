@@ -13,11 +13,13 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <new>
 #include <vector>
 
 #include "soc.h"
 #include "soc_device.h"
 #include "soc_kernels.h"
+#include "unet.h"
 
 using namespace soc;
 
@@ -931,20 +933,26 @@ soc_status soc_ubench(soc_ctx c, int32_t which, void *d_buf, void *d_buf2, uint6
     if (!c) return SOC_EINVAL;
     NOT_WHILE_CAPTURING(c);
     if (!d_buf || !ms || n == 0 || n > 0xFFFFFFFFull || per_thread < 1 || blocks < 1 || threads < 64 ||
-        threads > 1024 || which < 0 || which > 2 || (which != 0 && !d_buf2))
+        threads > 1024 || which < 0 || which > 2 || (which != 0 && !d_buf2) ||
+        (which == 0 && (mode < 0 || mode > 3 || (mode == 2 && n < 64) || (mode == 3 && n < 4096))))
         return fail(c, SOC_EINVAL, "bad micro-benchmark arguments");
     HIPCHK(c, hipSetDevice(c->device));
-    hipEvent_t e0, e1;
-    HIPCHK(c, hipEventCreate(&e0));
-    HIPCHK(c, hipEventCreate(&e1));
-    HIPCHK(c, hipEventRecord(e0, c->stream));
+    struct Events {   // destroyed on every return path
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Events()
+        {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } ev;
+    HIPCHK(c, hipEventCreate(&ev.e[0]));
+    HIPCHK(c, hipEventCreate(&ev.e[1]));
+    HIPCHK(c, hipEventRecord(ev.e[0], c->stream));
     HIPCHK(c, launch_ubench(which, d_buf, d_buf2, n, per_thread, mode, blocks, threads, c->stream));
-    HIPCHK(c, hipEventRecord(e1, c->stream));
-    HIPCHK(c, hipEventSynchronize(e1));
+    HIPCHK(c, hipEventRecord(ev.e[1], c->stream));
+    HIPCHK(c, hipEventSynchronize(ev.e[1]));
     float t = 0.0f;
-    HIPCHK(c, hipEventElapsedTime(&t, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    HIPCHK(c, hipEventElapsedTime(&t, ev.e[0], ev.e[1]));
     *ms = t;
     return SOC_OK;
 }
@@ -1001,3 +1009,127 @@ void soc_graph_destroy(soc_graph g)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- surrogate
+struct soc_unet_s {
+    soc_ctx ctx = nullptr;   // identity check only
+    int device = 0;
+    soc::unet::Net net;
+};
+
+#define UNET_ARGS(c, u)                                                            \
+    do {                                                                           \
+        if (!(c) || !(u)) return SOC_EINVAL;                                       \
+        if ((u)->device != (c)->device)                                            \
+            return fail((c), SOC_EINVAL, "network and context on different devices"); \
+        HIPCHK((c), hipSetDevice((c)->device));                                    \
+    } while (0)
+
+soc_status soc_unet_create(soc_ctx c, const soc_unet_desc *d, uint64_t seed, soc_unet *out)
+{
+    if (!c || !d || !out) return SOC_EINVAL;
+    NOT_WHILE_CAPTURING(c);
+    *out = nullptr;
+    HIPCHK(c, hipSetDevice(c->device));
+    soc_unet u = new (std::nothrow) soc_unet_s;
+    if (!u) return fail(c, SOC_ENOMEM, "host allocation failed");
+    u->ctx = c;
+    u->device = c->device;
+    const auto st =
+        u->net.create(c->device, d->cin, d->cout, d->base, d->levels, d->nmax, d->nz, d->ny, d->nx, seed, c->stream);
+    if (st.code != soc::unet::Net::OK) {
+        delete u;
+        const soc_status code = st.code == soc::unet::Net::BAD_SHAPE   ? SOC_EINVAL
+                                : st.code == soc::unet::Net::NO_MEMORY ? SOC_ENOMEM
+                                                                       : SOC_EHIP;
+        return fail(c, code, "soc_unet_create: %s", st.msg.c_str());
+    }
+    *out = u;
+    return SOC_OK;
+}
+
+void soc_unet_destroy(soc_unet u)
+{
+    if (!u) return;
+    (void)hipSetDevice(u->device);
+    delete u;
+}
+
+soc_status soc_unet_param_count(soc_unet u, int64_t *count)
+{
+    if (!u || !count) return SOC_EINVAL;
+    *count = u->net.param_count();
+    return SOC_OK;
+}
+
+soc_status soc_unet_set_params(soc_ctx c, soc_unet u, const float *h_params)
+{
+    UNET_ARGS(c, u);
+    NOT_WHILE_CAPTURING(c);
+    if (!h_params) return fail(c, SOC_EINVAL, "NULL parameters");
+    HIPCHK(c, u->net.set_params(h_params, c->stream));
+    return SOC_OK;
+}
+
+soc_status soc_unet_get_params(soc_ctx c, soc_unet u, float *h_params)
+{
+    UNET_ARGS(c, u);
+    NOT_WHILE_CAPTURING(c);
+    if (!h_params) return fail(c, SOC_EINVAL, "NULL parameters");
+    HIPCHK(c, u->net.get_params(h_params, c->stream));
+    return SOC_OK;
+}
+
+soc_status soc_unet_get_grads(soc_ctx c, soc_unet u, float *h_grads)
+{
+    UNET_ARGS(c, u);
+    NOT_WHILE_CAPTURING(c);
+    if (!h_grads) return fail(c, SOC_EINVAL, "NULL gradients");
+    HIPCHK(c, u->net.get_grads(h_grads, c->stream));
+    return SOC_OK;
+}
+
+soc_status soc_unet_forward(soc_ctx c, soc_unet u, int32_t n, const float *d_x, float *d_y)
+{
+    UNET_ARGS(c, u);
+    if (n < 1 || n > u->net.nmax_ || !d_x || !d_y)
+        return fail(c, SOC_EINVAL, "soc_unet_forward: batch %d outside [1, %d] or NULL buffer", n, u->net.nmax_);
+    HIPCHK(c, u->net.forward(n, d_x, d_y, c->stream));
+    return SOC_OK;
+}
+
+soc_status soc_unet_backward(soc_ctx c, soc_unet u, const float *d_dy)
+{
+    UNET_ARGS(c, u);
+    if (!d_dy) return fail(c, SOC_EINVAL, "NULL output gradient");
+    if (u->net.n_last_ < 1) return fail(c, SOC_ESTATE, "soc_unet_backward before any forward");
+    HIPCHK(c, u->net.backward(d_dy, c->stream));
+    return SOC_OK;
+}
+
+soc_status soc_unet_mse(soc_ctx c, soc_unet u, int32_t n, const float *d_y, const float *d_t, float *d_dy,
+                        double *loss)
+{
+    UNET_ARGS(c, u);
+    if (loss) NOT_WHILE_CAPTURING(c);
+    if (n < 1 || n > u->net.nmax_ || !d_y || !d_t) return fail(c, SOC_EINVAL, "soc_unet_mse: bad arguments");
+    HIPCHK(c, u->net.mse(n, d_y, d_t, d_dy, loss, c->stream));
+    return SOC_OK;
+}
+
+soc_status soc_unet_adam(soc_ctx c, soc_unet u, float lr, float beta1, float beta2, float eps, int32_t step)
+{
+    UNET_ARGS(c, u);
+    if (!(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f) ||
+        step < 1)
+        return fail(c, SOC_EINVAL, "soc_unet_adam: bad hyper-parameters");
+    HIPCHK(c, u->net.adam(lr, beta1, beta2, eps, step, c->stream));
+    return SOC_OK;
+}
+
+soc_status soc_unet_flops(soc_unet u, int32_t n, int64_t *flops)
+{
+    if (!u || !flops || n < 1) return SOC_EINVAL;
+    *flops = u->net.flops_forward(n);
+    return SOC_OK;
+}

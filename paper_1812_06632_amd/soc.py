@@ -430,3 +430,106 @@ def ubench(ctx: Context, which: int, buf: torch.Tensor, buf2: torch.Tensor | Non
                               C.c_void_p(buf2.data_ptr()) if buf2 is not None else None, C.c_uint64(n),
                               int(per_thread), int(mode), int(blocks), int(threads), C.byref(ms)))
     return ms.value
+
+
+# ---------------------------------------------------------------- surrogate
+class _UnetDesc(C.Structure):
+    _fields_ = [("cin", C.c_int32), ("cout", C.c_int32), ("base", C.c_int32), ("levels", C.c_int32),
+                ("nmax", C.c_int32), ("nz", C.c_int32), ("ny", C.c_int32), ("nx", C.c_int32)]
+
+
+_lib.soc_unet_create.argtypes = [C.c_void_p, C.POINTER(_UnetDesc), C.c_uint64, C.POINTER(C.c_void_p)]
+_lib.soc_unet_destroy.argtypes = [C.c_void_p]
+_lib.soc_unet_param_count.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+_lib.soc_unet_flops.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]
+for _n in ("soc_unet_set_params", "soc_unet_get_params", "soc_unet_get_grads"):
+    getattr(_lib, _n).argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.soc_unet_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+_lib.soc_unet_backward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.soc_unet_mse.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.POINTER(C.c_double)]
+_lib.soc_unet_adam.argtypes = [C.c_void_p, C.c_void_p, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32]
+
+
+class UNet:
+    """The 3-D U-Net surrogate (soc_unet_*): FP32 channels-last device
+    tensors in and out, BF16 matrix-core convolutions inside."""
+
+    def __init__(self, ctx: Context, cin: int, cout: int, base: int, levels: int, nmax: int, shape, seed: int = 0):
+        nz, ny, nx = (int(v) for v in shape)
+        self.ctx, self.cin, self.cout, self.nmax, self.shape = ctx, cin, cout, nmax, (nz, ny, nx)
+        self.base, self.levels = base, levels
+        d = _UnetDesc(cin, cout, base, levels, nmax, nz, ny, nx)
+        h = C.c_void_p()
+        ctx.check(_lib.soc_unet_create(ctx.h, C.byref(d), C.c_uint64(seed & (2**64 - 1)), C.byref(h)))
+        self.h = h
+        ctx._children.add(self)
+        n = C.c_int64()
+        ctx.check(_lib.soc_unet_param_count(h, C.byref(n)))
+        self.param_count = n.value
+        self.step = 0
+
+    def flops(self, n: int) -> int:
+        f = C.c_int64()
+        self.ctx.check(_lib.soc_unet_flops(self.h, int(n), C.byref(f)))
+        return f.value
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(p, dtype=np.float32).ravel()
+        if a.size != self.param_count:
+            raise ValueError(f"expected {self.param_count} parameters, got {a.size}")
+        self.ctx.check(_lib.soc_unet_set_params(self.ctx.h, self.h, a.ctypes.data_as(C.c_void_p)))
+
+    def _get(self, fn):
+        a = np.empty(self.param_count, np.float32)
+        self.ctx.check(fn(self.ctx.h, self.h, a.ctypes.data_as(C.c_void_p)))
+        return a
+
+    def get_params(self) -> np.ndarray:
+        return self._get(_lib.soc_unet_get_params)
+
+    def get_grads(self) -> np.ndarray:
+        return self._get(_lib.soc_unet_get_grads)
+
+    def _check_x(self, x, c, name):
+        if x.dim() != 5 or tuple(x.shape[1:4]) != self.shape or x.shape[4] != c:
+            raise ValueError(f"{name} must be [n, {self.shape[0]}, {self.shape[1]}, {self.shape[2]}, {c}]")
+        return _dev_ptr(x, torch.float32, name)
+
+    def forward(self, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
+        n = x.shape[0]
+        px = self._check_x(x, self.cin, "x")
+        if y is None:
+            y = torch.empty((n,) + self.shape + (self.cout,), dtype=torch.float32, device=x.device)
+        py = self._check_x(y, self.cout, "y")
+        self.ctx.check(_lib.soc_unet_forward(self.ctx.h, self.h, int(n), px, py))
+        return y
+
+    def backward(self, dy: torch.Tensor):
+        self.ctx.check(_lib.soc_unet_backward(self.ctx.h, self.h, self._check_x(dy, self.cout, "dy")))
+
+    def mse(self, y: torch.Tensor, t: torch.Tensor, grad: bool = True, loss: bool = True):
+        """(loss or None, dy or None)."""
+        n = y.shape[0]
+        dy = torch.empty_like(y) if grad else None
+        out = C.c_double()
+        self.ctx.check(_lib.soc_unet_mse(self.ctx.h, self.h, int(n), self._check_x(y, self.cout, "y"),
+                                         self._check_x(t, self.cout, "t"),
+                                         _dev_ptr(dy, torch.float32, "dy") if grad else None,
+                                         C.byref(out) if loss else None))
+        return (out.value if loss else None), dy
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, step: int | None = None):
+        self.step = self.step + 1 if step is None else int(step)
+        self.ctx.check(_lib.soc_unet_adam(self.ctx.h, self.h, lr, beta1, beta2, eps, self.step))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.soc_unet_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,237 @@
+"""GPU parity of the BF16 matrix-core U-Net against the FP64 oracle.
+
+The network's weights and inputs are rounded to BF16 before both sides see
+them, so the two compute the same function; what remains is the BF16
+rounding of the stored activations and gradients (relative 2^-9 per
+rounding) and FP32 summation order.  Two references:
+
+* the FP64 oracle itself;
+* a BF16-storage model: the oracle's own FP64 layer functions composed as
+  the device composes them, rounding to BF16 exactly where the device
+  stores a tensor (layer outputs after the leaky ReLU, the input, the
+  output gradient and every backward-data result).
+
+The device must agree with the storage model to a few 1e-3 (what is left
+is FP32 accumulation order and the occasional BF16 rounding that goes the
+other way), and its distance from the FP64 oracle must be no larger than
+the storage model's own distance from it, with a small margin: that
+separates layout or indexing mistakes (O(1) errors) from rounding, which
+the deep gradients amplify through cancellation."""
+import numpy as np
+import pytest
+
+from oracle import unet_oracle as U
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def soc():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1812_06632_amd import soc as m
+    return m
+
+
+def bf16_round(a):
+    """Round FP32/FP64 values to the nearest BF16 (ties to even), as FP64."""
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return (u.astype(np.uint32)).view(np.float32).astype(np.float64)
+
+
+def flat(P):
+    return np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for (w, b) in P.values()])
+
+
+def unflat(P, v):
+    out, o = {}, 0
+    for k, (w, b) in P.items():
+        out[k] = (v[o:o + w.size].reshape(w.shape), v[o + w.size:o + w.size + b.size])
+        o += w.size + b.size
+    return out
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def _slope(h):
+    return np.where(h > 0, 1.0, U.LEAK)
+
+
+def bf16_model_forward(P, x, levels):
+    """Forward pass with the device's BF16 storage points."""
+    act = lambda z: bf16_round(U.lrelu(z))
+    c = {"x": x}
+    h, skips = x, []
+    for l in range(levels):
+        c[f"e{l}a_in"] = h
+        h = act(U.conv3(h, *P[f"e{l}a"]))
+        c[f"e{l}b_in"] = h
+        h = act(U.conv3(h, *P[f"e{l}b"]))
+        if l < levels - 1:
+            skips.append(h)
+            c[f"d{l}_in"] = h
+            h = act(U.down2(h, *P[f"d{l}"]))
+    for l in range(levels - 2, -1, -1):
+        c[f"u{l}_in"] = h
+        u = act(U.up2(h, *P[f"u{l}"]))
+        h = np.concatenate([skips[l], u], axis=-1)
+        c[f"q{l}a_in"] = h
+        h = act(U.conv3(h, *P[f"q{l}a"]))
+        c[f"q{l}b_in"] = h
+        h = act(U.conv3(h, *P[f"q{l}b"]))
+    c["out_in"] = h
+    return U.conv3(h, *P["out"]), c
+
+
+def bf16_model_backward(P, c, dy, levels):
+    """Backward pass with the device's BF16 storage points: every
+    backward-data result is multiplied by the leaky ReLU slope of the layer
+    input (the sign of the stored activation) and rounded."""
+    G = {}
+    ch = [P[f"e{l}a"][0].shape[4] for l in range(levels)]
+    gy = bf16_round(dy)
+
+    def layer(name, fn, g, want_dx=True):
+        dx, dw, db = fn(c[f"{name}_in"], P[name][0], g)
+        G[name] = (dw, db)
+        return dx * _slope(c[f"{name}_in"]) if want_dx else None
+
+    g = bf16_round(layer("out", U.conv3_bwd, gy))
+    gskip = {}
+    for l in range(levels - 1):
+        g = bf16_round(layer(f"q{l}b", U.conv3_bwd, g))
+        gc = bf16_round(layer(f"q{l}a", U.conv3_bwd, g))
+        gskip[l] = gc[..., :ch[l]]
+        g = bf16_round(layer(f"u{l}", U.up2_bwd, gc[..., ch[l]:]))
+    for l in range(levels - 1, -1, -1):
+        g = bf16_round(layer(f"e{l}b", U.conv3_bwd, g))
+        g = layer(f"e{l}a", U.conv3_bwd, g, want_dx=l > 0)
+        if l > 0:
+            g = bf16_round(g)
+            g = bf16_round(layer(f"d{l - 1}", U.down2_bwd, g) + gskip[l - 1])
+    return G
+
+
+def _case(levels, base, n, shape, cin=2, cout=2, seed=0):
+    rng = np.random.default_rng(seed)
+    P = U.init_params(cin, cout, base, levels, seed)
+    P = {k: (bf16_round(w), bf16_round(0.05 * rng.standard_normal(b.shape))) for k, (w, b) in P.items()}
+    x = bf16_round(rng.standard_normal((n,) + shape + (cin,)))
+    dy = bf16_round(rng.standard_normal((n,) + shape + (cout,)))
+    return P, x, dy
+
+
+@pytest.mark.parametrize("levels,base,n,shape", [
+    (1, 16, 2, (8, 8, 8)),          # 3^3 convolutions only
+    (2, 16, 2, (8, 12, 16)),        # + down, up, concatenation; non-cubic
+    (3, 16, 2, (16, 16, 16)),       # three levels
+    (2, 32, 1, (16, 8, 8)),         # 32/64 channels: two column tiles per wave
+])
+def test_forward_and_gradients_match_oracle(soc, levels, base, n, shape):
+    P, x, dy = _case(levels, base, n, shape)
+    ctx = soc.Context(0)
+    net = soc.UNet(ctx, 2, 2, base, levels, n, shape)
+    net.set_params(flat(P).astype(np.float32))
+    assert np.array_equal(net.get_params(), flat(P).astype(np.float32))
+    xt = torch.from_numpy(x.astype(np.float32)).cuda()
+    y = net.forward(xt).cpu().numpy().astype(np.float64)
+    yo, cache = U.forward(P, x, levels)
+    ym, cm = bf16_model_forward(P, x, levels)
+    net.backward(torch.from_numpy(dy.astype(np.float32)).cuda())
+    G = unflat(P, net.get_grads().astype(np.float64))
+    Go = U.backward(P, cache, dy, levels)
+    Gm = bf16_model_backward(P, cm, dy, levels)
+    rows = [("y", rel(y, ym), rel(y, yo), rel(ym, yo))]
+    for k in P:
+        for j, part in ((0, "w"), (1, "b")):
+            rows.append((f"{k}.{part}", rel(G[k][j], Gm[k][j]), rel(G[k][j], Go[k][j]), rel(Gm[k][j], Go[k][j])))
+    print("\n  tensor       dev-vs-model  dev-vs-oracle  model-vs-oracle")
+    for name, a, b, c in rows:
+        print(f"  {name:10s}   {a:10.2e}   {b:10.2e}   {c:10.2e}")
+    bad = [(name, a, b, c) for name, a, b, c in rows if not (a < 5e-3 and b <= 2.0 * c + 5e-3)]
+    assert not bad, bad
+    assert rows[0][2] < 1e-2   # forward within 1e-2 of the FP64 oracle
+    ctx.close()
+
+
+def test_backward_is_deterministic(soc):
+    P, x, dy = _case(2, 16, 2, (8, 8, 8), seed=3)
+    ctx = soc.Context(0)
+    net = soc.UNet(ctx, 2, 2, 16, 2, 2, (8, 8, 8))
+    net.set_params(flat(P).astype(np.float32))
+    xt = torch.from_numpy(x.astype(np.float32)).cuda()
+    dyt = torch.from_numpy(dy.astype(np.float32)).cuda()
+    out = []
+    for _ in range(2):
+        y = net.forward(xt)
+        net.backward(dyt)
+        out.append((y.cpu().numpy(), net.get_grads()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    ctx.close()
+
+
+def test_mse_and_adam_step(soc):
+    """MSE value and gradient, and one Adam step, against numpy."""
+    P, x, _ = _case(2, 16, 2, (8, 8, 8), seed=4)
+    ctx = soc.Context(0)
+    net = soc.UNet(ctx, 2, 2, 16, 2, 2, (8, 8, 8))
+    p0 = flat(P).astype(np.float32)
+    net.set_params(p0)
+    xt = torch.from_numpy(x.astype(np.float32)).cuda()
+    y = net.forward(xt)
+    t = torch.randn_like(y)
+    loss, dy = net.mse(y, t)
+    d = (y - t).double().cpu().numpy()
+    assert loss == pytest.approx(float(np.mean(d * d)), rel=1e-12)
+    np.testing.assert_allclose(dy.cpu().numpy(), 2 * d / d.size, rtol=1e-6, atol=1e-12)
+    net.backward(dy)
+    g = net.get_grads().astype(np.float64)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    net.adam(lr, b1, b2, eps, step=1)
+    m, v = (1 - b1) * g, (1 - b2) * g * g
+    expect = p0 - lr * (m / (1 - b1)) / (np.sqrt(v / (1 - b2)) + eps)
+    np.testing.assert_allclose(net.get_params(), expect, rtol=2e-6, atol=2e-9)
+    ctx.close()
+
+
+def test_training_reduces_loss(soc):
+    """A few hundred Adam steps on a fixed batch fit a smooth target field."""
+    ctx = soc.Context(0)
+    shape = (16, 16, 16)
+    net = soc.UNet(ctx, 2, 2, 16, 3, 4, shape, seed=7)
+    g = torch.Generator(device="cuda").manual_seed(1)
+    x = torch.randn((4,) + shape + (2,), device="cuda", generator=g)
+    k = torch.ones(1, 1, 3, 3, 3, device="cuda") / 27.0
+    sm = torch.nn.functional.conv3d(x[..., :1].permute(0, 4, 1, 2, 3), k, padding=1).permute(0, 2, 3, 4, 1)
+    t = torch.cat([sm, 0.5 * x[..., 1:] + sm], dim=-1).contiguous()
+    losses = []
+    for step in range(300):
+        y = net.forward(x)
+        loss, dy = net.mse(y, t)
+        losses.append(loss)
+        net.backward(dy)
+        net.adam(lr=2e-3)
+    print(f"\nloss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.1 * losses[0]
+    ctx.close()
+
+
+def test_bad_shapes_rejected(soc):
+    ctx = soc.Context(0)
+    with pytest.raises(soc.SocError) as e:
+        soc.UNet(ctx, 2, 2, 24, 2, 1, (8, 8, 8))      # base not a multiple of 16
+    assert e.value.status == soc.EINVAL
+    with pytest.raises(soc.SocError):
+        soc.UNet(ctx, 2, 2, 16, 3, 1, (8, 8, 6))      # 6 not divisible by 4
+    net = soc.UNet(ctx, 2, 2, 16, 1, 1, (8, 8, 8))
+    with pytest.raises(soc.SocError):
+        net.forward(torch.zeros((2, 8, 8, 8, 2), device="cuda"))   # batch above nmax
+    with pytest.raises(ValueError):
+        net.forward(torch.zeros((1, 8, 8, 4, 2), device="cuda"))
+    ctx.close()
