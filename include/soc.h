@@ -206,6 +206,14 @@ soc_status soc_update_temperature(soc_ctx ctx, soc_grid grid, soc_temp_table tab
                                   const double *d_absorbed, const float *d_T_old, float *d_T_new,
                                   soc_temp_stats *stats);
 
+/* The same statistics (mean_T, hot5_mean_T; mean_rel_change and clamped
+ * are 0) of a given temperature field d_T (device FP32, ncells, read only)
+ * over the leaves with n > 0 -- the convergence statistics of Sect. 3.3
+ * for a field that did not come from a solve (a learned starting field).
+ * The table supplies the log-T histogram range.  Synchronises. */
+soc_status soc_temperature_stats(soc_ctx ctx, soc_grid grid, soc_temp_table table, const float *d_T,
+                                 soc_temp_stats *stats);
+
 /* ---------------------------------------------------------------- map */
 /* Emission map (Sect. 2.1.1 map kernel, pixel = smallest cell, Sect. 3.2)
  * seen along root-grid axis `axis & 3` (0..2) from the positive side, or

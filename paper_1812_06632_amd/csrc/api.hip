@@ -662,6 +662,30 @@ void soc_temp_table_destroy(soc_temp_table t)
     delete t;
 }
 
+// Statistics scratch of the temperature kernels (allocated on first use),
+// with the fine histogram cleared by kernels (no memset nodes in graphs).
+static soc_status temp_stats_buffers(soc_ctx c, TempArgs &a)
+{
+    if (!c->d_tpart) {
+        if (c->capturing) return fail(c, SOC_ESTATE, "first temperature statistics call inside a graph capture");
+        if (hipMalloc((void **)&c->d_tpart, (size_t)kTempBlocks * 8 * sizeof(double)) != hipSuccess ||
+            hipMalloc((void **)&c->d_thist, (size_t)(kTempBlocks + 1) * kHistBins * sizeof(unsigned int)) != hipSuccess ||
+            hipMalloc((void **)&c->d_tmeta, 8 * sizeof(double)) != hipSuccess ||
+            hipMalloc((void **)&c->d_tfine_n, kHistBins * sizeof(unsigned int)) != hipSuccess ||
+            hipMalloc((void **)&c->d_tfine_T, kHistBins * sizeof(double)) != hipSuccess)
+            return fail(c, SOC_ENOMEM, "temperature statistics buffers");
+    }
+    HIPCHK(c, launch_fill_i32((int32_t *)c->d_tfine_n, 0, kHistBins, c->stream));
+    HIPCHK(c, launch_fill_f64(c->d_tfine_T, 0.0, kHistBins, c->stream));
+    a.part = c->d_tpart;
+    a.hist_part = c->d_thist;
+    a.hist_total = c->d_thist + (size_t)kTempBlocks * kHistBins;
+    a.meta = c->d_tmeta;
+    a.fine_n = c->d_tfine_n;
+    a.fine_T = c->d_tfine_T;
+    return SOC_OK;
+}
+
 soc_status soc_update_temperature(soc_ctx c, soc_grid g, soc_temp_table t, const double *d_absorbed,
                                   const float *d_T_old, float *d_T_new, soc_temp_stats *stats)
 {
@@ -689,22 +713,8 @@ soc_status soc_update_temperature(soc_ctx c, soc_grid g, soc_temp_table t, const
     int64_t blocks = (g->ncells + 255) / 256;
     a.blocks = (int32_t)(blocks < kTempBlocks ? (blocks < 1 ? 1 : blocks) : kTempBlocks);
     if (stats) {
-        if (!c->d_tpart) {
-            if (hipMalloc((void **)&c->d_tpart, (size_t)kTempBlocks * 8 * sizeof(double)) != hipSuccess ||
-                hipMalloc((void **)&c->d_thist, (size_t)(kTempBlocks + 1) * kHistBins * sizeof(unsigned int)) != hipSuccess ||
-                hipMalloc((void **)&c->d_tmeta, 8 * sizeof(double)) != hipSuccess ||
-                hipMalloc((void **)&c->d_tfine_n, kHistBins * sizeof(unsigned int)) != hipSuccess ||
-                hipMalloc((void **)&c->d_tfine_T, kHistBins * sizeof(double)) != hipSuccess)
-                return fail(c, SOC_ENOMEM, "temperature statistics buffers");
-        }
-        HIPCHK(c, launch_fill_i32((int32_t *)c->d_tfine_n, 0, kHistBins, c->stream));
-        HIPCHK(c, launch_fill_f64(c->d_tfine_T, 0.0, kHistBins, c->stream));
-        a.part = c->d_tpart;
-        a.hist_part = c->d_thist;
-        a.hist_total = c->d_thist + (size_t)kTempBlocks * kHistBins;
-        a.meta = c->d_tmeta;
-        a.fine_n = c->d_tfine_n;
-        a.fine_T = c->d_tfine_T;
+        soc_status st = temp_stats_buffers(c, a);
+        if (st != SOC_OK) return st;
     }
     HIPCHK(c, launch_temp_update(a, c->stream));
     if (stats) {
@@ -717,6 +727,44 @@ soc_status soc_update_temperature(soc_ctx c, soc_grid g, soc_temp_table t, const
         stats->mean_rel_change = h[2];
         stats->clamped = (uint64_t)h[3];
     }
+    return SOC_OK;
+}
+
+soc_status soc_temperature_stats(soc_ctx c, soc_grid g, soc_temp_table t, const float *d_T, soc_temp_stats *stats)
+{
+    if (!c) return SOC_EINVAL;
+    if (!g || !t || !d_T || !stats) return fail(c, SOC_EINVAL, "NULL argument");
+    if (g->ctx != c || t->ctx != c) return fail(c, SOC_EINVAL, "grid/table belong to another context");
+    NOT_WHILE_CAPTURING(c);
+    HIPCHK(c, hipSetDevice(c->device));
+    TempArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.words = g->d_words;
+    a.ncells = g->ncells;
+    for (int i = 0; i <= kMaxLevels; ++i) a.level_offset[i] = i <= g->nlevels ? g->level_offset[i] : g->ncells;
+    a.nlevels = g->nlevels;
+    a.root_cell_cm = g->root_cell_cm;
+    a.lnG = t->d_lnG;
+    a.nT = t->nT;
+    a.lnTf = t->lnTf;
+    a.dlnT = t->dlnT;
+    a.T_floor = t->T_floor;
+    a.T_max = t->T_max;
+    a.T_new = const_cast<float *>(d_T);   // read only: the kernels never write in this mode
+    a.given = 1;
+    const int64_t blocks = (g->ncells + 255) / 256;
+    a.blocks = (int32_t)(blocks < kTempBlocks ? (blocks < 1 ? 1 : blocks) : kTempBlocks);
+    soc_status st = temp_stats_buffers(c, a);
+    if (st != SOC_OK) return st;
+    HIPCHK(c, launch_temp_update(a, c->stream));
+    HIPCHK(c, launch_temp_stats(a, c->d_tmp_out, c->stream));
+    double h[4];
+    HIPCHK(c, hipMemcpyAsync(h, c->d_tmp_out, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    stats->mean_T = h[0];
+    stats->hot5_mean_T = h[1];
+    stats->mean_rel_change = 0.0;
+    stats->clamped = 0;
     return SOC_OK;
 }
 

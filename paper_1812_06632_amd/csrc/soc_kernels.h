@@ -125,6 +125,7 @@ struct TempArgs {
     const double *absorbed;
     const float *T_old;
     float *T_new;
+    int32_t given;               // 1: T_new holds a given field; statistics only, nothing written
     int32_t blocks;              // workgroups of the update and refine passes
     // statistics (part == NULL: not requested)
     double *part;                // blocks x 8 partial sums

@@ -57,7 +57,8 @@ __device__ inline int coarse_bin(double lnT, double lnTf, double scale)
     return b < 0 ? 0 : (b >= kHistBins ? kHistBins - 1 : b);
 }
 
-// Temperature of every leaf.  With statistics requested, each workgroup
+// Temperature of every leaf (given: T_new already holds the temperatures
+// and only the statistics are taken).  With statistics requested, each workgroup
 // also writes its partial sums (count, sum T, sum |dT|/T_old, count with
 // T_old > 0, clamped) and its histogram of ln T over kHistBins coarse bins
 // (privatised in LDS) to its own row -- no global atomics, so the result
@@ -80,30 +81,34 @@ __global__ __launch_bounds__(kTempThreads) void temp_update_kernel(TempArgs a)
         const float nf = __uint_as_float(w);
         float Tout = 0.0f;
         if ((int32_t)w >= 0 && nf > 0.0f) {
-            const int L = level_index(c, a.level_offset, a.nlevels);
-            const double s = ldexp(a.root_cell_cm, -L);
-            const double y = a.absorbed[c] / ((double)nf * (s * s * s));
             double T;
             bool clamped = false;
-            if (!(y > 0.0)) {
-                T = a.T_floor;
-                clamped = true;
+            if (a.given) {
+                T = (double)a.T_new[c];
             } else {
-                const double ly = log(y);
-                if (!(ly > G0)) {
+                const int L = level_index(c, a.level_offset, a.nlevels);
+                const double s = ldexp(a.root_cell_cm, -L);
+                const double y = a.absorbed[c] / ((double)nf * (s * s * s));
+                if (!(y > 0.0)) {
                     T = a.T_floor;
                     clamped = true;
-                } else if (ly >= Gn) {
-                    T = a.T_max;
-                    clamped = true;
                 } else {
-                    int lo = 0, hi = a.nT - 1;   // lnG[lo] < ly < lnG[hi]
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (lds_lnG[mid] <= ly) lo = mid; else hi = mid;
+                    const double ly = log(y);
+                    if (!(ly > G0)) {
+                        T = a.T_floor;
+                        clamped = true;
+                    } else if (ly >= Gn) {
+                        T = a.T_max;
+                        clamped = true;
+                    } else {
+                        int lo = 0, hi = a.nT - 1;   // lnG[lo] < ly < lnG[hi]
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (lds_lnG[mid] <= ly) lo = mid; else hi = mid;
+                        }
+                        const double t = (ly - lds_lnG[lo]) / (lds_lnG[hi] - lds_lnG[lo]);
+                        T = exp(a.lnTf + a.dlnT * ((double)lo + t));
                     }
-                    const double t = (ly - lds_lnG[lo]) / (lds_lnG[hi] - lds_lnG[lo]);
-                    T = exp(a.lnTf + a.dlnT * ((double)lo + t));
                 }
             }
             Tout = (float)T;
@@ -119,10 +124,10 @@ __global__ __launch_bounds__(kTempThreads) void temp_update_kernel(TempArgs a)
                         nrel += 1.0;
                     }
                 }
-                atomicAdd(&sh_hist[coarse_bin(log(Tf), a.lnTf, hist_scale)], 1u);
+                atomicAdd(&sh_hist[coarse_bin(log(fmax(Tf, 1e-30)), a.lnTf, hist_scale)], 1u);
             }
         }
-        a.T_new[c] = Tout;
+        if (!a.given) a.T_new[c] = Tout;
     }
     if (!want) return;
     for (int o = 32; o >= 1; o >>= 1) {
@@ -227,7 +232,7 @@ __global__ __launch_bounds__(kTempThreads) void temp_stats_refine_kernel(TempArg
         const uint32_t w = a.words[c];
         if ((int32_t)w < 0 || !(__uint_as_float(w) > 0.0f)) continue;
         const double Tf = (double)a.T_new[c];
-        const double lt = log(Tf);
+        const double lt = log(fmax(Tf, 1e-30));   // a given field may hold zeros
         const int b = coarse_bin(lt, a.lnTf, hist_scale);
         if (b > tb) {
             above += Tf;

@@ -1,0 +1,101 @@
+"""Iteration driver of the plain method (Sect. 2.1.2, 3.3 of the paper).
+
+The constant sources (external field, point sources) are simulated once at
+every frequency and their absorbed energies kept; each later iteration
+re-simulates the dust emission at the current temperatures on top of the
+kept absorption and solves new temperatures.  The run stops when the
+relative change of the mean temperature, over all cells and over the
+hottest 5% of cells, falls below the tolerance between two consecutive
+iterations (the paper's two convergence statistics).
+
+Control flow only: every step is a call through the C-ABI library; the
+stopping rule compares two scalars the temperature kernel returns.
+"""
+from __future__ import annotations
+
+import time
+
+import torch
+
+from . import soc
+
+
+def converged(prev: dict, cur: dict, tol: float = 0.01) -> bool:
+    """Relative change of <T> and of the hottest-5% mean both below tol."""
+    return (abs(cur["mean_T"] - prev["mean_T"]) < tol * prev["mean_T"]
+            and abs(cur["hot5_mean_T"] - prev["hot5_mean_T"]) < tol * prev["hot5_mean_T"])
+
+
+class PlainSolver:
+    """One problem (workloads.Problem) resident on the device."""
+
+    def __init__(self, ctx: soc.Context, P, seed: int = 1, nT: int = 4096):
+        self.ctx, self.P, self.seed = ctx, P, seed
+        self.grid = soc.grid_from_workload(ctx, P.grid)
+        self.table = soc.temp_table_build(ctx, P.emit_nu, P.emit_w, P.emit_sigma_abs, P.T_floor, P.T_max, nT)
+        nc = P.grid.ncells
+        dev = "cuda"
+        self.A_const = torch.zeros(nc, dtype=torch.float64, device=dev)
+        self.A = torch.zeros(nc, dtype=torch.float64, device=dev)
+        self.T = torch.zeros(nc, dtype=torch.float32, device=dev)
+        self.T_new = torch.zeros(nc, dtype=torch.float32, device=dev)
+        self.freqs = [(float(P.nu[k]), float(P.w[k]), float(P.sigma_abs[k]), float(P.sigma_sca[k]), float(P.g[k]))
+                      for k in range(P.K)]
+
+    def constant_pass(self) -> dict:
+        """Iteration 1: the constant sources at every frequency, then the
+        temperatures they alone give (dust emission is zero at T = 0)."""
+        P = self.P
+        self.A_const.zero_()
+        for k in range(P.K):
+            soc.simulate_frequency(self.ctx, self.grid, self.freqs[k], self.A_const, I_bg=float(P.I_bg[k]),
+                                   ps_pos=P.ps_pos if len(P.ps_pos) else None,
+                                   ps_Lnu=P.ps_Lnu[:, k] if len(P.ps_pos) else None,
+                                   n_bg=P.n_bg, n_ps_pk=P.n_ps_pk if len(P.ps_pos) else 0,
+                                   seed=self.seed, iteration=1, freq_index=k)
+        return soc.update_temperature(self.ctx, self.grid, self.table, self.A_const, self.T, None, stats=True)
+
+    def set_temperature(self, T0: torch.Tensor) -> dict:
+        """Start the dust iterations from T0 instead of the constant-source
+        temperatures; returns its statistics (absorption unchanged)."""
+        self.T.copy_(T0.to(self.T.dtype).reshape(-1))
+        return self.temperature_stats(self.T)
+
+    def temperature_stats(self, T: torch.Tensor) -> dict:
+        """<T> and hottest-5% mean of a given field (library kernels)."""
+        return soc.temperature_stats(self.ctx, self.grid, self.table, T.reshape(-1))
+
+    def dust_iteration(self, it: int) -> dict:
+        """Dust emission at the current temperatures on top of the kept
+        constant-source absorption, then the temperature solve."""
+        P = self.P
+        self.A.copy_(self.A_const)
+        for k in range(P.K):
+            soc.simulate_frequency(self.ctx, self.grid, self.freqs[k], self.A, T=self.T, n_dust=P.n_dust, dust_mode=1,
+                                   seed=self.seed, iteration=it, freq_index=k)
+        s = soc.update_temperature(self.ctx, self.grid, self.table, self.A, self.T_new, self.T, stats=True)
+        self.T.copy_(self.T_new)
+        return s
+
+    def run(self, max_iter: int = 30, tol: float = 0.01, T0: torch.Tensor | None = None, log=None):
+        """Constant pass, optional start temperatures, dust iterations until
+        the stopping rule or max_iter.  Returns (history, converged_at)
+        where history holds (iteration, wall seconds since the start,
+        statistics)."""
+        torch.cuda.synchronize()
+        t0 = time.time()
+        s = self.constant_pass()
+        hist = [(1, time.time() - t0, s)]
+        if T0 is not None:
+            s = self.set_temperature(T0)
+            hist[-1] = (1, time.time() - t0, s)
+        if log:
+            log(f"iteration 1: <T> {s['mean_T']:.3f} K hot5 {s['hot5_mean_T']:.3f} K")
+        for it in range(2, max_iter + 1):
+            s = self.dust_iteration(it)
+            hist.append((it, time.time() - t0, s))
+            if log:
+                log(f"iteration {it}: <T> {s['mean_T']:.3f} K hot5 {s['hot5_mean_T']:.3f} K")
+            if converged(hist[-2][2], s, tol):
+                return hist, it
+        return hist, None

@@ -299,6 +299,18 @@ def update_temperature(ctx: Context, grid: Grid, table: TempTable, absorbed: tor
     return {k: getattr(st, k) for k, _ in _TempStats._fields_}
 
 
+_lib.soc_temperature_stats.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(_TempStats)]
+
+
+def temperature_stats(ctx: Context, grid: Grid, table: TempTable, T: torch.Tensor) -> dict:
+    """soc_temperature_stats: <T> and the hottest-5% mean of a given field."""
+    if T.numel() != grid.ncells:
+        raise ValueError("T must hold one value per cell")
+    st = _TempStats()
+    ctx.check(_lib.soc_temperature_stats(ctx.h, grid.h, table.h, _dev_ptr(T, torch.float32, "T"), C.byref(st)))
+    return {k: getattr(st, k) for k, _ in _TempStats._fields_}
+
+
 def map_shape(grid: Grid, axis: int):
     a = axis & 3
     N = [grid.nx, grid.ny, grid.nz]
