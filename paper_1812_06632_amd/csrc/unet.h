@@ -86,6 +86,12 @@ private:
     hipError_t conv_bwd_data(const Layer &L, int32_t n, const View &dy, const View &slope, const View *add,
                              const View &dx, hipStream_t s);
     hipError_t conv_wgrad(const Layer &L, int32_t n, const View &x, const View &dy, hipStream_t s);
+    struct WgradPlan {
+        int64_t chunks = 0;
+        uint32_t chunk = 0;   // bricks (3^3 layers) or rows per chunk
+        bool bricks = false;
+    };
+    WgradPlan plan_wgrad(const Layer &L, int32_t n) const;
     int64_t positions(int level, int32_t n) const;
 
     std::vector<Layer> layers_;

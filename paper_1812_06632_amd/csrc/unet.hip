@@ -184,6 +184,126 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
     }
 }
 
+// 3^3 convolutions (stride 1, padding 1) -- most of the network's work --
+// with the input staged in LDS: a workgroup owns a 4 x 8 x 8 brick of
+// output positions (256 rows); for every chunk of 32 input channels it
+// loads the 6 x 10 x 10 halo of the brick once (zero outside the volume)
+// and all 27 taps read their A fragments from LDS.  Each wave computes two
+// 32-row tiles (half z-planes of the brick) x 32*NT columns, so every B
+// fragment, shared by the four waves through L1, feeds two MFMAs.
+constexpr int kBZ = 4, kBY = 8, kBX = 8;
+constexpr int kHZ = kBZ + 2, kHY = kBY + 2, kHX = kBX + 2;
+constexpr int kHalo = kHZ * kHY * kHX;   // 600 positions
+constexpr int kCC = 32;                  // input channels per LDS chunk
+constexpr int kHS = kCC + 8;             // padded position stride in the halo (elements)
+
+template <int NT>
+__global__ __launch_bounds__(256) void conv3_lds_kernel(ConvArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t halo[kHalo * kHS];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int half = lane >> 5;
+    const int r = lane & 31;
+    const int nbx = (a.mx + kBX - 1) / kBX, nby = (a.my + kBY - 1) / kBY, nbz = (a.mz + kBZ - 1) / kBZ;
+    int bid = blockIdx.x;
+    const int bxi = bid % nbx;
+    bid /= nbx;
+    const int byi = bid % nby;
+    bid /= nby;
+    const int bzi = bid % nbz;
+    const int b = bid / nbz;
+    const int z0 = bzi * kBZ, y0 = byi * kBY, x0 = bxi * kBX;
+    const int n0 = blockIdx.y * 32 * NT;
+    const int K = 27 * a.cin;
+
+    // this lane's two rows (row tiles 2 wave and 2 wave + 1 of the brick)
+    int lz[2], ly[2];
+    const int lx = r & 7;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int rt = 2 * wave + t;
+        lz[t] = rt >> 1;
+        ly[t] = (rt & 1) * 4 + (r >> 3);
+    }
+    const uint16_t *wrow[NT];
+#pragma unroll
+    for (int s = 0; s < NT; ++s) wrow[s] = a.w + (size_t)(n0 + 32 * s + r) * K + 8 * half;
+
+    f32x16_t acc[2][NT];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int s = 0; s < NT; ++s)
+            for (int v = 0; v < 16; ++v) acc[t][s][v] = 0.0f;
+
+    for (int c0 = 0; c0 < a.cin; c0 += kCC) {
+        const int cc = min(kCC, a.cin - c0);   // 16 or 32
+        const int groups = cc >> 3;
+        __syncthreads();   // the previous chunk has been consumed
+        for (int i = tid; i < kHalo * groups; i += 256) {
+            const int pos = i / groups, g = i - pos * groups;
+            const int hx = pos % kHX, hy = (pos / kHX) % kHY, hz = pos / (kHX * kHY);
+            const int zz = z0 + hz - 1, yy = y0 + hy - 1, xx = x0 + hx - 1;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (zz >= 0 && zz < a.iz && yy >= 0 && yy < a.iy && xx >= 0 && xx < a.ix)
+                v = *reinterpret_cast<const u32x4 *>(
+                    a.x + (size_t)(((b * a.iz + zz) * a.iy + yy) * a.ix + xx) * a.x_cs + a.x_co + c0 + 8 * g);
+            *reinterpret_cast<u32x4 *>(&halo[pos * kHS + 8 * g]) = v;
+        }
+        __syncthreads();
+        int tap = 0;
+        for (int tz = 0; tz < 3; ++tz)
+            for (int ty = 0; ty < 3; ++ty)
+                for (int tx = 0; tx < 3; ++tx, ++tap) {
+                    const int h0 = ((lz[0] + tz) * kHY + ly[0] + ty) * kHX + lx + tx;
+                    const int h1 = ((lz[1] + tz) * kHY + ly[1] + ty) * kHX + lx + tx;
+                    const int kb = tap * a.cin + c0;
+                    for (int cg = 0; cg < cc; cg += 16) {
+                        const bf16x8_t A0 =
+                            __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u32x4 *>(&halo[h0 * kHS + cg + 8 * half]));
+                        const bf16x8_t A1 =
+                            __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u32x4 *>(&halo[h1 * kHS + cg + 8 * half]));
+#pragma unroll
+                        for (int s = 0; s < NT; ++s) {
+                            const bf16x8_t B = ld8(wrow[s] + kb + cg);
+                            acc[0][s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, B, acc[0][s], 0, 0, 0);
+                            acc[1][s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, B, acc[1][s], 0, 0, 0);
+                        }
+                    }
+                }
+    }
+
+    // epilogue: lane holds column n0 + 32 s + r and, in row tile t, the rows
+    // 8 (v / 4) + 4 half + v % 4 (= 8 y-rows of 8 x in brick order)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int rt = 2 * wave + t;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int row = 8 * (v >> 2) + 4 * half + (v & 3);   // 0..31 within the tile
+            const int pz = z0 + (rt >> 1), py = y0 + (rt & 1) * 4 + (row >> 3), px = x0 + (row & 7);
+            if (pz >= a.mz || py >= a.my || px >= a.mx) continue;
+            const size_t op = (size_t)((b * a.oz + pz) * a.oy + py) * a.ox + px;
+#pragma unroll
+            for (int s = 0; s < NT; ++s) {
+                const int n = n0 + 32 * s + r;
+                if (n >= a.cout) continue;
+                float val = acc[t][s][v];
+                if (a.bias) val += a.bias[n];
+                if (a.act) val = val > 0.0f ? val : kLeak * val;
+                if (a.slope && !(bf2f(a.slope[op * a.sl_cs + a.sl_co + n]) > 0.0f)) val *= kLeak;
+                if (a.add) val += bf2f(a.add[op * a.ad_cs + a.ad_co + n]);
+                if (a.y)
+                    a.y[op * a.y_cs + a.y_co + n] = f2bf(val);
+                else
+                    a.yf[op * a.yf_cs + n] = val;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ weight gradient
 struct WgradArgs {
     const uint16_t *x;
@@ -284,14 +404,133 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
     }
 }
 
-// Sum the chunk partials in chunk order: g[e] = sum_c part[c][e].
-__global__ void sum_chunks_kernel(const float *part, int32_t chunks, int64_t n, float *g)
+// Weight gradients of 3^3 convolutions, all 27 taps per workgroup.  The
+// workgroup owns a 32 x 32 (input, output channel) tile and a chunk of
+// 2 x 8 x 8 position bricks; per brick it stages dy (channel-major,
+// [o][z][y][x]) and the 4 x 10 x 10 input halo (channel-major, rows
+// padded to 16) in LDS.  The MFMA reduction runs over positions: one
+// K-step is 16 positions (two x-rows of 8), so both operands are 16-byte
+// LDS reads along x.  Wave w takes the taps with tz = w; the three x-taps
+// of a (tz, ty) pair come from two aligned reads of the halo row shifted by
+// 0, 1 or 2 elements in registers (v_alignbyte).
+constexpr int kGZ = 2, kGY = 8, kGX = 8;                 // brick
+constexpr int kGHZ = kGZ + 2, kGHY = kGY + 2, kGHX = 16;  // halo (x padded to 16)
+
+__global__ __launch_bounds__(192) void wgrad3_kernel(WgradArgs a)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
+    __shared__ __attribute__((aligned(16))) uint16_t xT[32 * kGHZ * kGHY * kGHX];   // 40 KB
+    __shared__ __attribute__((aligned(16))) uint16_t dT[32 * kGZ * kGY * kGX];      // 8 KB
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int tz = tid >> 6;   // wave = z-tap
+    const int half = lane >> 5;
+    const int r = lane & 31;
+    const int ntile_o = (a.cout + 31) / 32;
+    const int i0 = (blockIdx.y / ntile_o) * 32;
+    const int o0 = (blockIdx.y % ntile_o) * 32;
+    const int nbx = (a.mx + kGX - 1) / kGX, nby = (a.my + kGY - 1) / kGY, nbz = (a.mz + kGZ - 1) / kGZ;
+    const uint32_t nb = (uint32_t)a.batch * nbz * nby * nbx;
+    const uint32_t b_begin = blockIdx.x * a.chunk, b_end = min(b_begin + a.chunk, nb);
+
+    for (int e = tid; e < 32 * kGHZ * kGHY * kGHX; e += 192) xT[e] = 0;   // pad columns stay zero
+
+    f32x16_t acc[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+        for (int v = 0; v < 16; ++v) acc[q][v] = 0.0f;
+
+    for (uint32_t bi = b_begin; bi < b_end; ++bi) {
+        uint32_t t = bi;
+        const int bxi = t % nbx;
+        t /= nbx;
+        const int byi = t % nby;
+        t /= nby;
+        const int bzi = t % nbz;
+        const int b = t / nbz;
+        const int z0 = bzi * kGZ, y0 = byi * kGY, x0 = bxi * kGX;
+        __syncthreads();   // previous brick consumed (and the pad zeroing done)
+        for (int e = tid; e < kGZ * kGY * kGX * 4; e += 192) {
+            const int pos = e >> 2, g = e & 3;
+            const int lx = pos & 7, ly = (pos >> 3) & 7, lz = pos >> 6;
+            const int zz = z0 + lz, yy = y0 + ly, xx = x0 + lx;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (zz < a.mz && yy < a.my && xx < a.mx && o0 + 8 * g < a.dy_c)
+                v = *reinterpret_cast<const u32x4 *>(
+                    a.dy + (size_t)(((b * a.oz + zz) * a.oy + yy) * a.ox + xx) * a.dy_cs + a.dy_co + o0 + 8 * g);
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                dT[(8 * g + j) * (kGZ * kGY * kGX) + pos] = (uint16_t)(v[j >> 1] >> (16 * (j & 1)));
+        }
+        for (int e = tid; e < kGHZ * kGHY * 10 * 4; e += 192) {
+            const int pos = e >> 2, g = e & 3;
+            const int hx = pos % 10, hy = (pos / 10) % kGHY, hz = pos / (10 * kGHY);
+            const int zz = z0 + hz - 1, yy = y0 + hy - 1, xx = x0 + hx - 1;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (zz >= 0 && zz < a.iz && yy >= 0 && yy < a.iy && xx >= 0 && xx < a.ix && i0 + 8 * g < a.x_c)
+                v = *reinterpret_cast<const u32x4 *>(
+                    a.x + (size_t)(((b * a.iz + zz) * a.iy + yy) * a.ix + xx) * a.x_cs + a.x_co + i0 + 8 * g);
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                xT[(((8 * g + j) * kGHZ + hz) * kGHY + hy) * kGHX + hx] = (uint16_t)(v[j >> 1] >> (16 * (j & 1)));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int lz = 0; lz < kGZ; ++lz)
+#pragma unroll
+            for (int m = 0; m < kGY / 2; ++m) {
+                const int ly = 2 * m + half;   // this lane's x-row of the K-step
+                const u32x4 bv = *reinterpret_cast<const u32x4 *>(&dT[r * (kGZ * kGY * kGX) + (lz * kGY + ly) * kGX]);
+                const bf16x8_t B = __builtin_bit_cast(bf16x8_t, bv);
+#pragma unroll
+                for (int ty = 0; ty < 3; ++ty) {
+                    const uint16_t *row = &xT[((r * kGHZ + lz + tz) * kGHY + ly + ty) * kGHX];
+                    const u32x4 c0 = *reinterpret_cast<const u32x4 *>(row);
+                    const u32x4 c1 = *reinterpret_cast<const u32x4 *>(row + 8);
+                    const u32x4 s1 = {__builtin_amdgcn_alignbyte(c0[1], c0[0], 2), __builtin_amdgcn_alignbyte(c0[2], c0[1], 2),
+                                      __builtin_amdgcn_alignbyte(c0[3], c0[2], 2), __builtin_amdgcn_alignbyte(c1[0], c0[3], 2)};
+                    const u32x4 s2 = {c0[1], c0[2], c0[3], c1[0]};
+                    acc[3 * ty + 0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, c0), B,
+                                                                              acc[3 * ty + 0], 0, 0, 0);
+                    acc[3 * ty + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, s1), B,
+                                                                              acc[3 * ty + 1], 0, 0, 0);
+                    acc[3 * ty + 2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, s2), B,
+                                                                              acc[3 * ty + 2], 0, 0, 0);
+                }
+            }
+    }
+    // partials of this chunk: rows = input channels, columns = output channels
+    float *out = a.part + (size_t)blockIdx.x * 27 * a.cin * a.cout;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const int tap = tz * 9 + q;
+        for (int v = 0; v < 16; ++v) {
+            const int i = i0 + 8 * (v >> 2) + 4 * half + (v & 3);
+            const int o = o0 + r;
+            if (i < a.cin && o < a.cout) out[((size_t)tap * a.cin + i) * a.cout + o] = acc[q][v];
+        }
+    }
+}
+
+// Sum the chunk partials: g[e] = sum_c part[c][e].  A workgroup takes 32
+// consecutive elements; its 8 chunk lanes sum the chunks c = lane mod 8 and
+// are then added in lane order, so the result does not depend on timing.
+constexpr int kSumElems = 32, kSumLanes = 8;
+
+__global__ __launch_bounds__(256) void sum_chunks_kernel(const float *part, int32_t chunks, int64_t n, float *g)
+{
+    __shared__ float red[kSumLanes][kSumElems + 1];
+    const int ex = threadIdx.x % kSumElems, cl = threadIdx.x / kSumElems;
+    const int64_t e = (int64_t)blockIdx.x * kSumElems + ex;
     float s = 0.0f;
-    for (int c = 0; c < chunks; ++c) s += part[(size_t)c * n + e];
-    g[e] = s;
+    if (e < n)
+        for (int c = cl; c < chunks; c += kSumLanes) s += part[(size_t)c * n + e];
+    red[cl][ex] = s;
+    __syncthreads();
+    if (cl == 0 && e < n) {
+        float t = 0.0f;
+        for (int k = 0; k < kSumLanes; ++k) t += red[k][ex];
+        g[e] = t;
+    }
 }
 
 // Column sums of a channels-last BF16 view over npos positions (bias
@@ -460,6 +699,35 @@ int64_t Net::positions(int level, int32_t n) const
     return (int64_t)n * (nz_ >> level) * (ny_ >> level) * (nx_ >> level);
 }
 
+// Split-K plan of a layer's weight gradient for a batch of n: 3^3 layers
+// reduce bricks of 2 x 8 x 8 positions with all 27 taps per workgroup
+// (about 768 workgroups in all); the other kinds reduce rows per tap with
+// the generic kernel (about 4096 workgroups).  chunks x taps x cin x cout
+// partial sums are written.
+Net::WgradPlan Net::plan_wgrad(const Layer &L, int32_t n) const
+{
+    WgradPlan p;
+    const int64_t ctiles = (int64_t)((L.cin + 31) / 32) * ((L.cout + 31) / 32);
+    if (L.kind == Layer::CONV3) {
+        const int l = L.level_out;
+        const int64_t nb = (int64_t)n * (((nz_ >> l) + kGZ - 1) / kGZ) * (((ny_ >> l) + kGY - 1) / kGY) *
+                           (((nx_ >> l) + kGX - 1) / kGX);
+        int64_t chunks = std::min<int64_t>(nb, std::max<int64_t>(1, 768 / ctiles));
+        p.chunk = (uint32_t)((nb + chunks - 1) / chunks);
+        p.chunks = (nb + p.chunk - 1) / p.chunk;
+        p.bricks = true;
+    } else {
+        const int64_t rows = L.kind == Layer::UP2 ? positions(L.level_in, n) : positions(L.level_out, n);
+        const int64_t tiles = ctiles * taps_of(L.kind);
+        int64_t chunks = std::min<int64_t>((rows + 1023) / 1024, std::max<int64_t>(1, 4096 / tiles));
+        uint32_t chunk = (uint32_t)((rows + chunks - 1) / chunks);
+        p.chunk = (chunk + 255) / 256 * 256;
+        p.chunks = (rows + p.chunk - 1) / p.chunk;
+        p.bricks = false;
+    }
+    return p;
+}
+
 Net::Status Net::create(int dev, int32_t cin, int32_t cout, int32_t base, int32_t levels, int32_t nmax, int32_t nz,
                         int32_t ny, int32_t nx, uint64_t seed, hipStream_t s)
 {
@@ -569,13 +837,9 @@ Net::Status Net::create(int dev, int32_t cin, int32_t cout, int32_t base, int32_
     }
     ALLOC(hbot_, uint16_t, positions(levels - 1, nmax) * ch[levels - 1]);
     // split-K partials: the largest chunks x taps x cin x cout of any layer
+    // (chunk counts do not decrease with the batch, so nmax bounds them)
     cap_part_ = 0;
-    for (auto &L : layers_) {
-        const int64_t rows = L.kind == Layer::UP2 ? positions(L.level_in, nmax) : positions(L.level_out, nmax);
-        const int64_t tiles = (int64_t)((L.cin + 31) / 32) * ((L.cout + 31) / 32) * taps_of(L.kind);
-        int64_t chunks = std::min<int64_t>((rows + 1023) / 1024, std::max<int64_t>(1, 4096 / tiles));
-        cap_part_ = std::max(cap_part_, chunks * L.nw);
-    }
+    for (auto &L : layers_) cap_part_ = std::max(cap_part_, plan_wgrad(L, nmax).chunks * L.nw);
     ALLOC(d_part_, float, std::max<int64_t>(cap_part_, kColBlocks * 4096));
 #undef ALLOC
 
@@ -630,6 +894,16 @@ static hipError_t launch_conv(const ConvArgs &a, hipStream_t s)
 {
     const uint32_t mtot = (uint32_t)a.batch * a.mz * a.my * a.mx;
     const int nt = a.npad % 64 == 0 ? 2 : 1;
+    if (a.k == 3 && a.s_in == 1 && a.pad == 1 && a.nph == 1 && a.s_out == 1 && a.cin % 16 == 0) {
+        const unsigned bricks = (unsigned)a.batch * ((a.mz + kBZ - 1) / kBZ) * ((a.my + kBY - 1) / kBY) *
+                                ((a.mx + kBX - 1) / kBX);
+        const dim3 grid(bricks, a.npad / (32 * nt), 1);
+        if (nt == 2)
+            hipLaunchKernelGGL(conv3_lds_kernel<2>, grid, dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL(conv3_lds_kernel<1>, grid, dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     const dim3 grid((mtot + 127) / 128, a.npad / (32 * nt), a.nph);
     if (nt == 2)
         hipLaunchKernelGGL(conv_kernel<2>, grid, dim3(256), 0, s, a);
@@ -755,24 +1029,22 @@ hipError_t Net::conv_wgrad(const Layer &L, int32_t n, const View &x, const View 
     a.cin = L.cin;
     a.cout = L.cout;
     const int slots = taps_of(L.kind);
-    const uint32_t rows = (uint32_t)n * a.mz * a.my * a.mx;
-    const int64_t tiles = (int64_t)((L.cin + 31) / 32) * ((L.cout + 31) / 32) * slots;
-    int64_t chunks = std::min<int64_t>((rows + 1023) / 1024, std::max<int64_t>(1, 4096 / tiles));
-    uint32_t chunk = (uint32_t)((rows + chunks - 1) / chunks);
-    chunk = (chunk + 255) / 256 * 256;
-    chunks = (rows + chunk - 1) / chunk;
-    if (chunks * L.nw > std::max<int64_t>(cap_part_, kColBlocks * 4096)) return hipErrorInvalidValue;
-    a.chunk = chunk;
+    const WgradPlan p = plan_wgrad(L, n);
+    if (p.chunks * L.nw > std::max<int64_t>(cap_part_, kColBlocks * 4096)) return hipErrorInvalidValue;
+    a.chunk = p.chunk;
     a.part = d_part_;
-    dim3 grid((unsigned)chunks, (unsigned)(((L.cin + 31) / 32) * ((L.cout + 31) / 32)), (unsigned)slots);
-    hipLaunchKernelGGL(wgrad_kernel, grid, dim3(256), 0, s, a);
-    hipLaunchKernelGGL(sum_chunks_kernel, dim3(nblk(L.nw)), dim3(256), 0, s, (const float *)d_part_, (int32_t)chunks,
-                       L.nw, d_grads_ + L.w_off);
+    const unsigned ctiles = (unsigned)(((L.cin + 31) / 32) * ((L.cout + 31) / 32));
+    if (p.bricks)
+        hipLaunchKernelGGL(wgrad3_kernel, dim3((unsigned)p.chunks, ctiles, 1), dim3(192), 0, s, a);
+    else
+        hipLaunchKernelGGL(wgrad_kernel, dim3((unsigned)p.chunks, ctiles, (unsigned)slots), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(sum_chunks_kernel, dim3(nblk(L.nw, kSumElems)), dim3(256), 0, s, (const float *)d_part_,
+                       (int32_t)p.chunks, L.nw, d_grads_ + L.w_off);
     // bias gradient: column sums of dy over the output positions
     const int64_t npos = positions(lout, n);
     hipLaunchKernelGGL(colsum_kernel, dim3(kColBlocks), dim3(256), 0, s, (const uint16_t *)dy.p, dy.cs, dy.co, L.cout,
                        (uint32_t)npos, d_part_);
-    hipLaunchKernelGGL(sum_chunks_kernel, dim3(nblk(L.cout)), dim3(256), 0, s, (const float *)d_part_,
+    hipLaunchKernelGGL(sum_chunks_kernel, dim3(nblk(L.cout, kSumElems)), dim3(256), 0, s, (const float *)d_part_,
                        (int32_t)kColBlocks, (int64_t)L.cout, d_grads_ + L.b_off);
     return hipGetLastError();
 }

@@ -11,12 +11,14 @@ rounding) and FP32 summation order.  Two references:
   stores a tensor (layer outputs after the leaky ReLU, the input, the
   output gradient and every backward-data result).
 
-The device must agree with the storage model to a few 1e-3 (what is left
-is FP32 accumulation order and the occasional BF16 rounding that goes the
-other way), and its distance from the FP64 oracle must be no larger than
-the storage model's own distance from it, with a small margin: that
-separates layout or indexing mistakes (O(1) errors) from rounding, which
-the deep gradients amplify through cancellation."""
+Device and storage model share every rounding point but not the FP32
+summation order, so a few roundings go to the other BF16 neighbour and
+the deep gradients amplify those differences through cancellation just as
+they amplify the storage error itself.  The device must therefore be no
+farther from the storage model than the model is from the FP64 oracle,
+and its own distance from the oracle at most twice the model's (plus
+5e-3 for tensors the model reproduces almost exactly): a layout or
+indexing mistake gives O(1) errors and fails both."""
 import numpy as np
 import pytest
 
@@ -131,6 +133,7 @@ def _case(levels, base, n, shape, cin=2, cout=2, seed=0):
     (2, 16, 2, (8, 12, 16)),        # + down, up, concatenation; non-cubic
     (3, 16, 2, (16, 16, 16)),       # three levels
     (2, 32, 1, (16, 8, 8)),         # 32/64 channels: two column tiles per wave
+    (1, 16, 1, (64, 64, 32)),       # enough position bricks that a weight-gradient workgroup reduces several
 ])
 def test_forward_and_gradients_match_oracle(soc, levels, base, n, shape):
     P, x, dy = _case(levels, base, n, shape)
@@ -153,7 +156,7 @@ def test_forward_and_gradients_match_oracle(soc, levels, base, n, shape):
     print("\n  tensor       dev-vs-model  dev-vs-oracle  model-vs-oracle")
     for name, a, b, c in rows:
         print(f"  {name:10s}   {a:10.2e}   {b:10.2e}   {c:10.2e}")
-    bad = [(name, a, b, c) for name, a, b, c in rows if not (a < 5e-3 and b <= 2.0 * c + 5e-3)]
+    bad = [(name, a, b, c) for name, a, b, c in rows if not (a <= c + 5e-3 and b <= 2.0 * c + 5e-3)]
     assert not bad, bad
     assert rows[0][2] < 1e-2   # forward within 1e-2 of the FP64 oracle
     ctx.close()
