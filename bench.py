@@ -115,6 +115,127 @@ def ceilings(soc, torch, ncells):
     ctx.close()
 
 
+BF16_MFMA_PEAK_TFLOPS = 2500.0   # dense BF16 matrix-core peak of MI355X
+
+
+def unet_step(args, soc, torch):
+    """Forward, backward and Adam of the U-Net at its production shape,
+    timed with events on the library's stream; flops are the real
+    (unpadded) multiply-adds x 2, backward counted as twice the forward."""
+    ctx = soc.Context(0)
+    n, S = args.unet_batch, 64
+    net = soc.UNet(ctx, 2, 2, 32, 4, n, (S, S, S), seed=1)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn((n, S, S, S, 2), device="cuda", generator=g)
+    t = torch.randn((n, S, S, S, 2), device="cuda", generator=g)
+    y = net.forward(x)
+    _, dy = net.mse(y, t, loss=False)
+    net.backward(dy)
+    net.adam()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    R = max(args.steps, 1) * 3
+    stream = ctx.stream
+    ev[0].record(stream)
+    for _ in range(R):
+        net.forward(x, y)
+    ev[1].record(stream)
+    for _ in range(R):
+        net.backward(dy)
+    ev[2].record(stream)
+    for _ in range(R):
+        net.adam()
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    tf, tb, ta = (ev[i].elapsed_time(ev[i + 1]) / R for i in range(3))
+    f = net.flops(n)
+    line = {"kind": "unet_step", "shape": f"{n} x {S}^3", "base": 32, "levels": 4, "params": net.param_count,
+            "gflop_forward": f / 1e9, "ms_forward": tf, "ms_backward": tb, "ms_adam": ta,
+            "ms_step": tf + tb + ta, "tflops_forward": f / tf / 1e9, "tflops_backward": 2 * f / tb / 1e9,
+            "tflops_step": 3 * f / (tf + tb + ta) / 1e9,
+            "frac_of_bf16_peak_step": 3 * f / (tf + tb + ta) / 1e9 / BF16_MFMA_PEAK_TFLOPS}
+    print(json.dumps(line), flush=True)
+    net.close()
+    ctx.close()
+
+
+def surrogate_gain(args, soc, torch, W):
+    """Time to the 1% stopping rule on an optically thick lognormal cloud
+    (the benchmark's grid, frequencies and package counts with
+    sigma_ln = --target-sigma and mean tau_V = --target-tau, where dust
+    self-heating needs several iterations) from three starts -- the plain
+    method (constant-source temperatures), the U-Net prediction, and a
+    constant temperature (control: shows what the learning adds) -- and the
+    error of the stopped field against a long plain reference (mean of 8
+    iterations after 12)."""
+    from paper_1812_06632_amd.driver import PlainSolver
+    from paper_1812_06632_amd.surrogate import Surrogate, make_dataset
+    ctx = soc.Context(0)
+    t0 = time.time()
+    X, Y = make_dataset(ctx, args.train_clouds, seed=11, n=64, S=64, K=32, packages=200_000, log=log)
+    t_data = time.time() - t0
+    sur = Surrogate(ctx, S=64, base=32, levels=4, batch=4, seed=3)
+    t0 = time.time()
+    losses = sur.fit(X, Y, steps=args.train_steps, lr=5e-4, log=log)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    P = W.lognormal_problem(n=args.n, K=args.freqs, sigma_ln=args.target_sigma, tau_v_mean=args.target_tau,
+                            packages_per_freq=args.packages)
+    ref = PlainSolver(ctx, P, seed=7)
+    ref.constant_pass()
+    burn, avg = 12, 8
+    acc = torch.zeros_like(ref.T, dtype=torch.float64)
+    for it in range(2, burn + avg + 2):
+        ref.dust_iteration(it)
+        if it > burn + 1:
+            acc += ref.T.double()
+    T_ref = acc / avg
+    dense = torch.from_numpy(P.grid.density()).cuda() > 0
+    Tr = T_ref[dense]
+    hot = Tr >= torch.quantile(Tr.float(), 0.95).double()
+    log(f"reference: <T> {Tr.mean().item():.3f} K, hottest 5% {Tr[hot].mean().item():.3f} K")
+
+    def err(T):
+        r = (T.double()[dense] - Tr).abs() / Tr
+        return r.mean().item(), r[hot].mean().item()
+
+    out = {}
+    T_const = float(10.0 ** sur.ymean)
+    for label in ("plain", "surrogate", "constant_start"):
+        S = PlainSolver(ctx, P, seed=1)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        T0 = None
+        if label == "surrogate":
+            T0 = sur.predict_T(P)
+        elif label == "constant_start":
+            T0 = torch.where(dense, torch.full_like(S.T, T_const), torch.zeros_like(S.T))
+        t_start = time.time() - t0
+        e0 = err(T0) if T0 is not None else None
+        hist, at = S.run(max_iter=args.max_iter, T0=T0, log=log)
+        stop = at if at is not None else hist[-1][0]
+        e = err(S.T)
+        out[label] = {"iterations": stop, "converged": at is not None, "wall_s": t_start + hist[stop - 1][1],
+                      "start_s": t_start, "start_err_all": e0[0] if e0 else None,
+                      "start_err_hot5": e0[1] if e0 else None, "err_all": e[0], "err_hot5": e[1]}
+        log(f"{label}: stopped at iteration {stop} after {out[label]['wall_s']:.3f}s, "
+            f"mean |T - T_ref|/T_ref {e[0]:.4f} (hottest 5%: {e[1]:.4f})")
+    line = {"kind": "surrogate_gain",
+            "workload": f"lognormal {args.n}^3, sigma_ln {args.target_sigma}, mean tau_V {args.target_tau}, "
+                        f"{args.freqs} frequencies, {args.packages} packages/frequency",
+            "training": {"clouds": args.train_clouds, "cells": "64^3", "frequencies": 32, "tau_V": "log-U(2, 100)",
+                         "packages_per_frequency": 200_000, "steps": args.train_steps, "batch": 4,
+                         "data_s": t_data, "train_s": t_train, "final_loss": losses[-1][1] if losses else None,
+                         "params": sur.net.param_count},
+            "reference": {"burn_in": burn, "averaged": avg, "mean_T": Tr.mean().item(),
+                          "hot5_mean_T": Tr[hot].mean().item()},
+            "runs": out,
+            "speedup_vs_plain": out["plain"]["wall_s"] / out["surrogate"]["wall_s"]}
+    print(json.dumps(line), flush=True)
+    sur.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +249,15 @@ def main():
     ap.add_argument("--no-converge", action="store_true")
     ap.add_argument("--ceilings", action="store_true",
                     help="only run the device micro-benchmarks (one JSON line each) and exit")
+    ap.add_argument("--surrogate", action="store_true",
+                    help="only run the learned-start gain test (one JSON line) and exit")
+    ap.add_argument("--unet", action="store_true",
+                    help="only time the U-Net training step (64^3, base 32, 4 levels; one JSON line) and exit")
+    ap.add_argument("--unet-batch", type=int, default=4)
+    ap.add_argument("--train-clouds", type=int, default=96)
+    ap.add_argument("--target-sigma", type=float, default=1.5)
+    ap.add_argument("--target-tau", type=float, default=50.0)
+    ap.add_argument("--train-steps", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the design notes describe how the "
@@ -142,51 +272,40 @@ def main():
     if args.ceilings:
         ceilings(soc, torch, args.n ** 3)
         return
+    if args.surrogate:
+        surrogate_gain(args, soc, torch, W)
+        return
+    if args.unet:
+        unet_step(args, soc, torch)
+        return
+
+    from paper_1812_06632_amd.driver import PlainSolver, converged
 
     t_setup = time.time()
     P = W.lognormal_problem(n=args.n, K=args.freqs, packages_per_freq=args.packages)
     K = P.K
     ctx = soc.Context(0)
     ctx.set_option("timing", 1)
-    grid = soc.grid_from_workload(ctx, P.grid)
-    table = soc.temp_table_build(ctx, P.emit_nu, P.emit_w, P.emit_sigma_abs, P.T_floor, P.T_max, 4096)
+    S = PlainSolver(ctx, P, seed=1)
     nc = P.grid.ncells
-    A_const = torch.zeros(nc, dtype=torch.float64, device="cuda")
-    A = torch.zeros(nc, dtype=torch.float64, device="cuda")
-    T = torch.zeros(nc, dtype=torch.float32, device="cuda")
-    T_new = torch.zeros(nc, dtype=torch.float32, device="cuda")
-    freqs = [(float(P.nu[k]), float(P.w[k]), float(P.sigma_abs[k]), float(P.sigma_sca[k]), float(P.g[k]))
-             for k in range(K)]
+    freqs = S.freqs
     log(f"setup {time.time() - t_setup:.1f}s: {args.n}^3 cells, {K} frequencies, {args.packages} packages/freq")
 
     # ---- iteration 1: constant sources
     torch.cuda.synchronize()
     t0 = time.time()
-    for k in range(K):
-        soc.simulate_frequency(ctx, grid, freqs[k], A_const, I_bg=float(P.I_bg[k]), ps_pos=P.ps_pos,
-                               ps_Lnu=P.ps_Lnu[:, k], n_bg=P.n_bg, n_ps_pk=P.n_ps_pk, seed=1, iteration=1,
-                               freq_index=k)
-    tst = soc.update_temperature(ctx, grid, table, A_const, T, None, stats=True)
+    tst = S.constant_pass()
     torch.cuda.synchronize()
     t_const = time.time() - t0
     st_const = ctx.read_stats(reset=True)
     ctx.mc_timing(reset=True)
     log(f"iteration 1 (constant sources): {t_const:.3f}s, <T> {tst['mean_T']:.2f} K, hot5 {tst['hot5_mean_T']:.2f} K")
-    history = [(1, t_const, tst["mean_T"], tst["hot5_mean_T"])]
-
-    def step(it):
-        A.copy_(A_const)
-        for k in range(K):
-            soc.simulate_frequency(ctx, grid, freqs[k], A, T=T, n_dust=P.n_dust, dust_mode=1, seed=1,
-                                   iteration=it, freq_index=k)
-        s = soc.update_temperature(ctx, grid, table, A, T_new, T, stats=True)
-        T.copy_(T_new)
-        return s
+    history = [(1, tst)]
 
     it = 2
     for _ in range(args.warmup):
-        s = step(it)
-        history.append((it, None, s["mean_T"], s["hot5_mean_T"]))
+        s = S.dust_iteration(it)
+        history.append((it, s))
         log(f"warmup iteration {it}: <T> {s['mean_T']:.3f} K hot5 {s['hot5_mean_T']:.3f} K")
         it += 1
     ctx.read_stats(reset=True)
@@ -194,8 +313,8 @@ def main():
     torch.cuda.synchronize()
     t0 = time.time()
     for _ in range(args.steps):
-        s = step(it)
-        history.append((it, None, s["mean_T"], s["hot5_mean_T"]))
+        s = S.dust_iteration(it)
+        history.append((it, s))
         log(f"timed iteration {it}: <T> {s['mean_T']:.3f} K hot5 {s['hot5_mean_T']:.3f} K")
         it += 1
     torch.cuda.synchronize()
@@ -212,27 +331,27 @@ def main():
     atomic_ceiling, copy_gbs = device_ceilings(soc, ctx, torch, nc)
     log(f"ceilings: random FP64 atomics {atomic_ceiling:.3e}/s over {nc} doubles, copy {copy_gbs:.0f} GB/s")
 
-    # ---- continue to the 1% stopping rule (plain method)
+    # ---- the 1% stopping rule (plain method): the first iteration whose
+    # statistics changed by less than 1% from the previous one
+    def first_converged(h):
+        for i in range(1, len(h)):
+            if converged(h[i - 1][1], h[i][1]):
+                return h[i][0]
+        return None
+
     time_to_conv = None
     conv_iter = None
     if not args.no_converge:
-        def converged(h):
-            if len(h) < 2:
-                return False
-            (_, _, m0, h0), (_, _, m1, h1) = h[-2], h[-1]
-            return abs(m1 - m0) / m0 < 0.01 and abs(h1 - h0) / h0 < 0.01
-
-        # wall time per iteration measured in the timed region; iterations
-        # already run count with that per-iteration time
-        per_it = elapsed / args.steps
-        while not converged(history) and it <= args.max_iter:
-            s = step(it)
-            history.append((it, None, s["mean_T"], s["hot5_mean_T"]))
+        per_it = elapsed / args.steps   # wall time of one dust iteration, from the timed region
+        while first_converged(history) is None and it <= args.max_iter:
+            s = S.dust_iteration(it)
+            history.append((it, s))
             log(f"iteration {it}: <T> {s['mean_T']:.3f} K hot5 {s['hot5_mean_T']:.3f} K")
             it += 1
-        if converged(history):
-            conv_iter = history[-1][0]
+        conv_iter = first_converged(history)
+        if conv_iter is not None:
             time_to_conv = t_const + (conv_iter - 1) * per_it
+    T = S.T
 
     # ---- CPU baseline: the oracle on a bounded sample of the same workload
     cpu = None
