@@ -152,7 +152,7 @@ def grf_lognormal(n: int, sigma_ln: float, seed: int, slope: float = -3.0) -> np
     amp = np.zeros_like(kk)
     nz = kk > 0
     amp[nz] = kk[nz] ** (slope / 2.0)
-    field = np.fft.irfftn(np.fft.rfftn(white) * amp, s=(n, n, n))
+    field = np.fft.irfftn(np.fft.rfftn(white) * amp, s=(n, n, n), axes=(0, 1, 2))
     field -= field.mean()
     field /= field.std()
     return np.exp(sigma_ln * field - 0.5 * sigma_ln * sigma_ln)

@@ -1,0 +1,67 @@
+"""Host-side parts of the learned-start pipeline (no GPU): block averages,
+network inputs and targets, the training-cloud family."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1812_06632_amd import workloads as W
+
+surrogate = pytest.importorskip("paper_1812_06632_amd.surrogate")
+
+
+def test_block_mean_is_the_mean_over_blocks():
+    rng = np.random.default_rng(0)
+    a = rng.standard_normal((8, 8, 8))
+    m = surrogate.block_mean(a, 4)
+    assert m.shape == (4, 4, 4)
+    assert m[1, 2, 3] == pytest.approx(a[2:4, 4:6, 6:8].mean())
+    assert m.mean() == pytest.approx(a.mean())
+    with pytest.raises(ValueError):
+        surrogate.block_mean(a, 3)
+
+
+def test_features_optical_depth_and_source_flux():
+    P = W.lognormal_problem(n=32, K=8, packages_per_freq=1000)
+    X = surrogate.features(P, 16)
+    assert X.shape == (16, 16, 16, 2) and X.dtype == np.float32
+    # channel 0: log10 of the 0.55 um optical depth of a 2^3 block, / 2
+    rho = P.grid.density().reshape(32, 32, 32).astype(np.float64)
+    tau = W.SIGMA_V * rho[0:2, 2:4, 4:6].mean() * P.grid.root_cell_cm * 2
+    assert X[0, 1, 2, 0] == pytest.approx(math.log10(tau + 1e-4) / 2, rel=1e-5)
+    # channel 1 peaks at the block holding each point source
+    for (px, py, pz) in P.ps_pos:
+        bx, by, bz = int(px // 2), int(py // 2), int(pz // 2)
+        assert X[bz, by, bx, 1] == pytest.approx(X[..., 1].max(), rel=0.3)
+    # no sources: channel 1 vanishes
+    P.ps_pos = np.zeros((0, 3))
+    P.ps_Lnu = np.zeros((0, 8))
+    assert np.all(surrogate.features(P, 16)[..., 1] == 0)
+
+
+def test_targets_use_the_floor_in_empty_cells():
+    P = W.lognormal_problem(n=16, K=8, packages_per_freq=1000)
+    T = np.full(P.grid.ncells, 40.0)
+    Y = surrogate.targets(P, T, 8)
+    assert Y.shape == (8, 8, 8, 1)
+    rho = P.grid.density().reshape(16, 16, 16)
+    lt = np.where(rho > 0, math.log10(40.0), math.log10(P.T_floor))
+    assert np.allclose(Y[..., 0], surrogate.block_mean(lt, 8))
+
+
+def test_training_family_ranges():
+    rng = np.random.default_rng(3)
+    for _ in range(6):
+        P = surrogate.random_problem(rng, n=16, K=8, packages=4000)
+        rho = P.grid.density().reshape(16, 16, 16).astype(np.float64)
+        # mean face-to-face optical depth within the family's range
+        tau = W.SIGMA_V * P.grid.root_cell_cm * np.mean([rho.sum(axis=a).mean() for a in range(3)])
+        lo, hi = surrogate.TAU_RANGE
+        assert lo * 0.7 <= tau <= hi * 1.3
+        assert len(P.ps_pos) <= 2
+        if len(P.ps_pos):
+            assert P.n_bg + len(P.ps_pos) * P.n_ps_pk <= 4000
+            Lbol = (P.ps_Lnu * P.w[None, :]).sum(axis=1) / W.L_SUN
+            assert np.all((Lbol > 0.5e5) & (Lbol < 2e7))
+        else:
+            assert P.n_bg == 4000 and P.n_ps_pk == 0
