@@ -76,6 +76,7 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_kernel(McArgs A)
     Rng rng;
     bool active = false;   // lane holds a package
     bool pend = false;     // its last segment ended in a scattering whose new direction is not drawn yet
+    bool first_step = false;   // its first step is still to come
     unsigned long long pool_next = 0, pool_end = 0;   // wave-uniform
     bool exhausted = false;                           // wave-uniform
     unsigned long long n_pk = 0, n_st = 0, n_sc = 0, n_ru = 0;
@@ -89,16 +90,16 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_kernel(McArgs A)
         const int nidle = __popcll(idle);
         if (!exhausted && nidle > 0 && (nidle >= A.refill_min || nidle == 64)) {
             const unsigned long long avail = pool_end - pool_next;
-            unsigned long long fresh = 0;
+            unsigned long long grant = 0;   // first id of a new chunk from the global counter
             if (avail < (unsigned long long)nidle) {
                 const int leader = __ffsll((long long)idle) - 1;
                 unsigned long long b = 0;
                 if (lane == leader) b = atomicAdd(A.next_id, (unsigned long long)A.chunk);
-                fresh = (unsigned long long)__shfl((long long)b, leader, 64);
+                grant = (unsigned long long)__shfl((long long)b, leader, 64);
             }
             if (!active) {
                 const unsigned long long r = (unsigned long long)__popcll(idle & below);
-                const unsigned long long id = r < avail ? pool_next + r : fresh + (r - avail);
+                const unsigned long long id = r < avail ? pool_next + r : grant + (r - avail);
                 if (id < A.n_total) {
                     uint32_t cls, pid;
                     double W0;
@@ -106,11 +107,12 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_kernel(McArgs A)
                     n_pk += 1;
                     if (ok) e_em += W0;
                     active = ok;
+                    first_step = ok;
                 }
             }
             if (avail < (unsigned long long)nidle) {
-                pool_next = fresh + ((unsigned long long)nidle - avail);
-                pool_end = fresh + (unsigned long long)A.chunk;
+                pool_next = grant + ((unsigned long long)nidle - avail);
+                pool_end = grant + (unsigned long long)A.chunk;
             } else {
                 pool_next += (unsigned long long)nidle;
             }
@@ -139,16 +141,44 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_kernel(McArgs A)
         }
         ++since_flush;
         for (int s = 0; s < A.inner_steps; ++s) {
-            if (active && !pend) {
+            const bool stepping = active && !pend;
+            StepOut o;
+            o.cell = 0;
+            o.event = kEvCross;
+            o.dep = 0.0;
+            if (stepping) {
                 float d;
-                const StepOut o = step<float, Oct>(p, A, ks, ka, d);
+                o = step<float, Oct>(p, A, ks, ka, d);
                 n_st += 1;
-                if (o.dep > 0.0) {
-                    lds_dep[nbuf * bd + tid] = o.dep;
-                    lds_cell[nbuf * bd + tid] = o.cell;
-                    ++nbuf;
-                    e_ab += o.dep;
+                e_ab += o.dep;
+            }
+            // Packages refilled together often start in the same cell (the
+            // luminosity-weighted emission puts consecutive ids in the
+            // brightest cells): the first deposits of the lanes that share
+            // the cell of the lowest such lane are summed in registers and
+            // staged once, which spares the memory-side atomic unit a burst
+            // of same-address adds.
+            double dep = o.dep;
+            const bool first = stepping && first_step && dep > 0.0;
+            if (stepping) first_step = false;
+            const unsigned long long fm = __ballot(first);
+            if (fm & (fm - 1)) {   // at least two lanes
+                const int leader = __ffsll((long long)fm) - 1;
+                const int c0 = __shfl(o.cell, leader, 64);
+                const bool in = first && o.cell == c0;
+                const unsigned long long gm = __ballot(in);
+                if (gm & (gm - 1)) {
+                    double v = in ? dep : 0.0;
+                    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+                    if (in) dep = lane == leader ? v : 0.0;
                 }
+            }
+            if (dep > 0.0) {
+                lds_dep[nbuf * bd + tid] = dep;
+                lds_cell[nbuf * bd + tid] = o.cell;
+                ++nbuf;
+            }
+            if (stepping) {
                 if (o.event == kEvScatter) {
                     pend = true;
                     n_sc += 1;

@@ -10,8 +10,9 @@ takes more iterations).
 
 Inputs of the network (channels-last, S^3 cells, block averages of the
 cloud): the log10 of the optical depth of one cell at 0.55 um, and the
-log10 of 1 + the unattenuated bolometric flux of the point sources in
-units of 10^6 L_sun per cell-size squared.  Output: log10 T, normalised
+log10 of 1 + the ratio of the unattenuated bolometric flux of the point
+sources, sum L / (4 pi d^2), to the bolometric 4 pi J of the external
+field (the two heating terms a cell sees).  Output: log10 T, normalised
 by the training-set mean and standard deviation.  A prediction on a finer
 grid is trilinearly interpolated in log T.
 
@@ -40,6 +41,17 @@ def block_mean(a: np.ndarray, S: int) -> np.ndarray:
     return a.reshape(S, b, S, b, S, b).mean(axis=(1, 3, 5))
 
 
+_ISRF_BOL = None
+
+
+def _isrf_bolometric() -> float:
+    """Frequency integral of the external field's intensity (cached)."""
+    global _ISRF_BOL
+    if _ISRF_BOL is None:
+        _ISRF_BOL = W.isrf_integral()
+    return _ISRF_BOL
+
+
 def features(P: W.Problem, S: int) -> np.ndarray:
     """[S, S, S, 2] float32 network input of a regular cubic problem."""
     g = P.grid
@@ -51,12 +63,14 @@ def features(P: W.Problem, S: int) -> np.ndarray:
     f0 = np.log10(W.SIGMA_V * rho * cell + 1e-4) / 2.0
     c = (np.arange(S) + 0.5)
     zz, yy, xx = np.meshgrid(c, c, c, indexing="ij")
-    flux = np.zeros((S, S, S))
+    ratio = np.zeros((S, S, S))
     if len(P.ps_pos):
-        Lbol = (P.ps_Lnu * P.w[None, :]).sum(axis=1) / (1e6 * W.L_SUN)
+        Lbol = (P.ps_Lnu * P.w[None, :]).sum(axis=1)
+        f_ext = 4.0 * math.pi * _isrf_bolometric()
         for (px, py, pz), L in zip(np.asarray(P.ps_pos) * S / n, Lbol):
-            flux += L / ((xx - px) ** 2 + (yy - py) ** 2 + (zz - pz) ** 2 + 0.25)
-    f1 = np.log10(1.0 + flux)
+            d2 = ((xx - px) ** 2 + (yy - py) ** 2 + (zz - pz) ** 2 + 0.25) * cell * cell   # cm^2, softened
+            ratio += L / (4.0 * math.pi * d2) / f_ext
+    f1 = np.log10(1.0 + ratio) / 4.0
     return np.stack([f0, f1], axis=-1).astype(np.float32)
 
 

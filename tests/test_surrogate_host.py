@@ -29,10 +29,17 @@ def test_features_optical_depth_and_source_flux():
     rho = P.grid.density().reshape(32, 32, 32).astype(np.float64)
     tau = W.SIGMA_V * rho[0:2, 2:4, 4:6].mean() * P.grid.root_cell_cm * 2
     assert X[0, 1, 2, 0] == pytest.approx(math.log10(tau + 1e-4) / 2, rel=1e-5)
-    # channel 1 peaks at the block holding each point source
+    # channel 1: log10(1 + source flux / external 4 pi J) / 4, largest at the sources
     for (px, py, pz) in P.ps_pos:
         bx, by, bz = int(px // 2), int(py // 2), int(pz // 2)
         assert X[bz, by, bx, 1] == pytest.approx(X[..., 1].max(), rel=0.3)
+    Lbol = (P.ps_Lnu * P.w[None, :]).sum(axis=1)
+    cell = P.grid.root_cell_cm * 2
+    c = np.array([0.5, 0.5, 0.5])                      # block (0, 0, 0)
+    d2 = [((np.asarray(p) / 2 - c) ** 2).sum() + 0.25 for p in P.ps_pos]
+    ratio = sum(L / (4 * math.pi * d * cell * cell) for L, d in zip(Lbol, d2)) / (4 * math.pi * W.isrf_integral())
+    assert X[0, 0, 0, 1] == pytest.approx(math.log10(1 + ratio) / 4, rel=1e-4)
+    assert X[0, 0, 0, 1] > 0.1    # a 10^6 L_sun source still dominates the corner of the box
     # no sources: channel 1 vanishes
     P.ps_pos = np.zeros((0, 3))
     P.ps_Lnu = np.zeros((0, 8))
