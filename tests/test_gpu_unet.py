@@ -134,6 +134,7 @@ def _case(levels, base, n, shape, cin=2, cout=2, seed=0):
     (3, 16, 2, (16, 16, 16)),       # three levels
     (2, 32, 1, (16, 8, 8)),         # 32/64 channels: two column tiles per wave
     (1, 16, 1, (64, 64, 32)),       # enough position bricks that a weight-gradient workgroup reduces several
+    (1, 64, 1, (64, 64, 32)),       # 8^3-brick convolution with two column tiles per wave
 ])
 def test_forward_and_gradients_match_oracle(soc, levels, base, n, shape):
     P, x, dy = _case(levels, base, n, shape)
