@@ -118,6 +118,61 @@ def ceilings(soc, torch, ncells):
 BF16_MFMA_PEAK_TFLOPS = 2500.0   # dense BF16 matrix-core peak of MI355X
 
 
+def batch_bench(args, soc, torch, W):
+    """Many independent clouds in one persistent launch: lognormal models of
+    16^3-96^3 cells, 32 frequencies, 1e5-1e6 background packages per
+    (model, frequency) pair.  One pass = zero every absorbed array, the
+    batched launch over all pairs, the temperature update of every model;
+    it is captured once in a HIP graph and replayed (the iteration word
+    advances on every replay).  Reports packages/s and cell steps/s over
+    the timed replays."""
+    t0 = time.time()
+    grids, (nu, w, sabs, ssca, g, I), pk = W.batch_clouds(args.batch_models, args.batch_freqs)
+    log(f"batch workload: {len(grids)} models, {sum(gr.ncells for gr in grids)} cells, "
+        f"{int(pk.sum())} packages per pass ({time.time() - t0:.1f}s)")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ctx = soc.Context(0, stream=s)
+        G = [soc.grid_from_workload(ctx, gr) for gr in grids]
+        table = soc.temp_table_build(ctx, nu, w, sabs, 2.0, 3000.0, 1024)
+        A = [torch.zeros(gr.ncells, dtype=torch.float64, device="cuda") for gr in grids]
+        T = [torch.zeros(gr.ncells, dtype=torch.float32, device="cuda") for gr in grids]
+        pairs = [dict(grid=m, freq=(float(nu[k]), float(w[k]), float(sabs[k]), float(ssca[k]), float(g[k])),
+                      freq_index=k, I_bg=float(I[k]), n_bg=int(pk[m, k]), absorbed=A[m])
+                 for m in range(len(grids)) for k in range(len(nu))]
+        b = soc.Batch(ctx, G, pairs, seed=1, tile_packages=args.tile)
+        n_tiles, n_pk = b.info()
+        b.run(iteration=0)
+        torch.cuda.synchronize()
+        soc.graph_begin(ctx)
+        for a in A:
+            a.zero_()
+        b.run(iteration=soc.ITER_ADVANCE)
+        for m in range(len(grids)):
+            soc.update_temperature(ctx, G[m], table, A[m], T[m])
+        graph = soc.graph_end(ctx)
+        for _ in range(max(args.warmup, 1)):
+            graph.launch()
+        torch.cuda.synchronize()
+        before = ctx.read_stats()
+        t0 = time.time()
+        for _ in range(args.steps):
+            graph.launch()
+        torch.cuda.synchronize()
+        el = time.time() - t0
+        after = ctx.read_stats()
+        pk_done = after["packages"] - before["packages"]
+        st_done = after["cell_steps"] - before["cell_steps"]
+    line = {"kind": "batch", "models": len(grids), "pairs": len(pairs), "tiles": n_tiles,
+            "cells": int(sum(gr.ncells for gr in grids)), "packages_per_pass": n_pk, "passes": args.steps,
+            "ms_per_pass": el / args.steps * 1e3, "packages_per_s": pk_done / el, "cell_steps_per_s": st_done / el,
+            "tile_packages": args.tile, "graph": True}
+    print(json.dumps(line), flush=True)
+    graph.close()
+    b.close()
+    ctx.close()
+
+
 def unet_step(args, soc, torch):
     """Forward, backward and Adam of the U-Net at its production shape,
     timed with events on the library's stream; flops are the real
@@ -161,13 +216,14 @@ def unet_step(args, soc, torch):
 
 def surrogate_gain(args, soc, torch, W):
     """Time to the 1% stopping rule on an optically thick lognormal cloud
-    (the benchmark's grid, frequencies and package counts with
+    (the benchmark's frequencies, package counts and sources with
     sigma_ln = --target-sigma and mean tau_V = --target-tau, where dust
-    self-heating needs several iterations) from three starts -- the plain
-    method (constant-source temperatures), the U-Net prediction, and a
-    constant temperature (control: shows what the learning adds) -- and the
-    error of the stopped field against a long plain reference (mean of 8
-    iterations after 12)."""
+    self-heating needs several iterations), at the network's own 64^3 and
+    at the benchmark's n^3, from three starts -- the plain method
+    (constant-source temperatures), the U-Net prediction, and a constant
+    temperature (control: shows what the learning adds) -- and the error of
+    the stopped field against a long plain reference (mean of 8 iterations
+    after 12)."""
     from paper_1812_06632_amd.driver import PlainSolver
     from paper_1812_06632_amd.surrogate import Surrogate, make_dataset
     ctx = soc.Context(0)
@@ -179,58 +235,63 @@ def surrogate_gain(args, soc, torch, W):
     losses = sur.fit(X, Y, steps=args.train_steps, lr=5e-4, log=log)
     torch.cuda.synchronize()
     t_train = time.time() - t0
-    P = W.lognormal_problem(n=args.n, K=args.freqs, sigma_ln=args.target_sigma, tau_v_mean=args.target_tau,
-                            packages_per_freq=args.packages)
-    ref = PlainSolver(ctx, P, seed=7)
-    ref.constant_pass()
-    burn, avg = 12, 8
-    acc = torch.zeros_like(ref.T, dtype=torch.float64)
-    for it in range(2, burn + avg + 2):
-        ref.dust_iteration(it)
-        if it > burn + 1:
-            acc += ref.T.double()
-    T_ref = acc / avg
-    dense = torch.from_numpy(P.grid.density()).cuda() > 0
-    Tr = T_ref[dense]
-    hot = Tr >= torch.quantile(Tr.float(), 0.95).double()
-    log(f"reference: <T> {Tr.mean().item():.3f} K, hottest 5% {Tr[hot].mean().item():.3f} K")
+    def gain(n):
+        """The three starts on the thick cloud at n^3 (the network runs at
+        64^3; a finer grid is block-averaged in and interpolated out)."""
+        P = W.lognormal_problem(n=n, K=args.freqs, sigma_ln=args.target_sigma, tau_v_mean=args.target_tau,
+                                packages_per_freq=args.packages)
+        ref = PlainSolver(ctx, P, seed=7)
+        ref.constant_pass()
+        burn, avg = 12, 8
+        acc = torch.zeros_like(ref.T, dtype=torch.float64)
+        for it in range(2, burn + avg + 2):
+            ref.dust_iteration(it)
+            if it > burn + 1:
+                acc += ref.T.double()
+        T_ref = acc / avg
+        dense = torch.from_numpy(P.grid.density()).cuda() > 0
+        Tr = T_ref[dense]
+        hot = Tr >= torch.quantile(Tr.float(), 0.95).double()
+        log(f"{n}^3 reference: <T> {Tr.mean().item():.3f} K, hottest 5% {Tr[hot].mean().item():.3f} K")
 
-    def err(T):
-        r = (T.double()[dense] - Tr).abs() / Tr
-        return r.mean().item(), r[hot].mean().item()
+        def err(T):
+            r = (T.double()[dense] - Tr).abs() / Tr
+            return r.mean().item(), r[hot].mean().item()
 
-    out = {}
-    T_const = float(10.0 ** sur.ymean)
-    for label in ("plain", "surrogate", "constant_start"):
-        S = PlainSolver(ctx, P, seed=1)
-        torch.cuda.synchronize()
-        t0 = time.time()
-        T0 = None
-        if label == "surrogate":
-            T0 = sur.predict_T(P)
-        elif label == "constant_start":
-            T0 = torch.where(dense, torch.full_like(S.T, T_const), torch.zeros_like(S.T))
-        t_start = time.time() - t0
-        e0 = err(T0) if T0 is not None else None
-        hist, at = S.run(max_iter=args.max_iter, T0=T0, log=log)
-        stop = at if at is not None else hist[-1][0]
-        e = err(S.T)
-        out[label] = {"iterations": stop, "converged": at is not None, "wall_s": t_start + hist[stop - 1][1],
-                      "start_s": t_start, "start_err_all": e0[0] if e0 else None,
-                      "start_err_hot5": e0[1] if e0 else None, "err_all": e[0], "err_hot5": e[1]}
-        log(f"{label}: stopped at iteration {stop} after {out[label]['wall_s']:.3f}s, "
-            f"mean |T - T_ref|/T_ref {e[0]:.4f} (hottest 5%: {e[1]:.4f})")
+        out = {}
+        T_const = float(10.0 ** sur.ymean)
+        for label in ("plain", "surrogate", "constant_start"):
+            S = PlainSolver(ctx, P, seed=1)
+            torch.cuda.synchronize()
+            t0 = time.time()
+            T0 = None
+            if label == "surrogate":
+                T0 = sur.predict_T(P)
+            elif label == "constant_start":
+                T0 = torch.where(dense, torch.full_like(S.T, T_const), torch.zeros_like(S.T))
+            t_start = time.time() - t0
+            e0 = err(T0) if T0 is not None else None
+            hist, at = S.run(max_iter=args.max_iter, T0=T0, log=log)
+            stop = at if at is not None else hist[-1][0]
+            e = err(S.T)
+            out[label] = {"iterations": stop, "converged": at is not None, "wall_s": t_start + hist[stop - 1][1],
+                          "start_s": t_start, "start_err_all": e0[0] if e0 else None,
+                          "start_err_hot5": e0[1] if e0 else None, "err_all": e[0], "err_hot5": e[1]}
+            log(f"{n}^3 {label}: stopped at iteration {stop} after {out[label]['wall_s']:.3f}s, "
+                f"mean |T - T_ref|/T_ref {e[0]:.4f} (hottest 5%: {e[1]:.4f})")
+        return {"cells": f"{n}^3", "reference": {"burn_in": burn, "averaged": avg, "mean_T": Tr.mean().item(),
+                                                 "hot5_mean_T": Tr[hot].mean().item()},
+                "runs": out, "speedup_vs_plain": out["plain"]["wall_s"] / out["surrogate"]["wall_s"]}
+
+    targets = [gain(64), gain(args.n)]
     line = {"kind": "surrogate_gain",
-            "workload": f"lognormal {args.n}^3, sigma_ln {args.target_sigma}, mean tau_V {args.target_tau}, "
-                        f"{args.freqs} frequencies, {args.packages} packages/frequency",
+            "workload": f"lognormal, sigma_ln {args.target_sigma}, mean tau_V {args.target_tau}, two 1e6 L_sun "
+                        f"sources, {args.freqs} frequencies, {args.packages} packages/frequency",
             "training": {"clouds": args.train_clouds, "cells": "64^3", "frequencies": 32, "tau_V": "log-U(2, 100)",
                          "packages_per_frequency": 200_000, "steps": args.train_steps, "batch": 4,
                          "data_s": t_data, "train_s": t_train, "final_loss": losses[-1][1] if losses else None,
                          "params": sur.net.param_count},
-            "reference": {"burn_in": burn, "averaged": avg, "mean_T": Tr.mean().item(),
-                          "hot5_mean_T": Tr[hot].mean().item()},
-            "runs": out,
-            "speedup_vs_plain": out["plain"]["wall_s"] / out["surrogate"]["wall_s"]}
+            "targets": targets}
     print(json.dumps(line), flush=True)
     sur.close()
     ctx.close()
@@ -254,10 +315,15 @@ def main():
     ap.add_argument("--unet", action="store_true",
                     help="only time the U-Net training step (64^3, base 32, 4 levels; one JSON line) and exit")
     ap.add_argument("--unet-batch", type=int, default=4)
-    ap.add_argument("--train-clouds", type=int, default=96)
+    ap.add_argument("--batch", action="store_true",
+                    help="only time the batched many-cloud workload as a replayed HIP graph (one JSON line) and exit")
+    ap.add_argument("--batch-models", type=int, default=256)
+    ap.add_argument("--batch-freqs", type=int, default=32)
+    ap.add_argument("--tile", type=int, default=16384)
+    ap.add_argument("--train-clouds", type=int, default=128)
     ap.add_argument("--target-sigma", type=float, default=1.5)
     ap.add_argument("--target-tau", type=float, default=50.0)
-    ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--train-steps", type=int, default=3000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the design notes describe how the "
@@ -277,6 +343,9 @@ def main():
         return
     if args.unet:
         unet_step(args, soc, torch)
+        return
+    if args.batch:
+        batch_bench(args, soc, torch, W)
         return
 
     from paper_1812_06632_amd.driver import PlainSolver, converged

@@ -549,6 +549,12 @@ __global__ __launch_bounds__(192) void wgrad3_kernel(WgradArgs a)
 
     for (int e = tid; e < 32 * kGHZ * kGHY * kGHX; e += 192) xT[e] = 0;   // pad columns stay zero
 
+    // workgroups of the first input-channel tile also sum dy per output
+    // channel (the bias gradient): thread (o = tid % 32, part = tid / 32)
+    // adds the staged positions part, part + 6, ...
+    const bool want_bias = i0 == 0;
+    float bsum = 0.0f;
+
     f32x16_t acc[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q)
@@ -589,6 +595,8 @@ __global__ __launch_bounds__(192) void wgrad3_kernel(WgradArgs a)
                 xT[(((8 * g + j) * kGHZ + hz) * kGHY + hy) * kGHX + hx] = (uint16_t)(v[j >> 1] >> (16 * (j & 1)));
         }
         __syncthreads();
+        if (want_bias)
+            for (int pos = tid >> 5; pos < kGZ * kGY * kGX; pos += 6) bsum += bf2f(dT[(tid & 31) * (kGZ * kGY * kGX) + pos]);
 #pragma unroll
         for (int lz = 0; lz < kGZ; ++lz)
 #pragma unroll
@@ -612,6 +620,19 @@ __global__ __launch_bounds__(192) void wgrad3_kernel(WgradArgs a)
                                                                               acc[3 * ty + 2], 0, 0, 0);
                 }
             }
+    }
+    // bias partials of this chunk, after all weight partials: the six parts
+    // of each output channel added in order
+    if (want_bias) {
+        __shared__ float bred[6][32];
+        bred[tid >> 5][tid & 31] = bsum;
+        __syncthreads();
+        if (tid < 32 && o0 + tid < a.cout) {
+            float t = 0.0f;
+            for (int q = 0; q < 6; ++q) t += bred[q][tid];
+            const size_t nchunks = gridDim.x;
+            a.part[nchunks * 27 * a.cin * a.cout + (size_t)blockIdx.x * a.cout + o0 + tid] = t;
+        }
     }
     // partials of this chunk: rows = input channels, columns = output channels
     float *out = a.part + (size_t)blockIdx.x * 27 * a.cin * a.cout;
@@ -954,7 +975,7 @@ Net::Status Net::create(int dev, int32_t cin, int32_t cout, int32_t base, int32_
     // split-K partials: the largest chunks x taps x cin x cout of any layer
     // (chunk counts do not decrease with the batch, so nmax bounds them)
     cap_part_ = 0;
-    for (auto &L : layers_) cap_part_ = std::max(cap_part_, plan_wgrad(L, nmax).chunks * L.nw);
+    for (auto &L : layers_) cap_part_ = std::max(cap_part_, plan_wgrad(L, nmax).chunks * (L.nw + L.cout));
     ALLOC(d_part_, float, std::max<int64_t>(cap_part_, kColBlocks * 4096));
 #undef ALLOC
 
@@ -1022,8 +1043,10 @@ static hipError_t launch_conv(const ConvArgs &a, hipStream_t s)
         }
         const unsigned bricks = (unsigned)a.batch * ((a.mz + kBZ - 1) / kBZ) * ((a.my + kBY - 1) / kBY) *
                                 ((a.mx + kBX - 1) / kBX);
-        const dim3 grid(bricks, a.npad / (32 * nt), 1);
-        if (nt == 2)
+        // small grids: 32-column tiles give twice the workgroups
+        const int ntl = (nt == 2 && bricks * (unsigned)(a.npad / 64) < 512) ? 1 : nt;
+        const dim3 grid(bricks, a.npad / (32 * ntl), 1);
+        if (ntl == 2)
             hipLaunchKernelGGL(conv3_lds_kernel<2>, grid, dim3(256), 0, s, a);
         else
             hipLaunchKernelGGL(conv3_lds_kernel<1>, grid, dim3(256), 0, s, a);
@@ -1155,7 +1178,7 @@ hipError_t Net::conv_wgrad(const Layer &L, int32_t n, const View &x, const View 
     a.cout = L.cout;
     const int slots = taps_of(L.kind);
     const WgradPlan p = plan_wgrad(L, n);
-    if (p.chunks * L.nw > std::max<int64_t>(cap_part_, kColBlocks * 4096)) return hipErrorInvalidValue;
+    if (p.chunks * (L.nw + L.cout) > std::max<int64_t>(cap_part_, kColBlocks * 4096)) return hipErrorInvalidValue;
     a.chunk = p.chunk;
     a.part = d_part_;
     const unsigned ctiles = (unsigned)(((L.cin + 31) / 32) * ((L.cout + 31) / 32));
@@ -1165,6 +1188,12 @@ hipError_t Net::conv_wgrad(const Layer &L, int32_t n, const View &x, const View 
         hipLaunchKernelGGL(wgrad_kernel, dim3((unsigned)p.chunks, ctiles, (unsigned)slots), dim3(256), 0, s, a);
     hipLaunchKernelGGL(sum_chunks_kernel, dim3(nblk(L.nw, kSumElems)), dim3(256), 0, s, (const float *)d_part_,
                        (int32_t)p.chunks, L.nw, d_grads_ + L.w_off);
+    if (p.bricks) {   // the 27-tap kernel left the bias partials after the weight partials
+        hipLaunchKernelGGL(sum_chunks_kernel, dim3(nblk(L.cout, kSumElems)), dim3(256), 0, s,
+                           (const float *)d_part_ + p.chunks * L.nw, (int32_t)p.chunks, (int64_t)L.cout,
+                           d_grads_ + L.b_off);
+        return hipGetLastError();
+    }
     // bias gradient: column sums of dy over the output positions
     const int64_t npos = positions(lout, n);
     hipLaunchKernelGGL(colsum_kernel, dim3(kColBlocks), dim3(256), 0, s, (const uint16_t *)dy.p, dy.cs, dy.co, L.cout,

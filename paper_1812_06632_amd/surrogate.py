@@ -9,12 +9,16 @@ stopping rule then acts as a judge of the prediction: a poor start simply
 takes more iterations).
 
 Inputs of the network (channels-last, S^3 cells, block averages of the
-cloud): the log10 of the optical depth of one cell at 0.55 um, and the
-log10 of 1 + the ratio of the unattenuated bolometric flux of the point
+cloud): the log10 of the optical depth of one cell at 0.55 um; the log10
+of 1 + the ratio of the unattenuated bolometric flux of the point
 sources, sum L / (4 pi d^2), to the bolometric 4 pi J of the external
-field (the two heating terms a cell sees).  Output: log10 T, normalised
-by the training-set mean and standard deviation.  A prediction on a finer
-grid is trilinearly interpolated in log T.
+field; and the optically thin temperature of the cell -- the solution of
+4 pi sum_k w_k sigma_k B(nu_k, T) = 4 pi sum_k w_k sigma_k J_k with J the
+external field plus the unattenuated sources, L_nu / (16 pi^2 d^2) -- so
+that the network has only to learn the attenuation and the dust
+re-emission.  Output: log10 T, normalised by the training-set mean and
+standard deviation.  A prediction on a finer grid is trilinearly
+interpolated in log T.
 
 Everything runs on the device through the library; torch supplies the
 device arrays and the elementwise glue (normalisation, flips, the
@@ -52,8 +56,30 @@ def _isrf_bolometric() -> float:
     return _ISRF_BOL
 
 
+N_FEATURES = 3
+
+
+def _planck(nu: np.ndarray, T: np.ndarray) -> np.ndarray:
+    """B_nu(T) in erg s-1 cm-2 Hz-1 sr-1 (outer product of T and nu)."""
+    x = W._H * nu[None, :] / (W._K * T[:, None])
+    return 2.0 * W._H * nu[None, :] ** 3 / W._C ** 2 / np.expm1(np.minimum(x, 700.0))
+
+
+def thin_temperature(P: W.Problem, Jw: np.ndarray) -> np.ndarray:
+    """Equilibrium temperature of dust whose absorption is
+    Jw = sum_k w_k sigma_k J_k (per cell, J the mean intensity on the
+    problem's frequency grid), without attenuation: the root of
+    sum_k w_k sigma_k B(nu_k, T) = Jw, from a log-log table of the emission
+    on [T_floor, T_max]."""
+    ws = P.w * P.sigma_abs
+    Tg = np.exp(np.linspace(math.log(P.T_floor), math.log(P.T_max), 1024))
+    lg_emit = np.log(_planck(P.nu, Tg) @ ws)
+    lg_in = np.log(np.maximum(np.asarray(Jw, dtype=np.float64), 1e-300))
+    return np.exp(np.interp(lg_in, lg_emit, np.log(Tg)))
+
+
 def features(P: W.Problem, S: int) -> np.ndarray:
-    """[S, S, S, 2] float32 network input of a regular cubic problem."""
+    """[S, S, S, 3] float32 network input of a regular cubic problem."""
     g = P.grid
     if g.nlevels != 1 or not (g.nx == g.ny == g.nz):
         raise ValueError("the surrogate takes regular cubic grids")
@@ -64,14 +90,18 @@ def features(P: W.Problem, S: int) -> np.ndarray:
     c = (np.arange(S) + 0.5)
     zz, yy, xx = np.meshgrid(c, c, c, indexing="ij")
     ratio = np.zeros((S, S, S))
+    ws = P.w * P.sigma_abs
+    Jw = np.full((S, S, S), float(P.I_bg @ ws))   # external field, isotropic: J = I
     if len(P.ps_pos):
         Lbol = (P.ps_Lnu * P.w[None, :]).sum(axis=1)
         f_ext = 4.0 * math.pi * _isrf_bolometric()
-        for (px, py, pz), L in zip(np.asarray(P.ps_pos) * S / n, Lbol):
+        for (px, py, pz), L, Lnu in zip(np.asarray(P.ps_pos) * S / n, Lbol, P.ps_Lnu):
             d2 = ((xx - px) ** 2 + (yy - py) ** 2 + (zz - pz) ** 2 + 0.25) * cell * cell   # cm^2, softened
             ratio += L / (4.0 * math.pi * d2) / f_ext
+            Jw += float(Lnu @ ws) / (16.0 * math.pi ** 2 * d2)
     f1 = np.log10(1.0 + ratio) / 4.0
-    return np.stack([f0, f1], axis=-1).astype(np.float32)
+    f2 = (np.log10(thin_temperature(P, Jw.reshape(-1))).reshape(S, S, S) - 1.5) / 0.5
+    return np.stack([f0, f1, f2], axis=-1).astype(np.float32)
 
 
 def targets(P: W.Problem, T: np.ndarray, S: int) -> np.ndarray:
@@ -110,10 +140,10 @@ def random_problem(rng: np.random.Generator, n: int = 64, K: int = 32, packages:
 
 def make_dataset(ctx: soc.Context, count: int, seed: int, n: int = 64, S: int = 64, K: int = 32,
                  packages: int = 200_000, max_iter: int = 10, log=None):
-    """(X [count, S, S, S, 2] float32, Y [count, S, S, S, 1] float64):
-    random clouds solved by the plain method to the 1% rule."""
+    """(X [count, S, S, S, N_FEATURES] float32, Y [count, S, S, S, 1]
+    float64): random clouds solved by the plain method to the 1% rule."""
     rng = np.random.default_rng(seed)
-    X = np.empty((count, S, S, S, 2), np.float32)
+    X = np.empty((count, S, S, S, N_FEATURES), np.float32)
     Y = np.empty((count, S, S, S, 1), np.float64)
     t0 = time.time()
     for m in range(count):
@@ -144,11 +174,11 @@ class Surrogate:
     def __init__(self, ctx: soc.Context, S: int = 64, base: int = 32, levels: int = 4, batch: int = 4,
                  seed: int = 0):
         self.ctx, self.S, self.batch = ctx, S, batch
-        self.net = soc.UNet(ctx, 2, 1, base, levels, batch, (S, S, S), seed=seed)
+        self.net = soc.UNet(ctx, N_FEATURES, 1, base, levels, batch, (S, S, S), seed=seed)
         self.ymean = 0.0
         self.ystd = 1.0
 
-    def fit(self, X: np.ndarray, Y: np.ndarray, steps: int, lr: float = 5e-4, warmup: int = 100, seed: int = 0,
+    def fit(self, X: np.ndarray, Y: np.ndarray, steps: int, lr: float = 3e-4, warmup: int = 200, seed: int = 0,
             log=None):
         """Adam on the MSE of the normalised log T; the step size rises
         linearly over `warmup` steps, then decays on a cosine to zero."""

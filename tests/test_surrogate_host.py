@@ -24,7 +24,7 @@ def test_block_mean_is_the_mean_over_blocks():
 def test_features_optical_depth_and_source_flux():
     P = W.lognormal_problem(n=32, K=8, packages_per_freq=1000)
     X = surrogate.features(P, 16)
-    assert X.shape == (16, 16, 16, 2) and X.dtype == np.float32
+    assert X.shape == (16, 16, 16, 3) and X.dtype == np.float32
     # channel 0: log10 of the 0.55 um optical depth of a 2^3 block, / 2
     rho = P.grid.density().reshape(32, 32, 32).astype(np.float64)
     tau = W.SIGMA_V * rho[0:2, 2:4, 4:6].mean() * P.grid.root_cell_cm * 2
@@ -72,3 +72,26 @@ def test_training_family_ranges():
             assert np.all((Lbol > 0.5e5) & (Lbol < 2e7))
         else:
             assert P.n_bg == 4000 and P.n_ps_pk == 0
+
+
+def test_thin_temperature_balances_absorption_and_emission():
+    """The optically thin temperature solves 4 pi sum w sigma (B(T) - J) = 0:
+    for the external field alone it is one value everywhere, it rises
+    towards a point source, and the balance holds at the returned T."""
+    P = W.lognormal_problem(n=16, K=32, packages_per_freq=1000)
+    X = surrogate.features(P, 8)
+    T = 10 ** (X[..., 2].astype(np.float64) * 0.5 + 1.5)
+    J = P.I_bg[None, :]
+    ws = P.w * P.sigma_abs
+    T1 = surrogate.thin_temperature(P, J @ ws)[0]     # external field alone
+    assert 5.0 < T1 < 50.0
+    assert T.min() > T1                                # the sources only add heating
+    for (px, py, pz) in P.ps_pos:
+        assert T[int(pz // 2), int(py // 2), int(px // 2)] > 2 * T.min()
+    bal = (surrogate._planck(P.nu, np.array([T1])) @ ws)[0] / (J @ ws)[0]
+    assert bal == pytest.approx(1.0, rel=2e-3)
+    P.ps_pos = np.zeros((0, 3))
+    P.ps_Lnu = np.zeros((0, 32))
+    X0 = surrogate.features(P, 8)
+    assert np.ptp(X0[..., 2]) < 1e-6
+    assert 10 ** (float(X0[0, 0, 0, 2]) * 0.5 + 1.5) == pytest.approx(T1, rel=1e-5)
