@@ -36,10 +36,13 @@ struct soc_ctx_s {
     int64_t timing = 0;
     int64_t chunk = 256;
     int64_t scatter_min = 1;
+    int64_t xcd_copies = 1;
     // scratch
     DevStats *d_stats = nullptr;              // [0] per call, [1] running total
     unsigned long long *d_counter = nullptr;
     double *d_tmp_out = nullptr;              // small result buffer (temperature stats)
+    double *d_priv = nullptr;                 // 8 private copies of the absorbed array (zero between launches)
+    int64_t cap_priv = 0;
     double *d_L = nullptr, *d_incl = nullptr, *d_scan = nullptr;
     int64_t cap_L = 0, cap_incl = 0, cap_scan = 0;
     int32_t *d_pkcell = nullptr;
@@ -313,6 +316,7 @@ void soc_ctx_destroy(soc_ctx c)
     (void)hipFree(c->d_stats);
     (void)hipFree(c->d_counter);
     (void)hipFree(c->d_tmp_out);
+    (void)hipFree(c->d_priv);
     (void)hipFree(c->d_L);
     (void)hipFree(c->d_incl);
     (void)hipFree(c->d_scan);
@@ -366,6 +370,9 @@ soc_status soc_ctx_set_option(soc_ctx c, soc_option opt, int64_t v)
         if (v < 1 || v > 64) return fail(c, SOC_EINVAL, "scatter threshold must be in [1,64]");
         c->scatter_min = v;
         return SOC_OK;
+    case SOC_OPT_XCD_COPIES:
+        c->xcd_copies = v ? 1 : 0;
+        return SOC_OK;
     }
     return fail(c, SOC_EINVAL, "unknown option %d", (int)opt);
 }
@@ -381,6 +388,7 @@ soc_status soc_ctx_get_option(soc_ctx c, soc_option opt, int64_t *v)
     case SOC_OPT_INNER_STEPS: *v = c->inner_steps; return SOC_OK;
     case SOC_OPT_TIMING: *v = c->timing; return SOC_OK;
     case SOC_OPT_SCATTER_MIN: *v = c->scatter_min; return SOC_OK;
+    case SOC_OPT_XCD_COPIES: *v = c->xcd_copies; return SOC_OK;
     }
     return fail(c, SOC_EINVAL, "unknown option %d", (int)opt);
 }
@@ -519,6 +527,14 @@ soc_status soc_simulate_frequency(soc_ctx c, soc_grid g, const soc_freq *f, cons
     McArgs A;
     soc_status st = prepare(c, g, f, s, seed, iteration, freq_index, d_absorbed, A);
     if (st) return st;
+    if (c->xcd_copies) {
+        if (c->cap_priv < 8 * g->ncells) {   // new copies start zero; every fold leaves them zero
+            st = grow(c, &c->d_priv, c->cap_priv, 8 * g->ncells);
+            if (st) return st;
+            HIPCHK(c, launch_fill_f64(c->d_priv, 0.0, c->cap_priv, c->stream));
+        }
+        A.priv = c->d_priv;
+    }
     HIPCHK(c, launch_fill_u64((unsigned long long *)c->d_stats, 0ull, (int64_t)(sizeof(DevStats) / 8), c->stream));
     HIPCHK(c, launch_fill_u64(c->d_counter, 0ull, 1, c->stream));
     const int blocks = (int)(c->num_cus * c->blocks_per_cu);
@@ -534,6 +550,7 @@ soc_status soc_simulate_frequency(soc_ctx c, soc_grid g, const soc_freq *f, cons
         c->ev_start.push_back(e0);
         c->ev_stop.push_back(e1);
     }
+    if (A.priv) HIPCHK(c, launch_fold_copies(d_absorbed, A.priv, g->ncells, c->stream));
     if (stats) {
         DevStats h;
         HIPCHK(c, hipMemcpyAsync(&h, c->d_stats, sizeof h, hipMemcpyDeviceToHost, c->stream));

@@ -83,6 +83,7 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_kernel(McArgs A)
     double e_em = 0.0, e_ab = 0.0, e_es = 0.0;
     const float ks = A.ks_f, ka = A.ka_f;
     const HG<float> hg(A.g_f);
+    double *const dst = A.priv ? A.priv + (size_t)xcd_index() * (size_t)A.ncells : A.absorbed;
 
     for (;;) {
         // refill idle lanes from the wave's id pool
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_kernel(McArgs A)
         }
         if ((since_flush + 1) * A.inner_steps > kDepSlots) {
             for (int j = 0; j < kDepSlots; ++j)
-                if (j < nbuf) unsafeAtomicAdd(&A.absorbed[lds_cell[j * bd + tid]], lds_dep[j * bd + tid]);
+                if (j < nbuf) unsafeAtomicAdd(&dst[lds_cell[j * bd + tid]], lds_dep[j * bd + tid]);
             nbuf = 0;
             since_flush = 0;
         }
@@ -191,7 +192,7 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_kernel(McArgs A)
         }
     }
     for (int j = 0; j < kDepSlots; ++j)
-        if (j < nbuf) unsafeAtomicAdd(&A.absorbed[lds_cell[j * bd + tid]], lds_dep[j * bd + tid]);
+        if (j < nbuf) unsafeAtomicAdd(&dst[lds_cell[j * bd + tid]], lds_dep[j * bd + tid]);
     flush_stats(A, n_pk, n_st, n_sc, n_ru, e_em, e_ab, e_es);
 }
 

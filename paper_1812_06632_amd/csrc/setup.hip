@@ -9,6 +9,8 @@
 //    contain only kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "soc_kernels.h"
 
 namespace soc {
@@ -34,6 +36,28 @@ static hipError_t fill(T *p, T v, int64_t n, hipStream_t s)
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
+
+// Per-XCD private copies of the absorbed array: add the 8 copies into the
+// caller's array in copy order and leave them zero for the next launch.
+__global__ void fold_copies_kernel(double *absorbed, double *priv, int64_t n)
+{
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            s += priv[x * n + c];
+            priv[x * n + c] = 0.0;
+        }
+        if (s != 0.0) absorbed[c] += s;
+    }
+}
+
+hipError_t launch_fold_copies(double *absorbed, double *priv, int64_t n, hipStream_t s)
+{
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(fold_copies_kernel, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), 0, s, absorbed, priv, n);
+    return hipGetLastError();
+}
 
 // ------------------------------------------------------------------ levels
 __device__ inline int level_of(int64_t c, const int64_t *lo, int32_t nlevels)

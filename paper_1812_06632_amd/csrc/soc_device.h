@@ -15,6 +15,14 @@
 
 namespace soc {
 
+// Index (0..7) of the XCD the calling wave runs on (hardware register
+// XCC_ID, bits [3:0]); wave-uniform.
+__device__ inline uint32_t xcd_index()
+{
+    return __builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & 7u;
+}
+
+
 // ------------------------------------------------------------------ Philox
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
 // 32x32 -> 64-bit products with the published multipliers; the key is

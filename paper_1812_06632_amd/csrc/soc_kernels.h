@@ -63,6 +63,7 @@ struct McArgs {
     // transport
     int64_t step_cap;
     double *absorbed;
+    double *priv;                // NULL, or 8 private copies of ncells (one per XCD, hardware XCC id)
     // persistent scheduling
     unsigned long long *next_id;
     DevStats *st_call, *st_total;
@@ -91,6 +92,8 @@ hipError_t launch_trace(const McArgs &a, const TraceArgs &t, int precision, hipS
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+// absorbed[c] += sum_x priv[x n + c] over the 8 private copies, which are left zero.
+hipError_t launch_fold_copies(double *absorbed, double *priv, int64_t n, hipStream_t s);
 
 // dust emission setup
 hipError_t launch_dust_luminosity(const uint32_t *words, int64_t ncells, const int64_t *level_offset,

@@ -6,7 +6,7 @@
 // traffic counters).
 #include <hip/hip_runtime.h>
 
-#include "soc_kernels.h"
+#include "soc_device.h"
 
 namespace soc {
 
@@ -21,13 +21,8 @@ __device__ inline uint32_t mix32(uint32_t x)
     return x;
 }
 
-__device__ inline uint32_t xcc_id()
-{
-    return __builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & 7u;   // HW_REG_XCC_ID[3:0]
-}
-
 // mode 0: random addresses in one array shared by every XCD;
-// mode 1: random addresses in slice xcc_id() of 8 (per-XCD private copies);
+// mode 1: random addresses in slice xcd_index() of 8 (per-XCD private copies);
 // mode 2: wave-coalesced, every wave updating the 64 consecutive doubles of
 //         one random 64-double block (n >= 64);
 // mode 3: random addresses in a 4096-double LDS array of the workgroup
@@ -39,7 +34,7 @@ __global__ void ubench_atomic_kernel(double *a, uint32_t n, int32_t per_thread, 
     __shared__ double lds[kUbLds];
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t lane = threadIdx.x & 63u;
-    double *base = mode == 1 ? a + (size_t)xcc_id() * n : a;
+    double *base = mode == 1 ? a + (size_t)xcd_index() * n : a;
     if (mode == 3) {
         for (int i = threadIdx.x; i < kUbLds; i += blockDim.x) lds[i] = 0.0;
         __syncthreads();

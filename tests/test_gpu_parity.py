@@ -227,8 +227,10 @@ def test_cloud_all_sources_statistical_and_conservation(soc, ctx, cloud):
 
 def test_launch_configuration_independence(soc, ctx, cloud):
     """A package's random numbers depend only on its identity: any block
-    size, occupancy, refill threshold or inner-step count gives the same
-    tallies up to FP64 atomic ordering, and identical counters."""
+    size, occupancy, refill threshold, inner-step count, or shared versus
+    per-XCD accumulation gives the same tallies up to FP64 summation order,
+    and identical counters (repeated per-XCD runs also check that every
+    fold left the private copies zero)."""
     P, T = cloud
     g = soc.grid_from_workload(ctx, P.grid)
     k = _k_at(P, 2.0)
@@ -237,11 +239,13 @@ def test_launch_configuration_independence(soc, ctx, cloud):
     kw = dict(I_bg=P.I_bg[k], ps_pos=P.ps_pos, ps_Lnu=P.ps_Lnu[:, k], n_bg=5000, n_ps_pk=3000, n_dust=7001,
               dust_mode=1, T=Td, iteration=1, freq_index=k)
     ref, sref = _gpu_run(soc, ctx, g, P.grid.ncells, f, 77, **kw)
-    saved = {n: ctx.get_option(n) for n in ("block", "blocks_per_cu", "refill_min", "inner_steps", "scatter_min")}
+    saved = {n: ctx.get_option(n) for n in ("block", "blocks_per_cu", "refill_min", "inner_steps", "scatter_min",
+                                            "xcd_copies")}
     try:
         for cfg in ({"block": 64, "blocks_per_cu": 1}, {"block": 512, "blocks_per_cu": 2},
                     {"refill_min": 32, "inner_steps": 7}, {"refill_min": 64, "inner_steps": 8},
-                    {"scatter_min": 24}, {"scatter_min": 64, "inner_steps": 3}):
+                    {"scatter_min": 24}, {"scatter_min": 64, "inner_steps": 3},
+                    {"xcd_copies": 0}, {"xcd_copies": 0, "block": 128}, {"xcd_copies": 1, "block": 192}):
             for n_, v in cfg.items():
                 ctx.set_option(n_, v)
             A, st = _gpu_run(soc, ctx, g, P.grid.ncells, f, 77, **kw)
