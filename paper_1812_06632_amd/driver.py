@@ -77,25 +77,43 @@ class PlainSolver:
         self.T.copy_(self.T_new)
         return s
 
-    def run(self, max_iter: int = 30, tol: float = 0.01, T0: torch.Tensor | None = None, log=None):
+    def run(self, max_iter: int = 30, tol: float = 0.01, T0=None, log=None, on_iter=None, until_stop: bool = True):
         """Constant pass, optional start temperatures, dust iterations until
-        the stopping rule or max_iter.  Returns (history, converged_at)
-        where history holds (iteration, wall seconds since the start,
-        statistics)."""
+        the stopping rule (or, with until_stop False, all max_iter of them).
+        T0 is a field, or a callable that maps the constant-source
+        temperatures to the start field; the constant-source temperatures
+        are kept in self.T1.  on_iter(iteration, T) is called after every
+        iteration (outside the timing it reports).  Returns (history,
+        converged_at) where history holds (iteration, wall seconds since
+        the start, statistics) and converged_at is the first iteration that
+        met the stopping rule."""
         torch.cuda.synchronize()
         t0 = time.time()
         s = self.constant_pass()
+        self.T1 = self.T.clone()
         hist = [(1, time.time() - t0, s)]
         if T0 is not None:
-            s = self.set_temperature(T0)
+            s = self.set_temperature(T0(self.T1) if callable(T0) else T0)
             hist[-1] = (1, time.time() - t0, s)
         if log:
             log(f"iteration 1: <T> {s['mean_T']:.3f} K hot5 {s['hot5_mean_T']:.3f} K")
+        paused = 0.0
+        if on_iter:
+            tp = time.time()
+            on_iter(1, self.T)
+            paused += time.time() - tp
+        at = None
         for it in range(2, max_iter + 1):
             s = self.dust_iteration(it)
-            hist.append((it, time.time() - t0, s))
+            hist.append((it, time.time() - t0 - paused, s))
             if log:
                 log(f"iteration {it}: <T> {s['mean_T']:.3f} K hot5 {s['hot5_mean_T']:.3f} K")
-            if converged(hist[-2][2], s, tol):
-                return hist, it
-        return hist, None
+            if on_iter:
+                tp = time.time()
+                on_iter(it, self.T)
+                paused += time.time() - tp
+            if at is None and converged(hist[-2][2], s, tol):
+                at = it
+                if until_stop:
+                    break
+        return hist, at

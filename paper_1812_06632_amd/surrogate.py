@@ -12,13 +12,16 @@ Inputs of the network (channels-last, S^3 cells, block averages of the
 cloud): the log10 of the optical depth of one cell at 0.55 um; the log10
 of 1 + the ratio of the unattenuated bolometric flux of the point
 sources, sum L / (4 pi d^2), to the bolometric 4 pi J of the external
-field; and the optically thin temperature of the cell -- the solution of
+field; the optically thin temperature of the cell -- the solution of
 4 pi sum_k w_k sigma_k B(nu_k, T) = 4 pi sum_k w_k sigma_k J_k with J the
-external field plus the unattenuated sources, L_nu / (16 pi^2 d^2) -- so
-that the network has only to learn the attenuation and the dust
-re-emission.  Output: log10 T, normalised by the training-set mean and
-standard deviation.  A prediction on a finer grid is trilinearly
-interpolated in log T.
+external field plus the unattenuated sources, L_nu / (16 pi^2 d^2); and
+the temperature T1 the constant sources alone give (the plain method's
+first iteration, which is run in any case).  Output: log10(T / T1), the
+part the dust re-emission adds and the iteration has to build up,
+normalised by the training-set mean and standard deviation.  The start
+field is T1 times the predicted ratio; on a finer grid the ratio is
+trilinearly interpolated and applied to T1 at full resolution, so the
+structure that T1 resolves is kept.
 
 Everything runs on the device through the library; torch supplies the
 device arrays and the elementwise glue (normalisation, flips, the
@@ -56,7 +59,7 @@ def _isrf_bolometric() -> float:
     return _ISRF_BOL
 
 
-N_FEATURES = 3
+N_FEATURES = 4
 
 
 def _planck(nu: np.ndarray, T: np.ndarray) -> np.ndarray:
@@ -78,8 +81,15 @@ def thin_temperature(P: W.Problem, Jw: np.ndarray) -> np.ndarray:
     return np.exp(np.interp(lg_in, lg_emit, np.log(Tg)))
 
 
-def features(P: W.Problem, S: int) -> np.ndarray:
-    """[S, S, S, 3] float32 network input of a regular cubic problem."""
+def _log_T(P: W.Problem, T: np.ndarray) -> np.ndarray:
+    """log10 of a temperature field with empty and unset cells at the floor."""
+    rho = P.grid.density()
+    return np.log10(np.where(rho > 0, np.maximum(T, P.T_floor), P.T_floor))
+
+
+def features(P: W.Problem, S: int, T1: np.ndarray) -> np.ndarray:
+    """[S, S, S, 4] float32 network input of a regular cubic problem whose
+    constant-source temperatures are T1 (one per cell)."""
     g = P.grid
     if g.nlevels != 1 or not (g.nx == g.ny == g.nz):
         raise ValueError("the surrogate takes regular cubic grids")
@@ -101,17 +111,15 @@ def features(P: W.Problem, S: int) -> np.ndarray:
             Jw += float(Lnu @ ws) / (16.0 * math.pi ** 2 * d2)
     f1 = np.log10(1.0 + ratio) / 4.0
     f2 = (np.log10(thin_temperature(P, Jw.reshape(-1))).reshape(S, S, S) - 1.5) / 0.5
-    return np.stack([f0, f1, f2], axis=-1).astype(np.float32)
+    f3 = (block_mean(_log_T(P, T1).reshape(n, n, n), S) - 1.5) / 0.5
+    return np.stack([f0, f1, f2, f3], axis=-1).astype(np.float32)
 
 
-def targets(P: W.Problem, T: np.ndarray, S: int) -> np.ndarray:
-    """[S, S, S, 1] float64: block means of log10 T (empty cells count at
-    the floor temperature)."""
-    g = P.grid
-    n = g.nx
-    rho = g.density()
-    Tc = np.where(rho > 0, np.maximum(T, P.T_floor), P.T_floor)
-    return block_mean(np.log10(Tc).reshape(n, n, n), S)[..., None]
+def targets(P: W.Problem, T: np.ndarray, T1: np.ndarray, S: int) -> np.ndarray:
+    """[S, S, S, 1] float64: block means of log10(T / T1) (empty cells at
+    the floor temperature on both sides, so they contribute zero)."""
+    n = P.grid.nx
+    return block_mean((_log_T(P, T) - _log_T(P, T1)).reshape(n, n, n), S)[..., None]
 
 
 TAU_RANGE = (2.0, 100.0)
@@ -150,8 +158,9 @@ def make_dataset(ctx: soc.Context, count: int, seed: int, n: int = 64, S: int = 
         P = random_problem(rng, n, K, packages)
         solver = PlainSolver(ctx, P, seed=seed * 100003 + m)
         _, at = solver.run(max_iter=max_iter)
-        X[m] = features(P, S)
-        Y[m] = targets(P, solver.T.cpu().numpy().astype(np.float64), S)
+        T1 = solver.T1.cpu().numpy().astype(np.float64)
+        X[m] = features(P, S, T1)
+        Y[m] = targets(P, solver.T.cpu().numpy().astype(np.float64), T1, S)
         if log and (m + 1) % 16 == 0:
             log(f"training cloud {m + 1}/{count} solved ({time.time() - t0:.1f}s, last stopped at iteration {at})")
     return X, Y
@@ -180,7 +189,7 @@ class Surrogate:
 
     def fit(self, X: np.ndarray, Y: np.ndarray, steps: int, lr: float = 3e-4, warmup: int = 200, seed: int = 0,
             log=None):
-        """Adam on the MSE of the normalised log T; the step size rises
+        """Adam on the MSE of the normalised log ratio; the step size rises
         linearly over `warmup` steps, then decays on a cosine to zero."""
         self.ymean = float(Y.mean())
         self.ystd = float(Y.std()) + 1e-6
@@ -207,19 +216,21 @@ class Surrogate:
                     log(f"training step {step}/{steps}: loss {loss:.4f} ({time.time() - t0:.1f}s)")
         return losses
 
-    def predict_T(self, P: W.Problem) -> torch.Tensor:
-        """Starting temperatures (device FP32, one per cell; 0 in empty
-        cells) for a regular cubic problem whose size is a multiple of S."""
+    def predict_T(self, P: W.Problem, T1: torch.Tensor) -> torch.Tensor:
+        """Start temperatures (device FP32, one per cell; 0 in empty cells)
+        of a regular cubic problem whose size is a multiple of S, from its
+        constant-source temperatures T1 (device, one per cell)."""
         n = P.grid.nx
-        x = torch.from_numpy(features(P, self.S)[None]).cuda()
+        x = torch.from_numpy(features(P, self.S, T1.cpu().numpy().astype(np.float64))[None]).cuda()
         y = self.net.forward(x)
-        lt = y[..., 0] * self.ystd + self.ymean
+        lr = y[..., 0] * self.ystd + self.ymean            # log10(T / T1) at S^3
         if n != self.S:
-            lt = torch.nn.functional.interpolate(lt[:, None], size=(n, n, n), mode="trilinear",
+            lr = torch.nn.functional.interpolate(lr[:, None], size=(n, n, n), mode="trilinear",
                                                  align_corners=False)[:, 0]
-        T = torch.pow(10.0, lt).reshape(-1).float()
         rho = torch.from_numpy(P.grid.density()).cuda()
-        return torch.where(rho > 0, T.clamp(P.T_floor, P.T_max), torch.zeros_like(T))
+        T1c = torch.clamp(T1.reshape(-1).float(), min=P.T_floor)
+        T = (T1c * torch.pow(10.0, lr.reshape(-1).float())).clamp(P.T_floor, P.T_max)
+        return torch.where(rho > 0, T, torch.zeros_like(T))
 
     def close(self):
         self.net.close()

@@ -23,8 +23,9 @@ def test_block_mean_is_the_mean_over_blocks():
 
 def test_features_optical_depth_and_source_flux():
     P = W.lognormal_problem(n=32, K=8, packages_per_freq=1000)
-    X = surrogate.features(P, 16)
-    assert X.shape == (16, 16, 16, 3) and X.dtype == np.float32
+    T1 = np.full(P.grid.ncells, 20.0)
+    X = surrogate.features(P, 16, T1)
+    assert X.shape == (16, 16, 16, 4) and X.dtype == np.float32
     # channel 0: log10 of the 0.55 um optical depth of a 2^3 block, / 2
     rho = P.grid.density().reshape(32, 32, 32).astype(np.float64)
     tau = W.SIGMA_V * rho[0:2, 2:4, 4:6].mean() * P.grid.root_cell_cm * 2
@@ -43,17 +44,23 @@ def test_features_optical_depth_and_source_flux():
     # no sources: channel 1 vanishes
     P.ps_pos = np.zeros((0, 3))
     P.ps_Lnu = np.zeros((0, 8))
-    assert np.all(surrogate.features(P, 16)[..., 1] == 0)
+    assert np.all(surrogate.features(P, 16, T1)[..., 1] == 0)
 
 
-def test_targets_use_the_floor_in_empty_cells():
+def test_targets_are_block_log_ratios_with_empty_cells_neutral():
     P = W.lognormal_problem(n=16, K=8, packages_per_freq=1000)
-    T = np.full(P.grid.ncells, 40.0)
-    Y = surrogate.targets(P, T, 8)
+    rng = np.random.default_rng(2)
+    T1 = rng.uniform(10.0, 50.0, P.grid.ncells)
+    T = T1 * 1.25
+    Y = surrogate.targets(P, T, T1, 8)
     assert Y.shape == (8, 8, 8, 1)
     rho = P.grid.density().reshape(16, 16, 16)
-    lt = np.where(rho > 0, math.log10(40.0), math.log10(P.T_floor))
-    assert np.allclose(Y[..., 0], surrogate.block_mean(lt, 8))
+    lr = np.where(rho > 0, math.log10(1.25), 0.0)     # empty cells sit at the floor on both sides
+    assert np.allclose(Y[..., 0], surrogate.block_mean(lr, 8))
+    # the fourth input channel carries the block mean of log10 T1
+    X = surrogate.features(P, 8, T1)
+    lt1 = np.where(rho > 0, np.log10(T1.reshape(16, 16, 16)), math.log10(P.T_floor))
+    assert np.allclose(X[..., 3], (surrogate.block_mean(lt1, 8) - 1.5) / 0.5, atol=1e-6)
 
 
 def test_training_family_ranges():
@@ -79,7 +86,7 @@ def test_thin_temperature_balances_absorption_and_emission():
     for the external field alone it is one value everywhere, it rises
     towards a point source, and the balance holds at the returned T."""
     P = W.lognormal_problem(n=16, K=32, packages_per_freq=1000)
-    X = surrogate.features(P, 8)
+    X = surrogate.features(P, 8, np.full(P.grid.ncells, 20.0))
     T = 10 ** (X[..., 2].astype(np.float64) * 0.5 + 1.5)
     J = P.I_bg[None, :]
     ws = P.w * P.sigma_abs
@@ -92,6 +99,6 @@ def test_thin_temperature_balances_absorption_and_emission():
     assert bal == pytest.approx(1.0, rel=2e-3)
     P.ps_pos = np.zeros((0, 3))
     P.ps_Lnu = np.zeros((0, 32))
-    X0 = surrogate.features(P, 8)
+    X0 = surrogate.features(P, 8, np.full(P.grid.ncells, 20.0))
     assert np.ptp(X0[..., 2]) < 1e-6
     assert 10 ** (float(X0[0, 0, 0, 2]) * 0.5 + 1.5) == pytest.approx(T1, rel=1e-5)
