@@ -68,15 +68,17 @@ const char *soc_last_error(soc_ctx ctx);
 typedef enum {
     SOC_OPT_STEP_CAP = 0,        /* steps per package before it is stopped [10000000] */
     SOC_OPT_BLOCK = 1,           /* threads per workgroup of the MC kernel, multiple of 64 in 64..512 [256] */
-    SOC_OPT_BLOCKS_PER_CU = 2,   /* persistent workgroups launched per compute unit [8] */
+    SOC_OPT_BLOCKS_PER_CU = 2,   /* persistent workgroups launched per compute unit [4] */
     SOC_OPT_REFILL_MIN = 3,      /* refill a wave once this many lanes are idle, 1..64 [1] */
     SOC_OPT_INNER_STEPS = 4,     /* cell steps between refill checks, 1..8 [1] */
     SOC_OPT_TIMING = 5,          /* 1 = time each MC launch with HIP events [0] */
     SOC_OPT_SCATTER_MIN = 6,     /* draw new directions once this many lanes of a wave wait for one, 1..64 [1] */
-    SOC_OPT_XCD_COPIES = 7       /* 1 = the waves of each XCD add into a private copy of the absorbed array
+    SOC_OPT_XCD_COPIES = 7,      /* 1 = the waves of each XCD add into a private copy of the absorbed array
                                     (chosen by the hardware XCC id; context scratch of 8 x ncells doubles),
                                     summed into d_absorbed by one kernel after the launch: spreads the
                                     same-address adds of hot cells over 8 addresses [1] */
+    SOC_OPT_CHUNK = 8            /* package ids a wave takes from the global counter at a time, 64..65536
+                                    (smaller: finer load balance between waves) [256] */
 } soc_option;
 soc_status soc_ctx_set_option(soc_ctx ctx, soc_option opt, int64_t value);
 soc_status soc_ctx_get_option(soc_ctx ctx, soc_option opt, int64_t *value);

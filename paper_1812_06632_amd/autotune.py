@@ -1,8 +1,9 @@
 """Autotuner for the persistent Monte Carlo launches.
 
 Chooses the launch schedule of the persistent kernels -- workgroup size,
-persistent workgroups per compute unit, lane-refill threshold, deferred
-scattering threshold and, for batches, the tile size -- by timing short
+persistent workgroups per compute unit, package ids per grant from the
+global counter, lane-refill threshold, deferred scattering threshold and,
+for batches, the tile size -- by timing short
 calibration runs with HIP events (the library's own per-launch timing) and
 keeps the fastest candidate per problem class.  The class key buckets the
 grid kind, the number of cells (powers of two), the optical depth of a
@@ -20,7 +21,8 @@ import os
 
 DEFAULT_SPACE = {
     "block": (128, 256, 512),
-    "blocks_per_cu": (4, 8, 16),
+    "blocks_per_cu": (2, 4, 8),
+    "chunk": (256, 512),
     "refill_min": (1, 16),
     "scatter_min": (1,),
 }

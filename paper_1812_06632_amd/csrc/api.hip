@@ -30,7 +30,7 @@ struct soc_ctx_s {
     int num_cus = 256;
     int64_t step_cap = 10000000;
     int64_t block = 256;
-    int64_t blocks_per_cu = 8;
+    int64_t blocks_per_cu = 4;
     int64_t refill_min = 1;
     int64_t inner_steps = 1;
     int64_t timing = 0;
@@ -373,6 +373,10 @@ soc_status soc_ctx_set_option(soc_ctx c, soc_option opt, int64_t v)
     case SOC_OPT_XCD_COPIES:
         c->xcd_copies = v ? 1 : 0;
         return SOC_OK;
+    case SOC_OPT_CHUNK:   // >= 64: one grant must cover every idle lane of a wave
+        if (v < 64 || v > 65536) return fail(c, SOC_EINVAL, "chunk must be in [64,65536]");
+        c->chunk = v;
+        return SOC_OK;
     }
     return fail(c, SOC_EINVAL, "unknown option %d", (int)opt);
 }
@@ -389,6 +393,7 @@ soc_status soc_ctx_get_option(soc_ctx c, soc_option opt, int64_t *v)
     case SOC_OPT_TIMING: *v = c->timing; return SOC_OK;
     case SOC_OPT_SCATTER_MIN: *v = c->scatter_min; return SOC_OK;
     case SOC_OPT_XCD_COPIES: *v = c->xcd_copies; return SOC_OK;
+    case SOC_OPT_CHUNK: *v = c->chunk; return SOC_OK;
     }
     return fail(c, SOC_EINVAL, "unknown option %d", (int)opt);
 }

@@ -240,12 +240,13 @@ def test_launch_configuration_independence(soc, ctx, cloud):
               dust_mode=1, T=Td, iteration=1, freq_index=k)
     ref, sref = _gpu_run(soc, ctx, g, P.grid.ncells, f, 77, **kw)
     saved = {n: ctx.get_option(n) for n in ("block", "blocks_per_cu", "refill_min", "inner_steps", "scatter_min",
-                                            "xcd_copies")}
+                                            "xcd_copies", "chunk")}
     try:
         for cfg in ({"block": 64, "blocks_per_cu": 1}, {"block": 512, "blocks_per_cu": 2},
                     {"refill_min": 32, "inner_steps": 7}, {"refill_min": 64, "inner_steps": 8},
                     {"scatter_min": 24}, {"scatter_min": 64, "inner_steps": 3},
-                    {"xcd_copies": 0}, {"xcd_copies": 0, "block": 128}, {"xcd_copies": 1, "block": 192}):
+                    {"xcd_copies": 0}, {"xcd_copies": 0, "block": 128}, {"xcd_copies": 1, "block": 192},
+                    {"chunk": 64}, {"chunk": 64, "refill_min": 16}, {"chunk": 4096}):
             for n_, v in cfg.items():
                 ctx.set_option(n_, v)
             A, st = _gpu_run(soc, ctx, g, P.grid.ncells, f, 77, **kw)
