@@ -32,7 +32,7 @@ class _Sources(C.Structure):
     _fields_ = [("I_bg_nu", C.c_double), ("n_ps", C.c_int32), ("ps_pos", C.POINTER(C.c_double)),
                 ("ps_L_nu", C.POINTER(C.c_double)), ("T", C.POINTER(C.c_float)),
                 ("n_bg", C.c_uint64), ("n_ps_pk", C.c_uint64), ("n_dust", C.c_uint64),
-                ("dust_mode", C.c_int32)]
+                ("dust_mode", C.c_int32), ("L_ref", C.POINTER(C.c_double)), ("dust_cap", C.c_double)]
 
 
 class _Stats(C.Structure):
@@ -69,7 +69,7 @@ def lib():
         L.orc_leaf.restype = C.c_int64
         L.orc_validate_grid.restype = C.c_int32
         for name in ("orc_simulate_frequency", "orc_trace_package", "orc_trace_from",
-                     "orc_update_temperature", "orc_map"):
+                     "orc_update_temperature", "orc_map", "orc_dust_luminosity"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -147,15 +147,18 @@ def hg_scatter(g, u0, xi):
 
 
 class _SourcesView:
-    def __init__(self, I_bg=0.0, ps_pos=None, ps_Lnu=None, T=None, n_bg=0, n_ps_pk=0, n_dust=0, dust_mode=1):
+    def __init__(self, I_bg=0.0, ps_pos=None, ps_Lnu=None, T=None, n_bg=0, n_ps_pk=0, n_dust=0, dust_mode=1,
+                 L_ref=None, dust_cap=0.0):
         self.pos = np.ascontiguousarray(ps_pos if ps_pos is not None else np.zeros((0, 3)), dtype=np.float64)
         self.L = np.ascontiguousarray(ps_Lnu if ps_Lnu is not None else np.zeros(0), dtype=np.float64)
         self.T = None if T is None else np.ascontiguousarray(T, dtype=np.float32)
+        self.Lref = None if L_ref is None else np.ascontiguousarray(L_ref, dtype=np.float64)
         n_ps = self.pos.shape[0]
         self.s = _Sources(float(I_bg), n_ps, _p(self.pos, C.c_double) if n_ps else None,
                           _p(self.L, C.c_double) if n_ps else None,
                           _p(self.T, C.c_float) if self.T is not None else None,
-                          int(n_bg), int(n_ps_pk), int(n_dust), int(dust_mode))
+                          int(n_bg), int(n_ps_pk), int(n_dust), int(dust_mode),
+                          _p(self.Lref, C.c_double) if self.Lref is not None else None, float(dust_cap))
 
 
 def _stats_dict(st):
@@ -163,14 +166,15 @@ def _stats_dict(st):
 
 
 def simulate_frequency(grid, freq, *, I_bg=0.0, ps_pos=None, ps_Lnu=None, T=None, n_bg=0, n_ps_pk=0,
-                       n_dust=0, dust_mode=1, seed=1, iteration=0, freq_index=0, step_cap=0,
-                       nthreads=1, absorbed=None, want_path=False, hits=None):
+                       n_dust=0, dust_mode=1, L_ref=None, dust_cap=0.0, seed=1, iteration=0, freq_index=0,
+                       step_cap=0, nthreads=1, absorbed=None, want_path=False, hits=None):
     """One Monte Carlo pass at one frequency.  freq = (nu, w, sigma_abs,
     sigma_sca, g).  Returns (absorbed float64[ncells], stats dict,
     path lengths or None).  hits: optional int64[ncells] accumulated with
-    the number of depositing segments per cell."""
+    the number of depositing segments per cell.  dust_mode 2 emits the
+    difference between the dust emission at T and L_ref (per cell, erg/s)."""
     gv = GridView(grid)
-    sv = _SourcesView(I_bg, ps_pos, ps_Lnu, T, n_bg, n_ps_pk, n_dust, dust_mode)
+    sv = _SourcesView(I_bg, ps_pos, ps_Lnu, T, n_bg, n_ps_pk, n_dust, dust_mode, L_ref, dust_cap)
     f = _freq(freq)
     if absorbed is None:
         absorbed = np.zeros(grid.ncells, dtype=np.float64)
@@ -188,10 +192,10 @@ def simulate_frequency(grid, freq, *, I_bg=0.0, ps_pos=None, ps_Lnu=None, T=None
 
 
 def trace_package(grid, freq, cls, package_id, *, I_bg=0.0, ps_pos=None, ps_Lnu=None, T=None, n_bg=0,
-                  n_ps_pk=0, n_dust=0, dust_mode=1, seed=1, iteration=0, freq_index=0, step_cap=0,
-                  max_seg=100000):
+                  n_ps_pk=0, n_dust=0, dust_mode=1, L_ref=None, dust_cap=0.0, seed=1, iteration=0, freq_index=0,
+                  step_cap=0, max_seg=100000):
     gv = GridView(grid)
-    sv = _SourcesView(I_bg, ps_pos, ps_Lnu, T, n_bg, n_ps_pk, n_dust, dust_mode)
+    sv = _SourcesView(I_bg, ps_pos, ps_Lnu, T, n_bg, n_ps_pk, n_dust, dust_mode, L_ref, dust_cap)
     f = _freq(freq)
     out = np.zeros(max_seg, dtype=SEGMENT_DTYPE)
     ns = C.c_int32()
@@ -202,6 +206,18 @@ def trace_package(grid, freq, cls, package_id, *, I_bg=0.0, ps_pos=None, ps_Lnu=
     if rc != 0:
         raise ValueError(f"orc_trace_package failed: {rc}")
     return out[: min(ns.value, max_seg)].copy()
+
+
+def dust_luminosity(grid, freq, T):
+    """Dust emission of every cell at one frequency (erg/s, times w)."""
+    gv = GridView(grid)
+    f = _freq(freq)
+    Tc = np.ascontiguousarray(T, dtype=np.float32)
+    L = np.zeros(grid.ncells, dtype=np.float64)
+    rc = lib().orc_dust_luminosity(C.byref(gv.s), C.byref(f), _p(Tc, C.c_float), _p(L, C.c_double))
+    if rc != 0:
+        raise ValueError(f"orc_dust_luminosity failed: {rc}")
+    return L
 
 
 def trace_from(grid, freq, p0, u0, W0, tau0, *, seed=1, package_id=0, step_cap=0, absorbed=None,

@@ -291,7 +291,7 @@ static void transport(const orc_grid *g, const orc_freq *f, double p[3], double 
             double lo2[3], sz2;
             if (orc_leaf(g, q2, lo2, &sz2) < 0) ev = ORC_ESCAPE;
         }
-        if (ev != ORC_ESCAPE && W < ORC_WFLOOR * W0) {
+        if (ev != ORC_ESCAPE && fabs(W) < ORC_WFLOOR * fabs(W0)) {
             if (absorbed) absorbed[c] += W;
             W = 0.0;
             ev = ORC_FLOOR;
@@ -328,9 +328,12 @@ typedef struct {
     uint32_t iteration, freq_index;
     int64_t cap;
     double E_bg, W_bg;
-    double *L;          /* dust luminosity per cell (NULL if no dust) */
-    double *incl;       /* inclusive cumulative sum of L */
-    double S;           /* sum of L */
+    double *L;          /* dust luminosity per cell, or its difference to the reference
+                           (mode 2); NULL if no dust */
+    double *incl;       /* inclusive cumulative sum of the expected package counts
+                           (modes 1, 2; in units of |L| when there is no cap) */
+    double S;           /* sum of |L| */
+    double X_total;     /* capped: expected package total, sum of the capped counts */
     int64_t last_pos;   /* last cell with L > 0 */
     int64_t *leaves;    /* leaf cells in index order */
     int64_t nleaves;
@@ -352,6 +355,37 @@ static double box_area_root(const orc_grid *g)
     return 2.0 * ((double)g->ny * g->nz + (double)g->nx * g->nz + (double)g->nx * g->ny);
 }
 
+/* Dust emission per cell at one frequency (Sect. 3.2): 4 pi sigma_abs n V
+ * B_nu(T) w in every leaf, 0 in refined cells. */
+static void dust_lum(const orc_grid *g, const orc_freq *f, const float *T, double *L)
+{
+    for (int64_t c = 0; c < g->ncells; ++c) {
+        double Lc = 0.0;
+        if (word_i(g, c) >= 0) {
+            double n = word_f(g, c);
+            Lc = 4.0 * ORC_PI * f->sigma_abs * n * cell_volume(g, c) * orc_planck(f->nu, (double)T[c]) * f->w_nu;
+        }
+        L[c] = Lc;
+    }
+}
+
+/* Expected number of packages of cell c in the weighted modes: its share
+ * N |L_c| / S of the N packages, at most the cap (Sect. 3.2). */
+static double expected_count(const sim_ctx *X, int64_t c)
+{
+    double x = (double)X->s->n_dust * fabs(X->L[c]) / X->S;
+    if (X->s->dust_cap > 0.0 && x > X->s->dust_cap) x = X->s->dust_cap;
+    return x;
+}
+
+int32_t orc_dust_luminosity(const orc_grid *g, const orc_freq *f, const float *T, double *L)
+{
+    if (!g || !f || !T || !L) return -1;
+    if (orc_validate_grid(g) != 0) return -4;
+    dust_lum(g, f, T, L);
+    return 0;
+}
+
 static int32_t sim_setup(sim_ctx *X)
 {
     const orc_grid *g = X->g;
@@ -366,19 +400,26 @@ static int32_t sim_setup(sim_ctx *X)
         X->L = (double *)malloc(sizeof(double) * (size_t)g->ncells);
         X->incl = (double *)malloc(sizeof(double) * (size_t)g->ncells);
         if (!X->L || !X->incl) return -3;
+        dust_lum(g, f, s->T, X->L);
+        if (s->dust_mode == 2 && s->L_ref)
+            for (int64_t c = 0; c < g->ncells; ++c) X->L[c] -= s->L_ref[c];
+        /* selection weight |L|; with a cap, the expected count of cell c is
+         * min(N |L_c| / S, cap) and the cumulative sum is in package units */
         double acc = 0.0;
         for (int64_t c = 0; c < g->ncells; ++c) {
-            double Lc = 0.0;
-            if (word_i(g, c) >= 0) {
-                double n = word_f(g, c);
-                Lc = 4.0 * ORC_PI * f->sigma_abs * n * cell_volume(g, c) * orc_planck(f->nu, (double)s->T[c]) * f->w_nu;
-            }
-            X->L[c] = Lc;
-            acc += Lc;
+            acc += fabs(X->L[c]);
             X->incl[c] = acc;
-            if (Lc > 0.0) X->last_pos = c;
+            if (X->L[c] != 0.0) X->last_pos = c;
         }
         X->S = acc;
+        if (s->dust_mode != 0 && s->dust_cap > 0.0 && acc > 0.0) {
+            double xacc = 0.0;
+            for (int64_t c = 0; c < g->ncells; ++c) {
+                xacc += expected_count(X, c);
+                X->incl[c] = xacc;
+            }
+            X->X_total = xacc;
+        }
         /* lower corners: roots from their indices, children from parents
          * (children always follow their parent in the cell vector) */
         X->cell_lo = (double *)malloc(sizeof(double) * 3 * (size_t)g->ncells);
@@ -425,10 +466,19 @@ static void sim_free(sim_ctx *X)
 }
 
 /* Weighted dust emission: package j of N takes the cell whose cumulative
- * luminosity interval contains x_j = (j + u) S / N (systematic sampling). */
+ * interval contains x_j = (j + u) S / N, in units of |L| (systematic
+ * sampling: cell c receives floor or ceil of N |L_c| / S packages).  With
+ * a cap the intervals are the capped expected counts and x_j = j + u;
+ * positions past their total emit nothing (-1). */
 static int64_t weighted_cell(const sim_ctx *X, uint64_t j)
 {
-    double x = (((double)j + X->u_sys) * X->S) / (double)X->s->n_dust;
+    double x;
+    if (X->s->dust_cap > 0.0) {
+        x = (double)j + X->u_sys;
+        if (x >= X->X_total) return -1;
+    } else {
+        x = (((double)j + X->u_sys) * X->S) / (double)X->s->n_dust;
+    }
     int64_t lo = 0, hi = X->g->ncells;  /* first c with incl[c] > x */
     while (lo < hi) {
         int64_t mid = lo + (hi - lo) / 2;
@@ -490,11 +540,15 @@ static double run_package(const sim_ctx *X, uint64_t gid, double *absorbed, int6
             c = X->leaves[j / X->per_leaf];
             W0 = X->L[c] / (double)X->per_leaf;
         } else {
+            /* each package of cell c carries L_c over the cell's expected
+             * count, so the packages of c sum to L_c on average; in mode 2
+             * L_c is the signed difference to the reference emission */
             if (!(X->S > 0.0)) return 0.0;
             c = weighted_cell(X, j);
-            W0 = X->S / (double)s->n_dust;
+            if (c < 0) return 0.0;
+            W0 = X->L[c] / expected_count(X, c);
         }
-        if (!(W0 > 0.0)) return 0.0;
+        if (!(fabs(W0) > 0.0)) return 0.0;
         double size = ldexp(1.0, -cell_level(g, c));
         const double *lo = X->cell_lo + 3 * c;
         double x0 = stream_next(&rs), x1 = stream_next(&rs), x2 = stream_next(&rs);
@@ -513,6 +567,8 @@ static int32_t check_inputs(const orc_grid *g, const orc_freq *f, const orc_sour
     if (!(f->sigma_abs >= 0.0) || !(f->sigma_sca >= 0.0) || !(fabs(f->g) < 1.0)) return -1;
     if (s->n_ps > 0 && (!s->ps_pos || !s->ps_L_nu)) return -1;
     if (s->n_ps > 253) return -1;
+    if (s->T && s->n_dust && (s->dust_mode < 0 || s->dust_mode > 2)) return -1;
+    if (!(s->dust_cap >= 0.0)) return -1;
     for (int32_t i = 0; i < s->n_ps; ++i) {
         double q[3] = {s->ps_pos[3 * i], s->ps_pos[3 * i + 1], s->ps_pos[3 * i + 2]}, lo[3], sz;
         if (orc_leaf(g, q, lo, &sz) < 0) return -1;

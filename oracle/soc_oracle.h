@@ -20,7 +20,10 @@
  *     in empty cells.
  *   - Sect. 3.2: dust re-emission with an equal number of packages per cell
  *     (uniform) or with package numbers proportional to cell luminosity
- *     (weighted).
+ *     (weighted), optionally with a cap on the packages of one cell.
+ *   - Sect. 2.1.2 (reference field): an iteration simulates only the
+ *     difference between the current dust emission and a reference
+ *     emission, with packages of either sign.
  * The paper prints no equations; the estimator and sampling rules below are
  * the textbook Monte Carlo readings recorded in the design notes:
  *   continuous absorption along each segment, free paths drawn in
@@ -65,7 +68,12 @@ typedef struct {
     uint64_t n_bg;             /* background packages */
     uint64_t n_ps_pk;          /* packages per point source */
     uint64_t n_dust;           /* dust-emission packages */
-    int32_t dust_mode;         /* 0 = equal count per leaf, 1 = luminosity weighted */
+    int32_t dust_mode;         /* 0 = equal count per leaf, 1 = luminosity weighted,
+                                  2 = correction to a reference emission (below) */
+    const double *L_ref;       /* dust_mode 2: reference emission of each cell at this
+                                  frequency (erg s^-1, already times w_nu); NULL = zero */
+    double dust_cap;           /* modes 1 and 2: expected packages per cell at most this
+                                  many (0 = no cap); the excess is not re-assigned */
 } orc_sources;
 
 typedef struct {
@@ -98,6 +106,10 @@ int32_t orc_validate_grid(const orc_grid *g);                  /* 0 ok, <0 malfo
 /* Henyey-Greenstein draw + rotation for statistical pins: n new directions
  * from u0 using pairs of uniforms (xi_mu, xi_phi) from `xi` (2n values). */
 void orc_hg_scatter(double g, const double u0[3], int32_t n, const double *xi, double *out3n);
+
+/* Dust emission of every cell at one frequency, 4 pi sigma_abs n V B_nu(T) w
+ * (0 in refined and empty cells), into L (ncells). */
+int32_t orc_dust_luminosity(const orc_grid *g, const orc_freq *f, const float *T, double *L);
 
 /* ---- the Monte Carlo pass at one frequency ---- */
 /* absorbed (+=) must hold ncells doubles.  path_len (optional) receives the

@@ -403,6 +403,93 @@ def test_dust_emission_counts():
     assert counts[0] == 0
 
 
+def test_correction_packages_negate_and_vanish():
+    """Reference-field correction (Sect. 2.1.2): with the reference twice the
+    current emission the correction is -L, drawn from the same cells with the
+    same random numbers, so every deposit and the escaped energy are exactly
+    the negatives of the weighted run (a sign, selection or weight-floor
+    slip breaks this); with the reference equal to the emission nothing is
+    emitted."""
+    rng = np.random.default_rng(41)
+    d = rng.uniform(0.2, 3.0, (5, 4, 6)).astype(np.float32)
+    d[1, 2, 3] = 0.0
+    g = W.regular_grid(d, 0.7)
+    T = rng.uniform(8.0, 80.0, g.ncells).astype(np.float32)
+    f = (6e12, 1.0, 0.9, 0.7, 0.4)
+    L = orc.dust_luminosity(g, f, T)
+    kw = dict(T=T, n_dust=3000, seed=5, iteration=3, freq_index=2)
+    A1, s1, _ = orc.simulate_frequency(g, f, dust_mode=1, **kw)
+    A2, s2, _ = orc.simulate_frequency(g, f, dust_mode=2, L_ref=2.0 * L, **kw)
+    assert s1["cell_steps"] == s2["cell_steps"] and s1["scatterings"] == s2["scatterings"]
+    assert np.array_equal(A2, -A1)
+    assert s2["e_emitted"] == -s1["e_emitted"] and s2["e_escaped"] == -s1["e_escaped"]
+    assert (A2.sum() + s2["e_escaped"]) / s2["e_emitted"] == pytest.approx(1.0, abs=1e-12)
+    A0, s0, _ = orc.simulate_frequency(g, f, dust_mode=2, L_ref=L, **kw)
+    assert not A0.any() and s0["e_emitted"] == 0.0 and s0["cell_steps"] == 0
+    # the luminosity is the frequency term of Gamma(T) = 4 pi sum w sigma B(T)
+    V = 0.7 ** 3
+    rho = d.ravel().astype(np.float64)
+    nz = rho > 0
+    gam = np.array([orc.gamma([6e12], [1.0], [0.9], float(t)) for t in T[nz]])
+    assert np.allclose(L[nz] / (rho[nz] * V), gam, rtol=1e-12)
+    assert not L[~nz].any()
+
+
+def _opaque_cells(seed, shape=(6, 6, 6)):
+    """A grid of very opaque pure absorbers (optical depth 1e7 per cell):
+    every package deposits its energy in the cell that emits it, up to a
+    leak of ~1e-7."""
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(0.5, 2.0, shape).astype(np.float32)
+    g = W.regular_grid(d, 1.0)
+    f = (5e12, 1.0, 1e7 / 2.0, 0.0, 0.0)
+    T = rng.uniform(8.0, 60.0, g.ncells).astype(np.float32)
+    return g, f, T
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_opaque_cells_absorb_their_own_emission_with_cap(mode):
+    """Opaque cells keep what they emit, so each cell's absorbed energy is its
+    package count times its package weight.  Weighted sampling (Sect. 3.2)
+    gives each cell the floor or the ceiling of its expected count with
+    packages that sum to the cell's emission on average; a cap of 12
+    packages per cell makes the brightest cells emit exactly 12 packages of
+    L_c / 12, i.e. exactly L_c.  Mode 2 does the same for the signed
+    difference to a reference.  Over independent draws every cell's mean
+    converges to its emission (unbiased with and without the cap)."""
+    g, f, T = _opaque_cells(43)
+    L = orc.dust_luminosity(g, f, T)
+    ref = None
+    target = L
+    if mode == 2:
+        ref = L * np.random.default_rng(44).uniform(0.0, 2.0, g.ncells)
+        target = L - ref
+    N, cap = 2000, 12.0
+    share = N * np.abs(target) / np.abs(target).sum()
+    capped = share > cap
+    assert 5 < capped.sum() < 100
+    kw = dict(T=T, n_dust=N, dust_mode=mode, L_ref=ref, iteration=2)
+    runs = []
+    for b in range(24):
+        A, st, _ = orc.simulate_frequency(g, f, dust_cap=cap, seed=300 + b, **kw)
+        assert A.sum() == pytest.approx(st["e_emitted"], rel=1e-9)
+        assert np.allclose(A[capped], target[capped], rtol=1e-5)
+        w = np.abs(target) / np.minimum(share, cap)       # one package of each cell
+        assert np.all(np.abs(A - target) <= w * (1 + 1e-5))
+        assert np.all(A * target >= 0)
+        runs.append(A)
+        if b < 4:
+            A0, _, _ = orc.simulate_frequency(g, f, seed=300 + b, **kw)
+            assert np.all(np.abs(A0 - target) <= np.abs(target).sum() / N * (1 + 1e-5))
+    m = np.mean(runs, axis=0)
+    se = np.std(runs, axis=0, ddof=1) / math.sqrt(len(runs))
+    ok = ~capped & (se > 1e-6 * np.abs(target))   # capped cells are exact: checked above
+    z = (m[ok] - target[ok]) / se[ok]
+    assert abs(z.mean()) < 0.25 and z.std() < 1.5
+    tot = np.array([r.sum() for r in runs])
+    assert abs(tot.mean() - target.sum()) < 4 * tot.std(ddof=1) / math.sqrt(len(runs)) + 1e-9 * np.abs(target).sum()
+
+
 def test_octree_refined_once_equals_doubled_regular_grid():
     """A grid with every root cell refined once into equal-density children
     describes the same medium as the regular grid of twice the resolution:
