@@ -132,17 +132,38 @@ typedef struct { double x, y, z, L_nu; } soc_point_source;   /* root units; erg 
  *  - point sources: n_ps <= 32 isotropic sources, each with n_ps_pk
  *    packages and energy L_nu w;
  *  - dust emission at temperatures d_T (NULL = off): cell c emits
- *    4 pi sigma_abs n_c V_c B_nu(T_c) w; dust_mode 0 sends the same number
- *    of packages from every leaf (n_dust must be a multiple of the leaf
- *    count), dust_mode 1 draws n_dust packages in proportion to the cell
- *    luminosity by systematic sampling. */
+ *    L_c = 4 pi sigma_abs n_c V_c B_nu(T_c) w; dust_mode 0 sends the same
+ *    number of packages from every leaf (n_dust must be a multiple of the
+ *    leaf count), dust_mode 1 draws n_dust packages in proportion to the
+ *    cell luminosity by systematic sampling (each cell gets the floor or
+ *    the ceiling of its share N L_c / sum L, each package carries
+ *    sum L / N);
+ *  - dust_mode 2, the reference-field correction (Sect. 2.1.2): the
+ *    packages carry only the difference dL_c = L_c - L_ref,c between the
+ *    emission at d_T and the reference emission d_L_ref of this frequency
+ *    (device, ncells FP64, erg s^-1 including w).  Cells are drawn in
+ *    proportion to |dL_c| as in mode 1 and each package carries the sign
+ *    of dL_c (negative packages deposit negative energy).  In the same call
+ *    d_L_ref is blended towards the current emission, L_ref += ref_beta
+ *    dL (ref_beta in [0, 1]; 0 leaves it unchanged; the packages use the
+ *    reference as it was on entry).  The absorbed energies of the
+ *    reference field itself are the caller's (see soc_reference_blend);
+ *  - dust_cap > 0 (modes 1 and 2): the expected number of packages of one
+ *    cell is limited to dust_cap (Sect. 3.2), min(N |dL_c| / S, dust_cap)
+ *    with S = sum |dL|; a package of a capped cell carries |dL_c| /
+ *    dust_cap, and the excess is not re-assigned to other cells (fewer
+ *    than n_dust packages are emitted; the rest are counted but carry
+ *    nothing).  0 = no cap. */
 typedef struct {
     double I_bg_nu;
     int32_t n_ps;
     const soc_point_source *ps;    /* host, n_ps entries */
     const float *d_T;              /* device, ncells temperatures, or NULL */
     uint64_t n_bg, n_ps_pk, n_dust;
-    int32_t dust_mode;
+    int32_t dust_mode;             /* 0 uniform, 1 weighted, 2 reference-field correction */
+    double *d_L_ref;               /* dust_mode 2: device, ncells FP64 reference emission, updated in place */
+    double ref_beta;               /* dust_mode 2: blend weight of this call's emission in d_L_ref */
+    double dust_cap;               /* modes 1, 2: packages per cell at most (expected), 0 = no cap */
 } soc_sources;
 
 typedef struct {
@@ -164,6 +185,13 @@ typedef struct {
 soc_status soc_simulate_frequency(soc_ctx ctx, soc_grid grid, const soc_freq *freq,
                                   const soc_sources *src, uint64_t seed, uint32_t iteration,
                                   uint32_t freq_index, double *d_absorbed, soc_sim_stats *stats);
+
+/* Reference-field running mean (Sect. 2.1.2): d_ref += beta (d_x - d_ref)
+ * over n FP64 device values, enqueued on the context's stream.  With the
+ * weight beta = n_i / (sum of the package counts so far) of iteration i it
+ * keeps the reference absorption the package-weighted mean of the
+ * iterations' absorption estimates.  beta in [0, 1]; SOC_EINVAL otherwise. */
+soc_status soc_reference_blend(soc_ctx ctx, int64_t n, double beta, const double *d_x, double *d_ref);
 
 /* Statistics summed over every soc_simulate_frequency call on the context
  * since the last reset (synchronises). */

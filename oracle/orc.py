@@ -267,3 +267,62 @@ def map_image(grid, freq, T, axis):
     if rc != 0:
         raise ValueError(f"orc_map failed: {rc}")
     return img.reshape(npy.value, npx.value)
+
+
+def iterate(P, *, seed, iterations, packages=None, reference=False, cap=0.0, nthreads=8, dust_seed=None):
+    """The iteration of Sect. 2.1.2 on a problem P (attributes of a
+    workloads.Problem: grid, nu, w, sigma_abs, sigma_sca, g, I_bg, ps_pos,
+    ps_Lnu, n_bg, n_ps_pk, n_dust, emit_nu, emit_w, emit_sigma_abs,
+    T_floor, T_max).
+
+    Iteration 1 simulates the constant sources (external field, point
+    sources) at every frequency and keeps their absorption A_const; its
+    temperatures come from A_const alone.  Iteration i >= 2 uses
+    packages(i) dust packages per frequency (default P.n_dust):
+      * plain: A_i = A_const + the dust emission at T_{i-1};
+      * reference field: the packages carry the difference between the
+        emission at T_{i-1} and the reference emission L_ref, A_i = A_ref +
+        their absorption, and both references then move to the
+        package-weighted running mean, X_ref += n_i / (n_2 + ... + n_i)
+        (X_i - X_ref) -- so the constant sources, part of A_ref from the
+        start, are never simulated again.
+    The dust packages draw from dust_seed (default: seed).  Returns
+    [(T_i, stats_i)] for i = 1..iterations."""
+    dseed = seed if dust_seed is None else dust_seed
+    g = P.grid
+    K = len(P.nu)
+    emit = (P.emit_nu, P.emit_w, P.emit_sigma_abs)
+    fr = [(P.nu[k], P.w[k], P.sigma_abs[k], P.sigma_sca[k], P.g[k]) for k in range(K)]
+    have_ps = len(P.ps_pos) > 0
+    A_const = np.zeros(g.ncells)
+    for k in range(K):
+        simulate_frequency(g, fr[k], I_bg=P.I_bg[k], ps_pos=P.ps_pos if have_ps else None,
+                           ps_Lnu=P.ps_Lnu[:, k] if have_ps else None, n_bg=P.n_bg,
+                           n_ps_pk=P.n_ps_pk if have_ps else 0, seed=seed, iteration=1, freq_index=k,
+                           nthreads=nthreads, absorbed=A_const)
+    T, st = update_temperature(g, *emit, A_const, T_floor=P.T_floor, T_max=P.T_max)
+    out = [(T, st)]
+    A_ref = A_const.copy()
+    L_ref = np.zeros((K, g.ncells))
+    n_sum = 0
+    for it in range(2, iterations + 1):
+        n = int(packages(it)) if packages is not None else int(P.n_dust)
+        if reference:
+            n_sum += n
+            beta = n / n_sum
+            A = A_ref.copy()
+            for k in range(K):
+                simulate_frequency(g, fr[k], T=T, n_dust=n, dust_mode=2, L_ref=L_ref[k], dust_cap=cap, seed=dseed,
+                                   iteration=it, freq_index=k, nthreads=nthreads, absorbed=A)
+                L_ref[k] += beta * (dust_luminosity(g, fr[k], T) - L_ref[k])
+        else:
+            A = A_const.copy()
+            for k in range(K):
+                simulate_frequency(g, fr[k], T=T, n_dust=n, dust_mode=1, dust_cap=cap, seed=dseed, iteration=it,
+                                   freq_index=k, nthreads=nthreads, absorbed=A)
+        T_new, st = update_temperature(g, *emit, A, T_old=T, T_floor=P.T_floor, T_max=P.T_max)
+        if reference:
+            A_ref += beta * (A - A_ref)
+        T = T_new
+        out.append((T, st))
+    return out

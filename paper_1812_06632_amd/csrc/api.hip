@@ -45,6 +45,8 @@ struct soc_ctx_s {
     int64_t cap_priv = 0;
     double *d_L = nullptr, *d_incl = nullptr, *d_scan = nullptr;
     int64_t cap_L = 0, cap_incl = 0, cap_scan = 0;
+    double *d_a = nullptr, *d_S = nullptr;   // selection weights / capped counts; sum of |L| (capped mode)
+    int64_t cap_a = 0, cap_S = 0;
     int32_t *d_pkcell = nullptr;
     uint64_t cap_pk = 0;
     double *d_tpart = nullptr;           // temperature statistics scratch
@@ -166,7 +168,12 @@ soc_status prepare(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *
     if (!finite_nonneg(s->I_bg_nu)) return fail(c, SOC_EINVAL, "I_bg_nu must be finite and >= 0");
     if (s->n_ps < 0 || s->n_ps > kMaxPs) return fail(c, SOC_EINVAL, "n_ps must be in [0, %d]", kMaxPs);
     if (s->n_ps > 0 && !s->ps) return fail(c, SOC_EINVAL, "ps is NULL");
-    if (s->d_T && s->dust_mode != 0 && s->dust_mode != 1) return fail(c, SOC_EINVAL, "dust_mode must be 0 or 1");
+    if (s->d_T && (s->dust_mode < 0 || s->dust_mode > 2)) return fail(c, SOC_EINVAL, "dust_mode must be 0, 1 or 2");
+    if (s->d_T && s->dust_mode == 2 && !s->d_L_ref) return fail(c, SOC_EINVAL, "dust_mode 2 needs d_L_ref");
+    if (!(s->ref_beta >= 0.0 && s->ref_beta <= 1.0)) return fail(c, SOC_EINVAL, "ref_beta must be in [0, 1]");
+    if (!finite_nonneg(s->dust_cap)) return fail(c, SOC_EINVAL, "dust_cap must be finite and >= 0");
+    if (s->d_T && s->dust_mode == 0 && s->dust_cap > 0.0)
+        return fail(c, SOC_EINVAL, "dust_cap applies to the weighted modes (1, 2)");
     if (s->n_bg > 0xFFFFFFFFull || s->n_ps_pk > 0xFFFFFFFFull || s->n_dust > 0x7FFFFFFFull)
         return fail(c, SOC_EINVAL, "package counts exceed the 32-bit package id range");
 
@@ -212,15 +219,23 @@ soc_status prepare(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *
         A.ps[i].W = A.n_ps_pk ? q.L_nu * f->w_nu / (double)A.n_ps_pk : 0.0;
     }
 
-    // dust emission: per-cell luminosity, inclusive cumulative sum and, for
-    // the weighted mode, the cell of every package
+    // dust emission: per-cell luminosity (or its difference to the
+    // reference), inclusive cumulative sum of the selection weights and,
+    // for the weighted modes, the cell of every package
     A.n_dust = 0;
     A.dust_mode = s->dust_mode;
     if (s->d_T && s->n_dust > 0) {
         A.n_dust = s->n_dust;
         if ((st = grow(c, &c->d_L, c->cap_L, g->ncells))) return st;
-        HIPCHK(c, launch_dust_luminosity(g->d_words, g->ncells, g->level_offset.data(), g->nlevels, s_cm, f->nu,
-                                         f->sigma_abs, f->w_nu, s->d_T, c->d_L, c->stream));
+        if (s->dust_mode == 2) {
+            if ((st = grow(c, &c->d_a, c->cap_a, g->ncells))) return st;
+            HIPCHK(c, launch_dust_correction(g->d_words, g->ncells, g->level_offset.data(), g->nlevels, s_cm, f->nu,
+                                             f->sigma_abs, f->w_nu, s->d_T, s->d_L_ref, s->ref_beta, c->d_L, c->d_a,
+                                             c->stream));
+        } else {
+            HIPCHK(c, launch_dust_luminosity(g->d_words, g->ncells, g->level_offset.data(), g->nlevels, s_cm, f->nu,
+                                             f->sigma_abs, f->w_nu, s->d_T, c->d_L, c->stream));
+        }
         A.dust_L = c->d_L;
         if (s->dust_mode == 0) {
             if (s->n_dust % (uint64_t)g->nleaves != 0)
@@ -229,9 +244,26 @@ soc_status prepare(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *
             A.per_leaf = s->n_dust / (uint64_t)g->nleaves;
             A.leaves = g->d_leaves;
         } else {
+            const bool capped = s->dust_cap > 0.0;
+            if (capped && s->dust_mode == 1) {
+                if ((st = grow(c, &c->d_a, c->cap_a, g->ncells))) return st;
+                HIPCHK(c, launch_abs_f64(c->d_L, c->d_a, g->ncells, c->stream));
+            }
+            const double *weight = s->dust_mode == 2 || capped ? c->d_a : c->d_L;
             if ((st = grow(c, &c->d_incl, c->cap_incl, g->ncells))) return st;
             if ((st = grow(c, &c->d_scan, c->cap_scan, (int64_t)scan_f64_scratch_elems(g->ncells)))) return st;
-            HIPCHK(c, launch_scan_f64(c->d_L, c->d_incl, g->ncells, c->d_scan, c->stream));
+            HIPCHK(c, launch_scan_f64(weight, c->d_incl, g->ncells, c->d_scan, c->stream));
+            A.dust_S = c->d_incl + (g->ncells - 1);
+            if (capped) {
+                // expected counts min(N a / S, cap) replace the weights; their
+                // cumulative sum (package units) replaces the first one
+                if ((st = grow(c, &c->d_S, c->cap_S, 1))) return st;
+                HIPCHK(c, launch_dust_cap(c->d_a, g->ncells, c->d_incl + (g->ncells - 1), c->d_S, s->n_dust,
+                                          s->dust_cap, c->stream));
+                HIPCHK(c, launch_scan_f64(c->d_a, c->d_incl, g->ncells, c->d_scan, c->stream));
+                A.dust_S = c->d_S;
+                A.dust_cap = s->dust_cap;
+            }
             int64_t cap_pk = (int64_t)c->cap_pk;
             if ((st = grow(c, &c->d_pkcell, cap_pk, (int64_t)s->n_dust))) return st;
             c->cap_pk = (uint64_t)cap_pk;
@@ -239,8 +271,8 @@ soc_status prepare(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *
             uint32_t x0 = 0, x1 = 0xFFFFFFFFu, x2 = freq_index, x3 = (iteration << 8) | kClassDust;
             philox4x32_10(x0, x1, x2, x3, (uint32_t)seed, (uint32_t)(seed >> 32));
             const double u_sys = u01<double>(x0);
-            HIPCHK(c, launch_dust_select(c->d_incl, g->ncells, s->n_dust, u_sys, c->d_pkcell, c->stream));
-            A.dust_incl = c->d_incl;
+            HIPCHK(c, launch_dust_select(c->d_incl, g->ncells, s->n_dust, u_sys, capped ? 1 : 0, c->d_pkcell,
+                                         c->stream));
             A.dust_cell = c->d_pkcell;
         }
     }
@@ -319,6 +351,8 @@ void soc_ctx_destroy(soc_ctx c)
     (void)hipFree(c->d_priv);
     (void)hipFree(c->d_L);
     (void)hipFree(c->d_incl);
+    (void)hipFree(c->d_a);
+    (void)hipFree(c->d_S);
     (void)hipFree(c->d_scan);
     (void)hipFree(c->d_pkcell);
     (void)hipFree(c->d_tpart);
@@ -578,6 +612,17 @@ soc_status soc_read_stats(soc_ctx c, soc_sim_stats *out, int32_t reset)
     return SOC_OK;
 }
 
+soc_status soc_reference_blend(soc_ctx c, int64_t n, double beta, const double *d_x, double *d_ref)
+{
+    if (!c) return SOC_EINVAL;
+    if (n < 0) return fail(c, SOC_EINVAL, "n must be >= 0");
+    if (n > 0 && (!d_x || !d_ref)) return fail(c, SOC_EINVAL, "array is NULL");
+    if (!(beta >= 0.0 && beta <= 1.0)) return fail(c, SOC_EINVAL, "beta must be in [0, 1]");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_blend(d_x, d_ref, n, beta, c->stream));
+    return SOC_OK;
+}
+
 soc_status soc_trace_packages(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *s, uint64_t seed,
                               uint32_t iteration, uint32_t freq_index, uint32_t cls, const uint32_t *ids, int32_t n,
                               int32_t precision, soc_segment *out, int32_t max_seg, int32_t *n_seg)
@@ -587,8 +632,11 @@ soc_status soc_trace_packages(soc_ctx c, soc_grid g, const soc_freq *f, const so
     if (!ids || !out || !n_seg || n <= 0 || max_seg <= 0) return fail(c, SOC_EINVAL, "bad trace buffers");
     if (precision != 0 && precision != 1) return fail(c, SOC_EINVAL, "precision must be 0 or 1");
     HIPCHK(c, hipSetDevice(c->device));
+    if (!s) return fail(c, SOC_EINVAL, "sources is NULL");
+    soc_sources s_trace = *s;
+    s_trace.ref_beta = 0.0;   // tracing leaves the reference emission as it is
     McArgs A;
-    soc_status st = prepare(c, g, f, s, seed, iteration, freq_index, nullptr, A);
+    soc_status st = prepare(c, g, f, &s_trace, seed, iteration, freq_index, nullptr, A);
     if (st) return st;
     uint64_t limit;
     if (cls == kClassBg) limit = A.n_bg;

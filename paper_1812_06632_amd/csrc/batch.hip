@@ -53,7 +53,8 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_batch_kernel(BatchArgs B)
     A.n_dust = 0;
     A.dust_mode = 1;
     A.dust_L = nullptr;
-    A.dust_incl = nullptr;
+    A.dust_S = nullptr;
+    A.dust_cap = 0.0;
     A.dust_cell = nullptr;
     A.leaves = nullptr;
     A.per_leaf = 1;
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_batch_kernel(BatchArgs B)
                 float d;
                 const StepOut o = step<float, false>(p, A, ks, ka, d);
                 n_st += 1;
-                if (o.dep > 0.0) {
+                if (o.dep != 0.0) {
                     lds_dep[nbuf * bd + tid] = o.dep;
                     lds_cell[nbuf * bd + tid] = o.cell;
                     ++nbuf;

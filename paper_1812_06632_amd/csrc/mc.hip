@@ -160,7 +160,7 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_kernel(McArgs A)
             // staged once, which spares the memory-side atomic unit a burst
             // of same-address adds.
             double dep = o.dep;
-            const bool first = stepping && first_step && dep > 0.0;
+            const bool first = stepping && first_step && dep != 0.0;
             if (stepping) first_step = false;
             const unsigned long long fm = __ballot(first);
             if (fm & (fm - 1)) {   // at least two lanes
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_kernel(McArgs A)
                     if (in) dep = lane == leader ? v : 0.0;
                 }
             }
-            if (dep > 0.0) {
+            if (dep != 0.0) {
                 lds_dep[nbuf * bd + tid] = dep;
                 lds_cell[nbuf * bd + tid] = o.cell;
                 ++nbuf;

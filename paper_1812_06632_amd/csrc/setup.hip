@@ -1,8 +1,10 @@
 // setup.hip -- per-frequency setup and grid preparation kernels.
 //
 //  * dust luminosity per cell, 4 pi sigma_abs n V B_nu(T) w (Sect. 3.2 dust
-//    re-emission), its inclusive prefix sum and the systematic selection
-//    of the cell of every weighted dust package;
+//    re-emission), or its difference to a reference emission (Sect. 2.1.2),
+//    its inclusive prefix sum, the capped expected package counts and the
+//    systematic selection of the cell of every weighted dust package;
+//  * the running-mean blend of the reference field;
 //  * device-side validation of the hierarchical grid and construction of
 //    the reverse (parent) links and the leaf list (Sect. 2.1.1);
 //  * small fills used instead of hipMemsetAsync so that captured graphs
@@ -114,6 +116,97 @@ hipError_t launch_dust_luminosity(const uint32_t *words, int64_t ncells, const i
     return hipGetLastError();
 }
 
+// Reference-field emission (Sect. 2.1.2): the difference between the
+// dust emission at T and the reference emission, its magnitude (the
+// selection weight), and the reference blended towards the current
+// emission with weight beta.
+__global__ void dust_correction_kernel(const uint32_t *words, int64_t ncells, Levels lv, int32_t nlevels,
+                                       double root_cell_cm, double nu, double sigma_abs, double w_nu,
+                                       const float *T, double *L_ref, double beta, double *dL, double *a)
+{
+    const double four_pi = 12.566370614359172;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncells; c += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t w = words[c];
+        double L = 0.0;
+        if ((int32_t)w >= 0) {
+            const double n = (double)__uint_as_float(w);
+            const int Lv = level_of(c, lv.off, nlevels);
+            const double s = ldexp(root_cell_cm, -Lv);
+            L = four_pi * sigma_abs * n * (s * s * s) * planck_nu(nu, (double)T[c]) * w_nu;
+        }
+        const double r = L_ref[c];
+        const double d = L - r;
+        dL[c] = d;
+        a[c] = fabs(d);
+        if (beta != 0.0) L_ref[c] = r + beta * d;
+    }
+}
+
+hipError_t launch_dust_correction(const uint32_t *words, int64_t ncells, const int64_t *level_offset,
+                                  int32_t nlevels, double root_cell_cm, double nu, double sigma_abs,
+                                  double w_nu, const float *T, double *L_ref, double beta, double *dL, double *a,
+                                  hipStream_t s)
+{
+    Levels lv;
+    for (int i = 0; i <= kMaxLevels; ++i) lv.off[i] = i <= nlevels ? level_offset[i] : ncells;
+    int64_t blocks = (ncells + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(dust_correction_kernel, dim3((unsigned)blocks), dim3(256), 0, s, words, ncells, lv,
+                       nlevels, root_cell_cm, nu, sigma_abs, w_nu, T, L_ref, beta, dL, a);
+    return hipGetLastError();
+}
+
+__global__ void abs_f64_kernel(const double *L, double *a, int64_t n)
+{
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
+        a[c] = fabs(L[c]);
+}
+
+hipError_t launch_abs_f64(const double *L, double *a, int64_t n, hipStream_t s)
+{
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(abs_f64_kernel, dim3((unsigned)blocks), dim3(256), 0, s, L, a, n);
+    return hipGetLastError();
+}
+
+// Emission-weighting cap (Sect. 3.2): the expected package count of a
+// cell, N a_c / S, limited to `cap`; the excess is not re-assigned.
+__global__ void dust_cap_kernel(double *a, int64_t n, const double *S_in, double *S_out, uint64_t n_dust, double cap)
+{
+    const double S = *S_in;
+    if (threadIdx.x == 0 && blockIdx.x == 0) *S_out = S;
+    const double scale = S > 0.0 ? (double)n_dust / S : 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
+        a[c] = fmin(a[c] * scale, cap);
+}
+
+hipError_t launch_dust_cap(double *a, int64_t n, const double *S_in, double *S_out, uint64_t n_dust, double cap,
+                           hipStream_t s)
+{
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(dust_cap_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, n, S_in, S_out, n_dust, cap);
+    return hipGetLastError();
+}
+
+__global__ void blend_kernel(const double *x, double *ref, int64_t n, double beta)
+{
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+        const double r = ref[c];
+        ref[c] = r + beta * (x[c] - r);
+    }
+}
+
+hipError_t launch_blend(const double *x, double *ref, int64_t n, double beta, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(blend_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, ref, n, beta);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ scans
 // Three-pass inclusive scan: tile sums, a single-workgroup scan of the tile
 // sums (looping over chunks with a carry), then the per-tile scan with its
@@ -216,13 +309,20 @@ hipError_t launch_scan_f64(const double *in, double *out, int64_t n, double *scr
 }
 
 // Weighted dust emission: package j takes the first cell whose inclusive
-// cumulative luminosity exceeds x_j = (j + u) S / N (systematic sampling:
-// every cell receives floor or ceil of N L_c / S packages).
-__global__ void dust_select_kernel(const double *incl, int64_t ncells, uint64_t n_dust, double u_sys, int32_t *cell)
+// cumulative weight exceeds x_j = (j + u) S / N (systematic sampling:
+// every cell receives floor or ceil of N a_c / S packages).  In package
+// units (capped expected counts) x_j = j + u, and positions at or past the
+// total emit nothing.
+__global__ void dust_select_kernel(const double *incl, int64_t ncells, uint64_t n_dust, double u_sys,
+                                   int32_t package_units, int32_t *cell)
 {
     const double S = incl[ncells - 1];
     for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_dust; j += (uint64_t)gridDim.x * blockDim.x) {
-        const double x = (((double)j + u_sys) * S) / (double)n_dust;
+        const double x = package_units ? (double)j + u_sys : (((double)j + u_sys) * S) / (double)n_dust;
+        if (package_units ? !(x < S) : !(S > 0.0)) {   // past the capped total, or nothing to emit
+            cell[j] = -1;
+            continue;
+        }
         int64_t lo = 0, hi = ncells;
         while (lo < hi) {
             const int64_t mid = lo + ((hi - lo) >> 1);
@@ -237,14 +337,14 @@ __global__ void dust_select_kernel(const double *incl, int64_t ncells, uint64_t 
     }
 }
 
-hipError_t launch_dust_select(const double *incl, int64_t ncells, uint64_t n_dust, double u_sys,
+hipError_t launch_dust_select(const double *incl, int64_t ncells, uint64_t n_dust, double u_sys, int32_t package_units,
                               int32_t *cell_out, hipStream_t s)
 {
     if (n_dust == 0) return hipSuccess;
     uint64_t blocks = (n_dust + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(dust_select_kernel, dim3((unsigned)blocks), dim3(256), 0, s, incl, ncells, n_dust, u_sys,
-                       cell_out);
+                       package_units, cell_out);
     return hipGetLastError();
 }
 

@@ -392,10 +392,22 @@ __device__ inline bool emit(const AT &A, uint64_t gid, Pkg<R> &p, Rng &rng, uint
             c = A.leaves ? A.leaves[j / A.per_leaf] : (int64_t)(j / A.per_leaf);
             W0 = A.dust_L[c] / (double)A.per_leaf;
         } else {
+            // a package of cell c carries L_c over the cell's expected
+            // count min(N |L_c| / S, cap): S / N, or |L_c| / cap for a
+            // capped cell, with the sign of L_c (mode 2 emits the signed
+            // difference to the reference emission)
             c = A.dust_cell[j];
-            W0 = A.dust_incl[A.ncells - 1] / (double)A.n_dust;
+            if (c < 0) return false;
+            const double WN = *A.dust_S / (double)A.n_dust;
+            if (A.dust_mode == 1 && !(A.dust_cap > 0.0)) {
+                W0 = WN;
+            } else {
+                const double Lc = A.dust_L[c];
+                const double m = A.dust_cap > 0.0 ? fmax(WN, fabs(Lc) / A.dust_cap) : WN;
+                W0 = copysign(m, Lc);
+            }
         }
-        if (!(W0 > 0.0)) return false;
+        if (!(fabs(W0) > 0.0)) return false;
         int64_t root = c;
         if (Oct) {
             // level of the leaf, then up through the reverse links to its root ancestor
@@ -419,7 +431,7 @@ __device__ inline bool emit(const AT &A, uint64_t gid, Pkg<R> &p, Rng &rng, uint
     set_inverse(p);
     p.tau = -m_log(next_u<R>(rng, A));
     p.W = W0;
-    p.Wfloor = 1e-12 * W0;
+    p.Wfloor = 1e-12 * fabs(W0);
     p.steps = 0;
     return true;
 }
@@ -517,7 +529,7 @@ __device__ inline StepOut step(Pkg<R> &p, const AT &A, R ks_scale, R ka_scale, R
     p.steps += 1;
     d_out = d * edge;
     if (ev != kEvEscape) {
-        if (p.W < p.Wfloor) {
+        if (fabs(p.W) < p.Wfloor) {
             dep += p.W;
             p.W = 0.0;
             ev = kEvFloor;

@@ -53,9 +53,10 @@ struct McArgs {
     double face_cum[6];
     double face_tot;
     PsArg ps[kMaxPs];
-    const double *dust_L;        // per-cell luminosity (uniform mode)
-    const double *dust_incl;     // inclusive cumulative luminosity (weighted mode)
-    const int32_t *dust_cell;    // cell of every dust package (weighted mode)
+    const double *dust_L;        // per-cell luminosity; its difference to the reference (mode 2)
+    const double *dust_S;        // weighted modes: device scalar, sum over cells of |dust_L|
+    double dust_cap;             // weighted modes: expected packages per cell at most this (0 = no cap)
+    const int32_t *dust_cell;    // cell of every dust package (weighted modes; -1 = none)
     const int64_t *leaves;       // leaf list (octree, uniform mode); NULL = identity
     uint64_t per_leaf;
     // random numbers
@@ -101,8 +102,26 @@ hipError_t launch_dust_luminosity(const uint32_t *words, int64_t ncells, const i
                                   double w_nu, const float *T, double *L, hipStream_t s);
 size_t scan_f64_scratch_elems(int64_t n);
 hipError_t launch_scan_f64(const double *in, double *out, int64_t n, double *scratch, hipStream_t s);
-hipError_t launch_dust_select(const double *incl, int64_t ncells, uint64_t n_dust, double u_sys,
+// Correction emission: L = L(T) - L_ref into dL, |dL| into a, and
+// L_ref += beta dL (no write when beta == 0).
+hipError_t launch_dust_correction(const uint32_t *words, int64_t ncells, const int64_t *level_offset,
+                                  int32_t nlevels, double root_cell_cm, double nu, double sigma_abs,
+                                  double w_nu, const float *T, double *L_ref, double beta, double *dL, double *a,
+                                  hipStream_t s);
+// |L| into a.
+hipError_t launch_abs_f64(const double *L, double *a, int64_t n, hipStream_t s);
+// Capped expected counts: x_c = min(N a_c / S, cap) in place, S = *S_in
+// (copied to *S_out first by every workgroup's first thread).
+hipError_t launch_dust_cap(double *a, int64_t n, const double *S_in, double *S_out, uint64_t n_dust, double cap,
+                           hipStream_t s);
+// Systematic selection over an inclusive cumulative sum: package j takes
+// the first cell whose cumulative value exceeds (j + u) S / N (units of
+// the selection weight), or, in package units, j + u (cell -1 past the
+// total).
+hipError_t launch_dust_select(const double *incl, int64_t ncells, uint64_t n_dust, double u_sys, int32_t package_units,
                               int32_t *cell_out, hipStream_t s);
+// ref += beta (x - ref) over n doubles.
+hipError_t launch_blend(const double *x, double *ref, int64_t n, double beta, hipStream_t s);
 
 // grid validation / reverse links / leaf list
 hipError_t launch_validate_grid(const uint32_t *words, int64_t ncells, const int64_t *level_offset,
@@ -191,7 +210,8 @@ struct BatchView {
     double face_cum[6];
     double face_tot;
     const PsArg *ps;
-    const double *dust_L, *dust_incl;
+    const double *dust_L, *dust_S;
+    double dust_cap;
     const int32_t *dust_cell;
     const int64_t *leaves;
     uint64_t per_leaf;

@@ -1,12 +1,18 @@
-"""Iteration driver of the plain method (Sect. 2.1.2, 3.3 of the paper).
+"""Iteration drivers (Sect. 2.1.2, 3.3, 4.4 of the paper).
 
-The constant sources (external field, point sources) are simulated once at
-every frequency and their absorbed energies kept; each later iteration
-re-simulates the dust emission at the current temperatures on top of the
-kept absorption and solves new temperatures.  The run stops when the
-relative change of the mean temperature, over all cells and over the
-hottest 5% of cells, falls below the tolerance between two consecutive
+Plain method: the constant sources (external field, point sources) are
+simulated once at every frequency and their absorbed energies kept; each
+later iteration re-simulates the dust emission at the current temperatures
+on top of the kept absorption and solves new temperatures.  The run stops
+when the relative change of the mean temperature, over all cells and over
+the hottest 5% of cells, falls below the tolerance between two consecutive
 iterations (the paper's two convergence statistics).
+
+Reference-field method: each dust iteration simulates only the difference
+between the current emission and a reference emission (packages of either
+sign), adds their absorption to the reference absorption, and moves both
+references to the package-weighted running mean; the number of packages
+may grow over the iterations (a geometric schedule).
 
 Control flow only: every step is a call through the C-ABI library; the
 stopping rule compares two scalars the temperature kernel returns.
@@ -29,8 +35,13 @@ def converged(prev: dict, cur: dict, tol: float = 0.01) -> bool:
 class PlainSolver:
     """One problem (workloads.Problem) resident on the device."""
 
-    def __init__(self, ctx: soc.Context, P, seed: int = 1, nT: int = 4096):
+    def __init__(self, ctx: soc.Context, P, seed: int = 1, nT: int = 4096, packages=None, cap: float = 0.0):
+        """packages(it): dust packages per frequency of iteration it
+        (default P.n_dust); cap: expected packages per cell at most (0 =
+        none)."""
         self.ctx, self.P, self.seed = ctx, P, seed
+        self.packages = packages
+        self.cap = float(cap)
         self.grid = soc.grid_from_workload(ctx, P.grid)
         self.table = soc.temp_table_build(ctx, P.emit_nu, P.emit_w, P.emit_sigma_abs, P.T_floor, P.T_max, nT)
         nc = P.grid.ncells
@@ -69,13 +80,18 @@ class PlainSolver:
         """Dust emission at the current temperatures on top of the kept
         constant-source absorption, then the temperature solve."""
         P = self.P
+        n = self.n_packages(it)
         self.A.copy_(self.A_const)
         for k in range(P.K):
-            soc.simulate_frequency(self.ctx, self.grid, self.freqs[k], self.A, T=self.T, n_dust=P.n_dust, dust_mode=1,
-                                   seed=self.seed, iteration=it, freq_index=k)
+            soc.simulate_frequency(self.ctx, self.grid, self.freqs[k], self.A, T=self.T, n_dust=n, dust_mode=1,
+                                   dust_cap=self.cap, seed=self.seed, iteration=it, freq_index=k)
         s = soc.update_temperature(self.ctx, self.grid, self.table, self.A, self.T_new, self.T, stats=True)
         self.T.copy_(self.T_new)
+        s["packages"] = n
         return s
+
+    def n_packages(self, it: int) -> int:
+        return int(self.packages(it)) if self.packages is not None else int(self.P.n_dust)
 
     def run(self, max_iter: int = 30, tol: float = 0.01, T0=None, log=None, on_iter=None, until_stop: bool = True):
         """Constant pass, optional start temperatures, dust iterations until
@@ -117,3 +133,60 @@ class PlainSolver:
                 if until_stop:
                     break
         return hist, at
+
+
+def geometric_schedule(n_final: int, factor: float, iterations: int):
+    """Packages per frequency for dust iterations 2..iterations, growing so
+    that log n is linear in the iteration number, from n_final / factor at
+    iteration 2 to n_final at the last (Sect. 4.4)."""
+    if iterations < 2 or factor < 1.0 or n_final < 1:
+        raise ValueError("need iterations >= 2, factor >= 1, n_final >= 1")
+
+    def n(it: int) -> int:
+        if iterations == 2:
+            return n_final
+        t = min(max((it - 2) / (iterations - 2), 0.0), 1.0)
+        return max(1, int(round(n_final * factor ** (t - 1.0))))
+
+    return n
+
+
+class ReferenceFieldSolver(PlainSolver):
+    """Reference-field iteration (Sect. 2.1.2).  Device state: the
+    reference emission per frequency and cell (FP64, K x ncells) and the
+    reference absorption (FP64, ncells).  After the constant pass the
+    reference absorption is the constant sources' and the reference
+    emission zero; dust iteration i with n_i packages per frequency
+    simulates L(T_{i-1}) - L_ref (the library blends L_ref by
+    beta_i = n_i / (n_2 + ... + n_i) in the same call), solves T_i from
+    A_i = A_ref + that absorption, then blends A_ref by the same beta."""
+
+    def __init__(self, ctx: soc.Context, P, seed: int = 1, nT: int = 4096, packages=None, cap: float = 0.0):
+        super().__init__(ctx, P, seed, nT, packages, cap)
+        nc = P.grid.ncells
+        self.L_ref = torch.zeros((P.K, nc), dtype=torch.float64, device="cuda")
+        self.A_ref = torch.zeros(nc, dtype=torch.float64, device="cuda")
+        self.n_sum = 0
+
+    def constant_pass(self) -> dict:
+        s = super().constant_pass()
+        self.A_ref.copy_(self.A_const)
+        self.L_ref.zero_()
+        self.n_sum = 0
+        return s
+
+    def dust_iteration(self, it: int) -> dict:
+        P = self.P
+        n = self.n_packages(it)
+        self.n_sum += n
+        beta = n / self.n_sum
+        self.A.copy_(self.A_ref)
+        for k in range(P.K):
+            soc.simulate_frequency(self.ctx, self.grid, self.freqs[k], self.A, T=self.T, n_dust=n, dust_mode=2,
+                                   L_ref=self.L_ref[k], ref_beta=beta, dust_cap=self.cap, seed=self.seed,
+                                   iteration=it, freq_index=k)
+        s = soc.update_temperature(self.ctx, self.grid, self.table, self.A, self.T_new, self.T, stats=True)
+        soc.reference_blend(self.ctx, self.A, self.A_ref, beta)
+        self.T.copy_(self.T_new)
+        s["packages"] = n
+        return s

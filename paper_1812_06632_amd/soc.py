@@ -52,7 +52,8 @@ class _PointSource(C.Structure):
 class _Sources(C.Structure):
     _fields_ = [("I_bg_nu", C.c_double), ("n_ps", C.c_int32), ("ps", C.POINTER(_PointSource)),
                 ("d_T", C.c_void_p), ("n_bg", C.c_uint64), ("n_ps_pk", C.c_uint64), ("n_dust", C.c_uint64),
-                ("dust_mode", C.c_int32)]
+                ("dust_mode", C.c_int32), ("d_L_ref", C.c_void_p), ("ref_beta", C.c_double),
+                ("dust_cap", C.c_double)]
 
 
 class _SimStats(C.Structure):
@@ -81,6 +82,7 @@ _lib.soc_grid_destroy.argtypes = [C.c_void_p]
 _lib.soc_grid_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_void_p)]
 _lib.soc_simulate_frequency.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Freq), C.POINTER(_Sources), C.c_uint64,
                                         C.c_uint32, C.c_uint32, C.c_void_p, C.POINTER(_SimStats)]
+_lib.soc_reference_blend.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_void_p, C.c_void_p]
 _lib.soc_read_stats.argtypes = [C.c_void_p, C.POINTER(_SimStats), C.c_int32]
 _lib.soc_trace_packages.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Freq), C.POINTER(_Sources), C.c_uint64,
                                     C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint32), C.c_int32, C.c_int32,
@@ -212,24 +214,30 @@ def _freq(f):
 
 
 class _SourceView:
-    def __init__(self, I_bg=0.0, ps_pos=None, ps_Lnu=None, T=None, n_bg=0, n_ps_pk=0, n_dust=0, dust_mode=1):
+    def __init__(self, I_bg=0.0, ps_pos=None, ps_Lnu=None, T=None, n_bg=0, n_ps_pk=0, n_dust=0, dust_mode=1,
+                 L_ref=None, ref_beta=0.0, dust_cap=0.0):
         pos = np.zeros((0, 3)) if ps_pos is None else np.asarray(ps_pos, dtype=np.float64).reshape(-1, 3)
         L = np.zeros(0) if ps_Lnu is None else np.asarray(ps_Lnu, dtype=np.float64).reshape(-1)
         n_ps = pos.shape[0]
         self.arr = (_PointSource * max(n_ps, 1))(*[_PointSource(*pos[i], L[i]) for i in range(n_ps)])
         self.T = T
+        self.L_ref = L_ref
         self.s = _Sources(float(I_bg), n_ps, C.cast(self.arr, C.POINTER(_PointSource)) if n_ps else None,
                           _dev_ptr(T, torch.float32, "T") if T is not None else None,
-                          int(n_bg), int(n_ps_pk), int(n_dust), int(dust_mode))
+                          int(n_bg), int(n_ps_pk), int(n_dust), int(dust_mode),
+                          _dev_ptr(L_ref, torch.float64, "L_ref") if L_ref is not None else None,
+                          float(ref_beta), float(dust_cap))
 
 
 def simulate_frequency(ctx: Context, grid: Grid, freq, absorbed: torch.Tensor, *, I_bg=0.0, ps_pos=None,
-                       ps_Lnu=None, T=None, n_bg=0, n_ps_pk=0, n_dust=0, dust_mode=1, seed=1, iteration=0,
-                       freq_index=0, stats=False):
+                       ps_Lnu=None, T=None, n_bg=0, n_ps_pk=0, n_dust=0, dust_mode=1, L_ref=None, ref_beta=0.0,
+                       dust_cap=0.0, seed=1, iteration=0, freq_index=0, stats=False):
     """soc_simulate_frequency.  freq = (nu, w_nu, sigma_abs, sigma_sca, g);
-    absorbed: float64 CUDA tensor of ncells (accumulated).  Returns the
-    call's statistics dict if stats, else None (asynchronous)."""
-    sv = _SourceView(I_bg, ps_pos, ps_Lnu, T, n_bg, n_ps_pk, n_dust, dust_mode)
+    absorbed: float64 CUDA tensor of ncells (accumulated).  dust_mode 2
+    emits the difference to L_ref (float64 CUDA tensor of ncells, blended
+    in place with weight ref_beta).  Returns the call's statistics dict if
+    stats, else None (asynchronous)."""
+    sv = _SourceView(I_bg, ps_pos, ps_Lnu, T, n_bg, n_ps_pk, n_dust, dust_mode, L_ref, ref_beta, dust_cap)
     f = _freq(freq)
     st = _SimStats() if stats else None
     ctx.check(_lib.soc_simulate_frequency(ctx.h, grid.h, C.byref(f), C.byref(sv.s), C.c_uint64(seed),
@@ -242,14 +250,14 @@ def simulate_frequency(ctx: Context, grid: Grid, freq, absorbed: torch.Tensor, *
 
 
 def trace_packages(ctx: Context, grid: Grid, freq, cls, ids, *, precision=0, max_seg=4096, I_bg=0.0, ps_pos=None,
-                   ps_Lnu=None, T=None, n_bg=0, n_ps_pk=0, n_dust=0, dust_mode=1, seed=1, iteration=0,
-                   freq_index=0):
+                   ps_Lnu=None, T=None, n_bg=0, n_ps_pk=0, n_dust=0, dust_mode=1, L_ref=None, dust_cap=0.0, seed=1,
+                   iteration=0, freq_index=0):
     """soc_trace_packages: returns (segments[n, max_seg], n_seg[n])."""
     ids = np.ascontiguousarray(ids, dtype=np.uint32)
     n = ids.shape[0]
     out = np.zeros((n, max_seg), dtype=SEGMENT_DTYPE)
     nseg = np.zeros(n, dtype=np.int32)
-    sv = _SourceView(I_bg, ps_pos, ps_Lnu, T, n_bg, n_ps_pk, n_dust, dust_mode)
+    sv = _SourceView(I_bg, ps_pos, ps_Lnu, T, n_bg, n_ps_pk, n_dust, dust_mode, L_ref, 0.0, dust_cap)
     f = _freq(freq)
     ctx.check(_lib.soc_trace_packages(ctx.h, grid.h, C.byref(f), C.byref(sv.s), C.c_uint64(seed),
                                       C.c_uint32(iteration), C.c_uint32(freq_index), C.c_uint32(cls),
@@ -257,6 +265,14 @@ def trace_packages(ctx: Context, grid: Grid, freq, cls, ids, *, precision=0, max
                                       C.c_void_p(out.ctypes.data), int(max_seg),
                                       nseg.ctypes.data_as(C.POINTER(C.c_int32))))
     return out, nseg
+
+
+def reference_blend(ctx: Context, x: torch.Tensor, ref: torch.Tensor, beta: float):
+    """soc_reference_blend: ref += beta (x - ref), float64 CUDA tensors."""
+    if x.numel() != ref.numel():
+        raise ValueError("x and ref differ in size")
+    ctx.check(_lib.soc_reference_blend(ctx.h, C.c_int64(ref.numel()), C.c_double(beta),
+                                       _dev_ptr(x, torch.float64, "x"), _dev_ptr(ref, torch.float64, "ref")))
 
 
 class TempTable:

@@ -10,7 +10,16 @@ TINY = 1e-5   # segments shorter than this (cell units) are tie artefacts: a
 
 
 def _clean(seg):
-    return seg[seg["ds"] > TINY]
+    """Segments longer than TINY; the length of each shorter one is added
+    to the segment before it, so that a crossing split in two at a tie
+    keeps its whole length on both sides."""
+    keep = seg["ds"] > TINY
+    out = seg[keep].copy()
+    if not keep.all() and len(out):
+        prev = np.cumsum(keep) - 1           # last kept segment at or before each one
+        fold = ~keep & (prev >= 0)
+        np.add.at(out["ds"], prev[fold], seg["ds"][fold])
+    return out
 
 
 def compare_trace(gpu_seg, orc_seg, rtol, atol=1e-12):

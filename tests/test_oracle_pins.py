@@ -490,6 +490,43 @@ def test_opaque_cells_absorb_their_own_emission_with_cap(mode):
     assert abs(tot.mean() - target.sum()) < 4 * tot.std(ddof=1) / math.sqrt(len(runs)) + 1e-9 * np.abs(target).sum()
 
 
+def _hot_cloud():
+    """A cloud whose dust re-emission heats it markedly (mean tau_V 30, a
+    10^6 L_sun source): many constant-source packages, few dust packages."""
+    P = W.lognormal_problem(n=16, K=8, sigma_ln=1.0, tau_v_mean=30.0, seed=3, L_star_lsun=1e6,
+                            packages_per_freq=20000)
+    P.n_bg, P.n_ps_pk, P.n_dust = 100000, 50000, 4000
+    return P
+
+
+def test_reference_field_iteration_fixed_point_and_stability():
+    """Reference-field iteration (Sect. 2.1.2) against the plain one on the
+    same cloud: its first dust iteration is the plain one exactly (an empty
+    reference makes the correction the whole emission); it reaches the same
+    solution (mean and hottest-5% temperatures within 0.3%); and because
+    each later iteration simulates only the change of the emission, its
+    iterate-to-iterate changes are a small and shrinking fraction of the
+    plain method's, whose every iteration carries fresh full noise."""
+    P = _hot_cloud()
+    rho = P.grid.density() > 0
+    plain = orc.iterate(P, seed=7, dust_seed=1, iterations=10)
+    ref = orc.iterate(P, seed=7, dust_seed=1, iterations=10, reference=True)
+    assert np.array_equal(plain[0][0], ref[0][0]) and np.array_equal(plain[1][0], ref[1][0])
+    assert ref[2][0][rho].mean() != plain[2][0][rho].mean()
+    for key, tol in (("mean_T", 0.003), ("hot5_mean_T", 0.005)):
+        assert ref[-1][1][key] == pytest.approx(plain[-1][1][key], rel=tol)
+    # the dust heating matters here: iteration 1 (constant sources only) is far colder
+    assert plain[-1][1]["mean_T"] > 1.15 * plain[0][1]["mean_T"]
+
+    def jitter(run, i):
+        return np.mean(np.abs(run[i][0][rho] / run[i - 1][0][rho] - 1))
+
+    jp = [jitter(plain, i) for i in range(5, 10)]
+    jr = [jitter(ref, i) for i in range(5, 10)]
+    assert max(jr) < 0.15 * min(jp)
+    assert jr[-1] < 0.8 * jr[0]
+
+
 def test_octree_refined_once_equals_doubled_regular_grid():
     """A grid with every root cell refined once into equal-density children
     describes the same medium as the regular grid of twice the resolution:
