@@ -315,6 +315,94 @@ def surrogate_gain(args, soc, torch, W):
     ctx.close()
 
 
+def reference_gain(args, soc, torch, W):
+    """Plain versus reference-field iteration (Sect. 2.1.2, 4.4) on two
+    clouds -- the benchmark cloud (sigma_ln 1, mean tau_V 5) and an
+    optically thick one where dust self-heating takes several iterations
+    (sigma_ln --target-sigma, tau_V --target-tau) -- with the benchmark's
+    frequencies, sources and package count.  Six runs of --ref-iters
+    iterations each: plain and the two readings of the reference field
+    (correction packages; running mean of whole-emission estimates) with a
+    constant package count, and the same three with a count growing
+    geometrically from 1/--ref-factor of it.  Each is timed and compared with a long plain reference (mean of
+    8 iterations after 12): the first iteration within 1% of it (over all
+    cells and over the hottest 5%), the iteration the stopping rule fires,
+    and the rms temperature difference between two runs with independent
+    dust-emission seeds at the end (the paper's noise measure)."""
+    from paper_1812_06632_amd.driver import PlainSolver, ReferenceFieldSolver, geometric_schedule
+    ctx = soc.Context(0)
+    I = args.ref_iters
+    sched = geometric_schedule(args.packages, args.ref_factor, I)
+
+    def cloud(label, sigma, tau):
+        P = W.lognormal_problem(n=args.n, K=args.freqs, sigma_ln=sigma, tau_v_mean=tau,
+                                packages_per_freq=args.packages)
+        ref = PlainSolver(ctx, P, seed=7)
+        ref.constant_pass()
+        burn, avg = 12, 8
+        acc = torch.zeros_like(ref.T, dtype=torch.float64)
+        for it in range(2, burn + avg + 2):
+            ref.dust_iteration(it)
+            if it > burn + 1:
+                acc += ref.T.double()
+        T_ref = acc / avg
+        del ref
+        dense = torch.from_numpy(P.grid.density()).cuda() > 0
+        Tr = T_ref[dense]
+        hot = Tr >= torch.quantile(Tr.float(), 0.95).double()
+        log(f"{label}: reference <T> {Tr.mean().item():.3f} K, hottest 5% {Tr[hot].mean().item():.3f} K")
+
+        def err(T):
+            r = (T.double()[dense] - Tr).abs() / Tr
+            return r.mean().item(), r[hot].mean().item()
+
+        out = {}
+        runs = [("plain", None, None), ("correction", "correction", None), ("average", "average", None),
+                ("plain_growing", None, sched), ("correction_growing", "correction", sched),
+                ("average_growing", "average", sched)]
+        for name, mode, pk in runs:
+            finals = []
+            for seed in (1, 2):
+                if mode:
+                    S = ReferenceFieldSolver(ctx, P, seed=seed, packages=pk, mode=mode)
+                else:
+                    S = PlainSolver(ctx, P, seed=seed, packages=pk)
+                errs = {}
+                ctx.read_stats(reset=True)
+                hist, at = S.run(max_iter=I, until_stop=False,
+                                 on_iter=(lambda it, T: errs.__setitem__(it, err(T))) if seed == 1 else None)
+                st = ctx.read_stats(reset=True)
+                finals.append(S.T.double()[dense].clone())
+                if seed == 1:
+                    ref1 = next((it for it in sorted(errs) if errs[it][0] < 0.01 and errs[it][1] < 0.01), None)
+                    wall = hist[-1][1]
+                    rec = {"iterations": I, "wall_s": wall, "stopping_rule_at": at,
+                           "wall_s_to_stopping_rule": hist[at - 1][1] if at else None,
+                           "iterations_to_1pct_of_ref": ref1,
+                           "wall_s_to_1pct_of_ref": hist[ref1 - 1][1] if ref1 else None,
+                           "err_final": [round(v, 5) for v in errs[I]],
+                           "err_by_iteration": {int(k): [round(v[0], 5), round(v[1], 5)] for k, v in errs.items()},
+                           "dust_packages_per_freq": [S.n_packages(it) for it in range(2, I + 1)],
+                           "packages_per_s": st["packages"] / wall}
+                del S
+            d = finals[0] / finals[1] - 1.0
+            rec["rms_between_seeds"] = [math.sqrt((d * d).mean().item()), math.sqrt((d[hot] ** 2).mean().item())]
+            out[name] = rec
+            log(f"{label} {name}: {I} iterations {rec['wall_s']:.2f}s, within 1% of the reference from iteration "
+                f"{rec['iterations_to_1pct_of_ref']}, stopping rule at {rec['stopping_rule_at']}, final error "
+                f"{rec['err_final']}, rms between seeds {rec['rms_between_seeds'][0]:.4f} "
+                f"(hottest 5% {rec['rms_between_seeds'][1]:.4f})")
+        return {"cloud": label, "sigma_ln": sigma, "tau_V": tau, "reference_mean_T": Tr.mean().item(),
+                "reference_hot5_mean_T": Tr[hot].mean().item(), "runs": out}
+
+    clouds = [cloud("benchmark cloud", 1.0, 5.0), cloud("thick cloud", args.target_sigma, args.target_tau)]
+    line = {"kind": "reference_field", "cells": f"{args.n}^3", "frequencies": args.freqs,
+            "packages_per_freq": args.packages, "iterations": I, "growing_from": args.packages / args.ref_factor,
+            "clouds": clouds}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -342,6 +430,10 @@ def main():
     ap.add_argument("--target-sigma", type=float, default=1.5)
     ap.add_argument("--target-tau", type=float, default=50.0)
     ap.add_argument("--train-steps", type=int, default=5000)
+    ap.add_argument("--reference", action="store_true",
+                    help="plain versus reference-field iteration, constant and growing package counts")
+    ap.add_argument("--ref-iters", type=int, default=10)
+    ap.add_argument("--ref-factor", type=float, default=16.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the design notes describe how the "
@@ -364,6 +456,9 @@ def main():
         return
     if args.batch:
         batch_bench(args, soc, torch, W)
+        return
+    if args.reference:
+        reference_gain(args, soc, torch, W)
         return
 
     from paper_1812_06632_amd.driver import PlainSolver, converged

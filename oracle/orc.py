@@ -280,12 +280,17 @@ def iterate(P, *, seed, iterations, packages=None, reference=False, cap=0.0, nth
     temperatures come from A_const alone.  Iteration i >= 2 uses
     packages(i) dust packages per frequency (default P.n_dust):
       * plain: A_i = A_const + the dust emission at T_{i-1};
-      * reference field: the packages carry the difference between the
-        emission at T_{i-1} and the reference emission L_ref, A_i = A_ref +
-        their absorption, and both references then move to the
-        package-weighted running mean, X_ref += n_i / (n_2 + ... + n_i)
-        (X_i - X_ref) -- so the constant sources, part of A_ref from the
-        start, are never simulated again.
+      * reference field, reference=True or "correction": the packages
+        carry the difference between the emission at T_{i-1} and the
+        reference emission L_ref, A_i = A_ref + their absorption, and both
+        references then move to the package-weighted running mean,
+        X_ref += n_i / (n_2 + ... + n_i) (X_i - X_ref) -- so the constant
+        sources, part of A_ref from the start, are never simulated again;
+      * reference field, reference="average": the packages carry the whole
+        emission at T_{i-1} as in the plain method, A_i = A_const + their
+        absorption, the reference absorption moves to the package-weighted
+        running mean of the A_i in the same way, and the temperatures come
+        from the reference absorption (one stored number per cell).
     The dust packages draw from dust_seed (default: seed).  Returns
     [(T_i, stats_i)] for i = 1..iterations."""
     dseed = seed if dust_seed is None else dust_seed
@@ -305,11 +310,15 @@ def iterate(P, *, seed, iterations, packages=None, reference=False, cap=0.0, nth
     A_ref = A_const.copy()
     L_ref = np.zeros((K, g.ncells))
     n_sum = 0
+    mode = "correction" if reference is True else (reference or None)
+    if mode not in (None, "correction", "average"):
+        raise ValueError("reference must be False, True, 'correction' or 'average'")
     for it in range(2, iterations + 1):
         n = int(packages(it)) if packages is not None else int(P.n_dust)
-        if reference:
+        if mode:
             n_sum += n
             beta = n / n_sum
+        if mode == "correction":
             A = A_ref.copy()
             for k in range(K):
                 simulate_frequency(g, fr[k], T=T, n_dust=n, dust_mode=2, L_ref=L_ref[k], dust_cap=cap, seed=dseed,
@@ -320,8 +329,11 @@ def iterate(P, *, seed, iterations, packages=None, reference=False, cap=0.0, nth
             for k in range(K):
                 simulate_frequency(g, fr[k], T=T, n_dust=n, dust_mode=1, dust_cap=cap, seed=dseed, iteration=it,
                                    freq_index=k, nthreads=nthreads, absorbed=A)
+        if mode == "average":
+            A_ref += beta * (A - A_ref)
+            A = A_ref
         T_new, st = update_temperature(g, *emit, A, T_old=T, T_floor=P.T_floor, T_max=P.T_max)
-        if reference:
+        if mode == "correction":
             A_ref += beta * (A - A_ref)
         T = T_new
         out.append((T, st))

@@ -8,11 +8,15 @@ when the relative change of the mean temperature, over all cells and over
 the hottest 5% of cells, falls below the tolerance between two consecutive
 iterations (the paper's two convergence statistics).
 
-Reference-field method: each dust iteration simulates only the difference
-between the current emission and a reference emission (packages of either
-sign), adds their absorption to the reference absorption, and moves both
-references to the package-weighted running mean; the number of packages
-may grow over the iterations (a geometric schedule).
+Reference-field method, two readings of Sect. 2.1.2: "correction" -- each
+dust iteration simulates only the difference between the current emission
+and a reference emission (packages of either sign), adds their absorption
+to the reference absorption, and moves both references to the
+package-weighted running mean; "average" -- each dust iteration simulates
+the whole emission and the temperatures come from the package-weighted
+running mean of the absorption estimates (one stored number per cell).
+The number of packages may grow over the iterations (a geometric
+schedule).
 
 Control flow only: every step is a call through the C-ABI library; the
 stopping rule compares two scalars the temperature kernel returns.
@@ -152,26 +156,38 @@ def geometric_schedule(n_final: int, factor: float, iterations: int):
 
 
 class ReferenceFieldSolver(PlainSolver):
-    """Reference-field iteration (Sect. 2.1.2).  Device state: the
-    reference emission per frequency and cell (FP64, K x ncells) and the
-    reference absorption (FP64, ncells).  After the constant pass the
-    reference absorption is the constant sources' and the reference
-    emission zero; dust iteration i with n_i packages per frequency
-    simulates L(T_{i-1}) - L_ref (the library blends L_ref by
-    beta_i = n_i / (n_2 + ... + n_i) in the same call), solves T_i from
-    A_i = A_ref + that absorption, then blends A_ref by the same beta."""
+    """Reference-field iteration (Sect. 2.1.2).  Dust iteration i uses
+    n_i packages per frequency and the weight beta_i = n_i / (n_2 + ... +
+    n_i); after the constant pass the reference absorption A_ref is the
+    constant sources'.
 
-    def __init__(self, ctx: soc.Context, P, seed: int = 1, nT: int = 4096, packages=None, cap: float = 0.0):
+    mode "correction": device state adds the reference emission per
+    frequency and cell (FP64, K x ncells, zero at the start).  The
+    packages carry L(T_{i-1}) - L_ref (the library blends L_ref by beta_i
+    in the same call), T_i is solved from A_i = A_ref + their absorption,
+    then A_ref is blended towards A_i by beta_i.
+
+    mode "average": the packages carry the whole emission L(T_{i-1}) as in
+    the plain method, A_i = A_const + their absorption, A_ref is blended
+    towards A_i by beta_i and T_i is solved from A_ref."""
+
+    def __init__(self, ctx: soc.Context, P, seed: int = 1, nT: int = 4096, packages=None, cap: float = 0.0,
+                 mode: str = "correction"):
         super().__init__(ctx, P, seed, nT, packages, cap)
+        if mode not in ("correction", "average"):
+            raise ValueError("mode must be 'correction' or 'average'")
+        self.mode = mode
         nc = P.grid.ncells
-        self.L_ref = torch.zeros((P.K, nc), dtype=torch.float64, device="cuda")
+        self.L_ref = (torch.zeros((P.K, nc), dtype=torch.float64, device="cuda") if mode == "correction"
+                      else None)
         self.A_ref = torch.zeros(nc, dtype=torch.float64, device="cuda")
         self.n_sum = 0
 
     def constant_pass(self) -> dict:
         s = super().constant_pass()
         self.A_ref.copy_(self.A_const)
-        self.L_ref.zero_()
+        if self.L_ref is not None:
+            self.L_ref.zero_()
         self.n_sum = 0
         return s
 
@@ -180,13 +196,22 @@ class ReferenceFieldSolver(PlainSolver):
         n = self.n_packages(it)
         self.n_sum += n
         beta = n / self.n_sum
-        self.A.copy_(self.A_ref)
-        for k in range(P.K):
-            soc.simulate_frequency(self.ctx, self.grid, self.freqs[k], self.A, T=self.T, n_dust=n, dust_mode=2,
-                                   L_ref=self.L_ref[k], ref_beta=beta, dust_cap=self.cap, seed=self.seed,
-                                   iteration=it, freq_index=k)
-        s = soc.update_temperature(self.ctx, self.grid, self.table, self.A, self.T_new, self.T, stats=True)
-        soc.reference_blend(self.ctx, self.A, self.A_ref, beta)
+        if self.mode == "correction":
+            self.A.copy_(self.A_ref)
+            for k in range(P.K):
+                soc.simulate_frequency(self.ctx, self.grid, self.freqs[k], self.A, T=self.T, n_dust=n,
+                                       dust_mode=2, L_ref=self.L_ref[k], ref_beta=beta, dust_cap=self.cap,
+                                       seed=self.seed, iteration=it, freq_index=k)
+            s = soc.update_temperature(self.ctx, self.grid, self.table, self.A, self.T_new, self.T, stats=True)
+            soc.reference_blend(self.ctx, self.A, self.A_ref, beta)
+        else:
+            self.A.copy_(self.A_const)
+            for k in range(P.K):
+                soc.simulate_frequency(self.ctx, self.grid, self.freqs[k], self.A, T=self.T, n_dust=n,
+                                       dust_mode=1, dust_cap=self.cap, seed=self.seed, iteration=it, freq_index=k)
+            soc.reference_blend(self.ctx, self.A, self.A_ref, beta)
+            s = soc.update_temperature(self.ctx, self.grid, self.table, self.A_ref, self.T_new, self.T,
+                                       stats=True)
         self.T.copy_(self.T_new)
         s["packages"] = n
         return s

@@ -298,10 +298,11 @@ def test_reference_error_paths(soc, ctx, cloud):
     assert not A.any()
 
 
-@pytest.mark.parametrize("reference", [False, True])
+@pytest.mark.parametrize("reference", [False, "correction", "average"])
 def test_solver_follows_oracle_iteration(soc, ctx, reference):
-    """The library-driven iteration, plain and reference field, with a
-    package count growing geometrically over the iterations, follows the
+    """The library-driven iteration, plain and reference field (both
+    readings), with a package count growing geometrically over the
+    iterations, follows the
     oracle's iteration (Sect. 2.1.2) on the same seeds: per-iteration mean
     and hottest-5% temperatures agree to 2e-3 and the per-cell temperatures
     closely (the same packages; differences come from FP32 transport and,
@@ -312,7 +313,10 @@ def test_solver_follows_oracle_iteration(soc, ctx, reference):
                             packages_per_freq=20000)
     P.n_bg, P.n_ps_pk = 100000, 50000
     sched = geometric_schedule(8000, 8.0, 6)
-    solver = (ReferenceFieldSolver if reference else PlainSolver)(ctx, P, seed=7, packages=sched)
+    if reference:
+        solver = ReferenceFieldSolver(ctx, P, seed=7, packages=sched, mode=reference)
+    else:
+        solver = PlainSolver(ctx, P, seed=7, packages=sched)
     Ts = []
     hist, _ = solver.run(max_iter=6, until_stop=False, on_iter=lambda it, T: Ts.append(T.cpu().numpy().copy()))
     ref_run = orc.iterate(P, seed=7, iterations=6, packages=sched, reference=reference)
