@@ -32,7 +32,8 @@ class _Sources(C.Structure):
     _fields_ = [("I_bg_nu", C.c_double), ("n_ps", C.c_int32), ("ps_pos", C.POINTER(C.c_double)),
                 ("ps_L_nu", C.POINTER(C.c_double)), ("T", C.POINTER(C.c_float)),
                 ("n_bg", C.c_uint64), ("n_ps_pk", C.c_uint64), ("n_dust", C.c_uint64),
-                ("dust_mode", C.c_int32), ("L_ref", C.POINTER(C.c_double)), ("dust_cap", C.c_double)]
+                ("dust_mode", C.c_int32), ("L_ref", C.POINTER(C.c_double)), ("dust_cap", C.c_double),
+                ("ali_self", C.POINTER(C.c_double)), ("ali_emitted", C.POINTER(C.c_double))]
 
 
 class _Stats(C.Structure):
@@ -69,7 +70,8 @@ def lib():
         L.orc_leaf.restype = C.c_int64
         L.orc_validate_grid.restype = C.c_int32
         for name in ("orc_simulate_frequency", "orc_trace_package", "orc_trace_from",
-                     "orc_update_temperature", "orc_map", "orc_dust_luminosity"):
+                     "orc_update_temperature", "orc_map", "orc_dust_luminosity",
+                     "orc_update_temperature_ali"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -148,7 +150,7 @@ def hg_scatter(g, u0, xi):
 
 class _SourcesView:
     def __init__(self, I_bg=0.0, ps_pos=None, ps_Lnu=None, T=None, n_bg=0, n_ps_pk=0, n_dust=0, dust_mode=1,
-                 L_ref=None, dust_cap=0.0):
+                 L_ref=None, dust_cap=0.0, ali_self=None, ali_emitted=None):
         self.pos = np.ascontiguousarray(ps_pos if ps_pos is not None else np.zeros((0, 3)), dtype=np.float64)
         self.L = np.ascontiguousarray(ps_Lnu if ps_Lnu is not None else np.zeros(0), dtype=np.float64)
         self.T = None if T is None else np.ascontiguousarray(T, dtype=np.float32)
@@ -158,7 +160,10 @@ class _SourcesView:
                           _p(self.L, C.c_double) if n_ps else None,
                           _p(self.T, C.c_float) if self.T is not None else None,
                           int(n_bg), int(n_ps_pk), int(n_dust), int(dust_mode),
-                          _p(self.Lref, C.c_double) if self.Lref is not None else None, float(dust_cap))
+                          _p(self.Lref, C.c_double) if self.Lref is not None else None, float(dust_cap),
+                          _p(ali_self, C.c_double) if ali_self is not None else None,
+                          _p(ali_emitted, C.c_double) if ali_emitted is not None else None)
+        self.keep = (ali_self, ali_emitted)
 
 
 def _stats_dict(st):
@@ -167,14 +172,20 @@ def _stats_dict(st):
 
 def simulate_frequency(grid, freq, *, I_bg=0.0, ps_pos=None, ps_Lnu=None, T=None, n_bg=0, n_ps_pk=0,
                        n_dust=0, dust_mode=1, L_ref=None, dust_cap=0.0, seed=1, iteration=0, freq_index=0,
-                       step_cap=0, nthreads=1, absorbed=None, want_path=False, hits=None):
+                       step_cap=0, nthreads=1, absorbed=None, want_path=False, hits=None, ali_self=None,
+                       ali_emitted=None):
     """One Monte Carlo pass at one frequency.  freq = (nu, w, sigma_abs,
     sigma_sca, g).  Returns (absorbed float64[ncells], stats dict,
     path lengths or None).  hits: optional int64[ncells] accumulated with
     the number of depositing segments per cell.  dust_mode 2 emits the
-    difference between the dust emission at T and L_ref (per cell, erg/s)."""
+    difference between the dust emission at T and L_ref (per cell, erg/s).
+    ali_self / ali_emitted (float64[ncells], +=): diagonal ALI tallies."""
     gv = GridView(grid)
-    sv = _SourcesView(I_bg, ps_pos, ps_Lnu, T, n_bg, n_ps_pk, n_dust, dust_mode, L_ref, dust_cap)
+    for a in (ali_self, ali_emitted):
+        if a is not None and (a.dtype != np.float64 or not a.flags.c_contiguous or a.size != grid.ncells):
+            raise ValueError("ALI tallies must be contiguous float64 arrays of ncells")
+    sv = _SourcesView(I_bg, ps_pos, ps_Lnu, T, n_bg, n_ps_pk, n_dust, dust_mode, L_ref, dust_cap, ali_self,
+                      ali_emitted)
     f = _freq(freq)
     if absorbed is None:
         absorbed = np.zeros(grid.ncells, dtype=np.float64)
@@ -237,7 +248,9 @@ def trace_from(grid, freq, p0, u0, W0, tau0, *, seed=1, package_id=0, step_cap=0
     return out[: min(ns.value, max_seg)].copy(), wesc.value
 
 
-def update_temperature(grid, emit_nu, emit_w, emit_sabs, absorbed, T_old=None, T_floor=2.0, T_max=3000.0):
+def update_temperature(grid, emit_nu, emit_w, emit_sabs, absorbed, T_old=None, T_floor=2.0, T_max=3000.0,
+                       ali_self=None, ali_emitted=None):
+    """Equilibrium temperatures; with the ALI tallies, the diagonal-ALI solve."""
     gv = GridView(grid)
     K = len(emit_nu)
     arr = (_Freq * K)(*[_Freq(float(a), float(b), float(c), 0.0, 0.0)
@@ -246,9 +259,18 @@ def update_temperature(grid, emit_nu, emit_w, emit_sabs, absorbed, T_old=None, T
     To = None if T_old is None else np.ascontiguousarray(T_old, dtype=np.float32)
     Tn = np.zeros(grid.ncells, dtype=np.float32)
     st = _TStats()
-    rc = lib().orc_update_temperature(C.byref(gv.s), arr, C.c_int32(K), C.c_double(T_floor), C.c_double(T_max),
-                                      _p(A, C.c_double), _p(To, C.c_float) if To is not None else None,
-                                      _p(Tn, C.c_float), C.byref(st))
+    if ali_self is not None:
+        Sa = np.ascontiguousarray(ali_self, dtype=np.float64)
+        Ea = np.ascontiguousarray(ali_emitted, dtype=np.float64)
+        rc = lib().orc_update_temperature_ali(C.byref(gv.s), arr, C.c_int32(K), C.c_double(T_floor),
+                                              C.c_double(T_max), _p(A, C.c_double), _p(Sa, C.c_double),
+                                              _p(Ea, C.c_double), _p(To, C.c_float) if To is not None else None,
+                                              _p(Tn, C.c_float), C.byref(st))
+    else:
+        rc = lib().orc_update_temperature(C.byref(gv.s), arr, C.c_int32(K), C.c_double(T_floor),
+                                          C.c_double(T_max), _p(A, C.c_double),
+                                          _p(To, C.c_float) if To is not None else None, _p(Tn, C.c_float),
+                                          C.byref(st))
     if rc != 0:
         raise ValueError(f"orc_update_temperature failed: {rc}")
     return Tn, {k: getattr(st, k) for k, _ in _TStats._fields_}
@@ -269,7 +291,8 @@ def map_image(grid, freq, T, axis):
     return img.reshape(npy.value, npx.value)
 
 
-def iterate(P, *, seed, iterations, packages=None, reference=False, cap=0.0, nthreads=8, dust_seed=None):
+def iterate(P, *, seed, iterations, packages=None, reference=False, cap=0.0, nthreads=8, dust_seed=None,
+            ali=False):
     """The iteration of Sect. 2.1.2 on a problem P (attributes of a
     workloads.Problem: grid, nu, w, sigma_abs, sigma_sca, g, I_bg, ps_pos,
     ps_Lnu, n_bg, n_ps_pk, n_dust, emit_nu, emit_w, emit_sigma_abs,
@@ -291,6 +314,9 @@ def iterate(P, *, seed, iterations, packages=None, reference=False, cap=0.0, nth
         absorption, the reference absorption moves to the package-weighted
         running mean of the A_i in the same way, and the temperatures come
         from the reference absorption (one stored number per cell).
+    With ali (plain iteration only), every dust iteration also counts what
+    each cell's packages deposit in that cell and the energy it emitted,
+    and the temperatures come from the diagonal-ALI solve (Sect. 2.1.2).
     The dust packages draw from dust_seed (default: seed).  Returns
     [(T_i, stats_i)] for i = 1..iterations."""
     dseed = seed if dust_seed is None else dust_seed
@@ -313,6 +339,8 @@ def iterate(P, *, seed, iterations, packages=None, reference=False, cap=0.0, nth
     mode = "correction" if reference is True else (reference or None)
     if mode not in (None, "correction", "average"):
         raise ValueError("reference must be False, True, 'correction' or 'average'")
+    if ali and mode:
+        raise ValueError("ALI is combined here with the plain iteration only")
     for it in range(2, iterations + 1):
         n = int(packages(it)) if packages is not None else int(P.n_dust)
         if mode:
@@ -326,13 +354,19 @@ def iterate(P, *, seed, iterations, packages=None, reference=False, cap=0.0, nth
                 L_ref[k] += beta * (dust_luminosity(g, fr[k], T) - L_ref[k])
         else:
             A = A_const.copy()
+            S_ali = np.zeros(g.ncells) if ali else None
+            E_ali = np.zeros(g.ncells) if ali else None
             for k in range(K):
                 simulate_frequency(g, fr[k], T=T, n_dust=n, dust_mode=1, dust_cap=cap, seed=dseed, iteration=it,
-                                   freq_index=k, nthreads=nthreads, absorbed=A)
+                                   freq_index=k, nthreads=nthreads, absorbed=A, ali_self=S_ali, ali_emitted=E_ali)
         if mode == "average":
             A_ref += beta * (A - A_ref)
             A = A_ref
-        T_new, st = update_temperature(g, *emit, A, T_old=T, T_floor=P.T_floor, T_max=P.T_max)
+        if ali:
+            T_new, st = update_temperature(g, *emit, A, T_old=T, T_floor=P.T_floor, T_max=P.T_max, ali_self=S_ali,
+                                           ali_emitted=E_ali)
+        else:
+            T_new, st = update_temperature(g, *emit, A, T_old=T, T_floor=P.T_floor, T_max=P.T_max)
         if mode == "correction":
             A_ref += beta * (A - A_ref)
         T = T_new

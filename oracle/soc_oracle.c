@@ -249,7 +249,7 @@ typedef struct {
  * under the weight floor or hits the step cap. */
 static void transport(const orc_grid *g, const orc_freq *f, double p[3], double u[3], double W0,
                       double tau, stream_t *rs, int64_t cap, double *absorbed, int64_t *hits, pk_tally *t,
-                      orc_segment *seg, int32_t max_seg, int32_t *nseg)
+                      orc_segment *seg, int32_t max_seg, int32_t *nseg, int64_t origin, double *self_abs)
 {
     double W = W0;
     const double s_cm = g->root_cell_cm;
@@ -279,8 +279,11 @@ static void transport(const orc_grid *g, const orc_freq *f, double p[3], double 
             tau -= ks * dexit;
             ev = ORC_CROSS;
         }
+        /* deposits of a dust package in its own emitting cell are counted
+         * apart for diagonal ALI */
+        double *dst = (self_abs && c == origin) ? self_abs : absorbed;
         double dep = W * (-expm1(-ka * d));
-        if (absorbed && dep != 0.0) absorbed[c] += dep;
+        if (dst && dep != 0.0) dst[c] += dep;
         if (hits && dep != 0.0) hits[c] += 1;
         W -= dep;
         p[0] += d * u[0]; p[1] += d * u[1]; p[2] += d * u[2];
@@ -292,11 +295,11 @@ static void transport(const orc_grid *g, const orc_freq *f, double p[3], double 
             if (orc_leaf(g, q2, lo2, &sz2) < 0) ev = ORC_ESCAPE;
         }
         if (ev != ORC_ESCAPE && fabs(W) < ORC_WFLOOR * fabs(W0)) {
-            if (absorbed) absorbed[c] += W;
+            if (dst) dst[c] += W;
             W = 0.0;
             ev = ORC_FLOOR;
         } else if (ev != ORC_ESCAPE && (int64_t)t->steps >= cap) {
-            if (absorbed) absorbed[c] += W;
+            if (dst) dst[c] += W;
             W = 0.0;
             ev = ORC_RUNAWAY;
             t->runaway++;
@@ -491,8 +494,9 @@ static int64_t weighted_cell(const sim_ctx *X, uint64_t j)
 /* Emission of global package gid (class order bg | ps0..psN-1 | dust) and
  * its transport.  Returns the initial weight W0. */
 static double run_package(const sim_ctx *X, uint64_t gid, double *absorbed, int64_t *hits, pk_tally *t,
-                          orc_segment *seg, int32_t max_seg, int32_t *nseg)
+                          orc_segment *seg, int32_t max_seg, int32_t *nseg, double *self_abs, double *emitted)
 {
+    int64_t origin = -1;
     const orc_grid *g = X->g;
     const orc_sources *s = X->s;
     double p[3], u[3], W0;
@@ -549,6 +553,8 @@ static double run_package(const sim_ctx *X, uint64_t gid, double *absorbed, int6
             W0 = X->L[c] / expected_count(X, c);
         }
         if (!(fabs(W0) > 0.0)) return 0.0;
+        origin = c;
+        if (self_abs && emitted) emitted[c] += W0;
         double size = ldexp(1.0, -cell_level(g, c));
         const double *lo = X->cell_lo + 3 * c;
         double x0 = stream_next(&rs), x1 = stream_next(&rs), x2 = stream_next(&rs);
@@ -557,7 +563,8 @@ static double run_package(const sim_ctx *X, uint64_t gid, double *absorbed, int6
         iso_dir(x3, x4, u);
     }
     double tau = -log(stream_next(&rs));
-    transport(g, X->f, p, u, W0, tau, &rs, X->cap, absorbed, hits, t, seg, max_seg, nseg);
+    transport(g, X->f, p, u, W0, tau, &rs, X->cap, absorbed, hits, t, seg, max_seg, nseg, origin,
+              self_abs && emitted ? self_abs : NULL);
     return W0;
 }
 
@@ -601,17 +608,20 @@ int32_t orc_simulate_frequency(const orc_grid *g, const orc_freq *f, const orc_s
     {
         double *priv = (double *)calloc((size_t)ncells, sizeof(double));
         int64_t *phits = hits ? (int64_t *)calloc((size_t)ncells, sizeof(int64_t)) : NULL;
+        const int ali = s->ali_self && s->ali_emitted;
+        double *pself = ali ? (double *)calloc((size_t)ncells, sizeof(double)) : NULL;
+        double *pemit = ali ? (double *)calloc((size_t)ncells, sizeof(double)) : NULL;
         orc_stats loc;
         memset(&loc, 0, sizeof loc);
-        if (!priv || (hits && !phits)) failed = 1;
+        if (!priv || (hits && !phits) || (ali && (!pself || !pemit))) failed = 1;
 #ifdef _OPENMP
 #pragma omp for schedule(dynamic, 64)
 #endif
         for (int64_t gid = 0; gid < (int64_t)NT; ++gid) {
-            if (!priv || (hits && !phits)) continue;
+            if (!priv || (hits && !phits) || (ali && (!pself || !pemit))) continue;
             pk_tally t;
             memset(&t, 0, sizeof t);
-            double W0 = run_package(&X, (uint64_t)gid, priv, phits, &t, NULL, 0, NULL);
+            double W0 = run_package(&X, (uint64_t)gid, priv, phits, &t, NULL, 0, NULL, pself, pemit);
             loc.packages++;
             loc.cell_steps += t.steps;
             loc.scatterings += t.scatterings;
@@ -628,6 +638,12 @@ int32_t orc_simulate_frequency(const orc_grid *g, const orc_freq *f, const orc_s
                 for (int64_t c = 0; c < ncells; ++c) absorbed[c] += priv[c];
                 double a = 0.0;
                 for (int64_t c = 0; c < ncells; ++c) a += priv[c];
+                if (pself) {
+                    for (int64_t c = 0; c < ncells; ++c) a += pself[c];
+                    for (int64_t c = 0; c < ncells; ++c) s->ali_self[c] += pself[c];
+                }
+                if (pemit)
+                    for (int64_t c = 0; c < ncells; ++c) s->ali_emitted[c] += pemit[c];
                 loc.e_absorbed = a;
             }
             if (phits)
@@ -638,6 +654,8 @@ int32_t orc_simulate_frequency(const orc_grid *g, const orc_freq *f, const orc_s
         }
         free(priv);
         free(phits);
+        free(pself);
+        free(pemit);
     }
     sim_free(&X);
     if (failed) return -3;
@@ -673,7 +691,7 @@ int32_t orc_trace_package(const orc_grid *g, const orc_freq *f, const orc_source
     pk_tally t;
     memset(&t, 0, sizeof t);
     *n_seg = 0;
-    run_package(&X, gid, NULL, NULL, &t, out, max_seg, n_seg);
+    run_package(&X, gid, NULL, NULL, &t, out, max_seg, n_seg, NULL, NULL);
     sim_free(&X);
     return 0;
 }
@@ -690,7 +708,8 @@ int32_t orc_trace_from(const orc_grid *g, const orc_freq *f, const double p0[3],
     pk_tally t;
     memset(&t, 0, sizeof t);
     int32_t ns = 0;
-    transport(g, f, p, u, W0, tau0, &rs, step_cap > 0 ? step_cap : 10000000, absorbed, NULL, &t, out, max_seg, &ns);
+    transport(g, f, p, u, W0, tau0, &rs, step_cap > 0 ? step_cap : 10000000, absorbed, NULL, &t, out, max_seg, &ns,
+              -1, NULL);
     if (n_seg) *n_seg = ns;
     if (w_escaped) *w_escaped = t.escaped;
     return 0;
@@ -708,10 +727,32 @@ static int cmp_desc(const void *a, const void *b)
     return (x < y) - (x > y);
 }
 
+static int32_t update_temperature(const orc_grid *g, const orc_freq *emit, int32_t K, double T_floor,
+                                  double T_max, const double *absorbed, const double *self_abs,
+                                  const double *emitted, const float *T_old, float *T_new,
+                                  orc_temp_stats *stats);
+
 int32_t orc_update_temperature(const orc_grid *g, const orc_freq *emit, int32_t K,
                                double T_floor, double T_max,
                                const double *absorbed, const float *T_old, float *T_new,
                                orc_temp_stats *stats)
+{
+    return update_temperature(g, emit, K, T_floor, T_max, absorbed, NULL, NULL, T_old, T_new, stats);
+}
+
+int32_t orc_update_temperature_ali(const orc_grid *g, const orc_freq *emit, int32_t K,
+                                   double T_floor, double T_max, const double *absorbed,
+                                   const double *self_abs, const double *emitted,
+                                   const float *T_old, float *T_new, orc_temp_stats *stats)
+{
+    if (!self_abs || !emitted) return -1;
+    return update_temperature(g, emit, K, T_floor, T_max, absorbed, self_abs, emitted, T_old, T_new, stats);
+}
+
+static int32_t update_temperature(const orc_grid *g, const orc_freq *emit, int32_t K, double T_floor,
+                                  double T_max, const double *absorbed, const double *self_abs,
+                                  const double *emitted, const float *T_old, float *T_new,
+                                  orc_temp_stats *stats)
 {
     if (orc_validate_grid(g) != 0) return -4;
     if (!(T_floor > 0.0) || !(T_max > T_floor) || K < 1) return -1;
@@ -725,6 +766,12 @@ int32_t orc_update_temperature(const orc_grid *g, const orc_freq *emit, int32_t 
         double T = 0.0;
         if (word_i(g, c) >= 0 && word_f(g, c) > 0.0) {
             double y = absorbed[c] / (word_f(g, c) * cell_volume(g, c));
+            if (self_abs) {
+                /* escape probability of the cell's own emission */
+                double esc = emitted[c] > 0.0 ? 1.0 - self_abs[c] / emitted[c] : 1.0;
+                if (esc < 1e-6) esc = 1e-6;
+                y /= esc;
+            }
             if (!(y > G_lo)) { T = T_floor; clamped++; }
             else if (y >= G_hi) { T = T_max; clamped++; }
             else {

@@ -24,6 +24,9 @@
  *   - Sect. 2.1.2 (reference field): an iteration simulates only the
  *     difference between the current dust emission and a reference
  *     emission, with packages of either sign.
+ *   - Sect. 2.1.2, 4.1 (ALI with a diagonal operator): the part of a cell's
+ *     emission that it absorbs itself is counted apart, and the temperature
+ *     update solves that cell's own emission-absorption cycle exactly.
  * The paper prints no equations; the estimator and sampling rules below are
  * the textbook Monte Carlo readings recorded in the design notes:
  *   continuous absorption along each segment, free paths drawn in
@@ -74,6 +77,11 @@ typedef struct {
                                   frequency (erg s^-1, already times w_nu); NULL = zero */
     double dust_cap;           /* modes 1 and 2: expected packages per cell at most this
                                   many (0 = no cap); the excess is not re-assigned */
+    double *ali_self;          /* diagonal ALI (optional, +=, ncells): what dust packages
+                                  deposit in the cell that emitted them goes here instead
+                                  of into `absorbed` */
+    double *ali_emitted;       /* with ali_self: the initial weight of every dust package,
+                                  added to its emitting cell */
 } orc_sources;
 
 typedef struct {
@@ -137,11 +145,21 @@ int32_t orc_trace_from(const orc_grid *g, const orc_freq *f, const double p0[3],
                        double *w_escaped);
 
 /* ---- temperature update (equilibrium grains) ---- */
+
 typedef struct { double mean_T, hot5_mean_T, mean_rel_change; uint64_t clamped; } orc_temp_stats;
 int32_t orc_update_temperature(const orc_grid *g, const orc_freq *emit, int32_t K,
                                double T_floor, double T_max,
                                const double *absorbed, const float *T_old, float *T_new,
                                orc_temp_stats *stats);
+/* Diagonal ALI: with beta_c = self_c / emitted_c (0 where the cell emitted
+ * nothing; the escape probability 1 - beta_c is kept >= 1e-6), solve
+ * Gamma(T_c) n_c V_c (1 - beta_c) = absorbed_c: the cell's emission equals
+ * what it absorbs from elsewhere plus the fraction beta_c of its own
+ * emission.  Otherwise as orc_update_temperature. */
+int32_t orc_update_temperature_ali(const orc_grid *g, const orc_freq *emit, int32_t K,
+                                   double T_floor, double T_max, const double *absorbed,
+                                   const double *self_abs, const double *emitted,
+                                   const float *T_old, float *T_new, orc_temp_stats *stats);
 
 /* ---- emission map along a root-grid axis (axis 0..2, bit 2 = observer on
  * the negative side), pixel = finest cell; image is npy*npx doubles. ---- */
