@@ -153,7 +153,14 @@ typedef struct { double x, y, z, L_nu; } soc_point_source;   /* root units; erg 
  *    with S = sum |dL|; a package of a capped cell carries |dL_c| /
  *    dust_cap, and the excess is not re-assigned to other cells (fewer
  *    than n_dust packages are emitted; the rest are counted but carry
- *    nothing).  0 = no cap. */
+ *    nothing).  0 = no cap;
+ *  - diagonal ALI (Sect. 2.1.2, 4.1): with d_ali_self and d_ali_emitted
+ *    (device, ncells FP64 each, accumulated +=), what a dust package
+ *    deposits in the cell that emitted it -- on its way out, on returning
+ *    after scatterings, the weight-floor remainder -- goes to d_ali_self
+ *    instead of d_absorbed, and its initial weight is added to
+ *    d_ali_emitted of that cell; other classes are unaffected.  The
+ *    temperature solve soc_update_temperature_ali then uses them. */
 typedef struct {
     double I_bg_nu;
     int32_t n_ps;
@@ -164,6 +171,8 @@ typedef struct {
     double *d_L_ref;               /* dust_mode 2: device, ncells FP64 reference emission, updated in place */
     double ref_beta;               /* dust_mode 2: blend weight of this call's emission in d_L_ref */
     double dust_cap;               /* modes 1, 2: packages per cell at most (expected), 0 = no cap */
+    double *d_ali_self;            /* diagonal ALI (both or neither; modes 0, 1): device FP64 ncells, += */
+    double *d_ali_emitted;         /*   see below */
 } soc_sources;
 
 typedef struct {
@@ -239,6 +248,19 @@ typedef struct {
 soc_status soc_update_temperature(soc_ctx ctx, soc_grid grid, soc_temp_table table,
                                   const double *d_absorbed, const float *d_T_old, float *d_T_new,
                                   soc_temp_stats *stats);
+
+/* Diagonal ALI (Sect. 2.1.2, 4.1): as soc_update_temperature, with each
+ * cell's own absorption-emission cycle taken exactly.  beta_c =
+ * d_ali_self / d_ali_emitted (0 where the cell emitted nothing) is the
+ * fraction of its emission the cell absorbs itself, so its emission
+ * equals d_absorbed (what reached it from elsewhere) plus beta_c times
+ * itself: Gamma(T_c) n_c V_c (1 - beta_c) = d_absorbed_c.  The escape
+ * probability 1 - beta_c is kept >= 1e-6.  Tallies as filled by
+ * soc_simulate_frequency (device FP64, ncells each, read only). */
+soc_status soc_update_temperature_ali(soc_ctx ctx, soc_grid grid, soc_temp_table table,
+                                      const double *d_absorbed, const double *d_ali_self,
+                                      const double *d_ali_emitted, const float *d_T_old, float *d_T_new,
+                                      soc_temp_stats *stats);
 
 /* The same statistics (mean_T, hot5_mean_T; mean_rel_change and clamped
  * are 0) of a given temperature field d_T (device FP32, ncells, read only)

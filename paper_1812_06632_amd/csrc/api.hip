@@ -172,6 +172,10 @@ soc_status prepare(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *
     if (s->d_T && s->dust_mode == 2 && !s->d_L_ref) return fail(c, SOC_EINVAL, "dust_mode 2 needs d_L_ref");
     if (!(s->ref_beta >= 0.0 && s->ref_beta <= 1.0)) return fail(c, SOC_EINVAL, "ref_beta must be in [0, 1]");
     if (!finite_nonneg(s->dust_cap)) return fail(c, SOC_EINVAL, "dust_cap must be finite and >= 0");
+    if ((s->d_ali_self == nullptr) != (s->d_ali_emitted == nullptr))
+        return fail(c, SOC_EINVAL, "ALI needs both d_ali_self and d_ali_emitted");
+    if (s->d_ali_self && s->d_T && s->dust_mode == 2)
+        return fail(c, SOC_EINVAL, "ALI tallies apply to dust modes 0 and 1");
     if (s->d_T && s->dust_mode == 0 && s->dust_cap > 0.0)
         return fail(c, SOC_EINVAL, "dust_cap applies to the weighted modes (1, 2)");
     if (s->n_bg > 0xFFFFFFFFull || s->n_ps_pk > 0xFFFFFFFFull || s->n_dust > 0x7FFFFFFFull)
@@ -283,6 +287,8 @@ soc_status prepare(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *
     A.iteration = iteration;
     A.step_cap = c->step_cap;
     A.absorbed = d_absorbed;
+    A.ali_self = s->d_ali_self;
+    A.ali_emit = s->d_ali_emitted;
     A.next_id = c->d_counter;
     A.st_call = c->d_stats;
     A.st_total = c->d_stats + 1;
@@ -756,8 +762,28 @@ static soc_status temp_stats_buffers(soc_ctx c, TempArgs &a)
     return SOC_OK;
 }
 
+static soc_status update_temperature(soc_ctx c, soc_grid g, soc_temp_table t, const double *d_absorbed,
+                                     const double *d_self, const double *d_emitted, const float *d_T_old,
+                                     float *d_T_new, soc_temp_stats *stats);
+
 soc_status soc_update_temperature(soc_ctx c, soc_grid g, soc_temp_table t, const double *d_absorbed,
                                   const float *d_T_old, float *d_T_new, soc_temp_stats *stats)
+{
+    return update_temperature(c, g, t, d_absorbed, nullptr, nullptr, d_T_old, d_T_new, stats);
+}
+
+soc_status soc_update_temperature_ali(soc_ctx c, soc_grid g, soc_temp_table t, const double *d_absorbed,
+                                      const double *d_ali_self, const double *d_ali_emitted, const float *d_T_old,
+                                      float *d_T_new, soc_temp_stats *stats)
+{
+    if (!c) return SOC_EINVAL;
+    if (!d_ali_self || !d_ali_emitted) return fail(c, SOC_EINVAL, "ALI tallies are NULL");
+    return update_temperature(c, g, t, d_absorbed, d_ali_self, d_ali_emitted, d_T_old, d_T_new, stats);
+}
+
+static soc_status update_temperature(soc_ctx c, soc_grid g, soc_temp_table t, const double *d_absorbed,
+                                     const double *d_self, const double *d_emitted, const float *d_T_old,
+                                     float *d_T_new, soc_temp_stats *stats)
 {
     if (!c) return SOC_EINVAL;
     if (!g || !t || !d_absorbed || !d_T_new) return fail(c, SOC_EINVAL, "NULL argument");
@@ -778,6 +804,8 @@ soc_status soc_update_temperature(soc_ctx c, soc_grid g, soc_temp_table t, const
     a.T_floor = t->T_floor;
     a.T_max = t->T_max;
     a.absorbed = d_absorbed;
+    a.ali_self = d_self;
+    a.ali_emit = d_emitted;
     a.T_old = d_T_old;
     a.T_new = d_T_new;
     int64_t blocks = (g->ncells + 255) / 256;

@@ -61,8 +61,18 @@ __device__ inline void flush_stats(const McArgs &A, unsigned long long pk, unsig
     }
 }
 
-template <bool Oct>
-__global__ __launch_bounds__(kMcMaxBlock) void mc_kernel(McArgs A)
+// Stage of a deposit: with diagonal ALI a dust package's deposits in its
+// own emitting cell go to the self-absorption tally, marked by storing the
+// complement of the cell index.
+template <bool Ali>
+__device__ inline void flush_one(const McArgs &A, double *dst, int32_t key, double v)
+{
+    if (Ali && key < 0) unsafeAtomicAdd(&A.ali_self[~key], v);
+    else unsafeAtomicAdd(&dst[key], v);
+}
+
+template <bool Oct, bool Ali>
+__device__ __forceinline__ void mc_body(const McArgs &A)
 {
     extern __shared__ double lds_dep[];   // [kDepSlots][blockDim.x] deposits, then cells
     int32_t *lds_cell = (int32_t *)(lds_dep + kDepSlots * blockDim.x);
@@ -77,6 +87,7 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_kernel(McArgs A)
     bool active = false;   // lane holds a package
     bool pend = false;     // its last segment ended in a scattering whose new direction is not drawn yet
     bool first_step = false;   // its first step is still to come
+    int32_t origin = -1;       // ALI: emitting cell of a dust package
     unsigned long long pool_next = 0, pool_end = 0;   // wave-uniform
     bool exhausted = false;                           // wave-uniform
     unsigned long long n_pk = 0, n_st = 0, n_sc = 0, n_ru = 0;
@@ -109,6 +120,10 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_kernel(McArgs A)
                     if (ok) e_em += W0;
                     active = ok;
                     first_step = ok;
+                    if (Ali) {
+                        origin = ok && cls == kClassDust ? p.c : -1;
+                        if (origin >= 0) unsafeAtomicAdd(&A.ali_emit[origin], W0);
+                    }
                 }
             }
             if (avail < (unsigned long long)nidle) {
@@ -136,7 +151,7 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_kernel(McArgs A)
         }
         if ((since_flush + 1) * A.inner_steps > kDepSlots) {
             for (int j = 0; j < kDepSlots; ++j)
-                if (j < nbuf) unsafeAtomicAdd(&dst[lds_cell[j * bd + tid]], lds_dep[j * bd + tid]);
+                if (j < nbuf) flush_one<Ali>(A, dst, lds_cell[j * bd + tid], lds_dep[j * bd + tid]);
             nbuf = 0;
             since_flush = 0;
         }
@@ -160,13 +175,14 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_kernel(McArgs A)
             // staged once, which spares the memory-side atomic unit a burst
             // of same-address adds.
             double dep = o.dep;
+            const int32_t key = (Ali && o.cell == origin) ? ~o.cell : o.cell;
             const bool first = stepping && first_step && dep != 0.0;
             if (stepping) first_step = false;
             const unsigned long long fm = __ballot(first);
             if (fm & (fm - 1)) {   // at least two lanes
                 const int leader = __ffsll((long long)fm) - 1;
-                const int c0 = __shfl(o.cell, leader, 64);
-                const bool in = first && o.cell == c0;
+                const int c0 = __shfl(key, leader, 64);
+                const bool in = first && key == c0;
                 const unsigned long long gm = __ballot(in);
                 if (gm & (gm - 1)) {
                     double v = in ? dep : 0.0;
@@ -176,7 +192,7 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_kernel(McArgs A)
             }
             if (dep != 0.0) {
                 lds_dep[nbuf * bd + tid] = dep;
-                lds_cell[nbuf * bd + tid] = o.cell;
+                lds_cell[nbuf * bd + tid] = key;
                 ++nbuf;
             }
             if (stepping) {
@@ -192,14 +208,30 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_kernel(McArgs A)
         }
     }
     for (int j = 0; j < kDepSlots; ++j)
-        if (j < nbuf) unsafeAtomicAdd(&dst[lds_cell[j * bd + tid]], lds_dep[j * bd + tid]);
+        if (j < nbuf) flush_one<Ali>(A, dst, lds_cell[j * bd + tid], lds_dep[j * bd + tid]);
     flush_stats(A, n_pk, n_st, n_sc, n_ru, e_em, e_ab, e_es);
+}
+
+template <bool Oct>
+__global__ __launch_bounds__(kMcMaxBlock) void mc_kernel(McArgs A)
+{
+    mc_body<Oct, false>(A);
+}
+
+// The same with the diagonal-ALI tallies (Sect. 2.1.2).
+template <bool Oct>
+__global__ __launch_bounds__(kMcMaxBlock) void mc_ali_kernel(McArgs A)
+{
+    mc_body<Oct, true>(A);
 }
 
 hipError_t launch_mc(const McArgs &a, int blocks, int threads, hipStream_t s)
 {
     const size_t lds = (size_t)kDepSlots * threads * (sizeof(double) + sizeof(int32_t));
-    if (a.nlevels > 1) hipLaunchKernelGGL(mc_kernel<true>, dim3(blocks), dim3(threads), lds, s, a);
+    const bool ali = a.ali_self != nullptr;
+    if (a.nlevels > 1 && ali) hipLaunchKernelGGL(mc_ali_kernel<true>, dim3(blocks), dim3(threads), lds, s, a);
+    else if (ali) hipLaunchKernelGGL(mc_ali_kernel<false>, dim3(blocks), dim3(threads), lds, s, a);
+    else if (a.nlevels > 1) hipLaunchKernelGGL(mc_kernel<true>, dim3(blocks), dim3(threads), lds, s, a);
     else hipLaunchKernelGGL(mc_kernel<false>, dim3(blocks), dim3(threads), lds, s, a);
     return hipGetLastError();
 }

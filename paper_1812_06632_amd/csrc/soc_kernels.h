@@ -65,6 +65,8 @@ struct McArgs {
     int64_t step_cap;
     double *absorbed;
     double *priv;                // NULL, or 8 private copies of ncells (one per XCD, hardware XCC id)
+    double *ali_self;            // diagonal ALI (NULL = off): dust deposits in the emitting cell
+    double *ali_emit;            // ... and the initial weight of every dust package, per emitting cell
     // persistent scheduling
     unsigned long long *next_id;
     DevStats *st_call, *st_total;
@@ -145,6 +147,8 @@ struct TempArgs {
     int32_t nT;
     double lnTf, dlnT, T_floor, T_max;
     const double *absorbed;
+    const double *ali_self;      // diagonal ALI (NULL = off): self-absorbed and emitted dust energy
+    const double *ali_emit;
     const float *T_old;
     float *T_new;
     int32_t given;               // 1: T_new holds a given field; statistics only, nothing written

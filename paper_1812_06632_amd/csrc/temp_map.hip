@@ -88,7 +88,15 @@ __global__ __launch_bounds__(kTempThreads) void temp_update_kernel(TempArgs a)
             } else {
                 const int L = level_index(c, a.level_offset, a.nlevels);
                 const double s = ldexp(a.root_cell_cm, -L);
-                const double y = a.absorbed[c] / ((double)nf * (s * s * s));
+                double y = a.absorbed[c] / ((double)nf * (s * s * s));
+                if (a.ali_self) {
+                    // diagonal ALI: the cell re-absorbs the fraction self/emitted of its own
+                    // emission, so its emission is the absorption from elsewhere over the
+                    // escape probability (kept >= 1e-6)
+                    const double e = a.ali_emit[c];
+                    const double esc = e > 0.0 ? fmax(1.0 - a.ali_self[c] / e, 1e-6) : 1.0;
+                    y /= esc;
+                }
                 if (!(y > 0.0)) {
                     T = a.T_floor;
                     clamped = true;

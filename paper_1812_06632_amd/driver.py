@@ -18,6 +18,10 @@ running mean of the absorption estimates (one stored number per cell).
 The number of packages may grow over the iterations (a geometric
 schedule).
 
+Diagonal ALI (Sect. 2.1.2, 4.1, plain iteration): the dust packages count
+what they deposit in their own emitting cell apart, and the temperature
+solve takes each cell's own absorption-emission cycle exactly.
+
 Control flow only: every step is a call through the C-ABI library; the
 stopping rule compares two scalars the temperature kernel returns.
 """
@@ -39,13 +43,15 @@ def converged(prev: dict, cur: dict, tol: float = 0.01) -> bool:
 class PlainSolver:
     """One problem (workloads.Problem) resident on the device."""
 
-    def __init__(self, ctx: soc.Context, P, seed: int = 1, nT: int = 4096, packages=None, cap: float = 0.0):
+    def __init__(self, ctx: soc.Context, P, seed: int = 1, nT: int = 4096, packages=None, cap: float = 0.0,
+                 ali: bool = False):
         """packages(it): dust packages per frequency of iteration it
         (default P.n_dust); cap: expected packages per cell at most (0 =
-        none)."""
+        none); ali: diagonal ALI (Sect. 2.1.2) in the dust iterations."""
         self.ctx, self.P, self.seed = ctx, P, seed
         self.packages = packages
         self.cap = float(cap)
+        self.ali = bool(ali)
         self.grid = soc.grid_from_workload(ctx, P.grid)
         self.table = soc.temp_table_build(ctx, P.emit_nu, P.emit_w, P.emit_sigma_abs, P.T_floor, P.T_max, nT)
         nc = P.grid.ncells
@@ -56,6 +62,8 @@ class PlainSolver:
         self.T_new = torch.zeros(nc, dtype=torch.float32, device=dev)
         self.freqs = [(float(P.nu[k]), float(P.w[k]), float(P.sigma_abs[k]), float(P.sigma_sca[k]), float(P.g[k]))
                       for k in range(P.K)]
+        self.S_ali = torch.zeros(nc, dtype=torch.float64, device=dev) if self.ali else None
+        self.E_ali = torch.zeros(nc, dtype=torch.float64, device=dev) if self.ali else None
 
     def constant_pass(self) -> dict:
         """Iteration 1: the constant sources at every frequency, then the
@@ -86,10 +94,15 @@ class PlainSolver:
         P = self.P
         n = self.n_packages(it)
         self.A.copy_(self.A_const)
+        if self.ali:
+            self.S_ali.zero_()
+            self.E_ali.zero_()
         for k in range(P.K):
             soc.simulate_frequency(self.ctx, self.grid, self.freqs[k], self.A, T=self.T, n_dust=n, dust_mode=1,
-                                   dust_cap=self.cap, seed=self.seed, iteration=it, freq_index=k)
-        s = soc.update_temperature(self.ctx, self.grid, self.table, self.A, self.T_new, self.T, stats=True)
+                                   dust_cap=self.cap, ali_self=self.S_ali, ali_emitted=self.E_ali, seed=self.seed,
+                                   iteration=it, freq_index=k)
+        s = soc.update_temperature(self.ctx, self.grid, self.table, self.A, self.T_new, self.T, stats=True,
+                                   ali_self=self.S_ali, ali_emitted=self.E_ali)
         self.T.copy_(self.T_new)
         s["packages"] = n
         return s
@@ -173,7 +186,7 @@ class ReferenceFieldSolver(PlainSolver):
 
     def __init__(self, ctx: soc.Context, P, seed: int = 1, nT: int = 4096, packages=None, cap: float = 0.0,
                  mode: str = "correction"):
-        super().__init__(ctx, P, seed, nT, packages, cap)
+        super().__init__(ctx, P, seed, nT, packages, cap, ali=False)
         if mode not in ("correction", "average"):
             raise ValueError("mode must be 'correction' or 'average'")
         self.mode = mode

@@ -53,7 +53,7 @@ class _Sources(C.Structure):
     _fields_ = [("I_bg_nu", C.c_double), ("n_ps", C.c_int32), ("ps", C.POINTER(_PointSource)),
                 ("d_T", C.c_void_p), ("n_bg", C.c_uint64), ("n_ps_pk", C.c_uint64), ("n_dust", C.c_uint64),
                 ("dust_mode", C.c_int32), ("d_L_ref", C.c_void_p), ("ref_beta", C.c_double),
-                ("dust_cap", C.c_double)]
+                ("dust_cap", C.c_double), ("d_ali_self", C.c_void_p), ("d_ali_emitted", C.c_void_p)]
 
 
 class _SimStats(C.Structure):
@@ -82,6 +82,8 @@ _lib.soc_grid_destroy.argtypes = [C.c_void_p]
 _lib.soc_grid_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_void_p)]
 _lib.soc_simulate_frequency.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Freq), C.POINTER(_Sources), C.c_uint64,
                                         C.c_uint32, C.c_uint32, C.c_void_p, C.POINTER(_SimStats)]
+_lib.soc_update_temperature_ali.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(_TempStats)]
 _lib.soc_reference_blend.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_void_p, C.c_void_p]
 _lib.soc_read_stats.argtypes = [C.c_void_p, C.POINTER(_SimStats), C.c_int32]
 _lib.soc_trace_packages.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Freq), C.POINTER(_Sources), C.c_uint64,
@@ -215,7 +217,7 @@ def _freq(f):
 
 class _SourceView:
     def __init__(self, I_bg=0.0, ps_pos=None, ps_Lnu=None, T=None, n_bg=0, n_ps_pk=0, n_dust=0, dust_mode=1,
-                 L_ref=None, ref_beta=0.0, dust_cap=0.0):
+                 L_ref=None, ref_beta=0.0, dust_cap=0.0, ali_self=None, ali_emitted=None):
         pos = np.zeros((0, 3)) if ps_pos is None else np.asarray(ps_pos, dtype=np.float64).reshape(-1, 3)
         L = np.zeros(0) if ps_Lnu is None else np.asarray(ps_Lnu, dtype=np.float64).reshape(-1)
         n_ps = pos.shape[0]
@@ -226,18 +228,24 @@ class _SourceView:
                           _dev_ptr(T, torch.float32, "T") if T is not None else None,
                           int(n_bg), int(n_ps_pk), int(n_dust), int(dust_mode),
                           _dev_ptr(L_ref, torch.float64, "L_ref") if L_ref is not None else None,
-                          float(ref_beta), float(dust_cap))
+                          float(ref_beta), float(dust_cap),
+                          _dev_ptr(ali_self, torch.float64, "ali_self") if ali_self is not None else None,
+                          _dev_ptr(ali_emitted, torch.float64, "ali_emitted") if ali_emitted is not None else None)
+        self.ali = (ali_self, ali_emitted)
 
 
 def simulate_frequency(ctx: Context, grid: Grid, freq, absorbed: torch.Tensor, *, I_bg=0.0, ps_pos=None,
                        ps_Lnu=None, T=None, n_bg=0, n_ps_pk=0, n_dust=0, dust_mode=1, L_ref=None, ref_beta=0.0,
-                       dust_cap=0.0, seed=1, iteration=0, freq_index=0, stats=False):
+                       dust_cap=0.0, ali_self=None, ali_emitted=None, seed=1, iteration=0, freq_index=0,
+                       stats=False):
     """soc_simulate_frequency.  freq = (nu, w_nu, sigma_abs, sigma_sca, g);
     absorbed: float64 CUDA tensor of ncells (accumulated).  dust_mode 2
     emits the difference to L_ref (float64 CUDA tensor of ncells, blended
-    in place with weight ref_beta).  Returns the call's statistics dict if
-    stats, else None (asynchronous)."""
-    sv = _SourceView(I_bg, ps_pos, ps_Lnu, T, n_bg, n_ps_pk, n_dust, dust_mode, L_ref, ref_beta, dust_cap)
+    in place with weight ref_beta).  ali_self / ali_emitted: float64 CUDA
+    tensors of ncells, the diagonal-ALI tallies (+=).  Returns the call's
+    statistics dict if stats, else None (asynchronous)."""
+    sv = _SourceView(I_bg, ps_pos, ps_Lnu, T, n_bg, n_ps_pk, n_dust, dust_mode, L_ref, ref_beta, dust_cap,
+                     ali_self, ali_emitted)
     f = _freq(freq)
     st = _SimStats() if stats else None
     ctx.check(_lib.soc_simulate_frequency(ctx.h, grid.h, C.byref(f), C.byref(sv.s), C.c_uint64(seed),
@@ -304,12 +312,22 @@ def temp_table_build(ctx: Context, nu, w_nu, sigma_abs, T_floor=2.0, T_max=3000.
 
 
 def update_temperature(ctx: Context, grid: Grid, table: TempTable, absorbed: torch.Tensor, T_new: torch.Tensor,
-                       T_old: torch.Tensor | None = None, stats=False):
+                       T_old: torch.Tensor | None = None, stats=False, ali_self=None, ali_emitted=None):
+    """soc_update_temperature, or soc_update_temperature_ali with the ALI
+    tallies."""
     st = _TempStats() if stats else None
-    ctx.check(_lib.soc_update_temperature(ctx.h, grid.h, table.h, _dev_ptr(absorbed, torch.float64, "absorbed"),
-                                          _dev_ptr(T_old, torch.float32, "T_old") if T_old is not None else None,
-                                          _dev_ptr(T_new, torch.float32, "T_new"),
-                                          C.byref(st) if st is not None else None))
+    T_old_p = _dev_ptr(T_old, torch.float32, "T_old") if T_old is not None else None
+    if ali_self is not None or ali_emitted is not None:
+        ctx.check(_lib.soc_update_temperature_ali(ctx.h, grid.h, table.h,
+                                                  _dev_ptr(absorbed, torch.float64, "absorbed"),
+                                                  _dev_ptr(ali_self, torch.float64, "ali_self"),
+                                                  _dev_ptr(ali_emitted, torch.float64, "ali_emitted"), T_old_p,
+                                                  _dev_ptr(T_new, torch.float32, "T_new"),
+                                                  C.byref(st) if st is not None else None))
+    else:
+        ctx.check(_lib.soc_update_temperature(ctx.h, grid.h, table.h, _dev_ptr(absorbed, torch.float64, "absorbed"),
+                                              T_old_p, _dev_ptr(T_new, torch.float32, "T_new"),
+                                              C.byref(st) if st is not None else None))
     if st is None:
         return None
     return {k: getattr(st, k) for k, _ in _TempStats._fields_}
