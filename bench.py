@@ -403,6 +403,77 @@ def reference_gain(args, soc, torch, W):
     ctx.close()
 
 
+def ali_gain(args, soc, torch, W):
+    """Plain versus diagonal-ALI iteration (Sect. 2.1.2, 4.1) on the paper's
+    ALI test setup: a lognormal cloud shrunk to a (--ali-box pc)^3 box with
+    mean tau_V --ali-tau and one central --ali-lsun L_sun source, so that
+    dust near the source is hot and its emission is absorbed nearby.  The
+    same density field (made at 128^3) is block-averaged to 32^3, 64^3 and
+    128^3: coarser cells are optically thicker, where ALI should help most.
+    At each resolution, both iterations run --ali-iters iterations against a
+    long reference run (mean of the last 8 of --ali-ref-iters ALI
+    iterations; the two iterations share their fixed point, and in thick
+    clouds the plain one is still far from it after 40): the first
+    iteration whose mean and hottest-5% mean temperatures are within 1% of
+    the reference's (the paper's |<dT>| measure), the wall time to it, and
+    the cost per iteration."""
+    import dataclasses
+
+    from paper_1812_06632_amd.driver import PlainSolver
+    ctx = soc.Context(0)
+    base = W.lognormal_problem(n=128, K=args.freqs, sigma_ln=1.0, tau_v_mean=args.ali_tau, box_pc=args.ali_box,
+                               L_star_lsun=args.ali_lsun, ps_frac=((0.5, 0.5, 0.5),), packages_per_freq=args.packages)
+    rho128 = base.grid.density().reshape(128, 128, 128).astype(np.float64)
+    out = []
+    for n in (32, 64, 128):
+        f = 128 // n
+        rho = rho128.reshape(n, f, n, f, n, f).mean(axis=(1, 3, 5))
+        ps = base.ps_pos / f
+        for p in ps:
+            rho[int(p[2]), int(p[1]), int(p[0])] = 0.0   # the source sits in an empty cell
+        P = dataclasses.replace(base, grid=W.regular_grid(rho.astype(np.float32), base.grid.root_cell_cm * f),
+                                ps_pos=ps)
+        ref = PlainSolver(ctx, P, seed=7, ali=True)
+        ref.constant_pass()
+        avg = 8
+        burn = args.ali_ref_iters - avg
+        m_ref = h_ref = 0.0
+        for it in range(2, burn + avg + 2):
+            s = ref.dust_iteration(it)
+            if it > burn + 1:
+                m_ref += s["mean_T"] / avg
+                h_ref += s["hot5_mean_T"] / avg
+        del ref
+        log(f"{n}^3: reference <T> {m_ref:.3f} K, hottest 5% {h_ref:.3f} K")
+        runs = {}
+        for ali in (False, True):
+            S = PlainSolver(ctx, P, seed=1, ali=ali)
+            hist, at = S.run(max_iter=args.ali_iters, until_stop=False)
+            dm = [abs(h[2]["mean_T"] / m_ref - 1) for h in hist]
+            dh = [abs(h[2]["hot5_mean_T"] / h_ref - 1) for h in hist]
+            within = next((h[0] for h, a, b in zip(hist, dm, dh) if a < 0.01 and b < 0.01), None)
+            reach = {f"iterations_to_{int(x * 100)}pct": next((h[0] for h, a, b in zip(hist, dm, dh)
+                                                                 if a < x and b < x), None) for x in (0.1, 0.05)}
+            per_it = (hist[-1][1] - hist[0][1]) / (len(hist) - 1)
+            runs["ali" if ali else "plain"] = {
+                "iterations_to_1pct": within, "wall_s_to_1pct": hist[within - 1][1] if within else None,
+                "stopping_rule_at": at, "s_per_dust_iteration": per_it, **reach,
+                "rel_dmean_by_iteration": [round(x, 5) for x in dm], "rel_dhot5_by_iteration": [round(x, 5) for x in dh]}
+            log(f"{n}^3 {'ALI' if ali else 'plain'}: within 1% of the reference at iteration {within}, "
+                f"stopping rule at {at}, {per_it:.3f} s per dust iteration")
+            del S
+        rec = {"cells": f"{n}^3", "reference_mean_T": m_ref, "reference_hot5_mean_T": h_ref, "runs": runs,
+               "ali_overhead": runs["ali"]["s_per_dust_iteration"] / runs["plain"]["s_per_dust_iteration"] - 1.0}
+        if runs["ali"]["wall_s_to_1pct"] and runs["plain"]["wall_s_to_1pct"]:
+            rec["speedup_to_1pct"] = runs["plain"]["wall_s_to_1pct"] / runs["ali"]["wall_s_to_1pct"]
+        out.append(rec)
+    line = {"kind": "ali", "workload": f"lognormal sigma_ln 1, mean tau_V {args.ali_tau}, {args.ali_box} pc box, one "
+                                      f"{args.ali_lsun:g} L_sun source at the centre, {args.freqs} frequencies, "
+                                      f"{args.packages} packages/frequency", "resolutions": out}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -434,6 +505,12 @@ def main():
                     help="plain versus reference-field iteration, constant and growing package counts")
     ap.add_argument("--ref-iters", type=int, default=10)
     ap.add_argument("--ref-factor", type=float, default=16.0)
+    ap.add_argument("--ali", action="store_true", help="plain versus diagonal-ALI iteration at three resolutions")
+    ap.add_argument("--ali-iters", type=int, default=20)
+    ap.add_argument("--ali-ref-iters", type=int, default=60)
+    ap.add_argument("--ali-tau", type=float, default=500.0)
+    ap.add_argument("--ali-box", type=float, default=0.05)
+    ap.add_argument("--ali-lsun", type=float, default=1.0e5)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the design notes describe how the "
@@ -459,6 +536,9 @@ def main():
         return
     if args.reference:
         reference_gain(args, soc, torch, W)
+        return
+    if args.ali:
+        ali_gain(args, soc, torch, W)
         return
 
     from paper_1812_06632_amd.driver import PlainSolver, converged

@@ -43,6 +43,8 @@ struct soc_ctx_s {
     double *d_tmp_out = nullptr;              // small result buffer (temperature stats)
     double *d_priv = nullptr;                 // 8 private copies of the absorbed array (zero between launches)
     int64_t cap_priv = 0;
+    double *d_priv_self = nullptr;            // the same for the ALI self-absorption tally
+    int64_t cap_priv_self = 0;
     double *d_L = nullptr, *d_incl = nullptr, *d_scan = nullptr;
     int64_t cap_L = 0, cap_incl = 0, cap_scan = 0;
     double *d_a = nullptr, *d_S = nullptr;   // selection weights / capped counts; sum of |L| (capped mode)
@@ -288,7 +290,15 @@ soc_status prepare(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *
     A.step_cap = c->step_cap;
     A.absorbed = d_absorbed;
     A.ali_self = s->d_ali_self;
-    A.ali_emit = s->d_ali_emitted;
+    if (s->d_ali_emitted && A.n_dust > 0) {
+        // emitted dust energy per cell from the package assignment (no atomics)
+        if (A.dust_mode == 0)
+            HIPCHK(c, launch_dust_emitted_uniform(g->d_leaves, g->nleaves, A.dust_L, A.per_leaf, s->d_ali_emitted,
+                                                  c->stream));
+        else
+            HIPCHK(c, launch_dust_emitted_weighted(A.dust_cell, A.n_dust, A.dust_L, A.dust_S, A.dust_mode, A.dust_cap,
+                                                   s->d_ali_emitted, c->stream));
+    }
     A.next_id = c->d_counter;
     A.st_call = c->d_stats;
     A.st_total = c->d_stats + 1;
@@ -355,6 +365,7 @@ void soc_ctx_destroy(soc_ctx c)
     (void)hipFree(c->d_counter);
     (void)hipFree(c->d_tmp_out);
     (void)hipFree(c->d_priv);
+    (void)hipFree(c->d_priv_self);
     (void)hipFree(c->d_L);
     (void)hipFree(c->d_incl);
     (void)hipFree(c->d_a);
@@ -579,6 +590,14 @@ soc_status soc_simulate_frequency(soc_ctx c, soc_grid g, const soc_freq *f, cons
             HIPCHK(c, launch_fill_f64(c->d_priv, 0.0, c->cap_priv, c->stream));
         }
         A.priv = c->d_priv;
+        if (A.ali_self) {
+            if (c->cap_priv_self < 8 * g->ncells) {
+                st = grow(c, &c->d_priv_self, c->cap_priv_self, 8 * g->ncells);
+                if (st) return st;
+                HIPCHK(c, launch_fill_f64(c->d_priv_self, 0.0, c->cap_priv_self, c->stream));
+            }
+            A.priv_self = c->d_priv_self;
+        }
     }
     HIPCHK(c, launch_fill_u64((unsigned long long *)c->d_stats, 0ull, (int64_t)(sizeof(DevStats) / 8), c->stream));
     HIPCHK(c, launch_fill_u64(c->d_counter, 0ull, 1, c->stream));
@@ -596,6 +615,7 @@ soc_status soc_simulate_frequency(soc_ctx c, soc_grid g, const soc_freq *f, cons
         c->ev_stop.push_back(e1);
     }
     if (A.priv) HIPCHK(c, launch_fold_copies(d_absorbed, A.priv, g->ncells, c->stream));
+    if (A.priv_self) HIPCHK(c, launch_fold_copies(A.ali_self, A.priv_self, g->ncells, c->stream));
     if (stats) {
         DevStats h;
         HIPCHK(c, hipMemcpyAsync(&h, c->d_stats, sizeof h, hipMemcpyDeviceToHost, c->stream));
@@ -640,7 +660,9 @@ soc_status soc_trace_packages(soc_ctx c, soc_grid g, const soc_freq *f, const so
     HIPCHK(c, hipSetDevice(c->device));
     if (!s) return fail(c, SOC_EINVAL, "sources is NULL");
     soc_sources s_trace = *s;
-    s_trace.ref_beta = 0.0;   // tracing leaves the reference emission as it is
+    s_trace.ref_beta = 0.0;   // tracing leaves the reference emission and the ALI tallies as they are
+    s_trace.d_ali_self = nullptr;
+    s_trace.d_ali_emitted = nullptr;
     McArgs A;
     soc_status st = prepare(c, g, f, &s_trace, seed, iteration, freq_index, nullptr, A);
     if (st) return st;

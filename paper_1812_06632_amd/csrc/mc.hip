@@ -65,9 +65,9 @@ __device__ inline void flush_stats(const McArgs &A, unsigned long long pk, unsig
 // own emitting cell go to the self-absorption tally, marked by storing the
 // complement of the cell index.
 template <bool Ali>
-__device__ inline void flush_one(const McArgs &A, double *dst, int32_t key, double v)
+__device__ inline void flush_one(double *dst, double *sdst, int32_t key, double v)
 {
-    if (Ali && key < 0) unsafeAtomicAdd(&A.ali_self[~key], v);
+    if (Ali && key < 0) unsafeAtomicAdd(&sdst[~key], v);
     else unsafeAtomicAdd(&dst[key], v);
 }
 
@@ -95,6 +95,7 @@ __device__ __forceinline__ void mc_body(const McArgs &A)
     const float ks = A.ks_f, ka = A.ka_f;
     const HG<float> hg(A.g_f);
     double *const dst = A.priv ? A.priv + (size_t)xcd_index() * (size_t)A.ncells : A.absorbed;
+    double *const sdst = A.priv_self ? A.priv_self + (size_t)xcd_index() * (size_t)A.ncells : A.ali_self;
 
     for (;;) {
         // refill idle lanes from the wave's id pool
@@ -120,10 +121,7 @@ __device__ __forceinline__ void mc_body(const McArgs &A)
                     if (ok) e_em += W0;
                     active = ok;
                     first_step = ok;
-                    if (Ali) {
-                        origin = ok && cls == kClassDust ? p.c : -1;
-                        if (origin >= 0) unsafeAtomicAdd(&A.ali_emit[origin], W0);
-                    }
+                    if (Ali) origin = ok && cls == kClassDust ? p.c : -1;
                 }
             }
             if (avail < (unsigned long long)nidle) {
@@ -151,7 +149,7 @@ __device__ __forceinline__ void mc_body(const McArgs &A)
         }
         if ((since_flush + 1) * A.inner_steps > kDepSlots) {
             for (int j = 0; j < kDepSlots; ++j)
-                if (j < nbuf) flush_one<Ali>(A, dst, lds_cell[j * bd + tid], lds_dep[j * bd + tid]);
+                if (j < nbuf) flush_one<Ali>(dst, sdst, lds_cell[j * bd + tid], lds_dep[j * bd + tid]);
             nbuf = 0;
             since_flush = 0;
         }
@@ -208,7 +206,7 @@ __device__ __forceinline__ void mc_body(const McArgs &A)
         }
     }
     for (int j = 0; j < kDepSlots; ++j)
-        if (j < nbuf) flush_one<Ali>(A, dst, lds_cell[j * bd + tid], lds_dep[j * bd + tid]);
+        if (j < nbuf) flush_one<Ali>(dst, sdst, lds_cell[j * bd + tid], lds_dep[j * bd + tid]);
     flush_stats(A, n_pk, n_st, n_sc, n_ru, e_em, e_ab, e_es);
 }
 

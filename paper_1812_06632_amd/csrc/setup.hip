@@ -190,6 +190,59 @@ hipError_t launch_dust_cap(double *a, int64_t n, const double *S_in, double *S_o
     return hipGetLastError();
 }
 
+// Diagonal ALI, emitted dust energy per cell.  The packages of a cell form
+// one run of the non-decreasing cell list; the thread at the end of a run
+// finds its start by binary search and adds count x weight, so every cell
+// has one writer and no atomics are needed.
+__global__ void dust_emitted_weighted_kernel(const int32_t *cell, uint64_t n_dust, const double *dL, const double *S,
+                                             int32_t mode, double cap, double *E)
+{
+    const double WN = *S / (double)n_dust;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_dust; j += (uint64_t)gridDim.x * blockDim.x) {
+        const int32_t c = cell[j];
+        if (c < 0) continue;
+        if (j + 1 < n_dust && cell[j + 1] == c) continue;
+        uint64_t lo = 0, hi = j;   // first index whose cell is c (cells are non-decreasing before any -1)
+        while (lo < hi) {
+            const uint64_t mid = lo + ((hi - lo) >> 1);
+            if (cell[mid] < c) lo = mid + 1; else hi = mid;
+        }
+        const double W0 = (mode == 1 && !(cap > 0.0)) ? WN : weighted_package_weight(WN, cap, dL[c]);
+        E[c] += (double)(j - lo + 1) * W0;
+    }
+}
+
+hipError_t launch_dust_emitted_weighted(const int32_t *cell, uint64_t n_dust, const double *dL, const double *S,
+                                        int32_t mode, double cap, double *E, hipStream_t s)
+{
+    if (n_dust == 0) return hipSuccess;
+    uint64_t blocks = (n_dust + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(dust_emitted_weighted_kernel, dim3((unsigned)blocks), dim3(256), 0, s, cell, n_dust, dL, S,
+                       mode, cap, E);
+    return hipGetLastError();
+}
+
+__global__ void dust_emitted_uniform_kernel(const int64_t *leaves, int64_t nleaves, const double *L, uint64_t per_leaf,
+                                            double *E)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nleaves; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = leaves ? leaves[i] : i;
+        E[c] += (double)per_leaf * (L[c] / (double)per_leaf);
+    }
+}
+
+hipError_t launch_dust_emitted_uniform(const int64_t *leaves, int64_t nleaves, const double *L, uint64_t per_leaf,
+                                       double *E, hipStream_t s)
+{
+    if (nleaves == 0) return hipSuccess;
+    int64_t blocks = (nleaves + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(dust_emitted_uniform_kernel, dim3((unsigned)blocks), dim3(256), 0, s, leaves, nleaves, L,
+                       per_leaf, E);
+    return hipGetLastError();
+}
+
 __global__ void blend_kernel(const double *x, double *ref, int64_t n, double beta)
 {
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {

@@ -314,6 +314,7 @@ __device__ inline bool cross_octree(Pkg<R> &p, const AT &A, int a, bool fw)
 }
 
 // ------------------------------------------------------------------ emission
+
 // Emit package `gid` (global order: background | point sources | dust) and
 // draw its first free path.  Returns false for a package that carries no
 // energy (it is counted but not traced).  `cls`/`pid` receive the class
@@ -399,13 +400,7 @@ __device__ inline bool emit(const AT &A, uint64_t gid, Pkg<R> &p, Rng &rng, uint
             c = A.dust_cell[j];
             if (c < 0) return false;
             const double WN = *A.dust_S / (double)A.n_dust;
-            if (A.dust_mode == 1 && !(A.dust_cap > 0.0)) {
-                W0 = WN;
-            } else {
-                const double Lc = A.dust_L[c];
-                const double m = A.dust_cap > 0.0 ? fmax(WN, fabs(Lc) / A.dust_cap) : WN;
-                W0 = copysign(m, Lc);
-            }
+            W0 = (A.dust_mode == 1 && !(A.dust_cap > 0.0)) ? WN : weighted_package_weight(WN, A.dust_cap, A.dust_L[c]);
         }
         if (!(fabs(W0) > 0.0)) return false;
         int64_t root = c;

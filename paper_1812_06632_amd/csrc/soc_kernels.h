@@ -66,7 +66,7 @@ struct McArgs {
     double *absorbed;
     double *priv;                // NULL, or 8 private copies of ncells (one per XCD, hardware XCC id)
     double *ali_self;            // diagonal ALI (NULL = off): dust deposits in the emitting cell
-    double *ali_emit;            // ... and the initial weight of every dust package, per emitting cell
+    double *priv_self;           // NULL, or 8 private copies of ali_self (one per XCD)
     // persistent scheduling
     unsigned long long *next_id;
     DevStats *st_call, *st_total;
@@ -86,6 +86,15 @@ struct TraceArgs {
     SegmentDev *out;
     int32_t *nseg;
 };
+
+// Weight of a package of cell c in the weighted dust modes: L_c over the
+// cell's expected count min(N |L_c| / S, cap), i.e. S / N (= WN) or, for a
+// capped cell, |L_c| / cap, with the sign of L_c.
+__device__ inline double weighted_package_weight(double WN, double cap, double Lc)
+{
+    const double m = cap > 0.0 ? fmax(WN, fabs(Lc) / cap) : WN;
+    return copysign(m, Lc);
+}
 
 // ---- launchers (each returns the launch status) ----
 // Regular-grid kernels when a.nlevels == 1, octree kernels otherwise.
@@ -122,6 +131,14 @@ hipError_t launch_dust_cap(double *a, int64_t n, const double *S_in, double *S_o
 // total).
 hipError_t launch_dust_select(const double *incl, int64_t ncells, uint64_t n_dust, double u_sys, int32_t package_units,
                               int32_t *cell_out, hipStream_t s);
+// Diagonal ALI: the dust energy each cell emits in this call, added to E.
+// Weighted modes: from the cell of every package (non-decreasing, -1 past
+// a capped total), one writer per cell; uniform mode: per_leaf packages of
+// L_c / per_leaf in every leaf.
+hipError_t launch_dust_emitted_weighted(const int32_t *cell, uint64_t n_dust, const double *dL, const double *S,
+                                        int32_t mode, double cap, double *E, hipStream_t s);
+hipError_t launch_dust_emitted_uniform(const int64_t *leaves, int64_t nleaves, const double *L, uint64_t per_leaf,
+                                       double *E, hipStream_t s);
 // ref += beta (x - ref) over n doubles.
 hipError_t launch_blend(const double *x, double *ref, int64_t n, double beta, hipStream_t s);
 
