@@ -36,6 +36,10 @@ class _Sources(C.Structure):
                 ("ali_self", C.POINTER(C.c_double)), ("ali_emitted", C.POINTER(C.c_double))]
 
 
+class _ScatterParams(C.Structure):
+    _fields_ = [("axis", C.c_int32), ("forced", C.c_int32), ("max_scatter", C.c_int32), ("direct", C.c_int32)]
+
+
 class _Stats(C.Structure):
     _fields_ = [("packages", C.c_uint64), ("cell_steps", C.c_uint64), ("scatterings", C.c_uint64),
                 ("runaways", C.c_uint64), ("e_emitted", C.c_double), ("e_absorbed", C.c_double),
@@ -71,7 +75,7 @@ def lib():
         L.orc_validate_grid.restype = C.c_int32
         for name in ("orc_simulate_frequency", "orc_trace_package", "orc_trace_from",
                      "orc_update_temperature", "orc_map", "orc_dust_luminosity",
-                     "orc_update_temperature_ali"):
+                     "orc_update_temperature_ali", "orc_scatter_map"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -217,6 +221,29 @@ def trace_package(grid, freq, cls, package_id, *, I_bg=0.0, ps_pos=None, ps_Lnu=
     if rc != 0:
         raise ValueError(f"orc_trace_package failed: {rc}")
     return out[: min(ns.value, max_seg)].copy()
+
+
+def scatter_map(grid, freq, *, axis=2, forced=True, max_scatter=0, direct=False, I_bg=0.0, ps_pos=None,
+                ps_Lnu=None, n_bg=0, n_ps_pk=0, seed=1, iteration=0, freq_index=0, step_cap=0, nthreads=8):
+    """Peel-off image of scattered light (erg s^-1 cm^-2 Hz^-1 sr^-1),
+    npy x npx as map_image, and the run's statistics."""
+    gv = GridView(grid)
+    sv = _SourcesView(I_bg, ps_pos, ps_Lnu, None, n_bg, n_ps_pk, 0, 1)
+    f = _freq(freq)
+    a = axis & 3
+    N = [grid.nx, grid.ny, grid.nz]
+    b, c = (1 if a == 0 else 0), (1 if a == 2 else 2)
+    fine = 1 << (grid.nlevels - 1)
+    npx, npy = N[b] * fine, N[c] * fine
+    img = np.zeros(npx * npy, dtype=np.float64)
+    sp = _ScatterParams(int(axis), int(bool(forced)), int(max_scatter), int(bool(direct)))
+    st = _Stats()
+    rc = lib().orc_scatter_map(C.byref(gv.s), C.byref(f), C.byref(sv.s), C.c_uint64(seed), C.c_uint32(iteration),
+                               C.c_uint32(freq_index), C.byref(sp), C.c_int64(step_cap), C.c_int32(nthreads),
+                               _p(img, C.c_double), C.byref(st))
+    if rc != 0:
+        raise ValueError(f"orc_scatter_map failed: {rc}")
+    return img.reshape(npy, npx), _stats_dict(st)
 
 
 def dust_luminosity(grid, freq, T):

@@ -491,22 +491,25 @@ static int64_t weighted_cell(const sim_ctx *X, uint64_t j)
     return lo;
 }
 
-/* Emission of global package gid (class order bg | ps0..psN-1 | dust) and
- * its transport.  Returns the initial weight W0. */
-static double run_package(const sim_ctx *X, uint64_t gid, double *absorbed, int64_t *hits, pk_tally *t,
-                          orc_segment *seg, int32_t max_seg, int32_t *nseg, double *self_abs, double *emitted)
+/* Emission of global package gid (class order bg | ps0..psN-1 | dust):
+ * position p, direction u, energy W0 and the package's random stream.
+ * origin receives the emitting cell of a dust package (-1 otherwise) and
+ * cls its class.  Returns 0 for a package that carries no energy. */
+static int emit_package(const sim_ctx *X, uint64_t gid, double p[3], double u[3], double *W0_out, stream_t *rs_out,
+                        int64_t *origin_out, uint32_t *cls_out)
 {
     int64_t origin = -1;
     const orc_grid *g = X->g;
     const orc_sources *s = X->s;
-    double p[3], u[3], W0;
+    double W0;
     stream_t rs;
     uint64_t nbg = s->n_bg, nps = (uint64_t)s->n_ps * s->n_ps_pk;
     if (gid < nbg) {
         uint32_t pid = (uint32_t)gid;
         stream_init(&rs, X->seed, X->iteration, ORC_CLASS_BG, X->freq_index, pid);
+        *cls_out = ORC_CLASS_BG;
         W0 = X->W_bg;
-        if (!(W0 > 0.0)) return 0.0;
+        if (!(W0 > 0.0)) return 0;
         double N[3] = {(double)g->nx, (double)g->ny, (double)g->nz};
         double area[6] = {N[1] * N[2], N[1] * N[2], N[0] * N[2], N[0] * N[2], N[0] * N[1], N[0] * N[1]};
         double tot = area[0] + area[1] + area[2] + area[3] + area[4] + area[5];
@@ -531,14 +534,16 @@ static double run_package(const sim_ctx *X, uint64_t gid, double *absorbed, int6
         int32_t src = (int32_t)(k / s->n_ps_pk);
         uint32_t pid = (uint32_t)(k % s->n_ps_pk);
         stream_init(&rs, X->seed, X->iteration, ORC_CLASS_PS0 + (uint32_t)src, X->freq_index, pid);
+        *cls_out = ORC_CLASS_PS0 + (uint32_t)src;
         W0 = s->ps_L_nu[src] * X->f->w_nu / (double)s->n_ps_pk;
-        if (!(W0 > 0.0)) return 0.0;
+        if (!(W0 > 0.0)) return 0;
         p[0] = s->ps_pos[3 * src]; p[1] = s->ps_pos[3 * src + 1]; p[2] = s->ps_pos[3 * src + 2];
         double x0 = stream_next(&rs), x1 = stream_next(&rs);
         iso_dir(x0, x1, u);
     } else {
         uint64_t j = gid - nbg - nps;
         stream_init(&rs, X->seed, X->iteration, ORC_CLASS_DUST, X->freq_index, (uint32_t)j);
+        *cls_out = ORC_CLASS_DUST;
         int64_t c;
         if (s->dust_mode == 0) {
             c = X->leaves[j / X->per_leaf];
@@ -547,14 +552,13 @@ static double run_package(const sim_ctx *X, uint64_t gid, double *absorbed, int6
             /* each package of cell c carries L_c over the cell's expected
              * count, so the packages of c sum to L_c on average; in mode 2
              * L_c is the signed difference to the reference emission */
-            if (!(X->S > 0.0)) return 0.0;
+            if (!(X->S > 0.0)) return 0;
             c = weighted_cell(X, j);
-            if (c < 0) return 0.0;
+            if (c < 0) return 0;
             W0 = X->L[c] / expected_count(X, c);
         }
-        if (!(fabs(W0) > 0.0)) return 0.0;
+        if (!(fabs(W0) > 0.0)) return 0;
         origin = c;
-        if (self_abs && emitted) emitted[c] += W0;
         double size = ldexp(1.0, -cell_level(g, c));
         const double *lo = X->cell_lo + 3 * c;
         double x0 = stream_next(&rs), x1 = stream_next(&rs), x2 = stream_next(&rs);
@@ -562,10 +566,226 @@ static double run_package(const sim_ctx *X, uint64_t gid, double *absorbed, int6
         p[0] = lo[0] + x0 * size; p[1] = lo[1] + x1 * size; p[2] = lo[2] + x2 * size;
         iso_dir(x3, x4, u);
     }
+    *W0_out = W0;
+    *rs_out = rs;
+    *origin_out = origin;
+    return 1;
+}
+
+/* Emission of global package gid and its transport.  Returns the initial
+ * weight W0 (0 for a package that carries no energy). */
+static double run_package(const sim_ctx *X, uint64_t gid, double *absorbed, int64_t *hits, pk_tally *t,
+                          orc_segment *seg, int32_t max_seg, int32_t *nseg, double *self_abs, double *emitted)
+{
+    double p[3], u[3], W0;
+    stream_t rs;
+    int64_t origin;
+    uint32_t cls;
+    if (!emit_package(X, gid, p, u, &W0, &rs, &origin, &cls)) return 0.0;
+    if (origin >= 0 && self_abs && emitted) emitted[origin] += W0;
     double tau = -log(stream_next(&rs));
-    transport(g, X->f, p, u, W0, tau, &rs, X->cap, absorbed, hits, t, seg, max_seg, nseg, origin,
+    transport(X->g, X->f, p, u, W0, tau, &rs, X->cap, absorbed, hits, t, seg, max_seg, nseg, origin,
               self_abs && emitted ? self_abs : NULL);
     return W0;
+}
+
+static int32_t check_inputs(const orc_grid *g, const orc_freq *f, const orc_sources *s);
+
+/* ---- scattered light ---- */
+
+/* Optical depth (scattering only, or extinction) from p along direction o
+ * to the box boundary, leaf by leaf from a brute-force lookup. */
+static double ray_tau(const orc_grid *g, const orc_freq *f, const double p0[3], const double o[3], int ext)
+{
+    double p[3] = {p0[0], p0[1], p0[2]}, tau = 0.0;
+    const double s_cm = g->root_cell_cm;
+    const double k_unit = (ext ? f->sigma_abs + f->sigma_sca : f->sigma_sca) * s_cm;
+    for (int guard = 0; guard < 100000000; ++guard) {
+        double q[3] = {p[0] + ORC_EPS_PUSH * o[0], p[1] + ORC_EPS_PUSH * o[1], p[2] + ORC_EPS_PUSH * o[2]};
+        double lo[3], size;
+        int64_t c = orc_leaf(g, q, lo, &size);
+        if (c < 0) break;
+        double d = INFINITY;
+        for (int i = 0; i < 3; ++i) {
+            double di = INFINITY;
+            if (o[i] > 0.0) di = (lo[i] + size - p[i]) / o[i];
+            else if (o[i] < 0.0) di = (lo[i] - p[i]) / o[i];
+            if (di < 0.0) di = 0.0;
+            if (di < d) d = di;
+        }
+        tau += k_unit * word_f(g, c) * d;
+        p[0] += d * o[0]; p[1] += d * o[1]; p[2] += d * o[2];
+    }
+    return tau;
+}
+
+/* Henyey-Greenstein phase function normalised over the sphere. */
+static double hg_phase(double g, double mu)
+{
+    if (fabs(g) < 1e-4) return 1.0 / (4.0 * ORC_PI);
+    double d = 1.0 + g * g - 2.0 * g * mu;
+    return (1.0 - g * g) / (4.0 * ORC_PI * d * sqrt(d));
+}
+
+typedef struct {
+    int axis, neg, npx, npy;
+    double o[3], psz, scale;   /* scale: 1 / (A_pix w_nu) */
+} peel_geom;
+
+static int64_t peel_pixel(const peel_geom *G, const double p[3])
+{
+    int b = G->axis == 0 ? 1 : 0, c = G->axis == 2 ? 1 : 2;
+    int64_t i = (int64_t)floor(p[b] / G->psz), j = (int64_t)floor(p[c] / G->psz);
+    if (i < 0) i = 0;
+    if (i >= G->npx) i = G->npx - 1;
+    if (j < 0) j = 0;
+    if (j >= G->npy) j = G->npy - 1;
+    return j * G->npx + i;
+}
+
+/* One package of the scattered-light run: optional forced first
+ * scattering, then the per-cell loop of transport() without tallies,
+ * peeling off every scattering. */
+static void peel_package(const sim_ctx *X, uint64_t gid, const orc_scatter_params *sp, const peel_geom *G,
+                         double *image, pk_tally *t, double *W0_out)
+{
+    const orc_grid *g = X->g;
+    const orc_freq *f = X->f;
+    double p[3], u[3], W0;
+    stream_t rs;
+    int64_t origin;
+    uint32_t cls;
+    *W0_out = 0.0;
+    if (!emit_package(X, gid, p, u, &W0, &rs, &origin, &cls)) return;
+    *W0_out = W0;
+    if (sp->direct && cls >= ORC_CLASS_PS0)
+        image[peel_pixel(G, p)] += W0 / (4.0 * ORC_PI) * exp(-ray_tau(g, f, p, G->o, 1)) * G->scale;
+    double xi = stream_next(&rs);
+    double tau, W = W0;
+    if (sp->forced) {
+        double q = -expm1(-ray_tau(g, f, p, u, 0));   /* chance to scatter before leaving */
+        if (!(q > 0.0)) return;
+        W *= q;
+        tau = -log1p(-xi * q);
+    } else {
+        tau = -log(xi);
+    }
+    const double s_cm = g->root_cell_cm;
+    int nscat = 0;
+    for (;;) {
+        double q[3] = {p[0] + ORC_EPS_PUSH * u[0], p[1] + ORC_EPS_PUSH * u[1], p[2] + ORC_EPS_PUSH * u[2]};
+        double lo[3], size;
+        int64_t c = orc_leaf(g, q, lo, &size);
+        if (c < 0) { t->escaped += W; return; }
+        double dexit = INFINITY;
+        for (int i = 0; i < 3; ++i) {
+            double d = INFINITY;
+            if (u[i] > 0.0) d = (lo[i] + size - p[i]) / u[i];
+            else if (u[i] < 0.0) d = (lo[i] - p[i]) / u[i];
+            if (d < 0.0) d = 0.0;
+            if (d < dexit) dexit = d;
+        }
+        double n = word_f(g, c);
+        double ks = f->sigma_sca * n * s_cm, ka = f->sigma_abs * n * s_cm;
+        int scat = 0;
+        double d;
+        if (ks > 0.0 && ks * dexit >= tau) {
+            d = tau / ks;
+            if (d > dexit) d = dexit;
+            scat = 1;
+        } else {
+            d = dexit;
+            tau -= ks * dexit;
+        }
+        W *= exp(-ka * d);
+        p[0] += d * u[0]; p[1] += d * u[1]; p[2] += d * u[2];
+        t->steps++;
+        if (W < ORC_WFLOOR * W0) return;
+        if ((int64_t)t->steps >= X->cap) { t->runaway++; return; }
+        if (!scat) continue;
+        /* peel off towards the observer, then scatter */
+        double mu = u[0] * G->o[0] + u[1] * G->o[1] + u[2] * G->o[2];
+        image[peel_pixel(G, p)] += W * hg_phase(f->g, mu) * exp(-ray_tau(g, f, p, G->o, 1)) * G->scale;
+        t->scatterings++;
+        if (sp->max_scatter > 0 && ++nscat >= sp->max_scatter) return;
+        double xm = stream_next(&rs), xp = stream_next(&rs);
+        scatter_dir(f->g, xm, xp, u);
+        tau = -log(stream_next(&rs));
+    }
+}
+
+int32_t orc_scatter_map(const orc_grid *g, const orc_freq *f, const orc_sources *s, uint64_t seed,
+                        uint32_t iteration, uint32_t freq_index, const orc_scatter_params *sp,
+                        int64_t step_cap, int32_t nthreads, double *image, orc_stats *stats)
+{
+    int32_t rc = check_inputs(g, f, s);
+    if (rc) return rc;
+    if (!sp || !image || (s->T && s->n_dust) || (sp->axis & 3) > 2 || sp->max_scatter < 0) return -1;
+    if (!(f->w_nu > 0.0)) return -1;
+    sim_ctx X;
+    memset(&X, 0, sizeof X);
+    X.g = g; X.f = f; X.s = s; X.seed = seed; X.iteration = iteration; X.freq_index = freq_index;
+    X.cap = step_cap > 0 ? step_cap : 10000000;
+    rc = sim_setup(&X);
+    if (rc) { sim_free(&X); return rc; }
+    peel_geom G;
+    memset(&G, 0, sizeof G);
+    G.axis = sp->axis & 3;
+    G.neg = (sp->axis & 4) != 0;
+    G.o[G.axis] = G.neg ? -1.0 : 1.0;
+    int32_t N[3] = {g->nx, g->ny, g->nz};
+    int b = G.axis == 0 ? 1 : 0, c = G.axis == 2 ? 1 : 2;
+    int fine = 1 << (g->nlevels - 1);
+    G.npx = N[b] * fine;
+    G.npy = N[c] * fine;
+    G.psz = 1.0 / fine;
+    double pix_cm = g->root_cell_cm * G.psz;
+    G.scale = 1.0 / (pix_cm * pix_cm * f->w_nu);
+    int64_t npix = (int64_t)G.npx * G.npy;
+    orc_stats tot;
+    memset(&tot, 0, sizeof tot);
+    int failed = 0;
+    if (nthreads < 1) nthreads = 1;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nthreads)
+#endif
+    {
+        double *priv = (double *)calloc((size_t)npix, sizeof(double));
+        orc_stats loc;
+        memset(&loc, 0, sizeof loc);
+        if (!priv) failed = 1;
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 64)
+#endif
+        for (int64_t gid = 0; gid < (int64_t)X.n_total; ++gid) {
+            if (!priv) continue;
+            pk_tally t;
+            memset(&t, 0, sizeof t);
+            double W0;
+            peel_package(&X, (uint64_t)gid, sp, &G, priv, &t, &W0);
+            loc.packages++;
+            loc.cell_steps += t.steps;
+            loc.scatterings += t.scatterings;
+            loc.runaways += t.runaway;
+            loc.e_emitted += W0;
+            loc.e_escaped += t.escaped;
+        }
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+        {
+            if (priv)
+                for (int64_t k = 0; k < npix; ++k) image[k] += priv[k];
+            tot.packages += loc.packages; tot.cell_steps += loc.cell_steps;
+            tot.scatterings += loc.scatterings; tot.runaways += loc.runaways;
+            tot.e_emitted += loc.e_emitted; tot.e_escaped += loc.e_escaped;
+        }
+        free(priv);
+    }
+    sim_free(&X);
+    if (failed) return -3;
+    if (stats) *stats = tot;
+    return 0;
 }
 
 static int32_t check_inputs(const orc_grid *g, const orc_freq *f, const orc_sources *s)

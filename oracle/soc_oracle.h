@@ -144,6 +144,30 @@ int32_t orc_trace_from(const orc_grid *g, const orc_freq *f, const double p0[3],
                        double *absorbed, orc_segment *out, int32_t max_seg, int32_t *n_seg,
                        double *w_escaped);
 
+/* ---- scattered light (Sect. 2.1.1: separate runs with forced first
+ * scattering and peel-off) ---- */
+typedef struct {
+    int32_t axis;          /* observer along root axis axis & 3, on the positive side; bit 2: negative side */
+    int32_t forced;        /* 1: every package scatters at least once inside the box (weight times
+                              1 - exp(-tau_esc), free path from the truncated exponential) */
+    int32_t max_scatter;   /* 0: all scatterings; k: stop a package after its k-th (peeled) scattering */
+    int32_t direct;        /* 1: add the attenuated direct light of the point sources */
+} orc_scatter_params;
+
+/* Image of the light scattered towards a distant observer, by peel-off:
+ * at every scattering a package of weight W at p, moving along u, adds
+ * W Phi(u.o) exp(-tau_ext(p -> boundary along o)) / (A_pix w_nu) to the
+ * pixel under p, Phi the normalised Henyey-Greenstein function (1/4pi for
+ * |g| < 1e-4), o the direction towards the observer, tau_ext the
+ * extinction optical depth (absorption + scattering).  Sources: external
+ * field and point sources (no dust emission).  Pixels as orc_map: npy rows
+ * of npx, the lower and higher of the other two axes, finest-cell size.
+ * image (+=, npx*npy doubles) is in erg s^-1 cm^-2 Hz^-1 sr^-1.
+ * Returns 0 or a negative error. */
+int32_t orc_scatter_map(const orc_grid *g, const orc_freq *f, const orc_sources *s, uint64_t seed,
+                        uint32_t iteration, uint32_t freq_index, const orc_scatter_params *sp,
+                        int64_t step_cap, int32_t nthreads, double *image, orc_stats *stats);
+
 /* ---- temperature update (equilibrium grains) ---- */
 
 typedef struct { double mean_T, hot5_mean_T, mean_rel_change; uint64_t clamped; } orc_temp_stats;
