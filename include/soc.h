@@ -281,6 +281,42 @@ soc_status soc_temperature_stats(soc_ctx ctx, soc_grid grid, soc_temp_table tabl
 soc_status soc_map(soc_ctx ctx, soc_grid grid, const soc_freq *freq, const float *d_T, int32_t axis,
                    float *d_image, int32_t npx, int32_t npy);
 
+/* ---------------------------------------------------------------- scattered light */
+/* Image of scattered light (Sect. 2.1.1: scattered-light images come from
+ * separate runs with forced first scattering and peel-off).  The external
+ * field and point sources of `src` are simulated at one frequency (no dust
+ * emission, no tallies; src->d_T must be NULL or n_dust 0).  At every
+ * scattering a package of weight W at r, moving along u, adds
+ *   W Phi(u . o) exp(-tau_ext) / (A_pix w_nu)
+ * to the pixel under r: o the direction towards a distant observer on the
+ * positive side of root axis axis & 3 (bit 2: negative side), Phi the
+ * Henyey-Greenstein function normalised over the sphere (1/4pi for
+ * |g| < 1e-4), tau_ext the extinction optical depth from r to the box
+ * boundary along o, A_pix the pixel area.  forced != 0: each package first
+ * keeps the fraction 1 - exp(-tau_esc) of its weight that scatters before
+ * leaving the box (tau_esc the scattering optical depth ahead of it) and
+ * draws its first free path from the exponential truncated at tau_esc.
+ * direct != 0: point sources add their attenuated direct light W/(4pi)
+ * exp(-tau_ext) to their pixel.  max_scatter > 0 stops a package after its
+ * max_scatter-th scattering (0 = all orders).  d_image (device FP64, npy
+ * rows of npx pixels laid out as soc_map's, erg s^-1 cm^-2 Hz^-1 sr^-1) is
+ * accumulated (+=).  Random numbers as soc_simulate_frequency (forcing
+ * reuses the uniform of the first free path).  stats (host, optional)
+ * makes the call synchronise. */
+typedef struct {
+    int32_t axis;          /* 0..2, | 4 for an observer on the negative side */
+    int32_t forced;        /* forced first scattering */
+    int32_t max_scatter;   /* 0 = all orders */
+    int32_t direct;        /* add the direct light of point sources */
+} soc_scatter_params;
+typedef struct {
+    uint64_t packages, cell_steps, scatterings, ray_steps;   /* ray_steps: steps of the rays to the boundary */
+    double e_emitted, e_escaped;
+} soc_scatter_stats;
+soc_status soc_scatter_map(soc_ctx ctx, soc_grid grid, const soc_freq *freq, const soc_sources *src, uint64_t seed,
+                           uint32_t iteration, uint32_t freq_index, const soc_scatter_params *params,
+                           double *d_image, int32_t npx, int32_t npy, soc_scatter_stats *stats);
+
 /* ---------------------------------------------------------------- batches */
 /* Many independent Monte Carlo problems -- (cloud model, frequency) pairs
  * over regular grids of any size -- simulated by one persistent launch that

@@ -45,6 +45,8 @@ struct soc_ctx_s {
     int64_t cap_priv = 0;
     double *d_priv_self = nullptr;            // the same for the ALI self-absorption tally
     int64_t cap_priv_self = 0;
+    double *d_peel = nullptr;                 // totals of a scattered-light run
+    int64_t cap_peel = 0;
     double *d_L = nullptr, *d_incl = nullptr, *d_scan = nullptr;
     int64_t cap_L = 0, cap_incl = 0, cap_scan = 0;
     double *d_a = nullptr, *d_S = nullptr;   // selection weights / capped counts; sum of |L| (capped mode)
@@ -366,6 +368,7 @@ void soc_ctx_destroy(soc_ctx c)
     (void)hipFree(c->d_tmp_out);
     (void)hipFree(c->d_priv);
     (void)hipFree(c->d_priv_self);
+    (void)hipFree(c->d_peel);
     (void)hipFree(c->d_L);
     (void)hipFree(c->d_incl);
     (void)hipFree(c->d_a);
@@ -635,6 +638,63 @@ soc_status soc_read_stats(soc_ctx c, soc_sim_stats *out, int32_t reset)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     to_public(h, out);
     if (reset) HIPCHK(c, launch_fill_u64((unsigned long long *)(c->d_stats + 1), 0ull, (int64_t)(sizeof(DevStats) / 8), c->stream));
+    return SOC_OK;
+}
+
+soc_status soc_scatter_map(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *s, uint64_t seed,
+                           uint32_t iteration, uint32_t freq_index, const soc_scatter_params *sp, double *d_image,
+                           int32_t npx, int32_t npy, soc_scatter_stats *stats)
+{
+    if (!c) return SOC_EINVAL;
+    NOT_WHILE_CAPTURING(c);
+    if (!sp || !d_image) return fail(c, SOC_EINVAL, "NULL argument");
+    if (!s) return fail(c, SOC_EINVAL, "sources is NULL");
+    if (s->d_T && s->n_dust > 0) return fail(c, SOC_EINVAL, "scattered-light runs take no dust emission");
+    if (s->d_ali_self || s->d_ali_emitted) return fail(c, SOC_EINVAL, "scattered-light runs keep no ALI tallies");
+    if ((sp->axis & 3) > 2 || (sp->axis & ~7) != 0) return fail(c, SOC_EINVAL, "axis must be 0..2, optionally | 4");
+    if (sp->max_scatter < 0) return fail(c, SOC_EINVAL, "max_scatter must be >= 0");
+    if (!f || !(f->w_nu > 0.0)) return fail(c, SOC_EINVAL, "w_nu must be > 0 for an image");
+    HIPCHK(c, hipSetDevice(c->device));
+    McArgs A;
+    soc_status st = prepare(c, g, f, s, seed, iteration, freq_index, nullptr, A);
+    if (st) return st;
+    PeelArgs P;
+    std::memset(&P, 0, sizeof P);
+    P.axis = sp->axis & 3;
+    const bool neg = (sp->axis & 4) != 0;
+    P.ox = P.axis == 0 ? (neg ? -1.0f : 1.0f) : 0.0f;
+    P.oy = P.axis == 1 ? (neg ? -1.0f : 1.0f) : 0.0f;
+    P.oz = P.axis == 2 ? (neg ? -1.0f : 1.0f) : 0.0f;
+    const int32_t N[3] = {g->nx, g->ny, g->nz};
+    const int b = P.axis == 0 ? 1 : 0, cc = P.axis == 2 ? 1 : 2;
+    const int64_t fine = (int64_t)1 << (g->nlevels - 1);
+    if ((int64_t)npx != N[b] * fine || (int64_t)npy != N[cc] * fine)
+        return fail(c, SOC_EINVAL, "image must be %lld x %lld pixels", (long long)(N[b] * fine), (long long)(N[cc] * fine));
+    P.npx = npx;
+    P.npy = npy;
+    P.psz = 1.0 / (double)fine;
+    const double pix_cm = g->root_cell_cm * P.psz;
+    P.scale = 1.0 / (pix_cm * pix_cm * f->w_nu);
+    P.forced = sp->forced ? 1 : 0;
+    P.max_scatter = sp->max_scatter;
+    P.direct = sp->direct ? 1 : 0;
+    P.image = d_image;
+    if ((st = grow(c, &c->d_peel, c->cap_peel, 8))) return st;
+    HIPCHK(c, launch_fill_f64(c->d_peel, 0.0, 8, c->stream));
+    P.totals = c->d_peel;
+    const int blocks = (int)(c->num_cus * 8);
+    HIPCHK(c, launch_peel(A, P, blocks, c->stream));
+    if (stats) {
+        double h[6];
+        HIPCHK(c, hipMemcpyAsync(h, c->d_peel, sizeof h, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        stats->packages = (uint64_t)h[0];
+        stats->cell_steps = (uint64_t)h[1];
+        stats->scatterings = (uint64_t)h[2];
+        stats->ray_steps = (uint64_t)h[3];
+        stats->e_emitted = h[4];
+        stats->e_escaped = h[5];
+    }
     return SOC_OK;
 }
 

@@ -320,8 +320,23 @@ __device__ inline bool cross_octree(Pkg<R> &p, const AT &A, int a, bool fw)
 // energy (it is counted but not traced).  `cls`/`pid` receive the class
 // and the id within the class; W0 the package energy.
 template <typename R, bool Oct, typename AT>
+__device__ inline bool emit_base(const AT &A, uint64_t gid, Pkg<R> &p, Rng &rng, uint32_t &cls,
+                                 uint32_t &pid, double &W0);
+
+template <typename R, bool Oct, typename AT>
 __device__ inline bool emit(const AT &A, uint64_t gid, Pkg<R> &p, Rng &rng, uint32_t &cls,
                             uint32_t &pid, double &W0)
+{
+    if (!emit_base<R, Oct>(A, gid, p, rng, cls, pid, W0)) return false;
+    p.tau = -m_log(next_u<R>(rng, A));
+    return true;
+}
+
+// Emission without the free path: position, direction, weight; the next
+// uniform of the package's stream is its first free path.
+template <typename R, bool Oct, typename AT>
+__device__ inline bool emit_base(const AT &A, uint64_t gid, Pkg<R> &p, Rng &rng, uint32_t &cls,
+                                 uint32_t &pid, double &W0)
 {
     p.L = 0;
     const uint64_t nps_tot = (uint64_t)A.n_ps * A.n_ps_pk;
@@ -424,7 +439,6 @@ __device__ inline bool emit(const AT &A, uint64_t gid, Pkg<R> &p, Rng &rng, uint
     if (Oct && cls != kClassDust) descend(p, A);
     else p.n = (R)__uint_as_float(A.words[p.c]);
     set_inverse(p);
-    p.tau = -m_log(next_u<R>(rng, A));
     p.W = W0;
     p.Wfloor = 1e-12 * fabs(W0);
     p.steps = 0;

@@ -73,6 +73,18 @@ struct McArgs {
     int32_t refill_min, inner_steps, chunk, scatter_min;
 };
 
+// Scattered-light image (peel-off).  The observer is along +/- axis; the
+// image has npy rows of npx pixels of edge psz root units; scale is
+// 1 / (A_pix w_nu).  totals: packages, steps, scatterings, ray-march steps,
+// emitted and escaped energy (device doubles, +=).
+struct PeelArgs {
+    int32_t axis, npx, npy, forced, max_scatter, direct;
+    float ox, oy, oz;
+    double psz, scale;
+    double *image;
+    double *totals;
+};
+
 struct SegmentDev {
     int64_t cell;
     double ds;
@@ -100,6 +112,7 @@ __device__ inline double weighted_package_weight(double WN, double cap, double L
 // Regular-grid kernels when a.nlevels == 1, octree kernels otherwise.
 hipError_t launch_mc(const McArgs &a, int blocks, int threads, hipStream_t s);
 hipError_t launch_trace(const McArgs &a, const TraceArgs &t, int precision, hipStream_t s);
+hipError_t launch_peel(const McArgs &a, const PeelArgs &p, int blocks, hipStream_t s);
 
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);

@@ -62,6 +62,15 @@ class _SimStats(C.Structure):
                 ("e_escaped", C.c_double)]
 
 
+class _ScatterParams(C.Structure):
+    _fields_ = [("axis", C.c_int32), ("forced", C.c_int32), ("max_scatter", C.c_int32), ("direct", C.c_int32)]
+
+
+class _ScatterStats(C.Structure):
+    _fields_ = [("packages", C.c_uint64), ("cell_steps", C.c_uint64), ("scatterings", C.c_uint64),
+                ("ray_steps", C.c_uint64), ("e_emitted", C.c_double), ("e_escaped", C.c_double)]
+
+
 class _TempStats(C.Structure):
     _fields_ = [("mean_T", C.c_double), ("hot5_mean_T", C.c_double), ("mean_rel_change", C.c_double),
                 ("clamped", C.c_uint64)]
@@ -84,6 +93,9 @@ _lib.soc_simulate_frequency.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Freq)
                                         C.c_uint32, C.c_uint32, C.c_void_p, C.POINTER(_SimStats)]
 _lib.soc_update_temperature_ali.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                             C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(_TempStats)]
+_lib.soc_scatter_map.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Freq), C.POINTER(_Sources), C.c_uint64,
+                                 C.c_uint32, C.c_uint32, C.POINTER(_ScatterParams), C.c_void_p, C.c_int32, C.c_int32,
+                                 C.POINTER(_ScatterStats)]
 _lib.soc_reference_blend.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_void_p, C.c_void_p]
 _lib.soc_read_stats.argtypes = [C.c_void_p, C.POINTER(_SimStats), C.c_int32]
 _lib.soc_trace_packages.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Freq), C.POINTER(_Sources), C.c_uint64,
@@ -273,6 +285,33 @@ def trace_packages(ctx: Context, grid: Grid, freq, cls, ids, *, precision=0, max
                                       C.c_void_p(out.ctypes.data), int(max_seg),
                                       nseg.ctypes.data_as(C.POINTER(C.c_int32))))
     return out, nseg
+
+
+def scatter_image_shape(grid: Grid, axis: int):
+    """(npy, npx) of a map or scattered-light image along axis."""
+    a = axis & 3
+    N = [grid.nx, grid.ny, grid.nz]
+    fine = 1 << (grid.nlevels - 1)
+    b, c = (1 if a == 0 else 0), (1 if a == 2 else 2)
+    return N[c] * fine, N[b] * fine
+
+
+def scatter_map(ctx: Context, grid: Grid, freq, image: torch.Tensor, *, axis=2, forced=True, max_scatter=0,
+                direct=False, I_bg=0.0, ps_pos=None, ps_Lnu=None, n_bg=0, n_ps_pk=0, seed=1, iteration=0,
+                freq_index=0, stats=False):
+    """soc_scatter_map: image is a float64 CUDA tensor (npy, npx),
+    accumulated.  Returns the statistics dict if stats."""
+    sv = _SourceView(I_bg, ps_pos, ps_Lnu, None, n_bg, n_ps_pk, 0, 1)
+    f = _freq(freq)
+    npy, npx = image.shape
+    sp = _ScatterParams(int(axis), int(bool(forced)), int(max_scatter), int(bool(direct)))
+    st = _ScatterStats() if stats else None
+    ctx.check(_lib.soc_scatter_map(ctx.h, grid.h, C.byref(f), C.byref(sv.s), C.c_uint64(seed), C.c_uint32(iteration),
+                                   C.c_uint32(freq_index), C.byref(sp), _dev_ptr(image, torch.float64, "image"),
+                                   int(npx), int(npy), C.byref(st) if st is not None else None))
+    if st is None:
+        return None
+    return {k: getattr(st, k) for k, _ in _ScatterStats._fields_}
 
 
 def reference_blend(ctx: Context, x: torch.Tensor, ref: torch.Tensor, beta: float):

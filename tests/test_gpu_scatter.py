@@ -1,0 +1,174 @@
+"""GPU parity of the scattered-light image (forced first scattering and
+peel-off, Sect. 2.1.1) through the C ABI against the FP64 oracle:
+
+  * the direct light of a point source against its closed form;
+  * same-seed images on a lognormal cloud (regular grid and octree, all
+    orders of scattering, forced and free first scattering, both observer
+    sides);
+  * independent-seed z-scores per pixel;
+  * the first-order image against the quadrature of the single-scattering
+    integral;
+  * error paths.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import orc
+from paper_1812_06632_amd import workloads as W
+from tests.test_oracle_pins import _single_scatter_quadrature
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def soc():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1812_06632_amd import soc as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(soc):
+    c = soc.Context(0)
+    yield c
+    c.close()
+
+
+def _image(soc, grid_h, grid, axis):
+    return torch.zeros(soc.scatter_image_shape(grid, axis), dtype=torch.float64, device="cuda")
+
+
+@pytest.fixture(scope="module")
+def cloud():
+    """Lognormal 20^3 cloud, optical depth ~0.3 per cell at 0.55 um
+    (albedo 0.6, g 0.5 by the synthetic dust model), external field and
+    two point sources."""
+    P = W.lognormal_problem(n=20, K=16, sigma_ln=1.0, tau_v_mean=6.0, seed=9, L_star_lsun=1e5,
+                            packages_per_freq=40000)
+    lam = 2.99792458e14 / P.nu
+    k = int(np.argmin(np.abs(np.log(lam / 0.55))))
+    f = (float(P.nu[k]), float(P.w[k]), float(P.sigma_abs[k]), float(P.sigma_sca[k]), float(P.g[k]))
+    return P, k, f
+
+
+def test_scatter_map_direct_light(soc, ctx):
+    """Direct light of a point source in an absorbing box: L/(4 pi A_pix)
+    exp(-tau) in its pixel only (FP32 ray to the boundary)."""
+    grid = W.regular_grid(np.full((8, 7, 6), 1.0, np.float32), 2.0)
+    g = soc.grid_from_workload(ctx, grid)
+    f = (1e15, 0.5, 0.15, 0.0, 0.0)
+    for axis, tau in ((2, 0.3 * (8 - 4.2)), (2 | 4, 0.3 * 4.2), (0, 0.3 * (6 - 1.3))):
+        img = _image(soc, g, grid, axis)
+        st = soc.scatter_map(ctx, g, f, img, axis=axis, direct=True, ps_pos=[[1.3, 2.6, 4.2]], ps_Lnu=[3.0],
+                             n_ps_pk=999, stats=True)
+        a = img.cpu().numpy()
+        want = 3.0 / (4 * math.pi * 4.0) * math.exp(-tau)
+        assert np.count_nonzero(a) == 1 and a.max() == pytest.approx(want, rel=1e-5)
+        assert st["scatterings"] == 0 and st["packages"] == 999
+
+
+@pytest.mark.parametrize("kind,forced,axis", [("regular", True, 2), ("regular", False, 1 | 4), ("octree", True, 0)])
+def test_scatter_map_same_seed_matches_oracle(soc, ctx, cloud, kind, forced, axis):
+    """Same seed: the same packages scatter at the same places, so the GPU
+    image equals the oracle's pixel by pixel up to FP32 transport (median
+    relative difference 1e-4, 99th percentile 1e-2), with the same counts."""
+    P, k, f = cloud
+    grid = P.grid if kind == "regular" else W.refine_all_once(W.regular_grid(
+        P.grid.density().reshape(20, 20, 20)[:10, :10, :10].astype(np.float32), 2.0 * P.grid.root_cell_cm))
+    ps = P.ps_pos if kind == "regular" else np.array([[2.3, 5.1, 4.7]])
+    psL = P.ps_Lnu[:, k] if kind == "regular" else P.ps_Lnu[:1, k]
+    if kind == "octree":
+        d = grid.density()
+        assert d.size > 0
+    kw = dict(axis=axis, forced=forced, I_bg=float(P.I_bg[k]), ps_pos=ps, ps_Lnu=psL, n_bg=200_000,
+              n_ps_pk=100_000, seed=13, iteration=1, freq_index=k)
+    g = soc.grid_from_workload(ctx, grid)
+    img = _image(soc, g, grid, axis)
+    sg = soc.scatter_map(ctx, g, f, img, stats=True, **kw)
+    a = img.cpu().numpy()
+    o, so = orc.scatter_map(grid, f, nthreads=16, **kw)
+    assert a.shape == o.shape
+    assert sg["packages"] == so["packages"]
+    assert abs(sg["scatterings"] - so["scatterings"]) <= 1e-4 * so["scatterings"] + 2
+    assert sg["e_emitted"] == pytest.approx(so["e_emitted"], rel=1e-9)
+    sel = o > 1e-3 * o.max()
+    rel = np.abs(a[sel] - o[sel]) / o[sel]
+    print(f"\n{kind} forced={forced} axis={axis}: {sel.sum()} pixels, rel diff median {np.median(rel):.2e} "
+          f"p99 {np.quantile(rel, 0.99):.2e}, total {a.sum() / o.sum() - 1:.2e}")
+    assert sel.sum() > 50
+    assert np.median(rel) < 1e-4 and np.quantile(rel, 0.99) < 1e-2
+    assert a.sum() == pytest.approx(o.sum(), rel=1e-4)
+
+
+def test_scatter_map_statistical_parity(soc, ctx, cloud):
+    """Independent seeds, 16 batches per side: per-pixel z-scores of the
+    forced peel-off image follow Student's t, and the total agrees within 4
+    standard errors."""
+    from scipy import stats
+    P, k, f = cloud
+    g = soc.grid_from_workload(ctx, P.grid)
+    kw = dict(axis=2, forced=True, I_bg=float(P.I_bg[k]), ps_pos=P.ps_pos, ps_Lnu=P.ps_Lnu[:, k], n_bg=40_000,
+              n_ps_pk=20_000, iteration=1, freq_index=k)
+    B = 16
+    gb, ob = [], []
+    for b in range(B):
+        img = _image(soc, g, P.grid, 2)
+        soc.scatter_map(ctx, g, f, img, seed=100 + b, **kw)
+        gb.append(img.cpu().numpy())
+        ob.append(orc.scatter_map(P.grid, f, seed=900 + b, nthreads=8, **kw)[0])
+    gb, ob = np.array(gb), np.array(ob)
+    sp2 = 0.5 * (gb.var(0, ddof=1) + ob.var(0, ddof=1))
+    z = ((gb.mean(0) - ob.mean(0)) / np.sqrt(sp2 * 2.0 / B)).ravel()
+    z = z[np.isfinite(z)]
+    dof = 2 * B - 2
+    p = stats.kstest(z, stats.t(dof).cdf).pvalue
+    tg, to = gb.sum((1, 2)), ob.sum((1, 2))
+    zt = (tg.mean() - to.mean()) / math.sqrt(tg.var(ddof=1) / B + to.var(ddof=1) / B)
+    print(f"\nscattered light: {z.size} pixels, z mean {z.mean():.3f} std {z.std():.3f} KS p {p:.3g}, total z {zt:.2f}")
+    assert z.size > 300 and abs(z.mean()) < 0.1 and abs(z.std() - math.sqrt(dof / (dof - 2))) < 0.1 and p > 1e-3
+    assert abs(zt) < 4
+
+
+def test_scatter_map_single_scattering_quadrature(soc, ctx):
+    """First-order image (forced first scattering, stopped after it) of a
+    unit source at the centre of a uniform 8^3 cube against the quadrature
+    of the single-scattering integral, 60 pixels."""
+    grid = W.regular_grid(np.full((8, 8, 8), 1.0, np.float32), 1.0)
+    g = soc.grid_from_workload(ctx, grid)
+    ka, ks, gg = 0.1, 0.2, 0.6
+    f = (1e15, 1.0, ka, ks, gg)
+    runs = []
+    for s in range(8):
+        img = _image(soc, g, grid, 2)
+        soc.scatter_map(ctx, g, f, img, axis=2, forced=True, max_scatter=1, ps_pos=[[4.0, 4.0, 4.0]], ps_Lnu=[1.0],
+                        n_ps_pk=400_000, seed=s)
+        runs.append(img.cpu().numpy())
+    m = np.mean(runs, 0)
+    se = np.std(runs, 0, ddof=1) / math.sqrt(8)
+    z = []
+    for j in range(8):
+        for i in range(8):
+            if i in (3, 4) and j in (3, 4):
+                continue
+            z.append((m[j, i] - _single_scatter_quadrature(i, j, ka, ks, gg)) / se[j, i])
+    z = np.array(z)
+    assert abs(z.mean()) < 0.5 and z.std() < 1.6 and np.abs(z).max() < 6.0
+
+
+def test_scatter_map_error_paths(soc, ctx, cloud):
+    P, k, f = cloud
+    g = soc.grid_from_workload(ctx, P.grid)
+    bad = torch.zeros((3, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(soc.SocError, match="pixels"):
+        soc.scatter_map(ctx, g, f, bad, axis=2, n_bg=10, I_bg=1.0)
+    img = _image(soc, g, P.grid, 2)
+    with pytest.raises(soc.SocError, match="axis"):
+        soc.scatter_map(ctx, g, f, img, axis=3, n_bg=10, I_bg=1.0)
+    with pytest.raises(soc.SocError, match="w_nu"):
+        soc.scatter_map(ctx, g, (f[0], 0.0, f[2], f[3], f[4]), img, axis=2, n_bg=10, I_bg=1.0)
+    assert not img.any()
