@@ -474,6 +474,68 @@ def ali_gain(args, soc, torch, W):
     ctx.close()
 
 
+def scatter_bench(args, soc, torch, W):
+    """Scattered-light image (forced first scattering, peel-off of every
+    scattering, Sect. 2.1.1) of the benchmark cloud at 0.55 um, seen along
+    +z: external field and the two point sources, --packages packages.  The
+    work is dominated by the rays from every scattering to the boundary; a
+    ray step is one dependent 4-byte density gather, so the bound is the
+    measured dependent-gather rate.  CPU baseline: the oracle on a sample."""
+    P = W.lognormal_problem(n=args.n, K=args.freqs, packages_per_freq=args.packages)
+    lam = 2.99792458e14 / P.nu
+    k = int(np.argmin(np.abs(np.log(lam / 0.55))))
+    f = (float(P.nu[k]), float(P.w[k]), float(P.sigma_abs[k]), float(P.sigma_sca[k]), float(P.g[k]))
+    ctx = soc.Context(0)
+    g = soc.grid_from_workload(ctx, P.grid)
+    kw = dict(axis=2, forced=True, I_bg=float(P.I_bg[k]), ps_pos=P.ps_pos, ps_Lnu=P.ps_Lnu[:, k], n_bg=P.n_bg,
+              n_ps_pk=P.n_ps_pk, iteration=1, freq_index=k)
+    img = torch.zeros(soc.scatter_image_shape(g, 2), dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        soc.scatter_map(ctx, g, f, img, seed=99, stats=True, **kw)
+    tot = {"packages": 0, "cell_steps": 0, "scatterings": 0, "ray_steps": 0}
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for i in range(args.steps):
+        st = soc.scatter_map(ctx, g, f, img, seed=i + 1, stats=True, **kw)
+        for key in tot:
+            tot[key] += st[key]
+    torch.cuda.synchronize()
+    el = time.time() - t0
+    w = torch.randint(0, 2**31 - 1, (P.grid.ncells,), dtype=torch.int32, device="cuda")
+    out = torch.zeros(4, dtype=torch.int32, device="cuda")
+    soc.ubench(ctx, 1, w, out, P.grid.ncells, 64, 0, 16384, 256)
+    gather = 16384 * 256 * 64 / (min(soc.ubench(ctx, 1, w, out, P.grid.ncells, 64, 0, 16384, 256)
+                                     for _ in range(3)) * 1e-3)
+    steps_per_s = (tot["cell_steps"] + tot["ray_steps"]) / el
+    log(f"scattered light: {args.steps} images in {el:.3f}s, {tot['packages'] / el:.3e} packages/s, "
+        f"{tot['scatterings'] / el:.3e} peel-offs/s, {steps_per_s:.3e} steps/s (ray steps "
+        f"{tot['ray_steps'] / max(tot['cell_steps'] + tot['ray_steps'], 1):.2f} of all), gather ceiling {gather:.3e}/s")
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import orc
+        n_s = 20 * args.packages   # about 10 s on 16 host threads
+        kw_s = dict(kw)
+        kw_s["n_bg"], kw_s["n_ps_pk"] = n_s // 2, n_s // 4
+        nthreads = min(os.cpu_count() or 1, 16)
+        t1 = time.time()
+        _, so = orc.scatter_map(P.grid, f, seed=5, nthreads=nthreads, **kw_s)
+        el_c = time.time() - t1
+        cpu = {"value": so["packages"] / el_c, "unit": "packages/s", "cores": nthreads, "kind": "oracle",
+               "sample": f"{so['packages']} packages of the same image (FP64 C oracle, OpenMP)"}
+        log(f"oracle: {so['packages']} packages in {el_c:.2f}s")
+    line = {"kind": "scatter_map", "workload": f"lognormal {args.n}^3, 0.55 um, external field + 2 point sources, "
+                                               f"{args.packages} packages, forced first scattering, peel-off towards +z",
+            "steps": args.steps, "ms_per_image": el / args.steps * 1e3, "packages_per_s": tot["packages"] / el,
+            "peel_offs_per_s": tot["scatterings"] / el, "steps_per_s": steps_per_s,
+            "ray_step_fraction": tot["ray_steps"] / max(tot["cell_steps"] + tot["ray_steps"], 1),
+            "roofline": {"bound": "dependent 4-byte gathers (measured)", "achieved": steps_per_s, "peak": gather,
+                         "unit": "steps/s", "frac": steps_per_s / gather,
+                         "hbm_GBs_algorithmic": 4.0 * steps_per_s / 1e9},
+            "cpu_baseline": cpu}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -506,6 +568,7 @@ def main():
     ap.add_argument("--ref-iters", type=int, default=10)
     ap.add_argument("--ref-factor", type=float, default=16.0)
     ap.add_argument("--ali", action="store_true", help="plain versus diagonal-ALI iteration at three resolutions")
+    ap.add_argument("--scatter", action="store_true", help="scattered-light image by forced scattering and peel-off")
     ap.add_argument("--ali-iters", type=int, default=20)
     ap.add_argument("--ali-ref-iters", type=int, default=60)
     ap.add_argument("--ali-tau", type=float, default=500.0)
@@ -539,6 +602,9 @@ def main():
         return
     if args.ali:
         ali_gain(args, soc, torch, W)
+        return
+    if args.scatter:
+        scatter_bench(args, soc, torch, W)
         return
 
     from paper_1812_06632_amd.driver import PlainSolver, converged
