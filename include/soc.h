@@ -317,6 +317,37 @@ soc_status soc_scatter_map(soc_ctx ctx, soc_grid grid, const soc_freq *freq, con
                            uint32_t iteration, uint32_t freq_index, const soc_scatter_params *params,
                            double *d_image, int32_t npx, int32_t npy, soc_scatter_stats *stats);
 
+/* ---------------------------------------------------------------- stochastic heating */
+/* Stochastically heated grains (Sect. 2.1.1, Appendix B, "thermal continuous"
+ * approximation).  A grain model: K frequencies nu (Hz, increasing) with
+ * quadrature weights w (Hz), S grain sizes with abundances (grains per H),
+ * absorption cross sections sigma[S][K] (cm^2 per grain) and enthalpy grids
+ * U[S][N] (erg per grain, increasing) at temperatures T[S][N] (K); all host
+ * arrays, copied.  K <= 256, 2 <= N <= 256.  The model is tied to ctx. */
+typedef struct soc_shg_model_s *soc_shg_model;
+soc_status soc_shg_model_create(soc_ctx ctx, int32_t K, const double *nu, const double *w, int32_t S,
+                                const double *abundance, const double *sigma, int32_t N, const double *U,
+                                const double *T, soc_shg_model *out);
+void soc_shg_model_destroy(soc_shg_model model);   /* valid before or after its context is destroyed */
+
+/* Temperature distributions and emission of every leaf.  d_absorbed
+ * (device FP64 [K][ncells]): the energy absorbed per second in each band
+ * (erg/s per cell; the tallies of one soc_simulate_frequency call per
+ * band, with the model's total cross section).  Size s takes the share
+ * abundance_s sigma_sk / sum_s abundance_s sigma_sk of band k, divided among
+ * abundance_s n_H V grains, as r_k = photons per grain per second.  A photon
+ * raises a grain in bin i to U_i + h nu_k, split between the two bins
+ * around it in proportion to the distance (a target above the top bin goes
+ * to the top bin); a grain in bin i > 0 cools into bin i-1 at the rate
+ * L(T_i)/(U_i - U_{i-1}), L(T) = 4 pi sum_k sigma_sk B_nu_k(T) w_k.  The
+ * stationary populations P (sum 1) follow by forward substitution in FP64.
+ * d_emission (device FP64 [K][ncells], overwritten): sum over sizes of the
+ * grain count times 4 pi sigma_sk sum_i P_i B_nu_k(T_i), erg s^-1 Hz^-1 per
+ * cell (0 in empty and refined cells).  d_P (device FP64
+ * [ncells][S][N], optional): the populations.  Enqueued on ctx's stream. */
+soc_status soc_shg_solve(soc_ctx ctx, soc_grid grid, soc_shg_model model, const double *d_absorbed,
+                         double *d_emission, double *d_P);
+
 /* ---------------------------------------------------------------- batches */
 /* Many independent Monte Carlo problems -- (cloud model, frequency) pairs
  * over regular grids of any size -- simulated by one persistent launch that

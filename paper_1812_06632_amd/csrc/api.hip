@@ -101,6 +101,14 @@ struct soc_temp_table_s {
     double *d_lnG = nullptr;
 };
 
+struct soc_shg_model_s {
+    soc_ctx ctx = nullptr;   // identity check only
+    int device = 0;
+    int32_t S = 0, K = 0, N = 0;
+    double *d_buf = nullptr;   // every table in one allocation
+    soc::ShgModelDev dev{};
+};
+
 namespace {
 
 soc_status fail(soc_ctx c, soc_status s, const char *fmt, ...)
@@ -695,6 +703,116 @@ soc_status soc_scatter_map(soc_ctx c, soc_grid g, const soc_freq *f, const soc_s
         stats->e_emitted = h[4];
         stats->e_escaped = h[5];
     }
+    return SOC_OK;
+}
+
+soc_status soc_shg_model_create(soc_ctx c, int32_t K, const double *nu, const double *w, int32_t S,
+                                const double *abundance, const double *sigma, int32_t N, const double *U,
+                                const double *T, soc_shg_model *out)
+{
+    if (!c) return SOC_EINVAL;
+    if (!out) return fail(c, SOC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (K < 1 || K > kShgMaxK) return fail(c, SOC_EINVAL, "K must be in [1, %d]", kShgMaxK);
+    if (N < 2 || N > kShgMaxN) return fail(c, SOC_EINVAL, "the enthalpy grid needs 2..%d bins", kShgMaxN);
+    if (S < 1 || S > 4096) return fail(c, SOC_EINVAL, "S must be in [1, 4096]");
+    if (!nu || !w || !abundance || !sigma || !U || !T) return fail(c, SOC_EINVAL, "NULL table");
+    for (int k = 0; k < K; ++k) {
+        if (!(nu[k] > 0.0) || !std::isfinite(nu[k]) || !finite_nonneg(w[k]))
+            return fail(c, SOC_EINVAL, "nu must be > 0 and w >= 0");
+        if (k > 0 && !(nu[k] > nu[k - 1])) return fail(c, SOC_EINVAL, "frequencies must increase");
+    }
+    for (int i = 0; i < S; ++i)
+        if (!finite_nonneg(abundance[i])) return fail(c, SOC_EINVAL, "abundances must be finite and >= 0");
+    for (int64_t i = 0; i < (int64_t)S * K; ++i)
+        if (!finite_nonneg(sigma[i])) return fail(c, SOC_EINVAL, "cross sections must be finite and >= 0");
+    for (int s2 = 0; s2 < S; ++s2)
+        for (int i = 0; i < N; ++i) {
+            const double u = U[(int64_t)s2 * N + i], t = T[(int64_t)s2 * N + i];
+            if (!std::isfinite(u) || !(t > 0.0) || !std::isfinite(t)) return fail(c, SOC_EINVAL, "bad enthalpy grid");
+            if (i > 0 && !(u > U[(int64_t)s2 * N + i - 1])) return fail(c, SOC_EINVAL, "enthalpies must increase");
+        }
+    HIPCHK(c, hipSetDevice(c->device));
+    soc_shg_model m = new (std::nothrow) soc_shg_model_s;
+    if (!m) return fail(c, SOC_ENOMEM, "out of host memory");
+    m->ctx = c;
+    m->device = c->device;
+    m->S = S; m->K = K; m->N = N;
+    const int64_t sk = (int64_t)S * K, sn = (int64_t)S * N;
+    // layout: nu hnu inv_hnu w | abundance | sigma | U | T | share | emit | cool
+    const int64_t total = 4 * (int64_t)K + S + sk + 2 * sn + sk + sn * K + sn;
+    if (hipMalloc((void **)&m->d_buf, sizeof(double) * (size_t)total) != hipSuccess) {
+        delete m;
+        return fail(c, SOC_ENOMEM, "device allocation of the grain model failed");
+    }
+    std::vector<double> h(4 * (size_t)K + S + sk + 2 * sn);
+    const double hP = 6.62607015e-27;
+    for (int k = 0; k < K; ++k) {
+        h[k] = nu[k];
+        h[K + k] = hP * nu[k];
+        h[2 * K + k] = 1.0 / (hP * nu[k]);
+        h[3 * K + k] = w[k];
+    }
+    std::memcpy(&h[4 * K], abundance, sizeof(double) * S);
+    std::memcpy(&h[4 * K + S], sigma, sizeof(double) * sk);
+    std::memcpy(&h[4 * K + S + sk], U, sizeof(double) * sn);
+    std::memcpy(&h[4 * K + S + sk + sn], T, sizeof(double) * sn);
+    double *d = m->d_buf;
+    hipError_t e = hipMemcpyAsync(d, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, c->stream);
+    soc::ShgModelDev &v = m->dev;
+    v.S = S; v.K = K; v.N = N;
+    v.nu = d; v.hnu = d + K; v.inv_hnu = d + 2 * K;
+    const double *dw = d + 3 * K;
+    v.abundance = d + 4 * K;
+    v.sigma = d + 4 * K + S;
+    v.U = d + 4 * K + S + sk;
+    v.T = d + 4 * K + S + sk + sn;
+    v.share = d + 4 * K + S + sk + 2 * sn;
+    v.emit = v.share + sk;
+    v.cool = v.emit + sn * K;
+    if (e == hipSuccess) e = launch_shg_prep(v, dw, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(m->d_buf);
+        delete m;
+        return fail(c, SOC_EHIP, "grain model setup: %s", hipGetErrorString(e));
+    }
+    *out = m;
+    return SOC_OK;
+}
+
+void soc_shg_model_destroy(soc_shg_model m)
+{
+    if (!m) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(m->device);
+    (void)hipFree(m->d_buf);
+    (void)hipSetDevice(cur);
+    delete m;
+}
+
+soc_status soc_shg_solve(soc_ctx c, soc_grid g, soc_shg_model m, const double *d_absorbed, double *d_emission,
+                         double *d_P)
+{
+    if (!c) return SOC_EINVAL;
+    if (!g || !m || !d_absorbed || !d_emission) return fail(c, SOC_EINVAL, "NULL argument");
+    if (g->ctx != c || m->ctx != c) return fail(c, SOC_EINVAL, "grid/model belong to another context");
+    HIPCHK(c, hipSetDevice(c->device));
+    ShgArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.model = m->dev;
+    a.words = g->d_words;
+    a.ncells = g->ncells;
+    for (int i = 0; i <= kMaxLevels; ++i) a.level_offset[i] = i <= g->nlevels ? g->level_offset[i] : g->ncells;
+    a.nlevels = g->nlevels;
+    a.root_cell_cm = g->root_cell_cm;
+    a.absorbed = d_absorbed;
+    a.emission = d_emission;
+    a.P = d_P;
+    int64_t blocks = (g->ncells + 3) / 4;
+    if (blocks > 65536) blocks = 65536;
+    HIPCHK(c, launch_shg(a, (int)(blocks < 1 ? 1 : blocks), c->stream));
     return SOC_OK;
 }
 

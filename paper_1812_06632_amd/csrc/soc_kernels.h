@@ -85,6 +85,34 @@ struct PeelArgs {
     double *totals;
 };
 
+// Stochastically heated grains: model tables on the device (S sizes, K
+// frequencies, N enthalpy bins).
+constexpr int kShgMaxK = 256;
+constexpr int kShgMaxN = 256;
+struct ShgModelDev {
+    int32_t S, K, N;
+    const double *nu, *hnu, *inv_hnu;   // [K]
+    const double *abundance;            // [S] grains per H
+    const double *sigma;                // [S][K] cm^2 per grain
+    const double *U, *T;                // [S][N]
+    double *share;                      // [S][K] share of each size in the absorption of band k
+    double *emit;                       // [S][N][K] 4 pi sigma B_nu(T_i)
+    double *cool;                       // [S][N] cooling rate from bin i to i-1
+};
+struct ShgArgs {
+    ShgModelDev model;
+    const uint32_t *words;
+    int64_t ncells;
+    int64_t level_offset[kMaxLevels + 1];
+    int32_t nlevels;
+    double root_cell_cm;
+    const double *absorbed;             // [K][ncells]
+    double *emission;                   // [K][ncells]
+    double *P;                          // [ncells][S][N] or NULL
+};
+hipError_t launch_shg_prep(const ShgModelDev &m, const double *w, hipStream_t s);
+hipError_t launch_shg(const ShgArgs &a, int blocks, hipStream_t s);
+
 struct SegmentDev {
     int64_t cell;
     double ds;

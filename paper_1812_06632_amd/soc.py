@@ -96,6 +96,12 @@ _lib.soc_update_temperature_ali.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, 
 _lib.soc_scatter_map.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Freq), C.POINTER(_Sources), C.c_uint64,
                                  C.c_uint32, C.c_uint32, C.POINTER(_ScatterParams), C.c_void_p, C.c_int32, C.c_int32,
                                  C.POINTER(_ScatterStats)]
+_lib.soc_shg_model_create.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                      C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32,
+                                      C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_void_p)]
+_lib.soc_shg_model_destroy.argtypes = [C.c_void_p]
+_lib.soc_shg_model_destroy.restype = None
+_lib.soc_shg_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.soc_reference_blend.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_void_p, C.c_void_p]
 _lib.soc_read_stats.argtypes = [C.c_void_p, C.POINTER(_SimStats), C.c_int32]
 _lib.soc_trace_packages.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Freq), C.POINTER(_Sources), C.c_uint64,
@@ -312,6 +318,42 @@ def scatter_map(ctx: Context, grid: Grid, freq, image: torch.Tensor, *, axis=2, 
     if st is None:
         return None
     return {k: getattr(st, k) for k, _ in _ScatterStats._fields_}
+
+
+class ShgModel:
+    """soc_shg_model: a grain model (workloads.GrainModel) on the device."""
+
+    def __init__(self, ctx: Context, G):
+        self.ctx = ctx
+        self.S, self.K, self.N = len(G.a_cm), len(G.nu), G.U.shape[1]
+        arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in (G.nu, G.w, G.abundance, G.sigma, G.U, G.T)]
+        P = C.POINTER(C.c_double)
+        h = C.c_void_p()
+        ctx.check(_lib.soc_shg_model_create(ctx.h, self.K, arrs[0].ctypes.data_as(P), arrs[1].ctypes.data_as(P),
+                                            self.S, arrs[2].ctypes.data_as(P), arrs[3].ctypes.data_as(P), self.N,
+                                            arrs[4].ctypes.data_as(P), arrs[5].ctypes.data_as(P), C.byref(h)))
+        self.h = h
+        ctx._children.add(self)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.soc_shg_model_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def shg_solve(ctx: Context, grid: Grid, model: ShgModel, absorbed: torch.Tensor, emission: torch.Tensor,
+              P: torch.Tensor | None = None):
+    """soc_shg_solve: absorbed and emission float64 CUDA tensors [K, ncells];
+    P optional float64 [ncells, S, N]."""
+    ctx.check(_lib.soc_shg_solve(ctx.h, grid.h, model.h, _dev_ptr(absorbed, torch.float64, "absorbed"),
+                                 _dev_ptr(emission, torch.float64, "emission"),
+                                 _dev_ptr(P, torch.float64, "P") if P is not None else None))
 
 
 def reference_blend(ctx: Context, x: torch.Tensor, ref: torch.Tensor, beta: float):

@@ -240,6 +240,69 @@ def blackbody_Lnu(nu: np.ndarray, L_total: float, T_star: float) -> np.ndarray:
     return L_total * math.pi * _bb(nu, T_star) / (_SIGMA_SB * T_star ** 4)
 
 
+# ---------------------------------------------------------------- grains
+@dataclasses.dataclass
+class GrainModel:
+    """A synthetic size distribution of stochastically heated grains (the
+    DustEM silicates of the paper's Appendix B are not available): per size
+    bin s the grains per H, the absorption cross section per grain at the K
+    frequencies, and an enthalpy grid of nE bins (enthalpy U and
+    temperature T of each bin)."""
+    nu: np.ndarray            # [K] Hz
+    w: np.ndarray             # [K] quadrature weights, Hz
+    a_cm: np.ndarray          # [S] grain radius
+    abundance: np.ndarray     # [S] grains per H
+    sigma: np.ndarray         # [S, K] cm^2 per grain
+    U: np.ndarray             # [S, nE] erg per grain
+    T: np.ndarray             # [S, nE] K
+
+    @property
+    def sigma_per_H(self) -> np.ndarray:
+        """[K] absorption cross section per H of the whole distribution."""
+        return (self.abundance[:, None] * self.sigma).sum(axis=0)
+
+
+def grain_model(nu: np.ndarray, w: np.ndarray, n_size: int = 8, n_enthalpy: int = 128,
+                a_min_um: float = 0.001, a_max_um: float = 0.3, T_min: float = 4.0) -> GrainModel:
+    """Grains of radii log-spaced in [a_min, a_max] with an a^-3.5 size
+    distribution scaled so that the whole distribution absorbs
+    sigma_abs(0.55 um) of `dust_model` per H; Q_abs = x/(1+x) with x = 2 pi a
+    q(lambda)/lambda, q = (lambda/1 um)^-1 (Q ~ a lambda^-2 for small grains,
+    ~1 for large); density 3 g cm^-3, 20 amu per atom, heat capacity
+    3 N k f(T/500 K) with f(y) = c y^3/(1 + c y^3), c = 4 pi^4/5 (the Debye
+    T^3 law at low temperature, 3 N k at high); enthalpy bins at
+    temperatures log-spaced from T_min to T_max(a), which falls from
+    2500 K for the smallest to 150 K for the largest grains (log-linear in
+    a), as in the paper's tests."""
+    nu = np.asarray(nu, dtype=np.float64)
+    lam_cm = _C / nu
+    a = np.exp(np.linspace(math.log(a_min_um), math.log(a_max_um), n_size)) * 1e-4
+    dlna = (math.log(a_max_um) - math.log(a_min_um)) / max(n_size - 1, 1)
+    x = 2.0 * math.pi * a[:, None] * (lam_cm[None, :] / 1e-4) ** -1.0 / lam_cm[None, :]
+    sigma = math.pi * a[:, None] ** 2 * x / (1.0 + x)
+    ab = a ** -3.5 * a * dlna        # dn ~ a^-3.5 da
+    nu_v = _C / (LAMBDA_V_UM * 1e-4)
+    sv = np.array([math.pi * aa ** 2 * (lambda xx: xx / (1 + xx))(2 * math.pi * aa * (LAMBDA_V_UM) ** -1.0 /
+                                                                      (LAMBDA_V_UM * 1e-4)) for aa in a])
+    sabs_v = dust_model(np.array([nu_v]))[0][0]
+    ab *= sabs_v / float((ab * sv).sum())
+    rho, m_atom, theta = 3.0, 20.0 * 1.66053906660e-24, 500.0
+    c = 4.0 * math.pi ** 4 / 5.0
+    frac = (np.log(a) - math.log(a[0])) / max(math.log(a[-1]) - math.log(a[0]), 1e-30)
+    T_top = np.exp(math.log(2500.0) + frac * (math.log(150.0) - math.log(2500.0)))
+    U = np.empty((n_size, n_enthalpy))
+    T = np.empty((n_size, n_enthalpy))
+    for s in range(n_size):
+        n_atoms = 4.0 / 3.0 * math.pi * a[s] ** 3 * rho / m_atom
+        Tf = np.exp(np.linspace(math.log(1e-3), math.log(T_top[s] * 1.01), 40000))
+        y = Tf / theta
+        C = 3.0 * n_atoms * _K * c * y ** 3 / (1.0 + c * y ** 3)
+        Uf = np.concatenate([[0.0], np.cumsum(0.5 * (C[1:] + C[:-1]) * np.diff(Tf))])
+        T[s] = np.exp(np.linspace(math.log(T_min), math.log(T_top[s]), n_enthalpy))
+        U[s] = np.interp(np.log(T[s]), np.log(Tf), Uf)
+    return GrainModel(nu=nu, w=np.asarray(w, dtype=np.float64), a_cm=a, abundance=ab, sigma=sigma, U=U, T=T)
+
+
 # ---------------------------------------------------------------- configs
 @dataclasses.dataclass
 class Problem:

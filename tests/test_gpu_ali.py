@@ -78,7 +78,7 @@ def test_ali_tallies_match_oracle(soc, ctx, kind):
     a, s_, e = A.cpu().numpy(), S.cpu().numpy(), E.cpu().numpy()
     np.testing.assert_allclose(a + s_, A0.cpu().numpy(), rtol=1e-10, atol=1e-12 * A0.max().item())
     assert abs(a.sum() + s_.sum() + st["e_escaped"] - st["e_emitted"]) < 1e-6 * st["e_emitted"]
-    assert e.sum() == pytest.approx(st["e_emitted"], rel=1e-10)
+    assert e.sum() == pytest.approx(st["e_emitted"], rel=1e-10, abs=0)
     assert np.all(s_ <= e * (1 + 1e-9))
     Ao, So, Eo = np.zeros(nc), np.zeros(nc), np.zeros(nc)
     hits = np.zeros(nc, np.int64)
@@ -158,7 +158,7 @@ def test_ali_temperature_solve_matches_oracle(soc, ctx):
     assert np.max(np.abs(tg - To)) < 0.05
     ok = (rho > 0) & (np.arange(nc) != 5) & (T_true > P.T_floor)
     assert np.max(np.abs(To[ok] - T_true[ok]) / T_true[ok]) < 1e-6
-    assert sg["mean_T"] == pytest.approx(so["mean_T"], rel=1e-5)
+    assert sg["mean_T"] == pytest.approx(so["mean_T"], rel=1e-5, abs=0)
 
 
 def test_ali_grey_cell_closed_form_and_iteration(soc, ctx):
@@ -181,7 +181,7 @@ def test_ali_grey_cell_closed_form_and_iteration(soc, ctx):
         S = PlainSolver(ctx, P, seed=3, ali=ali)
         hist, _ = S.run(max_iter=3, until_stop=False)
         Ts[ali] = [h[2]["mean_T"] for h in hist]
-    assert Ts[True][1] == pytest.approx(30.0, rel=3e-3) and Ts[True][2] == pytest.approx(30.0, rel=3e-3)
+    assert Ts[True][1] == pytest.approx(30.0, rel=3e-3, abs=0) and Ts[True][2] == pytest.approx(30.0, rel=3e-3, abs=0)
     assert Ts[False][1] < 0.92 * 30.0
     # a thick cloud: library ALI iteration against the oracle's
     Q = W.lognormal_problem(n=8, K=16, sigma_ln=1.0, tau_v_mean=3000.0, seed=3, L_star_lsun=1e6,
@@ -191,8 +191,8 @@ def test_ali_grey_cell_closed_form_and_iteration(soc, ctx):
     hist, _ = S.run(max_iter=6, until_stop=False)
     ref = orc.iterate(Q, seed=7, iterations=6, ali=True)
     for (it, _, sg), (_, so) in zip(hist, ref):
-        assert sg["mean_T"] == pytest.approx(so["mean_T"], rel=2e-3)
-        assert sg["hot5_mean_T"] == pytest.approx(so["hot5_mean_T"], rel=2e-3)
+        assert sg["mean_T"] == pytest.approx(so["mean_T"], rel=2e-3, abs=0)
+        assert sg["hot5_mean_T"] == pytest.approx(so["hot5_mean_T"], rel=2e-3, abs=0)
 
 
 def test_ali_error_paths(soc, ctx):

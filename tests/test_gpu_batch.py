@@ -71,7 +71,7 @@ def test_batch_equals_single_calls(soc):
         st = b.run(iteration=3, stats=True)
         for key in ("packages", "cell_steps", "scatterings", "runaways"):
             assert st[key] == tot[key], (tile, key)
-        assert st["e_emitted"] == pytest.approx(tot["e_emitted"], rel=1e-12)
+        assert st["e_emitted"] == pytest.approx(tot["e_emitted"], rel=1e-12, abs=0)
         for m in range(len(grids)):
             a, r = A[m].cpu().numpy(), ref[m].cpu().numpy()
             np.testing.assert_allclose(a, r, rtol=1e-11, atol=1e-12 * r.max())
@@ -99,7 +99,7 @@ def test_batch_matches_oracle_counts(soc):
         steps += so["cell_steps"]
         absorbed += Ao.sum()
     assert abs(st["cell_steps"] - steps) <= 1e-4 * steps
-    assert sum(a.sum().item() for a in A) == pytest.approx(absorbed, rel=1e-4)
+    assert sum(a.sum().item() for a in A) == pytest.approx(absorbed, rel=1e-4, abs=0)
     assert abs((st["e_absorbed"] + st["e_escaped"]) / st["e_emitted"] - 1) < 1e-6
     ctx.close()
 

@@ -166,10 +166,10 @@ def test_same_seed_tallies_and_conservation(soc, ctx, sphere):
     assert sg["packages"] == so["packages"] == n
     assert abs(sg["cell_steps"] - so["cell_steps"]) <= 1e-4 * so["cell_steps"]
     assert abs(sg["scatterings"] - so["scatterings"]) <= 1e-4 * so["scatterings"]
-    assert sg["e_emitted"] == pytest.approx(so["e_emitted"], rel=1e-10)   # FP64 atomic summation order
+    assert sg["e_emitted"] == pytest.approx(so["e_emitted"], rel=1e-10, abs=0)   # FP64 atomic summation order
     cons = (Ag.sum() + sg["e_escaped"]) / sg["e_emitted"] - 1.0
     assert abs(cons) < 1e-6
-    assert sg["e_absorbed"] == pytest.approx(Ag.sum(), rel=1e-9)
+    assert sg["e_absorbed"] == pytest.approx(Ag.sum(), rel=1e-9, abs=0)
     sel = hits > 1000
     assert sel.sum() > 1000
     rel = np.abs(Ag[sel] - Ao[sel]) / Ao[sel]
@@ -219,7 +219,7 @@ def test_cloud_all_sources_statistical_and_conservation(soc, ctx, cloud):
         Ao, so, _ = orc.simulate_frequency(P.grid, f, T=T, seed=900 + b, nthreads=8,
                                            hits=hits if b == 0 else None, **kw)
         ob.append(Ao)
-        assert st["e_emitted"] == pytest.approx(so["e_emitted"], rel=1e-9)
+        assert st["e_emitted"] == pytest.approx(so["e_emitted"], rel=1e-9, abs=0)
     z, mg, mo, dof = batch_z(gb, ob)
     sel = hits * B > 1000
     check_z(z[sel], mg[sel], mo[sel], dof, "cloud, all sources")
@@ -283,9 +283,9 @@ def test_temperature_parity(soc, ctx, cloud):
     print(f"\nT max abs err {err.max():.3e} K")
     assert err.max() <= 0.05
     assert sg["clamped"] == so["clamped"]
-    assert sg["mean_T"] == pytest.approx(so["mean_T"], rel=1e-6)
-    assert sg["hot5_mean_T"] == pytest.approx(so["hot5_mean_T"], rel=1e-3)
-    assert sg["mean_rel_change"] == pytest.approx(so["mean_rel_change"], rel=1e-5)
+    assert sg["mean_T"] == pytest.approx(so["mean_T"], rel=1e-6, abs=0)
+    assert sg["hot5_mean_T"] == pytest.approx(so["hot5_mean_T"], rel=1e-3, abs=0)
+    assert sg["mean_rel_change"] == pytest.approx(so["mean_rel_change"], rel=1e-5, abs=0)
 
 
 # ------------------------------------------------------------------ map

@@ -113,10 +113,10 @@ def test_planck_limits_and_stefan_boltzmann():
     """Rayleigh-Jeans and Wien limits; pi * integral of B_nu = sigma_SB T^4."""
     T = 30.0
     nu_rj = 1e8
-    assert orc.planck(nu_rj, T) == pytest.approx(2 * nu_rj ** 2 * KB * T / CL ** 2, rel=1e-4)
+    assert orc.planck(nu_rj, T) == pytest.approx(2 * nu_rj ** 2 * KB * T / CL ** 2, rel=1e-4, abs=0)
     nu_w = 2e14
     x = H * nu_w / (KB * T)
-    assert orc.planck(nu_w, T) == pytest.approx(2 * H * nu_w ** 3 / CL ** 2 * math.exp(-x), rel=1e-12)
+    assert orc.planck(nu_w, T) == pytest.approx(2 * H * nu_w ** 3 / CL ** 2 * math.exp(-x), rel=1e-12, abs=0)
     val, _ = integrate.quad(lambda lnu: math.exp(lnu) * orc.planck(math.exp(lnu), T),
                             math.log(1e8), math.log(1e15), limit=400)
     assert math.pi * val == pytest.approx(SIGMA_SB * T ** 4, rel=1e-6)
@@ -586,8 +586,8 @@ def test_ali_tallies_split_the_absorption():
     assert np.allclose(A1 + S, A0, rtol=1e-12, atol=1e-300)
     assert S.sum() > 0.1 * E.sum() and np.all(S <= E * (1 + 1e-12))
     _, sd, _ = orc.simulate_frequency(g, f, T=T, n_dust=5000, seed=5, iteration=3, freq_index=2)
-    assert E.sum() == pytest.approx(sd["e_emitted"], rel=1e-12)
-    assert s1["e_absorbed"] == pytest.approx(s0["e_absorbed"], rel=1e-12)
+    assert E.sum() == pytest.approx(sd["e_emitted"], rel=1e-12, abs=0)
+    assert s1["e_absorbed"] == pytest.approx(s0["e_absorbed"], rel=1e-12, abs=0)
     S2, E2 = np.zeros(g.ncells), np.zeros(g.ncells)
     orc.simulate_frequency(g, f, I_bg=1e-9, n_bg=2000, ali_self=S2, ali_emitted=E2, seed=5)
     assert not S2.any() and not E2.any()
@@ -820,6 +820,6 @@ def test_map_front_attenuation_order():
     B0, B1 = orc.planck(3e12, 10.0), orc.planck(3e12, 40.0)
     t0, t1 = 0.5, 1.0
     up = orc.map_image(g, f, T, 2)[0, 0]              # observer at +z: cell z=1 is near
-    assert up == pytest.approx(B1 * (1 - math.exp(-t1)) + B0 * (1 - math.exp(-t0)) * math.exp(-t1), rel=1e-12)
+    assert up == pytest.approx(B1 * (1 - math.exp(-t1)) + B0 * (1 - math.exp(-t0)) * math.exp(-t1), rel=1e-12, abs=0)
     down = orc.map_image(g, f, T, 2 | 4)[0, 0]
-    assert down == pytest.approx(B0 * (1 - math.exp(-t0)) + B1 * (1 - math.exp(-t1)) * math.exp(-t0), rel=1e-12)
+    assert down == pytest.approx(B0 * (1 - math.exp(-t0)) + B1 * (1 - math.exp(-t1)) * math.exp(-t0), rel=1e-12, abs=0)
