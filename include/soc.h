@@ -323,7 +323,7 @@ soc_status soc_scatter_map(soc_ctx ctx, soc_grid grid, const soc_freq *freq, con
  * quadrature weights w (Hz), S grain sizes with abundances (grains per H),
  * absorption cross sections sigma[S][K] (cm^2 per grain) and enthalpy grids
  * U[S][N] (erg per grain, increasing) at temperatures T[S][N] (K); all host
- * arrays, copied.  K <= 256, 2 <= N <= 256.  The model is tied to ctx. */
+ * arrays, copied.  K <= 128, 2 <= N <= 128.  The model is tied to ctx. */
 typedef struct soc_shg_model_s *soc_shg_model;
 soc_status soc_shg_model_create(soc_ctx ctx, int32_t K, const double *nu, const double *w, int32_t S,
                                 const double *abundance, const double *sigma, int32_t N, const double *U,

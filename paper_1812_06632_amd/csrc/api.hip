@@ -739,8 +739,10 @@ soc_status soc_shg_model_create(soc_ctx c, int32_t K, const double *nu, const do
     m->device = c->device;
     m->S = S; m->K = K; m->N = N;
     const int64_t sk = (int64_t)S * K, sn = (int64_t)S * N;
-    // layout: nu hnu inv_hnu w | abundance | sigma | U | T | share | emit | cool
-    const int64_t total = 4 * (int64_t)K + S + sk + 2 * sn + sk + sn * K + sn;
+    // layout: nu hnu inv_hnu w | abundance | sigma | U | T | share | emit | icool | idu | ks (bytes) | band (int32)
+    int64_t ks_off = 4 * (int64_t)K + S + sk + 2 * sn + sk + sn * K + sn + sn;
+    ks_off += ks_off & 1;   // 16-byte aligned
+    const int64_t total = ks_off + ((int64_t)S * shg_ks_stride(N) + 4 * (int64_t)S + 7) / 8;
     if (hipMalloc((void **)&m->d_buf, sizeof(double) * (size_t)total) != hipSuccess) {
         delete m;
         return fail(c, SOC_ENOMEM, "device allocation of the grain model failed");
@@ -769,7 +771,10 @@ soc_status soc_shg_model_create(soc_ctx c, int32_t K, const double *nu, const do
     v.T = d + 4 * K + S + sk + sn;
     v.share = d + 4 * K + S + sk + 2 * sn;
     v.emit = v.share + sk;
-    v.cool = v.emit + sn * K;
+    v.icool = v.emit + sn * K;
+    v.idu = v.icool + sn;
+    v.ks = (uint8_t *)(d + ks_off);
+    v.band = (int32_t *)(v.ks + (int64_t)S * shg_ks_stride(N));
     if (e == hipSuccess) e = launch_shg_prep(v, dw, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
@@ -810,9 +815,7 @@ soc_status soc_shg_solve(soc_ctx c, soc_grid g, soc_shg_model m, const double *d
     a.absorbed = d_absorbed;
     a.emission = d_emission;
     a.P = d_P;
-    int64_t blocks = (g->ncells + 3) / 4;
-    if (blocks > 65536) blocks = 65536;
-    HIPCHK(c, launch_shg(a, (int)(blocks < 1 ? 1 : blocks), c->stream));
+    HIPCHK(c, launch_shg(a, c->stream));
     return SOC_OK;
 }
 

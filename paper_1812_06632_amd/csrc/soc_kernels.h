@@ -87,8 +87,8 @@ struct PeelArgs {
 
 // Stochastically heated grains: model tables on the device (S sizes, K
 // frequencies, N enthalpy bins).
-constexpr int kShgMaxK = 256;
-constexpr int kShgMaxN = 256;
+constexpr int kShgMaxK = 128;
+constexpr int kShgMaxN = 128;
 struct ShgModelDev {
     int32_t S, K, N;
     const double *nu, *hnu, *inv_hnu;   // [K]
@@ -97,7 +97,11 @@ struct ShgModelDev {
     const double *U, *T;                // [S][N]
     double *share;                      // [S][K] share of each size in the absorption of band k
     double *emit;                       // [S][N][K] 4 pi sigma B_nu(T_i)
-    double *cool;                       // [S][N] cooling rate from bin i to i-1
+    double *icool;                      // [S][N] inverse cooling rate from bin i to i-1: (U_i - U_i-1) / L(T_i)
+    double *idu;                        // [S][N] 1 / (U_i - U_i-1), 0 at i = 0
+    uint8_t *ks;                        // [S][ks stride] ks[j][i] (j, i < N): photons k < ks of bin i land below
+                                        // bin j (K at j = N-1); 16-byte aligned, each size padded to 16 bytes
+    int32_t *band;                      // [S] up[j][i] = 0 for j - i >= band
 };
 struct ShgArgs {
     ShgModelDev model;
@@ -110,8 +114,13 @@ struct ShgArgs {
     double *emission;                   // [K][ncells]
     double *P;                          // [ncells][S][N] or NULL
 };
+// bytes of one size's ks table, a multiple of 16 for vector copies
+__host__ __device__ inline int shg_ks_stride(int N)
+{
+    return (N * N + 15) & ~15;
+}
 hipError_t launch_shg_prep(const ShgModelDev &m, const double *w, hipStream_t s);
-hipError_t launch_shg(const ShgArgs &a, int blocks, hipStream_t s);
+hipError_t launch_shg(const ShgArgs &a, hipStream_t s);
 
 struct SegmentDev {
     int64_t cell;

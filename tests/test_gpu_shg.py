@@ -102,6 +102,6 @@ def test_shg_error_paths(soc, ctx):
     G.U[1, 3] = G.U[1, 2]
     with pytest.raises(soc.SocError, match="increase"):
         soc.ShgModel(ctx, G)
-    G2 = W.grain_model(nu, w, n_size=2, n_enthalpy=300)
+    G2 = W.grain_model(nu, w, n_size=2, n_enthalpy=200)
     with pytest.raises(soc.SocError, match="enthalpy grid"):
         soc.ShgModel(ctx, G2)
