@@ -536,6 +536,87 @@ def scatter_bench(args, soc, torch, W):
     ctx.close()
 
 
+def shg_bench(args, soc, torch, W):
+    """Stochastically heated grains (Sect. 2.1.1, Appendix A) on the
+    benchmark cloud: one Monte Carlo pass of the constant sources at each of
+    the --freqs frequencies into its own absorbed-energy array (the grain
+    model's cross sections), then the temperature distributions of
+    --shg-sizes grain sizes on --shg-bins enthalpy bins and the emission of
+    every cell at every frequency.  The paper's laptop GPU needed 0.5 ms per
+    cell for 25 sizes and 128 frequencies (App. A).  CPU baseline: the
+    oracle on a sample of cells."""
+    import dataclasses
+
+    P0 = W.lognormal_problem(n=args.n, K=args.freqs, packages_per_freq=args.packages)
+    G = W.grain_model(P0.nu, P0.w, n_size=args.shg_sizes, n_enthalpy=args.shg_bins)
+    P = dataclasses.replace(P0, sigma_abs=G.sigma_per_H, emit_sigma_abs=G.sigma_per_H)
+    ctx = soc.Context(0)
+    g = soc.grid_from_workload(ctx, P.grid)
+    nc = P.grid.ncells
+    A = torch.zeros((P.K, nc), dtype=torch.float64, device="cuda")
+    have_ps = len(P.ps_pos) > 0
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for k in range(P.K):
+        f = (float(P.nu[k]), float(P.w[k]), float(P.sigma_abs[k]), float(P.sigma_sca[k]), float(P.g[k]))
+        soc.simulate_frequency(ctx, g, f, A[k], I_bg=float(P.I_bg[k]), ps_pos=P.ps_pos if have_ps else None,
+                               ps_Lnu=P.ps_Lnu[:, k] if have_ps else None, n_bg=P.n_bg,
+                               n_ps_pk=P.n_ps_pk if have_ps else 0, seed=1, iteration=1, freq_index=k)
+    torch.cuda.synchronize()
+    t_mc = time.time() - t0
+    log(f"SHG: {P.K} Monte Carlo passes {t_mc:.3f}s")
+    model = soc.ShgModel(ctx, G)
+    E = torch.zeros_like(A)
+    t0 = time.time()
+    soc.shg_solve(ctx, g, model, A, E)       # warm-up
+    torch.cuda.synchronize()
+    log(f"SHG: first solve {time.time() - t0:.3f}s")
+    t0 = time.time()
+    for _ in range(args.steps):
+        soc.shg_solve(ctx, g, model, A, E)
+    torch.cuda.synchronize()
+    t_shg = (time.time() - t0) / args.steps
+    leaves = int((P.grid.density() > 0).sum())
+    flops_cell_size = 2.0 * args.shg_bins * P.K + 2.0 * args.shg_bins * args.shg_bins   # emission sum + substitution
+    rate = leaves / t_shg
+    log(f"SHG: {P.K} MC passes {t_mc:.3f}s; solve {t_shg * 1e3:.2f} ms for {leaves} cells x {args.shg_sizes} sizes "
+        f"x {args.shg_bins} bins = {rate:.3e} cells/s")
+    emitted = float((E * torch.from_numpy(P.w).cuda()[:, None]).sum())
+    absorbed = float(A.sum())
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import shg_oracle as O
+        Ah = A[:, :: max(1, nc // 4096)].cpu().numpy()
+        rho = P.grid.density()[:: max(1, nc // 4096)].astype(np.float64)
+        V = P.grid.root_cell_cm ** 3
+        n_s = 0
+        t1 = time.time()
+        for c in range(Ah.shape[1]):
+            if rho[c] > 0:
+                O.solve_cell(G, Ah[:, c], rho[c] * V)
+                n_s += 1
+            if time.time() - t1 > 10.0:
+                break
+        el = time.time() - t1
+        cpu = {"value": n_s / el, "unit": "cells/s", "cores": 1, "kind": "oracle",
+               "sample": f"{n_s} cells of the same cloud (FP64 numpy oracle, one thread)"}
+        log(f"oracle: {n_s} cells in {el:.2f}s")
+    line = {"kind": "shg", "workload": f"lognormal {args.n}^3 benchmark cloud, {P.K} frequencies, constant sources "
+                                       f"({args.packages} packages/frequency), {args.shg_sizes} grain sizes, "
+                                       f"{args.shg_bins} enthalpy bins", "cells": leaves,
+            "mc_s": t_mc, "solve_ms": t_shg * 1e3, "cells_per_s": rate,
+            "paper_laptop_cells_per_s_25_sizes_128_freq": 2000.0,
+            "emitted_over_absorbed": emitted / absorbed,
+            "roofline": {"bound": "alu (fp64)", "achieved": rate * args.shg_sizes * flops_cell_size / 1e12,
+                         "peak": 78.6, "unit": "TFLOP/s",
+                         "frac": rate * args.shg_sizes * flops_cell_size / 1e12 / 78.6,
+                         "flops_per_cell_and_size": flops_cell_size},
+            "cpu_baseline": cpu}
+    print(json.dumps(line), flush=True)
+    model.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -569,6 +650,9 @@ def main():
     ap.add_argument("--ref-factor", type=float, default=16.0)
     ap.add_argument("--ali", action="store_true", help="plain versus diagonal-ALI iteration at three resolutions")
     ap.add_argument("--scatter", action="store_true", help="scattered-light image by forced scattering and peel-off")
+    ap.add_argument("--shg", action="store_true", help="stochastically heated grains on the benchmark cloud")
+    ap.add_argument("--shg-sizes", type=int, default=25)
+    ap.add_argument("--shg-bins", type=int, default=128)
     ap.add_argument("--ali-iters", type=int, default=20)
     ap.add_argument("--ali-ref-iters", type=int, default=60)
     ap.add_argument("--ali-tau", type=float, default=500.0)
@@ -605,6 +689,9 @@ def main():
         return
     if args.scatter:
         scatter_bench(args, soc, torch, W)
+        return
+    if args.shg:
+        shg_bench(args, soc, torch, W)
         return
 
     from paper_1812_06632_amd.driver import PlainSolver, converged

@@ -318,7 +318,7 @@ soc_status soc_scatter_map(soc_ctx ctx, soc_grid grid, const soc_freq *freq, con
                            double *d_image, int32_t npx, int32_t npy, soc_scatter_stats *stats);
 
 /* ---------------------------------------------------------------- stochastic heating */
-/* Stochastically heated grains (Sect. 2.1.1, Appendix B, "thermal continuous"
+/* Stochastically heated grains (Sect. 2.1.1, Appendix A, "thermal continuous"
  * approximation).  A grain model: K frequencies nu (Hz, increasing) with
  * quadrature weights w (Hz), S grain sizes with abundances (grains per H),
  * absorption cross sections sigma[S][K] (cm^2 per grain) and enthalpy grids

@@ -6,7 +6,7 @@ the HIP path.
 
 What it computes follows Juvela, "SOC program for dust continuum
 radiative transfer" (A&A 2019, arXiv:1812.06632), Sect. 2.1.1 and
-Appendix B: the temperature distribution of each grain size in each cell
+Appendix A: the temperature distribution of each grain size in each cell
 from the absorbed photons, in the "thermal continuous" cooling
 approximation, where a grain cools only into the next lower enthalpy bin.
 

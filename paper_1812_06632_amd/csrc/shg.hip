@@ -1,5 +1,5 @@
 // shg.hip -- temperature distributions and emission of stochastically heated
-// grains (Sect. 2.1.1, Appendix B: the "thermal continuous" approximation,
+// grains (Sect. 2.1.1, Appendix A: the "thermal continuous" approximation,
 // cooling only into the next lower enthalpy bin, solved by forward
 // substitution in double precision).
 //

@@ -244,7 +244,7 @@ def blackbody_Lnu(nu: np.ndarray, L_total: float, T_star: float) -> np.ndarray:
 @dataclasses.dataclass
 class GrainModel:
     """A synthetic size distribution of stochastically heated grains (the
-    DustEM silicates of the paper's Appendix B are not available): per size
+    DustEM silicates of the paper's Appendix A are not available): per size
     bin s the grains per H, the absorption cross section per grain at the K
     frequencies, and an enthalpy grid of nE bins (enthalpy U and
     temperature T of each bin)."""

@@ -1,5 +1,5 @@
 """GPU parity of the stochastically heated grain solver (Sect. 2.1.1,
-Appendix B) through the C ABI against the FP64 oracle: populations and
+Appendix A) through the C ABI against the FP64 oracle: populations and
 emission per cell on regular and octree grids, weak fields (nearly all
 grains in the lowest bin) to strong ones (targets above the top bin), the
 production-size model, the energy balance of the output, error paths."""

@@ -1,4 +1,4 @@
-"""Pins of the stochastically heated grain oracle (Sect. 2.1.1, Appendix B)
+"""Pins of the stochastically heated grain oracle (Sect. 2.1.1, Appendix A)
 against what the physics and linear algebra fix, no GPU:
 
   * steady state: the grains emit exactly the power they absorb (the
