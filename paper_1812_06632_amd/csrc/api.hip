@@ -690,6 +690,7 @@ soc_status soc_scatter_map(soc_ctx c, soc_grid g, const soc_freq *f, const soc_s
     if ((st = grow(c, &c->d_peel, c->cap_peel, 8))) return st;
     HIPCHK(c, launch_fill_f64(c->d_peel, 0.0, 8, c->stream));
     P.totals = c->d_peel;
+    HIPCHK(c, launch_fill_u64(c->d_counter, 0ull, 1, c->stream));   // id pool of the refill
     const int blocks = (int)(c->num_cus * 8);
     HIPCHK(c, launch_peel(A, P, blocks, c->stream));
     if (stats) {

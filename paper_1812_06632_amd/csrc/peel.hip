@@ -11,43 +11,21 @@
 // optical depth tau_esc ahead of it, keeps the fraction 1 - exp(-tau_esc) of
 // its weight that scatters inside the box, and draws its first free path
 // from the exponential truncated at tau_esc (the same uniform that would
-// otherwise give -ln u).  One package per lane, grid-stride over the ids.
+// otherwise give -ln u).
+//
+// Each lane is a small state machine: idle, transporting its package, or
+// marching a ray to the boundary (the direct light of a point source, the
+// escape depth of forced scattering, or a peel-off).  Every pass of the loop
+// takes one step of whichever it is doing, so long rays and long packages do
+// not hold the rest of the wave; idle lanes are refilled together from a
+// wave-private id pool topped up with one atomic per `chunk` ids, as in the
+// Monte Carlo kernel.
 #include <hip/hip_runtime.h>
 
 #include "soc_device.h"
 #include "soc_kernels.h"
 
 namespace soc {
-
-// Optical depth from the package's position along direction (ox, oy, oz)
-// to the box boundary: scattering only, or extinction (absorption +
-// scattering).  A probe copy of the package steps through the grid with an
-// infinite free path.
-template <bool Oct>
-__device__ inline float ray_tau(const Pkg<float> &p0, const McArgs &A, float ox, float oy, float oz, bool ext,
-                                unsigned long long &steps)
-{
-    Pkg<float> q = p0;
-    q.ux = ox;
-    q.uy = oy;
-    q.uz = oz;
-    set_inverse(q);
-    q.tau = __builtin_huge_valf();
-    q.W = 1.0;
-    q.Wfloor = 0.0;
-    q.steps = 0;
-    const float k = ext ? A.ks_f + A.ka_f : A.ks_f;
-    float tau = 0.0f;
-    for (;;) {
-        const float n = q.n;
-        float d;
-        const StepOut o = step<float, Oct>(q, A, A.ks_f, A.ka_f, d);
-        tau += n * k * d;
-        ++steps;
-        if (o.event == kEvEscape || o.event == kEvRunaway) break;
-    }
-    return tau;
-}
 
 // Absolute position in root units.  Octree: up from the leaf through the
 // reverse links, halving the position and adding the octant at each level.
@@ -88,63 +66,164 @@ __device__ inline float hg_phase(float g, float mu)
     return inv4pi * (1.0f - g * g) / (d * sqrtf(d));
 }
 
+// Start a ray from the package's position along (ox, oy, oz): a probe copy
+// with an infinite free path and no weight floor.
+__device__ inline void ray_start(Pkg<float> &q, const Pkg<float> &p, float ox, float oy, float oz)
+{
+    q = p;
+    q.ux = ox;
+    q.uy = oy;
+    q.uz = oz;
+    set_inverse(q);
+    q.tau = __builtin_huge_valf();
+    q.W = 1.0;
+    q.Wfloor = 0.0;
+    q.steps = 0;
+}
+
+enum : int { kIdle = 0, kTransport = 1, kRay = 2, kAfterDirect = 3 };
+enum : int { kRayDirect = 0, kRayEscape = 1, kRayPeel = 2 };
+
 template <bool Oct>
-__global__ __launch_bounds__(256) void peel_kernel(McArgs A, PeelArgs P)
+__global__ __launch_bounds__(256, 3) void peel_kernel(McArgs A, PeelArgs P)
 {
     const HG<float> hg(A.g_f);
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     unsigned long long n_pk = 0, n_st = 0, n_sc = 0, n_ray = 0;
     double e_em = 0.0, e_es = 0.0;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; id < A.n_total; id += stride) {
-        Pkg<float> p;
-        Rng rng;
-        uint32_t cls, pid;
-        double W0;
-        n_pk += 1;
-        if (!emit_base<float, Oct>(A, id, p, rng, cls, pid, W0)) continue;
-        e_em += W0;
-        if (P.direct && cls >= kClassPs0) {
-            const PsArg &s = A.ps[cls - kClassPs0];
-            const float t = ray_tau<Oct>(p, A, P.ox, P.oy, P.oz, true, n_ray);
-            unsafeAtomicAdd(&P.image[pixel_of(P, s.x, s.y, s.z)], W0 * (0.0795774715459476679 * exp(-(double)t)) * P.scale);
+    // q is what the lane steps: its package, or the probe of one of the
+    // package's rays while p keeps the package
+    Pkg<float> p, q;
+    Rng rng;
+    int mode = kIdle, ray = kRayDirect, nscat = 0;
+    float xi = 0.0f, rtau = 0.0f, rk = 0.0f;
+    double W0 = 0.0;
+    int64_t src_pix = 0;
+    unsigned long long pool_next = 0, pool_end = 0;   // wave-uniform
+    bool exhausted = false;                           // wave-uniform
+    for (;;) {
+        // refill idle lanes from the wave's id pool
+        const unsigned long long idle = __ballot(mode == kIdle);
+        const int nidle = __popcll(idle);
+        if (!exhausted && nidle > 0) {
+            const unsigned long long avail = pool_end - pool_next;
+            unsigned long long grant = 0;
+            if (avail < (unsigned long long)nidle) {
+                const int leader = __ffsll((long long)idle) - 1;
+                unsigned long long b = 0;
+                if (lane == leader) b = atomicAdd(A.next_id, (unsigned long long)A.chunk);
+                grant = (unsigned long long)__shfl((long long)b, leader, 64);
+            }
+            if (mode == kIdle) {
+                const unsigned long long r = (unsigned long long)__popcll(idle & below);
+                const unsigned long long id = r < avail ? pool_next + r : grant + (r - avail);
+                if (id < A.n_total) {
+                    uint32_t cls, pid;
+                    n_pk += 1;
+                    if (emit_base<float, Oct>(A, id, q, rng, cls, pid, W0)) {
+                        e_em += W0;
+                        nscat = 0;
+                        xi = next_u<float>(rng, A);
+                        if (P.direct && cls >= kClassPs0) {
+                            const PsArg &s = A.ps[cls - kClassPs0];
+                            src_pix = pixel_of(P, s.x, s.y, s.z);
+                            p = q;
+                            ray_start(q, p, P.ox, P.oy, P.oz);
+                            ray = kRayDirect;
+                            rk = A.ks_f + A.ka_f;
+                            rtau = 0.0f;
+                            mode = kRay;
+                        } else {
+                            mode = kAfterDirect;
+                        }
+                    }
+                }
+            }
+            if (avail < (unsigned long long)nidle) {
+                pool_next = grant + ((unsigned long long)nidle - avail);
+                pool_end = grant + (unsigned long long)A.chunk;
+            } else {
+                pool_next += (unsigned long long)nidle;
+            }
+            if (pool_next >= A.n_total) exhausted = true;
         }
-        const float xi = next_u<float>(rng, A);
-        if (P.forced) {
-            const float tesc = ray_tau<Oct>(p, A, p.ux, p.uy, p.uz, false, n_ray);
-            const float q = -expm1f(-tesc);
-            if (!(q > 0.0f)) continue;
-            p.W *= (double)q;
-            p.tau = -log1pf(-xi * q);
+        // after the direct light (or at once): the escape depth, or the first free path
+        if (mode == kAfterDirect) {
+            if (P.forced) {
+                p = q;
+                ray_start(q, p, p.ux, p.uy, p.uz);
+                ray = kRayEscape;
+                rk = A.ks_f;
+                rtau = 0.0f;
+                mode = kRay;
+            } else {
+                q.tau = -m_log(xi);
+                mode = kTransport;
+            }
+        }
+        if (!__any(mode != kIdle)) {
+            if (exhausted) break;
+            continue;
+        }
+        if (mode == kIdle) continue;
+        const float n = q.n;
+        float d;
+        const StepOut o = step<float, Oct>(q, A, A.ks_f, A.ka_f, d);
+        if (mode == kRay) {
+            rtau += n * rk * d;
+            ++n_ray;
+            if (o.event == kEvEscape || o.event == kEvRunaway) {
+                q = p;   // back to the package
+                if (ray == kRayDirect) {
+                    unsafeAtomicAdd(&P.image[src_pix], W0 * (0.0795774715459476679 * exp(-(double)rtau)) * P.scale);
+                    mode = kAfterDirect;
+                } else if (ray == kRayEscape) {
+                    const float qf = -expm1f(-rtau);
+                    if (!(qf > 0.0f)) {
+                        mode = kIdle;
+                    } else {
+                        q.W *= (double)qf;
+                        q.tau = -log1pf(-xi * qf);
+                        mode = kTransport;
+                    }
+                } else {   // peel-off of the scattering at q
+                    const float mu = q.ux * P.ox + q.uy * P.oy + q.uz * P.oz;
+                    double x, y, z;
+                    abs_pos<Oct>(q, A, x, y, z);
+                    unsafeAtomicAdd(&P.image[pixel_of(P, x, y, z)],
+                                    q.W * (double)hg_phase(A.g_f, mu) * exp(-(double)rtau) * P.scale);
+                    if (P.max_scatter > 0 && ++nscat >= P.max_scatter) {
+                        mode = kIdle;
+                    } else {
+                        scatter_new_direction<float>(q, rng, A, hg);
+                        mode = kTransport;
+                    }
+                }
+            }
         } else {
-            p.tau = -m_log(xi);
-        }
-        int nscat = 0;
-        for (;;) {
-            float d;
-            const StepOut o = step<float, Oct>(p, A, A.ks_f, A.ka_f, d);
             n_st += 1;
             if (o.event == kEvEscape) {
-                e_es += p.W;
-                break;
+                e_es += q.W;
+                mode = kIdle;
+            } else if (o.event == kEvScatter) {   // peel off towards the observer, then scatter
+                n_sc += 1;
+                p = q;
+                ray_start(q, p, P.ox, P.oy, P.oz);
+                ray = kRayPeel;
+                rk = A.ks_f + A.ka_f;
+                rtau = 0.0f;
+                mode = kRay;
+            } else if (o.event != kEvCross) {   // weight floor or step cap
+                mode = kIdle;
             }
-            if (o.event != kEvScatter && o.event != kEvCross) break;   // weight floor or step cap
-            if (o.event == kEvCross) continue;
-            // peel off towards the observer, then scatter
-            n_sc += 1;
-            const float mu = p.ux * P.ox + p.uy * P.oy + p.uz * P.oz;
-            const float t = ray_tau<Oct>(p, A, P.ox, P.oy, P.oz, true, n_ray);
-            double x, y, z;
-            abs_pos<Oct>(p, A, x, y, z);
-            unsafeAtomicAdd(&P.image[pixel_of(P, x, y, z)], p.W * (double)hg_phase(A.g_f, mu) * exp(-(double)t) * P.scale);
-            if (P.max_scatter > 0 && ++nscat >= P.max_scatter) break;
-            scatter_new_direction<float>(p, rng, A, hg);
         }
     }
     // totals: summed over the wave, one set of atomics per wave
     double v[6] = {(double)n_pk, (double)n_st, (double)n_sc, (double)n_ray, e_em, e_es};
     for (int k = 0; k < 6; ++k)
         for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
-    if ((threadIdx.x & 63) == 0)
+    if (lane == 0)
         for (int k = 0; k < 6; ++k) unsafeAtomicAdd(&P.totals[k], v[k]);
 }
 
