@@ -323,7 +323,11 @@ soc_status soc_scatter_map(soc_ctx ctx, soc_grid grid, const soc_freq *freq, con
  * quadrature weights w (Hz), S grain sizes with abundances (grains per H),
  * absorption cross sections sigma[S][K] (cm^2 per grain) and enthalpy grids
  * U[S][N] (erg per grain, increasing) at temperatures T[S][N] (K); all host
- * arrays, copied.  K <= 128, 2 <= N <= 128.  The model is tied to ctx. */
+ * arrays, copied.  K <= 128, 2 <= N <= 128, 1 <= S <= 4096.  The model is
+ * tied to ctx.  Errors: SOC_EINVAL for sizes out of range, frequencies or
+ * enthalpies that do not increase, non-positive temperatures, negative or
+ * non-finite weights, abundances or cross sections (*out stays NULL);
+ * SOC_ENOMEM when its device tables cannot be allocated. */
 typedef struct soc_shg_model_s *soc_shg_model;
 soc_status soc_shg_model_create(soc_ctx ctx, int32_t K, const double *nu, const double *w, int32_t S,
                                 const double *abundance, const double *sigma, int32_t N, const double *U,
@@ -344,7 +348,9 @@ void soc_shg_model_destroy(soc_shg_model model);   /* valid before or after its 
  * d_emission (device FP64 [K][ncells], overwritten): sum over sizes of the
  * grain count times 4 pi sigma_sk sum_i P_i B_nu_k(T_i), erg s^-1 Hz^-1 per
  * cell (0 in empty and refined cells).  d_P (device FP64
- * [ncells][S][N], optional): the populations.  Enqueued on ctx's stream. */
+ * [ncells][S][N], optional): the populations.  Enqueued on ctx's stream.
+ * Errors: SOC_EINVAL for NULL arguments or a grid or model of another
+ * context; SOC_EHIP when the launch fails. */
 soc_status soc_shg_solve(soc_ctx ctx, soc_grid grid, soc_shg_model model, const double *d_absorbed,
                          double *d_emission, double *d_P);
 
