@@ -553,15 +553,10 @@ def shg_bench(args, soc, torch, W):
     ctx = soc.Context(0)
     g = soc.grid_from_workload(ctx, P.grid)
     nc = P.grid.ncells
-    A = torch.zeros((P.K, nc), dtype=torch.float64, device="cuda")
-    have_ps = len(P.ps_pos) > 0
+    from paper_1812_06632_amd.driver import absorbed_spectra
     torch.cuda.synchronize()
     t0 = time.time()
-    for k in range(P.K):
-        f = (float(P.nu[k]), float(P.w[k]), float(P.sigma_abs[k]), float(P.sigma_sca[k]), float(P.g[k]))
-        soc.simulate_frequency(ctx, g, f, A[k], I_bg=float(P.I_bg[k]), ps_pos=P.ps_pos if have_ps else None,
-                               ps_Lnu=P.ps_Lnu[:, k] if have_ps else None, n_bg=P.n_bg,
-                               n_ps_pk=P.n_ps_pk if have_ps else 0, seed=1, iteration=1, freq_index=k)
+    A = absorbed_spectra(ctx, g, P, seed=1, iteration=1)
     torch.cuda.synchronize()
     t_mc = time.time() - t0
     log(f"SHG: {P.K} Monte Carlo passes {t_mc:.3f}s")

@@ -228,3 +228,26 @@ class ReferenceFieldSolver(PlainSolver):
         self.T.copy_(self.T_new)
         s["packages"] = n
         return s
+
+
+def absorbed_spectra(ctx: soc.Context, grid: soc.Grid, P, T=None, n_dust: int = 0, seed: int = 1,
+                     iteration: int = 1, out=None) -> torch.Tensor:
+    """Absorbed energy of every cell in each frequency band of problem P,
+    float64 [K][ncells] (erg/s): one Monte Carlo pass per frequency into its
+    own row, of the constant sources and, given temperatures T, of n_dust
+    luminosity-weighted dust-emission packages.  Stochastically heated grains
+    need the absorptions per frequency rather than integrated (Sect. 2.1.1);
+    the paper keeps them in memory-mapped files on the host, here they stay
+    in device memory.  The cross sections are P's (for grains: the model's
+    total per H)."""
+    K, nc = P.K, P.grid.ncells
+    A = out if out is not None else torch.empty((K, nc), dtype=torch.float64, device="cuda")
+    have_ps = len(P.ps_pos) > 0
+    for k in range(K):
+        A[k].zero_()
+        f = (float(P.nu[k]), float(P.w[k]), float(P.sigma_abs[k]), float(P.sigma_sca[k]), float(P.g[k]))
+        soc.simulate_frequency(ctx, grid, f, A[k], I_bg=float(P.I_bg[k]), ps_pos=P.ps_pos if have_ps else None,
+                               ps_Lnu=P.ps_Lnu[:, k] if have_ps else None, n_bg=P.n_bg,
+                               n_ps_pk=P.n_ps_pk if have_ps else 0, T=T, n_dust=n_dust if T is not None else 0,
+                               dust_mode=1, seed=seed, iteration=iteration, freq_index=k)
+    return A

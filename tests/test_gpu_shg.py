@@ -105,3 +105,39 @@ def test_shg_error_paths(soc, ctx):
     G2 = W.grain_model(nu, w, n_size=2, n_enthalpy=200)
     with pytest.raises(soc.SocError, match="enthalpy grid"):
         soc.ShgModel(ctx, G2)
+
+
+def test_shg_from_monte_carlo_spectra(soc, ctx):
+    """The whole chain on a small cloud: one Monte Carlo pass per frequency
+    into its own row (driver.absorbed_spectra, the grain model's cross
+    sections), then the grain solve.  The rows sum to the frequency-integrated
+    absorption of the same packages, and the emission from these Monte Carlo
+    spectra (empty cells, reddened and unreddened cells, the point sources'
+    neighbourhood) matches the oracle's solve of the same arrays to 1e-9."""
+    import dataclasses
+
+    from paper_1812_06632_amd.driver import absorbed_spectra
+    P0 = W.lognormal_problem(n=10, K=16, sigma_ln=1.0, tau_v_mean=4.0, seed=4, L_star_lsun=1e3,
+                             packages_per_freq=20000)
+    G = W.grain_model(P0.nu, P0.w, n_size=4, n_enthalpy=48)
+    P = dataclasses.replace(P0, sigma_abs=G.sigma_per_H, emit_sigma_abs=G.sigma_per_H)
+    g = soc.grid_from_workload(ctx, P.grid)
+    A = absorbed_spectra(ctx, g, P, seed=3)
+    integ = torch.zeros(P.grid.ncells, dtype=torch.float64, device="cuda")
+    have_ps = len(P.ps_pos) > 0
+    for k in range(P.K):
+        f = (float(P.nu[k]), float(P.w[k]), float(P.sigma_abs[k]), float(P.sigma_sca[k]), float(P.g[k]))
+        soc.simulate_frequency(ctx, g, f, integ, I_bg=float(P.I_bg[k]), ps_pos=P.ps_pos if have_ps else None,
+                               ps_Lnu=P.ps_Lnu[:, k] if have_ps else None, n_bg=P.n_bg,
+                               n_ps_pk=P.n_ps_pk if have_ps else 0, seed=3, iteration=1, freq_index=k)
+    a = A.cpu().numpy()
+    np.testing.assert_allclose(a.sum(axis=0), integ.cpu().numpy(), rtol=1e-11, atol=0)
+    assert (a > 0).mean() > 0.9
+    model = soc.ShgModel(ctx, G)
+    E = torch.zeros_like(A)
+    soc.shg_solve(ctx, g, model, A, E)
+    rho = P.grid.density().astype(np.float64)
+    V = np.full(P.grid.ncells, P.grid.root_cell_cm ** 3)
+    E_o, _ = O.shg_solve(G, rho, V, a)
+    np.testing.assert_allclose(E.cpu().numpy(), E_o, rtol=1e-9, atol=1e-12 * np.abs(E_o).max())
+    model.close()
