@@ -217,3 +217,41 @@ def test_octree_full_package_count_and_temperatures(soc, ctx, octree_cloud):
     print(f"\noctree, 10^7 packages: {st['cell_steps']:.3e} steps, {st['scatterings']:.3e} scatterings; "
           f"temperatures of 5000 sampled leaves per level: max |dT| {worst:.3e} K")
     assert worst <= 0.05
+
+
+# ------------------------------------------------------------------ batch of 256 clouds
+def test_batch_of_256_clouds_at_full_size(soc, ctx):
+    """The batched workload as the benchmark runs it: 256 lognormal clouds of
+    16^3-96^3 cells, 32 frequencies, 10^5-10^6 packages per (cloud,
+    frequency) pair, tiles of 16384 packages.  Sampled clouds equal the
+    sum of their 32 single soc_simulate_frequency calls with the batch's
+    seeds, up to FP64 summation order.  The pair with the most packages per
+    cell against the oracle, same seed.  Energy is conserved over the whole
+    batch."""
+    grids, (nu, w, sabs, ssca, gg, I), pk = W.batch_clouds(256, 32)
+    G = [soc.grid_from_workload(ctx, gr) for gr in grids]
+    A = [torch.zeros(gr.ncells, dtype=torch.float64, device="cuda") for gr in grids]
+    freqs = [(float(nu[k]), float(w[k]), float(sabs[k]), float(ssca[k]), float(gg[k])) for k in range(len(nu))]
+    pairs = [dict(grid=m, freq=freqs[k], freq_index=k, I_bg=float(I[k]), n_bg=int(pk[m, k]), absorbed=A[m])
+             for m in range(len(grids)) for k in range(len(nu))]
+    seed = 0x5eed_0000_0001
+    b = soc.Batch(ctx, G, pairs, seed=seed, tile_packages=16384)
+    st = b.run(iteration=4, stats=True)
+    b.close()
+    assert st["packages"] == int(pk.sum()) and st["runaways"] == 0
+    assert abs((st["e_absorbed"] + st["e_escaped"]) / st["e_emitted"] - 1.0) < 1e-6
+    rng = np.random.default_rng(11)
+    sample = sorted(rng.choice(len(grids), size=6, replace=False).tolist() + [int(np.argmax([g.ncells for g in grids]))])
+    for m in sample:
+        ref = torch.zeros(grids[m].ncells, dtype=torch.float64, device="cuda")
+        for k in range(len(nu)):
+            soc.simulate_frequency(ctx, G[m], freqs[k], ref, I_bg=float(I[k]), n_bg=int(pk[m, k]),
+                                   seed=seed ^ (m << 32), iteration=4, freq_index=k)
+        a, r = A[m].cpu().numpy(), ref.cpu().numpy()
+        np.testing.assert_allclose(a, r, rtol=1e-11, atol=1e-12 * r.max())
+    # the oracle on the pair with the most packages per cell (well-sampled cells)
+    dens = pk / np.array([gr.ncells for gr in grids], dtype=np.float64)[:, None]
+    m, k = (int(v) for v in np.unravel_index(int(np.argmax(dens)), dens.shape))
+    print(f"\nbatch: {st['packages']} packages, {st['cell_steps']:.3e} steps; clouds {sample} equal their single calls")
+    _same_seed(soc, ctx, G[m], grids[m], freqs[k], f"batch cloud {m} ({grids[m].nx}^3), frequency {k}", I_bg=float(I[k]),
+               n_bg=int(pk[m, k]), seed=seed ^ (m << 32), iteration=4, freq_index=k)
