@@ -239,3 +239,24 @@ def test_bad_shapes_rejected(soc):
     with pytest.raises(ValueError):
         net.forward(torch.zeros((1, 8, 8, 4, 2), device="cuda"))
     ctx.close()
+
+
+def test_forward_at_full_size(soc):
+    """The surrogate's network at full size and in the benchmark's launch
+    configuration: 4 levels, base 32, the surrogate's input features and
+    one output, a batch of 4 samples of 64^3.  One sample, computed alone by
+    the oracle, is within 5e-3 of the BF16-storage model and within 1e-2
+    of the FP64 oracle (relative L2)."""
+    from paper_1812_06632_amd.surrogate import N_FEATURES
+    P, x, _ = _case(4, 32, 4, (64, 64, 64), cin=N_FEATURES, cout=1, seed=3)
+    ctx = soc.Context(0)
+    net = soc.UNet(ctx, N_FEATURES, 1, 32, 4, 4, (64, 64, 64))
+    net.set_params(flat(P).astype(np.float32))
+    y = net.forward(torch.from_numpy(x.astype(np.float32)).cuda()).cpu().numpy().astype(np.float64)
+    j = 2
+    ym, _ = bf16_model_forward(P, x[j:j + 1], 4)
+    yo, _ = U.forward(P, x[j:j + 1], 4)
+    a, b = rel(y[j:j + 1], ym), rel(y[j:j + 1], yo)
+    print(f"\nfull-size forward, sample {j}: dev-vs-model {a:.2e}, dev-vs-oracle {b:.2e}, model-vs-oracle {rel(ym, yo):.2e}")
+    assert a < 5e-3 and b < 1e-2
+    ctx.close()
