@@ -1034,11 +1034,11 @@ static hipError_t launch_conv(const ConvArgs &a, hipStream_t s)
         const unsigned big = (unsigned)a.batch * ((a.mz + kB3 - 1) / kB3) * ((a.my + kB3 - 1) / kB3) *
                              ((a.mx + kB3 - 1) / kB3);
         if (big >= 256) {   // enough 8^3 bricks to fill the device
-            const dim3 grid(big, a.npad / (32 * nt), 1);
-            if (nt == 2)
-                hipLaunchKernelGGL(conv3_big_kernel<2>, grid, dim3(256), 0, s, a);
-            else
-                hipLaunchKernelGGL(conv3_big_kernel<1>, grid, dim3(256), 0, s, a);
+            // one 32-column tile per wave: with two, the four row tiles'
+            // accumulators and operands need ~275 registers, one wave per
+            // SIMD, and the step was 2.6% slower
+            const dim3 grid(big, a.npad / 32, 1);
+            hipLaunchKernelGGL(conv3_big_kernel<1>, grid, dim3(256), 0, s, a);
             return hipGetLastError();
         }
         const unsigned bricks = (unsigned)a.batch * ((a.mz + kBZ - 1) / kBZ) * ((a.my + kBY - 1) / kBY) *
