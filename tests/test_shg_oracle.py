@@ -95,3 +95,46 @@ def test_no_field_and_density_scaling(model):
     assert not E[:, 0].any() and not PP[0].any()
     assert np.allclose(E[:, 2], 2 * E[:, 1], rtol=1e-12) and np.allclose(E[:, 3], 0.5 * E[:, 1], rtol=1e-12)
     assert np.allclose(PP[2], PP[1], rtol=1e-12, atol=1e-300)
+
+
+def test_rate_matrix_and_populations_by_hand():
+    """Three enthalpy bins U = (0, 1, 3) u and two photon energies 0.5 u and
+    2.5 u, the rate matrix written out by hand from the linear split of
+    Appendix A, and the populations of its forward substitution in closed form.
+
+    Expected upward rates:
+      - from bin 0, the 0.5 u photon lands halfway to bin 1: half of r1 to bin 1, half
+        stays;
+      - from bin 0, the 2.5 u photon lands at 2.5 u, between bins 1 and 2: 3/4 to bin 2,
+        1/4 to bin 1;
+      - from bin 1, the 0.5 u photon lands at 1.5 u: 1/4 to bin 2, 3/4 stays;
+      - from bin 1, the 2.5 u photon goes above the top: all of it to bin 2.
+    Cooling: bin 1 -> 0 at L(T_1)/1 u, bin 2 -> 1 at L(T_2)/2 u, with L from an
+    independent Planck function."""
+    h, k, c = 6.62607015e-27, 1.380649e-16, 2.99792458e10
+    u = 1e-12                                   # erg
+    nu = np.array([0.5 * u / h, 2.5 * u / h])
+    w = np.array([0.3 * nu[0], 0.2 * nu[1]])
+    T = np.array([[20.0, 80.0, 300.0]])
+    sigma = np.array([[2e-16, 5e-17]])
+    G = W.GrainModel(nu=nu, w=w, a_cm=np.array([1e-7]), abundance=np.array([1.0]), sigma=sigma,
+                     U=np.array([[0.0, 1.0, 3.0]]) * u, T=T)
+    r1, r2 = 3.0e-3, 7.0e-4
+
+    def L(Tk):
+        B = 2 * h * nu ** 3 / c ** 2 / np.expm1(h * nu / (k * Tk))
+        return 4 * math.pi * float((sigma[0] * B * w).sum())
+
+    Rh = np.zeros((3, 3))
+    Rh[1, 0] = 0.5 * r1 + 0.25 * r2
+    Rh[2, 0] = 0.75 * r2
+    Rh[2, 1] = 0.25 * r1 + r2
+    Rh[0, 1] = L(80.0) / u
+    Rh[1, 2] = L(300.0) / (2 * u)
+    Rh[np.diag_indices(3)] = -Rh.sum(axis=0)
+    R = O.rate_matrix(G, 0, np.array([r1, r2]))
+    np.testing.assert_allclose(R, Rh, rtol=1e-12, atol=0)
+    P = O.solve_forward(R)
+    p1 = (Rh[1, 0] + Rh[2, 0]) / Rh[0, 1]                 # flow across the cut between bins 0 and 1
+    p2 = (Rh[2, 0] + p1 * Rh[2, 1]) / Rh[1, 2]            # and between bins 1 and 2
+    np.testing.assert_allclose(P, np.array([1.0, p1, p2]) / (1.0 + p1 + p2), rtol=1e-12, atol=0)
