@@ -474,6 +474,93 @@ def ali_gain(args, soc, torch, W):
     ctx.close()
 
 
+def octree_bench(args, soc, torch, W):
+    """The octree workload: 64^3 root cells with three refinement levels
+    where the density exceeds 4x the mean (4.68 M leaves), a lognormal cloud
+    with a central dense core (tau_V 100 from the centre to the edge), a
+    10^4 K source of 10^6 L_sun inside the core and the external field, 128
+    frequencies, 10^7 packages per frequency (half from the field, half
+    from the source).  The persistent kernel's launch schedule is tuned by
+    the autotuner on short calibration passes; the whole 128-frequency pass
+    is then timed with the default and with the tuned schedule.  CPU
+    baseline: the oracle on a sample of the same packages."""
+    from paper_1812_06632_amd import autotune
+
+    t0 = time.time()
+    G = W.octree_lognormal(n_root=64, nlevels=4)
+    nu, w = W.frequency_grid(128)
+    sabs, ssca, gg = W.dust_model(nu)
+    log(f"octree: {G.ncells} cells, {int((G.words.view(np.int32) >= 0).sum())} leaves ({time.time() - t0:.1f}s)")
+    ctx = soc.Context(0)
+    g = soc.grid_from_workload(ctx, G)
+    A = torch.zeros(G.ncells, dtype=torch.float64, device="cuda")
+    pos = [[32.1, 31.9, 32.05]]
+    freqs = [(float(nu[k]), float(w[k]), float(sabs[k]), float(ssca[k]), float(gg[k])) for k in range(len(nu))]
+    I = W.isrf(nu)
+    Lnu = W.blackbody_Lnu(nu, 1e6 * W.L_SUN, 1e4)
+    n_half = 5_000_000
+
+    def one(k, n):
+        soc.simulate_frequency(ctx, g, freqs[k], A, I_bg=float(I[k]), ps_pos=pos, ps_Lnu=[float(Lnu[k])], n_bg=n,
+                               n_ps_pk=n, seed=1, iteration=1, freq_index=k)
+
+    def full_pass():
+        A.zero_()
+        ctx.read_stats(reset=True)
+        torch.cuda.synchronize()
+        t = time.time()
+        for k in range(len(nu)):
+            one(k, n_half)
+        torch.cuda.synchronize()
+        el = time.time() - t
+        st = ctx.read_stats(reset=True)
+        return el, st
+
+    # calibration: an optical and a far-infrared frequency, 10^6 packages each
+    ks = [int(np.argmin(np.abs(np.log(2.99792458e14 / nu / l)))) for l in (0.55, 100.0)]
+    tau_cell = float(sabs[ks[0]] + ssca[ks[0]]) * float(np.median(G.density()[G.density() > 0])) * G.root_cell_cm
+    key = autotune.class_key("octree", G.ncells, tau_cell, "bg+ps")
+    measure = autotune.event_timer(ctx, lambda cfg: [one(k, 500_000) for k in ks])
+    defaults = {n: ctx.get_option(n) for n in autotune.DEFAULT_SPACE}
+    t0 = time.time()
+    best = autotune.Autotuner().tune(key, measure)
+    log(f"octree: autotuned {best} in {time.time() - t0:.1f}s (default {defaults})")
+    autotune.apply(ctx, defaults)
+    one(ks[0], n_half)   # warm-up
+    t_def, st_def = full_pass()
+    autotune.apply(ctx, best)
+    t_tuned, st = full_pass()
+    log(f"octree: 128 frequencies x 10^7 packages: default schedule {t_def:.2f}s, tuned {t_tuned:.2f}s")
+    cons = (st["e_absorbed"] + st["e_escaped"]) / st["e_emitted"] - 1.0
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import orc
+        ncpu = min(os.cpu_count() or 1, 16)
+        t1 = time.time()
+        n_pk = n_st = 0
+        for k in ks:
+            _, so, _ = orc.simulate_frequency(G, freqs[k], I_bg=float(I[k]), ps_pos=pos, ps_Lnu=[float(Lnu[k])],
+                                              n_bg=3_000_000, n_ps_pk=3_000_000, seed=1, iteration=1, freq_index=k,
+                                              nthreads=ncpu)
+            n_pk += so["packages"]
+            n_st += so["cell_steps"]
+        tc = time.time() - t1
+        cpu = {"value": n_pk / tc, "unit": "packages/s", "cores": ncpu, "kind": "oracle",
+               "cell_steps_per_s": n_st / tc,
+               "sample": f"6 x 10^6 packages at each of frequencies {ks} of the same octree and sources "
+                         f"(FP64 C oracle, OpenMP)"}
+        log(f"oracle: {n_pk} packages in {tc:.2f}s")
+    line = {"kind": "octree", "workload": "octree 64^3 root + 3 levels (4.68 M leaves), central core tau_V 100, "
+                                          "10^4 K source of 10^6 L_sun + external field, 128 frequencies, "
+                                          "10^7 packages/frequency",
+            "packages": st["packages"], "cell_steps": st["cell_steps"], "s_per_pass": t_tuned,
+            "packages_per_s": st["packages"] / t_tuned, "cell_steps_per_s": st["cell_steps"] / t_tuned,
+            "s_per_pass_default_schedule": t_def, "schedule": best, "energy_conservation": cons,
+            "cpu_baseline": cpu}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def scatter_bench(args, soc, torch, W):
     """Scattered-light image (forced first scattering, peel-off of every
     scattering, Sect. 2.1.1) of the benchmark cloud at 0.55 um, seen along
@@ -646,6 +733,7 @@ def main():
     ap.add_argument("--ali", action="store_true", help="plain versus diagonal-ALI iteration at three resolutions")
     ap.add_argument("--scatter", action="store_true", help="scattered-light image by forced scattering and peel-off")
     ap.add_argument("--shg", action="store_true", help="stochastically heated grains on the benchmark cloud")
+    ap.add_argument("--octree", action="store_true", help="the octree workload with an autotuned launch schedule")
     ap.add_argument("--shg-sizes", type=int, default=25)
     ap.add_argument("--shg-bins", type=int, default=128)
     ap.add_argument("--ali-iters", type=int, default=20)
@@ -687,6 +775,9 @@ def main():
         return
     if args.shg:
         shg_bench(args, soc, torch, W)
+        return
+    if args.octree:
+        octree_bench(args, soc, torch, W)
         return
 
     from paper_1812_06632_amd.driver import PlainSolver, converged
