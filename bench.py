@@ -743,9 +743,9 @@ def main():
     ap.add_argument("--ali-lsun", type=float, default=1.0e5)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the design notes describe how the "
-              "package range would be split across GPUs with one all-reduce of the absorbed energy per "
-              "iteration).", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (several GPUs would each take a "
+              "range of package ids and sum their absorbed energy with one all-reduce per iteration).",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

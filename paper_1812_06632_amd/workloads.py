@@ -303,7 +303,7 @@ def grain_model(nu: np.ndarray, w: np.ndarray, n_size: int = 8, n_enthalpy: int 
     return GrainModel(nu=nu, w=np.asarray(w, dtype=np.float64), a_cm=a, abundance=ab, sigma=sigma, U=U, T=T)
 
 
-# ---------------------------------------------------------------- configs
+# ---------------------------------------------------------------- problems
 @dataclasses.dataclass
 class Problem:
     """One synthetic workload: grid, frequencies, dust and sources."""
