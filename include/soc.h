@@ -73,10 +73,11 @@ typedef enum {
     SOC_OPT_INNER_STEPS = 4,     /* cell steps between refill checks, 1..8 [1] */
     SOC_OPT_TIMING = 5,          /* 1 = time each MC launch with HIP events [0] */
     SOC_OPT_SCATTER_MIN = 6,     /* draw new directions once this many lanes of a wave wait for one, 1..64 [1] */
-    SOC_OPT_XCD_COPIES = 7,      /* 1 = the waves of each XCD add into a private copy of the absorbed array
-                                    (chosen by the hardware XCC id; context scratch of 8 x ncells doubles),
-                                    summed into d_absorbed by one kernel after the launch: spreads the
-                                    same-address adds of hot cells over 8 addresses [1] */
+    SOC_OPT_XCD_COPIES = 7,      /* 1 = each wave adds into one of 16 private copies of the absorbed array
+                                    (two per XCD: the hardware XCC id and the workgroup index's parity;
+                                    context scratch of 16 x ncells doubles), summed into d_absorbed by one
+                                    kernel after the launch: spreads the same-address adds of hot cells
+                                    over 16 addresses [1] */
     SOC_OPT_CHUNK = 8            /* package ids a wave takes from the global counter at a time, 64..65536
                                     (smaller: finer load balance between waves) [256] */
 } soc_option;

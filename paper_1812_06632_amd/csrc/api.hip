@@ -41,7 +41,7 @@ struct soc_ctx_s {
     DevStats *d_stats = nullptr;              // [0] per call, [1] running total
     unsigned long long *d_counter = nullptr;
     double *d_tmp_out = nullptr;              // small result buffer (temperature stats)
-    double *d_priv = nullptr;                 // 8 private copies of the absorbed array (zero between launches)
+    double *d_priv = nullptr;                 // kPrivCopies private copies of the absorbed array (zero between launches)
     int64_t cap_priv = 0;
     double *d_priv_self = nullptr;            // the same for the ALI self-absorption tally
     int64_t cap_priv_self = 0;
@@ -595,15 +595,15 @@ soc_status soc_simulate_frequency(soc_ctx c, soc_grid g, const soc_freq *f, cons
     soc_status st = prepare(c, g, f, s, seed, iteration, freq_index, d_absorbed, A);
     if (st) return st;
     if (c->xcd_copies) {
-        if (c->cap_priv < 8 * g->ncells) {   // new copies start zero; every fold leaves them zero
-            st = grow(c, &c->d_priv, c->cap_priv, 8 * g->ncells);
+        if (c->cap_priv < (int64_t)kPrivCopies * g->ncells) {   // new copies start zero; every fold leaves them zero
+            st = grow(c, &c->d_priv, c->cap_priv, (int64_t)kPrivCopies * g->ncells);
             if (st) return st;
             HIPCHK(c, launch_fill_f64(c->d_priv, 0.0, c->cap_priv, c->stream));
         }
         A.priv = c->d_priv;
         if (A.ali_self) {
-            if (c->cap_priv_self < 8 * g->ncells) {
-                st = grow(c, &c->d_priv_self, c->cap_priv_self, 8 * g->ncells);
+            if (c->cap_priv_self < (int64_t)kPrivCopies * g->ncells) {
+                st = grow(c, &c->d_priv_self, c->cap_priv_self, (int64_t)kPrivCopies * g->ncells);
                 if (st) return st;
                 HIPCHK(c, launch_fill_f64(c->d_priv_self, 0.0, c->cap_priv_self, c->stream));
             }

@@ -94,8 +94,8 @@ __device__ __forceinline__ void mc_body(const McArgs &A)
     double e_em = 0.0, e_ab = 0.0, e_es = 0.0;
     const float ks = A.ks_f, ka = A.ka_f;
     const HG<float> hg(A.g_f);
-    double *const dst = A.priv ? A.priv + (size_t)xcd_index() * (size_t)A.ncells : A.absorbed;
-    double *const sdst = A.priv_self ? A.priv_self + (size_t)xcd_index() * (size_t)A.ncells : A.ali_self;
+    double *const dst = A.priv ? A.priv + (size_t)priv_index() * (size_t)A.ncells : A.absorbed;
+    double *const sdst = A.priv_self ? A.priv_self + (size_t)priv_index() * (size_t)A.ncells : A.ali_self;
 
     for (;;) {
         // refill idle lanes from the wave's id pool

@@ -39,14 +39,14 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t 
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
 
-// Per-XCD private copies of the absorbed array: add the 8 copies into the
+// Private copies of the absorbed array: add the kPrivCopies copies into the
 // caller's array in copy order and leave them zero for the next launch.
 __global__ void fold_copies_kernel(double *absorbed, double *priv, int64_t n)
 {
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
         double s = 0.0;
 #pragma unroll
-        for (int x = 0; x < 8; ++x) {
+        for (uint32_t x = 0; x < kPrivCopies; ++x) {
             s += priv[x * n + c];
             priv[x * n + c] = 0.0;
         }

@@ -22,6 +22,13 @@ __device__ inline uint32_t xcd_index()
     return __builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & 7u;
 }
 
+// Private copy (0..kPrivCopies-1) a wave adds into: its XCD and the
+// workgroup's index modulo the copies per XCD; wave-uniform.
+__device__ inline uint32_t priv_index()
+{
+    return xcd_index() + 8u * (blockIdx.x % kPrivPerXcd);
+}
+
 
 // ------------------------------------------------------------------ Philox
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two

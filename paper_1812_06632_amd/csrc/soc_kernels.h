@@ -8,6 +8,13 @@
 
 namespace soc {
 
+// Private copies of a tally for the Monte Carlo launches: two per XCD, so
+// that the same-address adds of the hottest cells spread over 16 addresses
+// (8 copies: 410 ms per benchmark iteration, 16: 387 ms, 32: 400 ms, the
+// fold after each launch then costing more than it saves).
+constexpr uint32_t kPrivPerXcd = 2;
+constexpr uint32_t kPrivCopies = 8 * kPrivPerXcd;
+
 // Source classes: the low byte of Philox counter word 3.
 constexpr uint32_t kClassBg = 0;
 constexpr uint32_t kClassDust = 1;
@@ -64,9 +71,9 @@ struct McArgs {
     // transport
     int64_t step_cap;
     double *absorbed;
-    double *priv;                // NULL, or 8 private copies of ncells (one per XCD, hardware XCC id)
+    double *priv;                // NULL, or kPrivCopies private copies of ncells (see priv_index)
     double *ali_self;            // diagonal ALI (NULL = off): dust deposits in the emitting cell
-    double *priv_self;           // NULL, or 8 private copies of ali_self (one per XCD)
+    double *priv_self;           // NULL, or kPrivCopies private copies of ali_self
     // persistent scheduling
     unsigned long long *next_id;
     DevStats *st_call, *st_total;
@@ -154,7 +161,7 @@ hipError_t launch_peel(const McArgs &a, const PeelArgs &p, int blocks, hipStream
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
-// absorbed[c] += sum_x priv[x n + c] over the 8 private copies, which are left zero.
+// absorbed[c] += sum_x priv[x n + c] over the kPrivCopies private copies, which are left zero.
 hipError_t launch_fold_copies(double *absorbed, double *priv, int64_t n, hipStream_t s);
 
 // dust emission setup
