@@ -540,14 +540,14 @@ def octree_bench(args, soc, torch, W):
         n_pk = n_st = 0
         for k in ks:
             _, so, _ = orc.simulate_frequency(G, freqs[k], I_bg=float(I[k]), ps_pos=pos, ps_Lnu=[float(Lnu[k])],
-                                              n_bg=3_000_000, n_ps_pk=3_000_000, seed=1, iteration=1, freq_index=k,
+                                              n_bg=4_000_000, n_ps_pk=4_000_000, seed=1, iteration=1, freq_index=k,
                                               nthreads=ncpu)
             n_pk += so["packages"]
             n_st += so["cell_steps"]
         tc = time.time() - t1
         cpu = {"value": n_pk / tc, "unit": "packages/s", "cores": ncpu, "kind": "oracle",
                "cell_steps_per_s": n_st / tc,
-               "sample": f"6 x 10^6 packages at each of frequencies {ks} of the same octree and sources "
+               "sample": f"8 x 10^6 packages at each of frequencies {ks} of the same octree and sources "
                          f"(FP64 C oracle, OpenMP)"}
         log(f"oracle: {n_pk} packages in {tc:.2f}s")
     line = {"kind": "octree", "workload": "octree 64^3 root + 3 levels (4.68 M leaves), central core tau_V 100, "
