@@ -67,9 +67,9 @@ const char *soc_last_error(soc_ctx ctx);
 /* Tunables of the Monte Carlo kernels (defaults in brackets). */
 typedef enum {
     SOC_OPT_STEP_CAP = 0,        /* steps per package before it is stopped [10000000] */
-    SOC_OPT_BLOCK = 1,           /* threads per workgroup of the MC kernel, multiple of 64 in 64..512 [256] */
+    SOC_OPT_BLOCK = 1,           /* threads per workgroup of the MC kernel, multiple of 64 in 64..512 [128] */
     SOC_OPT_BLOCKS_PER_CU = 2,   /* persistent workgroups launched per compute unit [4] */
-    SOC_OPT_REFILL_MIN = 3,      /* refill a wave once this many lanes are idle, 1..64 [1] */
+    SOC_OPT_REFILL_MIN = 3,      /* refill a wave once this many lanes are idle, 1..64 [16] */
     SOC_OPT_INNER_STEPS = 4,     /* cell steps between refill checks, 1..8 [1] */
     SOC_OPT_TIMING = 5,          /* 1 = time each MC launch with HIP events [0] */
     SOC_OPT_SCATTER_MIN = 6,     /* draw new directions once this many lanes of a wave wait for one, 1..64 [1] */

@@ -29,9 +29,13 @@ struct soc_ctx_s {
     std::string err;
     int num_cus = 256;
     int64_t step_cap = 10000000;
-    int64_t block = 256;
+    // default schedule, from the autotuner on the 128^3 benchmark cloud (dust
+    // emission at three frequencies): 8 waves per compute unit, each refilled
+    // once 16 of its lanes are idle -- 374 ms per iteration against 387 ms
+    // with 16 waves per CU refilled at every idle lane
+    int64_t block = 128;
     int64_t blocks_per_cu = 4;
-    int64_t refill_min = 1;
+    int64_t refill_min = 16;
     int64_t inner_steps = 1;
     int64_t timing = 0;
     int64_t chunk = 256;
