@@ -316,7 +316,7 @@ def surrogate_gain(args, soc, torch, W):
 
 
 def reference_gain(args, soc, torch, W):
-    """Plain versus reference-field iteration (Sect. 2.1.2, 4.4) on two
+    """Plain versus reference-field iteration (Sect. 2.1.2, 3.6) on two
     clouds -- the benchmark cloud (sigma_ln 1, mean tau_V 5) and an
     optically thick one where dust self-heating takes several iterations
     (sigma_ln --target-sigma, tau_V --target-tau) -- with the benchmark's

@@ -1,4 +1,4 @@
-"""Iteration drivers (Sect. 2.1.2, 3.3, 4.4 of the paper).
+"""Iteration drivers (Sect. 2.1.2, 3.3, 3.6 of the paper).
 
 Plain method: the constant sources (external field, point sources) are
 simulated once at every frequency and their absorbed energies kept; each
@@ -155,7 +155,7 @@ class PlainSolver:
 def geometric_schedule(n_final: int, factor: float, iterations: int):
     """Packages per frequency for dust iterations 2..iterations, growing so
     that log n is linear in the iteration number, from n_final / factor at
-    iteration 2 to n_final at the last (Sect. 4.4)."""
+    iteration 2 to n_final at the last (Sect. 3.6)."""
     if iterations < 2 or factor < 1.0 or n_final < 1:
         raise ValueError("need iterations >= 2, factor >= 1, n_final >= 1")
 
