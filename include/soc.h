@@ -468,6 +468,22 @@ soc_status soc_unet_forward(soc_ctx ctx, soc_unet u, int32_t n, const float *d_x
 /* Gradients of sum(dy * y) with respect to every parameter, for the
  * inputs of the last forward call; they replace the previous gradients. */
 soc_status soc_unet_backward(soc_ctx ctx, soc_unet u, const float *d_dy);
+/* Test hooks for per-layer parity (layers indexed in parameter order,
+ * soc_unet_param_count's layout).  soc_unet_backward_to runs the backward
+ * pass of soc_unet_backward up to and including layer stop_layer (its
+ * weight gradient, and its backward-data pass where it has one) and
+ * returns; gradients of the layers not reached are left as they were.
+ * soc_unet_read copies one stored BF16 tensor of a layer to host FP32,
+ * real channels only, [n][positions][channels] for the batch n of the last
+ * forward (count must equal that size): which 0 its forward input, 1 its
+ * forward output (SOC_EINVAL for the last layer, whose output is the
+ * caller's FP32 array), 2 the output-side gradient its weight gradient and
+ * backward-data pass consumed, 3 its backward-data result (leaky-ReLU slope
+ * of the input and, for a down convolution, the skip gradient applied).
+ * 2 and 3 are defined for the layer the last backward stopped at (later
+ * layers of a full backward overwrite them).  Synchronises. */
+soc_status soc_unet_backward_to(soc_ctx ctx, soc_unet u, const float *d_dy, int32_t stop_layer);
+soc_status soc_unet_read(soc_ctx ctx, soc_unet u, int32_t layer, int32_t which, float *h_out, int64_t count);
 /* Mean of (y - t)^2 over n samples x cells x cout into *loss (host; NULL:
  * no result and no synchronisation) and its gradient 2 (y - t) / count into
  * d_dy (NULL: not written). */

@@ -1461,6 +1461,27 @@ soc_status soc_unet_backward(soc_ctx c, soc_unet u, const float *d_dy)
     return SOC_OK;
 }
 
+soc_status soc_unet_backward_to(soc_ctx c, soc_unet u, const float *d_dy, int32_t stop_layer)
+{
+    UNET_ARGS(c, u);
+    if (!d_dy) return fail(c, SOC_EINVAL, "NULL output gradient");
+    if (stop_layer < 0 || stop_layer >= u->net.layer_count())
+        return fail(c, SOC_EINVAL, "soc_unet_backward_to: layer %d outside [0, %d)", stop_layer, u->net.layer_count());
+    if (u->net.n_last_ < 1) return fail(c, SOC_ESTATE, "soc_unet_backward_to before any forward");
+    HIPCHK(c, u->net.backward(d_dy, c->stream, stop_layer));
+    return SOC_OK;
+}
+
+soc_status soc_unet_read(soc_ctx c, soc_unet u, int32_t layer, int32_t which, float *h_out, int64_t count)
+{
+    UNET_ARGS(c, u);
+    NOT_WHILE_CAPTURING(c);
+    const auto st = u->net.read(layer, which, h_out, count, c->stream);
+    if (st.code == soc::unet::Net::HIP_ERROR) return fail(c, SOC_EHIP, "soc_unet_read: %s", st.msg.c_str());
+    if (st.code != soc::unet::Net::OK) return fail(c, SOC_EINVAL, "soc_unet_read: %s", st.msg.c_str());
+    return SOC_OK;
+}
+
 soc_status soc_unet_mse(soc_ctx c, soc_unet u, int32_t n, const float *d_y, const float *d_t, float *d_dy,
                         double *loss)
 {

@@ -67,7 +67,21 @@ public:
     // x: device FP32 [n][nz][ny][nx][cin]; y: device FP32 [n][nz][ny][nx][cout]
     hipError_t forward(int32_t n, const float *d_x, float *d_y, hipStream_t s);
     // Gradients of sum(dy * y) for the last forward, into the FP32 gradient array.
-    hipError_t backward(const float *d_dy, hipStream_t s);
+    // stop_layer >= 0 (test hook): return once that layer (parameter order)
+    // has its weight gradient and, where it has one, its backward-data
+    // result, so that the tensors it consumed and produced are still intact.
+    hipError_t backward(const float *d_dy, hipStream_t s, int32_t stop_layer = -1);
+    // Test hook: copy one stored BF16 tensor of a layer (parameter order) to
+    // host FP32, real channels only, [n][positions][channels] for the batch
+    // of the last forward.  which: 0 the forward input, 1 the forward output
+    // (not stored for the last layer, whose output is the caller's FP32
+    // array), 2 the output-side gradient its weight gradient and
+    // backward-data pass consumed in the last backward, 3 its backward-data
+    // result (slope and skip gradient applied).  BAD_SHAPE when the tensor
+    // does not exist or count differs; 2 and 3 hold only for the layer a
+    // backward stopped at.
+    Status read(int32_t layer, int32_t which, float *h, int64_t count, hipStream_t s);
+    int32_t layer_count() const { return (int32_t)layers_.size(); }
     // Mean squared error of y against t over n samples (host FP64 result
     // when h_loss is non-NULL; synchronises), and its gradient into d_dy.
     hipError_t mse(int32_t n, const float *d_y, const float *d_t, float *d_dy, double *h_loss, hipStream_t s);
@@ -95,6 +109,8 @@ private:
     int64_t positions(int level, int32_t n) const;
 
     std::vector<Layer> layers_;
+    // views each layer used in the last forward / backward (read hook)
+    std::vector<View> fin_, fout_, bdy_, bdx_;
     int64_t nparam_ = 0;
     float *d_params_ = nullptr, *d_grads_ = nullptr, *d_m_ = nullptr, *d_v_ = nullptr;
     float *d_part_ = nullptr;   // split-K weight-gradient partials

@@ -1219,14 +1219,22 @@ hipError_t Net::forward(int32_t n, const float *d_x, float *d_y, hipStream_t s)
     auto chk = [&](hipError_t r) {
         if (r != hipSuccess && e == hipSuccess) e = r;
     };
+    fin_.assign(layers_.size(), View{});
+    fout_.assign(layers_.size(), View{});
+    auto conv = [&](const View &x, const View &y, float *yf, int32_t yf_cs) {
+        fin_[li] = x;
+        fout_[li] = y;
+        chk(conv_fwd(layers_[li], n, x, y, yf, yf_cs, s));
+        ++li;
+    };
     for (int l = 0; l < Lv; ++l) {
         const View a{ha_[l], ch[l], 0, ch[l]};
-        chk(conv_fwd(layers_[li++], n, h, a, nullptr, 0, s));
+        conv(h, a, nullptr, 0);
         const View bo = l < Lv - 1 ? View{cat_[l], 2 * ch[l], 0, ch[l]} : View{hbot_, ch[l], 0, ch[l]};
-        chk(conv_fwd(layers_[li++], n, a, bo, nullptr, 0, s));
+        conv(a, bo, nullptr, 0);
         if (l < Lv - 1) {
             const View d{hd_[l + 1], ch[l + 1], 0, ch[l + 1]};
-            chk(conv_fwd(layers_[li++], n, bo, d, nullptr, 0, s));
+            conv(bo, d, nullptr, 0);
             h = d;
         }
     }
@@ -1234,21 +1242,23 @@ hipError_t Net::forward(int32_t n, const float *d_x, float *d_y, hipStream_t s)
     for (int l = Lv - 2; l >= 0; --l) {
         const View uin = top;
         const View cat{cat_[l], 2 * ch[l], 0, 2 * ch[l]};
-        chk(conv_fwd(layers_[li++], n, uin, cat.at(ch[l], ch[l]), nullptr, 0, s));
+        conv(uin, cat.at(ch[l], ch[l]), nullptr, 0);
         const View qa{hqa_[l], ch[l], 0, ch[l]};
-        chk(conv_fwd(layers_[li++], n, cat, qa, nullptr, 0, s));
+        conv(cat, qa, nullptr, 0);
         const View qb{hqb_[l], ch[l], 0, ch[l]};
-        chk(conv_fwd(layers_[li++], n, qa, qb, nullptr, 0, s));
+        conv(qa, qb, nullptr, 0);
         top = qb;
     }
-    chk(conv_fwd(layers_[li++], n, top, View{}, d_y, cout_, s));
+    conv(top, View{}, d_y, cout_);
     return e;
 }
 
-hipError_t Net::backward(const float *d_dy, hipStream_t s)
+hipError_t Net::backward(const float *d_dy, hipStream_t s, int32_t stop_layer)
 {
     const int32_t n = n_last_;
     if (n < 1 || !d_dy) return hipErrorInvalidValue;
+    bdy_.assign(layers_.size(), View{});
+    bdx_.assign(layers_.size(), View{});
     const int Lv = levels_;
     std::vector<int32_t> ch(Lv);
     for (int l = 0; l < Lv; ++l) ch[l] = base_ << l;
@@ -1271,49 +1281,98 @@ hipError_t Net::backward(const float *d_dy, hipStream_t s)
     }
     const size_t out = li;
 
+    // a layer is done once its weight gradient and (if any) backward-data
+    // pass are enqueued; stop_layer ends the pass there (test hook)
+    bool stop = false;
+    auto wgrad = [&](size_t li, const View &x, const View &dy) {
+        bdy_[li] = dy;
+        chk(conv_wgrad(layers_[li], n, x, dy, s));
+        if ((int32_t)li == stop_layer && li == ea[0]) stop = true;
+    };
+    auto bdata = [&](size_t li, const View &dy, const View &slope, const View *add, const View &dx) {
+        bdx_[li] = dx;
+        chk(conv_bwd_data(layers_[li], n, dy, slope, add, dx, s));
+        if ((int32_t)li == stop_layer) stop = true;
+    };
     const int64_t P0 = positions(0, n);
     hipLaunchKernelGGL(to_bf16_padded_kernel, dim3(nblk(P0 * cout_pad_)), dim3(256), 0, s, d_dy, cout_, cout_pad_,
                        P0, d_gy_);
     const View top = Lv == 1 ? View{hbot_, ch[0], 0, ch[0]} : View{hqb_[0], ch[0], 0, ch[0]};
     const View gy{d_gy_, cout_pad_, 0, cout_pad_};
-    chk(conv_wgrad(layers_[out], n, top, gy, s));
+    wgrad(out, top, gy);
     View g{g1_[0], ch[0], 0, ch[0]};
-    chk(conv_bwd_data(layers_[out], n, gy, top, nullptr, g, s));
+    bdata(out, gy, top, nullptr, g);
+    if (stop) return e;
     for (int l = 0; l < Lv - 1; ++l) {
         const View hqa{hqa_[l], ch[l], 0, ch[l]};
         const View cat{cat_[l], 2 * ch[l], 0, 2 * ch[l]};
         const View uin = l == Lv - 2 ? View{hbot_, ch[l + 1], 0, ch[l + 1]} : View{hqb_[l + 1], ch[l + 1], 0, ch[l + 1]};
-        chk(conv_wgrad(layers_[qb[l]], n, hqa, g, s));
+        wgrad(qb[l], hqa, g);
         const View g2{g2_[l], ch[l], 0, ch[l]};
-        chk(conv_bwd_data(layers_[qb[l]], n, g, hqa, nullptr, g2, s));
-        chk(conv_wgrad(layers_[qa[l]], n, cat, g2, s));
+        bdata(qb[l], g, hqa, nullptr, g2);
+        if (stop) return e;
+        wgrad(qa[l], cat, g2);
         const View gc{gcat_[l], 2 * ch[l], 0, 2 * ch[l]};
-        chk(conv_bwd_data(layers_[qa[l]], n, g2, cat, nullptr, gc, s));
+        bdata(qa[l], g2, cat, nullptr, gc);
+        if (stop) return e;
         const View gu = gc.at(ch[l], ch[l]);
-        chk(conv_wgrad(layers_[up[l]], n, uin, gu, s));
+        wgrad(up[l], uin, gu);
         const View gn{g1_[l + 1], ch[l + 1], 0, ch[l + 1]};
-        chk(conv_bwd_data(layers_[up[l]], n, gu, uin, nullptr, gn, s));
+        bdata(up[l], gu, uin, nullptr, gn);
+        if (stop) return e;
         g = gn;
     }
     for (int l = Lv - 1; l >= 0; --l) {
         const View ha{ha_[l], ch[l], 0, ch[l]};
-        chk(conv_wgrad(layers_[eb[l]], n, ha, g, s));
+        wgrad(eb[l], ha, g);
         const View ga{g2_[l], ch[l], 0, ch[l]};
-        chk(conv_bwd_data(layers_[eb[l]], n, g, ha, nullptr, ga, s));
+        bdata(eb[l], g, ha, nullptr, ga);
+        if (stop) return e;
         const View in = l == 0 ? View{d_xin_, cin_pad_, 0, cin_pad_} : View{hd_[l], ch[l], 0, ch[l]};
-        chk(conv_wgrad(layers_[ea[l]], n, in, ga, s));
+        wgrad(ea[l], in, ga);
+        if (stop) return e;
         if (l > 0) {
             const View gd{g1_[l], ch[l], 0, ch[l]};
-            chk(conv_bwd_data(layers_[ea[l]], n, ga, in, nullptr, gd, s));
+            bdata(ea[l], ga, in, nullptr, gd);
+            if (stop) return e;
             const View skip{cat_[l - 1], 2 * ch[l - 1], 0, ch[l - 1]};
-            chk(conv_wgrad(layers_[dn[l - 1]], n, skip, gd, s));
+            wgrad(dn[l - 1], skip, gd);
             const View gskip{gcat_[l - 1], 2 * ch[l - 1], 0, ch[l - 1]};
             const View gp{g1_[l - 1], ch[l - 1], 0, ch[l - 1]};
-            chk(conv_bwd_data(layers_[dn[l - 1]], n, gd, skip, &gskip, gp, s));
+            bdata(dn[l - 1], gd, skip, &gskip, gp);
+            if (stop) return e;
             g = gp;
         }
     }
     return e;
+}
+
+Net::Status Net::read(int32_t layer, int32_t which, float *h, int64_t count, hipStream_t s)
+{
+    if (layer < 0 || layer >= (int32_t)layers_.size() || which < 0 || which > 3 || !h || n_last_ < 1)
+        return {BAD_SHAPE, "bad layer, tensor or state"};
+    const Layer &L = layers_[layer];
+    const std::vector<View> &vs = which == 0 ? fin_ : which == 1 ? fout_ : which == 2 ? bdy_ : bdx_;
+    if ((size_t)layer >= vs.size() || !vs[layer].p) return {BAD_SHAPE, "tensor not stored"};
+    const View v = vs[layer];
+    // input-side tensors (forward input, backward-data result) live at the
+    // input level with cin channels, output-side ones at the output level
+    const bool in_side = which == 0 || which == 3;
+    const int32_t c = in_side ? L.cin : L.cout;
+    const int64_t npos = positions(in_side ? L.level_in : L.level_out, n_last_);
+    if (c > v.c || count != npos * c) return {BAD_SHAPE, "count does not match the tensor"};
+    std::vector<uint16_t> tmp((size_t)(npos * v.cs));
+    hipError_t e = hipMemcpyAsync(tmp.data(), v.p, tmp.size() * sizeof(uint16_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return {HIP_ERROR, hipGetErrorString(e)};
+    for (int64_t p = 0; p < npos; ++p)
+        for (int32_t j = 0; j < c; ++j) {
+            const uint32_t bits = (uint32_t)tmp[(size_t)(p * v.cs + v.co + j)] << 16;
+            float f;
+            std::memcpy(&f, &bits, sizeof f);
+            h[p * c + j] = f;
+        }
+    return {OK, ""};
 }
 
 hipError_t Net::mse(int32_t n, const float *d_y, const float *d_t, float *d_dy, double *h_loss, hipStream_t s)

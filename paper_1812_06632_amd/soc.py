@@ -575,6 +575,8 @@ _lib.soc_unet_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
 _lib.soc_unet_backward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.soc_unet_mse.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                               C.POINTER(C.c_double)]
+_lib.soc_unet_backward_to.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]
+_lib.soc_unet_read.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64]
 _lib.soc_unet_adam.argtypes = [C.c_void_p, C.c_void_p, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32]
 
 
@@ -634,6 +636,19 @@ class UNet:
 
     def backward(self, dy: torch.Tensor):
         self.ctx.check(_lib.soc_unet_backward(self.ctx.h, self.h, self._check_x(dy, self.cout, "dy")))
+
+    def backward_to(self, dy: torch.Tensor, layer: int):
+        """Backward pass up to and including one layer (parameter order)."""
+        self.ctx.check(_lib.soc_unet_backward_to(self.ctx.h, self.h, self._check_x(dy, self.cout, "dy"), int(layer)))
+
+    def read(self, layer: int, which: int, n: int, positions: int, channels: int) -> np.ndarray:
+        """A stored tensor of one layer as FP32 [n * positions, channels]
+        (which: 0 forward input, 1 forward output, 2 output-side gradient,
+        3 backward-data result)."""
+        a = np.empty((n * positions, channels), np.float32)
+        self.ctx.check(_lib.soc_unet_read(self.ctx.h, self.h, int(layer), int(which), a.ctypes.data_as(C.c_void_p),
+                                          C.c_int64(a.size)))
+        return a
 
     def mse(self, y: torch.Tensor, t: torch.Tensor, grad: bool = True, loss: bool = True):
         """(loss or None, dy or None)."""

@@ -2,7 +2,7 @@
 
 The network's weights and inputs are rounded to BF16 before both sides see
 them, so the two compute the same function; what remains is the BF16
-rounding of the stored activations and gradients (relative 2^-9 per
+rounding of the stored activations and gradients (relative 2^-8 per
 rounding) and FP32 summation order.  Two references:
 
 * the FP64 oracle itself;
@@ -18,11 +18,17 @@ they amplify the storage error itself.  The device must therefore be no
 farther from the storage model than the model is from the FP64 oracle,
 and its own distance from the oracle at most twice the model's (plus
 5e-3 for tensors the model reproduces almost exactly): a layout or
-indexing mistake gives O(1) errors and fails both."""
+indexing mistake gives O(1) errors and fails both.
+
+Those norms are a diagnostic of the whole network.  The parity bar is per
+layer and per element: each layer's stored output, backward-data result
+and parameter gradients against the FP64 oracle's layer applied to the
+device's own stored inputs, within the rounding bounds derived below."""
 import numpy as np
 import pytest
 
 from oracle import unet_oracle as U
+from tests.unet_parity import bf16_round, check_backward_layers, check_forward_layers, print_rows
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -34,14 +40,6 @@ def soc():
         pytest.fail("GPU tests need a GPU")
     from paper_1812_06632_amd import soc as m
     return m
-
-
-def bf16_round(a):
-    """Round FP32/FP64 values to the nearest BF16 (ties to even), as FP64."""
-    f = np.ascontiguousarray(a, dtype=np.float32)
-    u = f.view(np.uint32).astype(np.uint64)
-    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
-    return (u.astype(np.uint32)).view(np.float32).astype(np.float64)
 
 
 def flat(P):
@@ -160,6 +158,12 @@ def test_forward_and_gradients_match_oracle(soc, levels, base, n, shape):
     bad = [(name, a, b, c) for name, a, b, c in rows if not (a <= c + 5e-3 and b <= 2.0 * c + 5e-3)]
     assert not bad, bad
     assert rows[0][2] < 1e-2   # forward within 1e-2 of the FP64 oracle
+    # per layer and per element, on the device's own stored tensors
+    dyt = torch.from_numpy(dy.astype(np.float32)).cuda()
+    net.forward(xt)
+    rep = check_forward_layers(net, P, n, shape, 2, 2, base, levels, y)
+    rep += check_backward_layers(net, P, dyt, n, shape, 2, 2, base, levels)
+    print_rows(rep)
     ctx.close()
 
 
@@ -259,4 +263,28 @@ def test_forward_at_full_size(soc):
     a, b = rel(y[j:j + 1], ym), rel(y[j:j + 1], yo)
     print(f"\nfull-size forward, sample {j}: dev-vs-model {a:.2e}, dev-vs-oracle {b:.2e}, model-vs-oracle {rel(ym, yo):.2e}")
     assert a < 5e-3 and b < 1e-2
+    # every layer, element by element, on sample j (and the batch offsets of
+    # the other samples through the output layer)
+    rep = check_forward_layers(net, P, 4, (64, 64, 64), N_FEATURES, 1, 32, 4, y, samples=[j])
+    print_rows(rep)
+    ctx.close()
+
+
+def test_backward_at_full_size(soc):
+    """The same network and batch: the weight and bias gradients of the
+    output layer, the first layer, the first layer of level 1 and the
+    level-0 down convolution over the whole batch, and their backward-data
+    results on one sample (the down convolution's with the skip gradient
+    added), per element against the FP64 reductions over the device's own
+    stored tensors."""
+    from paper_1812_06632_amd.surrogate import N_FEATURES
+    P, x, dy = _case(4, 32, 4, (64, 64, 64), cin=N_FEATURES, cout=1, seed=5)
+    ctx = soc.Context(0)
+    net = soc.UNet(ctx, N_FEATURES, 1, 32, 4, 4, (64, 64, 64))
+    net.set_params(flat(P).astype(np.float32))
+    net.forward(torch.from_numpy(x.astype(np.float32)).cuda())
+    dyt = torch.from_numpy(dy.astype(np.float32)).cuda()
+    rep = check_backward_layers(net, P, dyt, 4, (64, 64, 64), N_FEATURES, 1, 32, 4,
+                                layers={"out", "e1a", "d0", "e0a"}, dx_samples=[1])
+    print_rows(rep)
     ctx.close()

@@ -137,3 +137,42 @@ def test_unet_gradient_finite_differences():
         lm = loss_of()
         b[j] = old
         assert G[name][1][j] == pytest.approx((lp - lm) / (2 * eps), rel=1e-5, abs=1e-9), name
+
+
+# ---------------------------------------------------------------- the GPU parity checks themselves
+def _storage_case(plant=None):
+    from tests.unet_parity import Bf16StorageNet, bf16_round
+    levels, base, n, shape = 2, 16, 2, (8, 8, 8)
+    rng = np.random.default_rng(0)
+    P = U.init_params(2, 2, base, levels, 0)
+    P = {k: (bf16_round(w), bf16_round(0.05 * rng.standard_normal(b.shape))) for k, (w, b) in P.items()}
+    x = bf16_round(rng.standard_normal((n,) + shape + (2,)))
+    dy = bf16_round(rng.standard_normal((n,) + shape + (2,)))
+    net = Bf16StorageNet(P, 2, 2, base, levels, shape, plant=plant)
+    y = net.forward(x)
+    return net, P, y, dy, (n, shape, 2, 2, base, levels)
+
+
+def test_per_element_checks_accept_bf16_storage():
+    """The per-layer, per-element bounds the GPU parity tests apply hold for
+    a network that rounds exactly where the device stores tensors."""
+    from tests.unet_parity import check_backward_layers, check_forward_layers
+    net, P, y, dy, (n, shape, ci, co, base, levels) = _storage_case()
+    rows = check_forward_layers(net, P, n, shape, ci, co, base, levels, y)
+    rows += check_backward_layers(net, P, dy, n, shape, ci, co, base, levels)
+    assert len(rows) == 4 * 9 - 1   # 9 layers: forward, weight, bias, backward-data (none for e0a)
+    fwd = [r for (_, what, r, _) in rows if what == "forward"]
+    assert max(fwd) > 0.05   # the BF16 term is exercised, not vacuous
+
+
+@pytest.mark.parametrize("plant", [("e0b", "forward"), ("u0", "forward"), ("q0a", "wgrad"), ("e1a", "wgrad"),
+                                   ("d0", "dx"), ("q0b", "dx")])
+def test_per_element_checks_reject_an_indexing_mistake(plant):
+    """A one-row shift of one layer's output or backward-data result, or a
+    dropped tap in one weight gradient, fails the check of that layer."""
+    from tests.unet_parity import check_backward_layers, check_forward_layers
+    net, P, y, dy, (n, shape, ci, co, base, levels) = _storage_case(plant)
+    with pytest.raises(AssertionError) as e:
+        check_forward_layers(net, P, n, shape, ci, co, base, levels, y)
+        check_backward_layers(net, P, dy, n, shape, ci, co, base, levels)
+    assert e.value.args[0][0] == plant[0]
