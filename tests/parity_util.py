@@ -67,17 +67,65 @@ def batch_z(gpu_batches, orc_batches):
     return z, mg, mo, 2 * B - 2
 
 
-def check_z(z, mg, mo, dof, label):
-    """Parity criteria on selected cells: |mean z| < 0.1, std z within 0.1
-    of the Student-t value, KS p > 1e-3 against t(dof), aggregate relative
-    bias sum(mg - mo) / sum(mo) below 0.3%."""
+def relative_bias(gpu_batches, orc_batches, sel):
+    """Unweighted mean over the selected cells of the symmetric relative
+    difference 2 (mg - mo) / (mg + mo), and its standard error.
+
+    The symmetric form has expectation zero when both sides sample the same
+    distribution (dividing by the noisy oracle mean alone would be biased
+    upwards by its relative variance).  The standard error comes from the
+    batches, which are independent: the per-cell differences are not (one
+    package deposits along its whole path), so a per-cell standard error
+    would understate it several times on large grids."""
+    g = np.asarray(gpu_batches)[:, sel]
+    o = np.asarray(orc_batches)[:, sel]
+    m = 0.5 * (g.mean(0) + o.mean(0))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        sg = (g / m).mean(1)
+        so = (o / m).mean(1)
+    B = g.shape[0]
+    return float(sg.mean() - so.mean()), float(math.sqrt(sg.var(ddof=1) / B + so.var(ddof=1) / B))
+
+
+KS_CELLS = 2000   # cells in the KS test; a random subset when more are selected
+
+
+def check_z(gpu_batches, orc_batches, hits, label):
+    """Parity criteria over the cells with more than 10^3 hits (summed over
+    the batches):
+      * per-cell z-scores: |mean z| < 0.1, std z within 0.1 of the
+        Student-t value, KS p > 1e-3 against t(dof) on at most KS_CELLS
+        cells drawn at random (neighbouring cells share packages, so
+        their z-scores are correlated and a KS test over tens of
+        thousands of cells rejects even the oracle against itself);
+      * aggregate relative bias sum(mg - mo) / sum(mo) below 0.3%;
+      * unweighted mean relative bias (relative_bias) below 0.3% plus
+        three of its standard errors, over these cells and over the cells
+        with more than 10^4 hits.  The standard error is printed: where
+        it is well below 0.3% (the full-size clouds) the check is a 0.3%
+        bound; on small grids a few bright cells make the batch-to-batch
+        fluctuations of the mean larger, and the check is what the sample
+        can resolve."""
     from scipy import stats
+    z, mg, mo, dof = batch_z(gpu_batches, orc_batches)
+    B = dof // 2 + 1
+    sel = hits * B > 1000
+    assert sel.sum() >= 100, f"{label}: only {sel.sum()} well-sampled cells"
+    zs = z[sel]
     t_std = math.sqrt(dof / (dof - 2.0))
-    p = stats.kstest(z, stats.t(dof).cdf).pvalue
-    bias = float(np.sum(mg - mo) / np.sum(mo))
-    print(f"\n{label}: {z.size} cells, z mean {z.mean():.3f} std {z.std():.3f} (t std {t_std:.3f}) "
-          f"KS p {p:.3g} bias {bias:.2e}")
-    assert abs(z.mean()) < 0.1
-    assert abs(z.std() - t_std) < 0.1
+    rng = np.random.default_rng(12345)
+    zk = zs if zs.size <= KS_CELLS else rng.choice(zs, KS_CELLS, replace=False)
+    p = stats.kstest(zk, stats.t(dof).cdf).pvalue
+    agg = float(np.sum(mg[sel] - mo[sel]) / np.sum(mo[sel]))
+    b3, se3 = relative_bias(gpu_batches, orc_batches, sel)
+    sel4 = hits * B > 10000
+    b4, se4 = relative_bias(gpu_batches, orc_batches, sel4) if sel4.sum() >= 50 else (0.0, 0.0)
+    print(f"\n{label}: {zs.size} cells, z mean {zs.mean():.3f} std {zs.std():.3f} (t std {t_std:.3f}) "
+          f"KS p {p:.3g} ({zk.size} cells); aggregate bias {agg:.2e}; mean relative bias {b3:.2e} +- {se3:.1e} "
+          f"(> 10^3 hits), {b4:.2e} +- {se4:.1e} ({int(sel4.sum())} cells > 10^4 hits)")
+    assert abs(zs.mean()) < 0.1
+    assert abs(zs.std() - t_std) < 0.1
     assert p > 1e-3
-    assert abs(bias) < 3e-3
+    assert abs(agg) < 3e-3
+    assert abs(b3) < 3e-3 + 3.0 * se3
+    assert abs(b4) < 3e-3 + 3.0 * se4

@@ -24,6 +24,13 @@ Passes compared:
     solves from the constant sources (the first dust iteration);
   * on the octree, 10^6 packages at 0.55 and 250 um.
 
+Independent seeds, 32 batches per side (per-cell z-scores and relative
+bias over the cells with > 10^3 hits):
+  * the benchmark cloud's luminosity-weighted dust emission at 10 um,
+    10^5 packages per batch;
+  * the octree at 0.55 um, external field and the embedded source,
+    5 x 10^4 packages each per batch.
+
 Further checks:
   * a GPU pass with the full 10^7 packages per frequency on the octree
     conserves energy and emits the oracle's total;
@@ -36,6 +43,7 @@ import pytest
 
 from oracle import orc
 from paper_1812_06632_amd import workloads as W
+from tests.parity_util import check_z
 
 pytestmark = pytest.mark.gpu
 
@@ -145,6 +153,28 @@ def test_benchmark_cloud_dust_emission_same_seed(soc, ctx, bench_cloud, lam_um):
                dust_mode=1, seed=9, iteration=2, freq_index=k)
 
 
+def test_benchmark_cloud_dust_emission_independent_seeds(soc, ctx, bench_cloud):
+    """32 independent batches per side of the weighted dust emission at
+    10 um (10^5 packages each) at the constant-source temperatures: per-cell
+    z-scores and relative bias over the well-sampled cells."""
+    P, S = bench_cloud
+    k = _k_at(P.nu, 10.0)
+    T = S.T.cpu().numpy()
+    kw = dict(n_dust=100_000, dust_mode=1, iteration=2, freq_index=k)
+    B = 32
+    gb, ob = [], []
+    hits = np.zeros(P.grid.ncells, np.int64)
+    for b in range(B):
+        A = torch.zeros(P.grid.ncells, dtype=torch.float64, device="cuda")
+        soc.simulate_frequency(ctx, S.grid, S.freqs[k], A, T=S.T, seed=2000 + b, **kw)
+        gb.append(A.cpu().numpy())
+    for b in range(B):
+        Ao, _, _ = orc.simulate_frequency(P.grid, S.freqs[k], T=T, seed=7000 + b, nthreads=16,
+                                          hits=hits if b == 0 else None, **kw)
+        ob.append(Ao)
+    check_z(gb, ob, hits, "128^3 dust emission at 10 um, independent seeds")
+
+
 def test_benchmark_cloud_temperature_sample(soc, ctx, bench_cloud):
     P, S = bench_cloud
     A = S.A_const.cpu().numpy()
@@ -188,6 +218,27 @@ def test_octree_same_seed(soc, ctx, octree_cloud, lam_um):
     f = (float(nu[k]), float(w[k]), float(sabs[k]), float(ssca[k]), float(gg[k]))
     _same_seed(soc, ctx, g, G, f, f"octree, {lam_um} um", n_bg=500_000, n_ps_pk=500_000, seed=5, iteration=1,
                freq_index=k, **_octree_sources(nu, k))
+
+
+def test_octree_independent_seeds(soc, ctx, octree_cloud):
+    """32 independent batches per side at 0.55 um (external field and the
+    embedded source, 5 x 10^4 packages each per batch): per-cell z-scores
+    and relative bias over the well-sampled leaves."""
+    G, g, nu, w, sabs, ssca, gg, _ = octree_cloud
+    k = _k_at(nu, 0.55)
+    f = (float(nu[k]), float(w[k]), float(sabs[k]), float(ssca[k]), float(gg[k]))
+    kw = dict(n_bg=50_000, n_ps_pk=50_000, iteration=1, freq_index=k, **_octree_sources(nu, k))
+    B = 32
+    gb, ob = [], []
+    hits = np.zeros(G.ncells, np.int64)
+    for b in range(B):
+        A = torch.zeros(G.ncells, dtype=torch.float64, device="cuda")
+        soc.simulate_frequency(ctx, g, f, A, seed=2000 + b, **kw)
+        gb.append(A.cpu().numpy())
+    for b in range(B):
+        Ao, _, _ = orc.simulate_frequency(G, f, seed=7000 + b, nthreads=16, hits=hits if b == 0 else None, **kw)
+        ob.append(Ao)
+    check_z(gb, ob, hits, "octree at 0.55 um, independent seeds")
 
 
 def test_octree_full_package_count_and_temperatures(soc, ctx, octree_cloud):
