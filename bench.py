@@ -10,9 +10,16 @@ packages per frequency) once and keeps their absorbed energy.  Every later
 iteration -- one benchmark step -- re-simulates the dust emission at the
 current temperatures (10^6 luminosity-weighted packages per frequency, all
 64 frequencies) on top of the kept absorption and solves the temperatures.
-Steps are the iterations of the plain method "iterate T to 1% change";
-after the timed steps the run continues to the 1% stopping rule and
-reports the wall time to convergence.
+Steps are the iterations of the plain method "iterate T to 1% change".
+
+Time to 1% temperature convergence (the paper's two statistics of
+Sect. 3.3, taken against a reference field): T_ref is the mean temperature
+of the timed iterations.  Two more runs with the same seed, and so the
+same constant-source pass, are then timed from their constant pass to the
+first iteration within 1% of T_ref over all cells and over the hottest 5%:
+the plain method, and the learned start, whose U-Net is trained in this
+run on clouds the plain method solves here (its data and training seconds
+are reported beside it).
 
 Prints one JSON line (rank 0, N = 1 only).
 """
@@ -96,13 +103,17 @@ def ceilings(soc, torch, ncells):
     ctx = soc.Context(0)
     blocks, threads, per = 4096, 256, 64
     a = torch.zeros(8 * ncells, dtype=torch.float64, device="cuda")
-    names = {0: "random, one shared array", 1: "random, one private copy per XCD (hardware XCC id)",
-             2: "wave-coalesced 64-double blocks", 3: "random in a 4096-double LDS array"}
-    for mode, label in names.items():
-        soc.ubench(ctx, 0, a, None, ncells, per, mode, blocks, threads)
-        ms = min(soc.ubench(ctx, 0, a, None, ncells, per, mode, blocks, threads) for _ in range(3))
-        print(json.dumps({"kind": "fp64_atomic_add", "mode": mode, "pattern": label, "array_doubles": ncells,
-                          "ms": ms, "per_s": blocks * threads * per / (ms * 1e-3)}), flush=True)
+    names = {0: "FP64, random, one shared array", 1: "FP64, random, one private copy per XCD (hardware XCC id)",
+             2: "FP64, wave-coalesced 64-double blocks", 3: "FP64, random in a 4096-double LDS array",
+             4: "FP32, random, one shared array", 5: "uint64, random, one shared array",
+             6: "uint32, random, one shared array"}
+    for n_el in sorted({ncells, 1 << 15}, reverse=True):
+        for mode, label in names.items():
+            a.zero_()
+            soc.ubench(ctx, 0, a, None, n_el, per, mode, blocks, threads)
+            ms = min(soc.ubench(ctx, 0, a, None, n_el, per, mode, blocks, threads) for _ in range(3))
+            print(json.dumps({"kind": "atomic_add", "mode": mode, "pattern": label, "array_elems": n_el,
+                              "ms": ms, "per_s": blocks * threads * per / (ms * 1e-3)}), flush=True)
     w = torch.randint(0, 2**31 - 1, (ncells,), dtype=torch.int32, device="cuda")
     out = torch.zeros(4, dtype=torch.int32, device="cuda")
     for nb in (4096, 16384):
@@ -215,103 +226,142 @@ def unet_step(args, soc, torch):
 
 
 def surrogate_gain(args, soc, torch, W):
-    """Time to the 1% stopping rule on an optically thick lognormal cloud
-    (the benchmark's frequencies, package counts and sources with
-    sigma_ln = --target-sigma and mean tau_V = --target-tau, where dust
-    self-heating needs several iterations), at the network's own 64^3 and
-    at the benchmark's n^3, from three starts -- the plain method
-    (constant-source temperatures), the U-Net prediction, and a constant
-    temperature (control: shows what the learning adds) -- and the error of
-    the stopped field against a long plain reference (mean of 8 iterations
-    after 12)."""
-    from paper_1812_06632_amd.driver import PlainSolver
-    from paper_1812_06632_amd.surrogate import Surrogate, make_dataset
+    """The learned start on a thick cloud (sigma_ln --target-sigma, mean
+    tau_V --target-tau, --target-n^3 cells, the benchmark's frequencies and
+    sources, --target-packages per frequency and iteration).
+
+    Training: --train-clouds random 64^3 clouds of the training family
+    solved by the plain method here (plus --val-clouds held out); the
+    two-output U-Net is trained on them, and, for a learning curve, on
+    subsets of them (--curve), each scored on the held-out clouds.
+
+    Target runs, each timed from its constant pass to the first iteration
+    within 1% of T_ref (mean |T - T_ref| / T_ref over all cells with dust
+    and over the hottest 5%); T_ref is the mean of --ref-avg plain
+    iterations after --ref-burn, with the same seed and hence the same
+    constant-source pass:
+      plain        plain iterations from the constant-source temperatures;
+      mode_A       plain iterations from the network's temperatures;
+      mode_B       reference-field iterations (Sect. 2.1.2, running mean of
+                   whole-emission estimates) seeded with the network's
+                   temperatures and absorbed energies, the prediction
+                   counted as one iteration's packages;
+      reference    the same reference-field iterations without the network;
+      control      plain iterations from T1 times the training set's mean
+                   ratio T / T1 (no learning: what a global correction
+                   gives).
+    Every run also reports where the plain stopping rule (change between
+    iterations below 1%) fires and its error there: the plain method as
+    the judge of the prediction."""
+    from paper_1812_06632_amd.driver import PlainSolver, ReferenceFieldSolver
+    from paper_1812_06632_amd.surrogate import Surrogate, make_dataset, Y_SCALE
     ctx = soc.Context(0)
+    S = 64
     t0 = time.time()
-    X, Y = make_dataset(ctx, args.train_clouds, seed=11, n=64, S=64, K=32, packages=200_000, log=log)
-    Y_logT = X[..., 3].astype(np.float64) * 0.5 + 1.5 + Y[..., 0]   # log10 T of the training clouds
+    X, Y = make_dataset(ctx, args.train_clouds + args.val_clouds, seed=11, n=64, S=S, K=32,
+                        packages=args.train_packages, log=log)
     t_data = time.time() - t0
-    sur = Surrogate(ctx, S=64, base=32, levels=4, batch=4, seed=3)
-    t0 = time.time()
-    losses = sur.fit(X, Y, steps=args.train_steps, lr=5e-4, log=log)
+    ntr = args.train_clouds
+    Xv, Yv = X[ntr:], Y[ntr:]
+    mean_ratio = float(Y[:ntr, ..., 0].mean().item()) * Y_SCALE   # training-set mean log10(T / T1)
+
+    def val_loss(sur):
+        """Mean squared error per output channel on the held-out clouds."""
+        se = torch.zeros(Y.shape[-1], dtype=torch.float64, device="cuda")
+        for i in range(0, Xv.shape[0], 4):
+            y = sur.net.forward(Xv[i:i + 4].contiguous())
+            se += ((y - Yv[i:i + 4]) ** 2).double().sum(dim=(0, 1, 2, 3))
+        return (se / (Yv.numel() / Yv.shape[-1])).tolist()
+
+    curve = []
+    for n_sub in sorted({int(v) for v in args.curve.split(",") if v} | {ntr}):
+        if n_sub > ntr:
+            continue
+        sur = Surrogate(ctx, S=S, base=32, levels=4, batch=4, seed=3)
+        t0 = time.time()
+        losses = sur.fit(X[:n_sub], Y[:n_sub], steps=args.train_steps, lr=5e-4,
+                         log=log if n_sub == ntr else None)
+        torch.cuda.synchronize()
+        t_train = time.time() - t0
+        vl = val_loss(sur) if Xv.shape[0] else None
+        curve.append({"clouds": n_sub, "train_s": t_train, "final_loss": losses[-1][1] if losses else None,
+                      "val_mse_T": vl[0] if vl else None, "val_mse_A": vl[1] if vl else None})
+        log(f"learning curve: {n_sub} clouds, val mse {vl}")
+        if n_sub == ntr:
+            net = sur
+        else:
+            sur.close()
+    del X, Y, Xv, Yv
+
+    n = args.target_n
+    P = W.lognormal_problem(n=n, K=args.freqs, sigma_ln=args.target_sigma, tau_v_mean=args.target_tau,
+                            packages_per_freq=args.target_packages)
+    rho = P.grid.density().reshape(n, n, n).astype(np.float64)
+    tau_max = float(max((rho.sum(axis=a)).max() for a in range(3)) * W.SIGMA_V * P.grid.root_cell_cm)
+    del rho
+    ref = PlainSolver(ctx, P, seed=1)
     torch.cuda.synchronize()
-    t_train = time.time() - t0
-    def gain(n):
-        """The three starts on the thick cloud at n^3 (the network runs at
-        64^3; a finer grid is block-averaged in and interpolated out)."""
-        P = W.lognormal_problem(n=n, K=args.freqs, sigma_ln=args.target_sigma, tau_v_mean=args.target_tau,
-                                packages_per_freq=args.packages)
-        ref = PlainSolver(ctx, P, seed=7)
-        ref.constant_pass()
-        burn, avg = 12, 8
-        acc = torch.zeros_like(ref.T, dtype=torch.float64)
-        for it in range(2, burn + avg + 2):
-            ref.dust_iteration(it)
-            if it > burn + 1:
-                acc += ref.T.double()
-        T_ref = acc / avg
-        dense = torch.from_numpy(P.grid.density()).cuda() > 0
-        Tr = T_ref[dense]
-        hot = Tr >= torch.quantile(Tr.float(), 0.95).double()
-        log(f"{n}^3 reference: <T> {Tr.mean().item():.3f} K, hottest 5% {Tr[hot].mean().item():.3f} K")
+    t0 = time.time()
+    ref.constant_pass()
+    acc = torch.zeros(P.grid.ncells, dtype=torch.float64, device="cuda")
+    for it in range(2, args.ref_burn + args.ref_avg + 2):
+        ref.dust_iteration(it)
+        if it > args.ref_burn + 1:
+            acc += ref.T
+    T_ref = (acc / args.ref_avg).float()
+    t_ref = time.time() - t0
+    dense = torch.from_numpy(P.grid.density()).cuda() > 0
+    crit = RefCriterion(torch, T_ref, dense)
+    del ref, acc
+    log(f"{n}^3 reference ({args.ref_burn} + {args.ref_avg} iterations, {t_ref:.1f}s): <T> "
+        f"{crit.Tr.mean().item():.3f} K, hottest 5% {crit.Tr[crit.hot].mean().item():.3f} K")
 
-        def err(T):
-            r = (T.double()[dense] - Tr).abs() / Tr
-            return r.mean().item(), r[hot].mean().item()
+    def mode_a(s_):
+        return s_.set_temperature(net.predict_T(s_, s_.T))
 
-        out = {}
-        T_const = float(np.median(10.0 ** Y_logT))
-        for label in ("plain", "surrogate", "constant_start"):
-            S = PlainSolver(ctx, P, seed=1)
-            torch.cuda.synchronize()
-            t0 = time.time()
-            T0 = None
-            if label == "surrogate":   # predicted from the constant-source pass inside the run
-                T0 = lambda T1: sur.predict_T(P, T1)
-            elif label == "constant_start":
-                T0 = torch.where(dense, torch.full_like(S.T, T_const), torch.zeros_like(S.T))
-            t_start = time.time() - t0
-            errs = {}
-            hist, at = S.run(max_iter=8, T0=T0, log=log, until_stop=False,
-                             on_iter=lambda it, T: errs.__setitem__(it, err(T)))
-            stop = at if at is not None else hist[-1][0]
-            # the 1%-against-reference criterion: first iteration within 1% over
-            # all cells and over the hottest 5%
-            ref1 = next((it for it in sorted(errs) if errs[it][0] < 0.01 and errs[it][1] < 0.01), None)
-            e = errs[stop]
-            e0 = None
-            if label == "surrogate":
-                e0 = err(sur.predict_T(P, S.T1))
-            elif label == "constant_start":
-                e0 = err(T0)
-            out[label] = {"iterations": stop, "converged": at is not None, "wall_s": t_start + hist[stop - 1][1],
-                          "start_s": t_start, "start_err_all": e0[0] if e0 else None,
-                          "start_err_hot5": e0[1] if e0 else None, "err_all": e[0], "err_hot5": e[1],
-                          "iterations_to_1pct_of_ref": ref1,
-                          "wall_s_to_1pct_of_ref": t_start + hist[ref1 - 1][1] if ref1 else None,
-                          "err_by_iteration": {int(k): [round(v[0], 5), round(v[1], 5)] for k, v in errs.items()}}
-            log(f"{n}^3 {label}: stopping rule at iteration {stop} after {out[label]['wall_s']:.3f}s "
-                f"(mean |T - T_ref|/T_ref {e[0]:.4f}, hottest 5% {e[1]:.4f}); within 1% of the reference "
-                f"from iteration {ref1}")
-        return {"cells": f"{n}^3", "reference": {"burn_in": burn, "averaged": avg, "mean_T": Tr.mean().item(),
-                                                 "hot5_mean_T": Tr[hot].mean().item()},
-                "runs": out, "speedup_vs_plain": out["plain"]["wall_s"] / out["surrogate"]["wall_s"],
-                "speedup_vs_plain_to_1pct_of_ref":
-                    (out["plain"]["wall_s_to_1pct_of_ref"] / out["surrogate"]["wall_s_to_1pct_of_ref"]
-                     if out["plain"]["wall_s_to_1pct_of_ref"] and out["surrogate"]["wall_s_to_1pct_of_ref"]
-                     else None)}
+    def mode_b(s_):
+        y = net.predict(s_, s_.T)
+        T0 = net.predict_T(s_, s_.T, y=y)
+        A0 = net.predict_A(s_, s_.A_const, y)
+        return s_.seed(T0, A0, s_.n_packages(2))
 
-    targets = [gain(64), gain(args.n)]
+    def control(s_):
+        return s_.set_temperature(torch.clamp(s_.T * (10.0 ** mean_ratio), max=P.T_max) * (s_.T > 0))
+
+    runs = {}
+    for label, make, start in (("plain", lambda: PlainSolver(ctx, P, seed=1), None),
+                               ("mode_A", lambda: PlainSolver(ctx, P, seed=1), mode_a),
+                               ("mode_B", lambda: ReferenceFieldSolver(ctx, P, seed=1, mode="average"), mode_b),
+                               ("reference", lambda: ReferenceFieldSolver(ctx, P, seed=1, mode="average"), None),
+                               ("control", lambda: PlainSolver(ctx, P, seed=1), control)):
+        solver = make()
+        t_hit, n_hit, stop, hist = timed_to_criterion(torch, solver, crit, start=start, max_iter=args.max_iter,
+                                                      run_on=True)
+        at_stop = next((h for h in hist if h[0] == stop), None)
+        runs[label] = {"s_to_1pct": t_hit, "iterations_to_1pct": n_hit,
+                       "stopping_rule_iteration": stop,
+                       "err_at_stopping_rule": [at_stop[2], at_stop[3]] if at_stop else None,
+                       "by_iteration": [[h[0], round(h[1], 3), round(h[2], 5), round(h[3], 5)] for h in hist]}
+        log(f"{label}: within 1% of T_ref at iteration {n_hit} ({t_hit}s); stopping rule at {stop}; {hist}")
+        del solver
     line = {"kind": "surrogate_gain",
-            "workload": f"lognormal, sigma_ln {args.target_sigma}, mean tau_V {args.target_tau}, two 1e6 L_sun "
-                        f"sources, {args.freqs} frequencies, {args.packages} packages/frequency",
-            "training": {"clouds": args.train_clouds, "cells": "64^3", "frequencies": 32, "tau_V": "log-U(2, 100)",
-                         "packages_per_frequency": 200_000, "steps": args.train_steps, "batch": 4,
-                         "data_s": t_data, "train_s": t_train, "final_loss": losses[-1][1] if losses else None,
-                         "params": sur.net.param_count},
-            "targets": targets}
+            "workload": f"lognormal {n}^3, sigma_ln {args.target_sigma}, mean tau_V {args.target_tau} "
+                        f"(largest face-to-face tau_V {tau_max:.0f}), two 1e6 L_sun sources, {args.freqs} "
+                        f"frequencies, {args.target_packages} packages per frequency and iteration "
+                        f"({args.target_packages * args.freqs:.3g} per iteration)",
+            "T_ref": {"burn_in": args.ref_burn, "averaged": args.ref_avg, "seconds": t_ref,
+                      "mean_T": crit.Tr.mean().item(), "hot5_mean_T": crit.Tr[crit.hot].mean().item()},
+            "training": {"clouds": ntr, "held_out": args.val_clouds, "cells": "64^3", "frequencies": 32,
+                         "packages_per_frequency": args.train_packages, "steps": args.train_steps, "batch": 4,
+                         "data_s": t_data, "params": net.net.param_count, "learning_curve": curve,
+                         "control_mean_log10_T_over_T1": mean_ratio},
+            "runs": runs,
+            "speedup_mode_A": (runs["plain"]["s_to_1pct"] / runs["mode_A"]["s_to_1pct"]
+                               if runs["plain"]["s_to_1pct"] and runs["mode_A"]["s_to_1pct"] else None),
+            "speedup_mode_B": (runs["plain"]["s_to_1pct"] / runs["mode_B"]["s_to_1pct"]
+                               if runs["plain"]["s_to_1pct"] and runs["mode_B"]["s_to_1pct"] else None)}
     print(json.dumps(line), flush=True)
-    sur.close()
+    net.close()
     ctx.close()
 
 
@@ -702,14 +752,19 @@ def shg_bench(args, soc, torch, W):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--freqs", type=int, default=64)
     ap.add_argument("--packages", type=int, default=1_000_000)
-    ap.add_argument("--max-iter", type=int, default=30)
+    ap.add_argument("--max-iter", type=int, default=12, help="iterations at most of each learned-start run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-converge", action="store_true")
+    ap.add_argument("--no-converge", action="store_true",
+                    help="skip the time-to-1%% runs (plain and learned start)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned start in the time-to-1%% runs")
+    ap.add_argument("--lt-clouds", type=int, default=96, help="training clouds of the in-run learned start")
+    ap.add_argument("--lt-packages", type=int, default=100_000, help="their packages per frequency")
+    ap.add_argument("--lt-steps", type=int, default=1500, help="training steps of the in-run learned start")
     ap.add_argument("--ceilings", action="store_true",
                     help="only run the device micro-benchmarks (one JSON line each) and exit")
     ap.add_argument("--surrogate", action="store_true",
@@ -722,9 +777,16 @@ def main():
     ap.add_argument("--batch-models", type=int, default=256)
     ap.add_argument("--batch-freqs", type=int, default=32)
     ap.add_argument("--tile", type=int, default=16384)
-    ap.add_argument("--train-clouds", type=int, default=256)
+    ap.add_argument("--train-clouds", type=int, default=2000)
+    ap.add_argument("--val-clouds", type=int, default=48)
+    ap.add_argument("--train-packages", type=int, default=100_000)
+    ap.add_argument("--curve", default="250,500,1000", help="training-set sizes of the learning curve")
+    ap.add_argument("--target-n", type=int, default=256)
     ap.add_argument("--target-sigma", type=float, default=1.5)
     ap.add_argument("--target-tau", type=float, default=50.0)
+    ap.add_argument("--target-packages", type=int, default=1_562_500)
+    ap.add_argument("--ref-burn", type=int, default=12)
+    ap.add_argument("--ref-avg", type=int, default=8)
     ap.add_argument("--train-steps", type=int, default=5000)
     ap.add_argument("--reference", action="store_true",
                     help="plain versus reference-field iteration, constant and growing package counts")
@@ -780,6 +842,92 @@ def main():
         octree_bench(args, soc, torch, W)
         return
 
+    headline(args, soc, torch, W)
+
+
+def host_cpu():
+    """(threads the oracle may use, nproc, CPU model): the threads are the
+    OpenMP setting if one is made, else every CPU this process may run on."""
+    nproc = os.cpu_count() or 1
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = nproc
+    omp = os.environ.get("OMP_NUM_THREADS")
+    threads = int(omp) if omp and omp.isdigit() and int(omp) > 0 else allowed
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return threads, nproc, allowed, model
+
+
+class RefCriterion:
+    """The paper's two convergence statistics (Sect. 3.3) taken against a
+    reference field: mean |T - T_ref| / T_ref over the cells with dust and
+    over the hottest 5% of them (by T_ref)."""
+
+    def __init__(self, torch, T_ref, dense):
+        self.torch = torch
+        self.dense = dense
+        self.Tr = T_ref.double()[dense]
+        srt = torch.sort(self.Tr)[0]
+        self.hot = self.Tr >= srt[int(0.95 * (srt.numel() - 1))]
+
+    def __call__(self, T):
+        r = (T.double().reshape(-1)[self.dense] - self.Tr).abs() / self.Tr
+        return r.mean().item(), r[self.hot].mean().item()
+
+
+def timed_to_criterion(torch, S, crit, start=None, max_iter=8, tol=0.01, run_on=False):
+    """Wall clock of one run of the solver from its constant pass until the
+    end of the first iteration whose temperatures are within tol of the
+    reference field on both statistics.  start(S), if given, runs after the
+    constant pass and sets the state the dust iterations start from.  The
+    criterion is evaluated outside the clock.  With run_on the run goes on
+    to max_iter (and to the plain stopping rule) after meeting it.  Returns
+    (seconds or None, iterations or None, stopping-rule iteration or None,
+    [(iteration, seconds, err_all, err_hot5, <T>, hot5 <T>)])."""
+    from paper_1812_06632_amd.driver import converged
+    torch.cuda.synchronize()
+    t0 = time.time()
+    paused = 0.0
+    st = S.constant_pass()
+    if start is not None:
+        st = start(S)
+    torch.cuda.synchronize()
+    hist = []
+    it = 1
+    hit = None
+    stop = None
+    prev = None
+    while True:
+        t_it = time.time() - t0 - paused
+        tp = time.time()
+        e = crit(S.T)
+        paused += time.time() - tp
+        hist.append((it, t_it, e[0], e[1], st["mean_T"], st["hot5_mean_T"]))
+        if hit is None and e[0] < tol and e[1] < tol:
+            hit = (t_it, it)
+        if stop is None and prev is not None and converged(prev, st, tol):
+            stop = it
+        if (hit is not None and not run_on) or it >= max_iter or (run_on and hit and stop):
+            return (hit[0] if hit else None), (hit[1] if hit else None), stop, hist
+        prev = st
+        it += 1
+        st = S.dust_iteration(it)
+        torch.cuda.synchronize()
+
+
+def headline(args, soc, torch, W):
+    """The benchmark workload: dust-iteration throughput, the time to 1%
+    temperature convergence of the plain method and of the learned start,
+    the roofline of the MC kernel and the oracle on the host."""
     from paper_1812_06632_amd.driver import PlainSolver, converged
 
     t_setup = time.time()
@@ -811,10 +959,12 @@ def main():
         it += 1
     ctx.read_stats(reset=True)
     ctx.mc_timing(reset=True)
+    T_sum = torch.zeros(nc, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     t0 = time.time()
     for _ in range(args.steps):
         s = S.dust_iteration(it)
+        T_sum += S.T   # the reference field: mean of the timed iterations (one small add per step)
         history.append((it, s))
         log(f"timed iteration {it}: <T> {s['mean_T']:.3f} K hot5 {s['hot5_mean_T']:.3f} K")
         it += 1
@@ -822,6 +972,7 @@ def main():
     elapsed = time.time() - t0
     st = ctx.read_stats(reset=True)
     mc_ms, mc_launches = ctx.mc_timing(reset=True)
+    ctx.set_option("timing", 0)
     pk_per_s = st["packages"] / elapsed
     steps_per_s = st["cell_steps"] / elapsed
     avg_launch_s = mc_ms / 1e3 / max(mc_launches, 1)
@@ -832,33 +983,64 @@ def main():
     atomic_ceiling, copy_gbs = device_ceilings(soc, ctx, torch, nc)
     log(f"ceilings: random FP64 atomics {atomic_ceiling:.3e}/s over {nc} doubles, copy {copy_gbs:.0f} GB/s")
 
-    # ---- the 1% stopping rule (plain method): the first iteration whose
-    # statistics changed by less than 1% from the previous one
-    def first_converged(h):
-        for i in range(1, len(h)):
-            if converged(h[i - 1][1], h[i][1]):
-                return h[i][0]
-        return None
-
-    time_to_conv = None
-    conv_iter = None
-    if not args.no_converge:
-        per_it = elapsed / args.steps   # wall time of one dust iteration, from the timed region
-        while first_converged(history) is None and it <= args.max_iter:
-            s = S.dust_iteration(it)
-            history.append((it, s))
-            log(f"iteration {it}: <T> {s['mean_T']:.3f} K hot5 {s['hot5_mean_T']:.3f} K")
-            it += 1
-        conv_iter = first_converged(history)
-        if conv_iter is not None:
-            time_to_conv = t_const + (conv_iter - 1) * per_it
+    # ---- the stopping rule of the plain method (change between iterations)
+    stop_iter = None
+    for i in range(1, len(history)):
+        if converged(history[i - 1][1], history[i][1]):
+            stop_iter = history[i][0]
+            break
     T = S.T
+
+    # ---- time to 1% of the reference field, plain and learned start
+    conv = None
+    if not args.no_converge:
+        T_ref = (T_sum / max(args.steps, 1)).float()
+        dense = torch.from_numpy(P.grid.density()).cuda() > 0
+        crit = RefCriterion(torch, T_ref, dense)
+        conv = {"criterion": "mean |T - T_ref| / T_ref < 1% over all cells with dust and over the hottest 5% "
+                             "of them (by T_ref)",
+                "T_ref": f"mean temperature of the {args.steps} timed iterations of the plain run (iterations "
+                         f"{2 + args.warmup}-{1 + args.warmup + args.steps}), same seed and constant-source "
+                         f"pass as the timed runs",
+                "T_ref_mean_K": float(crit.Tr.mean().item()), "T_ref_hot5_mean_K": float(crit.Tr[crit.hot].mean().item())}
+        Sp = PlainSolver(ctx, P, seed=1)
+        t_plain, n_plain, _, h_plain = timed_to_criterion(torch, Sp, crit)
+        log(f"plain: within 1% of T_ref at iteration {n_plain} after {t_plain}s  {h_plain}")
+        conv.update({"plain_s": t_plain, "plain_iterations": n_plain,
+                     "plain_err_by_iteration": [[h[0], round(h[1], 4), round(h[2], 5), round(h[3], 5)]
+                                                for h in h_plain]})
+        if not args.no_learned:
+            from paper_1812_06632_amd.surrogate import Surrogate, make_dataset
+            t0 = time.time()
+            X, Y = make_dataset(ctx, args.lt_clouds, seed=11, n=64, S=64, K=32, packages=args.lt_packages, log=log)
+            t_data = time.time() - t0
+            sur = Surrogate(ctx, S=64, base=32, levels=4, batch=4, seed=3)
+            t0 = time.time()
+            losses = sur.fit(X, Y, steps=args.lt_steps, lr=5e-4, log=log)
+            torch.cuda.synchronize()
+            t_train = time.time() - t0
+            del X, Y
+            Ss = PlainSolver(ctx, P, seed=1)
+            t_sur, n_sur, _, h_sur = timed_to_criterion(torch, Ss, crit,
+                                                        start=lambda s_: s_.set_temperature(sur.predict_T(s_, s_.T)))
+            log(f"learned start: within 1% of T_ref at iteration {n_sur} after {t_sur}s  {h_sur}")
+            conv.update({"surrogate_s": t_sur, "surrogate_iterations": n_sur,
+                         "surrogate_err_by_iteration": [[h[0], round(h[1], 4), round(h[2], 5), round(h[3], 5)]
+                                                        for h in h_sur],
+                         "speedup": (t_plain / t_sur) if (t_plain and t_sur) else None,
+                         "training": {"clouds": args.lt_clouds, "cells": "64^3", "frequencies": 32,
+                                      "packages_per_frequency": args.lt_packages, "steps": args.lt_steps,
+                                      "batch": 4, "network": "U-Net 4 levels, base 32, BF16 MFMA, trained in this run",
+                                      "data_s": t_data, "train_s": t_train,
+                                      "final_loss": losses[-1][1] if losses else None,
+                                      "params": sur.net.param_count}})
+            sur.close()
 
     # ---- CPU baseline: the oracle on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import orc
-        ncpu = min(os.cpu_count() or 1, 16)
+        threads, nproc, allowed, model = host_cpu()
         Th = T.cpu().numpy()
         sample_f = [i * K // 5 for i in range(1, 5)]   # about 10-15 s of oracle work
         npk = 10_000_000
@@ -866,15 +1048,15 @@ def main():
         tot_pk = tot_st = 0
         for k in sample_f:
             _, so, _ = orc.simulate_frequency(P.grid, freqs[k], T=Th, n_dust=npk, dust_mode=1, seed=1,
-                                              iteration=it, freq_index=k, nthreads=ncpu)
+                                              iteration=it, freq_index=k, nthreads=threads)
             tot_pk += so["packages"]
             tot_st += so["cell_steps"]
             log(f"cpu oracle: frequency {k} done ({time.time() - t0:.1f}s)")
         tcpu = time.time() - t0
-        cpu = {"value": tot_pk / tcpu, "unit": "packages/s", "cores": ncpu, "kind": "oracle",
-               "cell_steps_per_s": tot_st / tcpu,
+        cpu = {"value": tot_pk / tcpu, "unit": "packages/s", "cores": threads, "kind": "oracle",
+               "cell_steps_per_s": tot_st / tcpu, "nproc": nproc, "cpus_allowed": allowed, "cpu_model": model,
                "sample": f"dust emission, {npk} weighted packages at each of frequencies {sample_f} of the "
-                         f"same {args.n}^3 workload and temperatures (FP64 C oracle, OpenMP)"}
+                         f"same {args.n}^3 workload and temperatures (FP64 C oracle, OpenMP, {threads} threads)"}
 
     traffic = recorded_traffic()
     out = {
@@ -896,18 +1078,22 @@ def main():
                    "packages_per_step": K * P.n_dust, "cells": nc},
         "cell_steps_per_s": steps_per_s,
         "const_sources_packages_per_s": st_const["packages"] / t_const,
-        "time_to_1pct_T_s": time_to_conv,
-        "iterations_to_1pct": conv_iter,
+        "time_to_1pct_T_s": conv["plain_s"] if conv else None,
+        "time_to_1pct_T_surrogate_s": conv.get("surrogate_s") if conv else None,
+        "time_to_1pct": conv,
+        "stopping_rule_iteration": stop_iter,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": MC_KERNEL, "avg_launch_ms": avg_launch_s * 1e3,
                      "cell_steps_per_launch": steps_per_launch, "bytes_per_cell_step": BYTES_PER_STEP,
+                     "binding": "memory-side FP64 atomic adds (one per cell step), not HBM bytes",
                      "atomic_ceiling_per_s": atomic_ceiling,
                      "atomic_frac": steps_per_launch / avg_launch_s / atomic_ceiling,
                      "copy_GBs": copy_gbs},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    ctx.close()
 
 
 if __name__ == "__main__":

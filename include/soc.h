@@ -400,6 +400,9 @@ soc_status soc_batch_run(soc_batch b, uint32_t iteration, soc_sim_stats *stats);
  *           the 64 consecutive doubles of one random 64-double block
  *           (n >= 64); mode 3 random addresses in a 4096-double LDS array
  *           per workgroup, folded into d_buf[0..4095] (n >= 4096);
+ *           mode 4 random FP32 atomic adds into n floats; mode 5 random
+ *           64-bit and mode 6 random 32-bit integer atomic adds of 1 into
+ *           n words;
  *  which 1: dependent random 4-byte gathers over n words of d_buf;
  *  which 2: streaming copy of n bytes from d_buf to d_buf2.
  * ms receives the kernel time. */
@@ -492,6 +495,66 @@ soc_status soc_unet_mse(soc_ctx ctx, soc_unet u, int32_t n, const float *d_y, co
 /* One Adam step (bias-corrected moments, step counts from 1) with the
  * current gradients; refreshes the BF16 weight copies. */
 soc_status soc_unet_adam(soc_ctx ctx, soc_unet u, float lr, float beta1, float beta2, float eps, int32_t step);
+
+/* The network's input and output on a regular cubic grid of n^3 cells
+ * seen as S^3 blocks of b^3 cells (n = b S; SOC_EINVAL for octrees,
+ * non-cubic grids or S not dividing n).  The plain method's first
+ * iteration (constant sources only) gives T1, the temperatures the dust
+ * iterations start from (Sect. 2.1.2, 3.3); the network predicts how far
+ * the dust re-emission raises them.  All temperatures are in cells with
+ * density 0 replaced by the table's T_floor, and below T_floor raised to
+ * it.
+ *
+ * soc_surrogate_features writes d_features[S^3][4] (device FP32,
+ * z-major like the grid, channels last): per block,
+ *   0: log10(sigma_v <n> s + 1e-4) / 2, s the block edge in cm;
+ *   1: log10(1 + sum_p L_p / (4 pi d_p^2) / F_ext) / 4, the unattenuated
+ *      bolometric flux of the point sources against the external field's
+ *      4 pi J, F_ext = 4 pi sum_k w_k I_k, L_p = sum_k w_k L_p,k;
+ *   2: (log10 T_thin - 1.5) / 0.5, T_thin the equilibrium temperature in
+ *      the unattenuated radiation field, from the table:
+ *      Gamma(T_thin) = 4 pi (sum_k w_k sigma_k I_k
+ *                            + sum_p sum_k w_k sigma_k L_p,k / (16 pi^2 d_p^2));
+ *   3: (mean of log10 T1 over the block - 1.5) / 0.5;
+ * d_p^2 = (|r - r_p|^2 + 1/4) s^2 between the block centre and source p.
+ * Host inputs: K frequencies' w_nu, sigma_abs (cm^2 per H), I_bg; sigma_v
+ * the 0.55 um extinction cross section; n_ps <= 32 sources at ps_pos
+ * [n_ps][3] (root units) with ps_Lnu [n_ps][K]; d_T1 device FP32 ncells.
+ *
+ * Coarse arrays hold several channels: block i's value of channel c is
+ * element [i * stride + c] (0 <= c < stride), so a network with several
+ * outputs is read and trained in place.
+ *
+ * soc_surrogate_target writes channel `channel` of d_target (S^3 blocks):
+ * the block mean of log10(T / T1) divided by scale > 0 (the training
+ * target of the temperatures).  soc_surrogate_target_absorbed does the
+ * same with the absorbed energies (device FP64 ncells each): the block
+ * mean of log10(A / A1) over the cells with dust and A1, A > 0 (other
+ * cells count 0), A1 the constant sources' absorption (Sect. 2.1.2: the
+ * reference field's stored absorptions).
+ *
+ * soc_surrogate_apply writes d_T (ncells): with r channel `channel` of the
+ * network output d_pred times scale plus offset, interpolated trilinearly
+ * to the cell centres (fine cell j maps to coarse coordinate
+ * (j + 1/2) / b - 1/2, clamped to [0, S - 1]), T = T1 10^r clamped to
+ * [T_floor, T_max]; 0 in cells of density 0.  soc_surrogate_apply_absorbed
+ * writes d_A = A1 10^r (scale only; 0 in cells of density 0).
+ * All of them only enqueue work on the context's stream. */
+soc_status soc_surrogate_features(soc_ctx ctx, soc_grid grid, soc_temp_table table, int32_t S, int32_t K,
+                                  const double *w_nu, const double *sigma_abs, const double *I_bg, double sigma_v,
+                                  int32_t n_ps, const double *ps_pos, const double *ps_Lnu, const float *d_T1,
+                                  float *d_features);
+soc_status soc_surrogate_target(soc_ctx ctx, soc_grid grid, soc_temp_table table, int32_t S, const float *d_T,
+                                const float *d_T1, double scale, float *d_target, int32_t stride, int32_t channel);
+soc_status soc_surrogate_target_absorbed(soc_ctx ctx, soc_grid grid, int32_t S, const double *d_A,
+                                         const double *d_A1, double scale, float *d_target, int32_t stride,
+                                         int32_t channel);
+soc_status soc_surrogate_apply(soc_ctx ctx, soc_grid grid, soc_temp_table table, int32_t S, const float *d_pred,
+                               int32_t stride, int32_t channel, double scale, double offset, const float *d_T1,
+                               float *d_T);
+soc_status soc_surrogate_apply_absorbed(soc_ctx ctx, soc_grid grid, int32_t S, const float *d_pred, int32_t stride,
+                                        int32_t channel, double scale, const double *d_A1, double *d_A);
+
 
 #ifdef __cplusplus
 }

@@ -1107,6 +1107,194 @@ soc_status soc_map(soc_ctx c, soc_grid g, const soc_freq *f, const float *d_T, i
     return SOC_OK;
 }
 
+// ---------------------------------------------------------------- learned start
+namespace {
+
+// n and b of a regular cubic grid split into S^3 blocks, or an error.
+soc_status sur_shape(soc_ctx c, soc_grid g, int32_t S, int32_t &n, int32_t &b)
+{
+    if (!g) return fail(c, SOC_EINVAL, "grid is NULL");
+    if (g->ctx != c) return fail(c, SOC_EINVAL, "grid belongs to another context");
+    if (g->nlevels != 1 || g->nx != g->ny || g->nx != g->nz)
+        return fail(c, SOC_EINVAL, "the learned start takes regular cubic grids");
+    if (S < 1 || g->nx % S != 0) return fail(c, SOC_EINVAL, "S must divide the grid size %d", g->nx);
+    n = g->nx;
+    b = n / S;
+    return SOC_OK;
+}
+
+soc_status sur_table(soc_ctx c, soc_temp_table t)
+{
+    if (!t) return fail(c, SOC_EINVAL, "table is NULL");
+    if (t->ctx != c) return fail(c, SOC_EINVAL, "table belongs to another context");
+    return SOC_OK;
+}
+
+}  // namespace
+
+soc_status soc_surrogate_features(soc_ctx c, soc_grid g, soc_temp_table t, int32_t S, int32_t K,
+                                  const double *w_nu, const double *sigma_abs, const double *I_bg, double sigma_v,
+                                  int32_t n_ps, const double *ps_pos, const double *ps_Lnu, const float *d_T1,
+                                  float *d_features)
+{
+    if (!c) return SOC_EINVAL;
+    int32_t n = 0, b = 0;
+    soc_status st = sur_shape(c, g, S, n, b);
+    if (st) return st;
+    if ((st = sur_table(c, t))) return st;
+    if (K < 1 || !w_nu || !sigma_abs || !I_bg || !d_T1 || !d_features) return fail(c, SOC_EINVAL, "NULL argument");
+    if (n_ps < 0 || n_ps > kMaxPs || (n_ps > 0 && (!ps_pos || !ps_Lnu)))
+        return fail(c, SOC_EINVAL, "n_ps must be in [0, %d] with positions and luminosities", kMaxPs);
+    if (!(sigma_v > 0.0 && std::isfinite(sigma_v))) return fail(c, SOC_EINVAL, "sigma_v must be finite and > 0");
+    SurFeatArgs a;
+    std::memset(&a, 0, sizeof a);
+    double F = 0.0, J = 0.0;
+    for (int k = 0; k < K; ++k) {
+        if (!finite_nonneg(w_nu[k]) || !finite_nonneg(sigma_abs[k]) || !finite_nonneg(I_bg[k]))
+            return fail(c, SOC_EINVAL, "frequency %d: bad w, sigma_abs or I_bg", k);
+        F += w_nu[k] * I_bg[k];
+        J += w_nu[k] * sigma_abs[k] * I_bg[k];
+    }
+    if (!(F > 0.0)) return fail(c, SOC_EINVAL, "the external field must be > 0 at some frequency");
+    a.F_ext = 4.0 * M_PI * F;
+    a.Jbg = J;
+    a.n_ps = n_ps;
+    for (int p = 0; p < n_ps; ++p) {
+        const double *q = ps_pos + 3 * p;
+        if (!(q[0] >= 0.0 && q[0] < n && q[1] >= 0.0 && q[1] < n && q[2] >= 0.0 && q[2] < n))
+            return fail(c, SOC_EINVAL, "point source %d lies outside the box", p);
+        a.px[p] = q[0] / b;
+        a.py[p] = q[1] / b;
+        a.pz[p] = q[2] / b;
+        double L = 0.0, Lw = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const double v = ps_Lnu[(size_t)p * K + k];
+            if (!finite_nonneg(v)) return fail(c, SOC_EINVAL, "point source %d: bad L_nu at frequency %d", p, k);
+            L += w_nu[k] * v;
+            Lw += w_nu[k] * sigma_abs[k] * v;
+        }
+        a.Lbol[p] = L;
+        a.Lw[p] = Lw;
+    }
+    a.words = g->d_words;
+    a.T1 = d_T1;
+    a.n = n;
+    a.S = S;
+    a.b = b;
+    a.cell_cm = g->root_cell_cm * b;
+    a.sigma_v = sigma_v;
+    a.T_floor = t->T_floor;
+    a.lnG = t->d_lnG;
+    a.nT = t->nT;
+    a.lnTf = t->lnTf;
+    a.dlnT = t->dlnT;
+    a.out = d_features;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_sur_features(a, c->stream));
+    return SOC_OK;
+}
+
+namespace {
+
+soc_status sur_map_args(soc_ctx c, soc_grid g, int32_t S, int32_t stride, int32_t channel, double scale,
+                        SurMapArgs &a)
+{
+    int32_t n = 0, b = 0;
+    soc_status st = sur_shape(c, g, S, n, b);
+    if (st) return st;
+    if (stride < 1 || channel < 0 || channel >= stride)
+        return fail(c, SOC_EINVAL, "need stride >= 1 and 0 <= channel < stride");
+    if (!(std::isfinite(scale) && scale != 0.0)) return fail(c, SOC_EINVAL, "scale must be finite and non-zero");
+    std::memset(&a, 0, sizeof a);
+    a.words = g->d_words;
+    a.n = n;
+    a.S = S;
+    a.b = b;
+    a.stride = stride;
+    a.channel = channel;
+    a.scale = scale;
+    return SOC_OK;
+}
+
+}  // namespace
+
+soc_status soc_surrogate_target(soc_ctx c, soc_grid g, soc_temp_table t, int32_t S, const float *d_T,
+                                const float *d_T1, double scale, float *d_target, int32_t stride, int32_t channel)
+{
+    if (!c) return SOC_EINVAL;
+    SurMapArgs a;
+    soc_status st = sur_map_args(c, g, S, stride, channel, scale, a);
+    if (st) return st;
+    if ((st = sur_table(c, t))) return st;
+    if (!d_T || !d_T1 || !d_target) return fail(c, SOC_EINVAL, "NULL argument");
+    if (!(scale > 0.0)) return fail(c, SOC_EINVAL, "scale must be > 0");
+    a.T_floor = t->T_floor;
+    a.T_max = t->T_max;
+    a.T = d_T;
+    a.T1 = d_T1;
+    a.coarse = d_target;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_sur_target(a, c->stream));
+    return SOC_OK;
+}
+
+soc_status soc_surrogate_target_absorbed(soc_ctx c, soc_grid g, int32_t S, const double *d_A, const double *d_A1,
+                                         double scale, float *d_target, int32_t stride, int32_t channel)
+{
+    if (!c) return SOC_EINVAL;
+    SurMapArgs a;
+    soc_status st = sur_map_args(c, g, S, stride, channel, scale, a);
+    if (st) return st;
+    if (!d_A || !d_A1 || !d_target) return fail(c, SOC_EINVAL, "NULL argument");
+    if (!(scale > 0.0)) return fail(c, SOC_EINVAL, "scale must be > 0");
+    a.absorbed = 1;
+    a.A = d_A;
+    a.A1 = d_A1;
+    a.coarse = d_target;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_sur_target(a, c->stream));
+    return SOC_OK;
+}
+
+soc_status soc_surrogate_apply(soc_ctx c, soc_grid g, soc_temp_table t, int32_t S, const float *d_pred,
+                               int32_t stride, int32_t channel, double scale, double offset, const float *d_T1,
+                               float *d_T)
+{
+    if (!c) return SOC_EINVAL;
+    SurMapArgs a;
+    soc_status st = sur_map_args(c, g, S, stride, channel, scale, a);
+    if (st) return st;
+    if ((st = sur_table(c, t))) return st;
+    if (!d_pred || !d_T1 || !d_T) return fail(c, SOC_EINVAL, "NULL argument");
+    if (!std::isfinite(offset)) return fail(c, SOC_EINVAL, "offset must be finite");
+    a.T_floor = t->T_floor;
+    a.T_max = t->T_max;
+    a.offset = offset;
+    a.T1 = d_T1;
+    a.pred = d_pred;
+    a.T_out = d_T;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_sur_apply(a, c->stream));
+    return SOC_OK;
+}
+
+soc_status soc_surrogate_apply_absorbed(soc_ctx c, soc_grid g, int32_t S, const float *d_pred, int32_t stride,
+                                        int32_t channel, double scale, const double *d_A1, double *d_A)
+{
+    if (!c) return SOC_EINVAL;
+    SurMapArgs a;
+    soc_status st = sur_map_args(c, g, S, stride, channel, scale, a);
+    if (st) return st;
+    if (!d_pred || !d_A1 || !d_A) return fail(c, SOC_EINVAL, "NULL argument");
+    a.absorbed = 1;
+    a.A1 = d_A1;
+    a.pred = d_pred;
+    a.A_out = d_A;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_sur_apply(a, c->stream));
+    return SOC_OK;
+}
+
 soc_status soc_batch_create(soc_ctx c, int32_t n_grids, const soc_grid *grids, int32_t n_pairs,
                             const soc_batch_pair *pairs, uint64_t seed, uint64_t tile_packages, soc_batch *out)
 {
@@ -1288,7 +1476,7 @@ soc_status soc_ubench(soc_ctx c, int32_t which, void *d_buf, void *d_buf2, uint6
     NOT_WHILE_CAPTURING(c);
     if (!d_buf || !ms || n == 0 || n > 0xFFFFFFFFull || per_thread < 1 || blocks < 1 || threads < 64 ||
         threads > 1024 || which < 0 || which > 2 || (which != 0 && !d_buf2) ||
-        (which == 0 && (mode < 0 || mode > 3 || (mode == 2 && n < 64) || (mode == 3 && n < 4096))))
+        (which == 0 && (mode < 0 || mode > 6 || (mode == 2 && n < 64) || (mode == 3 && n < 4096))))
         return fail(c, SOC_EINVAL, "bad micro-benchmark arguments");
     HIPCHK(c, hipSetDevice(c->device));
     struct Events {   // destroyed on every return path

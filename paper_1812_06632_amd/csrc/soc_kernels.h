@@ -235,6 +235,38 @@ struct TempArgs {
     unsigned int *fine_n;        // kHistBins fine bins inside the threshold bin
     double *fine_T;
 };
+// Learned starting temperatures (surrogate.hip): regular cubic grids of n^3
+// cells, S^3 block averages of b^3 cells each (n = b S).
+struct SurFeatArgs {
+    const uint32_t *words;
+    const float *T1;
+    int32_t n, S, b, n_ps;
+    double cell_cm, sigma_v, T_floor;
+    const double *lnG;           // temperature table: ln Gamma on nT log-spaced T from lnTf, step dlnT
+    int32_t nT;
+    double lnTf, dlnT;
+    double F_ext, Jbg;           // external field: 4 pi sum w I and sum w sigma I
+    double px[kMaxPs], py[kMaxPs], pz[kMaxPs];   // point sources in coarse-cell units
+    double Lbol[kMaxPs], Lw[kMaxPs];             // sum w L and sum w sigma L
+    float *out;                  // [S^3][4]
+};
+struct SurMapArgs {
+    const uint32_t *words;
+    int32_t n, S, b;
+    int32_t stride, channel;     // coarse arrays: block i at [i * stride + channel]
+    int32_t absorbed;            // 0: temperatures (FP32), 1: absorbed energies (FP64)
+    double T_floor, T_max, scale, offset;
+    const float *T1, *T;         // temperatures of the constant sources and of the field
+    const double *A1, *A;        // absorbed energies: the same
+    float *coarse;               // target: output
+    const float *pred;           // apply: network output
+    float *T_out;                // apply: start temperatures
+    double *A_out;               // apply: absorbed energies
+};
+hipError_t launch_sur_features(const SurFeatArgs &a, hipStream_t s);
+hipError_t launch_sur_target(const SurMapArgs &a, hipStream_t s);
+hipError_t launch_sur_apply(const SurMapArgs &a, hipStream_t s);
+
 constexpr int kHistBins = 4096;
 constexpr int kTempBlocks = 512;
 hipError_t launch_temp_update(const TempArgs &a, hipStream_t s);

@@ -26,7 +26,10 @@ __device__ inline uint32_t mix32(uint32_t x)
 // mode 2: wave-coalesced, every wave updating the 64 consecutive doubles of
 //         one random 64-double block (n >= 64);
 // mode 3: random addresses in a 4096-double LDS array of the workgroup
-//         (the LDS sum is folded into a[0..4095] at the end; n >= 4096).
+//         (the LDS sum is folded into a[0..4095] at the end; n >= 4096);
+// mode 4: random FP32 atomic adds into n floats;
+// mode 5: random 64-bit integer atomic adds into n words;
+// mode 6: random 32-bit integer atomic adds into n words.
 constexpr int kUbLds = 4096;
 
 __global__ void ubench_atomic_kernel(double *a, uint32_t n, int32_t per_thread, int32_t mode)
@@ -47,6 +50,12 @@ __global__ void ubench_atomic_kernel(double *a, uint32_t n, int32_t per_thread, 
             unsafeAtomicAdd(&base[blk * 64u + lane], 1.0);
         } else if (mode == 3) {
             unsafeAtomicAdd(&lds[h & (kUbLds - 1)], 1.0);
+        } else if (mode == 4) {
+            unsafeAtomicAdd(&((float *)a)[h % n], 1.0f);
+        } else if (mode == 5) {
+            atomicAdd(&((unsigned long long *)a)[h % n], 1ull);
+        } else if (mode == 6) {
+            atomicAdd(&((unsigned int *)a)[h % n], 1u);
         } else {
             unsafeAtomicAdd(&base[h % n], 1.0);
         }

@@ -204,6 +204,18 @@ class ReferenceFieldSolver(PlainSolver):
         self.n_sum = 0
         return s
 
+    def seed(self, T0: torch.Tensor, A0: torch.Tensor, weight: int) -> dict:
+        """After the constant pass, start from a predicted solution: the
+        temperatures T0 and, as the reference absorption, A0, counted as if
+        `weight` packages per frequency had estimated it (mode "average"
+        only: later estimates are averaged in and the seed's share falls as
+        weight / (weight + packages so far))."""
+        if self.mode != "average":
+            raise ValueError("a predicted reference absorption seeds the 'average' reading")
+        self.A_ref.copy_(A0.reshape(-1))
+        self.n_sum = int(weight)
+        return self.set_temperature(T0)
+
     def dust_iteration(self, it: int) -> dict:
         P = self.P
         n = self.n_packages(it)

@@ -580,6 +580,117 @@ _lib.soc_unet_read.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c
 _lib.soc_unet_adam.argtypes = [C.c_void_p, C.c_void_p, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32]
 
 
+_lib.soc_surrogate_features.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                        C.c_double, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                        C.c_void_p, C.c_void_p]
+_lib.soc_surrogate_target.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                      C.c_double, C.c_void_p, C.c_int32, C.c_int32]
+_lib.soc_surrogate_target_absorbed.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_double,
+                                               C.c_void_p, C.c_int32, C.c_int32]
+_lib.soc_surrogate_apply.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32,
+                                     C.c_double, C.c_double, C.c_void_p, C.c_void_p]
+_lib.soc_surrogate_apply_absorbed.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32,
+                                              C.c_double, C.c_void_p, C.c_void_p]
+
+
+def surrogate_features(ctx: Context, grid: Grid, table: TempTable, S: int, w_nu, sigma_abs, I_bg, sigma_v: float,
+                       ps_pos, ps_Lnu, T1: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """soc_surrogate_features: float32 CUDA tensor [S, S, S, 4]."""
+    P = C.POINTER(C.c_double)
+    w = np.ascontiguousarray(w_nu, dtype=np.float64)
+    sa = np.ascontiguousarray(sigma_abs, dtype=np.float64)
+    I = np.ascontiguousarray(I_bg, dtype=np.float64)
+    K = w.shape[0]
+    if sa.shape != (K,) or I.shape != (K,):
+        raise ValueError("w_nu, sigma_abs and I_bg need one value per frequency")
+    pos = np.ascontiguousarray(ps_pos if ps_pos is not None else np.zeros((0, 3)), dtype=np.float64).reshape(-1, 3)
+    L = np.ascontiguousarray(ps_Lnu if ps_Lnu is not None else np.zeros((0, K)), dtype=np.float64).reshape(-1, K)
+    if L.shape[0] != pos.shape[0]:
+        raise ValueError("one luminosity row per point source")
+    if T1.numel() != grid.ncells:
+        raise ValueError("T1 must hold one value per cell")
+    if out is None:
+        out = torch.empty((S, S, S, 4), dtype=torch.float32, device="cuda")
+    if out.numel() != 4 * S ** 3:
+        raise ValueError("out must hold [S, S, S, 4] values")
+    ctx.check(_lib.soc_surrogate_features(ctx.h, grid.h, table.h, int(S), int(K), w.ctypes.data_as(P),
+                                          sa.ctypes.data_as(P), I.ctypes.data_as(P), float(sigma_v), pos.shape[0],
+                                          pos.ctypes.data_as(P), L.ctypes.data_as(P),
+                                          _dev_ptr(T1, torch.float32, "T1"), _dev_ptr(out, torch.float32, "out")))
+    return out
+
+
+def _coarse(out, S, channels, name):
+    if out is None:
+        out = torch.empty((S, S, S, channels), dtype=torch.float32, device="cuda")
+    if out.numel() % (S ** 3) != 0 or out.numel() // (S ** 3) != channels:
+        raise ValueError(f"{name} must hold S^3 x {channels} values")
+    return out
+
+
+def surrogate_target(ctx: Context, grid: Grid, table: TempTable, S: int, T: torch.Tensor, T1: torch.Tensor,
+                     scale: float, out: torch.Tensor | None = None, channels: int = 1,
+                     channel: int = 0) -> torch.Tensor:
+    """soc_surrogate_target into channel `channel` of a float32 CUDA
+    tensor [S, S, S, channels]."""
+    if T.numel() != grid.ncells or T1.numel() != grid.ncells:
+        raise ValueError("T and T1 must hold one value per cell")
+    out = _coarse(out, S, channels, "out")
+    ctx.check(_lib.soc_surrogate_target(ctx.h, grid.h, table.h, int(S), _dev_ptr(T, torch.float32, "T"),
+                                        _dev_ptr(T1, torch.float32, "T1"), float(scale),
+                                        _dev_ptr(out, torch.float32, "out"), int(channels), int(channel)))
+    return out
+
+
+def surrogate_target_absorbed(ctx: Context, grid: Grid, S: int, A: torch.Tensor, A1: torch.Tensor, scale: float,
+                              out: torch.Tensor | None = None, channels: int = 1, channel: int = 0) -> torch.Tensor:
+    """soc_surrogate_target_absorbed into channel `channel` of a float32
+    CUDA tensor [S, S, S, channels]."""
+    if A.numel() != grid.ncells or A1.numel() != grid.ncells:
+        raise ValueError("A and A1 must hold one value per cell")
+    out = _coarse(out, S, channels, "out")
+    ctx.check(_lib.soc_surrogate_target_absorbed(ctx.h, grid.h, int(S), _dev_ptr(A, torch.float64, "A"),
+                                                 _dev_ptr(A1, torch.float64, "A1"), float(scale),
+                                                 _dev_ptr(out, torch.float32, "out"), int(channels), int(channel)))
+    return out
+
+
+def surrogate_apply(ctx: Context, grid: Grid, table: TempTable, S: int, pred: torch.Tensor, scale: float,
+                    offset: float, T1: torch.Tensor, out: torch.Tensor | None = None, channels: int = 1,
+                    channel: int = 0) -> torch.Tensor:
+    """soc_surrogate_apply: float32 CUDA tensor of ncells start
+    temperatures from channel `channel` of pred [S, S, S, channels]."""
+    _coarse(pred, S, channels, "pred")
+    if T1.numel() != grid.ncells:
+        raise ValueError("T1 must hold one value per cell")
+    if out is None:
+        out = torch.empty(grid.ncells, dtype=torch.float32, device="cuda")
+    if out.numel() != grid.ncells:
+        raise ValueError("out must hold one value per cell")
+    ctx.check(_lib.soc_surrogate_apply(ctx.h, grid.h, table.h, int(S), _dev_ptr(pred, torch.float32, "pred"),
+                                       int(channels), int(channel), float(scale), float(offset),
+                                       _dev_ptr(T1, torch.float32, "T1"), _dev_ptr(out, torch.float32, "out")))
+    return out
+
+
+def surrogate_apply_absorbed(ctx: Context, grid: Grid, S: int, pred: torch.Tensor, scale: float, A1: torch.Tensor,
+                             out: torch.Tensor | None = None, channels: int = 1, channel: int = 0) -> torch.Tensor:
+    """soc_surrogate_apply_absorbed: float64 CUDA tensor of ncells absorbed
+    energies from channel `channel` of pred [S, S, S, channels]."""
+    _coarse(pred, S, channels, "pred")
+    if A1.numel() != grid.ncells:
+        raise ValueError("A1 must hold one value per cell")
+    if out is None:
+        out = torch.empty(grid.ncells, dtype=torch.float64, device="cuda")
+    if out.numel() != grid.ncells:
+        raise ValueError("out must hold one value per cell")
+    ctx.check(_lib.soc_surrogate_apply_absorbed(ctx.h, grid.h, int(S), _dev_ptr(pred, torch.float32, "pred"),
+                                                int(channels), int(channel), float(scale),
+                                                _dev_ptr(A1, torch.float64, "A1"), _dev_ptr(out, torch.float64, "out")))
+    return out
+
+
 class UNet:
     """The 3-D U-Net surrogate (soc_unet_*): FP32 channels-last device
     tensors in and out, BF16 matrix-core convolutions inside."""

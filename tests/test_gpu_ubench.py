@@ -15,15 +15,18 @@ def soc():
     return m
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+_DTYPE = {4: torch.float32, 5: torch.int64, 6: torch.int32}
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4, 5, 6])
 def test_atomic_modes_count_every_add(soc, mode):
     ctx = soc.Context(0)
     n = 1 << 16
-    a = torch.zeros((8 if mode == 1 else 1) * n, dtype=torch.float64, device="cuda")
+    a = torch.zeros((8 if mode == 1 else 1) * n, dtype=_DTYPE.get(mode, torch.float64), device="cuda")
     blocks, threads, per = 64, 256, 5
     ms = soc.ubench(ctx, 0, a, None, n, per, mode, blocks, threads)
     assert ms > 0
-    assert a.sum().item() == blocks * threads * per
+    assert a.double().sum().item() == blocks * threads * per
     if mode == 2:
         # whole 64-double blocks: every block holds a multiple of 64 adds
         counts = a.view(-1, 64).sum(1).cpu()
@@ -39,7 +42,7 @@ def test_atomic_mode_bounds_rejected(soc):
     with pytest.raises(soc.SocError):
         soc.ubench(ctx, 0, a, None, 100, 1, 3, 1, 64)   # LDS mode needs n >= 4096
     with pytest.raises(soc.SocError):
-        soc.ubench(ctx, 0, a, None, 100, 1, 4, 1, 64)
+        soc.ubench(ctx, 0, a, None, 100, 1, 7, 1, 64)
     ctx.close()
 
 
