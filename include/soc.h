@@ -196,6 +196,30 @@ soc_status soc_simulate_frequency(soc_ctx ctx, soc_grid grid, const soc_freq *fr
                                   const soc_sources *src, uint64_t seed, uint32_t iteration,
                                   uint32_t freq_index, double *d_absorbed, soc_sim_stats *stats);
 
+/* soc_simulate_frequency without any device allocation, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels, random
+ * numbers and results (up to FP64 summation order) as
+ * soc_simulate_frequency; the caller still owns d_absorbed and the other
+ * device inputs.  Its scratch (refill counter, per-call statistics, the
+ * dust-emission tables and the per-XCD private copies of the tallies) is a
+ * fixed array of about 13 MB per device, held until the process ends, so:
+ *  - grids of at most 32768 cells (all levels) and, in the weighted dust
+ *    modes (1, 2), at most 2^20 dust packages per call; larger inputs
+ *    return SOC_EINVAL with a message, before any launch;
+ *  - every call on a device shares that device's array: calls that
+ *    overlap on one device (several contexts or streams) race and must be
+ *    serialised by the caller; each call clears what must start at zero;
+ *  - the context's timing option is ignored (no events are created); the
+ *    running totals of soc_read_stats include these calls;
+ *  - stats, if non-NULL, is filled after a synchronisation (not allowed
+ *    during graph capture: SOC_ESTATE).
+ * Returns SOC_EHIP if the array's device address could not be resolved
+ * when the context was created. */
+soc_status soc_simulate_frequency_noalloc(soc_ctx ctx, soc_grid grid, const soc_freq *freq,
+                                          const soc_sources *src, uint64_t seed, uint32_t iteration,
+                                          uint32_t freq_index, double *d_absorbed, soc_sim_stats *stats);
+
 /* Reference-field running mean (Sect. 2.1.2): d_ref += beta (d_x - d_ref)
  * over n FP64 device values, enqueued on the context's stream.  With the
  * weight beta = n_i / (sum of the package counts so far) of iteration i it
@@ -554,7 +578,6 @@ soc_status soc_surrogate_apply(soc_ctx ctx, soc_grid grid, soc_temp_table table,
                                float *d_T);
 soc_status soc_surrogate_apply_absorbed(soc_ctx ctx, soc_grid grid, int32_t S, const float *d_pred, int32_t stride,
                                         int32_t channel, double scale, const double *d_A1, double *d_A);
-
 
 #ifdef __cplusplus
 }

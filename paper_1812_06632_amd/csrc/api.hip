@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <new>
 #include <vector>
@@ -172,9 +173,52 @@ soc_status check_freq(soc_ctx c, const soc_freq *f)
     return SOC_OK;
 }
 
+// Where the scratch of one call lives: the context's buffers, grown on
+// demand (base == NULL), or fixed slices of the per-device no-allocation
+// array at base (sizes checked against its limits).
+struct ScratchSrc {
+    char *base = nullptr;
+};
+
+// Fixed slices of the no-allocation array (byte offsets, 256-aligned).
+constexpr int64_t kNaMaxCells = 32768;           // 32^3 cells, every level included
+constexpr int64_t kNaMaxDust = int64_t(1) << 20; // weighted dust packages per call
+constexpr size_t na_round(size_t b) { return (b + 255) & ~size_t(255); }
+constexpr size_t kNaStats = 0;                                              // 2 DevStats
+constexpr size_t kNaCounter = kNaStats + na_round(2 * sizeof(DevStats));    // refill counter
+constexpr size_t kNaS = kNaCounter + 256;                                   // capped dust total
+constexpr size_t kNaL = kNaS + 256;
+constexpr size_t kNaA = kNaL + na_round(sizeof(double) * kNaMaxCells);
+constexpr size_t kNaIncl = kNaA + na_round(sizeof(double) * kNaMaxCells);
+constexpr size_t kNaScan = kNaIncl + na_round(sizeof(double) * kNaMaxCells);
+constexpr size_t kNaScanElems = 1024;   // >= scan_f64_scratch_elems(kNaMaxCells), checked at run time
+constexpr size_t kNaPk = kNaScan + na_round(sizeof(double) * kNaScanElems);
+constexpr size_t kNaPriv = kNaPk + na_round(sizeof(int32_t) * kNaMaxDust);
+constexpr size_t kNaPrivSelf = kNaPriv + na_round(sizeof(double) * kPrivCopies * kNaMaxCells);
+constexpr size_t kNaBytes = kNaPrivSelf + na_round(sizeof(double) * kPrivCopies * kNaMaxCells);
+
+// A scratch buffer of `need` elements: the context's (grown) or the slice
+// at byte offset `off` of the no-allocation array.
+template <typename T>
+soc_status take(soc_ctx c, const ScratchSrc &src, T **ctx_p, int64_t &ctx_cap, int64_t need, size_t off,
+                int64_t max_need, T **out)
+{
+    if (!src.base) {
+        soc_status st = grow(c, ctx_p, ctx_cap, need);
+        *out = *ctx_p;
+        return st;
+    }
+    if (need > max_need)
+        return fail(c, SOC_EINVAL, "no-allocation call: %lld elements exceed its fixed scratch of %lld",
+                    (long long)need, (long long)max_need);
+    *out = (T *)(src.base + off);
+    return SOC_OK;
+}
+
 // Per-frequency argument block shared by the production and trace kernels.
 soc_status prepare(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *s, uint64_t seed,
-                   uint32_t iteration, uint32_t freq_index, double *d_absorbed, McArgs &A)
+                   uint32_t iteration, uint32_t freq_index, double *d_absorbed, McArgs &A,
+                   const ScratchSrc &src = ScratchSrc())
 {
     soc_status st = check_freq(c, f);
     if (st) return st;
@@ -246,17 +290,18 @@ soc_status prepare(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *
     A.dust_mode = s->dust_mode;
     if (s->d_T && s->n_dust > 0) {
         A.n_dust = s->n_dust;
-        if ((st = grow(c, &c->d_L, c->cap_L, g->ncells))) return st;
+        double *dL = nullptr, *da = nullptr;
+        if ((st = take(c, src, &c->d_L, c->cap_L, g->ncells, kNaL, kNaMaxCells, &dL))) return st;
         if (s->dust_mode == 2) {
-            if ((st = grow(c, &c->d_a, c->cap_a, g->ncells))) return st;
+            if ((st = take(c, src, &c->d_a, c->cap_a, g->ncells, kNaA, kNaMaxCells, &da))) return st;
             HIPCHK(c, launch_dust_correction(g->d_words, g->ncells, g->level_offset.data(), g->nlevels, s_cm, f->nu,
-                                             f->sigma_abs, f->w_nu, s->d_T, s->d_L_ref, s->ref_beta, c->d_L, c->d_a,
+                                             f->sigma_abs, f->w_nu, s->d_T, s->d_L_ref, s->ref_beta, dL, da,
                                              c->stream));
         } else {
             HIPCHK(c, launch_dust_luminosity(g->d_words, g->ncells, g->level_offset.data(), g->nlevels, s_cm, f->nu,
-                                             f->sigma_abs, f->w_nu, s->d_T, c->d_L, c->stream));
+                                             f->sigma_abs, f->w_nu, s->d_T, dL, c->stream));
         }
-        A.dust_L = c->d_L;
+        A.dust_L = dL;
         if (s->dust_mode == 0) {
             if (s->n_dust % (uint64_t)g->nleaves != 0)
                 return fail(c, SOC_EINVAL, "uniform dust mode needs n_dust to be a multiple of the %lld leaves",
@@ -266,34 +311,38 @@ soc_status prepare(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *
         } else {
             const bool capped = s->dust_cap > 0.0;
             if (capped && s->dust_mode == 1) {
-                if ((st = grow(c, &c->d_a, c->cap_a, g->ncells))) return st;
-                HIPCHK(c, launch_abs_f64(c->d_L, c->d_a, g->ncells, c->stream));
+                if ((st = take(c, src, &c->d_a, c->cap_a, g->ncells, kNaA, kNaMaxCells, &da))) return st;
+                HIPCHK(c, launch_abs_f64(dL, da, g->ncells, c->stream));
             }
-            const double *weight = s->dust_mode == 2 || capped ? c->d_a : c->d_L;
-            if ((st = grow(c, &c->d_incl, c->cap_incl, g->ncells))) return st;
-            if ((st = grow(c, &c->d_scan, c->cap_scan, (int64_t)scan_f64_scratch_elems(g->ncells)))) return st;
-            HIPCHK(c, launch_scan_f64(weight, c->d_incl, g->ncells, c->d_scan, c->stream));
-            A.dust_S = c->d_incl + (g->ncells - 1);
+            const double *weight = s->dust_mode == 2 || capped ? da : dL;
+            double *dincl = nullptr, *dscan = nullptr;
+            if ((st = take(c, src, &c->d_incl, c->cap_incl, g->ncells, kNaIncl, kNaMaxCells, &dincl))) return st;
+            if ((st = take(c, src, &c->d_scan, c->cap_scan, (int64_t)scan_f64_scratch_elems(g->ncells), kNaScan,
+                           (int64_t)kNaScanElems, &dscan)))
+                return st;
+            HIPCHK(c, launch_scan_f64(weight, dincl, g->ncells, dscan, c->stream));
+            A.dust_S = dincl + (g->ncells - 1);
             if (capped) {
                 // expected counts min(N a / S, cap) replace the weights; their
                 // cumulative sum (package units) replaces the first one
-                if ((st = grow(c, &c->d_S, c->cap_S, 1))) return st;
-                HIPCHK(c, launch_dust_cap(c->d_a, g->ncells, c->d_incl + (g->ncells - 1), c->d_S, s->n_dust,
+                double *dS = nullptr;
+                if ((st = take(c, src, &c->d_S, c->cap_S, 1, kNaS, 1, &dS))) return st;
+                HIPCHK(c, launch_dust_cap(da, g->ncells, dincl + (g->ncells - 1), dS, s->n_dust,
                                           s->dust_cap, c->stream));
-                HIPCHK(c, launch_scan_f64(c->d_a, c->d_incl, g->ncells, c->d_scan, c->stream));
-                A.dust_S = c->d_S;
+                HIPCHK(c, launch_scan_f64(da, dincl, g->ncells, dscan, c->stream));
+                A.dust_S = dS;
                 A.dust_cap = s->dust_cap;
             }
             int64_t cap_pk = (int64_t)c->cap_pk;
-            if ((st = grow(c, &c->d_pkcell, cap_pk, (int64_t)s->n_dust))) return st;
+            int32_t *dpk = nullptr;
+            if ((st = take(c, src, &c->d_pkcell, cap_pk, (int64_t)s->n_dust, kNaPk, kNaMaxDust, &dpk))) return st;
             c->cap_pk = (uint64_t)cap_pk;
             // systematic offset: first uniform of the stream of package id 2^32-1 of the dust class
             uint32_t x0 = 0, x1 = 0xFFFFFFFFu, x2 = freq_index, x3 = (iteration << 8) | kClassDust;
             philox4x32_10(x0, x1, x2, x3, (uint32_t)seed, (uint32_t)(seed >> 32));
             const double u_sys = u01<double>(x0);
-            HIPCHK(c, launch_dust_select(c->d_incl, g->ncells, s->n_dust, u_sys, capped ? 1 : 0, c->d_pkcell,
-                                         c->stream));
-            A.dust_cell = c->d_pkcell;
+            HIPCHK(c, launch_dust_select(dincl, g->ncells, s->n_dust, u_sys, capped ? 1 : 0, dpk, c->stream));
+            A.dust_cell = dpk;
         }
     }
     A.n_total = A.n_bg + (uint64_t)A.n_ps * A.n_ps_pk + A.n_dust;
@@ -313,8 +362,8 @@ soc_status prepare(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *
             HIPCHK(c, launch_dust_emitted_weighted(A.dust_cell, A.n_dust, A.dust_L, A.dust_S, A.dust_mode, A.dust_cap,
                                                    s->d_ali_emitted, c->stream));
     }
-    A.next_id = c->d_counter;
-    A.st_call = c->d_stats;
+    A.next_id = src.base ? (unsigned long long *)(src.base + kNaCounter) : c->d_counter;
+    A.st_call = src.base ? (DevStats *)(src.base + kNaStats) : c->d_stats;
     A.st_total = c->d_stats + 1;
     A.refill_min = (int32_t)c->refill_min;
     A.inner_steps = (int32_t)c->inner_steps;
@@ -336,6 +385,41 @@ void to_public(const DevStats &d, soc_sim_stats *o)
 
 }  // namespace
 
+// Scratch of soc_simulate_frequency_noalloc, one instance per device for the
+// life of the process.  Host code never passes this name to a kernel: it
+// resolves the device's own address once (soc_ctx_create, the device
+// current) and uses that.
+static __device__ __align__(256) char scratch[kNaBytes];
+
+namespace {
+
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mu;
+char *g_na_base[kNaMaxDevices] = {};
+
+// Address of the no-allocation array on the current device `dev`,
+// resolved on the first call for that device.
+hipError_t na_resolve(int dev)
+{
+    if (dev < 0 || dev >= kNaMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if (g_na_base[dev]) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_na_base[dev] = (char *)ptr;
+    return hipSuccess;
+}
+
+char *na_base(int dev)
+{
+    if (dev < 0 || dev >= kNaMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    return g_na_base[dev];
+}
+
+}  // namespace
+
 extern "C" {
 
 soc_status soc_ctx_create(int32_t hip_device, void *hip_stream, soc_ctx *out)
@@ -350,6 +434,7 @@ soc_status soc_ctx_create(int32_t hip_device, void *hip_stream, soc_ctx *out)
     c->device = hip_device;
     c->stream = (hipStream_t)hip_stream;
     if (hipSetDevice(hip_device) != hipSuccess) { delete c; return SOC_EHIP; }
+    if (na_resolve(hip_device) != hipSuccess) { delete c; return SOC_EHIP; }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess && prop.multiProcessorCount > 0)
         c->num_cus = prop.multiProcessorCount;
@@ -634,6 +719,49 @@ soc_status soc_simulate_frequency(soc_ctx c, soc_grid g, const soc_freq *f, cons
     if (stats) {
         DevStats h;
         HIPCHK(c, hipMemcpyAsync(&h, c->d_stats, sizeof h, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        to_public(h, stats);
+    }
+    return SOC_OK;
+}
+
+soc_status soc_simulate_frequency_noalloc(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *s,
+                                          uint64_t seed, uint32_t iteration, uint32_t freq_index,
+                                          double *d_absorbed, soc_sim_stats *stats)
+{
+    if (!c) return SOC_EINVAL;
+    if (!d_absorbed) return fail(c, SOC_EINVAL, "d_absorbed is NULL");
+    if (!g) return fail(c, SOC_EINVAL, "grid is NULL");
+    if (g->ncells > kNaMaxCells)
+        return fail(c, SOC_EINVAL, "no-allocation call: the grid's %lld cells exceed its limit of %lld",
+                    (long long)g->ncells, (long long)kNaMaxCells);
+    if (s && s->d_T && s->n_dust > 0 && s->dust_mode != 0 && s->n_dust > (uint64_t)kNaMaxDust)
+        return fail(c, SOC_EINVAL, "no-allocation call: %llu weighted dust packages exceed its limit of %lld",
+                    (unsigned long long)s->n_dust, (long long)kNaMaxDust);
+    if (c->capturing && stats) return fail(c, SOC_ESTATE, "statistics not allowed during graph capture");
+    HIPCHK(c, hipSetDevice(c->device));
+    ScratchSrc src;
+    src.base = na_base(c->device);
+    if (!src.base) return fail(c, SOC_EHIP, "no-allocation scratch of device %d is not resolved", c->device);
+    McArgs A;
+    soc_status st = prepare(c, g, f, s, seed, iteration, freq_index, d_absorbed, A, src);
+    if (st) return st;
+    if (c->xcd_copies) {   // the array keeps the last call's contents: clear the copies this call uses
+        A.priv = (double *)(src.base + kNaPriv);
+        HIPCHK(c, launch_fill_f64(A.priv, 0.0, (int64_t)kPrivCopies * g->ncells, c->stream));
+        if (A.ali_self) {
+            A.priv_self = (double *)(src.base + kNaPrivSelf);
+            HIPCHK(c, launch_fill_f64(A.priv_self, 0.0, (int64_t)kPrivCopies * g->ncells, c->stream));
+        }
+    }
+    HIPCHK(c, launch_fill_u64((unsigned long long *)A.st_call, 0ull, (int64_t)(sizeof(DevStats) / 8), c->stream));
+    HIPCHK(c, launch_fill_u64(A.next_id, 0ull, 1, c->stream));
+    HIPCHK(c, launch_mc(A, (int)(c->num_cus * c->blocks_per_cu), (int)c->block, c->stream));
+    if (A.priv) HIPCHK(c, launch_fold_copies(d_absorbed, A.priv, g->ncells, c->stream));
+    if (A.priv_self) HIPCHK(c, launch_fold_copies(A.ali_self, A.priv_self, g->ncells, c->stream));
+    if (stats) {
+        DevStats h;
+        HIPCHK(c, hipMemcpyAsync(&h, A.st_call, sizeof h, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         to_public(h, stats);
     }

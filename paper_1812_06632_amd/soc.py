@@ -91,6 +91,7 @@ _lib.soc_grid_destroy.argtypes = [C.c_void_p]
 _lib.soc_grid_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_void_p)]
 _lib.soc_simulate_frequency.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Freq), C.POINTER(_Sources), C.c_uint64,
                                         C.c_uint32, C.c_uint32, C.c_void_p, C.POINTER(_SimStats)]
+_lib.soc_simulate_frequency_noalloc.argtypes = _lib.soc_simulate_frequency.argtypes
 _lib.soc_update_temperature_ali.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                             C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(_TempStats)]
 _lib.soc_scatter_map.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Freq), C.POINTER(_Sources), C.c_uint64,
@@ -255,21 +256,22 @@ class _SourceView:
 def simulate_frequency(ctx: Context, grid: Grid, freq, absorbed: torch.Tensor, *, I_bg=0.0, ps_pos=None,
                        ps_Lnu=None, T=None, n_bg=0, n_ps_pk=0, n_dust=0, dust_mode=1, L_ref=None, ref_beta=0.0,
                        dust_cap=0.0, ali_self=None, ali_emitted=None, seed=1, iteration=0, freq_index=0,
-                       stats=False):
-    """soc_simulate_frequency.  freq = (nu, w_nu, sigma_abs, sigma_sca, g);
-    absorbed: float64 CUDA tensor of ncells (accumulated).  dust_mode 2
-    emits the difference to L_ref (float64 CUDA tensor of ncells, blended
-    in place with weight ref_beta).  ali_self / ali_emitted: float64 CUDA
-    tensors of ncells, the diagonal-ALI tallies (+=).  Returns the call's
-    statistics dict if stats, else None (asynchronous)."""
+                       stats=False, noalloc=False):
+    """soc_simulate_frequency (soc_simulate_frequency_noalloc if noalloc).
+    freq = (nu, w_nu, sigma_abs, sigma_sca, g); absorbed: float64 CUDA
+    tensor of ncells (accumulated).  dust_mode 2 emits the difference to
+    L_ref (float64 CUDA tensor of ncells, blended in place with weight
+    ref_beta).  ali_self / ali_emitted: float64 CUDA tensors of ncells, the
+    diagonal-ALI tallies (+=).  Returns the call's statistics dict if
+    stats, else None (asynchronous)."""
     sv = _SourceView(I_bg, ps_pos, ps_Lnu, T, n_bg, n_ps_pk, n_dust, dust_mode, L_ref, ref_beta, dust_cap,
                      ali_self, ali_emitted)
     f = _freq(freq)
     st = _SimStats() if stats else None
-    ctx.check(_lib.soc_simulate_frequency(ctx.h, grid.h, C.byref(f), C.byref(sv.s), C.c_uint64(seed),
-                                          C.c_uint32(iteration), C.c_uint32(freq_index),
-                                          _dev_ptr(absorbed, torch.float64, "absorbed"),
-                                          C.byref(st) if st is not None else None))
+    fn = _lib.soc_simulate_frequency_noalloc if noalloc else _lib.soc_simulate_frequency
+    ctx.check(fn(ctx.h, grid.h, C.byref(f), C.byref(sv.s), C.c_uint64(seed), C.c_uint32(iteration),
+                 C.c_uint32(freq_index), _dev_ptr(absorbed, torch.float64, "absorbed"),
+                 C.byref(st) if st is not None else None))
     if st is None:
         return None
     return {k: getattr(st, k) for k, _ in _SimStats._fields_}
