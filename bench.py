@@ -9,7 +9,8 @@ Iteration 1 simulates the constant sources (background 5e5 + 2 x 2.5e5
 packages per frequency) once and keeps their absorbed energy.  Every later
 iteration -- one benchmark step -- re-simulates the dust emission at the
 current temperatures (10^6 luminosity-weighted packages per frequency, all
-64 frequencies) on top of the kept absorption and solves the temperatures.
+64 frequencies in one persistent launch) on top of the kept absorption and
+solves the temperatures.
 Steps are the iterations of the plain method "iterate T to 1% change".
 
 Time to 1% temperature convergence (the paper's two statistics of
@@ -39,12 +40,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_STEP = 12.0   # 4 B density gather + 8 B FP64 absorbed update per cell step
-MC_KERNEL = "soc::mc_kernel<false>"   # regular-grid instantiation of the persistent MC kernel
+# regular-grid instantiation of the persistent MC kernel that runs every
+# frequency of a pass in one launch
+MC_KERNEL = "soc::mc_multi_kernel<false>"
 # HBM traffic of the MC kernel measured with rocprofv3 counters (FETCH_SIZE,
 # WRITE_SIZE, scaled by a 1 GiB copy); used only while the kernel sources
-# still hash to the value recorded with it.
+# and compile flags still hash to the value recorded with it.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mc_kernel_lognormal128_traffic.md")
-MC_SOURCES = ("mc.hip", "soc_device.h", "soc_kernels.h")
+MC_SOURCES = ("mc.hip", "soc_device.h")
 
 
 def log(msg):
@@ -52,11 +55,14 @@ def log(msg):
 
 
 def mc_source_hash():
+    """SHA-256 of the MC kernel's sources and the library's compile flags."""
     import hashlib
+    from __graft_entry__ import HIP_FLAGS
     h = hashlib.sha256()
     for name in MC_SOURCES:
         with open(os.path.join(ROOT, "paper_1812_06632_amd", "csrc", name), "rb") as f:
             h.update(f.read())
+    h.update(" ".join(HIP_FLAGS).encode())
     return h.hexdigest()
 
 
@@ -137,6 +143,7 @@ def batch_bench(args, soc, torch, W):
     it is captured once in a HIP graph and replayed (the iteration word
     advances on every replay).  Reports packages/s and cell steps/s over
     the timed replays."""
+    from paper_1812_06632_amd import autotune as AT
     t0 = time.time()
     grids, (nu, w, sabs, ssca, g, I), pk = W.batch_clouds(args.batch_models, args.batch_freqs)
     log(f"batch workload: {len(grids)} models, {sum(gr.ncells for gr in grids)} cells, "
@@ -148,10 +155,58 @@ def batch_bench(args, soc, torch, W):
         table = soc.temp_table_build(ctx, nu, w, sabs, 2.0, 3000.0, 1024)
         A = [torch.zeros(gr.ncells, dtype=torch.float64, device="cuda") for gr in grids]
         T = [torch.zeros(gr.ncells, dtype=torch.float32, device="cuda") for gr in grids]
-        pairs = [dict(grid=m, freq=(float(nu[k]), float(w[k]), float(sabs[k]), float(ssca[k]), float(g[k])),
-                      freq_index=k, I_bg=float(I[k]), n_bg=int(pk[m, k]), absorbed=A[m])
-                 for m in range(len(grids)) for k in range(len(nu))]
-        b = soc.Batch(ctx, G, pairs, seed=1, tile_packages=args.tile)
+
+        def pair_list(models, freqs):
+            return [dict(grid=m, freq=(float(nu[k]), float(w[k]), float(sabs[k]), float(ssca[k]), float(g[k])),
+                         freq_index=k, I_bg=float(I[k]), n_bg=int(pk[m, k]), absorbed=A[m])
+                    for m in models for k in freqs]
+
+        # ---- launch schedule: the autotuner on every 8th model at every 8th
+        # frequency (1/64 of the work, the same mix of sizes), timed with HIP
+        # events around the batched launch
+        tuned = None
+        lds_default = ctx.get_option("batch_lds_cells")
+        if not args.no_tune:
+            cal = pair_list(range(0, len(grids), 8), range(0, len(nu), 8))
+            default = {k: ctx.get_option(k) for k in ("block", "blocks_per_cu", "refill_min", "chunk")}
+            default.update(tile_packages=args.tile, batch_lds_cells=lds_default)
+            cal_batches = {}
+
+            def run(cfg):
+                kb = (cfg["tile_packages"], cfg["batch_lds_cells"])
+                if kb not in cal_batches:
+                    ctx.set_option("batch_lds_cells", cfg["batch_lds_cells"])
+                    cal_batches[kb] = soc.Batch(ctx, G, cal, seed=1, tile_packages=cfg["tile_packages"])
+                cal_batches[kb].run(iteration=0)
+
+            # two families: small grids tallied in LDS by whole-pair workgroups
+            # (fixed 512-lane launch shape), or every pair tiled
+            spaces = [{"tile_packages": AT.BATCH_TILES, "refill_min": (1, 16), "chunk": (256, 1024),
+                       "batch_lds_cells": (lds_default,)},
+                      {"tile_packages": AT.BATCH_TILES, "block": (128, 256), "blocks_per_cu": (2, 4, 8),
+                       "refill_min": (1, 16), "batch_lds_cells": (0,)}]
+            measure = AT.event_timer(ctx, run)
+            t0 = time.time()
+            results = []
+            for i, space in enumerate(spaces):
+                tuner = AT.Autotuner()
+                key = f"batch:{i}"
+                cfg = tuner.tune(key, measure, space=space, repeats=2)
+                results.append((tuner.cache[key]["seconds"], cfg, len(tuner.cache[key]["tried"])))
+            t_default = min(measure(default) for _ in range(2))
+            for bb in cal_batches.values():
+                bb.close()
+            best_s, tuned, n_cand = min(results, key=lambda r: r[0])
+            n_cand = sum(r[2] for r in results)
+            for k in ("block", "blocks_per_cu", "refill_min", "chunk"):
+                ctx.set_option(k, default[k])
+            AT.apply(ctx, tuned)
+            ctx.set_option("batch_lds_cells", tuned["batch_lds_cells"])
+            log(f"autotuned schedule {tuned} in {time.time() - t0:.1f}s: calibration launch {best_s * 1e3:.2f} ms "
+                f"(default schedule {t_default * 1e3:.2f} ms)")
+        tile = tuned["tile_packages"] if tuned else args.tile
+        pairs = pair_list(range(len(grids)), range(len(nu)))
+        b = soc.Batch(ctx, G, pairs, seed=1, tile_packages=tile)
         n_tiles, n_pk = b.info()
         b.run(iteration=0)
         torch.cuda.synchronize()
@@ -177,7 +232,13 @@ def batch_bench(args, soc, torch, W):
     line = {"kind": "batch", "models": len(grids), "pairs": len(pairs), "tiles": n_tiles,
             "cells": int(sum(gr.ncells for gr in grids)), "packages_per_pass": n_pk, "passes": args.steps,
             "ms_per_pass": el / args.steps * 1e3, "packages_per_s": pk_done / el, "cell_steps_per_s": st_done / el,
-            "tile_packages": args.tile, "graph": True}
+            "tile_packages": tile, "graph": True,
+            "schedule": {k: ctx.get_option(k) for k in ("block", "blocks_per_cu", "refill_min", "chunk",
+                                                       "scatter_min", "inner_steps", "batch_lds_cells")},
+            "autotuned": tuned is not None,
+            "calibration": ({"workload": "every 8th model at every 8th frequency (1/64 of the pass)",
+                             "best_s": best_s, "default_schedule_s": t_default, "candidates": n_cand}
+                            if tuned else None)}
     print(json.dumps(line), flush=True)
     graph.close()
     b.close()
@@ -323,7 +384,7 @@ def surrogate_gain(args, soc, torch, W):
         y = net.predict(s_, s_.T)
         T0 = net.predict_T(s_, s_.T, y=y)
         A0 = net.predict_A(s_, s_.A_const, y)
-        return s_.seed(T0, A0, s_.n_packages(2))
+        return s_.seed_prediction(T0, A0, s_.n_packages(2))
 
     def control(s_):
         return s_.set_temperature(torch.clamp(s_.T * (10.0 ** mean_ratio), max=P.T_max) * (s_.T > 0))
@@ -554,13 +615,19 @@ def octree_bench(args, soc, torch, W):
         soc.simulate_frequency(ctx, g, freqs[k], A, I_bg=float(I[k]), ps_pos=pos, ps_Lnu=[float(Lnu[k])], n_bg=n,
                                n_ps_pk=n, seed=1, iteration=1, freq_index=k)
 
-    def full_pass():
+    src = [dict(I_bg=float(I[k]), ps_pos=pos, ps_Lnu=[float(Lnu[k])], n_bg=n_half, n_ps_pk=n_half)
+           for k in range(len(nu))]
+
+    def full_pass(multi=False):
         A.zero_()
         ctx.read_stats(reset=True)
         torch.cuda.synchronize()
         t = time.time()
-        for k in range(len(nu)):
-            one(k, n_half)
+        if multi:
+            soc.simulate_frequencies(ctx, g, freqs, A, src, range(len(nu)), seed=1, iteration=1)   # one launch
+        else:
+            for k in range(len(nu)):
+                one(k, n_half)
         torch.cuda.synchronize()
         el = time.time() - t
         st = ctx.read_stats(reset=True)
@@ -580,12 +647,14 @@ def octree_bench(args, soc, torch, W):
     t_def, st_def = full_pass()
     autotune.apply(ctx, best)
     t_tuned, st = full_pass()
-    log(f"octree: 128 frequencies x 10^7 packages: default schedule {t_def:.2f}s, tuned {t_tuned:.2f}s")
+    t_multi, _ = full_pass(multi=True)
+    log(f"octree: 128 frequencies x 10^7 packages: default schedule {t_def:.2f}s, tuned {t_tuned:.2f}s, "
+        f"tuned in one launch {t_multi:.2f}s")
     cons = (st["e_absorbed"] + st["e_escaped"]) / st["e_emitted"] - 1.0
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import orc
-        ncpu = min(os.cpu_count() or 1, 16)
+        ncpu = host_cpu()[0]
         t1 = time.time()
         n_pk = n_st = 0
         for k in ks:
@@ -604,6 +673,7 @@ def octree_bench(args, soc, torch, W):
                                           "10^4 K source of 10^6 L_sun + external field, 128 frequencies, "
                                           "10^7 packages/frequency",
             "packages": st["packages"], "cell_steps": st["cell_steps"], "s_per_pass": t_tuned,
+            "s_per_pass_one_launch": t_multi,
             "packages_per_s": st["packages"] / t_tuned, "cell_steps_per_s": st["cell_steps"] / t_tuned,
             "s_per_pass_default_schedule": t_def, "schedule": best, "energy_conservation": cons,
             "cpu_baseline": cpu}
@@ -653,7 +723,7 @@ def scatter_bench(args, soc, torch, W):
         n_s = 20 * args.packages   # about 10 s on 16 host threads
         kw_s = dict(kw)
         kw_s["n_bg"], kw_s["n_ps_pk"] = n_s // 2, n_s // 4
-        nthreads = min(os.cpu_count() or 1, 16)
+        nthreads = host_cpu()[0]
         t1 = time.time()
         _, so = orc.scatter_map(P.grid, f, seed=5, nthreads=nthreads, **kw_s)
         el_c = time.time() - t1
@@ -762,6 +832,8 @@ def main():
     ap.add_argument("--no-converge", action="store_true",
                     help="skip the time-to-1%% runs (plain and learned start)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned start in the time-to-1%% runs")
+    ap.add_argument("--no-sub-records", action="store_true",
+                    help="skip the one-pass octree and batch records of the default line")
     ap.add_argument("--lt-clouds", type=int, default=96, help="training clouds of the in-run learned start")
     ap.add_argument("--lt-packages", type=int, default=100_000, help="their packages per frequency")
     ap.add_argument("--lt-steps", type=int, default=1500, help="training steps of the in-run learned start")
@@ -776,7 +848,8 @@ def main():
                     help="only time the batched many-cloud workload as a replayed HIP graph (one JSON line) and exit")
     ap.add_argument("--batch-models", type=int, default=256)
     ap.add_argument("--batch-freqs", type=int, default=32)
-    ap.add_argument("--tile", type=int, default=16384)
+    ap.add_argument("--tile", type=int, default=16384, help="tile size when the batch schedule is not tuned")
+    ap.add_argument("--no-tune", action="store_true", help="batch: default schedule, no autotuning")
     ap.add_argument("--train-clouds", type=int, default=2000)
     ap.add_argument("--val-clouds", type=int, default=48)
     ap.add_argument("--train-packages", type=int, default=100_000)
@@ -924,6 +997,91 @@ def timed_to_criterion(torch, S, crit, start=None, max_iter=8, tol=0.01, run_on=
         torch.cuda.synchronize()
 
 
+def octree_record(soc, torch, W):
+    """One 128-frequency pass of the octree workload (as `--octree`, 10^7
+    packages per frequency) with the library's default launch schedule:
+    packages/s and cell steps/s."""
+    t0 = time.time()
+    G = W.octree_lognormal(n_root=64, nlevels=4)
+    nu, w = W.frequency_grid(128)
+    sabs, ssca, gg = W.dust_model(nu)
+    t_build = time.time() - t0
+    ctx = soc.Context(0)
+    g = soc.grid_from_workload(ctx, G)
+    A = torch.zeros(G.ncells, dtype=torch.float64, device="cuda")
+    pos = [[32.1, 31.9, 32.05]]
+    I = W.isrf(nu)
+    Lnu = W.blackbody_Lnu(nu, 1e6 * W.L_SUN, 1e4)
+    freqs = [(float(nu[k]), float(w[k]), float(sabs[k]), float(ssca[k]), float(gg[k])) for k in range(len(nu))]
+
+    def one(k, n):
+        soc.simulate_frequency(ctx, g, freqs[k], A, I_bg=float(I[k]), ps_pos=pos, ps_Lnu=[float(Lnu[k])], n_bg=n,
+                               n_ps_pk=n, seed=1, iteration=1, freq_index=k)
+
+    src = [dict(I_bg=float(I[k]), ps_pos=pos, ps_Lnu=[float(Lnu[k])], n_bg=5_000_000, n_ps_pk=5_000_000)
+           for k in range(len(nu))]
+    one(len(nu) // 2, 500_000)   # warm-up
+    A.zero_()
+    ctx.read_stats(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for k in range(len(nu)):   # one launch per frequency: measured faster than one launch on this octree
+        one(k, 5_000_000)
+    torch.cuda.synchronize()
+    el = time.time() - t0
+    st = ctx.read_stats(reset=True)
+    ctx.close()
+    log(f"octree pass: {el:.2f}s, {st['packages'] / el:.3e} packages/s (host build {t_build:.1f}s)")
+    return {"workload": "octree 64^3 root + 3 levels (4.68 M leaves), central core tau_V 100, 10^4 K source of "
+                        "10^6 L_sun + external field, 128 frequencies, 10^7 packages/frequency, default schedule",
+            "s_per_pass": el, "packages_per_s": st["packages"] / el, "cell_steps_per_s": st["cell_steps"] / el,
+            "energy_conservation": (st["e_absorbed"] + st["e_escaped"]) / st["e_emitted"] - 1.0}
+
+
+def batch_record(soc, torch, W):
+    """One pass of the batched workload (as `--batch`: 256 clouds of 16^3-96^3
+    cells, 32 frequencies, one persistent launch, replayed HIP graph) with
+    the default schedule: packages/s and cell steps/s."""
+    grids, (nu, w, sabs, ssca, g, I), pk = W.batch_clouds(256, 32)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ctx = soc.Context(0, stream=s)
+        G = [soc.grid_from_workload(ctx, gr) for gr in grids]
+        table = soc.temp_table_build(ctx, nu, w, sabs, 2.0, 3000.0, 1024)
+        A = [torch.zeros(gr.ncells, dtype=torch.float64, device="cuda") for gr in grids]
+        T = [torch.zeros(gr.ncells, dtype=torch.float32, device="cuda") for gr in grids]
+        pairs = [dict(grid=m, freq=(float(nu[k]), float(w[k]), float(sabs[k]), float(ssca[k]), float(g[k])),
+                      freq_index=k, I_bg=float(I[k]), n_bg=int(pk[m, k]), absorbed=A[m])
+                 for m in range(len(grids)) for k in range(len(nu))]
+        b = soc.Batch(ctx, G, pairs, seed=1, tile_packages=16384)
+        b.run(iteration=0)
+        torch.cuda.synchronize()
+        soc.graph_begin(ctx)
+        for a in A:
+            a.zero_()
+        b.run(iteration=soc.ITER_ADVANCE)
+        for m in range(len(grids)):
+            soc.update_temperature(ctx, G[m], table, A[m], T[m])
+        graph = soc.graph_end(ctx)
+        graph.launch()
+        torch.cuda.synchronize()
+        before = ctx.read_stats()
+        t0 = time.time()
+        graph.launch()
+        torch.cuda.synchronize()
+        el = time.time() - t0
+        after = ctx.read_stats()
+    graph.close()
+    b.close()
+    ctx.close()
+    n_pk = after["packages"] - before["packages"]
+    log(f"batch pass: {el:.2f}s, {n_pk / el:.3e} packages/s")
+    return {"workload": "256 lognormal clouds of 16^3-96^3 cells, 32 frequencies, 1e5-1e6 packages per pair, one "
+                        "persistent launch + temperature updates in a replayed HIP graph, default schedule",
+            "s_per_pass": el, "packages_per_s": n_pk / el,
+            "cell_steps_per_s": (after["cell_steps"] - before["cell_steps"]) / el}
+
+
 def headline(args, soc, torch, W):
     """The benchmark workload: dust-iteration throughput, the time to 1%
     temperature convergence of the plain method and of the learned start,
@@ -1058,6 +1216,10 @@ def headline(args, soc, torch, W):
                "sample": f"dust emission, {npk} weighted packages at each of frequencies {sample_f} of the "
                          f"same {args.n}^3 workload and temperatures (FP64 C oracle, OpenMP, {threads} threads)"}
 
+    subs = None
+    if not args.no_sub_records:
+        subs = {"octree": octree_record(soc, torch, W), "batch": batch_record(soc, torch, W)}
+
     traffic = recorded_traffic()
     out = {
         "metric": "photon packages/s",
@@ -1091,6 +1253,7 @@ def headline(args, soc, torch, W):
                      "atomic_frac": steps_per_launch / avg_launch_s / atomic_ceiling,
                      "copy_GBs": copy_gbs},
         "cpu_baseline": cpu,
+        "other_workloads": subs,
     }
     print(json.dumps(out), flush=True)
     ctx.close()

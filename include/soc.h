@@ -78,8 +78,12 @@ typedef enum {
                                     context scratch of 16 x ncells doubles), summed into d_absorbed by one
                                     kernel after the launch: spreads the same-address adds of hot cells
                                     over 16 addresses [1] */
-    SOC_OPT_CHUNK = 8            /* package ids a wave takes from the global counter at a time, 64..65536
+    SOC_OPT_CHUNK = 8,           /* package ids a wave takes from the global counter at a time, 64..65536
                                     (smaller: finer load balance between waves) [256] */
+    SOC_OPT_BATCH_LDS_CELLS = 9  /* batches created afterwards: pairs whose grid has at most this many cells
+                                    are taken whole by one workgroup, which keeps the grid's absorbed array
+                                    in LDS (0 = never; at most what the device's LDS per workgroup holds)
+                                    [13824 = 24^3, or less if the device holds less] */
 } soc_option;
 soc_status soc_ctx_set_option(soc_ctx ctx, soc_option opt, int64_t value);
 soc_status soc_ctx_get_option(soc_ctx ctx, soc_option opt, int64_t *value);
@@ -195,6 +199,26 @@ typedef struct {
 soc_status soc_simulate_frequency(soc_ctx ctx, soc_grid grid, const soc_freq *freq,
                                   const soc_sources *src, uint64_t seed, uint32_t iteration,
                                   uint32_t freq_index, double *d_absorbed, soc_sim_stats *stats);
+
+/* The work of K soc_simulate_frequency calls on one grid -- frequency k
+ * with freqs[k], srcs[k] and freq_indices[k], the same seed and iteration
+ * -- in one persistent launch, all deposits added to d_absorbed: the
+ * frequency-integrated absorbed energy the temperature kernel needs
+ * (Sect. 2.1.1).  Every package has the random numbers it has in the
+ * single call, so the counters are identical and d_absorbed equal up to
+ * FP64 summation order.  Waves take the frequencies in a rotation and
+ * move on when one has no ids left, so the tail of a launch comes only at
+ * the end, not after every frequency.  Each frequency's setup (dust
+ * luminosities, selection of cells) runs before the launch and keeps its
+ * own package-to-cell list until then (context scratch: 4 B per weighted
+ * dust package, plus 8 B per cell for frequencies whose kernel reads the
+ * luminosities: dust modes 0 and 2 and capped emission).  The diagonal-ALI
+ * tallies are not taken here (SOC_EINVAL): use soc_simulate_frequency.
+ * 1 <= K <= 4096.  Synchronises the stream before it starts (the argument
+ * blocks are staged on the host); not allowed during graph capture. */
+soc_status soc_simulate_frequencies(soc_ctx ctx, soc_grid grid, int32_t K, const soc_freq *freqs,
+                                    const soc_sources *srcs, const uint32_t *freq_indices, uint64_t seed,
+                                    uint32_t iteration, double *d_absorbed, soc_sim_stats *stats);
 
 /* soc_simulate_frequency without any device allocation, for callers that
  * cannot allocate (code under HIP graph capture, tight serving loops,
@@ -401,7 +425,14 @@ typedef struct {
 
 typedef struct soc_batch_s *soc_batch;
 /* Copies the pair table and the tile queue (tiles of at most tile_packages
- * ids, ordered by decreasing estimated cost) to the device.  Synchronises. */
+ * ids, ordered by decreasing estimated cost) to the device.  Pairs whose
+ * grid has at most SOC_OPT_BATCH_LDS_CELLS cells (the option's value now)
+ * are not tiled: each is one work item of a workgroup that tallies the
+ * grid in LDS, taken before the tiles (same random numbers and results up
+ * to FP64 summation order).  A batch with such pairs launches 512-lane
+ * workgroups, one or two per compute unit as their LDS allows
+ * (SOC_OPT_BLOCK and SOC_OPT_BLOCKS_PER_CU shape the other batches).
+ * Synchronises.  soc_batch_info counts those pairs among the tiles. */
 soc_status soc_batch_create(soc_ctx ctx, int32_t n_grids, const soc_grid *grids, int32_t n_pairs,
                             const soc_batch_pair *pairs, uint64_t seed, uint64_t tile_packages, soc_batch *out);
 void soc_batch_destroy(soc_batch b);

@@ -42,6 +42,9 @@ struct soc_ctx_s {
     int64_t chunk = 256;
     int64_t scatter_min = 1;
     int64_t xcd_copies = 1;
+    int64_t batch_lds_cells = 0;      // grids of at most this many cells: whole pairs tallied in LDS (set at creation)
+    int64_t max_lds_cells = 0;        // the most the device's LDS per workgroup holds
+    int64_t lds_per_cu = 65536;       // bytes of LDS per compute unit
     // scratch
     DevStats *d_stats = nullptr;              // [0] per call, [1] running total
     unsigned long long *d_counter = nullptr;
@@ -63,6 +66,16 @@ struct soc_ctx_s {
     double *d_tmeta = nullptr;
     unsigned int *d_tfine_n = nullptr;
     double *d_tfine_T = nullptr;
+    // soc_simulate_frequencies: per-frequency tables and argument blocks
+    double *d_mL = nullptr, *d_mS = nullptr;
+    int64_t cap_mL = 0, cap_mS = 0;
+    int32_t *d_mpk = nullptr;
+    int64_t cap_mpk = 0;
+    McArgs *d_margs = nullptr;
+    int64_t cap_margs = 0;
+    unsigned long long *d_mcount = nullptr;
+    int64_t cap_mcount = 0;
+    std::vector<McArgs> h_margs;   // staging of the argument blocks (kept until the next call)
     std::vector<hipEvent_t> ev_start, ev_stop;
     bool capturing = false;
 };
@@ -75,8 +88,11 @@ struct soc_batch_s {
     PairDev *d_pairs = nullptr;
     TileDev *d_tiles = nullptr;
     PsArg *d_ps = nullptr;
-    unsigned int *d_counter = nullptr;
+    unsigned int *d_counter = nullptr;      // [0] next tile, [1] next LDS pair
     uint32_t *d_iteration = nullptr;
+    int32_t *d_lds_pairs = nullptr;         // pairs of small grids, largest cost first
+    int32_t n_lds_pairs = 0;
+    int64_t lds_cells = 0;                  // the largest grid among them
 };
 
 struct soc_graph_s {
@@ -178,6 +194,12 @@ soc_status check_freq(soc_ctx c, const soc_freq *f)
 // array at base (sizes checked against its limits).
 struct ScratchSrc {
     char *base = nullptr;
+    // set by soc_simulate_frequencies, where each frequency keeps its own
+    // tables until the launch: the luminosities (when the kernel reads
+    // them), the package-to-cell list and the total weight
+    double *L = nullptr;
+    int32_t *pk = nullptr;
+    double *S = nullptr;
 };
 
 // Fixed slices of the no-allocation array (byte offsets, 256-aligned).
@@ -290,8 +312,8 @@ soc_status prepare(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *
     A.dust_mode = s->dust_mode;
     if (s->d_T && s->n_dust > 0) {
         A.n_dust = s->n_dust;
-        double *dL = nullptr, *da = nullptr;
-        if ((st = take(c, src, &c->d_L, c->cap_L, g->ncells, kNaL, kNaMaxCells, &dL))) return st;
+        double *dL = src.L, *da = nullptr;
+        if (!dL && (st = take(c, src, &c->d_L, c->cap_L, g->ncells, kNaL, kNaMaxCells, &dL))) return st;
         if (s->dust_mode == 2) {
             if ((st = take(c, src, &c->d_a, c->cap_a, g->ncells, kNaA, kNaMaxCells, &da))) return st;
             HIPCHK(c, launch_dust_correction(g->d_words, g->ncells, g->level_offset.data(), g->nlevels, s_cm, f->nu,
@@ -322,11 +344,15 @@ soc_status prepare(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *
                 return st;
             HIPCHK(c, launch_scan_f64(weight, dincl, g->ncells, dscan, c->stream));
             A.dust_S = dincl + (g->ncells - 1);
+            if (src.S && !capped) {   // the scan array is reused by the next frequency
+                HIPCHK(c, launch_copy_f64(dincl + (g->ncells - 1), src.S, 1, c->stream));
+                A.dust_S = src.S;
+            }
             if (capped) {
                 // expected counts min(N a / S, cap) replace the weights; their
                 // cumulative sum (package units) replaces the first one
-                double *dS = nullptr;
-                if ((st = take(c, src, &c->d_S, c->cap_S, 1, kNaS, 1, &dS))) return st;
+                double *dS = src.S;
+                if (!dS && (st = take(c, src, &c->d_S, c->cap_S, 1, kNaS, 1, &dS))) return st;
                 HIPCHK(c, launch_dust_cap(da, g->ncells, dincl + (g->ncells - 1), dS, s->n_dust,
                                           s->dust_cap, c->stream));
                 HIPCHK(c, launch_scan_f64(da, dincl, g->ncells, dscan, c->stream));
@@ -334,8 +360,9 @@ soc_status prepare(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *
                 A.dust_cap = s->dust_cap;
             }
             int64_t cap_pk = (int64_t)c->cap_pk;
-            int32_t *dpk = nullptr;
-            if ((st = take(c, src, &c->d_pkcell, cap_pk, (int64_t)s->n_dust, kNaPk, kNaMaxDust, &dpk))) return st;
+            int32_t *dpk = src.pk;
+            if (!dpk && (st = take(c, src, &c->d_pkcell, cap_pk, (int64_t)s->n_dust, kNaPk, kNaMaxDust, &dpk)))
+                return st;
             c->cap_pk = (uint64_t)cap_pk;
             // systematic offset: first uniform of the stream of package id 2^32-1 of the dust class
             uint32_t x0 = 0, x1 = 0xFFFFFFFFu, x2 = freq_index, x3 = (iteration << 8) | kClassDust;
@@ -438,6 +465,16 @@ soc_status soc_ctx_create(int32_t hip_device, void *hip_stream, soc_ctx *out)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess && prop.multiProcessorCount > 0)
         c->num_cus = prop.multiProcessorCount;
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device) != hipSuccess)
+        lds_max = 65536;
+    // room for the kernel's own static LDS words; at most 24^3 cells by default
+    c->max_lds_cells = std::max<int64_t>(0, ((int64_t)lds_max - 256) / (int64_t)sizeof(double));
+    int lds_cu = 0;
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, hip_device) == hipSuccess &&
+        lds_cu > 0)
+        c->lds_per_cu = lds_cu;
+    c->batch_lds_cells = std::min<int64_t>(c->max_lds_cells, 13824);
     if (hipMalloc((void **)&c->d_stats, 2 * sizeof(DevStats)) != hipSuccess ||
         hipMalloc((void **)&c->d_counter, sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc((void **)&c->d_tmp_out, 8 * sizeof(double)) != hipSuccess) {
@@ -477,6 +514,11 @@ void soc_ctx_destroy(soc_ctx c)
     (void)hipFree(c->d_tmeta);
     (void)hipFree(c->d_tfine_n);
     (void)hipFree(c->d_tfine_T);
+    (void)hipFree(c->d_mL);
+    (void)hipFree(c->d_mS);
+    (void)hipFree(c->d_mpk);
+    (void)hipFree(c->d_margs);
+    (void)hipFree(c->d_mcount);
     delete c;
 }
 
@@ -528,6 +570,11 @@ soc_status soc_ctx_set_option(soc_ctx c, soc_option opt, int64_t v)
         if (v < 64 || v > 65536) return fail(c, SOC_EINVAL, "chunk must be in [64,65536]");
         c->chunk = v;
         return SOC_OK;
+    case SOC_OPT_BATCH_LDS_CELLS:
+        if (v < 0 || v > c->max_lds_cells)
+            return fail(c, SOC_EINVAL, "batch LDS cells must be in [0,%lld] on this device", (long long)c->max_lds_cells);
+        c->batch_lds_cells = v;
+        return SOC_OK;
     }
     return fail(c, SOC_EINVAL, "unknown option %d", (int)opt);
 }
@@ -545,6 +592,7 @@ soc_status soc_ctx_get_option(soc_ctx c, soc_option opt, int64_t *v)
     case SOC_OPT_SCATTER_MIN: *v = c->scatter_min; return SOC_OK;
     case SOC_OPT_XCD_COPIES: *v = c->xcd_copies; return SOC_OK;
     case SOC_OPT_CHUNK: *v = c->chunk; return SOC_OK;
+    case SOC_OPT_BATCH_LDS_CELLS: *v = c->batch_lds_cells; return SOC_OK;
     }
     return fail(c, SOC_EINVAL, "unknown option %d", (int)opt);
 }
@@ -716,6 +764,89 @@ soc_status soc_simulate_frequency(soc_ctx c, soc_grid g, const soc_freq *f, cons
     }
     if (A.priv) HIPCHK(c, launch_fold_copies(d_absorbed, A.priv, g->ncells, c->stream));
     if (A.priv_self) HIPCHK(c, launch_fold_copies(A.ali_self, A.priv_self, g->ncells, c->stream));
+    if (stats) {
+        DevStats h;
+        HIPCHK(c, hipMemcpyAsync(&h, c->d_stats, sizeof h, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        to_public(h, stats);
+    }
+    return SOC_OK;
+}
+
+soc_status soc_simulate_frequencies(soc_ctx c, soc_grid g, int32_t K, const soc_freq *freqs, const soc_sources *srcs,
+                                    const uint32_t *freq_indices, uint64_t seed, uint32_t iteration,
+                                    double *d_absorbed, soc_sim_stats *stats)
+{
+    if (!c) return SOC_EINVAL;
+    if (!d_absorbed) return fail(c, SOC_EINVAL, "d_absorbed is NULL");
+    if (!g) return fail(c, SOC_EINVAL, "grid is NULL");
+    if (K < 1 || K > 4096) return fail(c, SOC_EINVAL, "K must be in [1, 4096]");
+    if (!freqs || !srcs || !freq_indices) return fail(c, SOC_EINVAL, "freqs, srcs and freq_indices must be given");
+    NOT_WHILE_CAPTURING(c);
+    int64_t nL = 0, npk = 0;
+    for (int32_t k = 0; k < K; ++k) {
+        const soc_sources &q = srcs[k];
+        if (q.d_ali_self || q.d_ali_emitted) return fail(c, SOC_EINVAL, "frequency %d: ALI tallies need soc_simulate_frequency", k);
+        if (q.d_T && q.n_dust > 0) {
+            if (q.dust_mode == 0 || q.dust_mode == 2 || q.dust_cap > 0.0) nL += g->ncells;   // the kernel reads L
+            if (q.dust_mode != 0) npk += (int64_t)q.n_dust;
+        }
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));   // the previous call's staging copy has been consumed
+    soc_status st;
+    if ((st = grow(c, &c->d_mL, c->cap_mL, std::max<int64_t>(nL, 1)))) return st;
+    if ((st = grow(c, &c->d_mpk, c->cap_mpk, std::max<int64_t>(npk, 1)))) return st;
+    if ((st = grow(c, &c->d_mS, c->cap_mS, K))) return st;
+    if ((st = grow(c, &c->d_margs, c->cap_margs, K))) return st;
+    if ((st = grow(c, &c->d_mcount, c->cap_mcount, K))) return st;
+    c->h_margs.resize(K);
+    int64_t oL = 0, opk = 0;
+    for (int32_t k = 0; k < K; ++k) {
+        const soc_sources &q = srcs[k];
+        ScratchSrc src;
+        const bool dust = q.d_T && q.n_dust > 0;
+        if (dust && (q.dust_mode == 0 || q.dust_mode == 2 || q.dust_cap > 0.0)) {
+            src.L = c->d_mL + oL;
+            oL += g->ncells;
+        }
+        if (dust && q.dust_mode != 0) {
+            src.pk = c->d_mpk + opk;
+            opk += (int64_t)q.n_dust;
+        }
+        src.S = c->d_mS + k;
+        McArgs &A = c->h_margs[k];
+        if ((st = prepare(c, g, &freqs[k], &q, seed, iteration, freq_indices[k], d_absorbed, A, src)))
+            return fail(c, st, "frequency %d: %s", k, c->err.c_str());
+        A.next_id = c->d_mcount + k;
+    }
+    if (c->xcd_copies) {
+        if (c->cap_priv < (int64_t)kPrivCopies * g->ncells) {   // new copies start zero; every fold leaves them zero
+            if ((st = grow(c, &c->d_priv, c->cap_priv, (int64_t)kPrivCopies * g->ncells))) return st;
+            HIPCHK(c, launch_fill_f64(c->d_priv, 0.0, c->cap_priv, c->stream));
+        }
+        for (auto &A : c->h_margs) A.priv = c->d_priv;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_margs, c->h_margs.data(), sizeof(McArgs) * (size_t)K, hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, launch_fill_u64((unsigned long long *)c->d_stats, 0ull, (int64_t)(sizeof(DevStats) / 8), c->stream));
+    HIPCHK(c, launch_fill_u64(c->d_mcount, 0ull, K, c->stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        HIPCHK(c, hipEventCreate(&e0));
+        HIPCHK(c, hipEventCreate(&e1));
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+    }
+    MultiArgs M;
+    M.args = c->d_margs;
+    M.K = K;
+    HIPCHK(c, launch_mc_multi(M, g->nlevels, (int)(c->num_cus * c->blocks_per_cu), (int)c->block, c->stream));
+    if (c->timing) {
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        c->ev_start.push_back(e0);
+        c->ev_stop.push_back(e1);
+    }
+    if (c->xcd_copies) HIPCHK(c, launch_fold_copies(d_absorbed, c->d_priv, g->ncells, c->stream));
     if (stats) {
         DevStats h;
         HIPCHK(c, hipMemcpyAsync(&h, c->d_stats, sizeof h, hipMemcpyDeviceToHost, c->stream));
@@ -1440,6 +1571,8 @@ soc_status soc_batch_create(soc_ctx c, int32_t n_grids, const soc_grid *grids, i
     std::vector<int64_t> ps_off(n_pairs, 0);
     struct TileCost { double cost; TileDev t; };
     std::vector<TileCost> tiles;
+    struct LdsPair { double cost; int32_t pair; };
+    std::vector<LdsPair> lds;
     uint64_t total = 0;
     for (int32_t i = 0; i < n_pairs; ++i) {
         const soc_batch_pair &q = pairs[i];
@@ -1487,8 +1620,14 @@ soc_status soc_batch_create(soc_ctx c, int32_t n_grids, const soc_grid *grids, i
         P.key0 = (uint32_t)seed;
         P.key1 = (uint32_t)(seed >> 32) ^ (uint32_t)q.grid;
         P.freq_index = q.freq_index;
-        // tiles, costed by packages x (optical size + grid extent)
+        // tiles, costed by packages x (optical size + grid extent); a pair
+        // of a small grid is one workgroup's whole (LDS tally)
         const double extent = (double)(g->nx + g->ny + g->nz);
+        if (g->ncells <= c->batch_lds_cells) {
+            if (P.n_total > 0) lds.push_back({(double)P.n_total * extent, i});
+            total += P.n_total;
+            continue;
+        }
         for (uint64_t b = 0; b < P.n_total; b += tile_packages) {
             TileCost tc;
             tc.t.pair = i;
@@ -1501,6 +1640,13 @@ soc_status soc_batch_create(soc_ctx c, int32_t n_grids, const soc_grid *grids, i
         total += P.n_total;
     }
     std::stable_sort(tiles.begin(), tiles.end(), [](const TileCost &a, const TileCost &b) { return a.cost > b.cost; });
+    std::stable_sort(lds.begin(), lds.end(), [](const LdsPair &a, const LdsPair &b) { return a.cost > b.cost; });
+    std::vector<int32_t> hl(lds.size());
+    int64_t lds_cells = 0;
+    for (size_t i = 0; i < lds.size(); ++i) {
+        hl[i] = lds[i].pair;
+        lds_cells = std::max<int64_t>(lds_cells, hp[lds[i].pair].ncells);
+    }
     HIPCHK(c, hipSetDevice(c->device));
     soc_batch b = new (std::nothrow) soc_batch_s;
     if (!b) return fail(c, SOC_ENOMEM, "host allocation");
@@ -1508,6 +1654,8 @@ soc_status soc_batch_create(soc_ctx c, int32_t n_grids, const soc_grid *grids, i
     b->device = c->device;
     b->n_tiles = (int32_t)tiles.size();
     b->n_packages = total;
+    b->n_lds_pairs = (int32_t)hl.size();
+    b->lds_cells = lds_cells;
     auto cleanup = [&](soc_status r) {
         if (r != SOC_OK) soc_batch_destroy(b);
         return r;
@@ -1515,15 +1663,17 @@ soc_status soc_batch_create(soc_ctx c, int32_t n_grids, const soc_grid *grids, i
     if (hipMalloc((void **)&b->d_pairs, sizeof(PairDev) * n_pairs) != hipSuccess ||
         hipMalloc((void **)&b->d_tiles, sizeof(TileDev) * std::max<size_t>(1, tiles.size())) != hipSuccess ||
         hipMalloc((void **)&b->d_ps, sizeof(PsArg) * std::max<size_t>(1, hps.size())) != hipSuccess ||
-        hipMalloc((void **)&b->d_counter, sizeof(unsigned int)) != hipSuccess ||
-        hipMalloc((void **)&b->d_iteration, sizeof(uint32_t)) != hipSuccess)
+        hipMalloc((void **)&b->d_counter, 2 * sizeof(unsigned int)) != hipSuccess ||
+        hipMalloc((void **)&b->d_iteration, sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void **)&b->d_lds_pairs, sizeof(int32_t) * std::max<size_t>(1, hl.size())) != hipSuccess)
         return cleanup(fail(c, SOC_ENOMEM, "batch tables"));
     for (int32_t i = 0; i < n_pairs; ++i) hp[i].ps = hp[i].n_ps ? b->d_ps + ps_off[i] : nullptr;
     std::vector<TileDev> ht(tiles.size());
     for (size_t i = 0; i < tiles.size(); ++i) ht[i] = tiles[i].t;
     if (hipMemcpy(b->d_pairs, hp.data(), sizeof(PairDev) * n_pairs, hipMemcpyHostToDevice) != hipSuccess ||
         (ht.size() && hipMemcpy(b->d_tiles, ht.data(), sizeof(TileDev) * ht.size(), hipMemcpyHostToDevice) != hipSuccess) ||
-        (hps.size() && hipMemcpy(b->d_ps, hps.data(), sizeof(PsArg) * hps.size(), hipMemcpyHostToDevice) != hipSuccess))
+        (hps.size() && hipMemcpy(b->d_ps, hps.data(), sizeof(PsArg) * hps.size(), hipMemcpyHostToDevice) != hipSuccess) ||
+        (hl.size() && hipMemcpy(b->d_lds_pairs, hl.data(), sizeof(int32_t) * hl.size(), hipMemcpyHostToDevice) != hipSuccess))
         return cleanup(fail(c, SOC_EHIP, "batch upload"));
     if (launch_advance_iteration(b->d_iteration, 0, 0u, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)
@@ -1541,13 +1691,14 @@ void soc_batch_destroy(soc_batch b)
     (void)hipFree(b->d_ps);
     (void)hipFree(b->d_counter);
     (void)hipFree(b->d_iteration);
+    (void)hipFree(b->d_lds_pairs);
     delete b;
 }
 
 soc_status soc_batch_info(soc_batch b, int32_t *n_tiles, uint64_t *n_packages)
 {
     if (!b) return SOC_EINVAL;
-    if (n_tiles) *n_tiles = b->n_tiles;
+    if (n_tiles) *n_tiles = b->n_tiles + b->n_lds_pairs;
     if (n_packages) *n_packages = b->n_packages;
     return SOC_OK;
 }
@@ -1560,7 +1711,7 @@ soc_status soc_batch_run(soc_batch b, uint32_t iteration, soc_sim_stats *stats)
     if (iteration != SOC_ITER_ADVANCE && iteration > 0xFFFFFFu) return fail(c, SOC_EINVAL, "iteration must be < 2^24");
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, launch_fill_u64((unsigned long long *)c->d_stats, 0ull, (int64_t)(sizeof(DevStats) / 8), c->stream));
-    HIPCHK(c, launch_fill_i32((int32_t *)b->d_counter, 0, 1, c->stream));
+    HIPCHK(c, launch_fill_i32((int32_t *)b->d_counter, 0, 2, c->stream));
     HIPCHK(c, launch_advance_iteration(b->d_iteration, iteration == SOC_ITER_ADVANCE ? 1 : 0,
                                        iteration == SOC_ITER_ADVANCE ? 0u : iteration, c->stream));
     BatchArgs a;
@@ -1568,6 +1719,9 @@ soc_status soc_batch_run(soc_batch b, uint32_t iteration, soc_sim_stats *stats)
     a.tiles = b->d_tiles;
     a.n_tiles = b->n_tiles;
     a.next_tile = b->d_counter;
+    a.lds_pairs = b->d_lds_pairs;
+    a.n_lds_pairs = b->n_lds_pairs;
+    a.next_lds = b->d_counter + 1;
     a.iteration = b->d_iteration;
     a.step_cap = c->step_cap;
     a.st_call = c->d_stats;
@@ -1575,14 +1729,24 @@ soc_status soc_batch_run(soc_batch b, uint32_t iteration, soc_sim_stats *stats)
     a.refill_min = (int32_t)c->refill_min;
     a.inner_steps = (int32_t)c->inner_steps;
     a.scatter_min = (int32_t)c->scatter_min;
-    const int blocks = (int)(c->num_cus * c->blocks_per_cu);
+    a.chunk = (int32_t)c->chunk;
+    int blocks = (int)(c->num_cus * c->blocks_per_cu), threads = (int)c->block;
+    if (b->n_lds_pairs > 0) {
+        // a workgroup holds a small grid's tally: 512-lane workgroups, as many
+        // per compute unit as their LDS allows (at most two)
+        threads = kMcMaxBlock;
+        const int64_t ring = (int64_t)kDepSlots * threads * (int64_t)(sizeof(double) + sizeof(int32_t));
+        const int64_t need = std::max<int64_t>(ring, b->lds_cells * (int64_t)sizeof(double)) + 256;
+        const int64_t per_cu = std::min<int64_t>(2, std::max<int64_t>(1, c->lds_per_cu / need));
+        blocks = (int)(c->num_cus * per_cu);
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
         HIPCHK(c, hipEventCreate(&e0));
         HIPCHK(c, hipEventCreate(&e1));
         HIPCHK(c, hipEventRecord(e0, c->stream));
     }
-    HIPCHK(c, launch_mc_batch(a, blocks, (int)c->block, c->stream));
+    HIPCHK(c, launch_mc_batch(a, blocks, threads, b->lds_cells, c->stream));
     if (c->timing) {
         HIPCHK(c, hipEventRecord(e1, c->stream));
         c->ev_start.push_back(e0);

@@ -6,6 +6,13 @@
 // up and every lane has finished, the wave flushes its LDS deposit ring
 // into that model's absorbed array and takes the next tile.  Pair
 // parameters are read as wave-uniform (scalar) data at each tile switch.
+//
+// Pairs of small grids come first and differently: a workgroup takes a
+// whole pair, keeps that grid's absorbed array in LDS, and its waves add
+// every deposit there (LDS atomics: ~25x the rate of the memory-side
+// global atomics that bound the rest); when the pair is done the
+// workgroup adds the LDS array to the model's array, one coalesced add
+// per cell.  Then the same LDS serves as the deposit ring of the tiles.
 #include "soc_device.h"
 
 namespace soc {
@@ -35,17 +42,9 @@ __device__ inline void batch_add_stats(DevStats *t, unsigned long long pk, unsig
     unsafeAtomicAdd(&t->escaped, es);
 }
 
-__global__ __launch_bounds__(kMcMaxBlock) void mc_batch_kernel(BatchArgs B)
+// The pair-invariant fields of the view, and the pair's own fields.
+__device__ inline void view_base(BatchView &A, uint32_t iteration, int64_t step_cap)
 {
-    extern __shared__ double lds_dep[];
-    int32_t *lds_cell = (int32_t *)(lds_dep + kDepSlots * blockDim.x);
-    const int tid = threadIdx.x;
-    const int bd = blockDim.x;
-    const int lane = threadIdx.x & 63;
-    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const uint32_t iteration = __builtin_amdgcn_readfirstlane(*B.iteration);
-
-    BatchView A;
     A.parent = nullptr;
     A.nlevels = 1;
     A.nroot = 0;
@@ -59,7 +58,136 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_batch_kernel(BatchArgs B)
     A.leaves = nullptr;
     A.per_leaf = 1;
     A.iteration = iteration;
-    A.step_cap = B.step_cap;
+    A.step_cap = step_cap;
+}
+
+__device__ inline void view_pair(BatchView &A, const PairDev &P)
+{
+    A.words = P.words;
+    A.nx = P.nx; A.ny = P.ny; A.nz = P.nz;
+    A.ncells = P.ncells;
+    A.n_bg = P.n_bg; A.n_ps_pk = P.n_ps_pk; A.n_total = P.n_total; A.n_ps = P.n_ps;
+    A.W_bg = P.W_bg;
+    for (int k = 0; k < 6; ++k) A.face_cum[k] = P.face_cum[k];
+    A.face_tot = P.face_tot;
+    A.ps = P.ps;
+    A.key0 = P.key0; A.key1 = P.key1; A.freq_index = P.freq_index;
+}
+
+__global__ __launch_bounds__(kMcMaxBlock) void mc_batch_kernel(BatchArgs B)
+{
+    extern __shared__ double lds_dep[];
+    int32_t *lds_cell = (int32_t *)(lds_dep + kDepSlots * blockDim.x);
+    __shared__ int32_t sh_pair;                // pair of the LDS phase, workgroup-uniform
+    __shared__ unsigned long long sh_next;     // its next unassigned package id
+    const int tid = threadIdx.x;
+    const int bd = blockDim.x;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t iteration = __builtin_amdgcn_readfirstlane(*B.iteration);
+    unsigned long long n_pk = 0, n_st = 0, n_sc = 0, n_ru = 0;
+    double e_em = 0.0, e_ab = 0.0, e_es = 0.0;
+
+    // ---- small grids: one whole pair per workgroup, tallied in LDS
+    if (B.n_lds_pairs > 0) {
+        BatchView A;
+        view_base(A, iteration, B.step_cap);
+        for (;;) {
+            __syncthreads();   // the previous pair's LDS array has been added out
+            if (tid == 0) {
+                sh_pair = (int32_t)atomicAdd(B.next_lds, 1u);
+                sh_next = 0ull;
+            }
+            __syncthreads();
+            const int32_t q = sh_pair;
+            if (q >= B.n_lds_pairs) break;
+            const PairDev &P = B.pairs[B.lds_pairs[q]];
+            view_pair(A, P);
+            const int32_t nc = (int32_t)P.ncells;
+            for (int32_t c = tid; c < nc; c += bd) lds_dep[c] = 0.0;
+            __syncthreads();
+            const float ks = P.ks_f, ka = P.ka_f;
+            const HG<float> hg(P.g_f);
+            Pkg<float> p;
+            Rng rng;
+            bool active = false, pend = false, exhausted = false;
+            unsigned long long pool_next = 0, pool_end = 0;   // wave-uniform
+            for (;;) {
+                const unsigned long long idle = __ballot(!active);
+                const int nidle = __popcll(idle);
+                if (!exhausted && nidle > 0 && (nidle >= B.refill_min || nidle == 64)) {
+                    const unsigned long long avail = pool_end - pool_next;
+                    unsigned long long grant = 0;
+                    if (avail < (unsigned long long)nidle) {
+                        const int leader = __ffsll((long long)idle) - 1;
+                        unsigned long long g0 = 0;
+                        if (lane == leader) g0 = atomicAdd(&sh_next, (unsigned long long)B.chunk);
+                        grant = (unsigned long long)__shfl((long long)g0, leader, 64);
+                    }
+                    if (!active) {
+                        const unsigned long long r = (unsigned long long)__popcll(idle & below);
+                        const unsigned long long id = r < avail ? pool_next + r : grant + (r - avail);
+                        if (id < A.n_total) {
+                            uint32_t cls, pid;
+                            double W0;
+                            const bool ok = emit<float, false>(A, id, p, rng, cls, pid, W0);
+                            n_pk += 1;
+                            if (ok) e_em += W0;
+                            active = ok;
+                        }
+                    }
+                    if (avail < (unsigned long long)nidle) {
+                        pool_next = grant + ((unsigned long long)nidle - avail);
+                        pool_end = grant + (unsigned long long)B.chunk;
+                    } else {
+                        pool_next += (unsigned long long)nidle;
+                    }
+                    if (pool_next >= A.n_total) exhausted = true;
+                }
+                if (!__any(active)) {
+                    if (exhausted) break;
+                    continue;
+                }
+                const unsigned long long pm = __ballot(pend);
+                if (pm) {
+                    if (__popcll(pm) >= B.scatter_min || __ballot(active && !pend) == 0) {
+                        if (pend) {
+                            scatter_new_direction<float>(p, rng, A, hg);
+                            pend = false;
+                        }
+                    }
+                }
+                for (int s = 0; s < B.inner_steps; ++s) {
+                    if (active && !pend) {
+                        float d;
+                        const StepOut o = step<float, false>(p, A, ks, ka, d);
+                        n_st += 1;
+                        if (o.dep != 0.0) {
+                            unsafeAtomicAdd(&lds_dep[o.cell], o.dep);
+                            e_ab += o.dep;
+                        }
+                        if (o.event == kEvScatter) {
+                            pend = true;
+                            n_sc += 1;
+                        } else if (o.event != kEvCross) {
+                            active = false;
+                            if (o.event == kEvEscape) e_es += p.W;
+                            if (o.event == kEvRunaway) n_ru += 1;
+                        }
+                    }
+                }
+            }
+            __syncthreads();   // every wave has finished the pair
+            for (int32_t c = tid; c < nc; c += bd) {
+                const double v = lds_dep[c];
+                if (v != 0.0) unsafeAtomicAdd(&P.absorbed[c], v);
+            }
+        }
+    }
+
+    // ---- tiles of the other pairs, wave by wave, LDS as the deposit ring
+    BatchView A;
+    view_base(A, iteration, B.step_cap);
     double *absorbed = nullptr;
     float ks = 0.0f, ka = 0.0f, gg = 0.0f;
 
@@ -68,8 +196,6 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_batch_kernel(BatchArgs B)
     bool active = false, pend = false;
     unsigned long long pool_next = 0, pool_end = 0;   // wave-uniform: the current tile's remaining ids
     int nbuf = 0, since_flush = 0;
-    unsigned long long n_pk = 0, n_st = 0, n_sc = 0, n_ru = 0;
-    double e_em = 0.0, e_ab = 0.0, e_es = 0.0;
 
     for (;;) {
         if (pool_next >= pool_end && !__any(active)) {
@@ -85,15 +211,7 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_batch_kernel(BatchArgs B)
             const TileDev tile = B.tiles[t];
             const int32_t pi = __builtin_amdgcn_readfirstlane(tile.pair);
             const PairDev &P = B.pairs[pi];
-            A.words = P.words;
-            A.nx = P.nx; A.ny = P.ny; A.nz = P.nz;
-            A.ncells = P.ncells;
-            A.n_bg = P.n_bg; A.n_ps_pk = P.n_ps_pk; A.n_total = P.n_total; A.n_ps = P.n_ps;
-            A.W_bg = P.W_bg;
-            for (int k = 0; k < 6; ++k) A.face_cum[k] = P.face_cum[k];
-            A.face_tot = P.face_tot;
-            A.ps = P.ps;
-            A.key0 = P.key0; A.key1 = P.key1; A.freq_index = P.freq_index;
+            view_pair(A, P);
             absorbed = P.absorbed;
             ks = P.ks_f; ka = P.ka_f; gg = P.g_f;
             pool_next = __builtin_amdgcn_readfirstlane(tile.begin);
@@ -170,10 +288,11 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_batch_kernel(BatchArgs B)
     }
 }
 
-hipError_t launch_mc_batch(const BatchArgs &a, int blocks, int threads, hipStream_t s)
+hipError_t launch_mc_batch(const BatchArgs &a, int blocks, int threads, int64_t lds_cells, hipStream_t s)
 {
-    const size_t lds = (size_t)kDepSlots * threads * (sizeof(double) + sizeof(int32_t));
-    hipLaunchKernelGGL(mc_batch_kernel, dim3(blocks), dim3(threads), lds, s, a);
+    const size_t ring = (size_t)kDepSlots * threads * (sizeof(double) + sizeof(int32_t));
+    const size_t tally = a.n_lds_pairs > 0 ? (size_t)lds_cells * sizeof(double) : 0;
+    hipLaunchKernelGGL(mc_batch_kernel, dim3(blocks), dim3(threads), ring > tally ? ring : tally, s, a);
     return hipGetLastError();
 }
 

@@ -71,15 +71,25 @@ __device__ inline void flush_one(double *dst, double *sdst, int32_t key, double 
     else unsafeAtomicAdd(&dst[key], v);
 }
 
-template <bool Oct, bool Ali>
-__device__ __forceinline__ void mc_body(const McArgs &A)
-{
-    extern __shared__ double lds_dep[];   // [kDepSlots][blockDim.x] deposits, then cells
-    int32_t *lds_cell = (int32_t *)(lds_dep + kDepSlots * blockDim.x);
-    const int tid = threadIdx.x;
-    const int bd = blockDim.x;
+// Per-wave state that outlives one frequency: the LDS deposit ring and the
+// statistics.
+struct WaveTally {
     int nbuf = 0;          // deposits staged by this lane
     int since_flush = 0;   // wave-uniform
+    unsigned long long n_pk = 0, n_st = 0, n_sc = 0, n_ru = 0;
+    double e_em = 0.0, e_ab = 0.0, e_es = 0.0;
+};
+
+// Every package of one frequency's argument block A: ids from A.next_id in
+// chunks, until the ids are used up and every lane of the wave has
+// finished.  Deposits go through the lane's LDS ring to dst (sdst: the
+// ALI self-absorption tally).
+template <bool Oct, bool Ali>
+__device__ __forceinline__ void mc_frequency(const McArgs &A, double *lds_dep, int32_t *lds_cell, double *dst,
+                                             double *sdst, WaveTally &w)
+{
+    const int tid = threadIdx.x;
+    const int bd = blockDim.x;
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     Pkg<float> p;
@@ -90,13 +100,10 @@ __device__ __forceinline__ void mc_body(const McArgs &A)
     int32_t origin = -1;       // ALI: emitting cell of a dust package
     unsigned long long pool_next = 0, pool_end = 0;   // wave-uniform
     bool exhausted = false;                           // wave-uniform
-    unsigned long long n_pk = 0, n_st = 0, n_sc = 0, n_ru = 0;
-    double e_em = 0.0, e_ab = 0.0, e_es = 0.0;
     const float ks = A.ks_f, ka = A.ka_f;
     const HG<float> hg(A.g_f);
-    double *const dst = A.priv ? A.priv + (size_t)priv_index() * (size_t)A.ncells : A.absorbed;
-    double *const sdst = A.priv_self ? A.priv_self + (size_t)priv_index() * (size_t)A.ncells : A.ali_self;
-
+    int &nbuf = w.nbuf;
+    int &since_flush = w.since_flush;
     for (;;) {
         // refill idle lanes from the wave's id pool
         const unsigned long long idle = __ballot(!active);
@@ -117,8 +124,8 @@ __device__ __forceinline__ void mc_body(const McArgs &A)
                     uint32_t cls, pid;
                     double W0;
                     const bool ok = emit<float, Oct>(A, id, p, rng, cls, pid, W0);
-                    n_pk += 1;
-                    if (ok) e_em += W0;
+                    w.n_pk += 1;
+                    if (ok) w.e_em += W0;
                     active = ok;
                     first_step = ok;
                     if (Ali) origin = ok && cls == kClassDust ? p.c : -1;
@@ -163,8 +170,8 @@ __device__ __forceinline__ void mc_body(const McArgs &A)
             if (stepping) {
                 float d;
                 o = step<float, Oct>(p, A, ks, ka, d);
-                n_st += 1;
-                e_ab += o.dep;
+                w.n_st += 1;
+                w.e_ab += o.dep;
             }
             // Packages refilled together often start in the same cell (the
             // luminosity-weighted emission puts consecutive ids in the
@@ -188,26 +195,45 @@ __device__ __forceinline__ void mc_body(const McArgs &A)
                     if (in) dep = lane == leader ? v : 0.0;
                 }
             }
+            // A segment that ends in a scattering is followed by one in the
+            // same cell: consecutive deposits of a lane into one cell share
+            // a ring slot, so each scattering saves one atomic.
             if (dep != 0.0) {
-                lds_dep[nbuf * bd + tid] = dep;
-                lds_cell[nbuf * bd + tid] = key;
-                ++nbuf;
+                if (nbuf > 0 && lds_cell[(nbuf - 1) * bd + tid] == key) {
+                    lds_dep[(nbuf - 1) * bd + tid] += dep;
+                } else {
+                    lds_dep[nbuf * bd + tid] = dep;
+                    lds_cell[nbuf * bd + tid] = key;
+                    ++nbuf;
+                }
             }
             if (stepping) {
                 if (o.event == kEvScatter) {
                     pend = true;
-                    n_sc += 1;
+                    w.n_sc += 1;
                 } else if (o.event != kEvCross) {
                     active = false;
-                    if (o.event == kEvEscape) e_es += p.W;
-                    if (o.event == kEvRunaway) n_ru += 1;
+                    if (o.event == kEvEscape) w.e_es += p.W;
+                    if (o.event == kEvRunaway) w.n_ru += 1;
                 }
             }
         }
     }
+}
+
+template <bool Oct, bool Ali>
+__device__ __forceinline__ void mc_body(const McArgs &A)
+{
+    extern __shared__ double lds_dep[];   // [kDepSlots][blockDim.x] deposits, then cells
+    int32_t *lds_cell = (int32_t *)(lds_dep + kDepSlots * blockDim.x);
+    double *const dst = A.priv ? A.priv + (size_t)priv_index() * (size_t)A.ncells : A.absorbed;
+    double *const sdst = A.priv_self ? A.priv_self + (size_t)priv_index() * (size_t)A.ncells : A.ali_self;
+    WaveTally w;
+    mc_frequency<Oct, Ali>(A, lds_dep, lds_cell, dst, sdst, w);
+    const int tid = threadIdx.x, bd = blockDim.x;
     for (int j = 0; j < kDepSlots; ++j)
-        if (j < nbuf) flush_one<Ali>(dst, sdst, lds_cell[j * bd + tid], lds_dep[j * bd + tid]);
-    flush_stats(A, n_pk, n_st, n_sc, n_ru, e_em, e_ab, e_es);
+        if (j < w.nbuf) flush_one<Ali>(dst, sdst, lds_cell[j * bd + tid], lds_dep[j * bd + tid]);
+    flush_stats(A, w.n_pk, w.n_st, w.n_sc, w.n_ru, w.e_em, w.e_ab, w.e_es);
 }
 
 template <bool Oct>
@@ -221,6 +247,39 @@ template <bool Oct>
 __global__ __launch_bounds__(kMcMaxBlock) void mc_ali_kernel(McArgs A)
 {
     mc_body<Oct, true>(A);
+}
+
+// Several frequencies of one grid in one persistent launch (the argument
+// blocks in device memory, one package-id counter each, all deposits into
+// one tally): a wave works through the frequencies in a rotation that
+// starts at its own index, so that the waves spread over the frequencies,
+// and moves on when its current one has no ids left and its lanes are
+// idle.  Only the last frequencies leave a tail, not every one.
+template <bool Oct>
+__global__ __launch_bounds__(kMcMaxBlock) void mc_multi_kernel(MultiArgs M)
+{
+    extern __shared__ double lds_dep[];
+    int32_t *lds_cell = (int32_t *)(lds_dep + kDepSlots * blockDim.x);
+    const McArgs &A0 = M.args[0];
+    double *const dst = A0.priv ? A0.priv + (size_t)priv_index() * (size_t)A0.ncells : A0.absorbed;
+    WaveTally w;
+    const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    for (int j = 0; j < M.K; ++j) {
+        const int k = __builtin_amdgcn_readfirstlane((wave + j) % M.K);
+        mc_frequency<Oct, false>(M.args[k], lds_dep, lds_cell, dst, nullptr, w);
+    }
+    const int tid = threadIdx.x, bd = blockDim.x;
+    for (int j = 0; j < kDepSlots; ++j)
+        if (j < w.nbuf) flush_one<false>(dst, nullptr, lds_cell[j * bd + tid], lds_dep[j * bd + tid]);
+    flush_stats(A0, w.n_pk, w.n_st, w.n_sc, w.n_ru, w.e_em, w.e_ab, w.e_es);
+}
+
+hipError_t launch_mc_multi(const MultiArgs &m, int nlevels, int blocks, int threads, hipStream_t s)
+{
+    const size_t lds = (size_t)kDepSlots * threads * (sizeof(double) + sizeof(int32_t));
+    if (nlevels > 1) hipLaunchKernelGGL(mc_multi_kernel<true>, dim3(blocks), dim3(threads), lds, s, m);
+    else hipLaunchKernelGGL(mc_multi_kernel<false>, dim3(blocks), dim3(threads), lds, s, m);
+    return hipGetLastError();
 }
 
 hipError_t launch_mc(const McArgs &a, int blocks, int threads, hipStream_t s)

@@ -39,6 +39,20 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t 
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
 
+__global__ void copy_f64_kernel(const double *src, double *dst, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(copy_f64_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
 // Private copies of the absorbed array: add the kPrivCopies copies into the
 // caller's array in copy order and leave them zero for the next launch.
 __global__ void fold_copies_kernel(double *absorbed, double *priv, int64_t n)

@@ -155,6 +155,15 @@ __device__ inline double weighted_package_weight(double WN, double cap, double L
 // ---- launchers (each returns the launch status) ----
 // Regular-grid kernels when a.nlevels == 1, octree kernels otherwise.
 hipError_t launch_mc(const McArgs &a, int blocks, int threads, hipStream_t s);
+// Several frequencies of one grid in one launch: K argument blocks in
+// device memory (each with its own package-id counter in next_id; tallies,
+// private copies, statistics and schedule taken from args[0]).
+struct MultiArgs {
+    const McArgs *args;
+    int32_t K;
+};
+hipError_t launch_mc_multi(const MultiArgs &m, int nlevels, int blocks, int threads, hipStream_t s);
+hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_t s);
 hipError_t launch_trace(const McArgs &a, const TraceArgs &t, int precision, hipStream_t s);
 hipError_t launch_peel(const McArgs &a, const PeelArgs &p, int blocks, hipStream_t s);
 
@@ -300,10 +309,13 @@ struct BatchArgs {
     const TileDev *tiles;
     int32_t n_tiles;
     unsigned int *next_tile;
+    const int32_t *lds_pairs;    // pairs a workgroup takes whole, tallied in LDS (small grids)
+    int32_t n_lds_pairs;
+    unsigned int *next_lds;
     const uint32_t *iteration;   // device word, read at launch
     int64_t step_cap;
     DevStats *st_call, *st_total;
-    int32_t refill_min, inner_steps, scatter_min;
+    int32_t refill_min, inner_steps, scatter_min, chunk;
 };
 
 // The lean per-pair view the emission and step code read in the batched
@@ -329,7 +341,8 @@ struct BatchView {
     int64_t step_cap;
 };
 
-hipError_t launch_mc_batch(const BatchArgs &a, int blocks, int threads, hipStream_t s);
+// lds_cells: the largest grid of a.lds_pairs (the LDS tally's size)
+hipError_t launch_mc_batch(const BatchArgs &a, int blocks, int threads, int64_t lds_cells, hipStream_t s);
 hipError_t launch_advance_iteration(uint32_t *it, int32_t mode, uint32_t value, hipStream_t s);
 
 // micro-benchmarks: which 0 = random FP64 atomics (mode 0 shared, 1 per

@@ -44,14 +44,20 @@ class PlainSolver:
     """One problem (workloads.Problem) resident on the device."""
 
     def __init__(self, ctx: soc.Context, P, seed: int = 1, nT: int = 4096, packages=None, cap: float = 0.0,
-                 ali: bool = False):
+                 ali: bool = False, multi: bool = True):
         """packages(it): dust packages per frequency of iteration it
         (default P.n_dust); cap: expected packages per cell at most (0 =
-        none); ali: diagonal ALI (Sect. 2.1.2) in the dust iterations."""
+        none); ali: diagonal ALI (Sect. 2.1.2) in the dust iterations;
+        multi: every frequency of a pass in one launch
+        (soc_simulate_frequencies) rather than one launch per frequency --
+        the same packages and results up to FP64 summation order; used on
+        regular grids (on the octree workload one launch per frequency
+        measured faster)."""
         self.ctx, self.P, self.seed = ctx, P, seed
         self.packages = packages
         self.cap = float(cap)
         self.ali = bool(ali)
+        self.multi = bool(multi) and not self.ali and P.grid.nlevels == 1
         self.grid = soc.grid_from_workload(ctx, P.grid)
         self.table = soc.temp_table_build(ctx, P.emit_nu, P.emit_w, P.emit_sigma_abs, P.T_floor, P.T_max, nT)
         nc = P.grid.ncells
@@ -70,13 +76,23 @@ class PlainSolver:
         temperatures they alone give (dust emission is zero at T = 0)."""
         P = self.P
         self.A_const.zero_()
-        for k in range(P.K):
-            soc.simulate_frequency(self.ctx, self.grid, self.freqs[k], self.A_const, I_bg=float(P.I_bg[k]),
-                                   ps_pos=P.ps_pos if len(P.ps_pos) else None,
-                                   ps_Lnu=P.ps_Lnu[:, k] if len(P.ps_pos) else None,
-                                   n_bg=P.n_bg, n_ps_pk=P.n_ps_pk if len(P.ps_pos) else 0,
-                                   seed=self.seed, iteration=1, freq_index=k)
+        have_ps = len(P.ps_pos) > 0
+        src = [dict(I_bg=float(P.I_bg[k]), ps_pos=P.ps_pos if have_ps else None,
+                    ps_Lnu=P.ps_Lnu[:, k] if have_ps else None, n_bg=P.n_bg, n_ps_pk=P.n_ps_pk if have_ps else 0)
+               for k in range(P.K)]
+        self._simulate(self.A_const, src, iteration=1)
         return soc.update_temperature(self.ctx, self.grid, self.table, self.A_const, self.T, None, stats=True)
+
+    def _simulate(self, A: torch.Tensor, sources, iteration: int):
+        """One pass over every frequency (source keyword sets per
+        frequency) into A: one launch, or one per frequency."""
+        if self.multi:
+            soc.simulate_frequencies(self.ctx, self.grid, self.freqs, A, sources, range(self.P.K), seed=self.seed,
+                                     iteration=iteration)
+            return
+        for k, q in enumerate(sources):
+            soc.simulate_frequency(self.ctx, self.grid, self.freqs[k], A, seed=self.seed, iteration=iteration,
+                                   freq_index=k, **q)
 
     def set_temperature(self, T0: torch.Tensor) -> dict:
         """Start the dust iterations from T0 instead of the constant-source
@@ -97,10 +113,10 @@ class PlainSolver:
         if self.ali:
             self.S_ali.zero_()
             self.E_ali.zero_()
-        for k in range(P.K):
-            soc.simulate_frequency(self.ctx, self.grid, self.freqs[k], self.A, T=self.T, n_dust=n, dust_mode=1,
-                                   dust_cap=self.cap, ali_self=self.S_ali, ali_emitted=self.E_ali, seed=self.seed,
-                                   iteration=it, freq_index=k)
+            self._simulate(self.A, [dict(T=self.T, n_dust=n, dust_mode=1, dust_cap=self.cap, ali_self=self.S_ali,
+                                         ali_emitted=self.E_ali)] * P.K, iteration=it)
+        else:
+            self._simulate(self.A, [dict(T=self.T, n_dust=n, dust_mode=1, dust_cap=self.cap)] * P.K, iteration=it)
         s = soc.update_temperature(self.ctx, self.grid, self.table, self.A, self.T_new, self.T, stats=True,
                                    ali_self=self.S_ali, ali_emitted=self.E_ali)
         self.T.copy_(self.T_new)
@@ -185,8 +201,8 @@ class ReferenceFieldSolver(PlainSolver):
     towards A_i by beta_i and T_i is solved from A_ref."""
 
     def __init__(self, ctx: soc.Context, P, seed: int = 1, nT: int = 4096, packages=None, cap: float = 0.0,
-                 mode: str = "correction"):
-        super().__init__(ctx, P, seed, nT, packages, cap, ali=False)
+                 mode: str = "correction", multi: bool = True):
+        super().__init__(ctx, P, seed, nT, packages, cap, ali=False, multi=multi)
         if mode not in ("correction", "average"):
             raise ValueError("mode must be 'correction' or 'average'")
         self.mode = mode
@@ -204,7 +220,7 @@ class ReferenceFieldSolver(PlainSolver):
         self.n_sum = 0
         return s
 
-    def seed(self, T0: torch.Tensor, A0: torch.Tensor, weight: int) -> dict:
+    def seed_prediction(self, T0: torch.Tensor, A0: torch.Tensor, weight: int) -> dict:
         """After the constant pass, start from a predicted solution: the
         temperatures T0 and, as the reference absorption, A0, counted as if
         `weight` packages per frequency had estimated it (mode "average"
@@ -223,17 +239,13 @@ class ReferenceFieldSolver(PlainSolver):
         beta = n / self.n_sum
         if self.mode == "correction":
             self.A.copy_(self.A_ref)
-            for k in range(P.K):
-                soc.simulate_frequency(self.ctx, self.grid, self.freqs[k], self.A, T=self.T, n_dust=n,
-                                       dust_mode=2, L_ref=self.L_ref[k], ref_beta=beta, dust_cap=self.cap,
-                                       seed=self.seed, iteration=it, freq_index=k)
+            self._simulate(self.A, [dict(T=self.T, n_dust=n, dust_mode=2, L_ref=self.L_ref[k], ref_beta=beta,
+                                         dust_cap=self.cap) for k in range(P.K)], iteration=it)
             s = soc.update_temperature(self.ctx, self.grid, self.table, self.A, self.T_new, self.T, stats=True)
             soc.reference_blend(self.ctx, self.A, self.A_ref, beta)
         else:
             self.A.copy_(self.A_const)
-            for k in range(P.K):
-                soc.simulate_frequency(self.ctx, self.grid, self.freqs[k], self.A, T=self.T, n_dust=n,
-                                       dust_mode=1, dust_cap=self.cap, seed=self.seed, iteration=it, freq_index=k)
+            self._simulate(self.A, [dict(T=self.T, n_dust=n, dust_mode=1, dust_cap=self.cap)] * P.K, iteration=it)
             soc.reference_blend(self.ctx, self.A, self.A_ref, beta)
             s = soc.update_temperature(self.ctx, self.grid, self.table, self.A_ref, self.T_new, self.T,
                                        stats=True)

@@ -25,7 +25,7 @@ OK, EINVAL, ENOMEM, EHIP, EGRID, ESTATE = 0, -1, -2, -3, -4, -5
 CROSS, SCATTER, ESCAPE, FLOOR, RUNAWAY = 0, 1, 2, 3, 4
 CLASS_BG, CLASS_DUST, CLASS_PS0 = 0, 1, 2
 OPTIONS = {"step_cap": 0, "block": 1, "blocks_per_cu": 2, "refill_min": 3, "inner_steps": 4, "timing": 5,
-           "scatter_min": 6, "xcd_copies": 7, "chunk": 8}
+           "scatter_min": 6, "xcd_copies": 7, "chunk": 8, "batch_lds_cells": 9}
 
 
 class SocError(RuntimeError):
@@ -92,6 +92,9 @@ _lib.soc_grid_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_v
 _lib.soc_simulate_frequency.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Freq), C.POINTER(_Sources), C.c_uint64,
                                         C.c_uint32, C.c_uint32, C.c_void_p, C.POINTER(_SimStats)]
 _lib.soc_simulate_frequency_noalloc.argtypes = _lib.soc_simulate_frequency.argtypes
+_lib.soc_simulate_frequencies.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(_Freq), C.POINTER(_Sources),
+                                          C.POINTER(C.c_uint32), C.c_uint64, C.c_uint32, C.c_void_p,
+                                          C.POINTER(_SimStats)]
 _lib.soc_update_temperature_ali.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                             C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(_TempStats)]
 _lib.soc_scatter_map.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Freq), C.POINTER(_Sources), C.c_uint64,
@@ -272,6 +275,30 @@ def simulate_frequency(ctx: Context, grid: Grid, freq, absorbed: torch.Tensor, *
     ctx.check(fn(ctx.h, grid.h, C.byref(f), C.byref(sv.s), C.c_uint64(seed), C.c_uint32(iteration),
                  C.c_uint32(freq_index), _dev_ptr(absorbed, torch.float64, "absorbed"),
                  C.byref(st) if st is not None else None))
+    if st is None:
+        return None
+    return {k: getattr(st, k) for k, _ in _SimStats._fields_}
+
+
+def simulate_frequencies(ctx: Context, grid: Grid, freqs, absorbed: torch.Tensor, sources, freq_indices, *,
+                         seed=1, iteration=0, stats=False):
+    """soc_simulate_frequencies: freqs a list of K (nu, w_nu, sigma_abs,
+    sigma_sca, g); sources a list of K dicts with the keyword arguments of
+    simulate_frequency's sources (I_bg, ps_pos, ps_Lnu, T, n_bg, n_ps_pk,
+    n_dust, dust_mode, L_ref, ref_beta, dust_cap); freq_indices K ints.
+    All deposits are added to absorbed.  Returns the statistics dict if
+    stats."""
+    K = len(freqs)
+    if len(sources) != K or len(freq_indices) != K:
+        raise ValueError("one source set and one frequency index per frequency")
+    views = [_SourceView(**q) for q in sources]
+    farr = (_Freq * K)(*[_freq(f) for f in freqs])
+    sarr = (_Sources * K)(*[v.s for v in views])
+    karr = (C.c_uint32 * K)(*[int(k) for k in freq_indices])
+    st = _SimStats() if stats else None
+    ctx.check(_lib.soc_simulate_frequencies(ctx.h, grid.h, K, farr, sarr, karr, C.c_uint64(seed), C.c_uint32(iteration),
+                                            _dev_ptr(absorbed, torch.float64, "absorbed"),
+                                            C.byref(st) if st is not None else None))
     if st is None:
         return None
     return {k: getattr(st, k) for k, _ in _SimStats._fields_}

@@ -48,13 +48,19 @@ def _pairs(grids, freqs, A, n_bg=3000):
     return pairs
 
 
-def test_batch_equals_single_calls(soc):
+@pytest.mark.parametrize("lds_cells", [None, 0, 1000])
+def test_batch_equals_single_calls(soc, lds_cells):
     """Pair (m, k) of a batch follows the same random numbers as a single
     soc_simulate_frequency call with seed ^ (m << 32): identical counters,
     identical absorbed energies up to FP64 summation order, for several
-    tile sizes."""
+    tile sizes; with every grid tallied in LDS by whole-pair workgroups
+    (the default: all five grids are small), none, or the grids of at most
+    1000 cells (a mix of both phases in one launch)."""
     grids, freqs = _clouds()
     ctx = soc.Context(0)
+    if lds_cells is not None:
+        ctx.set_option("batch_lds_cells", lds_cells)
+    assert ctx.get_option("batch_lds_cells") >= (lds_cells or 0)
     G = [soc.grid_from_workload(ctx, g) for g in grids]
     seed = 0x1234_0000_0042
     ref = [torch.zeros(g.ncells, dtype=torch.float64, device="cuda") for g in grids]
@@ -172,6 +178,10 @@ def test_batch_errors(soc):
     with pytest.raises(soc.SocError):
         soc.Batch(ctx, [oc], [dict(grid=0, freq=freqs[0][1], I_bg=1.0, n_bg=10,
                                    absorbed=torch.zeros(oc.ncells, dtype=torch.float64, device="cuda"))])
+    with pytest.raises(soc.SocError, match="LDS"):
+        ctx.set_option("batch_lds_cells", 1 << 30)   # more than any workgroup's LDS holds
+    with pytest.raises(soc.SocError):
+        ctx.set_option("batch_lds_cells", -1)
     ctx.close()
 
 

@@ -330,3 +330,37 @@ def test_solver_follows_oracle_iteration(soc, ctx, reference):
         assert np.median(rel) < 1e-3 and np.quantile(rel, 0.99) < 5e-2
     if reference:
         assert solver.n_sum == sum(sched(i) for i in range(2, 7))
+
+
+def test_seeded_average_reference_blends_the_prediction(soc, ctx):
+    """Mode B of the learned start: after the constant pass the 'average'
+    reference field is seeded with temperatures T0 and an absorption A0
+    counted as w packages; the next iteration's reference absorption is
+    (w A0 + n A_2) / (w + n), where A_2 is what a plain iteration from T0
+    with the same seed absorbs, and the temperatures are solved from it."""
+    from paper_1812_06632_amd.driver import PlainSolver, ReferenceFieldSolver
+    P = W.lognormal_problem(n=16, K=8, sigma_ln=1.0, tau_v_mean=5.0, seed=5, L_star_lsun=1e5,
+                            packages_per_freq=20000)
+    plain = PlainSolver(ctx, P, seed=11)
+    plain.constant_pass()
+    rng = np.random.default_rng(9)
+    T0 = plain.T * torch.from_numpy(rng.uniform(1.0, 1.3, P.grid.ncells).astype(np.float32)).cuda()
+    A0 = plain.A_const * torch.from_numpy(rng.uniform(1.0, 3.0, P.grid.ncells)).cuda()
+    plain.set_temperature(T0)
+    plain.dust_iteration(2)
+    A2 = plain.A.clone()
+    ref = ReferenceFieldSolver(ctx, P, seed=11, mode="average")
+    ref.constant_pass()
+    w = 30000
+    ref.seed_prediction(T0, A0, w)
+    np.testing.assert_array_equal(ref.T.cpu().numpy(), T0.cpu().numpy())
+    ref.dust_iteration(2)
+    n = ref.n_packages(2)
+    want = (w * A0 + n * A2) / (w + n)
+    np.testing.assert_allclose(ref.A_ref.cpu().numpy(), want.cpu().numpy(), rtol=1e-11,
+                               atol=1e-12 * float(want.max()))
+    Tw = torch.zeros_like(ref.T)
+    soc.update_temperature(ctx, ref.grid, ref.table, want.contiguous(), Tw)
+    np.testing.assert_allclose(ref.T.cpu().numpy(), Tw.cpu().numpy(), rtol=1e-6, atol=1e-6)
+    with pytest.raises(ValueError):
+        ReferenceFieldSolver(ctx, P, seed=11, mode="correction").seed_prediction(T0, A0, w)
