@@ -570,29 +570,56 @@ __global__ __launch_bounds__(192) void wgrad3_kernel(WgradArgs a)
         const int b = t / nbz;
         const int z0 = bzi * kGZ, y0 = byi * kGY, x0 = bxi * kGX;
         __syncthreads();   // previous brick consumed (and the pad zeroing done)
-        for (int e = tid; e < kGZ * kGY * kGX * 4; e += 192) {
-            const int pos = e >> 2, g = e & 3;
-            const int lx = pos & 7, ly = (pos >> 3) & 7, lz = pos >> 6;
-            const int zz = z0 + lz, yy = y0 + ly, xx = x0 + lx;
-            u32x4 v = {0u, 0u, 0u, 0u};
-            if (zz < a.mz && yy < a.my && xx < a.mx && o0 + 8 * g < a.dy_c)
-                v = *reinterpret_cast<const u32x4 *>(
-                    a.dy + (size_t)(((b * a.oz + zz) * a.oy + yy) * a.ox + xx) * a.dy_cs + a.dy_co + o0 + 8 * g);
+        // Both tiles are staged four positions along x at a time: the four
+        // 8-channel loads of a quad are transposed in registers into one
+        // 64-bit word (four positions) per channel, so each channel-major
+        // LDS row takes 8-byte writes instead of 2-byte ones.
+        for (int e = tid; e < (kGZ * kGY * kGX / 4) * 4; e += 192) {
+            const int q = e >> 2, g = e & 3;
+            const int lx0 = (q & 1) * 4, ly = (q >> 1) & 7, lz = q >> 4;
+            const int zz = z0 + lz, yy = y0 + ly;
+            u32x4 v[4];
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                dT[(8 * g + j) * (kGZ * kGY * kGX) + pos] = (uint16_t)(v[j >> 1] >> (16 * (j & 1)));
+            for (int u = 0; u < 4; ++u) {
+                const int xx = x0 + lx0 + u;
+                v[u] = u32x4{0u, 0u, 0u, 0u};
+                if (zz < a.mz && yy < a.my && xx < a.mx && o0 + 8 * g < a.dy_c)
+                    v[u] = *reinterpret_cast<const u32x4 *>(
+                        a.dy + (size_t)(((b * a.oz + zz) * a.oy + yy) * a.ox + xx) * a.dy_cs + a.dy_co + o0 + 8 * g);
+            }
+            const int pos0 = (lz * kGY + ly) * kGX + lx0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const uint32_t sh = 16 * (j & 1);
+                const uint32_t lo = ((v[0][j >> 1] >> sh) & 0xFFFFu) | (((v[1][j >> 1] >> sh) & 0xFFFFu) << 16);
+                const uint32_t hi = ((v[2][j >> 1] >> sh) & 0xFFFFu) | (((v[3][j >> 1] >> sh) & 0xFFFFu) << 16);
+                *reinterpret_cast<uint2 *>(&dT[(8 * g + j) * (kGZ * kGY * kGX) + pos0]) = make_uint2(lo, hi);
+            }
         }
-        for (int e = tid; e < kGHZ * kGHY * 10 * 4; e += 192) {
-            const int pos = e >> 2, g = e & 3;
-            const int hx = pos % 10, hy = (pos / 10) % kGHY, hz = pos / (10 * kGHY);
-            const int zz = z0 + hz - 1, yy = y0 + hy - 1, xx = x0 + hx - 1;
-            u32x4 v = {0u, 0u, 0u, 0u};
-            if (zz >= 0 && zz < a.iz && yy >= 0 && yy < a.iy && xx >= 0 && xx < a.ix && i0 + 8 * g < a.x_c)
-                v = *reinterpret_cast<const u32x4 *>(
-                    a.x + (size_t)(((b * a.iz + zz) * a.iy + yy) * a.ix + xx) * a.x_cs + a.x_co + i0 + 8 * g);
+        // halo rows: x positions 0..11 of the padded row in three quads (10
+        // and 11 lie beyond the halo and are written as zero)
+        for (int e = tid; e < kGHZ * kGHY * 3 * 4; e += 192) {
+            const int q = e >> 2, g = e & 3;
+            const int hx0 = (q % 3) * 4, hy = (q / 3) % kGHY, hz = q / (3 * kGHY);
+            const int zz = z0 + hz - 1, yy = y0 + hy - 1;
+            u32x4 v[4];
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                xT[(((8 * g + j) * kGHZ + hz) * kGHY + hy) * kGHX + hx] = (uint16_t)(v[j >> 1] >> (16 * (j & 1)));
+            for (int u = 0; u < 4; ++u) {
+                const int hx = hx0 + u, xx = x0 + hx - 1;
+                v[u] = u32x4{0u, 0u, 0u, 0u};
+                if (hx < 10 && zz >= 0 && zz < a.iz && yy >= 0 && yy < a.iy && xx >= 0 && xx < a.ix &&
+                    i0 + 8 * g < a.x_c)
+                    v[u] = *reinterpret_cast<const u32x4 *>(
+                        a.x + (size_t)(((b * a.iz + zz) * a.iy + yy) * a.ix + xx) * a.x_cs + a.x_co + i0 + 8 * g);
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const uint32_t sh = 16 * (j & 1);
+                const uint32_t lo = ((v[0][j >> 1] >> sh) & 0xFFFFu) | (((v[1][j >> 1] >> sh) & 0xFFFFu) << 16);
+                const uint32_t hi = ((v[2][j >> 1] >> sh) & 0xFFFFu) | (((v[3][j >> 1] >> sh) & 0xFFFFu) << 16);
+                *reinterpret_cast<uint2 *>(&xT[(((8 * g + j) * kGHZ + hz) * kGHY + hy) * kGHX + hx0]) =
+                    make_uint2(lo, hi);
+            }
         }
         __syncthreads();
         if (want_bias)
