@@ -300,7 +300,8 @@ def surrogate_gain(args, soc, torch, W):
     within 1% of T_ref (mean |T - T_ref| / T_ref over all cells with dust
     and over the hottest 5%); T_ref is the mean of --ref-avg plain
     iterations after --ref-burn, with the same seed and hence the same
-    constant-source pass:
+    constant-source pass, their dust emission drawn from iteration indices
+    beyond --max-iter:
       plain        plain iterations from the constant-source temperatures;
       mode_A       plain iterations from the network's temperatures;
       mode_B       reference-field iterations (Sect. 2.1.2, running mean of
@@ -365,10 +366,16 @@ def surrogate_gain(args, soc, torch, W):
     t0 = time.time()
     ref.constant_pass()
     acc = torch.zeros(P.grid.ncells, dtype=torch.float64, device="cuda")
+    # the averaged iterations draw from iteration streams past the timed
+    # runs' last one, so that no timed iterate shares its dust-emission
+    # random numbers with T_ref (only the constant-source pass is shared)
+    shift = max(0, args.max_iter - args.ref_burn)
     for it in range(2, args.ref_burn + args.ref_avg + 2):
-        ref.dust_iteration(it)
         if it > args.ref_burn + 1:
+            ref.dust_iteration(it + shift)
             acc += ref.T
+        else:
+            ref.dust_iteration(it)
     T_ref = (acc / args.ref_avg).float()
     t_ref = time.time() - t0
     dense = torch.from_numpy(P.grid.density()).cuda() > 0
@@ -399,7 +406,12 @@ def surrogate_gain(args, soc, torch, W):
         t_hit, n_hit, stop, hist = timed_to_criterion(torch, solver, crit, start=start, max_iter=args.max_iter,
                                                       run_on=True)
         at_stop = next((h for h in hist if h[0] == stop), None)
+        levels = {}
+        for lev in (0.05, 0.03, 0.02, 0.015, 0.01):
+            h = next((h for h in hist if h[2] < lev and h[3] < lev), None)
+            levels[f"{lev:g}"] = [h[0], round(h[1], 3)] if h else None
         runs[label] = {"s_to_1pct": t_hit, "iterations_to_1pct": n_hit,
+                       "iteration_and_s_within": levels,
                        "stopping_rule_iteration": stop,
                        "err_at_stopping_rule": [at_stop[2], at_stop[3]] if at_stop else None,
                        "by_iteration": [[h[0], round(h[1], 3), round(h[2], 5), round(h[3], 5)] for h in hist]}

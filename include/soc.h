@@ -80,10 +80,13 @@ typedef enum {
                                     over 16 addresses [1] */
     SOC_OPT_CHUNK = 8,           /* package ids a wave takes from the global counter at a time, 64..65536
                                     (smaller: finer load balance between waves) [256] */
-    SOC_OPT_BATCH_LDS_CELLS = 9  /* batches created afterwards: pairs whose grid has at most this many cells
+    SOC_OPT_BATCH_LDS_CELLS = 9, /* batches created afterwards: pairs whose grid has at most this many cells
                                     are taken whole by one workgroup, which keeps the grid's absorbed array
                                     in LDS (0 = never; at most what the device's LDS per workgroup holds)
                                     [13824 = 24^3, or less if the device holds less] */
+    SOC_OPT_MULTI_SPREAD = 10    /* soc_simulate_frequencies: 1 = wave w starts its rotation over the
+                                    frequencies at w mod K (the waves divide over the frequencies); 0 = every
+                                    wave starts at the first, the next filling in as each ends [1] */
 } soc_option;
 soc_status soc_ctx_set_option(soc_ctx ctx, soc_option opt, int64_t value);
 soc_status soc_ctx_get_option(soc_ctx ctx, soc_option opt, int64_t *value);

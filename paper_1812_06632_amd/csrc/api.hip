@@ -42,6 +42,7 @@ struct soc_ctx_s {
     int64_t chunk = 256;
     int64_t scatter_min = 1;
     int64_t xcd_copies = 1;
+    int64_t multi_spread = 1;
     int64_t batch_lds_cells = 0;      // grids of at most this many cells: whole pairs tallied in LDS (set at creation)
     int64_t max_lds_cells = 0;        // the most the device's LDS per workgroup holds
     int64_t lds_per_cu = 65536;       // bytes of LDS per compute unit
@@ -570,6 +571,9 @@ soc_status soc_ctx_set_option(soc_ctx c, soc_option opt, int64_t v)
         if (v < 64 || v > 65536) return fail(c, SOC_EINVAL, "chunk must be in [64,65536]");
         c->chunk = v;
         return SOC_OK;
+    case SOC_OPT_MULTI_SPREAD:
+        c->multi_spread = v ? 1 : 0;
+        return SOC_OK;
     case SOC_OPT_BATCH_LDS_CELLS:
         if (v < 0 || v > c->max_lds_cells)
             return fail(c, SOC_EINVAL, "batch LDS cells must be in [0,%lld] on this device", (long long)c->max_lds_cells);
@@ -593,6 +597,7 @@ soc_status soc_ctx_get_option(soc_ctx c, soc_option opt, int64_t *v)
     case SOC_OPT_XCD_COPIES: *v = c->xcd_copies; return SOC_OK;
     case SOC_OPT_CHUNK: *v = c->chunk; return SOC_OK;
     case SOC_OPT_BATCH_LDS_CELLS: *v = c->batch_lds_cells; return SOC_OK;
+    case SOC_OPT_MULTI_SPREAD: *v = c->multi_spread; return SOC_OK;
     }
     return fail(c, SOC_EINVAL, "unknown option %d", (int)opt);
 }
@@ -840,6 +845,7 @@ soc_status soc_simulate_frequencies(soc_ctx c, soc_grid g, int32_t K, const soc_
     MultiArgs M;
     M.args = c->d_margs;
     M.K = K;
+    M.spread = (int32_t)c->multi_spread;
     HIPCHK(c, launch_mc_multi(M, g->nlevels, (int)(c->num_cus * c->blocks_per_cu), (int)c->block, c->stream));
     if (c->timing) {
         HIPCHK(c, hipEventRecord(e1, c->stream));

@@ -251,10 +251,12 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_ali_kernel(McArgs A)
 
 // Several frequencies of one grid in one persistent launch (the argument
 // blocks in device memory, one package-id counter each, all deposits into
-// one tally): a wave works through the frequencies in a rotation that
-// starts at its own index, so that the waves spread over the frequencies,
-// and moves on when its current one has no ids left and its lanes are
-// idle.  Only the last frequencies leave a tail, not every one.
+// one tally): a wave works through the frequencies in a rotation and moves
+// on when its current one has no ids left and its lanes are idle, so only
+// the last frequencies leave a tail, not every one.  The rotation starts
+// at the wave's own index (spread: the waves divide over the frequencies)
+// or at 0 (all waves on one frequency, the next one filling in as it
+// ends).
 template <bool Oct>
 __global__ __launch_bounds__(kMcMaxBlock) void mc_multi_kernel(MultiArgs M)
 {
@@ -264,8 +266,9 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_multi_kernel(MultiArgs M)
     double *const dst = A0.priv ? A0.priv + (size_t)priv_index() * (size_t)A0.ncells : A0.absorbed;
     WaveTally w;
     const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    const int k0 = M.spread ? wave % M.K : 0;
     for (int j = 0; j < M.K; ++j) {
-        const int k = __builtin_amdgcn_readfirstlane((wave + j) % M.K);
+        const int k = __builtin_amdgcn_readfirstlane((k0 + j) % M.K);
         mc_frequency<Oct, false>(M.args[k], lds_dep, lds_cell, dst, nullptr, w);
     }
     const int tid = threadIdx.x, bd = blockDim.x;

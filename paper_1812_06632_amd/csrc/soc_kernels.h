@@ -161,6 +161,7 @@ hipError_t launch_mc(const McArgs &a, int blocks, int threads, hipStream_t s);
 struct MultiArgs {
     const McArgs *args;
     int32_t K;
+    int32_t spread;   // 1: wave w starts at frequency w mod K; 0: every wave starts at 0
 };
 hipError_t launch_mc_multi(const MultiArgs &m, int nlevels, int blocks, int threads, hipStream_t s);
 hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_t s);

@@ -25,7 +25,7 @@ OK, EINVAL, ENOMEM, EHIP, EGRID, ESTATE = 0, -1, -2, -3, -4, -5
 CROSS, SCATTER, ESCAPE, FLOOR, RUNAWAY = 0, 1, 2, 3, 4
 CLASS_BG, CLASS_DUST, CLASS_PS0 = 0, 1, 2
 OPTIONS = {"step_cap": 0, "block": 1, "blocks_per_cu": 2, "refill_min": 3, "inner_steps": 4, "timing": 5,
-           "scatter_min": 6, "xcd_copies": 7, "chunk": 8, "batch_lds_cells": 9}
+           "scatter_min": 6, "xcd_copies": 7, "chunk": 8, "batch_lds_cells": 9, "multi_spread": 10}
 
 
 class SocError(RuntimeError):

@@ -84,12 +84,19 @@ def test_constant_sources(soc, ctx, cloud, copies):
         ctx.set_option("xcd_copies", saved)
 
 
-@pytest.mark.parametrize("cap", [0.0, 8.0])
-def test_weighted_dust_emission(soc, ctx, cloud, cap):
+@pytest.mark.parametrize("cap,spread", [(0.0, 1), (8.0, 1), (0.0, 0)])
+def test_weighted_dust_emission(soc, ctx, cloud, cap, spread):
+    """Both orders in which the waves take the frequencies (option
+    multi_spread) give the same counters and tallies."""
     P, T = cloud
-    g = soc.grid_from_workload(ctx, P.grid)
-    src = [dict(T=T, n_dust=20000 + 1001 * k, dust_mode=1, dust_cap=cap) for k in range(P.K)]
-    _check(*_both(soc, ctx, g, P.grid.ncells, _freqs(P), src, list(range(P.K)), 12, 4))
+    saved = ctx.get_option("multi_spread")
+    ctx.set_option("multi_spread", spread)
+    try:
+        g = soc.grid_from_workload(ctx, P.grid)
+        src = [dict(T=T, n_dust=20000 + 1001 * k, dust_mode=1, dust_cap=cap) for k in range(P.K)]
+        _check(*_both(soc, ctx, g, P.grid.ncells, _freqs(P), src, list(range(P.K)), 12, 4))
+    finally:
+        ctx.set_option("multi_spread", saved)
 
 
 def test_uniform_dust_emission_and_subset_of_frequencies(soc, ctx, cloud):
