@@ -521,33 +521,47 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
 
 // Weight gradients of 3^3 convolutions, all 27 taps per workgroup.  The
 // workgroup owns a 32 x 32 (input, output channel) tile and a chunk of
-// 2 x 8 x 8 position bricks; per brick it stages dy (channel-major,
-// [o][z][y][x]) and the 4 x 10 x 10 input halo (channel-major, rows
-// padded to 16) in LDS.  The MFMA reduction runs over positions: one
-// K-step is 16 positions (two x-rows of 8), so both operands are 16-byte
-// LDS reads along x.  Wave w takes the taps with tz = w; the three x-taps
-// of a (tz, ty) pair come from two aligned reads of the halo row shifted by
-// 0, 1 or 2 elements in registers (v_alignbyte).
+// 2 x 8 x 8 position bricks; per brick it stages dy and the 4 x 10 x 10
+// input halo in LDS as they are in memory, channels last (one 16-byte
+// write per 8 channels of a position).  The MFMA reduction runs over
+// positions: one K-step is 16 positions (two x-rows of 8).  Its operands
+// need 8 positions of one channel per lane, which the LDS transpose read
+// (ds_read_b64_tr_b16) delivers from the channels-last tiles: within each
+// group of 16 lanes, lane s gives the address of 4 channels (4 (s mod 4)
+// onwards) at position s / 4, and lane i receives channel i at the 4
+// positions.  Wave w takes the taps with tz = w; a tap's x-shift is an
+// offset of the positions read.
 constexpr int kGZ = 2, kGY = 8, kGX = 8;                 // brick
 constexpr int kGHZ = kGZ + 2, kGHY = kGY + 2, kGHX = 16;  // halo (x padded to 16)
 
-__global__ __launch_bounds__(192) void wgrad3_kernel(WgradArgs a)
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+// 4 positions (pos0 .. pos0 + 3, row stride 32 channels) of the lane's
+// channel c0 + (lane mod 16), read transposed from a channels-last tile.
+__device__ inline uint2 tr_read4(const uint16_t *tile, int pos0, int c0, int lane)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t xT[32 * kGHZ * kGHY * kGHX];   // 40 KB
-    __shared__ __attribute__((aligned(16))) uint16_t dT[32 * kGZ * kGY * kGX];      // 8 KB
+    const int s = lane & 15;
+    const uint16_t *p = tile + (pos0 + (s >> 2)) * 32 + c0 + 4 * (s & 3);
+    const s16x4 v = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) s16x4 *)p);
+    return __builtin_bit_cast(uint2, v);
+}
+
+__global__ __launch_bounds__(192, 2) void wgrad3_kernel(WgradArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t xL[kGHZ * kGHY * kGHX * 32];   // 40 KB, [hz][hy][hx][ch]
+    __shared__ __attribute__((aligned(16))) uint16_t dL[kGZ * kGY * kGX * 32];      // 8 KB, [lz][ly][lx][ch]
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int tz = tid >> 6;   // wave = z-tap
     const int half = lane >> 5;
     const int r = lane & 31;
+    const int cg = 16 * ((lane >> 4) & 1);   // channel group of the lane's 16-lane group
     const int ntile_o = (a.cout + 31) / 32;
     const int i0 = (blockIdx.y / ntile_o) * 32;
     const int o0 = (blockIdx.y % ntile_o) * 32;
     const int nbx = (a.mx + kGX - 1) / kGX, nby = (a.my + kGY - 1) / kGY, nbz = (a.mz + kGZ - 1) / kGZ;
     const uint32_t nb = (uint32_t)a.batch * nbz * nby * nbx;
     const uint32_t b_begin = blockIdx.x * a.chunk, b_end = min(b_begin + a.chunk, nb);
-
-    for (int e = tid; e < 32 * kGHZ * kGHY * kGHX; e += 192) xT[e] = 0;   // pad columns stay zero
 
     // workgroups of the first input-channel tile also sum dy per output
     // channel (the bias gradient): thread (o = tid % 32, part = tid / 32)
@@ -560,91 +574,80 @@ __global__ __launch_bounds__(192) void wgrad3_kernel(WgradArgs a)
     for (int q = 0; q < 9; ++q)
         for (int v = 0; v < 16; ++v) acc[q][v] = 0.0f;
 
-    for (uint32_t bi = b_begin; bi < b_end; ++bi) {
+    // The next brick's input halo (the larger tile) is loaded into registers
+    // while the current brick is multiplied: 9 16-byte loads per thread
+    // (1600 items over 192 threads); the dy tile is loaded when staged.
+    constexpr int kDyItems = kGZ * kGY * kGX * 4, kHaloItems = kGHZ * kGHY * 10 * 4;
+    constexpr int kHaloPer = (kHaloItems + 191) / 192;
+    u32x4 ph[kHaloPer];
+    struct Brick { int b, z0, y0, x0; };
+    auto brick = [&](uint32_t bi) {
         uint32_t t = bi;
         const int bxi = t % nbx;
         t /= nbx;
         const int byi = t % nby;
         t /= nby;
         const int bzi = t % nbz;
-        const int b = t / nbz;
-        const int z0 = bzi * kGZ, y0 = byi * kGY, x0 = bxi * kGX;
-        __syncthreads();   // previous brick consumed (and the pad zeroing done)
-        // Both tiles are staged four positions along x at a time: the four
-        // 8-channel loads of a quad are transposed in registers into one
-        // 64-bit word (four positions) per channel, so each channel-major
-        // LDS row takes 8-byte writes instead of 2-byte ones.
-        for (int e = tid; e < (kGZ * kGY * kGX / 4) * 4; e += 192) {
-            const int q = e >> 2, g = e & 3;
-            const int lx0 = (q & 1) * 4, ly = (q >> 1) & 7, lz = q >> 4;
-            const int zz = z0 + lz, yy = y0 + ly;
-            u32x4 v[4];
+        return Brick{(int)(t / nbz), bzi * kGZ, byi * kGY, bxi * kGX};
+    };
+    auto load_halo = [&](const Brick &k) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int xx = x0 + lx0 + u;
-                v[u] = u32x4{0u, 0u, 0u, 0u};
-                if (zz < a.mz && yy < a.my && xx < a.mx && o0 + 8 * g < a.dy_c)
-                    v[u] = *reinterpret_cast<const u32x4 *>(
-                        a.dy + (size_t)(((b * a.oz + zz) * a.oy + yy) * a.ox + xx) * a.dy_cs + a.dy_co + o0 + 8 * g);
-            }
-            const int pos0 = (lz * kGY + ly) * kGX + lx0;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const uint32_t sh = 16 * (j & 1);
-                const uint32_t lo = ((v[0][j >> 1] >> sh) & 0xFFFFu) | (((v[1][j >> 1] >> sh) & 0xFFFFu) << 16);
-                const uint32_t hi = ((v[2][j >> 1] >> sh) & 0xFFFFu) | (((v[3][j >> 1] >> sh) & 0xFFFFu) << 16);
-                *reinterpret_cast<uint2 *>(&dT[(8 * g + j) * (kGZ * kGY * kGX) + pos0]) = make_uint2(lo, hi);
-            }
+        for (int j = 0; j < kHaloPer; ++j) {
+            const int e = tid + 192 * j;
+            ph[j] = u32x4{0u, 0u, 0u, 0u};
+            const int pos = e >> 2, g = e & 3;
+            const int hx = pos % 10, hy = (pos / 10) % kGHY, hz = pos / (10 * kGHY);
+            const int zz = k.z0 + hz - 1, yy = k.y0 + hy - 1, xx = k.x0 + hx - 1;
+            if (e < kHaloItems && zz >= 0 && zz < a.iz && yy >= 0 && yy < a.iy && xx >= 0 && xx < a.ix &&
+                i0 + 8 * g < a.x_c)
+                ph[j] = *reinterpret_cast<const u32x4 *>(
+                    a.x + (size_t)(((k.b * a.iz + zz) * a.iy + yy) * a.ix + xx) * a.x_cs + a.x_co + i0 + 8 * g);
         }
-        // halo rows: x positions 0..11 of the padded row in three quads (10
-        // and 11 lie beyond the halo and are written as zero)
-        for (int e = tid; e < kGHZ * kGHY * 3 * 4; e += 192) {
-            const int q = e >> 2, g = e & 3;
-            const int hx0 = (q % 3) * 4, hy = (q / 3) % kGHY, hz = q / (3 * kGHY);
-            const int zz = z0 + hz - 1, yy = y0 + hy - 1;
-            u32x4 v[4];
+    };
+    if (b_begin < b_end) load_halo(brick(b_begin));
+    for (uint32_t bi = b_begin; bi < b_end; ++bi) {
+        const Brick k = brick(bi);
+        __syncthreads();   // previous brick consumed
+        for (int e = tid; e < kDyItems; e += 192) {
+            const int pos = e >> 2, g = e & 3;
+            const int lx = pos & 7, ly = (pos >> 3) & 7, lz = pos >> 6;
+            const int zz = k.z0 + lz, yy = k.y0 + ly, xx = k.x0 + lx;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (zz < a.mz && yy < a.my && xx < a.mx && o0 + 8 * g < a.dy_c)
+                v = *reinterpret_cast<const u32x4 *>(
+                    a.dy + (size_t)(((k.b * a.oz + zz) * a.oy + yy) * a.ox + xx) * a.dy_cs + a.dy_co + o0 + 8 * g);
+            *reinterpret_cast<u32x4 *>(&dL[pos * 32 + 8 * g]) = v;
+        }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int hx = hx0 + u, xx = x0 + hx - 1;
-                v[u] = u32x4{0u, 0u, 0u, 0u};
-                if (hx < 10 && zz >= 0 && zz < a.iz && yy >= 0 && yy < a.iy && xx >= 0 && xx < a.ix &&
-                    i0 + 8 * g < a.x_c)
-                    v[u] = *reinterpret_cast<const u32x4 *>(
-                        a.x + (size_t)(((b * a.iz + zz) * a.iy + yy) * a.ix + xx) * a.x_cs + a.x_co + i0 + 8 * g);
-            }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const uint32_t sh = 16 * (j & 1);
-                const uint32_t lo = ((v[0][j >> 1] >> sh) & 0xFFFFu) | (((v[1][j >> 1] >> sh) & 0xFFFFu) << 16);
-                const uint32_t hi = ((v[2][j >> 1] >> sh) & 0xFFFFu) | (((v[3][j >> 1] >> sh) & 0xFFFFu) << 16);
-                *reinterpret_cast<uint2 *>(&xT[(((8 * g + j) * kGHZ + hz) * kGHY + hy) * kGHX + hx0]) =
-                    make_uint2(lo, hi);
-            }
+        for (int j = 0; j < kHaloPer; ++j) {
+            const int e = tid + 192 * j;
+            const int pos = e >> 2;
+            const int hx = pos % 10, hy = (pos / 10) % kGHY, hz = pos / (10 * kGHY);
+            if (e < kHaloItems) *reinterpret_cast<u32x4 *>(&xL[((hz * kGHY + hy) * kGHX + hx) * 32 + 8 * (e & 3)]) = ph[j];
         }
         __syncthreads();
+        if (bi + 1 < b_end) load_halo(brick(bi + 1));
         if (want_bias)
-            for (int pos = tid >> 5; pos < kGZ * kGY * kGX; pos += 6) bsum += bf2f(dT[(tid & 31) * (kGZ * kGY * kGX) + pos]);
+            for (int pos = tid >> 5; pos < kGZ * kGY * kGX; pos += 6) bsum += bf2f(dL[pos * 32 + (tid & 31)]);
+        // (the row loop stays rolled: unrolled, the hoisted transpose reads
+        // need 336 registers, one wave per SIMD; rolled, 188)
 #pragma unroll
         for (int lz = 0; lz < kGZ; ++lz)
-#pragma unroll
+#pragma unroll 1
             for (int m = 0; m < kGY / 2; ++m) {
                 const int ly = 2 * m + half;   // this lane's x-row of the K-step
-                const u32x4 bv = *reinterpret_cast<const u32x4 *>(&dT[r * (kGZ * kGY * kGX) + (lz * kGY + ly) * kGX]);
-                const bf16x8_t B = __builtin_bit_cast(bf16x8_t, bv);
+                const int drow = (lz * kGY + ly) * kGX;
+                const uint2 b0 = tr_read4(dL, drow, cg, lane), b1 = tr_read4(dL, drow + 4, cg, lane);
+                const bf16x8_t B = __builtin_bit_cast(bf16x8_t, u32x4{b0.x, b0.y, b1.x, b1.y});
 #pragma unroll
                 for (int ty = 0; ty < 3; ++ty) {
-                    const uint16_t *row = &xT[((r * kGHZ + lz + tz) * kGHY + ly + ty) * kGHX];
-                    const u32x4 c0 = *reinterpret_cast<const u32x4 *>(row);
-                    const u32x4 c1 = *reinterpret_cast<const u32x4 *>(row + 8);
-                    const u32x4 s1 = {__builtin_amdgcn_alignbyte(c0[1], c0[0], 2), __builtin_amdgcn_alignbyte(c0[2], c0[1], 2),
-                                      __builtin_amdgcn_alignbyte(c0[3], c0[2], 2), __builtin_amdgcn_alignbyte(c1[0], c0[3], 2)};
-                    const u32x4 s2 = {c0[1], c0[2], c0[3], c1[0]};
-                    acc[3 * ty + 0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, c0), B,
-                                                                              acc[3 * ty + 0], 0, 0, 0);
-                    acc[3 * ty + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, s1), B,
-                                                                              acc[3 * ty + 1], 0, 0, 0);
-                    acc[3 * ty + 2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, s2), B,
-                                                                              acc[3 * ty + 2], 0, 0, 0);
+                    const int xrow = ((lz + tz) * kGHY + ly + ty) * kGHX;
+#pragma unroll
+                    for (int tx = 0; tx < 3; ++tx) {
+                        const uint2 a0 = tr_read4(xL, xrow + tx, cg, lane), a1 = tr_read4(xL, xrow + tx + 4, cg, lane);
+                        const bf16x8_t A = __builtin_bit_cast(bf16x8_t, u32x4{a0.x, a0.y, a1.x, a1.y});
+                        acc[3 * ty + tx] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc[3 * ty + tx], 0, 0, 0);
+                    }
                 }
             }
     }
