@@ -66,11 +66,13 @@ def mc_source_hash():
     return h.hexdigest()
 
 
-def recorded_traffic():
-    """Bytes per MC launch from the committed counter summary, or None when
-    it is absent or was taken on other kernel sources."""
+def recorded_counters():
+    """(HBM bytes per MC launch, memory-side atomic transactions per cell
+    step) from the committed counter summary; None for each value that is
+    absent, and for both when the summary was taken on other kernel
+    sources."""
     if not os.path.exists(TRAFFIC_FILE):
-        return None
+        return None, None
     vals = {}
     with open(TRAFFIC_FILE) as f:
         for line in f:
@@ -78,11 +80,14 @@ def recorded_traffic():
                 k, v = line[2:].split(":", 1)
                 vals[k.strip()] = v.strip().strip("`")
     if vals.get("mc_source_sha256") != mc_source_hash():
-        return None
-    try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+        return None, None
+
+    def num(key):
+        try:
+            return float(vals[key])
+        except (KeyError, ValueError):
+            return None
+    return num("hbm_bytes_per_launch"), num("atomic_transactions_per_cell_step")
 
 
 def device_ceilings(soc, ctx, torch, ncells):
@@ -1232,7 +1237,7 @@ def headline(args, soc, torch, W):
     if not args.no_sub_records:
         subs = {"octree": octree_record(soc, torch, W), "batch": batch_record(soc, torch, W)}
 
-    traffic = recorded_traffic()
+    traffic, tx_per_step = recorded_counters()
     out = {
         "metric": "photon packages/s",
         "value": pk_per_s,
@@ -1260,9 +1265,13 @@ def headline(args, soc, torch, W):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": MC_KERNEL, "avg_launch_ms": avg_launch_s * 1e3,
                      "cell_steps_per_launch": steps_per_launch, "bytes_per_cell_step": BYTES_PER_STEP,
-                     "binding": "memory-side FP64 atomic adds (one per cell step), not HBM bytes",
+                     "binding": "memory-side FP64 atomic transactions (one per deposit, except that the deposits "
+                                "of one atomic instruction in one 64-byte line merge), not HBM bytes",
                      "atomic_ceiling_per_s": atomic_ceiling,
-                     "atomic_frac": steps_per_launch / avg_launch_s / atomic_ceiling,
+                     "atomic_transactions_per_cell_step": tx_per_step,
+                     "atomic_frac": (steps_per_launch / avg_launch_s * tx_per_step / atomic_ceiling
+                                     if tx_per_step else None),
+                     "cell_steps_per_s_over_atomic_ceiling": steps_per_launch / avg_launch_s / atomic_ceiling,
                      "copy_GBs": copy_gbs},
         "cpu_baseline": cpu,
         "other_workloads": subs,

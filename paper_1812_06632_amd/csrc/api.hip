@@ -726,6 +726,13 @@ soc_status soc_grid_info(soc_grid g, int64_t *n_leaves, const int32_t **d_parent
     return SOC_OK;
 }
 
+// Private copies of a regular grid with even dimensions are kept in
+// 2 x 2 x 2 bricks (neighbouring cells share 64-byte lines).
+static int32_t brick_copies(const soc_grid g)
+{
+    return g->nlevels == 1 && g->nx % 2 == 0 && g->ny % 2 == 0 && g->nz % 2 == 0 ? 1 : 0;
+}
+
 soc_status soc_simulate_frequency(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *s, uint64_t seed,
                                   uint32_t iteration, uint32_t freq_index, double *d_absorbed, soc_sim_stats *stats)
 {
@@ -743,6 +750,7 @@ soc_status soc_simulate_frequency(soc_ctx c, soc_grid g, const soc_freq *f, cons
             HIPCHK(c, launch_fill_f64(c->d_priv, 0.0, c->cap_priv, c->stream));
         }
         A.priv = c->d_priv;
+        A.brick = brick_copies(g);
         if (A.ali_self) {
             if (c->cap_priv_self < (int64_t)kPrivCopies * g->ncells) {
                 st = grow(c, &c->d_priv_self, c->cap_priv_self, (int64_t)kPrivCopies * g->ncells);
@@ -767,8 +775,9 @@ soc_status soc_simulate_frequency(soc_ctx c, soc_grid g, const soc_freq *f, cons
         c->ev_start.push_back(e0);
         c->ev_stop.push_back(e1);
     }
-    if (A.priv) HIPCHK(c, launch_fold_copies(d_absorbed, A.priv, g->ncells, c->stream));
-    if (A.priv_self) HIPCHK(c, launch_fold_copies(A.ali_self, A.priv_self, g->ncells, c->stream));
+    if (A.priv) HIPCHK(c, launch_fold_copies(d_absorbed, A.priv, g->ncells, A.brick, g->nx, g->ny, c->stream));
+    if (A.priv_self)
+        HIPCHK(c, launch_fold_copies(A.ali_self, A.priv_self, g->ncells, A.brick, g->nx, g->ny, c->stream));
     if (stats) {
         DevStats h;
         HIPCHK(c, hipMemcpyAsync(&h, c->d_stats, sizeof h, hipMemcpyDeviceToHost, c->stream));
@@ -830,7 +839,10 @@ soc_status soc_simulate_frequencies(soc_ctx c, soc_grid g, int32_t K, const soc_
             if ((st = grow(c, &c->d_priv, c->cap_priv, (int64_t)kPrivCopies * g->ncells))) return st;
             HIPCHK(c, launch_fill_f64(c->d_priv, 0.0, c->cap_priv, c->stream));
         }
-        for (auto &A : c->h_margs) A.priv = c->d_priv;
+        for (auto &A : c->h_margs) {
+            A.priv = c->d_priv;
+            A.brick = brick_copies(g);
+        }
     }
     HIPCHK(c, hipMemcpyAsync(c->d_margs, c->h_margs.data(), sizeof(McArgs) * (size_t)K, hipMemcpyHostToDevice,
                              c->stream));
@@ -852,7 +864,8 @@ soc_status soc_simulate_frequencies(soc_ctx c, soc_grid g, int32_t K, const soc_
         c->ev_start.push_back(e0);
         c->ev_stop.push_back(e1);
     }
-    if (c->xcd_copies) HIPCHK(c, launch_fold_copies(d_absorbed, c->d_priv, g->ncells, c->stream));
+    if (c->xcd_copies)
+        HIPCHK(c, launch_fold_copies(d_absorbed, c->d_priv, g->ncells, brick_copies(g), g->nx, g->ny, c->stream));
     if (stats) {
         DevStats h;
         HIPCHK(c, hipMemcpyAsync(&h, c->d_stats, sizeof h, hipMemcpyDeviceToHost, c->stream));
@@ -885,6 +898,7 @@ soc_status soc_simulate_frequency_noalloc(soc_ctx c, soc_grid g, const soc_freq 
     if (st) return st;
     if (c->xcd_copies) {   // the array keeps the last call's contents: clear the copies this call uses
         A.priv = (double *)(src.base + kNaPriv);
+        A.brick = brick_copies(g);
         HIPCHK(c, launch_fill_f64(A.priv, 0.0, (int64_t)kPrivCopies * g->ncells, c->stream));
         if (A.ali_self) {
             A.priv_self = (double *)(src.base + kNaPrivSelf);
@@ -894,8 +908,9 @@ soc_status soc_simulate_frequency_noalloc(soc_ctx c, soc_grid g, const soc_freq 
     HIPCHK(c, launch_fill_u64((unsigned long long *)A.st_call, 0ull, (int64_t)(sizeof(DevStats) / 8), c->stream));
     HIPCHK(c, launch_fill_u64(A.next_id, 0ull, 1, c->stream));
     HIPCHK(c, launch_mc(A, (int)(c->num_cus * c->blocks_per_cu), (int)c->block, c->stream));
-    if (A.priv) HIPCHK(c, launch_fold_copies(d_absorbed, A.priv, g->ncells, c->stream));
-    if (A.priv_self) HIPCHK(c, launch_fold_copies(A.ali_self, A.priv_self, g->ncells, c->stream));
+    if (A.priv) HIPCHK(c, launch_fold_copies(d_absorbed, A.priv, g->ncells, A.brick, g->nx, g->ny, c->stream));
+    if (A.priv_self)
+        HIPCHK(c, launch_fold_copies(A.ali_self, A.priv_self, g->ncells, A.brick, g->nx, g->ny, c->stream));
     if (stats) {
         DevStats h;
         HIPCHK(c, hipMemcpyAsync(&h, A.st_call, sizeof h, hipMemcpyDeviceToHost, c->stream));
@@ -1741,7 +1756,7 @@ soc_status soc_batch_run(soc_batch b, uint32_t iteration, soc_sim_stats *stats)
         // a workgroup holds a small grid's tally: 512-lane workgroups, as many
         // per compute unit as their LDS allows (at most two)
         threads = kMcMaxBlock;
-        const int64_t ring = (int64_t)kDepSlots * threads * (int64_t)(sizeof(double) + sizeof(int32_t));
+        const int64_t ring = (int64_t)kRingStride * threads * (int64_t)(sizeof(double) + sizeof(int32_t));
         const int64_t need = std::max<int64_t>(ring, b->lds_cells * (int64_t)sizeof(double)) + 256;
         const int64_t per_cu = std::min<int64_t>(2, std::max<int64_t>(1, c->lds_per_cu / need));
         blocks = (int)(c->num_cus * per_cu);

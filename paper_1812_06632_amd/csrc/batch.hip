@@ -76,8 +76,8 @@ __device__ inline void view_pair(BatchView &A, const PairDev &P)
 
 __global__ __launch_bounds__(kMcMaxBlock) void mc_batch_kernel(BatchArgs B)
 {
-    extern __shared__ double lds_dep[];
-    int32_t *lds_cell = (int32_t *)(lds_dep + kDepSlots * blockDim.x);
+    extern __shared__ double lds_dep[];   // LDS phase: a grid's tally; tiles: [blockDim.x][kRingStride] deposits, then cells
+    int32_t *lds_cell = (int32_t *)(lds_dep + kRingStride * blockDim.x);
     __shared__ int32_t sh_pair;                // pair of the LDS phase, workgroup-uniform
     __shared__ unsigned long long sh_next;     // its next unassigned package id
     const int tid = threadIdx.x;
@@ -200,8 +200,7 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_batch_kernel(BatchArgs B)
     for (;;) {
         if (pool_next >= pool_end && !__any(active)) {
             // tile finished: flush its deposits, take the next tile
-            for (int j = 0; j < kDepSlots; ++j)
-                if (j < nbuf) unsafeAtomicAdd(&absorbed[lds_cell[j * bd + tid]], lds_dep[j * bd + tid]);
+            flush_rings(lds_dep, lds_cell, nbuf, [&](int32_t c, double v) { unsafeAtomicAdd(&absorbed[c], v); });
             nbuf = 0;
             since_flush = 0;
             unsigned int t = 0;
@@ -247,8 +246,7 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_batch_kernel(BatchArgs B)
             }
         }
         if ((since_flush + 1) * B.inner_steps > kDepSlots) {
-            for (int j = 0; j < kDepSlots; ++j)
-                if (j < nbuf) unsafeAtomicAdd(&absorbed[lds_cell[j * bd + tid]], lds_dep[j * bd + tid]);
+            flush_rings(lds_dep, lds_cell, nbuf, [&](int32_t c, double v) { unsafeAtomicAdd(&absorbed[c], v); });
             nbuf = 0;
             since_flush = 0;
         }
@@ -259,8 +257,8 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_batch_kernel(BatchArgs B)
                 const StepOut o = step<float, false>(p, A, ks, ka, d);
                 n_st += 1;
                 if (o.dep != 0.0) {
-                    lds_dep[nbuf * bd + tid] = o.dep;
-                    lds_cell[nbuf * bd + tid] = o.cell;
+                    lds_dep[tid * kRingStride + nbuf] = o.dep;
+                    lds_cell[tid * kRingStride + nbuf] = o.cell;
                     ++nbuf;
                     e_ab += o.dep;
                 }
@@ -290,7 +288,7 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_batch_kernel(BatchArgs B)
 
 hipError_t launch_mc_batch(const BatchArgs &a, int blocks, int threads, int64_t lds_cells, hipStream_t s)
 {
-    const size_t ring = (size_t)kDepSlots * threads * (sizeof(double) + sizeof(int32_t));
+    const size_t ring = (size_t)kRingStride * threads * (sizeof(double) + sizeof(int32_t));
     const size_t tally = a.n_lds_pairs > 0 ? (size_t)lds_cells * sizeof(double) : 0;
     hipLaunchKernelGGL(mc_batch_kernel, dim3(blocks), dim3(threads), ring > tally ? ring : tally, s, a);
     return hipGetLastError();

@@ -15,7 +15,11 @@
 // wait for the previous step's atomic round trip.  Each lane therefore
 // stages its deposits in an LDS ring of kDepSlots entries and the wave
 // flushes the rings as one burst of atomics every kDepSlots iterations:
-// one atomic latency per kDepSlots steps instead of per step.
+// one atomic latency per kDepSlots steps instead of per step.  The burst
+// is transposed (flush_rings): each atomic instruction carries consecutive
+// deposits of a few packages, and on a regular grid the private copies are
+// kept in 2 x 2 x 2 bricks (brick_cell), so that these neighbouring cells
+// often share a 64-byte line and one memory-side transaction.
 #include "soc_device.h"
 
 namespace soc {
@@ -61,14 +65,17 @@ __device__ inline void flush_stats(const McArgs &A, unsigned long long pk, unsig
     }
 }
 
-// Stage of a deposit: with diagonal ALI a dust package's deposits in its
-// own emitting cell go to the self-absorption tally, marked by storing the
-// complement of the cell index.
+// Flush of the wave's deposit rings: with diagonal ALI a dust package's
+// deposits in its own emitting cell go to the self-absorption tally, marked
+// by storing the complement of the cell index.
 template <bool Ali>
-__device__ inline void flush_one(double *dst, double *sdst, int32_t key, double v)
+__device__ inline void flush_deposits(double *dst, double *sdst, const double *lds_dep, const int32_t *lds_cell,
+                                      int nbuf)
 {
-    if (Ali && key < 0) unsafeAtomicAdd(&sdst[~key], v);
-    else unsafeAtomicAdd(&dst[key], v);
+    flush_rings(lds_dep, lds_cell, nbuf, [&](int32_t key, double v) {
+        if (Ali && key < 0) unsafeAtomicAdd(&sdst[~key], v);
+        else unsafeAtomicAdd(&dst[key], v);
+    });
 }
 
 // Per-wave state that outlives one frequency: the LDS deposit ring and the
@@ -83,15 +90,16 @@ struct WaveTally {
 // Every package of one frequency's argument block A: ids from A.next_id in
 // chunks, until the ids are used up and every lane of the wave has
 // finished.  Deposits go through the lane's LDS ring to dst (sdst: the
-// ALI self-absorption tally).
+// ALI self-absorption tally), keyed by brick_cell when A.brick is set.
 template <bool Oct, bool Ali>
 __device__ __forceinline__ void mc_frequency(const McArgs &A, double *lds_dep, int32_t *lds_cell, double *dst,
                                              double *sdst, WaveTally &w)
 {
-    const int tid = threadIdx.x;
-    const int bd = blockDim.x;
+    const int ring = (int)threadIdx.x * kRingStride;
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const bool brick = !Oct && A.brick;
+    const int32_t hx = A.nx >> 1, hy = A.ny >> 1;
     Pkg<float> p;
     Rng rng;
     bool active = false;   // lane holds a package
@@ -155,8 +163,7 @@ __device__ __forceinline__ void mc_frequency(const McArgs &A, double *lds_dep, i
             }
         }
         if ((since_flush + 1) * A.inner_steps > kDepSlots) {
-            for (int j = 0; j < kDepSlots; ++j)
-                if (j < nbuf) flush_one<Ali>(dst, sdst, lds_cell[j * bd + tid], lds_dep[j * bd + tid]);
+            flush_deposits<Ali>(dst, sdst, lds_dep, lds_cell, nbuf);
             nbuf = 0;
             since_flush = 0;
         }
@@ -167,6 +174,7 @@ __device__ __forceinline__ void mc_frequency(const McArgs &A, double *lds_dep, i
             o.cell = 0;
             o.event = kEvCross;
             o.dep = 0.0;
+            const int32_t bcell = brick ? brick_cell(p.cx, p.cy, p.cz, hx, hy) : 0;   // the cell before the step
             if (stepping) {
                 float d;
                 o = step<float, Oct>(p, A, ks, ka, d);
@@ -180,7 +188,8 @@ __device__ __forceinline__ void mc_frequency(const McArgs &A, double *lds_dep, i
             // staged once, which spares the memory-side atomic unit a burst
             // of same-address adds.
             double dep = o.dep;
-            const int32_t key = (Ali && o.cell == origin) ? ~o.cell : o.cell;
+            const int32_t tcell = brick ? bcell : o.cell;
+            const int32_t key = (Ali && o.cell == origin) ? ~tcell : tcell;
             const bool first = stepping && first_step && dep != 0.0;
             if (stepping) first_step = false;
             const unsigned long long fm = __ballot(first);
@@ -199,11 +208,11 @@ __device__ __forceinline__ void mc_frequency(const McArgs &A, double *lds_dep, i
             // same cell: consecutive deposits of a lane into one cell share
             // a ring slot, so each scattering saves one atomic.
             if (dep != 0.0) {
-                if (nbuf > 0 && lds_cell[(nbuf - 1) * bd + tid] == key) {
-                    lds_dep[(nbuf - 1) * bd + tid] += dep;
+                if (nbuf > 0 && lds_cell[ring + nbuf - 1] == key) {
+                    lds_dep[ring + nbuf - 1] += dep;
                 } else {
-                    lds_dep[nbuf * bd + tid] = dep;
-                    lds_cell[nbuf * bd + tid] = key;
+                    lds_dep[ring + nbuf] = dep;
+                    lds_cell[ring + nbuf] = key;
                     ++nbuf;
                 }
             }
@@ -224,15 +233,13 @@ __device__ __forceinline__ void mc_frequency(const McArgs &A, double *lds_dep, i
 template <bool Oct, bool Ali>
 __device__ __forceinline__ void mc_body(const McArgs &A)
 {
-    extern __shared__ double lds_dep[];   // [kDepSlots][blockDim.x] deposits, then cells
-    int32_t *lds_cell = (int32_t *)(lds_dep + kDepSlots * blockDim.x);
+    extern __shared__ double lds_dep[];   // [blockDim.x][kRingStride] deposits, then cells
+    int32_t *lds_cell = (int32_t *)(lds_dep + kRingStride * blockDim.x);
     double *const dst = A.priv ? A.priv + (size_t)priv_index() * (size_t)A.ncells : A.absorbed;
     double *const sdst = A.priv_self ? A.priv_self + (size_t)priv_index() * (size_t)A.ncells : A.ali_self;
     WaveTally w;
     mc_frequency<Oct, Ali>(A, lds_dep, lds_cell, dst, sdst, w);
-    const int tid = threadIdx.x, bd = blockDim.x;
-    for (int j = 0; j < kDepSlots; ++j)
-        if (j < w.nbuf) flush_one<Ali>(dst, sdst, lds_cell[j * bd + tid], lds_dep[j * bd + tid]);
+    flush_deposits<Ali>(dst, sdst, lds_dep, lds_cell, w.nbuf);
     flush_stats(A, w.n_pk, w.n_st, w.n_sc, w.n_ru, w.e_em, w.e_ab, w.e_es);
 }
 
@@ -260,8 +267,8 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_ali_kernel(McArgs A)
 template <bool Oct>
 __global__ __launch_bounds__(kMcMaxBlock) void mc_multi_kernel(MultiArgs M)
 {
-    extern __shared__ double lds_dep[];
-    int32_t *lds_cell = (int32_t *)(lds_dep + kDepSlots * blockDim.x);
+    extern __shared__ double lds_dep[];   // [blockDim.x][kRingStride] deposits, then cells
+    int32_t *lds_cell = (int32_t *)(lds_dep + kRingStride * blockDim.x);
     const McArgs &A0 = M.args[0];
     double *const dst = A0.priv ? A0.priv + (size_t)priv_index() * (size_t)A0.ncells : A0.absorbed;
     WaveTally w;
@@ -271,15 +278,13 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_multi_kernel(MultiArgs M)
         const int k = __builtin_amdgcn_readfirstlane((k0 + j) % M.K);
         mc_frequency<Oct, false>(M.args[k], lds_dep, lds_cell, dst, nullptr, w);
     }
-    const int tid = threadIdx.x, bd = blockDim.x;
-    for (int j = 0; j < kDepSlots; ++j)
-        if (j < w.nbuf) flush_one<false>(dst, nullptr, lds_cell[j * bd + tid], lds_dep[j * bd + tid]);
+    flush_deposits<false>(dst, nullptr, lds_dep, lds_cell, w.nbuf);
     flush_stats(A0, w.n_pk, w.n_st, w.n_sc, w.n_ru, w.e_em, w.e_ab, w.e_es);
 }
 
 hipError_t launch_mc_multi(const MultiArgs &m, int nlevels, int blocks, int threads, hipStream_t s)
 {
-    const size_t lds = (size_t)kDepSlots * threads * (sizeof(double) + sizeof(int32_t));
+    const size_t lds = (size_t)kRingStride * threads * (sizeof(double) + sizeof(int32_t));
     if (nlevels > 1) hipLaunchKernelGGL(mc_multi_kernel<true>, dim3(blocks), dim3(threads), lds, s, m);
     else hipLaunchKernelGGL(mc_multi_kernel<false>, dim3(blocks), dim3(threads), lds, s, m);
     return hipGetLastError();
@@ -287,7 +292,7 @@ hipError_t launch_mc_multi(const MultiArgs &m, int nlevels, int blocks, int thre
 
 hipError_t launch_mc(const McArgs &a, int blocks, int threads, hipStream_t s)
 {
-    const size_t lds = (size_t)kDepSlots * threads * (sizeof(double) + sizeof(int32_t));
+    const size_t lds = (size_t)kRingStride * threads * (sizeof(double) + sizeof(int32_t));
     const bool ali = a.ali_self != nullptr;
     if (a.nlevels > 1 && ali) hipLaunchKernelGGL(mc_ali_kernel<true>, dim3(blocks), dim3(threads), lds, s, a);
     else if (ali) hipLaunchKernelGGL(mc_ali_kernel<false>, dim3(blocks), dim3(threads), lds, s, a);

@@ -29,6 +29,43 @@ __device__ inline uint32_t priv_index()
     return xcd_index() + 8u * (blockIdx.x % kPrivPerXcd);
 }
 
+// Index of cell (x, y, z) of a regular grid with even dimensions stored in
+// 2 x 2 x 2 bricks (hx = nx / 2, hy = ny / 2): the eight cells of a brick
+// are 64 consecutive bytes of an FP64 array, bricks in x-fastest order.
+__device__ inline int32_t brick_cell(int32_t x, int32_t y, int32_t z, int32_t hx, int32_t hy)
+{
+    return ((((z >> 1) * hy + (y >> 1)) * hx + (x >> 1)) << 3) | ((z & 1) << 2) | ((y & 1) << 1) | (x & 1);
+}
+
+// Per-lane deposit rings in LDS: lane t's kDepSlots entries start at
+// t * kRingStride (the pad entry puts neighbouring lanes' rings on
+// different banks).  flush_rings adds every ring of the wave through
+// add(key, value), transposed: with R = 64 / kDepSlots rings per
+// instruction, instruction j takes the rings of lanes R j .. R j + R - 1,
+// and lane L the slot L mod kDepSlots of ring R j + L / kDepSlots.  One
+// instruction then carries consecutive deposits of a few packages instead
+// of one deposit of each of 64: neighbouring cells, often in one 64-byte
+// line, and the memory side performs the adds of one instruction that fall
+// in one line as one transaction.  Call with the whole wave.
+template <typename F>
+__device__ inline void flush_rings(const double *lds_dep, const int32_t *lds_cell, int nbuf, F add)
+{
+    static_assert(64 % kDepSlots == 0, "rings must tile a wave");
+    constexpr int R = 64 / kDepSlots;
+    const int lane = (int)threadIdx.x & 63;
+    const int base = (int)threadIdx.x - lane;
+    const int slot = lane % kDepSlots;
+#pragma unroll
+    for (int j = 0; j < kDepSlots; ++j) {
+        const int ring = R * j + lane / kDepSlots;
+        const int nb = __shfl(nbuf, ring, 64);
+        if (slot < nb) {
+            const int e = (base + ring) * kRingStride + slot;
+            add(lds_cell[e], lds_dep[e]);
+        }
+    }
+}
+
 
 // ------------------------------------------------------------------ Philox
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
@@ -252,16 +289,35 @@ __device__ inline void split_coord(double p, int32_t n, int32_t &c, R &f)
     f = (R)(p - fl);
 }
 
+// A position on the face between cells c - 1 and c (f = 0) or c and c + 1
+// (f = 1) belongs to the cell the direction u points into, the cell a
+// position moved an infinitesimal step along u lies in; on the box
+// boundary it stays in the box.
+template <typename R>
+__device__ inline void face_tie(int32_t &c, R &f, R u, int32_t n)
+{
+    if (f == (R)0 && u < (R)0 && c > 0) {
+        c -= 1;
+        f = (R)1;
+    } else if (f == (R)1 && u > (R)0 && c < n - 1) {
+        c += 1;
+        f = (R)0;
+    }
+}
+
 // ------------------------------------------------------------------ octree walk
 // Descend from cell p.c (position p.f in its units) to the leaf containing
-// the position: child octant o = [f >= 1/2] per axis, f -> 2 f - o.  The
-// leaf's word is its density.
+// the position: child octant o = [f > 1/2, or f = 1/2 and u >= 0] per axis
+// (a position on the plane between two octants goes where the direction
+// points), f -> 2 f - o.  The leaf's word is its density.
 template <typename R, typename AT>
 __device__ inline void descend(Pkg<R> &p, const AT &A)
 {
     int32_t w = (int32_t)A.words[p.c];
     while (w < 0) {
-        const int32_t ox = p.fx >= (R)0.5, oy = p.fy >= (R)0.5, oz = p.fz >= (R)0.5;
+        const int32_t ox = p.fx > (R)0.5 || (p.fx == (R)0.5 && p.ux >= (R)0);
+        const int32_t oy = p.fy > (R)0.5 || (p.fy == (R)0.5 && p.uy >= (R)0);
+        const int32_t oz = p.fz > (R)0.5 || (p.fz == (R)0.5 && p.uz >= (R)0);
         p.fx = (R)2 * p.fx - (R)ox;
         p.fy = (R)2 * p.fy - (R)oy;
         p.fz = (R)2 * p.fz - (R)oz;
@@ -374,6 +430,8 @@ __device__ inline bool emit_base(const AT &A, uint64_t gid, Pkg<R> &p, Rng &rng,
         const int32_t Nc = a == 2 ? A.ny : A.nz;
         split_coord<R>((double)x1 * Nb, Nb, cb, fb);
         split_coord<R>((double)x2 * Nc, Nc, cc, fc);
+        face_tie<R>(cb, fb, ub, Nb);
+        face_tie<R>(cc, fc, uc, Nc);
         const int32_t Na = a == 0 ? A.nx : (a == 1 ? A.ny : A.nz);
         const int32_t ca = neg ? 0 : Na - 1;
         const R fa = neg ? (R)0 : (R)1;
@@ -402,9 +460,12 @@ __device__ inline bool emit_base(const AT &A, uint64_t gid, Pkg<R> &p, Rng &rng,
         split_coord<R>(A.ps[s].x, A.nx, p.cx, p.fx);
         split_coord<R>(A.ps[s].y, A.ny, p.cy, p.fy);
         split_coord<R>(A.ps[s].z, A.nz, p.cz, p.fz);
-        p.c = p.cx + A.nx * (p.cy + A.ny * p.cz);
         const R x0 = next_u<R>(rng, A), x1 = next_u<R>(rng, A);
         iso_dir<R>(x0, x1, p.ux, p.uy, p.uz);
+        face_tie<R>(p.cx, p.fx, p.ux, A.nx);   // a source on a cell face
+        face_tie<R>(p.cy, p.fy, p.uy, A.ny);
+        face_tie<R>(p.cz, p.fz, p.uz, A.nz);
+        p.c = p.cx + A.nx * (p.cy + A.ny * p.cz);
     } else {
         const uint64_t j = gid - A.n_bg - nps_tot;
         cls = kClassDust;

@@ -29,7 +29,8 @@ constexpr int kEvRunaway = 4;
 
 constexpr int kMaxPs = 32;
 constexpr int kDepSlots = 8;      // LDS deposit ring per lane of the MC kernel
-constexpr int kMcMaxBlock = 512;  // MC workgroup size limit (LDS ring: 48 KB at 512)
+constexpr int kRingStride = kDepSlots + 1;   // LDS entries per lane's ring (one pad entry)
+constexpr int kMcMaxBlock = 512;  // MC workgroup size limit (LDS rings: 54 KB at 512)
 constexpr int kMaxLevels = 16;
 
 struct PsArg {
@@ -72,6 +73,8 @@ struct McArgs {
     int64_t step_cap;
     double *absorbed;
     double *priv;                // NULL, or kPrivCopies private copies of ncells (see priv_index)
+    int32_t brick;               // 1: the private copies hold a regular grid of even dimensions in
+                                 // 2 x 2 x 2 bricks (brick_cell), folded back to the cell order
     double *ali_self;            // diagonal ALI (NULL = off): dust deposits in the emitting cell
     double *priv_self;           // NULL, or kPrivCopies private copies of ali_self
     // persistent scheduling
@@ -172,7 +175,10 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t 
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 // absorbed[c] += sum_x priv[x n + c] over the kPrivCopies private copies, which are left zero.
-hipError_t launch_fold_copies(double *absorbed, double *priv, int64_t n, hipStream_t s);
+// Add the private copies into absorbed and clear them; brick: the copies
+// are in the brick order of a regular nx x ny x nz grid (even dimensions).
+hipError_t launch_fold_copies(double *absorbed, double *priv, int64_t n, int32_t brick, int32_t nx, int32_t ny,
+                              hipStream_t s);
 
 // dust emission setup
 hipError_t launch_dust_luminosity(const uint32_t *words, int64_t ncells, const int64_t *level_offset,
