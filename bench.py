@@ -665,8 +665,11 @@ def octree_bench(args, soc, torch, W):
     autotune.apply(ctx, best)
     t_tuned, st = full_pass()
     t_multi, _ = full_pass(multi=True)
+    ctx.set_option("multi_spread", 0)   # one launch, each frequency drained by all waves in turn
+    t_multi_seq, _ = full_pass(multi=True)
+    ctx.set_option("multi_spread", 1)
     log(f"octree: 128 frequencies x 10^7 packages: default schedule {t_def:.2f}s, tuned {t_tuned:.2f}s, "
-        f"tuned in one launch {t_multi:.2f}s")
+        f"tuned in one launch {t_multi:.2f}s (frequencies in turn: {t_multi_seq:.2f}s)")
     cons = (st["e_absorbed"] + st["e_escaped"]) / st["e_emitted"] - 1.0
     cpu = None
     if not args.no_cpu_baseline:
@@ -690,7 +693,7 @@ def octree_bench(args, soc, torch, W):
                                           "10^4 K source of 10^6 L_sun + external field, 128 frequencies, "
                                           "10^7 packages/frequency",
             "packages": st["packages"], "cell_steps": st["cell_steps"], "s_per_pass": t_tuned,
-            "s_per_pass_one_launch": t_multi,
+            "s_per_pass_one_launch": t_multi, "s_per_pass_one_launch_frequencies_in_turn": t_multi_seq,
             "packages_per_s": st["packages"] / t_tuned, "cell_steps_per_s": st["cell_steps"] / t_tuned,
             "s_per_pass_default_schedule": t_def, "schedule": best, "energy_conservation": cons,
             "cpu_baseline": cpu}

@@ -77,7 +77,10 @@ typedef enum {
                                     (two per XCD: the hardware XCC id and the workgroup index's parity;
                                     context scratch of 16 x ncells doubles), summed into d_absorbed by one
                                     kernel after the launch: spreads the same-address adds of hot cells
-                                    over 16 addresses [1] */
+                                    over 16 addresses.  With even root dimensions the copies hold the root
+                                    cells in 2 x 2 x 2 bricks, so that a package's consecutive deposits
+                                    often share one memory-side transaction.  Batches created while it is
+                                    1 also tally their tiled arrays in a brick-ordered scratch [1] */
     SOC_OPT_CHUNK = 8,           /* package ids a wave takes from the global counter at a time, 64..65536
                                     (smaller: finer load balance between waves) [256] */
     SOC_OPT_BATCH_LDS_CELLS = 9, /* batches created afterwards: pairs whose grid has at most this many cells
@@ -435,7 +438,12 @@ typedef struct soc_batch_s *soc_batch;
  * to FP64 summation order).  A batch with such pairs launches 512-lane
  * workgroups, one or two per compute unit as their LDS allows
  * (SOC_OPT_BLOCK and SOC_OPT_BLOCKS_PER_CU shape the other batches).
- * Synchronises.  soc_batch_info counts those pairs among the tiles. */
+ * With SOC_OPT_XCD_COPIES 1 (now), an array that only tiled pairs of one
+ * grid with even dimensions add into is tallied in a batch-owned scratch
+ * copy in 2 x 2 x 2 brick order (one FP64 per cell of every such array),
+ * which each soc_batch_run adds into the array after its launch and leaves
+ * zero.  Synchronises.  soc_batch_info counts the LDS pairs among the
+ * tiles. */
 soc_status soc_batch_create(soc_ctx ctx, int32_t n_grids, const soc_grid *grids, int32_t n_pairs,
                             const soc_batch_pair *pairs, uint64_t seed, uint64_t tile_packages, soc_batch *out);
 void soc_batch_destroy(soc_batch b);

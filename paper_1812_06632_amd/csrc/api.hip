@@ -15,6 +15,7 @@
 #include <mutex>
 #include <string>
 #include <new>
+#include <map>
 #include <vector>
 
 #include "soc.h"
@@ -94,6 +95,10 @@ struct soc_batch_s {
     int32_t *d_lds_pairs = nullptr;         // pairs of small grids, largest cost first
     int32_t n_lds_pairs = 0;
     int64_t lds_cells = 0;                  // the largest grid among them
+    double *d_brick = nullptr;              // brick-ordered tallies of the tiled arrays (zero between runs)
+    BrickFold *d_folds = nullptr;           // each tally and its array
+    int32_t n_folds = 0;
+    int64_t max_fold_cells = 0;
 };
 
 struct soc_graph_s {
@@ -726,11 +731,12 @@ soc_status soc_grid_info(soc_grid g, int64_t *n_leaves, const int32_t **d_parent
     return SOC_OK;
 }
 
-// Private copies of a regular grid with even dimensions are kept in
-// 2 x 2 x 2 bricks (neighbouring cells share 64-byte lines).
+// The root cells of a grid with even root dimensions (every cell of such a
+// regular grid) are kept in 2 x 2 x 2 bricks in the private copies, so that
+// neighbouring cells share 64-byte lines.
 static int32_t brick_copies(const soc_grid g)
 {
-    return g->nlevels == 1 && g->nx % 2 == 0 && g->ny % 2 == 0 && g->nz % 2 == 0 ? 1 : 0;
+    return g->nx % 2 == 0 && g->ny % 2 == 0 && g->nz % 2 == 0 ? 1 : 0;
 }
 
 soc_status soc_simulate_frequency(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *s, uint64_t seed,
@@ -775,9 +781,9 @@ soc_status soc_simulate_frequency(soc_ctx c, soc_grid g, const soc_freq *f, cons
         c->ev_start.push_back(e0);
         c->ev_stop.push_back(e1);
     }
-    if (A.priv) HIPCHK(c, launch_fold_copies(d_absorbed, A.priv, g->ncells, A.brick, g->nx, g->ny, c->stream));
+    if (A.priv) HIPCHK(c, launch_fold_copies(d_absorbed, A.priv, g->ncells, A.brick, g->nx, g->ny, g->nroot, c->stream));
     if (A.priv_self)
-        HIPCHK(c, launch_fold_copies(A.ali_self, A.priv_self, g->ncells, A.brick, g->nx, g->ny, c->stream));
+        HIPCHK(c, launch_fold_copies(A.ali_self, A.priv_self, g->ncells, A.brick, g->nx, g->ny, g->nroot, c->stream));
     if (stats) {
         DevStats h;
         HIPCHK(c, hipMemcpyAsync(&h, c->d_stats, sizeof h, hipMemcpyDeviceToHost, c->stream));
@@ -865,7 +871,7 @@ soc_status soc_simulate_frequencies(soc_ctx c, soc_grid g, int32_t K, const soc_
         c->ev_stop.push_back(e1);
     }
     if (c->xcd_copies)
-        HIPCHK(c, launch_fold_copies(d_absorbed, c->d_priv, g->ncells, brick_copies(g), g->nx, g->ny, c->stream));
+        HIPCHK(c, launch_fold_copies(d_absorbed, c->d_priv, g->ncells, brick_copies(g), g->nx, g->ny, g->nroot, c->stream));
     if (stats) {
         DevStats h;
         HIPCHK(c, hipMemcpyAsync(&h, c->d_stats, sizeof h, hipMemcpyDeviceToHost, c->stream));
@@ -908,9 +914,9 @@ soc_status soc_simulate_frequency_noalloc(soc_ctx c, soc_grid g, const soc_freq 
     HIPCHK(c, launch_fill_u64((unsigned long long *)A.st_call, 0ull, (int64_t)(sizeof(DevStats) / 8), c->stream));
     HIPCHK(c, launch_fill_u64(A.next_id, 0ull, 1, c->stream));
     HIPCHK(c, launch_mc(A, (int)(c->num_cus * c->blocks_per_cu), (int)c->block, c->stream));
-    if (A.priv) HIPCHK(c, launch_fold_copies(d_absorbed, A.priv, g->ncells, A.brick, g->nx, g->ny, c->stream));
+    if (A.priv) HIPCHK(c, launch_fold_copies(d_absorbed, A.priv, g->ncells, A.brick, g->nx, g->ny, g->nroot, c->stream));
     if (A.priv_self)
-        HIPCHK(c, launch_fold_copies(A.ali_self, A.priv_self, g->ncells, A.brick, g->nx, g->ny, c->stream));
+        HIPCHK(c, launch_fold_copies(A.ali_self, A.priv_self, g->ncells, A.brick, g->nx, g->ny, g->nroot, c->stream));
     if (stats) {
         DevStats h;
         HIPCHK(c, hipMemcpyAsync(&h, A.st_call, sizeof h, hipMemcpyDeviceToHost, c->stream));
@@ -1660,6 +1666,36 @@ soc_status soc_batch_create(soc_ctx c, int32_t n_grids, const soc_grid *grids, i
         }
         total += P.n_total;
     }
+    // brick-ordered tallies (private copies on): one per array that only
+    // tiled pairs of one grid with even dimensions add into
+    struct Target { int32_t grid; bool ok; int64_t off; };
+    std::map<double *, Target> targets;
+    for (int32_t i = 0; i < n_pairs; ++i) {
+        const soc_grid g = grids[pairs[i].grid];
+        const bool tiled = g->ncells > c->batch_lds_cells;
+        const bool even = g->nx % 2 == 0 && g->ny % 2 == 0 && g->nz % 2 == 0;
+        auto it = targets.find(pairs[i].d_absorbed);
+        if (it == targets.end())
+            targets[pairs[i].d_absorbed] = Target{pairs[i].grid, tiled && even && c->xcd_copies != 0, 0};
+        else if (it->second.grid != pairs[i].grid || !tiled)
+            it->second.ok = false;
+    }
+    std::vector<BrickFold> folds;
+    int64_t brick_cells = 0, max_fold_cells = 0;
+    for (auto &kv : targets) {
+        if (!kv.second.ok) continue;
+        const soc_grid g = grids[kv.second.grid];
+        kv.second.off = brick_cells;
+        BrickFold f;
+        f.tally = nullptr;   // set once the scratch exists
+        f.absorbed = kv.first;
+        f.nx = g->nx;
+        f.ny = g->ny;
+        f.ncells = g->ncells;
+        folds.push_back(f);
+        brick_cells += g->ncells;
+        max_fold_cells = std::max<int64_t>(max_fold_cells, g->ncells);
+    }
     std::stable_sort(tiles.begin(), tiles.end(), [](const TileCost &a, const TileCost &b) { return a.cost > b.cost; });
     std::stable_sort(lds.begin(), lds.end(), [](const LdsPair &a, const LdsPair &b) { return a.cost > b.cost; });
     std::vector<int32_t> hl(lds.size());
@@ -1677,6 +1713,8 @@ soc_status soc_batch_create(soc_ctx c, int32_t n_grids, const soc_grid *grids, i
     b->n_packages = total;
     b->n_lds_pairs = (int32_t)hl.size();
     b->lds_cells = lds_cells;
+    b->n_folds = (int32_t)folds.size();
+    b->max_fold_cells = max_fold_cells;
     auto cleanup = [&](soc_status r) {
         if (r != SOC_OK) soc_batch_destroy(b);
         return r;
@@ -1686,15 +1724,26 @@ soc_status soc_batch_create(soc_ctx c, int32_t n_grids, const soc_grid *grids, i
         hipMalloc((void **)&b->d_ps, sizeof(PsArg) * std::max<size_t>(1, hps.size())) != hipSuccess ||
         hipMalloc((void **)&b->d_counter, 2 * sizeof(unsigned int)) != hipSuccess ||
         hipMalloc((void **)&b->d_iteration, sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc((void **)&b->d_lds_pairs, sizeof(int32_t) * std::max<size_t>(1, hl.size())) != hipSuccess)
+        hipMalloc((void **)&b->d_lds_pairs, sizeof(int32_t) * std::max<size_t>(1, hl.size())) != hipSuccess ||
+        hipMalloc((void **)&b->d_folds, sizeof(BrickFold) * std::max<size_t>(1, folds.size())) != hipSuccess ||
+        (brick_cells > 0 && hipMalloc((void **)&b->d_brick, sizeof(double) * (size_t)brick_cells) != hipSuccess))
         return cleanup(fail(c, SOC_ENOMEM, "batch tables"));
-    for (int32_t i = 0; i < n_pairs; ++i) hp[i].ps = hp[i].n_ps ? b->d_ps + ps_off[i] : nullptr;
+    if (brick_cells > 0 && launch_fill_f64(b->d_brick, 0.0, brick_cells, c->stream) != hipSuccess)
+        return cleanup(fail(c, SOC_EHIP, "batch init"));
+    for (auto &f : folds) f.tally = b->d_brick + targets[f.absorbed].off;
+    for (int32_t i = 0; i < n_pairs; ++i) {
+        hp[i].ps = hp[i].n_ps ? b->d_ps + ps_off[i] : nullptr;
+        const Target &t = targets[hp[i].absorbed];
+        hp[i].tally = t.ok ? b->d_brick + t.off : hp[i].absorbed;
+        hp[i].brick = t.ok ? 1 : 0;
+    }
     std::vector<TileDev> ht(tiles.size());
     for (size_t i = 0; i < tiles.size(); ++i) ht[i] = tiles[i].t;
     if (hipMemcpy(b->d_pairs, hp.data(), sizeof(PairDev) * n_pairs, hipMemcpyHostToDevice) != hipSuccess ||
         (ht.size() && hipMemcpy(b->d_tiles, ht.data(), sizeof(TileDev) * ht.size(), hipMemcpyHostToDevice) != hipSuccess) ||
         (hps.size() && hipMemcpy(b->d_ps, hps.data(), sizeof(PsArg) * hps.size(), hipMemcpyHostToDevice) != hipSuccess) ||
-        (hl.size() && hipMemcpy(b->d_lds_pairs, hl.data(), sizeof(int32_t) * hl.size(), hipMemcpyHostToDevice) != hipSuccess))
+        (hl.size() && hipMemcpy(b->d_lds_pairs, hl.data(), sizeof(int32_t) * hl.size(), hipMemcpyHostToDevice) != hipSuccess) ||
+        (folds.size() && hipMemcpy(b->d_folds, folds.data(), sizeof(BrickFold) * folds.size(), hipMemcpyHostToDevice) != hipSuccess))
         return cleanup(fail(c, SOC_EHIP, "batch upload"));
     if (launch_advance_iteration(b->d_iteration, 0, 0u, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)
@@ -1713,6 +1762,8 @@ void soc_batch_destroy(soc_batch b)
     (void)hipFree(b->d_counter);
     (void)hipFree(b->d_iteration);
     (void)hipFree(b->d_lds_pairs);
+    (void)hipFree(b->d_folds);
+    (void)hipFree(b->d_brick);
     delete b;
 }
 
@@ -1768,6 +1819,7 @@ soc_status soc_batch_run(soc_batch b, uint32_t iteration, soc_sim_stats *stats)
         HIPCHK(c, hipEventRecord(e0, c->stream));
     }
     HIPCHK(c, launch_mc_batch(a, blocks, threads, b->lds_cells, c->stream));
+    HIPCHK(c, launch_batch_fold(b->d_folds, b->n_folds, b->max_fold_cells, c->stream));
     if (c->timing) {
         HIPCHK(c, hipEventRecord(e1, c->stream));
         c->ev_start.push_back(e0);

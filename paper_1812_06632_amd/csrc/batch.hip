@@ -4,8 +4,12 @@
 // time: its lanes are refilled from the tile's id range (wave ballot and
 // lane rank, as in the single-problem kernel), and once the range is used
 // up and every lane has finished, the wave flushes its LDS deposit ring
-// into that model's absorbed array and takes the next tile.  Pair
-// parameters are read as wave-uniform (scalar) data at each tile switch.
+// into that model's tally and takes the next tile.  The tally is the
+// model's array or, with private copies on, a brick-ordered scratch copy
+// of it (neighbouring cells in one 64-byte line, so that the transposed
+// flush merges their adds), added into the array after the launch by
+// batch_fold_kernel.  Pair parameters are read as wave-uniform (scalar)
+// data at each tile switch.
 //
 // Pairs of small grids come first and differently: a workgroup takes a
 // whole pair, keeps that grid's absorbed array in LDS, and its waves add
@@ -13,6 +17,8 @@
 // global atomics that bound the rest); when the pair is done the
 // workgroup adds the LDS array to the model's array, one coalesced add
 // per cell.  Then the same LDS serves as the deposit ring of the tiles.
+#include <algorithm>
+
 #include "soc_device.h"
 
 namespace soc {
@@ -188,7 +194,9 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_batch_kernel(BatchArgs B)
     // ---- tiles of the other pairs, wave by wave, LDS as the deposit ring
     BatchView A;
     view_base(A, iteration, B.step_cap);
-    double *absorbed = nullptr;
+    double *tally = nullptr;   // the pair's tile tally: brick-ordered scratch or the model's array
+    bool brick = false;
+    int32_t hx = 0, hy = 0;
     float ks = 0.0f, ka = 0.0f, gg = 0.0f;
 
     Pkg<float> p;
@@ -200,7 +208,7 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_batch_kernel(BatchArgs B)
     for (;;) {
         if (pool_next >= pool_end && !__any(active)) {
             // tile finished: flush its deposits, take the next tile
-            flush_rings(lds_dep, lds_cell, nbuf, [&](int32_t c, double v) { unsafeAtomicAdd(&absorbed[c], v); });
+            flush_rings(lds_dep, lds_cell, nbuf, [&](int32_t c, double v) { unsafeAtomicAdd(&tally[c], v); });
             nbuf = 0;
             since_flush = 0;
             unsigned int t = 0;
@@ -211,7 +219,10 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_batch_kernel(BatchArgs B)
             const int32_t pi = __builtin_amdgcn_readfirstlane(tile.pair);
             const PairDev &P = B.pairs[pi];
             view_pair(A, P);
-            absorbed = P.absorbed;
+            tally = P.tally;
+            brick = P.brick != 0;
+            hx = P.nx >> 1;
+            hy = P.ny >> 1;
             ks = P.ks_f; ka = P.ka_f; gg = P.g_f;
             pool_next = __builtin_amdgcn_readfirstlane(tile.begin);
             pool_end = __builtin_amdgcn_readfirstlane(tile.end);
@@ -246,7 +257,7 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_batch_kernel(BatchArgs B)
             }
         }
         if ((since_flush + 1) * B.inner_steps > kDepSlots) {
-            flush_rings(lds_dep, lds_cell, nbuf, [&](int32_t c, double v) { unsafeAtomicAdd(&absorbed[c], v); });
+            flush_rings(lds_dep, lds_cell, nbuf, [&](int32_t c, double v) { unsafeAtomicAdd(&tally[c], v); });
             nbuf = 0;
             since_flush = 0;
         }
@@ -254,11 +265,12 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_batch_kernel(BatchArgs B)
         for (int s = 0; s < B.inner_steps; ++s) {
             if (active && !pend) {
                 float d;
+                const int32_t bcell = brick ? brick_cell(p.cx, p.cy, p.cz, hx, hy) : 0;   // the cell before the step
                 const StepOut o = step<float, false>(p, A, ks, ka, d);
                 n_st += 1;
                 if (o.dep != 0.0) {
                     lds_dep[tid * kRingStride + nbuf] = o.dep;
-                    lds_cell[tid * kRingStride + nbuf] = o.cell;
+                    lds_cell[tid * kRingStride + nbuf] = brick ? bcell : o.cell;
                     ++nbuf;
                     e_ab += o.dep;
                 }
@@ -291,6 +303,31 @@ hipError_t launch_mc_batch(const BatchArgs &a, int blocks, int threads, int64_t 
     const size_t ring = (size_t)kRingStride * threads * (sizeof(double) + sizeof(int32_t));
     const size_t tally = a.n_lds_pairs > 0 ? (size_t)lds_cells * sizeof(double) : 0;
     hipLaunchKernelGGL(mc_batch_kernel, dim3(blocks), dim3(threads), ring > tally ? ring : tally, s, a);
+    return hipGetLastError();
+}
+
+// Brick-ordered tallies into their arrays: blockIdx.y is the tally, the
+// x dimension strides over its entries (brick order as fold_copies_kernel).
+__global__ void batch_fold_kernel(const BrickFold *folds)
+{
+    const BrickFold f = folds[blockIdx.y];
+    const int32_t hx = f.nx >> 1, hy = f.ny >> 1;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < f.ncells;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = f.tally[i];
+        if (v == 0.0) continue;
+        f.tally[i] = 0.0;
+        const int64_t b = i >> 3, bx = b % hx, t = b / hx, by = t % hy, bz = t / hy;
+        const int64_t c = ((2 * bz + ((i >> 2) & 1)) * (2 * hy) + 2 * by + ((i >> 1) & 1)) * (2 * hx) + 2 * bx + (i & 1);
+        f.absorbed[c] += v;
+    }
+}
+
+hipError_t launch_batch_fold(const BrickFold *folds, int32_t n, int64_t max_cells, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t bx = std::min<int64_t>((max_cells + 255) / 256, 256);
+    hipLaunchKernelGGL(batch_fold_kernel, dim3((unsigned)std::max<int64_t>(bx, 1), (unsigned)n), dim3(256), 0, s, folds);
     return hipGetLastError();
 }
 

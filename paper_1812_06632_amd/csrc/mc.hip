@@ -18,8 +18,10 @@
 // one atomic latency per kDepSlots steps instead of per step.  The burst
 // is transposed (flush_rings): each atomic instruction carries consecutive
 // deposits of a few packages, and on a regular grid the private copies are
-// kept in 2 x 2 x 2 bricks (brick_cell), so that these neighbouring cells
-// often share a 64-byte line and one memory-side transaction.
+// kept in 2 x 2 x 2 bricks (brick_cell; on an octree its root cells, the
+// eight children of a cell being contiguous already), so that these
+// neighbouring cells often share a 64-byte line and one memory-side
+// transaction.
 #include "soc_device.h"
 
 namespace soc {
@@ -98,8 +100,9 @@ __device__ __forceinline__ void mc_frequency(const McArgs &A, double *lds_dep, i
     const int ring = (int)threadIdx.x * kRingStride;
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const bool brick = !Oct && A.brick;
+    const bool brick = A.brick;
     const int32_t hx = A.nx >> 1, hy = A.ny >> 1;
+    const int64_t nroot = A.nroot;
     Pkg<float> p;
     Rng rng;
     bool active = false;   // lane holds a package
@@ -174,7 +177,9 @@ __device__ __forceinline__ void mc_frequency(const McArgs &A, double *lds_dep, i
             o.cell = 0;
             o.event = kEvCross;
             o.dep = 0.0;
-            const int32_t bcell = brick ? brick_cell(p.cx, p.cy, p.cz, hx, hy) : 0;   // the cell before the step
+            // the cell before the step; a root cell (every cell of a regular
+            // grid) by its brick index
+            const int32_t bcell = brick ? (p.c < nroot ? brick_cell(p.cx, p.cy, p.cz, hx, hy) : p.c) : 0;
             if (stepping) {
                 float d;
                 o = step<float, Oct>(p, A, ks, ka, d);

@@ -55,10 +55,11 @@ hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_
 
 // Private copies of the absorbed array: add the kPrivCopies copies into the
 // caller's array in copy order and leave them zero for the next launch.
-// Brick order (hx = nx / 2 > 0, hy = ny / 2): copy entry i is cell
-// (2 bx + i mod 2, 2 by + (i / 2) mod 2, 2 bz + (i / 4) mod 2) of brick
-// i / 8 = bx + hx (by + hy bz).
-__global__ void fold_copies_kernel(double *absorbed, double *priv, int64_t n, int32_t hx, int32_t hy)
+// Brick order of the root cells (hx = nx / 2 > 0, hy = ny / 2, entries
+// i < nroot): copy entry i is root cell (2 bx + i mod 2, 2 by + (i / 2) mod 2,
+// 2 bz + (i / 4) mod 2) of brick i / 8 = bx + hx (by + hy bz); the other
+// entries are in cell order.
+__global__ void fold_copies_kernel(double *absorbed, double *priv, int64_t n, int32_t hx, int32_t hy, int64_t nroot)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double s = 0.0;
@@ -68,7 +69,7 @@ __global__ void fold_copies_kernel(double *absorbed, double *priv, int64_t n, in
             priv[x * n + i] = 0.0;
         }
         int64_t c = i;
-        if (hx > 0) {
+        if (hx > 0 && i < nroot) {
             const int64_t b = i >> 3, bx = b % hx, t = b / hx, by = t % hy, bz = t / hy;
             c = ((2 * bz + ((i >> 2) & 1)) * (2 * hy) + 2 * by + ((i >> 1) & 1)) * (2 * hx) + 2 * bx + (i & 1);
         }
@@ -77,11 +78,11 @@ __global__ void fold_copies_kernel(double *absorbed, double *priv, int64_t n, in
 }
 
 hipError_t launch_fold_copies(double *absorbed, double *priv, int64_t n, int32_t brick, int32_t nx, int32_t ny,
-                              hipStream_t s)
+                              int64_t nroot, hipStream_t s)
 {
     const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
     hipLaunchKernelGGL(fold_copies_kernel, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), 0, s, absorbed, priv, n,
-                       brick ? nx / 2 : 0, brick ? ny / 2 : 0);
+                       brick ? nx / 2 : 0, brick ? ny / 2 : 0, nroot);
     return hipGetLastError();
 }
 

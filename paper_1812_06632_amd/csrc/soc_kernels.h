@@ -73,8 +73,8 @@ struct McArgs {
     int64_t step_cap;
     double *absorbed;
     double *priv;                // NULL, or kPrivCopies private copies of ncells (see priv_index)
-    int32_t brick;               // 1: the private copies hold a regular grid of even dimensions in
-                                 // 2 x 2 x 2 bricks (brick_cell), folded back to the cell order
+    int32_t brick;               // 1: the private copies hold the root cells (even root dimensions)
+                                 // in 2 x 2 x 2 bricks (brick_cell), folded back to the cell order
     double *ali_self;            // diagonal ALI (NULL = off): dust deposits in the emitting cell
     double *priv_self;           // NULL, or kPrivCopies private copies of ali_self
     // persistent scheduling
@@ -175,10 +175,11 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t 
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 // absorbed[c] += sum_x priv[x n + c] over the kPrivCopies private copies, which are left zero.
-// Add the private copies into absorbed and clear them; brick: the copies
-// are in the brick order of a regular nx x ny x nz grid (even dimensions).
+// Add the private copies into absorbed and clear them; brick: their first
+// nroot entries are the root cells of an nx x ny x nz root grid (even
+// dimensions) in brick order.
 hipError_t launch_fold_copies(double *absorbed, double *priv, int64_t n, int32_t brick, int32_t nx, int32_t ny,
-                              hipStream_t s);
+                              int64_t nroot, hipStream_t s);
 
 // dust emission setup
 hipError_t launch_dust_luminosity(const uint32_t *words, int64_t ncells, const int64_t *level_offset,
@@ -298,6 +299,8 @@ struct PairDev {
     const PsArg *ps;          // n_ps entries, device
     int32_t nx, ny, nz, n_ps;
     int64_t ncells;
+    double *tally;            // tiles' deposits: the batch's brick-ordered scratch of this array, or absorbed
+    int32_t brick, pad0;      // 1: tally is in 2 x 2 x 2 brick order (even dimensions)
     float ks_f, ka_f, g_f, pad;
     double W_bg, face_tot;
     double face_cum[6];
@@ -350,6 +353,15 @@ struct BatchView {
 
 // lds_cells: the largest grid of a.lds_pairs (the LDS tally's size)
 hipError_t launch_mc_batch(const BatchArgs &a, int blocks, int threads, int64_t lds_cells, hipStream_t s);
+// A brick-ordered tally of the batch and the array it is added to.
+struct BrickFold {
+    double *tally;
+    double *absorbed;
+    int32_t nx, ny;
+    int64_t ncells;
+};
+// Add every brick-ordered tally into its array in cell order and clear it.
+hipError_t launch_batch_fold(const BrickFold *folds, int32_t n, int64_t max_cells, hipStream_t s);
 hipError_t launch_advance_iteration(uint32_t *it, int32_t mode, uint32_t value, hipStream_t s);
 
 // micro-benchmarks: which 0 = random FP64 atomics (mode 0 shared, 1 per

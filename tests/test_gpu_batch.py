@@ -48,16 +48,20 @@ def _pairs(grids, freqs, A, n_bg=3000):
     return pairs
 
 
-@pytest.mark.parametrize("lds_cells", [None, 0, 1000])
-def test_batch_equals_single_calls(soc, lds_cells):
+@pytest.mark.parametrize("lds_cells,copies", [(None, 1), (0, 1), (1000, 1), (0, 0)])
+def test_batch_equals_single_calls(soc, lds_cells, copies):
     """Pair (m, k) of a batch follows the same random numbers as a single
     soc_simulate_frequency call with seed ^ (m << 32): identical counters,
     identical absorbed energies up to FP64 summation order, for several
     tile sizes; with every grid tallied in LDS by whole-pair workgroups
     (the default: all five grids are small), none, or the grids of at most
-    1000 cells (a mix of both phases in one launch)."""
+    1000 cells (a mix of both phases in one launch).  Tiled grids with even
+    dimensions are tallied in a brick-ordered scratch copy that is folded
+    into their arrays after the launch (private copies on, copies 1), or
+    straight into their arrays (copies 0)."""
     grids, freqs = _clouds()
     ctx = soc.Context(0)
+    ctx.set_option("xcd_copies", copies)
     if lds_cells is not None:
         ctx.set_option("batch_lds_cells", lds_cells)
     assert ctx.get_option("batch_lds_cells") >= (lds_cells or 0)
@@ -110,15 +114,20 @@ def test_batch_matches_oracle_counts(soc):
     ctx.close()
 
 
-def test_batch_graph_replays_match_eager(soc):
+@pytest.mark.parametrize("lds_cells", [None, 0])
+def test_batch_graph_replays_match_eager(soc, lds_cells):
     """Capture [zero the absorbed arrays, batch launch with an advancing
     iteration, temperature update of every model] in a HIP graph; every
     replay equals the eager computation of the same iteration (replays
-    interleaved with eager work and synchronisations)."""
+    interleaved with eager work and synchronisations).  With every grid
+    tiled (lds_cells 0) the graph also holds the fold of the brick-ordered
+    scratch tallies."""
     grids, freqs = _clouds()
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         ctx = soc.Context(0, stream=s)
+        if lds_cells is not None:
+            ctx.set_option("batch_lds_cells", lds_cells)
         G = [soc.grid_from_workload(ctx, g) for g in grids]
         nu, w = W.frequency_grid(32)
         sabs, _, _ = W.dust_model(nu)

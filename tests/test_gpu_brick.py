@@ -1,13 +1,15 @@
-"""Private copies in 2 x 2 x 2 bricks.  On a regular grid with even
-dimensions the Monte Carlo kernels key their deposits into the private
-copies by brick, and the fold puts them back in cell order; with private
-copies off (option xcd_copies 0) deposits go straight to the caller's
-array in cell order.  The two must give identical counters and tallies
-equal up to FP64 summation order: on cubic and non-cubic grids, even and
-odd (odd dimensions keep the cell order), for one frequency with and
-without the diagonal-ALI tallies, for one launch of several frequencies,
-and for the no-allocation entry point.  One non-cubic even grid is also
-compared with the oracle for the same seed."""
+"""Private copies in 2 x 2 x 2 bricks.  On a grid with even root
+dimensions the Monte Carlo kernels key their deposits into the root cells
+of the private copies by brick (every cell of a regular grid; an octree's
+refined cells keep their order), and the fold puts them back in cell
+order; with private copies off (option xcd_copies 0) deposits go straight
+to the caller's array in cell order.  The two must give identical counters
+and tallies equal up to FP64 summation order: on cubic and non-cubic
+regular grids and octrees, even and odd (odd dimensions keep the cell
+order), for one frequency with and without the diagonal-ALI tallies, for
+one launch of several frequencies, and for the no-allocation entry point.
+One non-cubic even grid is also compared with the oracle for the same
+seed."""
 import numpy as np
 import pytest
 
@@ -175,3 +177,44 @@ def test_non_cubic_grid_against_oracle(soc, ctx):
     rel = np.abs(Ag[sel] - Ao[sel]) / Ao[sel]
     print(f"\nsame-seed per-cell rel diff: median {np.median(rel):.2e} max {rel.max():.2e} over {sel.sum()} cells")
     assert np.median(rel) < 1e-4 and rel.max() < 1e-2
+
+
+@pytest.mark.parametrize("n_root", [8, 7])
+def test_octree_root_cells(soc, ctx, n_root):
+    G = W.octree_lognormal(n_root=n_root, nlevels=3, sigma_ln=1.2, seed=5)
+    assert G.nlevels == 3 and G.ncells > G.nroot
+    g = soc.grid_from_workload(ctx, G)
+    rng = np.random.default_rng(2)
+    T = rng.uniform(10.0, 80.0, G.ncells).astype(np.float32)
+    T[G.density() == 0] = 0.0
+    Td = torch.from_numpy(T).cuda()
+    src = [dict(I_bg=float(I_BG[k]), n_bg=20000, ps_pos=[[0.41 * n_root, 0.52 * n_root, 0.47 * n_root]],
+                ps_Lnu=[1e22], n_ps_pk=10000, T=Td, n_dust=20000, dust_mode=1) for k in range(K)]
+
+    def one():
+        A = torch.zeros(G.ncells, dtype=torch.float64, device="cuda")
+        st = soc.simulate_frequency(ctx, g, FREQS[2], A, seed=7, iteration=2, freq_index=2, stats=True, **src[2])
+        return st, A.cpu().numpy()
+
+    def ali():
+        A = torch.zeros(G.ncells, dtype=torch.float64, device="cuda")
+        S = torch.zeros_like(A)
+        E = torch.zeros_like(A)
+        st = soc.simulate_frequency(ctx, g, FREQS[1], A, seed=8, iteration=2, freq_index=1, stats=True, T=Td,
+                                    n_dust=30000, dust_mode=1, ali_self=S, ali_emitted=E)
+        return st, A.cpu().numpy(), S.cpu().numpy()
+
+    def multi():
+        A = torch.zeros(G.ncells, dtype=torch.float64, device="cuda")
+        st = soc.simulate_frequencies(ctx, g, FREQS, A, src, list(range(K)), seed=9, iteration=3, stats=True)
+        return st, A.cpu().numpy()
+
+    for fn in (one, multi):
+        s1, a1 = _with_copies(ctx, 1, fn)
+        s0, a0 = _with_copies(ctx, 0, fn)
+        _same(s0, a0, s1, a1)
+    s1, a1, S1 = _with_copies(ctx, 1, ali)
+    s0, a0, S0 = _with_copies(ctx, 0, ali)
+    _same(s0, a0, s1, a1)
+    assert np.abs(S0).max() > 0
+    np.testing.assert_allclose(S1, S0, rtol=1e-11, atol=1e-12 * np.abs(S0).max())
