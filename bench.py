@@ -47,7 +47,7 @@ MC_KERNEL = "soc::mc_multi_kernel<false>"
 # WRITE_SIZE, scaled by a 1 GiB copy); used only while the kernel sources
 # and compile flags still hash to the value recorded with it.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mc_kernel_lognormal128_traffic.md")
-MC_SOURCES = ("mc.hip", "soc_device.h")
+MC_SOURCES = ("mc.hip", "soc_device.h", "soc_kernels.h")
 
 
 def log(msg):

@@ -70,7 +70,7 @@ typedef enum {
     SOC_OPT_BLOCK = 1,           /* threads per workgroup of the MC kernel, multiple of 64 in 64..512 [128] */
     SOC_OPT_BLOCKS_PER_CU = 2,   /* persistent workgroups launched per compute unit [4] */
     SOC_OPT_REFILL_MIN = 3,      /* refill a wave once this many lanes are idle, 1..64 [16] */
-    SOC_OPT_INNER_STEPS = 4,     /* cell steps between refill checks, 1..8 [1] */
+    SOC_OPT_INNER_STEPS = 4,     /* cell steps between refill checks, 1..16 [1] */
     SOC_OPT_TIMING = 5,          /* 1 = time each MC launch with HIP events [0] */
     SOC_OPT_SCATTER_MIN = 6,     /* draw new directions once this many lanes of a wave wait for one, 1..64 [1] */
     SOC_OPT_XCD_COPIES = 7,      /* 1 = each wave adds into one of 16 private copies of the absorbed array
