@@ -209,44 +209,68 @@ def batch_bench(args, soc, torch, W):
             ctx.set_option("batch_lds_cells", tuned["batch_lds_cells"])
             log(f"autotuned schedule {tuned} in {time.time() - t0:.1f}s: calibration launch {best_s * 1e3:.2f} ms "
                 f"(default schedule {t_default * 1e3:.2f} ms)")
-        tile = tuned["tile_packages"] if tuned else args.tile
         pairs = pair_list(range(len(grids)), range(len(nu)))
-        b = soc.Batch(ctx, G, pairs, seed=1, tile_packages=tile)
-        n_tiles, n_pk = b.info()
-        b.run(iteration=0)
-        torch.cuda.synchronize()
-        soc.graph_begin(ctx)
-        for a in A:
-            a.zero_()
-        b.run(iteration=soc.ITER_ADVANCE)
-        for m in range(len(grids)):
-            soc.update_temperature(ctx, G[m], table, A[m], T[m])
-        graph = soc.graph_end(ctx)
-        for _ in range(max(args.warmup, 1)):
-            graph.launch()
-        torch.cuda.synchronize()
-        before = ctx.read_stats()
-        t0 = time.time()
-        for _ in range(args.steps):
-            graph.launch()
-        torch.cuda.synchronize()
-        el = time.time() - t0
-        after = ctx.read_stats()
-        pk_done = after["packages"] - before["packages"]
-        st_done = after["cell_steps"] - before["cell_steps"]
+
+        def full_pass(cfg, reps):
+            """Build the whole batch under schedule cfg, capture one pass in a
+            graph and time reps replays: (s per pass, packages, cell steps,
+            tiles, packages per pass)."""
+            AT.apply(ctx, cfg)
+            ctx.set_option("batch_lds_cells", cfg["batch_lds_cells"])
+            bb = soc.Batch(ctx, G, pairs, seed=1, tile_packages=cfg["tile_packages"])
+            nt, npk = bb.info()
+            bb.run(iteration=0)
+            torch.cuda.synchronize()
+            soc.graph_begin(ctx)
+            for a in A:
+                a.zero_()
+            bb.run(iteration=soc.ITER_ADVANCE)
+            for m in range(len(grids)):
+                soc.update_temperature(ctx, G[m], table, A[m], T[m])
+            gr = soc.graph_end(ctx)
+            for _ in range(max(args.warmup, 1)):
+                gr.launch()
+            torch.cuda.synchronize()
+            before = ctx.read_stats()
+            t1 = time.time()
+            for _ in range(reps):
+                gr.launch()
+            torch.cuda.synchronize()
+            el_ = time.time() - t1
+            after = ctx.read_stats()
+            gr.close()
+            bb.close()
+            return (el_ / reps, after["packages"] - before["packages"], after["cell_steps"] - before["cell_steps"],
+                    nt, npk)
+
+        # the calibration sample is 1/64 of the pass; the tuned schedule is
+        # kept only if it also beats the default on two replays of the
+        # whole pass
+        default_cfg = {k: ctx.get_option(k) for k in ("block", "blocks_per_cu", "refill_min", "chunk")}
+        default_cfg.update(tile_packages=args.tile, batch_lds_cells=lds_default)
+        full_check = None
+        chosen = default_cfg
+        if tuned:
+            tuned_cfg = dict(default_cfg, **tuned)
+            t_tuned_full = full_pass(tuned_cfg, 2)[0]
+            t_default_full = full_pass(default_cfg, 2)[0]
+            full_check = {"tuned_s": t_tuned_full, "default_s": t_default_full}
+            chosen = tuned_cfg if t_tuned_full <= t_default_full else default_cfg
+            log(f"whole pass: tuned {t_tuned_full:.3f}s, default {t_default_full:.3f}s")
+        per_pass, pk_done, st_done, n_tiles, n_pk = full_pass(chosen, args.steps)
+        el = per_pass * args.steps
     line = {"kind": "batch", "models": len(grids), "pairs": len(pairs), "tiles": n_tiles,
             "cells": int(sum(gr.ncells for gr in grids)), "packages_per_pass": n_pk, "passes": args.steps,
-            "ms_per_pass": el / args.steps * 1e3, "packages_per_s": pk_done / el, "cell_steps_per_s": st_done / el,
-            "tile_packages": tile, "graph": True,
+            "ms_per_pass": per_pass * 1e3, "packages_per_s": pk_done / el, "cell_steps_per_s": st_done / el,
+            "tile_packages": chosen["tile_packages"], "graph": True,
             "schedule": {k: ctx.get_option(k) for k in ("block", "blocks_per_cu", "refill_min", "chunk",
                                                        "scatter_min", "inner_steps", "batch_lds_cells")},
-            "autotuned": tuned is not None,
+            "autotuned": tuned is not None, "schedule_kept": "tuned" if chosen is not default_cfg else "default",
+            "whole_pass_check": full_check,
             "calibration": ({"workload": "every 8th model at every 8th frequency (1/64 of the pass)",
                              "best_s": best_s, "default_schedule_s": t_default, "candidates": n_cand}
                             if tuned else None)}
     print(json.dumps(line), flush=True)
-    graph.close()
-    b.close()
     ctx.close()
 
 

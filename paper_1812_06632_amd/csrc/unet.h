@@ -115,6 +115,9 @@ private:
     float *d_params_ = nullptr, *d_grads_ = nullptr, *d_m_ = nullptr, *d_v_ = nullptr;
     float *d_part_ = nullptr;   // split-K weight-gradient partials
     int64_t cap_part_ = 0;
+    void *d_prep_ = nullptr;    // the weight-layout jobs of every layer (device table)
+    int32_t n_prep_ = 0;
+    int64_t max_prep_ = 0;      // elements of the largest job
     double *d_loss_part_ = nullptr;
     uint16_t *d_xin_ = nullptr;   // padded BF16 input
     uint16_t *d_gy_ = nullptr;    // padded BF16 output gradient

@@ -309,17 +309,23 @@ __global__ __launch_bounds__(256) void conv3_lds_kernel(ConvArgs a)
 // channels per LDS chunk, and four 32-row tiles per wave (two z-planes),
 // so every B fragment feeds four MFMAs per column tile.  The x-taps and
 // the per-tap channel groups are unrolled so that the weight loads of a
-// tap row are issued before its MFMAs.
+// tap row are issued before its MFMAs.  A halo position is its 16
+// channels (32 bytes, two 16-byte units) and a halo row of 10 positions
+// is padded to 21 units: the 16 lanes of an operand read that the LDS
+// serves together (two x-rows of 8 positions) then fall on 16 different
+// units of a 256-byte window, the even ones for one row and the odd ones
+// for the other, so the reads are free of bank conflicts; the halo takes
+// 33.6 KB, and with at most 128 registers four workgroups share a CU.
 constexpr int kB3 = 8;
 constexpr int kH3 = kB3 + 2;             // 10
 constexpr int kHalo3 = kH3 * kH3 * kH3;  // 1000 positions
-constexpr int kCC3 = 16;
-constexpr int kHS3 = kCC3 + 8;           // 24 elements = 48 bytes per position
+constexpr int kCC3 = 16;                 // 32 bytes per position, unpadded
+constexpr int kRow3 = kH3 * kCC3 + 8;    // 168 elements per halo row: an odd number of 16-byte units
 
 template <int NT>
-__global__ __launch_bounds__(256) void conv3_big_kernel(ConvArgs a)
+__global__ __launch_bounds__(256, 4) void conv3_big_kernel(ConvArgs a)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t halo[kHalo3 * kHS3];   // 48000 B
+    __shared__ __attribute__((aligned(16))) uint16_t halo[kH3 * kH3 * kRow3];   // 33600 B
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -343,7 +349,7 @@ __global__ __launch_bounds__(256) void conv3_big_kernel(ConvArgs a)
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const int lz = 2 * wave + (t >> 1), ly = (t & 1) * 4 + (r >> 3);
-        hbase[t] = (lz * kH3 + ly) * kH3 + lx;
+        hbase[t] = (lz * kH3 + ly) * kRow3 + lx * kCC3 + 8 * half;
     }
     const uint16_t *wrow[NT];
 #pragma unroll
@@ -366,12 +372,12 @@ __global__ __launch_bounds__(256) void conv3_big_kernel(ConvArgs a)
             if (zz >= 0 && zz < a.iz && yy >= 0 && yy < a.iy && xx >= 0 && xx < a.ix)
                 v = *reinterpret_cast<const u32x4 *>(
                     a.x + (size_t)(((b * a.iz + zz) * a.iy + yy) * a.ix + xx) * a.x_cs + a.x_co + c0 + 8 * g);
-            *reinterpret_cast<u32x4 *>(&halo[pos * kHS3 + 8 * g]) = v;
+            *reinterpret_cast<u32x4 *>(&halo[(hz * kH3 + hy) * kRow3 + hx * kCC3 + 8 * g]) = v;
         }
         __syncthreads();
         for (int tzy = 0; tzy < 9; ++tzy) {
             const int tz = tzy / 3, ty = tzy % 3;
-            const int hoff = (tz * kH3 + ty) * kH3;
+            const int hoff = (tz * kH3 + ty) * kRow3;
             bf16x8_t B[3][NT];
 #pragma unroll
             for (int tx = 0; tx < 3; ++tx)
@@ -383,7 +389,7 @@ __global__ __launch_bounds__(256) void conv3_big_kernel(ConvArgs a)
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
                     A[t] = __builtin_bit_cast(
-                        bf16x8_t, *reinterpret_cast<const u32x4 *>(&halo[(hbase[t] + hoff + tx) * kHS3 + 8 * half]));
+                        bf16x8_t, *reinterpret_cast<const u32x4 *>(&halo[hbase[t] + hoff + tx * kCC3]));
 #pragma unroll
                 for (int s = 0; s < NT; ++s)
 #pragma unroll
@@ -660,12 +666,12 @@ __global__ __launch_bounds__(192, 2) void wgrad3_kernel(WgradArgs a)
         if (tid < 32 && o0 + tid < a.cout) {
             float t = 0.0f;
             for (int q = 0; q < 6; ++q) t += bred[q][tid];
-            const size_t nchunks = gridDim.x;
-            a.part[nchunks * 27 * a.cin * a.cout + (size_t)blockIdx.x * a.cout + o0 + tid] = t;
+            const size_t row = (size_t)27 * a.cin * a.cout + a.cout;   // a chunk's weight partials, then its bias partials
+            a.part[(size_t)blockIdx.x * row + (size_t)27 * a.cin * a.cout + o0 + tid] = t;
         }
     }
     // partials of this chunk: rows = input channels, columns = output channels
-    float *out = a.part + (size_t)blockIdx.x * 27 * a.cin * a.cout;
+    float *out = a.part + (size_t)blockIdx.x * ((size_t)27 * a.cin * a.cout + a.cout);
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         const int tap = tz * 9 + q;
@@ -743,26 +749,30 @@ struct PrepArgs {
     int32_t transposed, flip;
 };
 
-__global__ void prep_weights_kernel(PrepArgs a)
+// Every layout job of the network in one launch: blockIdx.y is the job,
+// the x dimension strides over its elements.
+__global__ void prep_weights_kernel(const PrepArgs *jobs)
 {
+    const PrepArgs a = jobs[blockIdx.y];
     const int64_t total = (int64_t)a.nph * a.npad * a.taps * a.crow;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= total) return;
-    int64_t t = e;
-    const int c = t % a.crow;
-    t /= a.crow;
-    const int tap = t % a.taps;
-    t /= a.taps;
-    const int n = t % a.npad;
-    const int ph = t / a.npad;
-    const int slot = a.nph > 1 ? ph : (a.flip ? a.nslots - 1 - tap : tap);
-    float v = 0.0f;
-    if (a.transposed) {
-        if (n < a.cin && c < a.cout) v = a.W[((size_t)slot * a.cin + n) * a.cout + c];
-    } else {
-        if (c < a.cin && n < a.cout) v = a.W[((size_t)slot * a.cin + c) * a.cout + n];
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int64_t t = e;
+        const int c = t % a.crow;
+        t /= a.crow;
+        const int tap = t % a.taps;
+        t /= a.taps;
+        const int n = t % a.npad;
+        const int ph = t / a.npad;
+        const int slot = a.nph > 1 ? ph : (a.flip ? a.nslots - 1 - tap : tap);
+        float v = 0.0f;
+        if (a.transposed) {
+            if (n < a.cin && c < a.cout) v = a.W[((size_t)slot * a.cin + n) * a.cout + c];
+        } else {
+            if (c < a.cin && n < a.cout) v = a.W[((size_t)slot * a.cin + c) * a.cout + n];
+        }
+        a.out[e] = f2bf(v);
     }
-    a.out[e] = f2bf(v);
 }
 
 // FP32 [npos][c] -> BF16 [npos][cpad], zero padded.
@@ -896,6 +906,29 @@ Net::WgradPlan Net::plan_wgrad(const Layer &L, int32_t n) const
     return p;
 }
 
+// The forward and backward-data layout jobs of every layer.
+static std::vector<PrepArgs> prep_jobs(const std::vector<Layer> &layers, float *params)
+{
+    std::vector<PrepArgs> jobs;
+    for (const auto &L : layers) {
+        const int taps = taps_of(L.kind);
+        PrepArgs f{params + L.w_off, L.cin, L.cout, taps, L.wf, 1, taps, L.npad_f, L.cin_buf, 0, 0};
+        PrepArgs b{params + L.w_off, L.cin, L.cout, taps, L.wb, 1, taps, L.npad_b, L.cout_buf, 1, 0};
+        if (L.kind == Layer::CONV3) {
+            b.flip = 1;
+        } else if (L.kind == Layer::UP2) {
+            f.nph = 8;   // forward: eight phase GEMMs over the input channels
+            f.taps = 1;
+        } else {
+            b.nph = 8;   // down2 backward-data: eight phase GEMMs
+            b.taps = 1;
+        }
+        jobs.push_back(f);
+        jobs.push_back(b);
+    }
+    return jobs;
+}
+
 Net::Status Net::create(int dev, int32_t cin, int32_t cout, int32_t base, int32_t levels, int32_t nmax, int32_t nz,
                         int32_t ny, int32_t nx, uint64_t seed, hipStream_t s)
 {
@@ -1009,6 +1042,15 @@ Net::Status Net::create(int dev, int32_t cin, int32_t cout, int32_t base, int32_
     cap_part_ = 0;
     for (auto &L : layers_) cap_part_ = std::max(cap_part_, plan_wgrad(L, nmax).chunks * (L.nw + L.cout));
     ALLOC(d_part_, float, std::max<int64_t>(cap_part_, kColBlocks * 4096));
+    {
+        const std::vector<PrepArgs> jobs = prep_jobs(layers_, d_params_);
+        ALLOC(d_prep_, PrepArgs, jobs.size());
+        if (hipMemcpy(d_prep_, jobs.data(), sizeof(PrepArgs) * jobs.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return {HIP_ERROR, "weight-layout table upload failed"};
+        n_prep_ = (int32_t)jobs.size();
+        max_prep_ = 0;
+        for (const auto &j : jobs) max_prep_ = std::max<int64_t>(max_prep_, (int64_t)j.nph * j.npad * j.taps * j.crow);
+    }
 #undef ALLOC
 
     // He-normal weights, zero biases, zero optimiser state
@@ -1037,24 +1079,10 @@ void Net::destroy()
 
 hipError_t Net::prep_weights(hipStream_t s)
 {
-    for (auto &L : layers_) {
-        const int taps = taps_of(L.kind);
-        PrepArgs f{d_params_ + L.w_off, L.cin, L.cout, taps, L.wf, 1, taps, L.npad_f, L.cin_buf, 0, 0};
-        PrepArgs b{d_params_ + L.w_off, L.cin, L.cout, taps, L.wb, 1, taps, L.npad_b, L.cout_buf, 1, 0};
-        if (L.kind == Layer::CONV3) {
-            b.flip = 1;
-        } else if (L.kind == Layer::UP2) {
-            f.nph = 8;   // forward: eight phase GEMMs over the input channels
-            f.taps = 1;
-        } else {
-            b.nph = 8;   // down2 backward-data: eight phase GEMMs
-            b.taps = 1;
-        }
-        hipLaunchKernelGGL(prep_weights_kernel, dim3(nblk((int64_t)f.nph * f.npad * f.taps * f.crow)), dim3(256), 0,
-                           s, f);
-        hipLaunchKernelGGL(prep_weights_kernel, dim3(nblk((int64_t)b.nph * b.npad * b.taps * b.crow)), dim3(256), 0,
-                           s, b);
-    }
+    if (n_prep_ == 0) return hipSuccess;
+    const int64_t gx = std::min<int64_t>(nblk(max_prep_), 1024);
+    hipLaunchKernelGGL(prep_weights_kernel, dim3((unsigned)gx, (unsigned)n_prep_), dim3(256), 0, s,
+                       (const PrepArgs *)d_prep_);
     return hipGetLastError();
 }
 
@@ -1218,14 +1246,13 @@ hipError_t Net::conv_wgrad(const Layer &L, int32_t n, const View &x, const View 
         hipLaunchKernelGGL(wgrad3_kernel, dim3((unsigned)p.chunks, ctiles, 1), dim3(192), 0, s, a);
     else
         hipLaunchKernelGGL(wgrad_kernel, dim3((unsigned)p.chunks, ctiles, (unsigned)slots), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(sum_chunks_kernel, dim3(nblk(L.nw, kSumElems)), dim3(256), 0, s, (const float *)d_part_,
-                       (int32_t)p.chunks, L.nw, d_grads_ + L.w_off);
-    if (p.bricks) {   // the 27-tap kernel left the bias partials after the weight partials
-        hipLaunchKernelGGL(sum_chunks_kernel, dim3(nblk(L.cout, kSumElems)), dim3(256), 0, s,
-                           (const float *)d_part_ + p.chunks * L.nw, (int32_t)p.chunks, (int64_t)L.cout,
-                           d_grads_ + L.b_off);
+    if (p.bricks) {   // the 27-tap kernel's chunk rows hold the weight, then the bias partials (b_off = w_off + nw)
+        hipLaunchKernelGGL(sum_chunks_kernel, dim3(nblk(L.nw + L.cout, kSumElems)), dim3(256), 0, s,
+                           (const float *)d_part_, (int32_t)p.chunks, L.nw + L.cout, d_grads_ + L.w_off);
         return hipGetLastError();
     }
+    hipLaunchKernelGGL(sum_chunks_kernel, dim3(nblk(L.nw, kSumElems)), dim3(256), 0, s, (const float *)d_part_,
+                       (int32_t)p.chunks, L.nw, d_grads_ + L.w_off);
     // bias gradient: column sums of dy over the output positions
     const int64_t npos = positions(lout, n);
     hipLaunchKernelGGL(colsum_kernel, dim3(kColBlocks), dim3(256), 0, s, (const uint16_t *)dy.p, dy.cs, dy.co, L.cout,
