@@ -325,10 +325,14 @@ __global__ void batch_fold_kernel(const BrickFold *folds)
 
 hipError_t launch_batch_fold(const BrickFold *folds, int32_t n, int64_t max_cells, hipStream_t s)
 {
-    if (n <= 0) return hipSuccess;
-    const int64_t bx = std::min<int64_t>((max_cells + 255) / 256, 256);
-    hipLaunchKernelGGL(batch_fold_kernel, dim3((unsigned)std::max<int64_t>(bx, 1), (unsigned)n), dim3(256), 0, s, folds);
-    return hipGetLastError();
+    const int64_t bx = std::max<int64_t>(std::min<int64_t>((max_cells + 255) / 256, 256), 1);
+    for (int32_t f0 = 0; f0 < n; f0 += 65535) {   // the grid's y dimension holds at most 65535 tallies
+        const int32_t nf = std::min<int32_t>(65535, n - f0);
+        hipLaunchKernelGGL(batch_fold_kernel, dim3((unsigned)bx, (unsigned)nf), dim3(256), 0, s, folds + f0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // mode 0: set the iteration word to value; mode 1: advance it by one
