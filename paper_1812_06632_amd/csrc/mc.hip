@@ -93,8 +93,8 @@ struct WaveTally {
 // chunks, until the ids are used up and every lane of the wave has
 // finished.  Deposits go through the lane's LDS ring to dst (sdst: the
 // ALI self-absorption tally), keyed by brick_cell when A.brick is set.
-template <bool Oct, bool Ali>
-__device__ __forceinline__ void mc_frequency(const McArgs &A, double *lds_dep, int32_t *lds_cell, double *dst,
+template <bool Oct, bool Ali, typename AT>
+__device__ __forceinline__ void mc_frequency(const AT &A, double *lds_dep, int32_t *lds_cell, double *dst,
                                              double *sdst, WaveTally &w)
 {
     const int ring = (int)threadIdx.x * kRingStride;
@@ -274,6 +274,9 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_multi_kernel(MultiArgs M)
 {
     extern __shared__ double lds_dep[];   // [blockDim.x][kRingStride] deposits, then cells
     int32_t *lds_cell = (int32_t *)(lds_dep + kRingStride * blockDim.x);
+    // the argument blocks do not change during the launch: read them through
+    // the constant address space, so that their fields are scalar loads
+    const __attribute__((address_space(4))) McArgs *args = (const __attribute__((address_space(4))) McArgs *)M.args;
     const McArgs &A0 = M.args[0];
     double *const dst = A0.priv ? A0.priv + (size_t)priv_index() * (size_t)A0.ncells : A0.absorbed;
     WaveTally w;
@@ -281,7 +284,7 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_multi_kernel(MultiArgs M)
     const int k0 = M.spread ? wave % M.K : 0;
     for (int j = 0; j < M.K; ++j) {
         const int k = __builtin_amdgcn_readfirstlane((k0 + j) % M.K);
-        mc_frequency<Oct, false>(M.args[k], lds_dep, lds_cell, dst, nullptr, w);
+        mc_frequency<Oct, false>(args[k], lds_dep, lds_cell, dst, nullptr, w);
     }
     flush_deposits<false>(dst, nullptr, lds_dep, lds_cell, w.nbuf);
     flush_stats(A0, w.n_pk, w.n_st, w.n_sc, w.n_ru, w.e_em, w.e_ab, w.e_es);
