@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_STEP = 12.0   # 4 B density gather + 8 B FP64 absorbed update per cell step
 # regular-grid instantiation of the persistent MC kernel that runs every
 # frequency of a pass in one launch
-MC_KERNEL = "soc::mc_multi_kernel<false>"
+MC_KERNEL = "soc::mc_multi_kernel<false, false>"
 # HBM traffic of the MC kernel measured with rocprofv3 counters (FETCH_SIZE,
 # WRITE_SIZE, scaled by a 1 GiB copy); used only while the kernel sources
 # and compile flags still hash to the value recorded with it.

@@ -806,7 +806,8 @@ soc_status soc_simulate_frequencies(soc_ctx c, soc_grid g, int32_t K, const soc_
     int64_t nL = 0, npk = 0;
     for (int32_t k = 0; k < K; ++k) {
         const soc_sources &q = srcs[k];
-        if (q.d_ali_self || q.d_ali_emitted) return fail(c, SOC_EINVAL, "frequency %d: ALI tallies need soc_simulate_frequency", k);
+        if (q.d_ali_self != srcs[0].d_ali_self || q.d_ali_emitted != srcs[0].d_ali_emitted)
+            return fail(c, SOC_EINVAL, "frequency %d: every frequency of the call must use the same ALI tallies", k);
         if (q.d_T && q.n_dust > 0) {
             if (q.dust_mode == 0 || q.dust_mode == 2 || q.dust_cap > 0.0) nL += g->ncells;   // the kernel reads L
             if (q.dust_mode != 0) npk += (int64_t)q.n_dust;
@@ -849,6 +850,13 @@ soc_status soc_simulate_frequencies(soc_ctx c, soc_grid g, int32_t K, const soc_
             A.priv = c->d_priv;
             A.brick = brick_copies(g);
         }
+        if (srcs[0].d_ali_self) {
+            if (c->cap_priv_self < (int64_t)kPrivCopies * g->ncells) {
+                if ((st = grow(c, &c->d_priv_self, c->cap_priv_self, (int64_t)kPrivCopies * g->ncells))) return st;
+                HIPCHK(c, launch_fill_f64(c->d_priv_self, 0.0, c->cap_priv_self, c->stream));
+            }
+            for (auto &A : c->h_margs) A.priv_self = c->d_priv_self;
+        }
     }
     HIPCHK(c, hipMemcpyAsync(c->d_margs, c->h_margs.data(), sizeof(McArgs) * (size_t)K, hipMemcpyHostToDevice,
                              c->stream));
@@ -864,7 +872,8 @@ soc_status soc_simulate_frequencies(soc_ctx c, soc_grid g, int32_t K, const soc_
     M.args = c->d_margs;
     M.K = K;
     M.spread = (int32_t)c->multi_spread;
-    HIPCHK(c, launch_mc_multi(M, g->nlevels, (int)(c->num_cus * c->blocks_per_cu), (int)c->block, c->stream));
+    const bool ali = srcs[0].d_ali_self != nullptr;
+    HIPCHK(c, launch_mc_multi(M, g->nlevels, ali, (int)(c->num_cus * c->blocks_per_cu), (int)c->block, c->stream));
     if (c->timing) {
         HIPCHK(c, hipEventRecord(e1, c->stream));
         c->ev_start.push_back(e0);
@@ -872,6 +881,9 @@ soc_status soc_simulate_frequencies(soc_ctx c, soc_grid g, int32_t K, const soc_
     }
     if (c->xcd_copies)
         HIPCHK(c, launch_fold_copies(d_absorbed, c->d_priv, g->ncells, brick_copies(g), g->nx, g->ny, g->nroot, c->stream));
+    if (c->xcd_copies && ali)
+        HIPCHK(c, launch_fold_copies(srcs[0].d_ali_self, c->d_priv_self, g->ncells, brick_copies(g), g->nx, g->ny, g->nroot,
+                                     c->stream));
     if (stats) {
         DevStats h;
         HIPCHK(c, hipMemcpyAsync(&h, c->d_stats, sizeof h, hipMemcpyDeviceToHost, c->stream));

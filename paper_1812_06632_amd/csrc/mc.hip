@@ -268,8 +268,9 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_ali_kernel(McArgs A)
 // the last frequencies leave a tail, not every one.  The rotation starts
 // at the wave's own index (spread: the waves divide over the frequencies)
 // or at 0 (all waves on one frequency, the next one filling in as it
-// ends).
-template <bool Oct>
+// ends).  With Ali, a dust package's deposits in its emitting cell go to
+// the self-absorption tally, as in mc_ali_kernel.
+template <bool Oct, bool Ali>
 __global__ __launch_bounds__(kMcMaxBlock) void mc_multi_kernel(MultiArgs M)
 {
     extern __shared__ double lds_dep[];   // [blockDim.x][kRingStride] deposits, then cells
@@ -279,22 +280,26 @@ __global__ __launch_bounds__(kMcMaxBlock) void mc_multi_kernel(MultiArgs M)
     const __attribute__((address_space(4))) McArgs *args = (const __attribute__((address_space(4))) McArgs *)M.args;
     const McArgs &A0 = M.args[0];
     double *const dst = A0.priv ? A0.priv + (size_t)priv_index() * (size_t)A0.ncells : A0.absorbed;
+    double *const sdst = !Ali ? nullptr
+                              : (A0.priv_self ? A0.priv_self + (size_t)priv_index() * (size_t)A0.ncells : A0.ali_self);
     WaveTally w;
     const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     const int k0 = M.spread ? wave % M.K : 0;
     for (int j = 0; j < M.K; ++j) {
         const int k = __builtin_amdgcn_readfirstlane((k0 + j) % M.K);
-        mc_frequency<Oct, false>(args[k], lds_dep, lds_cell, dst, nullptr, w);
+        mc_frequency<Oct, Ali>(args[k], lds_dep, lds_cell, dst, sdst, w);
     }
-    flush_deposits<false>(dst, nullptr, lds_dep, lds_cell, w.nbuf);
+    flush_deposits<Ali>(dst, sdst, lds_dep, lds_cell, w.nbuf);
     flush_stats(A0, w.n_pk, w.n_st, w.n_sc, w.n_ru, w.e_em, w.e_ab, w.e_es);
 }
 
-hipError_t launch_mc_multi(const MultiArgs &m, int nlevels, int blocks, int threads, hipStream_t s)
+hipError_t launch_mc_multi(const MultiArgs &m, int nlevels, bool ali, int blocks, int threads, hipStream_t s)
 {
     const size_t lds = (size_t)kRingStride * threads * (sizeof(double) + sizeof(int32_t));
-    if (nlevels > 1) hipLaunchKernelGGL(mc_multi_kernel<true>, dim3(blocks), dim3(threads), lds, s, m);
-    else hipLaunchKernelGGL(mc_multi_kernel<false>, dim3(blocks), dim3(threads), lds, s, m);
+    if (nlevels > 1 && ali) hipLaunchKernelGGL((mc_multi_kernel<true, true>), dim3(blocks), dim3(threads), lds, s, m);
+    else if (nlevels > 1) hipLaunchKernelGGL((mc_multi_kernel<true, false>), dim3(blocks), dim3(threads), lds, s, m);
+    else if (ali) hipLaunchKernelGGL((mc_multi_kernel<false, true>), dim3(blocks), dim3(threads), lds, s, m);
+    else hipLaunchKernelGGL((mc_multi_kernel<false, false>), dim3(blocks), dim3(threads), lds, s, m);
     return hipGetLastError();
 }
 

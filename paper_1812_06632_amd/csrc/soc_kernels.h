@@ -169,7 +169,7 @@ struct MultiArgs {
     int32_t K;
     int32_t spread;   // 1: wave w starts at frequency w mod K; 0: every wave starts at 0
 };
-hipError_t launch_mc_multi(const MultiArgs &m, int nlevels, int blocks, int threads, hipStream_t s);
+hipError_t launch_mc_multi(const MultiArgs &m, int nlevels, bool ali, int blocks, int threads, hipStream_t s);
 hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_t s);
 hipError_t launch_trace(const McArgs &a, const TraceArgs &t, int precision, hipStream_t s);
 hipError_t launch_peel(const McArgs &a, const PeelArgs &p, int blocks, hipStream_t s);

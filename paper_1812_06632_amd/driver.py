@@ -50,13 +50,12 @@ class PlainSolver:
         none); ali: diagonal ALI (Sect. 2.1.2) in the dust iterations;
         multi: every frequency of a pass in one launch
         (soc_simulate_frequencies) rather than one launch per frequency --
-        the same packages and results up to FP64 summation order (not with
-        ALI, whose tallies need one launch per frequency)."""
+        the same packages and results up to FP64 summation order."""
         self.ctx, self.P, self.seed = ctx, P, seed
         self.packages = packages
         self.cap = float(cap)
         self.ali = bool(ali)
-        self.multi = bool(multi) and not self.ali
+        self.multi = bool(multi)
         self.grid = soc.grid_from_workload(ctx, P.grid)
         self.table = soc.temp_table_build(ctx, P.emit_nu, P.emit_w, P.emit_sigma_abs, P.T_floor, P.T_max, nT)
         nc = P.grid.ncells

@@ -6,7 +6,8 @@ summation order.  Covered: constant sources (field and point sources),
 luminosity-weighted dust emission with and without the per-cell cap,
 uniform dust emission, the reference-field correction (mode 2, its
 per-frequency reference blended in place), frequencies with different
-package counts, an octree, K = 1, and the argument errors.  The
+package counts, the diagonal-ALI tallies, an octree, K = 1, and the
+argument errors.  The
 iteration drivers run on top of it (tests/test_gpu_driver.py,
 tests/test_gpu_reference.py)."""
 import numpy as np
@@ -148,13 +149,49 @@ def test_octree_and_single_frequency(soc, ctx):
     _check(*_both(soc, ctx, g, G.ncells, freqs[2:3], src[2:3], [2], 16, 1))
 
 
+@pytest.mark.parametrize("copies", [1, 0])
+def test_ali_tallies(soc, ctx, cloud, copies):
+    """Diagonal ALI in one launch: the absorbed energy, the self-absorption
+    and the emitted-energy tallies equal those of one call per frequency."""
+    P, T = cloud
+    saved = ctx.get_option("xcd_copies")
+    ctx.set_option("xcd_copies", copies)
+    try:
+        g = soc.grid_from_workload(ctx, P.grid)
+        out = []
+        for multi in (False, True):
+            A = torch.zeros(P.grid.ncells, dtype=torch.float64, device="cuda")
+            S = torch.zeros_like(A)
+            E = torch.zeros_like(A)
+            src = [dict(T=T, n_dust=20000 + 501 * k, dust_mode=1, ali_self=S, ali_emitted=E) for k in range(P.K)]
+            if multi:
+                st = soc.simulate_frequencies(ctx, g, _freqs(P), A, src, list(range(P.K)), seed=17, iteration=2,
+                                              stats=True)
+            else:
+                st = None
+                for k in range(P.K):
+                    s = soc.simulate_frequency(ctx, g, _freqs(P)[k], A, seed=17, iteration=2, freq_index=k,
+                                               stats=True, **src[k])
+                    st = s if st is None else {key: st[key] + s[key] for key in st}
+            out.append((A.cpu().numpy(), st, S.cpu().numpy(), E.cpu().numpy()))
+        (a1, s1, S1, E1), (a2, s2, S2, E2) = out
+        _check(a1, s1, a2, s2)
+        assert np.abs(S1).max() > 0 and np.abs(E1).max() > 0
+        np.testing.assert_allclose(S2, S1, rtol=1e-11, atol=1e-12 * np.abs(S1).max())
+        np.testing.assert_allclose(E2, E1, rtol=1e-11, atol=1e-12 * np.abs(E1).max())
+    finally:
+        ctx.set_option("xcd_copies", saved)
+
+
 def test_errors(soc, ctx, cloud):
     P, T = cloud
     g = soc.grid_from_workload(ctx, P.grid)
     A = torch.zeros(P.grid.ncells, dtype=torch.float64, device="cuda")
-    with pytest.raises(soc.SocError, match="ALI"):
-        soc.simulate_frequencies(ctx, g, _freqs(P)[:1], A, [dict(T=T, n_dust=100, dust_mode=1, ali_self=A,
-                                                               ali_emitted=torch.zeros_like(A))], [0])
+    S, E = torch.zeros_like(A), torch.zeros_like(A)
+    with pytest.raises(soc.SocError, match="same ALI tallies"):
+        soc.simulate_frequencies(ctx, g, _freqs(P)[:2], A, [dict(T=T, n_dust=100, dust_mode=1, ali_self=S,
+                                                               ali_emitted=E), dict(T=T, n_dust=100, dust_mode=1)],
+                                 [0, 1])
     with pytest.raises(soc.SocError, match="frequency 1"):
         soc.simulate_frequencies(ctx, g, _freqs(P)[:2], A, [dict(I_bg=1.0, n_bg=10), dict(I_bg=-1.0, n_bg=10)],
                                  [0, 1])
