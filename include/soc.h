@@ -68,7 +68,7 @@ const char *soc_last_error(soc_ctx ctx);
 typedef enum {
     SOC_OPT_STEP_CAP = 0,        /* steps per package before it is stopped [10000000] */
     SOC_OPT_BLOCK = 1,           /* threads per workgroup of the MC kernel, multiple of 64 in 64..512 [128] */
-    SOC_OPT_BLOCKS_PER_CU = 2,   /* persistent workgroups launched per compute unit [4] */
+    SOC_OPT_BLOCKS_PER_CU = 2,   /* persistent workgroups launched per compute unit [6] */
     SOC_OPT_REFILL_MIN = 3,      /* refill a wave once this many lanes are idle, 1..64 [16] */
     SOC_OPT_INNER_STEPS = 4,     /* cell steps between refill checks, 1..16 [1] */
     SOC_OPT_TIMING = 5,          /* 1 = time each MC launch with HIP events [0] */

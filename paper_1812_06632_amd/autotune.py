@@ -21,7 +21,7 @@ import os
 
 DEFAULT_SPACE = {
     "block": (128, 256, 512),
-    "blocks_per_cu": (2, 4, 8),
+    "blocks_per_cu": (2, 4, 6, 8),
     "chunk": (256, 512),
     "refill_min": (1, 16),
     "scatter_min": (1,),

@@ -31,12 +31,15 @@ struct soc_ctx_s {
     std::string err;
     int num_cus = 256;
     int64_t step_cap = 10000000;
-    // default schedule, from the autotuner on the 128^3 benchmark cloud (dust
-    // emission at three frequencies): 8 waves per compute unit, each refilled
-    // once 16 of its lanes are idle -- 374 ms per iteration against 387 ms
-    // with 16 waves per CU refilled at every idle lane
+    // default schedule: 12 waves per compute unit, each refilled once 16 of
+    // its lanes are idle.  12 waves is what the Monte Carlo kernels' 152-163
+    // VGPRs allow per CU (3 per SIMD) and about what their deposit rings
+    // allow in LDS (157 KB of 160).  The regular-grid benchmark iteration
+    // takes the same time at 8, 10 or 12 waves (it waits on the memory-side
+    // atomics); the octree pass, bound by the latency of its dependent
+    // gathers, is 23% faster at 12 than at 8.
     int64_t block = 128;
-    int64_t blocks_per_cu = 4;
+    int64_t blocks_per_cu = 6;
     int64_t refill_min = 16;
     int64_t inner_steps = 1;
     int64_t timing = 0;

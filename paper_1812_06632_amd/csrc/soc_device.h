@@ -182,6 +182,7 @@ template <typename R>
 struct Pkg {
     int32_t cx, cy, cz;
     int32_t c, L;
+    int32_t par;   // octree: the parent of cell c when known (L > 0), else -1
     R fx, fy, fz;
     R ux, uy, uz;
     R ix, iy, iz;
@@ -321,6 +322,7 @@ __device__ inline void descend(Pkg<R> &p, const AT &A)
         p.fx = (R)2 * p.fx - (R)ox;
         p.fy = (R)2 * p.fy - (R)oy;
         p.fz = (R)2 * p.fz - (R)oz;
+        p.par = p.c;
         p.c = -w + ox + 2 * oy + 4 * oz;
         p.L += 1;
         w = (int32_t)A.words[p.c];
@@ -333,9 +335,11 @@ __device__ inline void descend(Pkg<R> &p, const AT &A)
 // while the face is also a face of the parent, across to the sibling (or
 // the neighbouring root cell), then down by position.  The exit coordinate
 // must already be on the face (1 when fw, 0 otherwise).  Returns false
-// when the package leaves the box.  Octets are 8-aligned relative to every
-// level offset, all of which are congruent to nroot mod 8, so the octant of
-// a non-root cell is (c - nroot) & 7.
+// when the package leaves the box.  The first step up takes the parent
+// the package passed on its way down (p.par) instead of reading the link.
+// Octets are 8-aligned relative to every level offset, all of which are
+// congruent to nroot mod 8, so the octant of a non-root cell is
+// (c - nroot) & 7.
 template <typename R, typename AT>
 __device__ inline bool cross_octree(Pkg<R> &p, const AT &A, int a, bool fw)
 {
@@ -355,6 +359,7 @@ __device__ inline bool cross_octree(Pkg<R> &p, const AT &A, int a, bool fw)
                 p.fz = fw ? (R)0 : (R)1;
             }
             p.c = p.cx + A.nx * (p.cy + A.ny * p.cz);
+            p.par = -1;
             break;
         }
         const int32_t o = (int32_t)((p.c - A.nroot) & 7);
@@ -369,7 +374,12 @@ __device__ inline bool cross_octree(Pkg<R> &p, const AT &A, int a, bool fw)
         p.fx = (p.fx + (R)(o & 1)) * (R)0.5;
         p.fy = (p.fy + (R)((o >> 1) & 1)) * (R)0.5;
         p.fz = (p.fz + (R)((o >> 2) & 1)) * (R)0.5;
-        p.c = A.parent[(p.c - A.nroot) >> 3];
+        // the parent is known when the package came down into this octet;
+        // the link is read only above that
+        int32_t up = p.par;
+        if (up < 0) up = A.parent[(p.c - A.nroot) >> 3];
+        p.c = up;
+        p.par = -1;
         p.L -= 1;
     }
     descend(p, A);
@@ -402,6 +412,7 @@ __device__ inline bool emit_base(const AT &A, uint64_t gid, Pkg<R> &p, Rng &rng,
                                  uint32_t &pid, double &W0)
 {
     p.L = 0;
+    p.par = -1;
     const uint64_t nps_tot = (uint64_t)A.n_ps * A.n_ps_pk;
     if (gid < A.n_bg) {
         cls = kClassBg;
@@ -492,7 +503,10 @@ __device__ inline bool emit_base(const AT &A, uint64_t gid, Pkg<R> &p, Rng &rng,
             int L = 0;
             while (L + 1 < A.nlevels && c >= A.level_offset[L + 1]) ++L;
             p.L = L;
-            for (int l = L; l > 0; --l) root = A.parent[(root - A.nroot) >> 3];
+            for (int l = L; l > 0; --l) {
+                root = A.parent[(root - A.nroot) >> 3];
+                if (l == L) p.par = (int32_t)root;
+            }
         }
         p.c = (int32_t)c;
         p.cx = (int32_t)(root % A.nx);
