@@ -81,6 +81,13 @@ struct soc_ctx_s {
     unsigned long long *d_mcount = nullptr;
     int64_t cap_mcount = 0;
     std::vector<McArgs> h_margs;   // staging of the argument blocks (kept until the next call)
+    // batched weighted-mode dust setup: one luminosity/cumulative row and
+    // one scan scratch row per frequency, the jobs and their staging
+    double *d_mincl = nullptr, *d_msums = nullptr;
+    int64_t cap_mincl = 0, cap_msums = 0;
+    DustJob *d_djobs = nullptr;
+    int64_t cap_djobs = 0;
+    std::vector<DustJob> h_djobs;
     std::vector<hipEvent_t> ev_start, ev_stop;
     bool capturing = false;
 };
@@ -209,7 +216,26 @@ struct ScratchSrc {
     double *L = nullptr;
     int32_t *pk = nullptr;
     double *S = nullptr;
+    // weighted mode without a cap: the luminosity row, its scan scratch and
+    // the job that the caller's batched setup fills them from (the tables
+    // are then not built here)
+    DustJob *job = nullptr;
+    double *incl = nullptr, *sums = nullptr;
 };
+
+// Largest total of the per-frequency luminosity rows that
+// soc_simulate_frequencies builds together (16 GiB: 64 frequencies of a
+// 256^3 grid take 8.6 GB).
+constexpr int64_t kDustRowsMaxBytes = int64_t(16) << 30;
+
+// Systematic-sampling offset of one frequency's weighted dust emission: the
+// first uniform of the stream of package id 2^32-1 of the dust class.
+double dust_offset(uint64_t seed, uint32_t iteration, uint32_t freq_index)
+{
+    uint32_t x0 = 0, x1 = 0xFFFFFFFFu, x2 = freq_index, x3 = (iteration << 8) | kClassDust;
+    philox4x32_10(x0, x1, x2, x3, (uint32_t)seed, (uint32_t)(seed >> 32));
+    return u01<double>(x0);
+}
 
 // Fixed slices of the no-allocation array (byte offsets, 256-aligned).
 constexpr int64_t kNaMaxCells = 32768;           // 32^3 cells, every level included
@@ -319,7 +345,23 @@ soc_status prepare(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *
     // for the weighted modes, the cell of every package
     A.n_dust = 0;
     A.dust_mode = s->dust_mode;
-    if (s->d_T && s->n_dust > 0) {
+    const bool deferred = src.job && s->d_T && s->n_dust > 0 && s->dust_mode == 1 && !(s->dust_cap > 0.0);
+    if (deferred) {
+        A.n_dust = s->n_dust;
+        DustJob &J = *src.job;
+        J.T = s->d_T;
+        J.nu = f->nu;
+        J.sigma_abs = f->sigma_abs;
+        J.w_nu = f->w_nu;
+        J.incl = src.incl;
+        J.sums = src.sums;
+        J.cell = src.pk;
+        J.n_dust = s->n_dust;
+        J.u_sys = dust_offset(seed, iteration, freq_index);
+        A.dust_L = src.incl;   // not read in this mode
+        A.dust_S = src.incl + (g->ncells - 1);
+        A.dust_cell = src.pk;
+    } else if (s->d_T && s->n_dust > 0) {
         A.n_dust = s->n_dust;
         double *dL = src.L, *da = nullptr;
         if (!dL && (st = take(c, src, &c->d_L, c->cap_L, g->ncells, kNaL, kNaMaxCells, &dL))) return st;
@@ -373,10 +415,7 @@ soc_status prepare(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *
             if (!dpk && (st = take(c, src, &c->d_pkcell, cap_pk, (int64_t)s->n_dust, kNaPk, kNaMaxDust, &dpk)))
                 return st;
             c->cap_pk = (uint64_t)cap_pk;
-            // systematic offset: first uniform of the stream of package id 2^32-1 of the dust class
-            uint32_t x0 = 0, x1 = 0xFFFFFFFFu, x2 = freq_index, x3 = (iteration << 8) | kClassDust;
-            philox4x32_10(x0, x1, x2, x3, (uint32_t)seed, (uint32_t)(seed >> 32));
-            const double u_sys = u01<double>(x0);
+            const double u_sys = dust_offset(seed, iteration, freq_index);
             HIPCHK(c, launch_dust_select(dincl, g->ncells, s->n_dust, u_sys, capped ? 1 : 0, dpk, c->stream));
             A.dust_cell = dpk;
         }
@@ -389,8 +428,9 @@ soc_status prepare(soc_ctx c, soc_grid g, const soc_freq *f, const soc_sources *
     A.step_cap = c->step_cap;
     A.absorbed = d_absorbed;
     A.ali_self = s->d_ali_self;
-    if (s->d_ali_emitted && A.n_dust > 0) {
+    if (s->d_ali_emitted && A.n_dust > 0 && !deferred) {
         // emitted dust energy per cell from the package assignment (no atomics)
+        // (a deferred frequency's comes after the caller's batched setup)
         if (A.dust_mode == 0)
             HIPCHK(c, launch_dust_emitted_uniform(g->d_leaves, g->nleaves, A.dust_L, A.per_leaf, s->d_ali_emitted,
                                                   c->stream));
@@ -528,6 +568,9 @@ void soc_ctx_destroy(soc_ctx c)
     (void)hipFree(c->d_mpk);
     (void)hipFree(c->d_margs);
     (void)hipFree(c->d_mcount);
+    (void)hipFree(c->d_mincl);
+    (void)hipFree(c->d_msums);
+    (void)hipFree(c->d_djobs);
     delete c;
 }
 
@@ -806,7 +849,11 @@ soc_status soc_simulate_frequencies(soc_ctx c, soc_grid g, int32_t K, const soc_
     if (K < 1 || K > 4096) return fail(c, SOC_EINVAL, "K must be in [1, 4096]");
     if (!freqs || !srcs || !freq_indices) return fail(c, SOC_EINVAL, "freqs, srcs and freq_indices must be given");
     NOT_WHILE_CAPTURING(c);
-    int64_t nL = 0, npk = 0;
+    int64_t nL = 0, npk = 0, njobs = 0;
+    uint64_t max_dust = 0;
+    const auto batched = [](const soc_sources &q) {
+        return q.d_T && q.n_dust > 0 && q.dust_mode == 1 && !(q.dust_cap > 0.0);
+    };
     for (int32_t k = 0; k < K; ++k) {
         const soc_sources &q = srcs[k];
         if (q.d_ali_self != srcs[0].d_ali_self || q.d_ali_emitted != srcs[0].d_ali_emitted)
@@ -815,7 +862,15 @@ soc_status soc_simulate_frequencies(soc_ctx c, soc_grid g, int32_t K, const soc_
             if (q.dust_mode == 0 || q.dust_mode == 2 || q.dust_cap > 0.0) nL += g->ncells;   // the kernel reads L
             if (q.dust_mode != 0) npk += (int64_t)q.n_dust;
         }
+        if (batched(q)) {
+            ++njobs;
+            max_dust = std::max<uint64_t>(max_dust, q.n_dust);
+        }
     }
+    // the weighted-mode tables of all frequencies are built together when
+    // their rows fit in kDustRowsMaxBytes; otherwise one frequency at a time
+    const int64_t scan_elems = (int64_t)scan_f64_scratch_elems(g->ncells);
+    if ((double)njobs * (double)g->ncells * sizeof(double) > (double)kDustRowsMaxBytes) njobs = 0;
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, hipStreamSynchronize(c->stream));   // the previous call's staging copy has been consumed
     soc_status st;
@@ -824,11 +879,23 @@ soc_status soc_simulate_frequencies(soc_ctx c, soc_grid g, int32_t K, const soc_
     if ((st = grow(c, &c->d_mS, c->cap_mS, K))) return st;
     if ((st = grow(c, &c->d_margs, c->cap_margs, K))) return st;
     if ((st = grow(c, &c->d_mcount, c->cap_mcount, K))) return st;
+    if (njobs > 0) {
+        if ((st = grow(c, &c->d_mincl, c->cap_mincl, njobs * g->ncells))) return st;
+        if ((st = grow(c, &c->d_msums, c->cap_msums, njobs * scan_elems))) return st;
+        if ((st = grow(c, &c->d_djobs, c->cap_djobs, njobs))) return st;
+    }
     c->h_margs.resize(K);
-    int64_t oL = 0, opk = 0;
+    c->h_djobs.assign((size_t)njobs, DustJob{});
+    int64_t oL = 0, opk = 0, j = 0;
     for (int32_t k = 0; k < K; ++k) {
         const soc_sources &q = srcs[k];
         ScratchSrc src;
+        if (njobs > 0 && batched(q)) {
+            src.job = &c->h_djobs[(size_t)j];
+            src.incl = c->d_mincl + j * g->ncells;
+            src.sums = c->d_msums + j * scan_elems;
+            ++j;
+        }
         const bool dust = q.d_T && q.n_dust > 0;
         if (dust && (q.dust_mode == 0 || q.dust_mode == 2 || q.dust_cap > 0.0)) {
             src.L = c->d_mL + oL;
@@ -843,6 +910,20 @@ soc_status soc_simulate_frequencies(soc_ctx c, soc_grid g, int32_t K, const soc_
         if ((st = prepare(c, g, &freqs[k], &q, seed, iteration, freq_indices[k], d_absorbed, A, src)))
             return fail(c, st, "frequency %d: %s", k, c->err.c_str());
         A.next_id = c->d_mcount + k;
+    }
+    if (njobs > 0) {
+        HIPCHK(c, hipMemcpyAsync(c->d_djobs, c->h_djobs.data(), sizeof(DustJob) * (size_t)njobs,
+                                 hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, launch_dust_setup_rows(g->d_words, g->ncells, g->level_offset.data(), g->nlevels, g->root_cell_cm,
+                                         c->d_djobs, (int32_t)njobs, max_dust, c->stream));
+        if (srcs[0].d_ali_emitted) {
+            for (int32_t k = 0; k < K; ++k) {
+                const McArgs &A = c->h_margs[k];
+                if (!batched(srcs[k])) continue;
+                HIPCHK(c, launch_dust_emitted_weighted(A.dust_cell, A.n_dust, A.dust_L, A.dust_S, A.dust_mode,
+                                                       A.dust_cap, srcs[k].d_ali_emitted, c->stream));
+            }
+        }
     }
     if (c->xcd_copies) {
         if (c->cap_priv < (int64_t)kPrivCopies * g->ncells) {   // new copies start zero; every fold leaves them zero

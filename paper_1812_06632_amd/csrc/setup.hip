@@ -110,22 +110,27 @@ __device__ inline double planck_nu(double nu, double T)
     return pre / expm1(x);
 }
 
+// Dust luminosity of cell c in one frequency band: 4 pi sigma_abs n V B_nu(T) w_nu
+// (Sect. 3.2); zero for a refined cell.
+__device__ inline double cell_luminosity(const uint32_t *words, int64_t c, const Levels &lv, int32_t nlevels,
+                                         double root_cell_cm, double nu, double sigma_abs, double w_nu,
+                                         const float *T)
+{
+    const double four_pi = 12.566370614359172;
+    const uint32_t w = words[c];
+    if ((int32_t)w < 0) return 0.0;
+    const double n = (double)__uint_as_float(w);
+    const int Lv = level_of(c, lv.off, nlevels);
+    const double s = ldexp(root_cell_cm, -Lv);
+    return four_pi * sigma_abs * n * (s * s * s) * planck_nu(nu, (double)T[c]) * w_nu;
+}
+
 __global__ void dust_luminosity_kernel(const uint32_t *words, int64_t ncells, Levels lv, int32_t nlevels,
                                        double root_cell_cm, double nu, double sigma_abs, double w_nu,
                                        const float *T, double *L)
 {
-    const double four_pi = 12.566370614359172;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncells; c += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t w = words[c];
-        double out = 0.0;
-        if ((int32_t)w >= 0) {
-            const double n = (double)__uint_as_float(w);
-            const int Lv = level_of(c, lv.off, nlevels);
-            const double s = ldexp(root_cell_cm, -Lv);
-            out = four_pi * sigma_abs * n * (s * s * s) * planck_nu(nu, (double)T[c]) * w_nu;
-        }
-        L[c] = out;
-    }
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncells; c += (int64_t)gridDim.x * blockDim.x)
+        L[c] = cell_luminosity(words, c, lv, nlevels, root_cell_cm, nu, sigma_abs, w_nu, T);
 }
 
 hipError_t launch_dust_luminosity(const uint32_t *words, int64_t ncells, const int64_t *level_offset,
@@ -311,22 +316,30 @@ __device__ inline T block_inclusive_scan(T v, T *sh)
     return r;
 }
 
+// The three passes of the scan as block bodies (tile = the block's tile),
+// shared by the single-array kernels and the batched ones below.
 template <typename T>
-__global__ __launch_bounds__(kScanThreads) void scan_tile_sums(const T *in, int64_t n, T *sums)
+__device__ inline void tile_sums_body(const T *in, int64_t n, T *sums, int64_t tile, T *sh)
 {
-    __shared__ T sh[kScanThreads];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    const int64_t base = tile * kScanTile + (int64_t)threadIdx.x * kScanItems;
     T acc = 0;
     for (int k = 0; k < kScanItems; ++k) {
         const int64_t i = base + k;
         if (i < n) acc += in[i];
     }
     T tot = block_inclusive_scan<T>(acc, sh);
-    if (threadIdx.x == kScanThreads - 1) sums[blockIdx.x] = tot;
+    if (threadIdx.x == kScanThreads - 1) sums[tile] = tot;
 }
 
 template <typename T>
-__global__ __launch_bounds__(kScanThreads) void scan_sums_exclusive(T *sums, int64_t m)
+__global__ __launch_bounds__(kScanThreads) void scan_tile_sums(const T *in, int64_t n, T *sums)
+{
+    __shared__ T sh[kScanThreads];
+    tile_sums_body<T>(in, n, sums, blockIdx.x, sh);
+}
+
+template <typename T>
+__device__ inline void sums_exclusive_body(T *sums, int64_t m)
 {
     __shared__ T sh[kScanThreads];
     __shared__ T tail;
@@ -344,11 +357,18 @@ __global__ __launch_bounds__(kScanThreads) void scan_sums_exclusive(T *sums, int
 }
 
 template <typename T>
-__global__ __launch_bounds__(kScanThreads) void scan_tiles_apply(const T *in, int64_t n, const T *offsets, T *out,
-                                                                 int inclusive)
+__global__ __launch_bounds__(kScanThreads) void scan_sums_exclusive(T *sums, int64_t m)
 {
-    __shared__ T sh[kScanThreads];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    sums_exclusive_body<T>(sums, m);
+}
+
+// Every thread reads its items before it writes, and the threads' ranges
+// are disjoint, so `out` may be `in`.
+template <typename T>
+__device__ inline void tiles_apply_body(const T *in, int64_t n, const T *offsets, T *out, int inclusive, int64_t tile,
+                                        T *sh)
+{
+    const int64_t base = tile * kScanTile + (int64_t)threadIdx.x * kScanItems;
     T v[kScanItems];
     T acc = 0;
     for (int k = 0; k < kScanItems; ++k) {
@@ -357,13 +377,21 @@ __global__ __launch_bounds__(kScanThreads) void scan_tiles_apply(const T *in, in
         acc += v[k];
     }
     const T inc = block_inclusive_scan<T>(acc, sh);
-    T run = offsets[blockIdx.x] + inc - acc;
+    T run = offsets[tile] + inc - acc;
     for (int k = 0; k < kScanItems; ++k) {
         const int64_t i = base + k;
         const T before = run;
         run += v[k];
         if (i < n) out[i] = inclusive ? run : before;
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void scan_tiles_apply(const T *in, int64_t n, const T *offsets, T *out,
+                                                                 int inclusive)
+{
+    __shared__ T sh[kScanThreads];
+    tiles_apply_body<T>(in, n, offsets, out, inclusive, blockIdx.x, sh);
 }
 
 template <typename T>
@@ -391,8 +419,8 @@ hipError_t launch_scan_f64(const double *in, double *out, int64_t n, double *scr
 // every cell receives floor or ceil of N a_c / S packages).  In package
 // units (capped expected counts) x_j = j + u, and positions at or past the
 // total emit nothing.
-__global__ void dust_select_kernel(const double *incl, int64_t ncells, uint64_t n_dust, double u_sys,
-                                   int32_t package_units, int32_t *cell)
+__device__ inline void dust_select_body(const double *incl, int64_t ncells, uint64_t n_dust, double u_sys,
+                                        int32_t package_units, int32_t *cell)
 {
     const double S = incl[ncells - 1];
     for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_dust; j += (uint64_t)gridDim.x * blockDim.x) {
@@ -415,6 +443,12 @@ __global__ void dust_select_kernel(const double *incl, int64_t ncells, uint64_t 
     }
 }
 
+__global__ void dust_select_kernel(const double *incl, int64_t ncells, uint64_t n_dust, double u_sys,
+                                   int32_t package_units, int32_t *cell)
+{
+    dust_select_body(incl, ncells, n_dust, u_sys, package_units, cell);
+}
+
 hipError_t launch_dust_select(const double *incl, int64_t ncells, uint64_t n_dust, double u_sys, int32_t package_units,
                               int32_t *cell_out, hipStream_t s)
 {
@@ -423,6 +457,73 @@ hipError_t launch_dust_select(const double *incl, int64_t ncells, uint64_t n_dus
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(dust_select_kernel, dim3((unsigned)blocks), dim3(256), 0, s, incl, ncells, n_dust, u_sys,
                        package_units, cell_out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ batched dust setup
+// The same luminosity, inclusive cumulative sum and package cells for
+// every frequency of a multi-frequency launch at once: blockIdx.y is the
+// frequency's job, blockIdx.x the same block index as in the one-array
+// kernels, so each row's values are those of the per-frequency path bit
+// for bit.  The luminosity is written into the row and scanned in place.
+__global__ void dust_luminosity_rows_kernel(const uint32_t *words, int64_t ncells, Levels lv, int32_t nlevels,
+                                            double root_cell_cm, const DustJob *jobs)
+{
+    const DustJob &J = jobs[blockIdx.y];
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncells; c += (int64_t)gridDim.x * blockDim.x)
+        J.incl[c] = cell_luminosity(words, c, lv, nlevels, root_cell_cm, J.nu, J.sigma_abs, J.w_nu, J.T);
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_tile_sums_rows_kernel(const DustJob *jobs, int64_t n)
+{
+    __shared__ double sh[kScanThreads];
+    const DustJob &J = jobs[blockIdx.y];
+    tile_sums_body<double>(J.incl, n, J.sums, blockIdx.x, sh);
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_sums_exclusive_rows_kernel(const DustJob *jobs, int64_t m)
+{
+    sums_exclusive_body<double>(jobs[blockIdx.y].sums, m);
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_tiles_apply_rows_kernel(const DustJob *jobs, int64_t n)
+{
+    __shared__ double sh[kScanThreads];
+    const DustJob &J = jobs[blockIdx.y];
+    tiles_apply_body<double>(J.incl, n, J.sums, J.incl, 1, blockIdx.x, sh);
+}
+
+__global__ void dust_select_rows_kernel(const DustJob *jobs, int64_t ncells)
+{
+    const DustJob &J = jobs[blockIdx.y];
+    dust_select_body(J.incl, ncells, J.n_dust, J.u_sys, 0, J.cell);
+}
+
+hipError_t launch_dust_setup_rows(const uint32_t *words, int64_t ncells, const int64_t *level_offset, int32_t nlevels,
+                                  double root_cell_cm, const DustJob *d_jobs, int32_t njobs, uint64_t max_dust,
+                                  hipStream_t s)
+{
+    if (njobs <= 0 || ncells <= 0) return hipSuccess;
+    if (njobs > 65535) return hipErrorInvalidValue;
+    Levels lv;
+    for (int i = 0; i <= kMaxLevels; ++i) lv.off[i] = i <= nlevels ? level_offset[i] : ncells;
+    // about 16 K workgroups in all, at least 64 per row
+    const int64_t per_row = std::max<int64_t>(64, 16384 / njobs);
+    const int64_t bl = std::min<int64_t>((ncells + 255) / 256, per_row);
+    hipLaunchKernelGGL(dust_luminosity_rows_kernel, dim3((unsigned)bl, (unsigned)njobs), dim3(256), 0, s, words,
+                       ncells, lv, nlevels, root_cell_cm, d_jobs);
+    const int64_t tiles = (ncells + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(scan_tile_sums_rows_kernel, dim3((unsigned)tiles, (unsigned)njobs), dim3(kScanThreads), 0, s,
+                       d_jobs, ncells);
+    hipLaunchKernelGGL(scan_sums_exclusive_rows_kernel, dim3(1, (unsigned)njobs), dim3(kScanThreads), 0, s, d_jobs,
+                       tiles);
+    hipLaunchKernelGGL(scan_tiles_apply_rows_kernel, dim3((unsigned)tiles, (unsigned)njobs), dim3(kScanThreads), 0, s,
+                       d_jobs, ncells);
+    if (max_dust > 0) {
+        const int64_t bs = std::min<int64_t>((int64_t)((max_dust + 255) / 256), per_row);
+        hipLaunchKernelGGL(dust_select_rows_kernel, dim3((unsigned)bs, (unsigned)njobs), dim3(256), 0, s, d_jobs,
+                           ncells);
+    }
     return hipGetLastError();
 }
 

@@ -208,6 +208,23 @@ hipError_t launch_dust_cap(double *a, int64_t n, const double *S_in, double *S_o
 // total).
 hipError_t launch_dust_select(const double *incl, int64_t ncells, uint64_t n_dust, double u_sys, int32_t package_units,
                               int32_t *cell_out, hipStream_t s);
+// One frequency of the batched weighted-mode setup (mode 1, no cap).
+struct DustJob {
+    const float *T;              // temperatures [ncells]
+    double nu, sigma_abs, w_nu;  // the band
+    double *incl;                // [ncells]: the luminosity, then its inclusive cumulative sum
+    double *sums;                // scan scratch, scan_f64_scratch_elems(ncells) elements
+    int32_t *cell;               // [n_dust] cell of every package
+    uint64_t n_dust;
+    double u_sys;                // systematic-sampling offset
+};
+// Luminosity, inclusive cumulative sum and package cells of njobs
+// frequencies in five launches (d_jobs: device array of njobs jobs,
+// max_dust = the largest n_dust); each row equals what
+// launch_dust_luminosity, launch_scan_f64 and launch_dust_select give.
+hipError_t launch_dust_setup_rows(const uint32_t *words, int64_t ncells, const int64_t *level_offset, int32_t nlevels,
+                                  double root_cell_cm, const DustJob *d_jobs, int32_t njobs, uint64_t max_dust,
+                                  hipStream_t s);
 // Diagonal ALI: the dust energy each cell emits in this call, added to E.
 // Weighted modes: from the cell of every package (non-decreasing, -1 past
 // a capped total), one writer per cell; uniform mode: per_leaf packages of

@@ -6,8 +6,8 @@ summation order.  Covered: constant sources (field and point sources),
 luminosity-weighted dust emission with and without the per-cell cap,
 uniform dust emission, the reference-field correction (mode 2, its
 per-frequency reference blended in place), frequencies with different
-package counts, the diagonal-ALI tallies, an octree, K = 1, and the
-argument errors.  The
+package counts, a call that mixes these setups, the diagonal-ALI tallies,
+an octree, K = 1, and the argument errors.  The
 iteration drivers run on top of it (tests/test_gpu_driver.py,
 tests/test_gpu_reference.py)."""
 import numpy as np
@@ -147,6 +147,27 @@ def test_octree_and_single_frequency(soc, ctx):
     src = [dict(I_bg=float(I[k]), ps_pos=[[4.1, 3.9, 4.05]], ps_Lnu=[1e21], n_bg=5000, n_ps_pk=3000) for k in range(6)]
     _check(*_both(soc, ctx, g, G.ncells, freqs, src, list(range(6)), 15, 1))
     _check(*_both(soc, ctx, g, G.ncells, freqs[2:3], src[2:3], [2], 16, 1))
+
+
+def test_mixed_dust_setups(soc, ctx, cloud):
+    """One call whose frequencies mix the weighted mode without a cap
+    (their tables are built together for all of them), the capped mode and
+    constant sources only (built one frequency at a time), on the regular
+    cloud and on an octree (the luminosity of refined levels)."""
+    P, T = cloud
+    g = soc.grid_from_workload(ctx, P.grid)
+    kinds = [dict(T=T, n_dust=18000 + 700 * k, dust_mode=1) if k % 3 == 0 else
+             dict(T=T, n_dust=16000, dust_mode=1, dust_cap=6.0) if k % 3 == 1 else
+             dict(I_bg=float(P.I_bg[k]), n_bg=5000) for k in range(P.K)]
+    _check(*_both(soc, ctx, g, P.grid.ncells, _freqs(P), kinds, list(range(P.K)), 18, 5))
+    G = W.octree_lognormal(n_root=8, nlevels=3, sigma_ln=1.2, seed=6)
+    go = soc.grid_from_workload(ctx, G)
+    rng = np.random.default_rng(8)
+    To = rng.uniform(10.0, 60.0, G.ncells).astype(np.float32)
+    To[G.density() == 0] = 0.0
+    Td = torch.from_numpy(To).cuda()
+    src = [dict(T=Td, n_dust=12000 + 300 * k, dust_mode=1) for k in range(P.K)]
+    _check(*_both(soc, ctx, go, G.ncells, _freqs(P), src, list(range(P.K)), 19, 5))
 
 
 @pytest.mark.parametrize("copies", [1, 0])
