@@ -291,7 +291,15 @@ def simulate_frequencies(ctx: Context, grid: Grid, freqs, absorbed: torch.Tensor
     K = len(freqs)
     if len(sources) != K or len(freq_indices) != K:
         raise ValueError("one source set and one frequency index per frequency")
-    views = [_SourceView(**q) for q in sources]
+    # a source set given for several frequencies (the same dict object) is
+    # marshalled once
+    built = {}
+    views = []
+    for q in sources:
+        v = built.get(id(q))
+        if v is None:
+            v = built[id(q)] = _SourceView(**q)
+        views.append(v)
     farr = (_Freq * K)(*[_freq(f) for f in freqs])
     sarr = (_Sources * K)(*[v.s for v in views])
     karr = (C.c_uint32 * K)(*[int(k) for k in freq_indices])
