@@ -218,10 +218,15 @@ soc_status soc_simulate_frequency(soc_ctx ctx, soc_grid grid, const soc_freq *fr
  * luminosities, selection of cells) runs before the launch and keeps its
  * own package-to-cell list until then (context scratch: 4 B per weighted
  * dust package, plus 8 B per cell for frequencies whose kernel reads the
- * luminosities: dust modes 0 and 2 and capped emission).  The diagonal-ALI
- * tallies (Sect. 2.1.2) are taken as in soc_simulate_frequency when every
- * srcs[k] names the same d_ali_self and d_ali_emitted (SOC_EINVAL when
- * they differ between frequencies).  1 <= K <= 4096.  Synchronises the stream before it starts (the argument
+ * luminosities: dust modes 0 and 2 and capped emission).  The frequencies
+ * in weighted mode 1 without a cap have their tables built together, a
+ * few launches for all of them (context scratch: 8 B per cell and
+ * frequency, when that comes to at most 16 GiB; one frequency at a time
+ * otherwise); the package cells are the same either way.  The
+ * diagonal-ALI tallies (Sect. 2.1.2) are taken as in
+ * soc_simulate_frequency when every srcs[k] names the same d_ali_self and
+ * d_ali_emitted (SOC_EINVAL when they differ between frequencies).
+ * 1 <= K <= 4096.  Synchronises the stream before it starts (the argument
  * blocks are staged on the host); not allowed during graph capture. */
 soc_status soc_simulate_frequencies(soc_ctx ctx, soc_grid grid, int32_t K, const soc_freq *freqs,
                                     const soc_sources *srcs, const uint32_t *freq_indices, uint64_t seed,
