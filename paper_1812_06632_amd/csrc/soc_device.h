@@ -183,6 +183,7 @@ struct Pkg {
     int32_t cx, cy, cz;
     int32_t c, L;
     int32_t par;   // octree: the parent of cell c when known (L > 0), else -1
+    int32_t gpar;  // octree: the parent of par when known (L > 1), else -1
     R fx, fy, fz;
     R ux, uy, uz;
     R ix, iy, iz;
@@ -322,6 +323,7 @@ __device__ inline void descend(Pkg<R> &p, const AT &A)
         p.fx = (R)2 * p.fx - (R)ox;
         p.fy = (R)2 * p.fy - (R)oy;
         p.fz = (R)2 * p.fz - (R)oz;
+        p.gpar = p.par;
         p.par = p.c;
         p.c = -w + ox + 2 * oy + 4 * oz;
         p.L += 1;
@@ -335,8 +337,9 @@ __device__ inline void descend(Pkg<R> &p, const AT &A)
 // while the face is also a face of the parent, across to the sibling (or
 // the neighbouring root cell), then down by position.  The exit coordinate
 // must already be on the face (1 when fw, 0 otherwise).  Returns false
-// when the package leaves the box.  The first step up takes the parent
-// the package passed on its way down (p.par) instead of reading the link.
+// when the package leaves the box.  The first two steps up take the
+// parent and grandparent the package passed on its way down (p.par,
+// p.gpar) instead of reading the links.
 // Octets are 8-aligned relative to every level offset, all of which are
 // congruent to nroot mod 8, so the octant of a non-root cell is
 // (c - nroot) & 7.
@@ -360,6 +363,7 @@ __device__ inline bool cross_octree(Pkg<R> &p, const AT &A, int a, bool fw)
             }
             p.c = p.cx + A.nx * (p.cy + A.ny * p.cz);
             p.par = -1;
+            p.gpar = -1;
             break;
         }
         const int32_t o = (int32_t)((p.c - A.nroot) & 7);
@@ -374,12 +378,14 @@ __device__ inline bool cross_octree(Pkg<R> &p, const AT &A, int a, bool fw)
         p.fx = (p.fx + (R)(o & 1)) * (R)0.5;
         p.fy = (p.fy + (R)((o >> 1) & 1)) * (R)0.5;
         p.fz = (p.fz + (R)((o >> 2) & 1)) * (R)0.5;
-        // the parent is known when the package came down into this octet;
-        // the link is read only above that
+        // the parent is known when the package came down into this octet
+        // (and the next one up when it came down two levels); the link is
+        // read only above that
         int32_t up = p.par;
         if (up < 0) up = A.parent[(p.c - A.nroot) >> 3];
         p.c = up;
-        p.par = -1;
+        p.par = p.gpar;
+        p.gpar = -1;
         p.L -= 1;
     }
     descend(p, A);
@@ -413,6 +419,7 @@ __device__ inline bool emit_base(const AT &A, uint64_t gid, Pkg<R> &p, Rng &rng,
 {
     p.L = 0;
     p.par = -1;
+    p.gpar = -1;
     const uint64_t nps_tot = (uint64_t)A.n_ps * A.n_ps_pk;
     if (gid < A.n_bg) {
         cls = kClassBg;
@@ -506,6 +513,7 @@ __device__ inline bool emit_base(const AT &A, uint64_t gid, Pkg<R> &p, Rng &rng,
             for (int l = L; l > 0; --l) {
                 root = A.parent[(root - A.nroot) >> 3];
                 if (l == L) p.par = (int32_t)root;
+                if (l == L - 1) p.gpar = (int32_t)root;
             }
         }
         p.c = (int32_t)c;
