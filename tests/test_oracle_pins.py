@@ -309,6 +309,76 @@ def test_cauchy_mean_chord_empty_box():
     assert st["e_emitted"] == pytest.approx(math.pi * 1.0 * S, rel=1e-12)
 
 
+def _radiance_cloud():
+    """Non-cubic lognormal cloud, 1-cm cells, mean scattering optical depth
+    0.6 per cell (4-6 across), absorption 1e-6 of that."""
+    rng = np.random.default_rng(12)
+    rho = np.exp(rng.normal(0.0, 0.8, (6, 8, 10))).astype(np.float32)
+    s_sca = 0.6 / float(rho.mean())
+    return W.regular_grid(rho, 1.0), rho.astype(np.float64), s_sca * 1e-6, s_sca
+
+
+@pytest.mark.parametrize("g_hg", [0.0, 0.6])
+def test_scattering_cloud_keeps_uniform_isotropic_radiance(g_hg):
+    """Isotropic external field on a scattering cloud that (almost) does not
+    absorb: the radiance inside stays uniform and isotropic, equal to the
+    field's, whatever the scattering.  Hence (i) the mean path length of
+    the entering packages is 4V/S as in an empty box (the invariance of
+    Blanco & Fournier 2003, Cauchy's formula with scattering), and (ii) to
+    first order in k_abs every cell absorbs 4 pi k_abs V I w, the optically
+    thin result: a closed form for the per-cell absorption of a scattering
+    cloud.  (ii) is tested cell by cell with z-scores over 16 independent
+    seeds."""
+    g, rho, s_abs, s_sca = _radiance_cloud()
+    freq = (1e14, 1.0, s_abs, s_sca, g_hg)
+    V, S = 6 * 8 * 10, 2 * (48 + 60 + 80)
+    runs, paths = [], []
+    for seed in range(16):
+        A, st, path = orc.simulate_frequency(g, freq, I_bg=1.0, n_bg=40000, seed=100 + seed, want_path=True,
+                                             nthreads=8)
+        assert st["e_emitted"] == pytest.approx(math.pi * S, rel=1e-12)
+        runs.append(A)
+        paths.append(path)
+    path = np.concatenate(paths)
+    assert st["scatterings"] > 2 * st["packages"]
+    assert abs(path.mean() - 4 * V / S) < 4 * path.std() / math.sqrt(path.size)
+    R = np.array(runs)
+    pred = 4 * math.pi * s_abs * rho.reshape(-1) * 1.0
+    z = (R.mean(axis=0) - pred) / (R.std(axis=0, ddof=1) / math.sqrt(len(runs)))
+    assert np.all(np.abs(z) < 6.0), np.abs(z).max()
+    assert abs(z.mean()) < 4.0 / math.sqrt(z.size)
+    assert R.sum(axis=1).mean() == pytest.approx(pred.sum(), rel=3e-3)
+
+
+def test_scattering_octree_keeps_uniform_isotropic_radiance():
+    """The same closed form on an octree with physical units: each leaf
+    absorbs 4 pi k_abs V I w with V its own level's volume; refined cells
+    absorb nothing."""
+    G = W.octree_lognormal(n_root=8, nlevels=3, sigma_ln=1.0, seed=4)
+    dens = G.density().astype(np.float64)
+    lv = np.zeros(G.ncells, np.int64)
+    for L in range(1, G.nlevels):
+        lv[G.level_offset[L]:] = L
+    s = G.root_cell_cm
+    vol = (s * 0.5 ** lv) ** 3
+    s_sca = 0.6 / (float((dens * vol).sum() / vol[dens > 0].sum()) * s)
+    runs = []
+    for seed in range(16):
+        A, st, _ = orc.simulate_frequency(G, (1e14, 1.0, s_sca * 1e-6, s_sca, 0.5), I_bg=1.0, n_bg=40000,
+                                          seed=300 + seed, nthreads=8)
+        runs.append(A)
+    assert st["e_emitted"] == pytest.approx(math.pi * 6 * (8 * s) ** 2, rel=1e-12)
+    assert st["scatterings"] > 2 * st["packages"]
+    R = np.array(runs)
+    pred = 4 * math.pi * s_sca * 1e-6 * dens * vol
+    sel = pred > 0
+    assert np.all(R[:, ~sel] == 0.0)
+    z = (R.mean(axis=0)[sel] - pred[sel]) / (R.std(axis=0, ddof=1)[sel] / math.sqrt(len(runs)))
+    assert np.all(np.abs(z) < 6.0), np.abs(z).max()
+    assert abs(z.mean()) < 4.0 / math.sqrt(z.size)
+    assert R.sum(axis=1).mean() == pytest.approx(pred.sum(), rel=3e-3)
+
+
 def test_isotropic_field_on_absorbing_sphere():
     """Pure-absorber sphere of radius R and centre-to-edge optical depth t in
     an isotropic field absorbs the fraction 1 - [1-(1+2t)e^{-2t}]/(2t^2) of
