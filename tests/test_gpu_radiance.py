@@ -50,8 +50,9 @@ def _check(soc, ctx, grid, dens, vol, s_abs, s_sca, g_hg, area, n_bg):
     print(f"\nmax |z| {np.abs(z).max():.2f}, mean z {z.mean():.3f} over {z.size} cells")
     assert np.all(R[:, ~sel] == 0.0)
     assert np.all(np.abs(z) < 6.0)
-    assert abs(z.mean()) < 4.0 / math.sqrt(z.size)
-    assert R.sum(axis=1).mean() == pytest.approx(pred.sum(), rel=2e-3)
+    tot = R.sum(axis=1)   # the cells share packages: the total has its own spread
+    print(f"total / closed form {tot.mean() / pred.sum():.6f} +- {tot.std(ddof=1) / math.sqrt(len(runs)) / pred.sum():.6f}")
+    assert abs(tot.mean() - pred.sum()) < 4.5 * tot.std(ddof=1) / math.sqrt(len(runs))
 
 
 @pytest.mark.parametrize("g_hg", [0.0, 0.6])

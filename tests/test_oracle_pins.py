@@ -346,8 +346,8 @@ def test_scattering_cloud_keeps_uniform_isotropic_radiance(g_hg):
     pred = 4 * math.pi * s_abs * rho.reshape(-1) * 1.0
     z = (R.mean(axis=0) - pred) / (R.std(axis=0, ddof=1) / math.sqrt(len(runs)))
     assert np.all(np.abs(z) < 6.0), np.abs(z).max()
-    assert abs(z.mean()) < 4.0 / math.sqrt(z.size)
-    assert R.sum(axis=1).mean() == pytest.approx(pred.sum(), rel=3e-3)
+    tot = R.sum(axis=1)   # the cells share packages: the total has its own spread
+    assert abs(tot.mean() - pred.sum()) < 4.5 * tot.std(ddof=1) / math.sqrt(len(runs))
 
 
 def test_scattering_octree_keeps_uniform_isotropic_radiance():
@@ -375,8 +375,8 @@ def test_scattering_octree_keeps_uniform_isotropic_radiance():
     assert np.all(R[:, ~sel] == 0.0)
     z = (R.mean(axis=0)[sel] - pred[sel]) / (R.std(axis=0, ddof=1)[sel] / math.sqrt(len(runs)))
     assert np.all(np.abs(z) < 6.0), np.abs(z).max()
-    assert abs(z.mean()) < 4.0 / math.sqrt(z.size)
-    assert R.sum(axis=1).mean() == pytest.approx(pred.sum(), rel=3e-3)
+    tot = R.sum(axis=1)   # the cells share packages: the total has its own spread
+    assert abs(tot.mean() - pred.sum()) < 4.5 * tot.std(ddof=1) / math.sqrt(len(runs))
 
 
 def test_isotropic_field_on_absorbing_sphere():
